@@ -1,0 +1,246 @@
+"""FP64 CPU oracle for the MAC projection: Python side.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the HIP library; it is fed by the seeded input generators and nothing else.
+
+Wraps ``mg_oracle.c`` (plain C, FP64, built with gcc) through ctypes.  The
+arithmetic and the discretisation are documented in that file's header: the
+projection enforcing the divergence constraint of the paper (Sec. 2) with
+multigrid (Sec. 3).
+
+Two ways to run the solver:
+
+* ``mode="algorithm"``: the V(nu1, nu2) red-black Gauss-Seidel cycle step by
+  step, stopping at the first cycle whose relative residual is <= rtol;
+* ``mode="definition"``: the same cycles iterated to stagnation, i.e. the
+  exact discrete solution up to round-off.  This is the reference for phi and
+  U parity.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mg_oracle.c")
+_LIB = os.path.join(_HERE, "libmgoracle.so")
+
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BAD_SIZE", -3: "INCOMPATIBLE_RHS",
+          -4: "NOT_CONVERGED", -5: "NONFINITE", -6: "OOM"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas",
+               _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        i, d = ctypes.c_int, ctypes.c_double
+        L.orc_face_coeffs.argtypes = [i, i, i, i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_rhs.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_apply.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp]
+        L.orc_residual.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_rbgs.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, i]
+        L.orc_num_levels.argtypes = [i, i, i]
+        L.orc_mg_create.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _ip]
+        L.orc_mg_create.restype = ctypes.c_void_p
+        L.orc_mg_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_mg_nlevels.argtypes = [ctypes.c_void_p]
+        L.orc_mg_level_info.argtypes = [ctypes.c_void_p, i, _ip, _dp]
+        L.orc_mg_io.argtypes = [ctypes.c_void_p, i, i, _dp, i]
+        L.orc_mg_smooth.argtypes = [ctypes.c_void_p, i, i]
+        L.orc_mg_resid_restrict.argtypes = [ctypes.c_void_p, i]
+        L.orc_mg_prolong.argtypes = [ctypes.c_void_p, i]
+        L.orc_mg_coarse.argtypes = [ctypes.c_void_p]
+        L.orc_mg_vcycle.argtypes = [ctypes.c_void_p, i, i, i]
+        L.orc_mg_solve.argtypes = [ctypes.c_void_p, _dp, _dp, d, i, i, i, i, _dp, i, _ip]
+        L.orc_correct.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_mac_project.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                      d, i, i, i, i, _dp, i, _dp]
+        L.orc_max_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _shape_args(n, periodic):
+    nx, ny, nz = n
+    px, py, pz = (1 if p else 0 for p in periodic)
+    return nx, ny, nz, px, py, pz
+
+
+def num_levels(n) -> int:
+    return lib().orc_num_levels(*n)
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
+
+
+def face_coeffs(n, periodic, rho, b0c, b0e):
+    """Full face arrays bx (nz,ny,nx+1), by (nz,ny+1,nx), bz (nz+1,ny,nx)."""
+    nx, ny, nz = n
+    bx = np.empty((nz, ny, nx + 1))
+    by = np.empty((nz, ny + 1, nx))
+    bz = np.empty((nz + 1, ny, nx))
+    lib().orc_face_coeffs(*_shape_args(n, periodic), _p(rho), _p(b0c), _p(b0e), _p(bx), _p(by), _p(bz))
+    return bx, by, bz
+
+
+def rhs(n, periodic, h, b0c, b0e, u, v, w, S):
+    """f = D(beta0 U) - beta0 S (before mean removal)."""
+    nx, ny, nz = n
+    f = np.empty((nz, ny, nx))
+    lib().orc_rhs(*_shape_args(n, periodic), h, _p(b0c), _p(b0e), _p(u), _p(v), _p(w), _p(S), _p(f))
+    return f
+
+
+def apply(n, periodic, h, coeffs, phi):
+    """L phi."""
+    bx, by, bz = coeffs
+    out = np.empty_like(phi)
+    lib().orc_apply(*_shape_args(n, periodic), h, _p(bx), _p(by), _p(bz), _p(phi), _p(out))
+    return out
+
+
+def residual(n, periodic, h, coeffs, phi, f):
+    bx, by, bz = coeffs
+    r = np.empty_like(phi)
+    lib().orc_residual(*_shape_args(n, periodic), h, _p(bx), _p(by), _p(bz), _p(phi), _p(f), _p(r))
+    return r
+
+
+def rbgs(n, periodic, h, coeffs, phi, f, nsweeps=1):
+    """Red-black Gauss-Seidel sweeps, returns a new array."""
+    bx, by, bz = coeffs
+    out = np.ascontiguousarray(phi, dtype=np.float64).copy()
+    lib().orc_rbgs(*_shape_args(n, periodic), h, _p(bx), _p(by), _p(bz), _p(out), _p(f), nsweeps)
+    return out
+
+
+def correct(n, periodic, h, b0c, b0e, coeffs, phi, u, v, w):
+    """Corrected copies of u, v, w."""
+    bx, by, bz = coeffs
+    u, v, w = u.copy(), v.copy(), w.copy()
+    lib().orc_correct(*_shape_args(n, periodic), h, _p(b0c), _p(b0e), _p(bx), _p(by), _p(bz),
+                      _p(phi), _p(u), _p(v), _p(w))
+    return u, v, w
+
+
+class Hierarchy:
+    """The oracle's multigrid hierarchy, exposing every step of the V-cycle."""
+
+    def __init__(self, n, periodic, h, coeffs):
+        self.n = tuple(n)
+        self.periodic = tuple(periodic)
+        bx, by, bz = (np.ascontiguousarray(c) for c in coeffs)
+        st = ctypes.c_int(0)
+        self._h = lib().orc_mg_create(*_shape_args(n, periodic), h, _p(bx), _p(by), _p(bz),
+                                      ctypes.byref(st))
+        if not self._h:
+            raise RuntimeError(f"oracle hierarchy: {STATUS.get(st.value, st.value)}")
+        self.nlevels = lib().orc_mg_nlevels(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_mg_destroy(self._h)
+            self._h = None
+
+    def level(self, l):
+        dims = (ctypes.c_int * 3)()
+        h = ctypes.c_double()
+        lib().orc_mg_level_info(self._h, l, dims, ctypes.byref(h))
+        return (dims[0], dims[1], dims[2]), h.value
+
+    _WHICH = {"phi": 0, "f": 1, "r": 2, "bx": 3, "by": 4, "bz": 5}
+
+    def _shape(self, l, which):
+        (nx, ny, nz), _ = self.level(l)
+        return {"phi": (nz, ny, nx), "f": (nz, ny, nx), "r": (nz, ny, nx),
+                "bx": (nz, ny, nx + 1), "by": (nz, ny + 1, nx), "bz": (nz + 1, ny, nx)}[which]
+
+    def get(self, l, which):
+        out = np.empty(self._shape(l, which))
+        st = lib().orc_mg_io(self._h, l, self._WHICH[which], _p(out), 0)
+        assert st == 0
+        return out
+
+    def set(self, l, which, arr):
+        arr = np.ascontiguousarray(arr, dtype=np.float64)
+        assert arr.shape == self._shape(l, which)
+        st = lib().orc_mg_io(self._h, l, self._WHICH[which], _p(arr), 1)
+        assert st == 0
+
+    def smooth(self, l, nsweeps):
+        lib().orc_mg_smooth(self._h, l, nsweeps)
+
+    def resid_restrict(self, l):
+        lib().orc_mg_resid_restrict(self._h, l)
+
+    def prolong(self, l):
+        lib().orc_mg_prolong(self._h, l)
+
+    def coarse(self):
+        lib().orc_mg_coarse(self._h)
+
+    def vcycle(self, l=0, nu1=2, nu2=2):
+        lib().orc_mg_vcycle(self._h, l, nu1, nu2)
+
+    def solve(self, f, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, mode="algorithm"):
+        """Solve L phi = f (f must already have zero mean).  Returns (status, phi, hist)."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        phi = np.empty_like(f)
+        hist = np.full(max_cycles + 1, np.nan)
+        cyc = ctypes.c_int(0)
+        st = lib().orc_mg_solve(self._h, _p(f), _p(phi), rtol, max_cycles, nu1, nu2,
+                                1 if mode == "definition" else 0, _p(hist), len(hist), ctypes.byref(cyc))
+        return st, phi, hist[: cyc.value + 1]
+
+
+def mac_project(prob, mode="algorithm", rtol=None, max_cycles=None, nu1=None, nu2=None):
+    """The whole projection on host copies of ``prob`` (an inputs.Problem).
+
+    Returns a dict with status, phi (zero mean), corrected u/v/w, the residual
+    history and the RHS statistics.
+    """
+    n, per = prob.n, prob.periodic
+    rtol = prob.rtol if rtol is None else rtol
+    max_cycles = (prob.max_cycles if mode == "algorithm" else 200) if max_cycles is None else max_cycles
+    nu1 = prob.pre_sweeps if nu1 is None else nu1
+    nu2 = prob.post_sweeps if nu2 is None else nu2
+    u, v, w = prob.u.copy(), prob.v.copy(), prob.w.copy()
+    nx, ny, nz = n
+    phi = np.zeros((nz, ny, nx))
+    hist = np.full(max_cycles + 1, np.nan)
+    stats = np.zeros(8)
+    st = lib().orc_mac_project(*_shape_args(n, per), prob.dx, _p(prob.rho), _p(prob.beta0_cc),
+                               _p(prob.beta0_edge), _p(prob.S), _p(u), _p(v), _p(w), _p(phi),
+                               rtol, max_cycles, nu1, nu2, 1 if mode == "definition" else 0,
+                               _p(hist), len(hist), _p(stats))
+    cycles = int(stats[0])
+    return {"status": st, "status_name": STATUS.get(st, str(st)), "phi": phi, "u": u, "v": v, "w": w,
+            "cycles": cycles, "hist": hist[: cycles + 1], "rel_resid": stats[1],
+            "mean_removed": stats[2], "sum_f": stats[3], "sum_abs_f": stats[4], "norm_f": stats[5]}

@@ -1,0 +1,194 @@
+"""Seeded synthetic inputs for the variable-coefficient MAC projection.
+
+This module only draws and lays out input fields; it holds none of the
+projection's arithmetic, so both the HIP path and the CPU oracle can be fed
+from it.  Every field is float64, C-ordered ``[k][j][i]`` (i fastest):
+
+* cell fields (rho, S): shape ``(nz, ny, nx)``
+* x-face velocity u: ``(nz, ny, nx+1)``, face i sits between cells i-1 and i
+* y-face velocity v: ``(nz, ny+1, nx)``
+* z-face velocity w: ``(nz+1, ny, nx)``
+* base state beta0 at cell centres ``(nz,)`` and at z-faces ``(nz+1,)``
+
+The stratified base state follows the plane-parallel reading of the paper's
+1-D base state beta0(r) (Sec. 2, definition of beta0) with r taken as the
+height z and an exponential profile exp(-z/H).  The expansion term S is an
+input field (Sec. 2, constraint and expansion-term equations); where it is
+random its beta0-weighted mean is removed so that the divergence constraint is
+solvable with periodic / solid-wall boundaries.
+
+Draw order for a problem (one ``numpy.random.default_rng(seed)`` stream):
+rho noise (nz,ny,nx); S noise (nz,ny,nx) only when S is random; u faces
+0..nx-1; v faces 0..ny-1; w faces 1..nz-1 (all standard normal).  Periodic
+duplicate faces (face n) are then copied from face 0; wall faces are zero.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+__all__ = [
+    "Problem", "make_problem", "stratified_base_state",
+    "mixed_batch_specs", "serving_requests",
+    "SMALL_BOX", "STEEP_256", "MIXED_512",
+]
+
+
+@dataclasses.dataclass
+class Problem:
+    """One projection problem: inputs and solver parameters (host arrays)."""
+    n: tuple            # (nx, ny, nz) cells
+    dx: float
+    periodic: tuple     # (px, py, pz) booleans; False means solid walls on both sides
+    rho: np.ndarray
+    beta0_cc: np.ndarray
+    beta0_edge: np.ndarray
+    S: np.ndarray
+    u: np.ndarray
+    v: np.ndarray
+    w: np.ndarray
+    rtol: float = 1e-10
+    max_cycles: int = 100
+    pre_sweeps: int = 2
+    post_sweeps: int = 2
+    seed: int = 0
+    H: float = 0.3
+
+    @property
+    def ncells(self) -> int:
+        nx, ny, nz = self.n
+        return nx * ny * nz
+
+    def copy(self) -> "Problem":
+        out = dataclasses.replace(self)
+        for name in ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w"):
+            setattr(out, name, getattr(self, name).copy())
+        return out
+
+
+def stratified_base_state(nz: int, dx: float, H: float):
+    """beta0 = exp(-z/H) at cell centres z=(k+1/2)dx and at z-faces z=k dx."""
+    zc = (np.arange(nz, dtype=np.float64) + 0.5) * dx
+    ze = np.arange(nz + 1, dtype=np.float64) * dx
+    return np.exp(-zc / H), np.exp(-ze / H)
+
+
+def _fill_faces(u, v, w, periodic):
+    px, py, pz = periodic
+    if px:
+        u[:, :, -1] = u[:, :, 0]
+    else:
+        u[:, :, 0] = 0.0
+        u[:, :, -1] = 0.0
+    if py:
+        v[:, -1, :] = v[:, 0, :]
+    else:
+        v[:, 0, :] = 0.0
+        v[:, -1, :] = 0.0
+    if pz:
+        w[-1] = w[0]
+    else:
+        w[0] = 0.0
+        w[-1] = 0.0
+
+
+def make_problem(n, *, H=0.3, rho_noise=0.01, S_kind="random", S_amp=0.1,
+                 seed=0, dx=None, periodic=(True, True, False), rtol=1e-10,
+                 max_cycles=100, vel_scale=1.0) -> Problem:
+    """Draw one seeded problem.
+
+    ``n`` is an int (cubic box) or an ``(nx, ny, nz)`` tuple.  ``dx`` defaults
+    to ``1/nx`` (the unit box for cubic grids).  ``S_kind`` is ``"random"``
+    (S_amp * N(0,1) with the beta0-weighted mean removed), ``"sine"``
+    (sin(2 pi x) sin(2 pi y) cos(pi z) at cell centres) or ``"zero"``.
+    """
+    if isinstance(n, int):
+        n = (n, n, n)
+    nx, ny, nz = (int(a) for a in n)
+    if dx is None:
+        dx = 1.0 / nx
+    periodic = tuple(bool(p) for p in periodic)
+    rng = np.random.default_rng(seed)
+    b0c, b0e = stratified_base_state(nz, dx, H)
+    xi_rho = rng.standard_normal((nz, ny, nx))
+    rho = b0c[:, None, None] * (1.0 + rho_noise * xi_rho)
+    if S_kind == "random":
+        S = S_amp * rng.standard_normal((nz, ny, nx))
+        wts = np.broadcast_to(b0c[:, None, None], S.shape)
+        S -= float(np.sum(wts * S) / np.sum(wts))
+    elif S_kind == "sine":
+        x = (np.arange(nx) + 0.5) * dx
+        y = (np.arange(ny) + 0.5) * dx
+        z = (np.arange(nz) + 0.5) * dx
+        S = (np.cos(np.pi * z)[:, None, None] * np.sin(2 * np.pi * y)[None, :, None]
+             * np.sin(2 * np.pi * x)[None, None, :])
+    elif S_kind == "zero":
+        S = np.zeros((nz, ny, nx))
+    else:
+        raise ValueError(f"unknown S_kind {S_kind!r}")
+    u = np.zeros((nz, ny, nx + 1))
+    v = np.zeros((nz, ny + 1, nx))
+    w = np.zeros((nz + 1, ny, nx))
+    u[:, :, :nx] = vel_scale * rng.standard_normal((nz, ny, nx))
+    v[:, :ny, :] = vel_scale * rng.standard_normal((nz, ny, nx))
+    if nz > 1:
+        w[1:nz] = vel_scale * rng.standard_normal((nz - 1, ny, nx))
+    if periodic[2]:
+        # periodic z: face 0 is a real face, drawn after the interior faces
+        w[0] = vel_scale * rng.standard_normal((ny, nx))
+    _fill_faces(u, v, w, periodic)
+    return Problem(n=(nx, ny, nz), dx=float(dx), periodic=periodic, rho=rho,
+                   beta0_cc=b0c, beta0_edge=b0e, S=np.ascontiguousarray(S),
+                   u=u, v=v, w=w, rtol=rtol, max_cycles=max_cycles, seed=seed, H=H)
+
+
+# Named workloads (unit box, periodic in x and y, solid walls in z).
+def SMALL_BOX(seed=0):
+    """32^3, H=0.3, 1% density noise, S = sin(2 pi x) sin(2 pi y) cos(pi z)."""
+    return make_problem(32, H=0.3, rho_noise=0.01, S_kind="sine", seed=seed)
+
+
+def STEEP_256(seed=1, n=256):
+    """256^3 steeply stratified box, H=0.1 (density contrast ~2e4), S=0.1 N(0,1)."""
+    return make_problem(n, H=0.1, rho_noise=0.01, S_kind="random", seed=seed)
+
+
+def MIXED_512(seed=2, n=512):
+    """512^3 box, H=0.15, 5% density noise, S=0.1 N(0,1); solved in mixed precision."""
+    return make_problem(n, H=0.15, rho_noise=0.05, S_kind="random", seed=seed)
+
+
+def mixed_batch_specs(count=64, seed=3, edges=(32, 48, 64, 96, 128), hmin=0.08, hmax=0.5):
+    """(edge, H, problem_seed) for a batch of independent cubic problems."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(count):
+        e = int(rng.choice(np.asarray(edges)))
+        H = float(rng.uniform(hmin, hmax))
+        out.append((e, H, seed * 1000 + p))
+    return out
+
+
+def serving_requests(count, rate, seed=4, edges=(32, 64, 128, 256),
+                     weights=(0.4, 0.3, 0.2, 0.1), rtols=(1e-8, 1e-10),
+                     hmin=0.08, hmax=0.5):
+    """Open-loop Poisson arrivals: list of (t_arrival_s, edge, H, rtol, seed)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        e = int(rng.choice(np.asarray(edges), p=np.asarray(weights)))
+        H = float(rng.uniform(hmin, hmax))
+        tol = float(rtols[int(rng.integers(0, len(rtols)))])
+        out.append((t, e, H, tol, seed * 10000 + r))
+    return out
+
+
+def domain_centres(n, dx):
+    """Cell-centre coordinates (x, y, z) along each axis."""
+    nx, ny, nz = n
+    return ((np.arange(nx) + 0.5) * dx, (np.arange(ny) + 0.5) * dx,
+            (np.arange(nz) + 0.5) * dx)
+

@@ -1,0 +1,385 @@
+"""Pins of the FP64 CPU oracle against things other than itself (CPU only).
+
+Each test ties one part of the oracle to a closed form, an independent
+face-by-face assembly solved by a library direct solver, an exact reduction, a
+manufactured solution or an invariant of the projection (paper Sec. 2: the
+divergence constraint; Sec. 3: multigrid projection).
+"""
+import numpy as np
+import pytest
+
+import direct_ref as D
+from oracle import oracle as O
+from paper_1910_12979_amd import inputs as I
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def coeffs_of(p):
+    return O.face_coeffs(p.n, p.periodic, p.rho, p.beta0_cc, p.beta0_edge)
+
+
+BCS = [(True, True, False), (False, False, False), (True, True, True), (False, True, False)]
+
+
+# ---------------------------------------------------------------- operator
+@pytest.mark.parametrize("per", BCS)
+def test_operator_matches_face_assembly(per):
+    """Stencil apply == sparse matrix assembled face by face from rho, beta0."""
+    p = I.make_problem((6, 4, 8), H=0.2, rho_noise=0.3, seed=5, periodic=per, dx=0.125)
+    A = D.assemble(p.n, per, p.dx, p.rho, p.beta0_cc, p.beta0_edge)
+    phi = np.random.default_rng(1).standard_normal(p.rho.shape)
+    got = O.apply(p.n, per, p.dx, coeffs_of(p), phi)
+    want = (A @ phi.ravel()).reshape(phi.shape)
+    assert rel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("per", BCS)
+def test_rhs_matches_face_divergence(per):
+    """f = D(beta0 U) - beta0 S matches a face-by-face flux accumulation."""
+    p = I.make_problem((6, 4, 8), H=0.2, seed=7, periodic=per, dx=0.125)
+    f = O.rhs(p.n, per, p.dx, p.beta0_cc, p.beta0_edge, p.u, p.v, p.w, p.S)
+    want = D.divergence(p.n, per, p.dx, p.beta0_cc, p.beta0_edge, p.u, p.v, p.w) \
+        - p.beta0_cc[:, None, None] * p.S
+    assert rel(f, want) < 1e-13
+
+
+def test_operator_invariants():
+    """L 1 = 0 and <Lx, y> = <x, Ly> (symmetric, constant null space)."""
+    p = I.make_problem((8, 6, 10), H=0.1, rho_noise=0.2, seed=3, dx=0.1)
+    c = coeffs_of(p)
+    one = np.ones(p.rho.shape)
+    assert np.max(np.abs(O.apply(p.n, p.periodic, p.dx, c, one))) < 1e-10
+    rng = np.random.default_rng(0)
+    x, y = rng.standard_normal(p.rho.shape), rng.standard_normal(p.rho.shape)
+    lhs = np.vdot(O.apply(p.n, p.periodic, p.dx, c, x), y)
+    rhs = np.vdot(x, O.apply(p.n, p.periodic, p.dx, c, y))
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+def _eigen_problem(n):
+    """rho = beta0 = 1 so b = 1 on every non-wall face."""
+    h = 1.0 / n
+    x, y, z = I.domain_centres((n, n, n), h)
+    phi = (np.cos(np.pi * z)[:, None, None] * np.cos(2 * np.pi * y)[None, :, None]
+           * np.cos(2 * np.pi * x)[None, None, :])
+    lam = -(4.0 / h ** 2) * (2 * np.sin(np.pi * h) ** 2 + np.sin(np.pi * h / 2) ** 2)
+    ones = np.ones((n, n, n))
+    c = O.face_coeffs((n, n, n), (True, True, False), ones, np.ones(n), np.ones(n + 1))
+    return h, phi, lam, c
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_closed_form_eigenmode(n):
+    """cos(2 pi x)cos(2 pi y)cos(pi z) is an exact eigenvector of the discrete L."""
+    h, phi, lam, c = _eigen_problem(n)
+    got = O.apply((n, n, n), (True, True, False), h, c, phi)
+    assert rel(got, lam * phi) < 1e-13
+    H = O.Hierarchy((n, n, n), (True, True, False), h, c)
+    st, sol, _ = H.solve(lam * phi, mode="definition")
+    assert st == 0
+    assert rel(sol, phi) < 1e-12
+
+
+def test_coarse_operator_is_rediscretised():
+    """With b = 1 the level-1 operator is the 2h Laplacian (its eigenvalue)."""
+    n = 16
+    h, _, _, c = _eigen_problem(n)
+    H = O.Hierarchy((n, n, n), (True, True, False), h, c)
+    (nx, ny, nz), h1 = H.level(1)
+    assert (nx, h1) == (8, 2 * h)
+    c1 = (H.get(1, "bx"), H.get(1, "by"), H.get(1, "bz"))
+    _, phi1, lam1, _ = _eigen_problem(8)
+    got = O.apply((8, 8, 8), (True, True, False), h1, c1, phi1)
+    assert rel(got, lam1 * phi1) < 1e-13
+    assert np.all(c1[0] == 1.0) and np.all(c1[2][1:-1] == 1.0) and np.all(c1[2][[0, -1]] == 0.0)
+
+
+def test_one_dimensional_reduction():
+    """rho, beta0, f depending on z only: the 3-D solve equals the exact 1-D solution."""
+    n = (4, 4, 64)
+    h = 1.0 / 64
+    zc = (np.arange(64) + 0.5) * h
+    b0c, b0e = I.stratified_base_state(64, h, 0.1)          # contrast ~2e4
+    rho = np.broadcast_to((b0c * (1 + 0.3 * np.sin(7 * zc)))[:, None, None], (64, 4, 4)).copy()
+    fz = np.cos(3 * np.pi * zc) + 0.2 * zc
+    fz -= fz.mean()
+    f = np.broadcast_to(fz[:, None, None], (64, 4, 4)).copy()
+    c = O.face_coeffs(n, (True, True, False), rho, b0c, b0e)
+    H = O.Hierarchy(n, (True, True, False), h, c)
+    st, phi, _ = H.solve(f, mode="definition")
+    assert st == 0
+    bz_faces = np.zeros(65)
+    bz_faces[1:64] = b0e[1:64] / (0.5 * (rho[:-1, 0, 0] + rho[1:, 0, 0]))
+    want = D.column_solve_1d(h, bz_faces, fz)
+    assert rel(phi[:, 1, 2], want) < 1e-11
+    assert np.max(np.abs(phi - phi[:, :1, :1])) < 1e-12 * np.max(np.abs(phi))
+
+
+@pytest.mark.parametrize("per", BCS[:3])
+def test_mg_vs_dense_bordered_solve_8(per):
+    """8^3: MG (definition) = dense LU of the bordered system [A 1; 1^T 0]."""
+    p = I.make_problem(8, H=0.1, rho_noise=0.2, seed=11, periodic=per)
+    A = D.assemble(p.n, per, p.dx, p.rho, p.beta0_cc, p.beta0_edge)
+    f = O.rhs(p.n, per, p.dx, p.beta0_cc, p.beta0_edge, p.u, p.v, p.w, p.S)
+    f -= f.mean()
+    want = D.solve_bordered_dense(A, f).reshape(f.shape)
+    H = O.Hierarchy(p.n, per, p.dx, coeffs_of(p))
+    st, phi, _ = H.solve(f, mode="definition")
+    assert st == 0
+    assert rel(phi, want) < 1e-12
+    st, phi_a, hist = H.solve(f, rtol=1e-10)
+    assert st == 0 and hist[-1] <= 1e-10
+    assert rel(phi_a, want) < 1e-9
+
+
+@pytest.mark.parametrize("n,seed", [(16, 12), (32, 0)])
+def test_mg_vs_sparse_lu(n, seed):
+    """16^3 and the 32^3 small box: full projection == sparse LU + face-wise correction."""
+    p = I.SMALL_BOX(seed) if n == 32 else I.make_problem(n, H=0.1, seed=seed)
+    A = D.assemble(p.n, p.periodic, p.dx, p.rho, p.beta0_cc, p.beta0_edge)
+    f = D.divergence(p.n, p.periodic, p.dx, p.beta0_cc, p.beta0_edge, p.u, p.v, p.w) \
+        - p.beta0_cc[:, None, None] * p.S
+    assert abs(f.sum()) <= 1e-8 * np.abs(f).sum()
+    f -= f.mean()
+    want = D.solve_pinned_sparse(A, f).reshape(f.shape)
+    res = O.mac_project(p, mode="definition")
+    assert res["status"] == 0
+    assert rel(res["phi"], want) < 1e-11
+    u, v, w = D.gradient_update(p.n, p.periodic, p.dx, p.rho, p.beta0_cc, p.beta0_edge,
+                                want, p.u, p.v, p.w)
+    # G amplifies the reference's own LU round-off by 1/h: 1e-10 on U
+    for got, exp in zip((res["u"], res["v"], res["w"]), (u, v, w)):
+        assert rel(got, exp) < 1e-10
+    alg = O.mac_project(p)
+    assert alg["status"] == 0 and alg["rel_resid"] <= 1e-10
+    assert rel(alg["phi"], want) < 1e-9
+
+
+# -------------------------------------------------------- smoother / transfer
+def test_rbgs_red_first_black_residual_zero():
+    """After one sweep (red then black) the black cells' residual vanishes."""
+    p = I.make_problem((8, 8, 8), H=0.2, rho_noise=0.1, seed=2)
+    c = coeffs_of(p)
+    f = np.random.default_rng(3).standard_normal(p.rho.shape)
+    f -= f.mean()
+    phi0 = np.random.default_rng(4).standard_normal(p.rho.shape)
+    phi = O.rbgs(p.n, p.periodic, p.dx, c, phi0, f, 1)
+    r = O.residual(p.n, p.periodic, p.dx, c, phi, f)
+    k, j, i = np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij")
+    black = (i + j + k) % 2 == 1
+    scale = np.max(np.abs(f))
+    assert np.max(np.abs(r[black])) < 1e-12 * scale
+    assert np.max(np.abs(r[~black])) > 1e-3 * scale
+    # red cells after the sweep depend only on the black cells before it
+    phi_b = phi0.copy()
+    phi_b[~black] = 123.0
+    assert np.array_equal(O.rbgs(p.n, p.periodic, p.dx, c, phi_b, f, 1)[~black], phi[~black])
+
+
+def test_rbgs_fixed_point():
+    """The exact discrete solution is left unchanged by a sweep."""
+    p = I.make_problem(8, H=0.2, seed=21)
+    c = coeffs_of(p)
+    A = D.assemble(p.n, p.periodic, p.dx, p.rho, p.beta0_cc, p.beta0_edge)
+    f = np.random.default_rng(0).standard_normal(p.rho.shape)
+    f -= f.mean()
+    x = D.solve_bordered_dense(A, f).reshape(f.shape)
+    assert rel(O.rbgs(p.n, p.periodic, p.dx, c, x, f, 2), x) < 1e-12
+
+
+def test_restriction_and_prolongation():
+    """R = 8-cell average (block reshape mean), P = parent injection = 8 R^T."""
+    p = I.make_problem((16, 8, 12), H=0.3, seed=9, dx=1 / 16)
+    H = O.Hierarchy(p.n, p.periodic, p.dx, coeffs_of(p))
+    rng = np.random.default_rng(5)
+    phi = rng.standard_normal((12, 8, 16))
+    f = rng.standard_normal((12, 8, 16))
+    H.set(0, "phi", phi)
+    H.set(0, "f", f)
+    H.resid_restrict(0)
+    r = H.get(0, "r")
+    c = coeffs_of(p)
+    assert rel(r, O.residual(p.n, p.periodic, p.dx, c, phi, f)) < 1e-15
+    fc = H.get(1, "f")
+    want = r.reshape(6, 2, 4, 2, 8, 2).mean(axis=(1, 3, 5))
+    assert rel(fc, want) < 1e-14
+    assert np.all(H.get(1, "phi") == 0.0)
+    e = rng.standard_normal((6, 4, 8))
+    H.set(1, "phi", e)
+    H.set(0, "phi", phi)
+    H.prolong(0)
+    want_p = phi + np.repeat(np.repeat(np.repeat(e, 2, 0), 2, 1), 2, 2)
+    assert rel(H.get(0, "phi"), want_p) < 1e-15
+    # adjointness <R r, e> * 8 = <r, P e>
+    Pe = np.repeat(np.repeat(np.repeat(e, 2, 0), 2, 1), 2, 2)
+    assert abs(8 * np.vdot(want, e) - np.vdot(r, Pe)) < 1e-11 * abs(np.vdot(r, Pe))
+
+
+def test_coarse_coefficients_are_four_face_means():
+    p = I.make_problem((8, 8, 8), H=0.2, rho_noise=0.3, seed=4)
+    c = coeffs_of(p)
+    H = O.Hierarchy(p.n, p.periodic, p.dx, c)
+    bx, by, bz = c
+    want_x = 0.25 * (bx[0::2, 0::2, 0::2] + bx[0::2, 1::2, 0::2] + bx[1::2, 0::2, 0::2] + bx[1::2, 1::2, 0::2])
+    want_y = 0.25 * (by[0::2, 0::2, 0::2] + by[0::2, 0::2, 1::2] + by[1::2, 0::2, 0::2] + by[1::2, 0::2, 1::2])
+    want_z = 0.25 * (bz[0::2, 0::2, 0::2] + bz[0::2, 0::2, 1::2] + bz[0::2, 1::2, 0::2] + bz[0::2, 1::2, 1::2])
+    assert rel(H.get(1, "bx"), want_x) < 1e-15
+    assert rel(H.get(1, "by"), want_y) < 1e-15
+    assert rel(H.get(1, "bz"), want_z) < 1e-15
+
+
+def test_coarse_solve_is_min_norm_least_squares():
+    """Coarsest exact solve = zero-mean solution (numpy lstsq of the singular system)."""
+    p = I.make_problem((4, 4, 4), H=0.2, rho_noise=0.3, seed=8, dx=0.25)
+    A = D.assemble(p.n, p.periodic, p.dx, p.rho, p.beta0_cc, p.beta0_edge).toarray()
+    H = O.Hierarchy(p.n, p.periodic, p.dx, coeffs_of(p))
+    assert H.nlevels == 1
+    f = np.random.default_rng(1).standard_normal((4, 4, 4))
+    H.set(0, "f", f)
+    H.coarse()
+    fm = (f - f.mean()).ravel()
+    want = np.linalg.lstsq(A, fm, rcond=None)[0]
+    assert rel(H.get(0, "phi").ravel(), want - want.mean()) < 1e-12
+
+
+def test_level_count_rule():
+    assert O.num_levels((256, 256, 256)) == 7      # 256 -> 4
+    assert O.num_levels((32, 32, 32)) == 4          # 32 -> 4
+    assert O.num_levels((48, 48, 48)) == 5          # 48 -> 3
+    assert O.num_levels((96, 96, 96)) == 6          # 96 -> 3
+    assert O.num_levels((8, 8, 8)) == 2
+    assert O.num_levels((4, 4, 4)) == 1
+    assert O.num_levels((37, 37, 37)) == 0          # odd and > 512 cells
+    assert O.num_levels((6, 10, 14)) == 2           # 840 -> 105 (odd dims stop)
+
+
+# -------------------------------------------------- whole projection pins
+def _hodge_problem(n, seed):
+    """beta0 U_sol = discrete curl of an edge potential (zero on the z walls)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    b0c, b0e = I.stratified_base_state(n, h, 0.2)
+    rho = b0c[:, None, None] * (1 + 0.2 * rng.standard_normal((n, n, n)))
+    Ax = rng.standard_normal((n + 1, n, n))   # x-edges (k node, j node, i+1/2)
+    Ay = rng.standard_normal((n + 1, n, n))   # y-edges (k node, j+1/2, i node)
+    Az = rng.standard_normal((n, n, n))       # z-edges (k+1/2, j node, i node)
+    Ax[0] = Ax[-1] = 0.0
+    Ay[0] = Ay[-1] = 0.0
+    # fluxes through faces, periodic in x and y
+    Fx = ((np.roll(Az, -1, axis=1) - Az) - (Ay[1:] - Ay[:-1])) / h            # (n,n,n): face i
+    Fy = ((Ax[1:] - Ax[:-1]) - (np.roll(Az, -1, axis=2) - Az)) / h            # face j
+    Fz = ((np.roll(Ay, -1, axis=2) - Ay) - (np.roll(Ax, -1, axis=1) - Ax)) / h  # (n+1,n,n)
+    # node-centred potentials put the flux of x-face i at (i, j+1/2, k+1/2);
+    # index i of Fx is x-face i
+    u = np.zeros((n, n, n + 1))
+    v = np.zeros((n, n + 1, n))
+    w = np.zeros((n + 1, n, n))
+    u[:, :, :n] = Fx / b0c[:, None, None]
+    u[:, :, n] = u[:, :, 0]
+    v[:, :n, :] = Fy / b0c[:, None, None]
+    v[:, n, :] = v[:, 0, :]
+    w[:] = Fz / b0e[:, None, None]
+    psi = rng.standard_normal((n, n, n))
+    return h, b0c, b0e, rho, u, v, w, psi
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_manufactured_hodge_decomposition(n):
+    """U* = U_sol + (1/rho) grad psi with div(beta0 U_sol)=0, S=0: the projection
+    returns U_sol and phi = psi - mean(psi)."""
+    h, b0c, b0e, rho, u, v, w, psi = _hodge_problem(n, seed=n)
+    per = (True, True, False)
+    div0 = D.divergence((n, n, n), per, h, b0c, b0e, u, v, w)
+    assert np.max(np.abs(div0)) < 1e-10 * np.max(np.abs(u)) / h
+    us, vs, ws = D.gradient_update((n, n, n), per, h, rho, b0c, b0e, -psi, u, v, w)
+    prob = I.Problem(n=(n, n, n), dx=h, periodic=per, rho=rho, beta0_cc=b0c, beta0_edge=b0e,
+                     S=np.zeros((n, n, n)), u=us, v=vs, w=ws)
+    res = O.mac_project(prob, mode="definition")
+    assert res["status"] == 0
+    assert rel(res["phi"], psi - psi.mean()) < 1e-10
+    for got, exp in zip((res["u"], res["v"], res["w"]), (u, v, w)):
+        assert rel(got, exp) < 1e-10
+
+
+def test_post_projection_constraint_and_idempotence():
+    """D(beta0 U_new) - beta0 S equals the final residual; projecting twice is a no-op;
+    adding a constant to phi leaves the corrected U unchanged."""
+    p = I.make_problem(16, H=0.1, rho_noise=0.05, seed=31)
+    res = O.mac_project(p)
+    assert res["status"] == 0
+    c = coeffs_of(p)
+    f = O.rhs(p.n, p.periodic, p.dx, p.beta0_cc, p.beta0_edge, p.u, p.v, p.w, p.S)
+    f -= f.mean()
+    r = O.residual(p.n, p.periodic, p.dx, c, res["phi"], f)
+    div_new = O.rhs(p.n, p.periodic, p.dx, p.beta0_cc, p.beta0_edge, res["u"], res["v"], res["w"], p.S)
+    assert np.max(np.abs((div_new - res["mean_removed"]) - r)) < 1e-13 * np.max(np.abs(f))
+    assert np.linalg.norm(div_new - div_new.mean()) <= 1.01e-10 * np.linalg.norm(f)
+    q = p.copy()
+    q.u, q.v, q.w = res["u"], res["v"], res["w"]
+    res2 = O.mac_project(q, mode="definition")
+    assert np.linalg.norm(res2["phi"]) <= 1e-9 * np.linalg.norm(res["phi"])
+    for a, b in zip((res2["u"], res2["v"], res2["w"]), (res["u"], res["v"], res["w"])):
+        assert rel(a, b) < 1e-10
+    u1 = O.correct(p.n, p.periodic, p.dx, p.beta0_cc, p.beta0_edge, c, res["phi"], p.u, p.v, p.w)
+    shift = 0.5 * np.max(np.abs(res["phi"]))     # exact only up to the shift's rounding
+    u2 = O.correct(p.n, p.periodic, p.dx, p.beta0_cc, p.beta0_edge, c, res["phi"] + shift, p.u, p.v, p.w)
+    for a, b in zip(u1, u2):
+        assert rel(a, b) < 1e-11
+
+
+def test_second_order_consistency():
+    """Manufactured continuous solution: error falls ~4x per refinement."""
+    errs = []
+    for n in (16, 32, 64):
+        h = 1.0 / n
+        x, y, z = I.domain_centres((n, n, n), h)
+        X, Y, Z = x[None, None, :], y[None, :, None], z[:, None, None]
+        sx, cx = np.sin(2 * np.pi * X), np.cos(2 * np.pi * X)
+        sy, cy = np.sin(2 * np.pi * Y), np.cos(2 * np.pi * Y)
+        cz = np.cos(np.pi * Z)
+        a = 1 + 0.5 * sx * sy
+        phi = cx * cy * cz
+        f = -9 * np.pi ** 2 * a * phi - 4 * np.pi ** 2 * sx * cx * sy * cy * cz
+        f = np.ascontiguousarray(f - f.mean())
+        rho = np.ascontiguousarray(np.broadcast_to(1.0 / a, (n, n, n)))
+        c = O.face_coeffs((n, n, n), (True, True, False), rho, np.ones(n), np.ones(n + 1))
+        H = O.Hierarchy((n, n, n), (True, True, False), h, c)
+        st, sol, _ = H.solve(f, mode="definition")
+        assert st == 0
+        ex = phi - phi.mean()
+        errs.append(np.max(np.abs(sol - ex)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.6 and 3.7 < r2 < 4.3, errs
+
+
+def test_convergence_factor_and_history():
+    """The V(2,2) cycle contracts the residual well below 0.3 per cycle."""
+    p = I.make_problem(32, H=0.1, seed=1)
+    res = O.mac_project(p)
+    assert res["status"] == 0
+    h = res["hist"]
+    assert h[0] == 1.0 and np.all(np.diff(h) < 0)
+    assert np.max(h[1:] / h[:-1]) < 0.3
+    assert res["cycles"] <= 14
+
+
+# ------------------------------------------------------------ error paths
+def test_oracle_error_codes():
+    p = I.make_problem(8, seed=1)
+    q = p.copy(); q.w[0, 2, 3] = 1.0           # flux through a solid wall
+    assert O.mac_project(q)["status_name"] == "INCOMPATIBLE_RHS"
+    q = p.copy(); q.rho[1, 1, 1] = -1.0
+    assert O.mac_project(q)["status_name"] == "INVALID_ARG"
+    q = p.copy(); q.S[0, 0, 0] = np.nan
+    assert O.mac_project(q)["status_name"] == "NONFINITE"
+    q = p.copy(); q.max_cycles = 1
+    r = O.mac_project(q)
+    assert r["status_name"] == "NOT_CONVERGED" and r["cycles"] == 1
+    big = I.make_problem(37, seed=1)
+    assert O.mac_project(big)["status_name"] == "BAD_SIZE"
+    z = I.make_problem(8, S_kind="zero", vel_scale=0.0, seed=1)
+    r = O.mac_project(z)
+    assert r["status"] == 0 and r["cycles"] == 0 and np.all(r["phi"] == 0.0)
