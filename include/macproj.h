@@ -1,0 +1,216 @@
+/*
+ * macproj.h -- C ABI of the MI355X (gfx950) variable-coefficient MAC projection.
+ *
+ * What the library computes (arXiv:1910.12979):
+ *   The low Mach number velocity obeys the divergence constraint
+ *   div(beta0 U) = beta0 S (Sec. 2, constraint equation; the caller folds the
+ *   d p0/dt term into S).  A projection enforces it (Sec. 3: second-order
+ *   projection method with multigrid solvers): solve
+ *       div((beta0/rho) grad phi) = div(beta0 U) - beta0 S
+ *   by geometric multigrid and correct the face velocities
+ *       U <- U - (1/rho) grad phi
+ *   which is the (beta0/rho) grad(.) pressure-gradient form of the momentum
+ *   equation (Sec. 2) with the potential absorbing beta0.  beta0(r) is the
+ *   1-D base state (Sec. 2, beta0 definition) taken along the height z.
+ *
+ * Discretisation: uniform cubic cells of spacing dx, cell-centred phi, rho, S;
+ * face-normal velocities (MAC).  Face coefficient
+ *     b = beta0_face / (0.5 (rho_left + rho_right)),
+ * beta0_face = beta0_cc[k] on x and y faces of layer k, beta0_edge[k] on the
+ * z face k.  (L phi)_c = dx^-2 sum_faces b (phi_nb - phi_c).  Solid-wall faces
+ * carry no flux and their normal velocity is never modified.  In a periodic
+ * direction face n duplicates face 0: it is ignored on input and overwritten
+ * with face 0 on output.
+ *
+ * Multigrid: V(pre, post) cycles of red-black Gauss-Seidel (red =
+ * (i+j+k) even, first), 8-cell-average restriction, piecewise-constant
+ * prolongation, coarse coefficients = mean of the 4 coincident fine faces,
+ * coarsening while every dimension is even and the level has more than 64
+ * cells; exact solve on the coarsest level (at most 512 cells).  Stop when
+ * ||f - L phi||_2 / ||f||_2 <= rtol (f after mean removal).
+ *
+ * Layout: every field is float64, C order [k][j][i] (i fastest), contiguous:
+ *   rho, S, phi      (nz, ny, nx)
+ *   u                (nz, ny, nx+1)   face i between cells i-1 and i
+ *   v                (nz, ny+1, nx)
+ *   w                (nz+1, ny, nx)
+ *   beta0_cc (nz), beta0_edge (nz+1)
+ * All field pointers are DEVICE pointers on the current HIP device, owned by
+ * the caller, which keeps them alive until the call (or ticket) completes.
+ * Streams are hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Errors: every int-returning call returns MG_OK (0), MG_PENDING (1) or a
+ * negative mg_status.  No C++ exception crosses this boundary and the library
+ * never exits or aborts.  mg_last_error() gives a thread-local detail string.
+ */
+#ifndef MACPROJ_H
+#define MACPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_PENDING = 1,
+    MG_ERR_INVALID_ARG = -1,      /* null pointer, rho <= 0, beta0 <= 0, dx <= 0, bad bc */
+    MG_ERR_BAD_SIZE = -2,         /* coarsest level would exceed 512 cells, or n < 1 */
+    MG_ERR_INCOMPATIBLE_RHS = -3, /* |sum f| > 1e-8 sum |f|: no solution exists */
+    MG_ERR_NOT_CONVERGED = -4,    /* max_cycles reached; outputs and stats still written */
+    MG_ERR_NONFINITE = -5,        /* NaN/Inf in an input or in the residual */
+    MG_ERR_OOM = -6,
+    MG_ERR_HIP = -7,              /* a HIP runtime call failed, detail in mg_last_error() */
+    MG_ERR_BUDGET = -8,           /* a request can never fit the server's memory budget */
+    MG_ERR_BUSY = -9              /* no free slot right now (non-blocking submit) */
+} mg_status;
+
+typedef enum { MG_BC_PERIODIC = 0, MG_BC_WALL = 1 } mg_bc;
+typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
+
+typedef struct {
+    int32_t n[3];            /* nx, ny, nz (cells) */
+    double  dx;              /* uniform cubic spacing */
+    int32_t bc[3];           /* per direction, both sides: MG_BC_PERIODIC or MG_BC_WALL */
+    int32_t pre_sweeps;      /* red-black GS sweeps before restriction (default 2) */
+    int32_t post_sweeps;     /* sweeps after prolongation (default 2) */
+    double  rtol;            /* relative L2 residual target (default 1e-10) */
+    int32_t max_cycles;      /* V-cycles (or refinement steps) cap (default 100) */
+    int32_t precision;       /* mg_precision */
+} mg_params;
+
+#define MG_HIST_MAX 128
+
+typedef struct {
+    int32_t status;          /* mg_status of the solve */
+    int32_t cycles;          /* V-cycles (FP64) or refinement steps (mixed) */
+    int32_t nlevels;
+    int32_t hist_len;        /* entries used in resid_hist */
+    double  rel_resid;       /* final ||f - L phi||_2 / ||f||_2 */
+    double  mean_removed;    /* mean of the right-hand side before removal */
+    double  sum_f, sum_abs_f, norm_f;
+    double  phi_mean;        /* mean removed from phi on exit */
+    double  ms_total;        /* device time of the call (HIP events) */
+    double  bytes_model;     /* algorithmic HBM bytes of the call */
+    double  resid_hist[MG_HIST_MAX]; /* relative residual after c cycles, [0] = 1 */
+} mg_stats;
+
+typedef struct mg_hierarchy* mg_handle;
+
+/* One problem for project_batch / serve_submit.  Pointers as for mac_project. */
+typedef struct {
+    mg_params p;
+    const double* rho;
+    const double* beta0_cc;
+    const double* beta0_edge;
+    const double* S;
+    double* u;
+    double* v;
+    double* w;
+    double* phi;             /* nullable */
+} mg_problem;
+
+/* Fill *p with the defaults (V(2,2), rtol 1e-10, 100 cycles, FP64,
+ * periodic x,y and walls in z) for an nx*ny*nz box of spacing dx. */
+void mg_default_params(mg_params* p, int32_t nx, int32_t ny, int32_t nz, double dx);
+
+/* Number of multigrid levels for params (0 if the shape is not solvable). */
+int32_t mg_num_levels_for(const mg_params* p);
+
+/* Device bytes the hierarchy needs for params (0 on invalid params). */
+size_t mg_workspace_bytes(const mg_params* p);
+
+/* Build a hierarchy for the shape in *p on the current device.
+ * workspace: NULL -> the library allocates (and frees in mg_destroy);
+ * otherwise a device buffer of at least mg_workspace_bytes(p) bytes, 256-byte
+ * aligned, owned by the caller and kept alive until mg_destroy. */
+int mg_setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_handle* out);
+
+/* Release a hierarchy (NULL is allowed). */
+int mg_destroy(mg_handle h);
+
+/* Replace the solver controls (rtol, max_cycles, sweeps, precision) of h.
+ * The shape, dx and bc must equal those given to mg_setup. */
+int mg_set_params(mg_handle h, const mg_params* p);
+
+/* Face coefficients b = beta0/rho_face on every level and the coarsest-level
+ * factorisation, from rho (nz,ny,nx), beta0_cc (nz), beta0_edge (nz+1).
+ * mac_project calls this itself; exposed for mg_vcycle users. */
+int mg_set_coefficients(mg_handle h, const double* rho, const double* beta0_cc,
+                        const double* beta0_edge, void* stream);
+
+/* The whole projection: coefficients and right-hand side from (rho, beta0,
+ * U, S), compatibility check and mean removal, V-cycles to rtol, mean removal
+ * of phi, velocity correction.  u, v, w are updated in place; phi (nullable)
+ * receives the zero-mean potential.  Blocks until the work on `stream` is
+ * done.  stats may be NULL. */
+int mac_project(mg_handle h, const double* rho, const double* beta0_cc,
+                const double* beta0_edge, const double* S, double* u, double* v,
+                double* w, double* phi, mg_stats* stats, void* stream);
+
+/* One V(pre, post) cycle on level 0 with the current coefficients: phi
+ * (nz,ny,nx, in/out) is improved for L phi = rhs (rhs must have zero mean).
+ * *rel_resid_out (nullable) = ||rhs - L phi||_2 / ||rhs||_2 afterwards. */
+int mg_vcycle(mg_handle h, double* phi, const double* rhs, double* rel_resid_out, void* stream);
+
+/* ---- single steps of the cycle, for step-by-step verification ---------- */
+typedef enum {
+    MG_STEP_SMOOTH = 0,          /* `arg` red-black GS sweeps on level l (phi_l, f_l) */
+    MG_STEP_RESID_RESTRICT = 1,  /* f_{l+1} = R (f_l - L phi_l); phi_{l+1} = 0 */
+    MG_STEP_PROLONG = 2,         /* phi_l += P phi_{l+1} */
+    MG_STEP_COARSE = 3,          /* exact solve on the coarsest level */
+    MG_STEP_DOWN = 4,            /* fused: `arg` sweeps + residual + restriction */
+    MG_STEP_UP = 5               /* fused: prolongation + `arg` sweeps */
+} mg_step;
+
+typedef enum { MG_ARR_PHI = 0, MG_ARR_F = 1, MG_ARR_BX = 2, MG_ARR_BY = 3, MG_ARR_BZ = 4 } mg_array;
+
+/* Level l's shape and spacing. */
+int mg_level_info(mg_handle h, int32_t level, int32_t dims[3], double* dx);
+
+/* Copy a level array between the hierarchy and a caller device buffer,
+ * enqueued on `stream`
+ * (to_hierarchy = 1: buffer -> hierarchy).  Cell arrays are (nz,ny,nx); the
+ * coefficient arrays hold, per cell, the coefficient of its LOW face in that
+ * direction (face n of a periodic direction is face 0; walls hold 0). */
+int mg_level_copy(mg_handle h, int32_t level, int32_t array, void* buffer,
+                  int32_t to_hierarchy, void* stream);
+
+/* Run one step (mg_step) on level l.  Like mg_level_copy, stream-ordered:
+ * returns after enqueueing the work on `stream`. */
+int mg_level_step(mg_handle h, int32_t level, int32_t step, int32_t arg, void* stream);
+
+/* ---- batches and serving ------------------------------------------------ */
+
+/* Solve `count` independent problems (any shapes, each with its own params)
+ * with shared launches; stats has `count` entries (nullable).  Each result is
+ * the one mac_project gives for that problem alone.  Blocks until done. */
+int project_batch(int32_t count, const mg_problem* probs, mg_stats* stats, void* stream);
+
+/* Continuous-batching server on the current device.  hbm_budget_bytes caps
+ * the device memory of resident hierarchies plus in-flight work;
+ * max_inflight caps the problems on the device at once. */
+int serve_create(size_t hbm_budget_bytes, int32_t max_inflight, void** server);
+/* Queue a problem; never blocks.  The problem's buffers must stay alive until
+ * its ticket completes. */
+int serve_submit(void* server, const mg_problem* prob, uint64_t* ticket);
+/* MG_PENDING while the ticket is queued or running; else its final status,
+ * with *out (nullable) filled. */
+int serve_poll(void* server, uint64_t ticket, mg_stats* out);
+/* Block until the ticket completes; returns its status. */
+int serve_wait(void* server, uint64_t ticket, mg_stats* out);
+/* Server counters: [0] submitted, [1] completed, [2] queued, [3] in flight,
+ * [4] resident bytes, [5] peak in-flight problems. */
+int serve_counters(void* server, double out[6]);
+/* Finish all tickets and release the server. */
+int serve_destroy(void* server);
+
+const char* mg_strerror(int code);
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MACPROJ_H */

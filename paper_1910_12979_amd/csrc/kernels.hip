@@ -1,0 +1,670 @@
+// gfx950 kernels of the MAC projection: coefficients and right-hand side,
+// red-black Gauss-Seidel, residual + restriction, prolongation, residual norm,
+// coarsest-level direct solve and velocity correction.
+//
+// The operator is the cell-centred discretisation of div((beta0/rho) grad phi)
+// whose right-hand side is div(beta0 U) - beta0 S (arXiv:1910.12979, Sec. 2,
+// divergence constraint), solved by multigrid as the paper's projections are
+// (Sec. 3).  Every kernel here is HBM-bandwidth bound: plain coalesced sweeps,
+// one thread per cell, fixed-order reductions so results are reproducible.
+//
+// Arithmetic order inside each cell update follows the face order x-low,
+// x-high, y-low, y-high, z-low, z-high; the library is compiled without FMA
+// contraction so the per-cell results do not depend on which kernel variant
+// (single problem, batched) evaluates them.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "mg_internal.h"
+
+namespace mg {
+namespace {
+
+constexpr int kBlock = 256;          // threads per block for cell kernels
+constexpr int kMaxPartialBlocks = 2048;
+
+struct Launch3 {
+    dim3 grid, block;
+};
+
+inline int pow2_at_least(int v, int cap) {
+    int p = 1;
+    while (p < v && p < cap) p <<= 1;
+    return p;
+}
+
+// Block shape: up to 64 threads along x (one wavefront per row), the rest
+// along y then z; grid covers the box.
+inline Launch3 cell_launch(int nx, int ny, int nz) {
+    int bx = pow2_at_least(nx, 64);
+    int by = pow2_at_least(ny, kBlock / bx);
+    int bz = pow2_at_least(nz, kBlock / (bx * by));
+    Launch3 L;
+    L.block = dim3(bx, by, bz);
+    L.grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, (nz + bz - 1) / bz);
+    return L;
+}
+
+inline int partial_blocks(size_t N) {
+    size_t b = (N + kBlock - 1) / kBlock;
+    return (int)(b < (size_t)kMaxPartialBlocks ? b : (size_t)kMaxPartialBlocks);
+}
+
+__device__ inline size_t cidx(int i, int j, int k, int nx, int ny) {
+    return ((size_t)k * ny + j) * nx + i;
+}
+
+// Reduce a row of 4 values over a 1-D block of kBlock threads: [0],[1],[3]
+// summed, [2] max.  Fixed tree order.  Thread 0 writes the row.
+__device__ void block_reduce_row(double v0, double v1, double v2, double v3, double* out) {
+    __shared__ double sh[4][kBlock];
+    int t = threadIdx.x;
+    sh[0][t] = v0;
+    sh[1][t] = v1;
+    sh[2][t] = v2;
+    sh[3][t] = v3;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sh[0][t] = sh[0][t] + sh[0][t + s];
+            sh[1][t] = sh[1][t] + sh[1][t + s];
+            sh[2][t] = fmax(sh[2][t], sh[2][t + s]);
+            sh[3][t] = sh[3][t] + sh[3][t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = sh[0][0];
+        out[1] = sh[1][0];
+        out[2] = sh[2][0];
+        out[3] = sh[3][0];
+    }
+}
+
+__device__ inline bool finite_d(double x) { return isfinite(x); }
+
+// ---------------------------------------------------------------------------
+// Level-0 face coefficients (+ optional right-hand side).  Grid-stride over
+// cells so the number of partial rows stays small.
+// ---------------------------------------------------------------------------
+template <bool kRhs>
+__global__ __launch_bounds__(kBlock) void k_coeff_rhs(
+    int nx, int ny, int nz, int px, int py, int pz, double h, const double* __restrict__ rho,
+    const double* __restrict__ b0c, const double* __restrict__ b0e, const double* __restrict__ S,
+    const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+    double* __restrict__ bx, double* __restrict__ by, double* __restrict__ bz,
+    double* __restrict__ f, double* __restrict__ partials) {
+    const size_t N = (size_t)nx * ny * nz;
+    double sf = 0.0, saf = 0.0, bad = 0.0, nonfin = 0.0;
+    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock) {
+        int i = (int)(c % nx);
+        int j = (int)((c / nx) % ny);
+        int k = (int)(c / ((size_t)nx * ny));
+        double rc = rho[c];
+        double bk = b0c[k];
+        double bek = b0e[k];
+        if (!finite_d(rc) || !finite_d(bk) || !finite_d(bek)) nonfin += 1.0;
+        if (!(rc > 0.0) || !(bk > 0.0) || !(bek > 0.0)) bad = 1.0;
+        // x-low face i
+        double cx;
+        if (i > 0) cx = bk / (0.5 * (rho[c - 1] + rc));
+        else cx = px ? bk / (0.5 * (rho[c + (nx - 1)] + rc)) : 0.0;
+        // y-low face j
+        double cy;
+        if (j > 0) cy = bk / (0.5 * (rho[c - nx] + rc));
+        else cy = py ? bk / (0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc)) : 0.0;
+        // z-low face k (periodic: face 0 uses beta0_edge[0])
+        double cz;
+        size_t plane = (size_t)nx * ny;
+        if (k > 0) cz = bek / (0.5 * (rho[c - plane] + rc));
+        else cz = pz ? b0e[0] / (0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc)) : 0.0;
+        bx[c] = cx;
+        by[c] = cy;
+        bz[c] = cz;
+        if (kRhs) {
+            size_t ub = ((size_t)k * ny + j) * (nx + 1);
+            double ul = u[ub + i];
+            double uh = (i == nx - 1 && px) ? u[ub] : u[ub + i + 1];
+            size_t vb = (size_t)k * (ny + 1) * nx + i;
+            double vl = v[vb + (size_t)j * nx];
+            double vh = (j == ny - 1 && py) ? v[vb] : v[vb + (size_t)(j + 1) * nx];
+            size_t wc = (size_t)j * nx + i;
+            double wl = w[(size_t)k * plane + wc];
+            double bl = b0e[k];
+            double wh, bh;
+            if (k == nz - 1 && pz) {
+                wh = w[wc];
+                bh = b0e[0];
+            } else {
+                wh = w[(size_t)(k + 1) * plane + wc];
+                bh = b0e[k + 1];
+            }
+            if (k == 0 && pz) bl = b0e[0];
+            double sc = S[c];
+            if (!finite_d(ul) || !finite_d(uh) || !finite_d(vl) || !finite_d(vh) ||
+                !finite_d(wl) || !finite_d(wh) || !finite_d(sc))
+                nonfin += 1.0;
+            double div = (bk * (uh - ul) + bk * (vh - vl) + (bh * wh - bl * wl)) / h;
+            double fc = div - bk * sc;
+            f[c] = fc;
+            sf += fc;
+            saf += fabs(fc);
+        }
+    }
+    block_reduce_row(sf, saf, bad, nonfin, partials + (size_t)blockIdx.x * kReduceWidth);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partials, int nparts,
+                                                   double* __restrict__ out) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int r = threadIdx.x; r < nparts; r += kBlock) {
+        const double* p = partials + (size_t)r * kReduceWidth;
+        a0 += p[0];
+        a1 += p[1];
+        a2 = fmax(a2, p[2]);
+        a3 += p[3];
+    }
+    block_reduce_row(a0, a1, a2, a3, out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_shift_norm(size_t N, double* __restrict__ f, double shift,
+                                                       double* __restrict__ partials) {
+    double s = 0.0;
+    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock) {
+        double x = f[c] - shift;
+        f[c] = x;
+        s += x * x;
+    }
+    block_reduce_row(s, 0.0, 0.0, 0.0, partials + (size_t)blockIdx.x * kReduceWidth);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum(size_t N, const double* __restrict__ a,
+                                                double* __restrict__ partials) {
+    double s = 0.0;
+    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock)
+        s += a[c];
+    block_reduce_row(s, 0.0, 0.0, 0.0, partials + (size_t)blockIdx.x * kReduceWidth);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse coefficients: coarse face I <- fine face 2I, averaged over the 2x2
+// fine faces it covers (orders as in the reference definition).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_avg_coeff(int nx, int ny, int nz, const T* __restrict__ bx, const T* __restrict__ by,
+                            const T* __restrict__ bz, T* __restrict__ cbx, T* __restrict__ cby,
+                            T* __restrict__ cbz) {
+    int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    int J = blockIdx.y * blockDim.y + threadIdx.y;
+    int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= cx || J >= cy || K >= cz) return;
+    int i = 2 * I, j = 2 * J, k = 2 * K;
+    size_t C = cidx(I, J, K, cx, cy);
+    const T q = T(0.25);
+    cbx[C] = q * (bx[cidx(i, j, k, nx, ny)] + bx[cidx(i, j + 1, k, nx, ny)] +
+                  bx[cidx(i, j, k + 1, nx, ny)] + bx[cidx(i, j + 1, k + 1, nx, ny)]);
+    cby[C] = q * (by[cidx(i, j, k, nx, ny)] + by[cidx(i + 1, j, k, nx, ny)] +
+                  by[cidx(i, j, k + 1, nx, ny)] + by[cidx(i + 1, j, k + 1, nx, ny)]);
+    cbz[C] = q * (bz[cidx(i, j, k, nx, ny)] + bz[cidx(i + 1, j, k, nx, ny)] +
+                  bz[cidx(i, j + 1, k, nx, ny)] + bz[cidx(i + 1, j + 1, k, nx, ny)]);
+}
+
+// ---------------------------------------------------------------------------
+// Red-black Gauss-Seidel: one colour per launch, one thread per cell of that
+// colour.  phi_c <- (sum_f b_f phi_nb - h^2 f_c) / sum_f b_f.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_rbgs_colour(int nx, int ny, int nz, T h2, T* __restrict__ phi, const T* __restrict__ f,
+                              const T* __restrict__ bx, const T* __restrict__ by,
+                              const T* __restrict__ bz, int colour) {
+    int ih = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y * blockDim.y + threadIdx.y;
+    int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (2 * ih >= nx || j >= ny || k >= nz) return;
+    int i = 2 * ih + ((j + k + colour) & 1);
+    if (i >= nx) return;
+    int im = i > 0 ? i - 1 : nx - 1, ip = i < nx - 1 ? i + 1 : 0;
+    int jm = j > 0 ? j - 1 : ny - 1, jp = j < ny - 1 ? j + 1 : 0;
+    int km = k > 0 ? k - 1 : nz - 1, kp = k < nz - 1 ? k + 1 : 0;
+    size_t c = cidx(i, j, k, nx, ny);
+    T bxl = bx[c], bxh = bx[cidx(ip, j, k, nx, ny)];
+    T byl = by[c], byh = by[cidx(i, jp, k, nx, ny)];
+    T bzl = bz[c], bzh = bz[cidx(i, j, kp, nx, ny)];
+    T num = bxl * phi[cidx(im, j, k, nx, ny)];
+    num = num + bxh * phi[cidx(ip, j, k, nx, ny)];
+    num = num + byl * phi[cidx(i, jm, k, nx, ny)];
+    num = num + byh * phi[cidx(i, jp, k, nx, ny)];
+    num = num + bzl * phi[cidx(i, j, km, nx, ny)];
+    num = num + bzh * phi[cidx(i, j, kp, nx, ny)];
+    T den = bxl + bxh;
+    den = den + byl;
+    den = den + byh;
+    den = den + bzl;
+    den = den + bzh;
+    phi[c] = (num - h2 * f[c]) / den;
+}
+
+// (L phi)_c * h^2 ... returned as (sum_f b_f (phi_nb - phi_c)) / h^2.
+template <typename T>
+__device__ inline T apply_cell(int i, int j, int k, int nx, int ny, int nz, T h2, const T* __restrict__ phi,
+                               const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz) {
+    int im = i > 0 ? i - 1 : nx - 1, ip = i < nx - 1 ? i + 1 : 0;
+    int jm = j > 0 ? j - 1 : ny - 1, jp = j < ny - 1 ? j + 1 : 0;
+    int km = k > 0 ? k - 1 : nz - 1, kp = k < nz - 1 ? k + 1 : 0;
+    size_t c = cidx(i, j, k, nx, ny);
+    T pc = phi[c];
+    T s = bx[c] * (phi[cidx(im, j, k, nx, ny)] - pc);
+    s = s + bx[cidx(ip, j, k, nx, ny)] * (phi[cidx(ip, j, k, nx, ny)] - pc);
+    s = s + by[c] * (phi[cidx(i, jm, k, nx, ny)] - pc);
+    s = s + by[cidx(i, jp, k, nx, ny)] * (phi[cidx(i, jp, k, nx, ny)] - pc);
+    s = s + bz[c] * (phi[cidx(i, j, km, nx, ny)] - pc);
+    s = s + bz[cidx(i, j, kp, nx, ny)] * (phi[cidx(i, j, kp, nx, ny)] - pc);
+    return s / h2;
+}
+
+template <typename T>
+__global__ void k_resid_restrict(int nx, int ny, int nz, T h2, const T* __restrict__ phi,
+                                 const T* __restrict__ f, const T* __restrict__ bx,
+                                 const T* __restrict__ by, const T* __restrict__ bz, T* __restrict__ fc,
+                                 T* __restrict__ phic) {
+    int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    int J = blockIdx.y * blockDim.y + threadIdx.y;
+    int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= cx || J >= cy || K >= cz) return;
+    T s = T(0);
+    for (int dk = 0; dk < 2; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                T r = f[cidx(i, j, k, nx, ny)] - apply_cell<T>(i, j, k, nx, ny, nz, h2, phi, bx, by, bz);
+                s = s + r;
+            }
+    size_t C = cidx(I, J, K, cx, cy);
+    fc[C] = T(0.125) * s;
+    phic[C] = T(0);
+}
+
+template <typename T>
+__global__ void k_prolong(int nx, int ny, int nz, T* __restrict__ phi, const T* __restrict__ phic) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y * blockDim.y + threadIdx.y;
+    int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= nx || j >= ny || k >= nz) return;
+    size_t c = cidx(i, j, k, nx, ny);
+    phi[c] = phi[c] + phic[cidx(i / 2, j / 2, k / 2, nx / 2, ny / 2)];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_resid_norm(int nx, int ny, int nz, T h2, const T* __restrict__ phi,
+                                                       const T* __restrict__ f, const T* __restrict__ bx,
+                                                       const T* __restrict__ by, const T* __restrict__ bz,
+                                                       double* __restrict__ r_out, double* __restrict__ partials) {
+    const size_t N = (size_t)nx * ny * nz;
+    double s = 0.0, mx = 0.0, nonfin = 0.0;
+    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock) {
+        int i = (int)(c % nx);
+        int j = (int)((c / nx) % ny);
+        int k = (int)(c / ((size_t)nx * ny));
+        double r = (double)(f[c] - apply_cell<T>(i, j, k, nx, ny, nz, h2, phi, bx, by, bz));
+        if (r_out) r_out[c] = r;
+        if (!finite_d(r)) nonfin += 1.0;
+        s += r * r;
+        mx = fmax(mx, fabs(r));
+    }
+    block_reduce_row(s, 0.0, mx, nonfin, partials + (size_t)blockIdx.x * kReduceWidth);
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level.  One workgroup builds M = -A + c 1 1^T (c = mean diagonal
+// of -A) and inverts it in place by Gauss-Jordan elimination (M is SPD, so
+// no pivoting is needed).  The per-cycle solve is then a mat-vec.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_coarse_setup(int nx, int ny, int nz, double h,
+                                                         const double* __restrict__ bx,
+                                                         const double* __restrict__ by,
+                                                         const double* __restrict__ bz,
+                                                         double* __restrict__ M) {
+    __shared__ double fac[kCoarseMax];
+    __shared__ double shift;
+    const int n = nx * ny * nz;
+    const double ih2 = 1.0 / (h * h);
+    for (size_t e = threadIdx.x; e < (size_t)n * n; e += kBlock) M[e] = 0.0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += kBlock) {
+        int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+        int im = i > 0 ? i - 1 : nx - 1, ip = i < nx - 1 ? i + 1 : 0;
+        int jm = j > 0 ? j - 1 : ny - 1, jp = j < ny - 1 ? j + 1 : 0;
+        int km = k > 0 ? k - 1 : nz - 1, kp = k < nz - 1 ? k + 1 : 0;
+        double b[6] = {bx[c], bx[cidx(ip, j, k, nx, ny)], by[c], by[cidx(i, jp, k, nx, ny)],
+                       bz[c], bz[cidx(i, j, kp, nx, ny)]};
+        size_t nb[6] = {cidx(im, j, k, nx, ny), cidx(ip, j, k, nx, ny), cidx(i, jm, k, nx, ny),
+                        cidx(i, jp, k, nx, ny), cidx(i, j, km, nx, ny), cidx(i, j, kp, nx, ny)};
+        double* row = M + (size_t)c * n;
+        for (int q = 0; q < 6; ++q) {
+            if (b[q] == 0.0) continue;      // wall face: no coupling
+            row[c] += b[q] * ih2;
+            row[nb[q]] -= b[q] * ih2;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double d = 0.0;
+        for (int c = 0; c < n; ++c) d += M[(size_t)c * n + c];
+        shift = d / n;
+    }
+    __syncthreads();
+    for (size_t e = threadIdx.x; e < (size_t)n * n; e += kBlock) M[e] += shift;
+    __syncthreads();
+    // in-place Gauss-Jordan inversion
+    for (int p = 0; p < n; ++p) {
+        double piv = M[(size_t)p * n + p];
+        __syncthreads();
+        for (int jj = threadIdx.x; jj < n; jj += kBlock)
+            M[(size_t)p * n + jj] = (jj == p) ? 1.0 / piv : M[(size_t)p * n + jj] / piv;
+        for (int ii = threadIdx.x; ii < n; ii += kBlock) fac[ii] = (ii == p) ? 0.0 : M[(size_t)ii * n + p];
+        __syncthreads();
+        for (int ii = threadIdx.x; ii < n; ii += kBlock)
+            if (ii != p) M[(size_t)ii * n + p] = 0.0;
+        __syncthreads();
+        for (size_t e = threadIdx.x; e < (size_t)n * n; e += kBlock) {
+            int ii = (int)(e / n), jj = (int)(e % n);
+            if (ii != p) M[e] -= fac[ii] * M[(size_t)p * n + jj];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __restrict__ Minv,
+                                                         const T* __restrict__ f, T* __restrict__ phi) {
+    __shared__ double rhs[kCoarseMax];
+    __shared__ double x[kCoarseMax];
+    __shared__ double mean;
+    for (int c = threadIdx.x; c < n; c += kBlock) rhs[c] = (double)f[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int c = 0; c < n; ++c) s += rhs[c];
+        mean = s / n;
+    }
+    __syncthreads();
+    double m = mean;
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += kBlock) rhs[c] = -(rhs[c] - m);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += kBlock) {
+        const double* row = Minv + (size_t)r * n;
+        double s = 0.0;
+        for (int c = 0; c < n; ++c) s += row[c] * rhs[c];
+        x[r] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int c = 0; c < n; ++c) s += x[c];
+        mean = s / n;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += kBlock) phi[c] = (T)(x[c] - mean);
+}
+
+// ---------------------------------------------------------------------------
+// Velocity correction: U <- U - (b/beta0)_f (phi_c - phi_nb)/h on every
+// non-wall face (low faces of each cell), periodic duplicate faces refreshed.
+// ---------------------------------------------------------------------------
+__global__ void k_correct(int nx, int ny, int nz, int px, int py, int pz, double h,
+                          const double* __restrict__ b0c, const double* __restrict__ b0e,
+                          const double* __restrict__ bx, const double* __restrict__ by,
+                          const double* __restrict__ bz, const double* __restrict__ phi,
+                          const double* __restrict__ phi_sum, double* __restrict__ u,
+                          double* __restrict__ v, double* __restrict__ w, double* __restrict__ phi_out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y * blockDim.y + threadIdx.y;
+    int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= nx || j >= ny || k >= nz) return;
+    const size_t N = (size_t)nx * ny * nz;
+    const double m = phi_sum[0] / (double)N;
+    size_t c = cidx(i, j, k, nx, ny);
+    double pc = phi[c] - m;
+    if (phi_out) phi_out[c] = pc;
+    size_t plane = (size_t)nx * ny;
+    if (px || i > 0) {
+        int im = i > 0 ? i - 1 : nx - 1;
+        double g = (pc - (phi[cidx(im, j, k, nx, ny)] - m)) / h;
+        size_t e = ((size_t)k * ny + j) * (nx + 1) + i;
+        double un = u[e] - (bx[c] / b0c[k]) * g;
+        u[e] = un;
+        if (px && i == 0) u[e + nx] = un;
+    }
+    if (py || j > 0) {
+        int jm = j > 0 ? j - 1 : ny - 1;
+        double g = (pc - (phi[cidx(i, jm, k, nx, ny)] - m)) / h;
+        size_t e = ((size_t)k * (ny + 1) + j) * nx + i;
+        double vn = v[e] - (by[c] / b0c[k]) * g;
+        v[e] = vn;
+        if (py && j == 0) v[e + (size_t)ny * nx] = vn;
+    }
+    if (pz || k > 0) {
+        int km = k > 0 ? k - 1 : nz - 1;
+        double g = (pc - (phi[cidx(i, j, km, nx, ny)] - m)) / h;
+        size_t e = (size_t)k * plane + (size_t)j * nx + i;
+        double wn = w[e] - (bz[c] / b0e[k]) * g;
+        w[e] = wn;
+        if (pz && k == 0) w[e + (size_t)nz * plane] = wn;
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ a, size_t n, T value) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        a[e] = value;
+}
+
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        dst[e] = src[e];
+}
+
+// Mixed precision helpers ---------------------------------------------------
+__global__ void k_to_f32(const double* __restrict__ r, float* __restrict__ r32, size_t n,
+                         const double* __restrict__ scale_inv) {
+    const double s = 1.0 / scale_inv[0];
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        r32[e] = (float)(r[e] * s);
+}
+
+__global__ void k_accumulate(double* __restrict__ phi, const float* __restrict__ e32, size_t n,
+                             const double* __restrict__ scale_inv) {
+    const double s = scale_inv[0];
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        phi[e] = phi[e] + (double)e32[e] * s;
+}
+
+__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        b[e] = (float)a[e];
+}
+
+inline int stream_blocks(size_t n) {
+    size_t b = (n + kBlock - 1) / kBlock;
+    return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+}  // namespace
+
+// ============================================================================
+// launchers
+// ============================================================================
+int num_blocks_for_partials(const Shape& s) { return partial_blocks(s.N()); }
+
+hipError_t launch_coeff_rhs(const Shape& s, int px, int py, int pz, double h, const double* rho,
+                            const double* b0c, const double* b0e, const double* S, const double* u,
+                            const double* v, const double* w, double* bx, double* by, double* bz,
+                            double* f, double* partials, int* nparts, hipStream_t st) {
+    int nb = partial_blocks(s.N());
+    hipLaunchKernelGGL(k_coeff_rhs<true>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, px, py, pz, h,
+                       rho, b0c, b0e, S, u, v, w, bx, by, bz, f, partials);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_coeff(const Shape& s, int px, int py, int pz, const double* rho, const double* b0c,
+                        const double* b0e, double* bx, double* by, double* bz, double* partials,
+                        int* nparts, hipStream_t st) {
+    int nb = partial_blocks(s.N());
+    hipLaunchKernelGGL(k_coeff_rhs<false>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, px, py, pz, 1.0,
+                       rho, b0c, b0e, nullptr, nullptr, nullptr, nullptr, bx, by, bz, nullptr, partials);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int nparts, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_norm(const Shape& s, double* f, double shift, double* partials, int* nparts,
+                             hipStream_t st) {
+    int nb = partial_blocks(s.N());
+    hipLaunchKernelGGL(k_shift_norm, dim3(nb), dim3(kBlock), 0, st, s.N(), f, shift, partials);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const Shape& s, const double* a, double* partials, int* nparts, hipStream_t st) {
+    int nb = partial_blocks(s.N());
+    hipLaunchKernelGGL(k_sum, dim3(nb), dim3(kBlock), 0, st, s.N(), a, partials);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_avg_coeff(const Shape& fine, const T* bx, const T* by, const T* bz, T* cbx, T* cby,
+                            T* cbz, hipStream_t st) {
+    Launch3 L = cell_launch(fine.nx / 2, fine.ny / 2, fine.nz / 2);
+    hipLaunchKernelGGL(k_avg_coeff<T>, L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz, bx, by, bz, cbx,
+                       cby, cbz);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rbgs(const Shape& s, double h, T* phi, const T* f, const T* bx, const T* by,
+                       const T* bz, int nsweeps, hipStream_t st) {
+    Launch3 L = cell_launch(s.nx / 2, s.ny, s.nz);
+    T h2 = (T)(h * h);
+    for (int sw = 0; sw < nsweeps; ++sw)
+        for (int colour = 0; colour < 2; ++colour)
+            hipLaunchKernelGGL(k_rbgs_colour<T>, L.grid, L.block, 0, st, s.nx, s.ny, s.nz, h2, phi, f, bx, by,
+                               bz, colour);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_resid_restrict(const Shape& fine, double h, const T* phi, const T* f, const T* bx,
+                                 const T* by, const T* bz, T* fc, T* phic, hipStream_t st) {
+    Launch3 L = cell_launch(fine.nx / 2, fine.ny / 2, fine.nz / 2);
+    hipLaunchKernelGGL(k_resid_restrict<T>, L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz, (T)(h * h), phi,
+                       f, bx, by, bz, fc, phic);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(const Shape& fine, T* phi, const T* phic, hipStream_t st) {
+    Launch3 L = cell_launch(fine.nx, fine.ny, fine.nz);
+    hipLaunchKernelGGL(k_prolong<T>, L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz, phi, phic);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_resid_norm(const Shape& s, double h, const T* phi, const T* f, const T* bx, const T* by,
+                             const T* bz, double* partials, int* nparts, hipStream_t st) {
+    int nb = partial_blocks(s.N());
+    hipLaunchKernelGGL(k_resid_norm<T>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, (T)(h * h), phi, f,
+                       bx, by, bz, (double*)nullptr, partials);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_store(const Shape& s, double h, const double* phi, const double* f,
+                              const double* bx, const double* by, const double* bz, double* r,
+                              double* partials, int* nparts, hipStream_t st) {
+    int nb = partial_blocks(s.N());
+    hipLaunchKernelGGL(k_resid_norm<double>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, h * h, phi, f,
+                       bx, by, bz, r, partials);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_setup(const Shape& s, double h, const double* bx, const double* by,
+                               const double* bz, double* minv, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse_setup, dim3(1), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, h, bx, by, bz, minv);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve(int N, const double* minv, const double* f, double* phi, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse_solve<double>, dim3(1), dim3(kBlock), 0, st, N, minv, f, phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve_f32(int N, const double* minv, const float* f, float* phi, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse_solve<float>, dim3(1), dim3(kBlock), 0, st, N, minv, f, phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(const Shape& s, int px, int py, int pz, double h, const double* b0c,
+                          const double* b0e, const double* bx, const double* by, const double* bz,
+                          const double* phi, const double* phi_sum, double* u, double* v, double* w,
+                          double* phi_out, hipStream_t st) {
+    Launch3 L = cell_launch(s.nx, s.ny, s.nz);
+    hipLaunchKernelGGL(k_correct, L.grid, L.block, 0, st, s.nx, s.ny, s.nz, px, py, pz, h, b0c, b0e, bx, by, bz,
+                       phi, phi_sum, u, v, w, phi_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* a, size_t n, T value, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill<T>, dim3(stream_blocks(n)), dim3(kBlock), 0, st, a, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(double* dst, const double* src, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy, dim3(stream_blocks(n)), dim3(kBlock), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* scale_inv, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_f32, dim3(stream_blocks(n)), dim3(kBlock), 0, st, r, r32, n, scale_inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const double* scale_inv,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_accumulate, dim3(stream_blocks(n)), dim3(kBlock), 0, st, phi, e32, n, scale_inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_coeff_to_f32(const double* a, float* b, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_d2f, dim3(stream_blocks(n)), dim3(kBlock), 0, st, a, b, n);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+#define MG_INST(T)                                                                                      \
+    template hipError_t launch_avg_coeff<T>(const Shape&, const T*, const T*, const T*, T*, T*, T*,      \
+                                            hipStream_t);                                                \
+    template hipError_t launch_rbgs<T>(const Shape&, double, T*, const T*, const T*, const T*, const T*, \
+                                       int, hipStream_t);                                                \
+    template hipError_t launch_resid_restrict<T>(const Shape&, double, const T*, const T*, const T*,     \
+                                                 const T*, const T*, T*, T*, hipStream_t);               \
+    template hipError_t launch_prolong<T>(const Shape&, T*, const T*, hipStream_t);                      \
+    template hipError_t launch_resid_norm<T>(const Shape&, double, const T*, const T*, const T*,         \
+                                             const T*, const T*, double*, int*, hipStream_t);            \
+    template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);
+MG_INST(double)
+MG_INST(float)
+#undef MG_INST
+
+}  // namespace mg

@@ -1,0 +1,125 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// the MAC-projection library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/macproj.h"
+
+namespace mg {
+
+constexpr int kMaxLevels = 24;
+constexpr int kCoarseMax = 512;     // cells on the coarsest (directly solved) level
+constexpr int kCoarsenMin = 64;     // keep coarsening while a level has more cells than this
+constexpr int kReduceWidth = 4;     // doubles per block in a partial-sum row
+
+// One multigrid level.  Coefficient arrays are cell-aligned: b?[c] is the
+// coefficient of the LOW face of cell c in that direction; face n of a
+// direction is face 0 (walls hold 0 there, periodic faces wrap).
+template <typename T>
+struct LevelArrays {
+    T* phi = nullptr;
+    T* f = nullptr;
+    T* bx = nullptr;
+    T* by = nullptr;
+    T* bz = nullptr;
+};
+
+struct Level {
+    int nx = 0, ny = 0, nz = 0;
+    size_t N = 0;
+    double h = 0.0;
+    LevelArrays<double> d;   // FP64 arrays
+    LevelArrays<float> s;    // FP32 mirrors (mixed precision only)
+};
+
+struct Shape {
+    int nx, ny, nz;
+    size_t N() const { return (size_t)nx * ny * nz; }
+};
+
+// ---- kernel launchers (kernels.hip) ---------------------------------------
+// All launch on `stream` and return hipGetLastError().
+
+// Level-0 coefficients and right-hand side, plus per-block partial sums
+// {sum f, sum |f|, #non-finite inputs, #non-positive rho/beta0}.
+hipError_t launch_coeff_rhs(const Shape& s, int px, int py, int pz, double h,
+                            const double* rho, const double* b0c, const double* b0e,
+                            const double* S, const double* u, const double* v, const double* w,
+                            double* bx, double* by, double* bz, double* f,
+                            double* partials, int* nparts, hipStream_t st);
+// Coefficients only (no right-hand side).  Partials as above (sum f = 0).
+hipError_t launch_coeff(const Shape& s, int px, int py, int pz, const double* rho,
+                        const double* b0c, const double* b0e, double* bx, double* by,
+                        double* bz, double* partials, int* nparts, hipStream_t st);
+// Fixed-order reduction of nparts rows of kReduceWidth doubles into out[0..3].
+hipError_t launch_reduce(const double* partials, int nparts, double* out, hipStream_t st);
+// f -= shift; partial row = {sum f^2 (after), 0, 0, 0}.
+hipError_t launch_shift_norm(const Shape& s, double* f, double shift, double* partials,
+                             int* nparts, hipStream_t st);
+// Coarse coefficients = mean of the 4 coincident fine faces.
+template <typename T>
+hipError_t launch_avg_coeff(const Shape& fine, const T* bx, const T* by, const T* bz,
+                            T* cbx, T* cby, T* cbz, hipStream_t st);
+// One red-black GS sweep (red then black), in place.
+template <typename T>
+hipError_t launch_rbgs(const Shape& s, double h, T* phi, const T* f, const T* bx,
+                       const T* by, const T* bz, int nsweeps, hipStream_t st);
+// f_c = R (f - L phi); phi_c = 0.
+template <typename T>
+hipError_t launch_resid_restrict(const Shape& fine, double h, const T* phi, const T* f,
+                                 const T* bx, const T* by, const T* bz, T* fc, T* phic,
+                                 hipStream_t st);
+// phi += P phic.
+template <typename T>
+hipError_t launch_prolong(const Shape& fine, T* phi, const T* phic, hipStream_t st);
+// Partial rows {sum r^2, max |r|, #non-finite, 0} of r = f - L phi.
+template <typename T>
+hipError_t launch_resid_norm(const Shape& s, double h, const T* phi, const T* f, const T* bx,
+                             const T* by, const T* bz, double* partials, int* nparts,
+                             hipStream_t st);
+// Coarsest level: build M = -A + c 1 1^T from the coefficients and invert it
+// in place (one workgroup).  minv holds N*N doubles.
+hipError_t launch_coarse_setup(const Shape& s, double h, const double* bx, const double* by,
+                               const double* bz, double* minv, hipStream_t st);
+// Coarsest level: phi = zero-mean solution of L phi = f (f's mean removed first).
+hipError_t launch_coarse_solve(int N, const double* minv, const double* f, double* phi,
+                               hipStream_t st);
+// Partial rows {sum phi, 0, 0, 0}.
+hipError_t launch_sum(const Shape& s, const double* a, double* partials, int* nparts,
+                      hipStream_t st);
+// Velocity correction on non-wall faces with the zero-mean potential
+// phi - (*phi_sum)/N; writes phi_out (nullable) = phi - mean.
+hipError_t launch_correct(const Shape& s, int px, int py, int pz, double h, const double* b0c,
+                          const double* b0e, const double* bx, const double* by,
+                          const double* bz, const double* phi, const double* phi_sum,
+                          double* u, double* v, double* w, double* phi_out, hipStream_t st);
+// Fills and copies (graph-safe replacements for memset / memcpy).
+template <typename T>
+hipError_t launch_fill(T* a, size_t n, T value, hipStream_t st);
+hipError_t launch_copy(double* dst, const double* src, size_t n, hipStream_t st);
+
+// Mixed precision helpers.
+// r = f - L phi (FP64), partial rows {sum r^2, max|r|, #nonfinite, 0}; r stored.
+hipError_t launch_resid_store(const Shape& s, double h, const double* phi, const double* f,
+                              const double* bx, const double* by, const double* bz, double* r,
+                              double* partials, int* nparts, hipStream_t st);
+// r32 = (float)(r * scale).
+hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* scale_inv,
+                         hipStream_t st);
+// phi += (double)e32 * (*scale_inv).
+hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const double* scale_inv,
+                             hipStream_t st);
+// FP32 copies of the coefficients.
+hipError_t launch_coeff_to_f32(const double* a, float* b, size_t n, hipStream_t st);
+// Coarsest level in FP32 cycles: phi32 = (float) solve((double) f32).
+hipError_t launch_coarse_solve_f32(int N, const double* minv, const float* f, float* phi,
+                                   hipStream_t st);
+
+int num_blocks_for_partials(const Shape& s);
+
+}  // namespace mg

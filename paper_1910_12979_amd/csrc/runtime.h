@@ -1,0 +1,48 @@
+// Host-side hierarchy object and the internal entry points shared by the
+// single-problem, batch and serving front ends.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "mg_internal.h"
+
+// Slots (rows of 4 doubles) in the device scalar block of a hierarchy.
+namespace mg {
+constexpr int kSlotRhs = 0;    // {sum f, sum |f|, bad rho/beta0, #non-finite}
+constexpr int kSlotNorm = 1;   // {||f||^2 after mean removal, ...}
+constexpr int kSlotRes = 2;    // {||r||^2, -, max |r|, #non-finite}
+constexpr int kSlotPhi = 3;    // {sum phi, ...}
+}  // namespace mg
+
+struct mg_hierarchy {
+    mg_params p{};
+    int device = 0;
+    int nlev = 0;
+    int px = 0, py = 0, pz = 0;
+    mg::Level lev[mg::kMaxLevels];
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool owns_ws = false;
+    bool coeffs_valid = false;
+    double* partials = nullptr;   // 2048 rows x 4
+    double* scal = nullptr;       // 16 rows x 4 device scalars
+    double* host = nullptr;       // pinned mirror of scal
+    double* minv = nullptr;       // inverse of the coarsest-level matrix
+    double* r64 = nullptr;        // FP64 residual (mixed precision)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace mg {
+void set_error(const std::string& s);
+int hip_fail(hipError_t e, const char* what, int line);
+int count_levels(int nx, int ny, int nz);
+int validate_params(const mg_params* p);
+size_t workspace_bytes(const mg_params* p);
+int setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_hierarchy** out);
+int destroy(mg_hierarchy* H);
+int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
+            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st);
+double model_bytes(const mg_params& p, int cycles, int mixed);
+}  // namespace mg

@@ -1,0 +1,696 @@
+// Host runtime of the MAC-projection library: hierarchy construction,
+// V-cycle driver, FP64 and mixed-precision (FP32 cycle + FP64 iterative
+// refinement) solves, velocity correction, and the single-problem C ABI.
+//
+// Method: the projection of arXiv:1910.12979 (Sec. 2 divergence constraint,
+// Sec. 3 multigrid projection).  The multigrid cycle, coarsening rule and
+// coarsest solve are spelled out in include/macproj.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "mg_internal.h"
+#include "runtime.h"
+
+namespace mg {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& s) { g_last_error = s; }
+
+int hip_fail(hipError_t e, const char* what, int line) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s failed (line %d): %s", what, line, hipGetErrorString(e));
+    set_error(buf);
+    return MG_ERR_HIP;
+}
+
+int count_levels(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    int n = 1;
+    while (nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && (long long)nx * ny * nz > kCoarsenMin &&
+           n < kMaxLevels) {
+        nx /= 2;
+        ny /= 2;
+        nz /= 2;
+        ++n;
+    }
+    if ((long long)nx * ny * nz > kCoarseMax) return 0;
+    return n;
+}
+
+int validate_params(const mg_params* p) {
+    if (!p) {
+        set_error("null params");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (!(p->dx > 0.0) || !std::isfinite(p->dx)) {
+        set_error("dx must be positive and finite");
+        return MG_ERR_INVALID_ARG;
+    }
+    for (int d = 0; d < 3; ++d)
+        if (p->bc[d] != MG_BC_PERIODIC && p->bc[d] != MG_BC_WALL) {
+            set_error("bc must be MG_BC_PERIODIC or MG_BC_WALL");
+            return MG_ERR_INVALID_ARG;
+        }
+    if (p->pre_sweeps < 0 || p->post_sweeps < 0 || p->max_cycles < 0 || p->max_cycles > 100000 ||
+        !(p->rtol >= 0.0) || (p->precision != MG_FP64 && p->precision != MG_MIXED)) {
+        set_error("invalid solver controls");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (count_levels(p->n[0], p->n[1], p->n[2]) == 0) {
+        set_error("shape not solvable: coarsest level would exceed 512 cells (or n < 1)");
+        return MG_ERR_BAD_SIZE;
+    }
+    return MG_OK;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Walk the workspace layout; with base == nullptr only the size is computed.
+size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* ptr = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return ptr;
+    };
+    int nl = count_levels(p->n[0], p->n[1], p->n[2]);
+    bool mixed = p->precision == MG_MIXED;
+    for (int l = 0; l < nl; ++l) {
+        size_t N = (size_t)(p->n[0] >> l) * (p->n[1] >> l) * (p->n[2] >> l);
+        LevelArrays<double> d;
+        d.phi = (double*)take(N * 8);
+        d.f = (double*)take(N * 8);
+        d.bx = (double*)take(N * 8);
+        d.by = (double*)take(N * 8);
+        d.bz = (double*)take(N * 8);
+        LevelArrays<float> s;
+        if (mixed) {
+            s.phi = (float*)take(N * 4);
+            s.f = (float*)take(N * 4);
+            s.bx = (float*)take(N * 4);
+            s.by = (float*)take(N * 4);
+            s.bz = (float*)take(N * 4);
+        }
+        if (H) {
+            H->lev[l].d = d;
+            H->lev[l].s = s;
+        }
+    }
+    size_t Nc = (size_t)(p->n[0] >> (nl - 1)) * (p->n[1] >> (nl - 1)) * (p->n[2] >> (nl - 1));
+    double* minv = (double*)take(Nc * Nc * 8);
+    double* partials = (double*)take((size_t)2048 * kReduceWidth * 8);
+    double* scal = (double*)take(64 * 8);
+    double* r64 = nullptr;
+    if (mixed) r64 = (double*)take((size_t)p->n[0] * p->n[1] * p->n[2] * 8);
+    if (H) {
+        H->minv = minv;
+        H->partials = partials;
+        H->scal = scal;
+        H->r64 = r64;
+    }
+    return off;
+}
+
+}  // namespace
+
+size_t workspace_bytes(const mg_params* p) {
+    if (validate_params(p) != MG_OK) return 0;
+    return layout(nullptr, p, nullptr);
+}
+
+#define HIPCHK(expr)                                    \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__); \
+    } while (0)
+
+int setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_hierarchy** out) {
+    if (!out) {
+        set_error("null output handle");
+        return MG_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    int st = validate_params(p);
+    if (st != MG_OK) return st;
+    size_t need = layout(nullptr, p, nullptr);
+    mg_hierarchy* H = new (std::nothrow) mg_hierarchy();
+    if (!H) return MG_ERR_OOM;
+    H->p = *p;
+    H->px = p->bc[0] == MG_BC_PERIODIC;
+    H->py = p->bc[1] == MG_BC_PERIODIC;
+    H->pz = p->bc[2] == MG_BC_PERIODIC;
+    H->nlev = count_levels(p->n[0], p->n[1], p->n[2]);
+    hipGetDevice(&H->device);
+    if (workspace) {
+        if (ws_bytes < need || ((uintptr_t)workspace % kAlign) != 0) {
+            delete H;
+            set_error("workspace too small or not 256-byte aligned");
+            return MG_ERR_INVALID_ARG;
+        }
+        H->ws = workspace;
+        H->owns_ws = false;
+    } else {
+        hipError_t e = hipMalloc(&H->ws, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete H;
+            set_error("hipMalloc of the hierarchy workspace failed");
+            return MG_ERR_OOM;
+        }
+        H->owns_ws = true;
+    }
+    H->ws_bytes = need;
+    layout(H, p, (char*)H->ws);
+    for (int l = 0; l < H->nlev; ++l) {
+        Level& L = H->lev[l];
+        L.nx = p->n[0] >> l;
+        L.ny = p->n[1] >> l;
+        L.nz = p->n[2] >> l;
+        L.N = (size_t)L.nx * L.ny * L.nz;
+        L.h = p->dx * (double)(1 << l);
+    }
+    hipError_t e = hipHostMalloc((void**)&H->host, 64 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        if (H->owns_ws) hipFree(H->ws);
+        delete H;
+        return hip_fail(e, "hipHostMalloc", __LINE__);
+    }
+    hipEventCreate(&H->ev0);
+    hipEventCreate(&H->ev1);
+    *out = H;
+    return MG_OK;
+}
+
+int destroy(mg_hierarchy* H) {
+    if (!H) return MG_OK;
+    if (H->owns_ws && H->ws) hipFree(H->ws);
+    if (H->host) hipHostFree(H->host);
+    hipEventDestroy(H->ev0);
+    hipEventDestroy(H->ev1);
+    delete H;
+    return MG_OK;
+}
+
+static Shape shape_of(const Level& L) { return Shape{L.nx, L.ny, L.nz}; }
+
+// Reduce the partial rows into scal[slot*4 .. slot*4+3].
+static int reduce_to(mg_hierarchy* H, int nparts, int slot, hipStream_t st) {
+    HIPCHK(launch_reduce(H->partials, nparts, H->scal + slot * kReduceWidth, st));
+    return MG_OK;
+}
+
+static int read_scalars(mg_hierarchy* H, int first, int count, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(H->host + first, H->scal + first, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return MG_OK;
+}
+
+int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
+                       const double* S, const double* u, const double* v, const double* w,
+                       hipStream_t st) {
+    Level& L0 = H->lev[0];
+    int np = 0;
+    if (S) {
+        HIPCHK(launch_coeff_rhs(shape_of(L0), H->px, H->py, H->pz, L0.h, rho, b0c, b0e, S, u, v, w, L0.d.bx,
+                                L0.d.by, L0.d.bz, L0.d.f, H->partials, &np, st));
+    } else {
+        HIPCHK(launch_coeff(shape_of(L0), H->px, H->py, H->pz, rho, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
+                            H->partials, &np, st));
+    }
+    int rc = reduce_to(H, np, kSlotRhs, st);
+    if (rc) return rc;
+    for (int l = 0; l + 1 < H->nlev; ++l) {
+        Level& F = H->lev[l];
+        Level& C = H->lev[l + 1];
+        HIPCHK(launch_avg_coeff<double>(shape_of(F), F.d.bx, F.d.by, F.d.bz, C.d.bx, C.d.by, C.d.bz, st));
+    }
+    Level& Lc = H->lev[H->nlev - 1];
+    HIPCHK(launch_coarse_setup(shape_of(Lc), Lc.h, Lc.d.bx, Lc.d.by, Lc.d.bz, H->minv, st));
+    if (H->p.precision == MG_MIXED) {
+        for (int l = 0; l < H->nlev; ++l) {
+            Level& L = H->lev[l];
+            HIPCHK(launch_coeff_to_f32(L.d.bx, L.s.bx, L.N, st));
+            HIPCHK(launch_coeff_to_f32(L.d.by, L.s.by, L.N, st));
+            HIPCHK(launch_coeff_to_f32(L.d.bz, L.s.bz, L.N, st));
+        }
+    }
+    H->coeffs_valid = true;
+    return MG_OK;
+}
+
+// V-cycle from level l on the FP64 arrays.
+static int vcycle64(mg_hierarchy* H, int l, hipStream_t st) {
+    Level& F = H->lev[l];
+    if (l == H->nlev - 1) {
+        HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st));
+        return MG_OK;
+    }
+    Level& C = H->lev[l + 1];
+    Shape s = shape_of(F);
+    HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, H->p.pre_sweeps, st));
+    HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f, C.d.phi, st));
+    int rc = vcycle64(H, l + 1, st);
+    if (rc) return rc;
+    HIPCHK(launch_prolong<double>(s, F.d.phi, C.d.phi, st));
+    HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, H->p.post_sweeps, st));
+    return MG_OK;
+}
+
+// V-cycle from level l on the FP32 arrays; the coarsest solve runs in FP64.
+static int vcycle32(mg_hierarchy* H, int l, hipStream_t st) {
+    Level& F = H->lev[l];
+    if (l == H->nlev - 1) {
+        HIPCHK(launch_coarse_solve_f32((int)F.N, H->minv, F.s.f, F.s.phi, st));
+        return MG_OK;
+    }
+    Level& C = H->lev[l + 1];
+    Shape s = shape_of(F);
+    HIPCHK(launch_rbgs<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, H->p.pre_sweeps, st));
+    HIPCHK(launch_resid_restrict<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, C.s.f, C.s.phi, st));
+    int rc = vcycle32(H, l + 1, st);
+    if (rc) return rc;
+    HIPCHK(launch_prolong<float>(s, F.s.phi, C.s.phi, st));
+    HIPCHK(launch_rbgs<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, H->p.post_sweeps, st));
+    return MG_OK;
+}
+
+int vcycle_from(mg_hierarchy* H, int l, hipStream_t st) { return vcycle64(H, l, st); }
+
+// Relative residual of level 0 (FP64) into host[kSlotRes*4..]; returns status.
+static int level0_residual(mg_hierarchy* H, double* r_store, hipStream_t st) {
+    Level& L0 = H->lev[0];
+    int np = 0;
+    if (r_store) {
+        HIPCHK(launch_resid_store(shape_of(L0), L0.h, L0.d.phi, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, r_store,
+                                  H->partials, &np, st));
+    } else {
+        HIPCHK(launch_resid_norm<double>(shape_of(L0), L0.h, L0.d.phi, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz,
+                                         H->partials, &np, st));
+    }
+    int rc = reduce_to(H, np, kSlotRes, st);
+    if (rc) return rc;
+    return read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
+}
+
+double model_bytes(const mg_params& p, int cycles, int mixed) {
+    double N = (double)p.n[0] * p.n[1] * p.n[2];
+    if (!mixed) return N * (156.0 + cycles * 326.0);
+    return N * (192.0 + cycles * 199.0);
+}
+
+// Solve on level 0 after f (mean-removed) and the coefficients are in place.
+static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStream_t st) {
+    Level& L0 = H->lev[0];
+    HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
+    int status = MG_ERR_NOT_CONVERGED;
+    int cycles = 0;
+    double rel = 1.0;
+    if (stats) {
+        stats->resid_hist[0] = 1.0;
+        stats->hist_len = 1;
+    }
+    const bool mixed = H->p.precision == MG_MIXED;
+    if (H->p.rtol >= 1.0) status = MG_OK;
+    if (mixed) {
+        // phi = 0, so the FP64 residual is f itself
+        int rc = level0_residual(H, H->r64, st);
+        if (rc) return rc;
+    }
+    while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
+        if (!mixed) {
+            int rc = vcycle64(H, 0, st);
+            if (rc) return rc;
+        } else {
+            // correction from an FP32 cycle on the scaled FP64 residual r64
+            double rmax = H->host[kSlotRes * kReduceWidth + 2];
+            if (!(rmax > 0.0)) break;
+            HIPCHK(launch_to_f32(H->r64, L0.s.f, L0.N, H->scal + kSlotRes * kReduceWidth + 2, st));
+            HIPCHK(launch_fill<float>(L0.s.phi, L0.N, 0.0f, st));
+            int rc = vcycle32(H, 0, st);
+            if (rc) return rc;
+            HIPCHK(launch_accumulate(L0.d.phi, L0.s.phi, L0.N, H->scal + kSlotRes * kReduceWidth + 2, st));
+        }
+        ++cycles;
+        int rc = level0_residual(H, mixed ? H->r64 : nullptr, st);
+        if (rc) return rc;
+        const double* r = H->host + kSlotRes * kReduceWidth;
+        rel = std::sqrt(r[0]) / fnorm;
+        if (stats && cycles < MG_HIST_MAX) {
+            stats->resid_hist[cycles] = rel;
+            stats->hist_len = cycles + 1;
+        }
+        if (r[3] > 0.0 || !std::isfinite(rel)) {
+            status = MG_ERR_NONFINITE;
+            set_error("non-finite residual during the solve");
+            break;
+        }
+        if (rel <= H->p.rtol) status = MG_OK;
+    }
+    if (stats) {
+        stats->cycles = cycles;
+        stats->rel_resid = rel;
+    }
+    return status;
+}
+
+int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
+            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st) {
+    if (!H || !rho || !b0c || !b0e || !S || !u || !v || !w) {
+        set_error("null argument to mac_project");
+        return MG_ERR_INVALID_ARG;
+    }
+    mg_stats local;
+    std::memset(&local, 0, sizeof local);
+    mg_stats* S_ = stats ? stats : &local;
+    std::memset(S_, 0, sizeof *S_);
+    S_->nlevels = H->nlev;
+    HIPCHK(hipEventRecord(H->ev0, st));
+    Level& L0 = H->lev[0];
+    int rc = build_coefficients(H, rho, b0c, b0e, S, u, v, w, st);
+    if (rc) return rc;
+    rc = read_scalars(H, kSlotRhs * kReduceWidth, kReduceWidth, st);
+    if (rc) return rc;
+    const double* q = H->host + kSlotRhs * kReduceWidth;
+    double sf = q[0], saf = q[1], bad = q[2], nonfin = q[3];
+    S_->sum_f = sf;
+    S_->sum_abs_f = saf;
+    if (nonfin > 0.0 || !std::isfinite(sf) || !std::isfinite(saf)) {
+        set_error("non-finite value in rho, beta0, U or S");
+        return S_->status = MG_ERR_NONFINITE;
+    }
+    if (bad > 0.0) {
+        set_error("rho and beta0 must be positive");
+        return S_->status = MG_ERR_INVALID_ARG;
+    }
+    if (std::fabs(sf) > 1e-8 * saf) {
+        set_error("incompatible right-hand side: |sum f| > 1e-8 sum |f|");
+        return S_->status = MG_ERR_INCOMPATIBLE_RHS;
+    }
+    int status = MG_OK;
+    if (saf == 0.0) {
+        HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
+        S_->hist_len = 1;
+        S_->resid_hist[0] = 0.0;
+    } else {
+        double mean = sf / (double)L0.N;
+        S_->mean_removed = mean;
+        int np = 0;
+        HIPCHK(launch_shift_norm(shape_of(L0), L0.d.f, mean, H->partials, &np, st));
+        rc = reduce_to(H, np, kSlotNorm, st);
+        if (rc) return rc;
+        rc = read_scalars(H, kSlotNorm * kReduceWidth, kReduceWidth, st);
+        if (rc) return rc;
+        double fnorm = std::sqrt(H->host[kSlotNorm * kReduceWidth]);
+        S_->norm_f = fnorm;
+        if (fnorm == 0.0) {
+            HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
+        } else {
+            status = solve_level0(H, fnorm, S_, st);
+            if (status != MG_OK && status != MG_ERR_NOT_CONVERGED) return S_->status = status;
+        }
+    }
+    int np = 0;
+    HIPCHK(launch_sum(shape_of(L0), L0.d.phi, H->partials, &np, st));
+    rc = reduce_to(H, np, kSlotPhi, st);
+    if (rc) return rc;
+    HIPCHK(launch_correct(shape_of(L0), H->px, H->py, H->pz, L0.h, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
+                          L0.d.phi, H->scal + kSlotPhi * kReduceWidth, u, v, w, phi_out, st));
+    HIPCHK(hipEventRecord(H->ev1, st));
+    rc = read_scalars(H, kSlotPhi * kReduceWidth, kReduceWidth, st);
+    if (rc) return rc;
+    S_->phi_mean = H->host[kSlotPhi * kReduceWidth] / (double)L0.N;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, H->ev0, H->ev1);
+    S_->ms_total = ms;
+    S_->bytes_model = model_bytes(H->p, S_->cycles, H->p.precision == MG_MIXED);
+    S_->status = status;
+    if (status == MG_ERR_NOT_CONVERGED) set_error("maximum number of cycles reached");
+    return status;
+}
+
+int vcycle_api(mg_hierarchy* H, double* phi, const double* rhs, double* rel_out, hipStream_t st) {
+    if (!H || !phi || !rhs) {
+        set_error("null argument to mg_vcycle");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (!H->coeffs_valid) {
+        set_error("mg_vcycle before mg_set_coefficients / mac_project");
+        return MG_ERR_INVALID_ARG;
+    }
+    Level& L0 = H->lev[0];
+    HIPCHK(launch_copy(L0.d.f, rhs, L0.N, st));
+    HIPCHK(launch_copy(L0.d.phi, phi, L0.N, st));
+    int rc = vcycle64(H, 0, st);
+    if (rc) return rc;
+    HIPCHK(launch_copy(phi, L0.d.phi, L0.N, st));
+    if (rel_out) {
+        int np = 0;
+        HIPCHK(launch_shift_norm(shape_of(L0), L0.d.f, 0.0, H->partials, &np, st));
+        rc = reduce_to(H, np, kSlotNorm, st);
+        if (rc) return rc;
+        rc = read_scalars(H, kSlotNorm * kReduceWidth, kReduceWidth, st);
+        if (rc) return rc;
+        double fn = std::sqrt(H->host[kSlotNorm * kReduceWidth]);
+        rc = level0_residual(H, nullptr, st);
+        if (rc) return rc;
+        double rn = std::sqrt(H->host[kSlotRes * kReduceWidth]);
+        *rel_out = fn > 0.0 ? rn / fn : 0.0;
+    }
+    return MG_OK;
+}
+
+int level_copy(mg_hierarchy* H, int l, int which, void* buf, int to_h, hipStream_t st) {
+    if (!H || !buf || l < 0 || l >= H->nlev) {
+        set_error("bad level_copy arguments");
+        return MG_ERR_INVALID_ARG;
+    }
+    Level& L = H->lev[l];
+    double* a;
+    switch (which) {
+        case MG_ARR_PHI: a = L.d.phi; break;
+        case MG_ARR_F: a = L.d.f; break;
+        case MG_ARR_BX: a = L.d.bx; break;
+        case MG_ARR_BY: a = L.d.by; break;
+        case MG_ARR_BZ: a = L.d.bz; break;
+        default: set_error("bad array id"); return MG_ERR_INVALID_ARG;
+    }
+    if (to_h) {
+        HIPCHK(launch_copy(a, (const double*)buf, L.N, st));
+        if (which >= MG_ARR_BX) H->coeffs_valid = true;
+    } else {
+        HIPCHK(launch_copy((double*)buf, a, L.N, st));
+    }
+    return MG_OK;
+}
+
+int level_step(mg_hierarchy* H, int l, int step, int arg, hipStream_t st) {
+    if (!H || l < 0 || l >= H->nlev) {
+        set_error("bad level");
+        return MG_ERR_INVALID_ARG;
+    }
+    Level& F = H->lev[l];
+    Shape s = shape_of(F);
+    bool has_coarse = l + 1 < H->nlev;
+    switch (step) {
+        case MG_STEP_SMOOTH:
+            if (!has_coarse) break;
+            HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, arg, st));
+            break;
+        case MG_STEP_RESID_RESTRICT:
+        case MG_STEP_DOWN: {
+            if (!has_coarse) {
+                set_error("no coarser level");
+                return MG_ERR_INVALID_ARG;
+            }
+            Level& C = H->lev[l + 1];
+            if (step == MG_STEP_DOWN)
+                HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, arg, st));
+            HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f,
+                                                 C.d.phi, st));
+            break;
+        }
+        case MG_STEP_PROLONG:
+        case MG_STEP_UP: {
+            if (!has_coarse) {
+                set_error("no coarser level");
+                return MG_ERR_INVALID_ARG;
+            }
+            Level& C = H->lev[l + 1];
+            HIPCHK(launch_prolong<double>(s, F.d.phi, C.d.phi, st));
+            if (step == MG_STEP_UP)
+                HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, arg, st));
+            break;
+        }
+        case MG_STEP_COARSE:
+            if (has_coarse) {
+                set_error("MG_STEP_COARSE needs the coarsest level");
+                return MG_ERR_INVALID_ARG;
+            }
+            HIPCHK(launch_coarse_setup(s, F.h, F.d.bx, F.d.by, F.d.bz, H->minv, st));
+            HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st));
+            break;
+        default:
+            set_error("unknown step");
+            return MG_ERR_INVALID_ARG;
+    }
+    return MG_OK;
+}
+
+}  // namespace mg
+
+// ============================================================================
+// C ABI
+// ============================================================================
+using namespace mg;
+
+extern "C" {
+
+void mg_default_params(mg_params* p, int32_t nx, int32_t ny, int32_t nz, double dx) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->n[0] = nx;
+    p->n[1] = ny;
+    p->n[2] = nz;
+    p->dx = dx;
+    p->bc[0] = MG_BC_PERIODIC;
+    p->bc[1] = MG_BC_PERIODIC;
+    p->bc[2] = MG_BC_WALL;
+    p->pre_sweeps = 2;
+    p->post_sweeps = 2;
+    p->rtol = 1e-10;
+    p->max_cycles = 100;
+    p->precision = MG_FP64;
+}
+
+int32_t mg_num_levels_for(const mg_params* p) {
+    if (!p) return 0;
+    return count_levels(p->n[0], p->n[1], p->n[2]);
+}
+
+size_t mg_workspace_bytes(const mg_params* p) { return workspace_bytes(p); }
+
+int mg_setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_handle* out) {
+    try {
+        return setup(p, workspace, ws_bytes, out);
+    } catch (...) {
+        set_error("internal error in mg_setup");
+        return MG_ERR_HIP;
+    }
+}
+
+int mg_destroy(mg_handle h) { return destroy(h); }
+
+int mg_set_params(mg_handle h, const mg_params* p) {
+    if (!h) {
+        set_error("null handle");
+        return MG_ERR_INVALID_ARG;
+    }
+    int st = validate_params(p);
+    if (st) return st;
+    for (int d = 0; d < 3; ++d)
+        if (p->n[d] != h->p.n[d] || p->bc[d] != h->p.bc[d]) {
+            set_error("mg_set_params cannot change the shape or boundary types");
+            return MG_ERR_INVALID_ARG;
+        }
+    if (p->dx != h->p.dx) {
+        set_error("mg_set_params cannot change dx");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (p->precision == MG_MIXED && h->p.precision != MG_MIXED) {
+        set_error("hierarchy was built without FP32 mirrors; set up with MG_MIXED");
+        return MG_ERR_INVALID_ARG;
+    }
+    h->p = *p;
+    return MG_OK;
+}
+
+int mg_set_coefficients(mg_handle h, const double* rho, const double* beta0_cc, const double* beta0_edge,
+                        void* stream) {
+    if (!h || !rho || !beta0_cc || !beta0_edge) {
+        set_error("null argument to mg_set_coefficients");
+        return MG_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = build_coefficients(h, rho, beta0_cc, beta0_edge, nullptr, nullptr, nullptr, nullptr, st);
+    if (rc) return rc;
+    rc = read_scalars(h, kSlotRhs * kReduceWidth, kReduceWidth, st);
+    if (rc) return rc;
+    const double* q = h->host + kSlotRhs * kReduceWidth;
+    if (q[3] > 0.0) {
+        h->coeffs_valid = false;
+        set_error("non-finite rho or beta0");
+        return MG_ERR_NONFINITE;
+    }
+    if (q[2] > 0.0) {
+        h->coeffs_valid = false;
+        set_error("rho and beta0 must be positive");
+        return MG_ERR_INVALID_ARG;
+    }
+    return MG_OK;
+}
+
+int mac_project(mg_handle h, const double* rho, const double* beta0_cc, const double* beta0_edge,
+                const double* S, double* u, double* v, double* w, double* phi, mg_stats* stats,
+                void* stream) {
+    try {
+        return project(h, rho, beta0_cc, beta0_edge, S, u, v, w, phi, stats, (hipStream_t)stream);
+    } catch (...) {
+        set_error("internal error in mac_project");
+        return MG_ERR_HIP;
+    }
+}
+
+int mg_vcycle(mg_handle h, double* phi, const double* rhs, double* rel_resid_out, void* stream) {
+    return vcycle_api(h, phi, rhs, rel_resid_out, (hipStream_t)stream);
+}
+
+int mg_level_info(mg_handle h, int32_t level, int32_t dims[3], double* dx) {
+    if (!h || level < 0 || level >= h->nlev || !dims) {
+        set_error("bad level");
+        return MG_ERR_INVALID_ARG;
+    }
+    dims[0] = h->lev[level].nx;
+    dims[1] = h->lev[level].ny;
+    dims[2] = h->lev[level].nz;
+    if (dx) *dx = h->lev[level].h;
+    return MG_OK;
+}
+
+int mg_level_copy(mg_handle h, int32_t level, int32_t array, void* buffer, int32_t to_hierarchy,
+                  void* stream) {
+    return level_copy(h, level, array, buffer, to_hierarchy, (hipStream_t)stream);
+}
+
+int mg_level_step(mg_handle h, int32_t level, int32_t step, int32_t arg, void* stream) {
+    return level_step(h, level, step, arg, (hipStream_t)stream);
+}
+
+const char* mg_strerror(int code) {
+    switch (code) {
+        case MG_OK: return "ok";
+        case MG_PENDING: return "pending";
+        case MG_ERR_INVALID_ARG: return "invalid argument";
+        case MG_ERR_BAD_SIZE: return "unsupported size";
+        case MG_ERR_INCOMPATIBLE_RHS: return "incompatible right-hand side";
+        case MG_ERR_NOT_CONVERGED: return "not converged";
+        case MG_ERR_NONFINITE: return "non-finite value";
+        case MG_ERR_OOM: return "out of device memory";
+        case MG_ERR_HIP: return "HIP runtime error";
+        case MG_ERR_BUDGET: return "request exceeds the memory budget";
+        case MG_ERR_BUSY: return "busy";
+        default: return "unknown status";
+    }
+}
+
+const char* mg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

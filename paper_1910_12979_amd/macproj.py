@@ -1,0 +1,359 @@
+"""Python binding of libmacproj.so (ctypes): argument marshalling only.
+
+Every step of the projection runs in the HIP library; this module turns torch
+tensors into device pointers (``data_ptr()``) and torch's current stream into
+a ``hipStream_t``.  Function names follow the C ABI in include/macproj.h.
+The library must be built (``python -m paper_1910_12979_amd.build``); there is
+no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from types import SimpleNamespace
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmacproj.so")
+
+MG_OK, MG_PENDING = 0, 1
+STATUS = {0: "OK", 1: "PENDING", -1: "INVALID_ARG", -2: "BAD_SIZE", -3: "INCOMPATIBLE_RHS",
+          -4: "NOT_CONVERGED", -5: "NONFINITE", -6: "OOM", -7: "HIP", -8: "BUDGET", -9: "BUSY"}
+MG_BC_PERIODIC, MG_BC_WALL = 0, 1
+MG_FP64, MG_MIXED = 0, 1
+STEP = {"smooth": 0, "resid_restrict": 1, "prolong": 2, "coarse": 3, "down": 4, "up": 5}
+ARRAY = {"phi": 0, "f": 1, "bx": 2, "by": 3, "bz": 4}
+HIST_MAX = 128
+
+
+class MGError(RuntimeError):
+    def __init__(self, code, detail=""):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__(f"{self.name} ({code}): {detail}")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double), ("bc", ctypes.c_int32 * 3),
+                ("pre_sweeps", ctypes.c_int32), ("post_sweeps", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("nlevels", ctypes.c_int32),
+                ("hist_len", ctypes.c_int32), ("rel_resid", ctypes.c_double),
+                ("mean_removed", ctypes.c_double), ("sum_f", ctypes.c_double),
+                ("sum_abs_f", ctypes.c_double), ("norm_f", ctypes.c_double),
+                ("phi_mean", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("bytes_model", ctypes.c_double), ("resid_hist", ctypes.c_double * HIST_MAX)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "resid_hist"}
+        d["status_name"] = STATUS.get(self.status, str(self.status))
+        d["hist"] = list(self.resid_hist[: max(self.hist_len, 0)])
+        return d
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("p", Params), ("rho", ctypes.c_void_p), ("beta0_cc", ctypes.c_void_p),
+                ("beta0_edge", ctypes.c_void_p), ("S", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("w", ctypes.c_void_p), ("phi", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmacproj.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1910_12979_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        P, S = ctypes.POINTER(Params), ctypes.POINTER(Stats)
+        L.mg_default_params.argtypes = [P, i32, i32, i32, d]
+        L.mg_default_params.restype = None
+        L.mg_num_levels_for.argtypes = [P]
+        L.mg_num_levels_for.restype = i32
+        L.mg_workspace_bytes.argtypes = [P]
+        L.mg_workspace_bytes.restype = ctypes.c_size_t
+        L.mg_setup.argtypes = [P, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.mg_destroy.argtypes = [vp]
+        L.mg_set_params.argtypes = [vp, P]
+        L.mg_set_coefficients.argtypes = [vp, vp, vp, vp, vp]
+        L.mac_project.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
+        L.mg_vcycle.argtypes = [vp, vp, vp, ctypes.POINTER(d), vp]
+        L.mg_level_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(d)]
+        L.mg_level_copy.argtypes = [vp, i32, i32, vp, i32, vp]
+        L.mg_level_step.argtypes = [vp, i32, i32, i32, vp]
+        L.project_batch.argtypes = [i32, ctypes.POINTER(Problem), S, vp]
+        L.serve_create.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(vp)]
+        L.serve_submit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_uint64)]
+        L.serve_poll.argtypes = [vp, ctypes.c_uint64, S]
+        L.serve_wait.argtypes = [vp, ctypes.c_uint64, S]
+        L.serve_counters.argtypes = [vp, ctypes.POINTER(d)]
+        L.serve_destroy.argtypes = [vp]
+        L.mg_strerror.argtypes = [ctypes.c_int]
+        L.mg_strerror.restype = ctypes.c_char_p
+        L.mg_last_error.argtypes = []
+        L.mg_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().mg_last_error().decode()
+
+
+def _check(code, allow=(MG_OK,)):
+    if code not in allow:
+        raise MGError(code, last_error())
+    return code
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, dtype=None, shape=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(n, dx, periodic=(True, True, False), pre_sweeps=2, post_sweeps=2, rtol=1e-10,
+                max_cycles=100, precision="fp64") -> Params:
+    p = Params()
+    nx, ny, nz = n
+    lib().mg_default_params(ctypes.byref(p), nx, ny, nz, float(dx))
+    for d in range(3):
+        p.bc[d] = MG_BC_PERIODIC if periodic[d] else MG_BC_WALL
+    p.pre_sweeps, p.post_sweeps = pre_sweeps, post_sweeps
+    p.rtol, p.max_cycles = float(rtol), int(max_cycles)
+    p.precision = MG_MIXED if precision in ("mixed", MG_MIXED) else MG_FP64
+    return p
+
+
+def mg_num_levels_for(params: Params) -> int:
+    return lib().mg_num_levels_for(ctypes.byref(params))
+
+
+def mg_workspace_bytes(params: Params) -> int:
+    return lib().mg_workspace_bytes(ctypes.byref(params))
+
+
+def field_shapes(n):
+    nx, ny, nz = n
+    return {"rho": (nz, ny, nx), "S": (nz, ny, nx), "phi": (nz, ny, nx), "u": (nz, ny, nx + 1),
+            "v": (nz, ny + 1, nx), "w": (nz + 1, ny, nx), "beta0_cc": (nz,), "beta0_edge": (nz + 1,)}
+
+
+class Hierarchy:
+    """An mg_setup handle: one box shape on the current device."""
+
+    def __init__(self, params: Params, workspace=None):
+        self.params = params
+        self.n = tuple(params.n)
+        self._h = ctypes.c_void_p()
+        ws = _ptr(workspace, name="workspace") if workspace is not None else None
+        nbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        _check(lib().mg_setup(ctypes.byref(params), ws, nbytes, ctypes.byref(self._h)))
+        self.nlevels = lib().mg_num_levels_for(ctypes.byref(params))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().mg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: Params):
+        _check(lib().mg_set_params(self._h, ctypes.byref(params)))
+        self.params = params
+
+    def set_coefficients(self, rho, beta0_cc, beta0_edge, stream=None):
+        import torch
+        sh = field_shapes(self.n)
+        _check(lib().mg_set_coefficients(self._h, _ptr(rho, torch.float64, sh["rho"], "rho"),
+                                         _ptr(beta0_cc, torch.float64, sh["beta0_cc"], "beta0_cc"),
+                                         _ptr(beta0_edge, torch.float64, sh["beta0_edge"], "beta0_edge"),
+                                         _stream(stream)))
+
+    def mac_project(self, rho, beta0_cc, beta0_edge, S, u, v, w, phi=None, stream=None,
+                    allow=(MG_OK,)):
+        """Project in place; returns the stats dict.  Raises MGError unless the
+        status is in ``allow``."""
+        import torch
+        sh = field_shapes(self.n)
+        f64 = torch.float64
+        st = Stats()
+        code = lib().mac_project(self._h, _ptr(rho, f64, sh["rho"], "rho"),
+                                 _ptr(beta0_cc, f64, sh["beta0_cc"], "beta0_cc"),
+                                 _ptr(beta0_edge, f64, sh["beta0_edge"], "beta0_edge"),
+                                 _ptr(S, f64, sh["S"], "S"), _ptr(u, f64, sh["u"], "u"),
+                                 _ptr(v, f64, sh["v"], "v"), _ptr(w, f64, sh["w"], "w"),
+                                 _ptr(phi, f64, sh["phi"], "phi"), ctypes.byref(st), _stream(stream))
+        _check(code, allow)
+        out = st.as_dict()
+        out["code"] = code
+        return out
+
+    def mg_vcycle(self, phi, rhs, stream=None):
+        import torch
+        sh = field_shapes(self.n)["phi"]
+        rel = ctypes.c_double()
+        _check(lib().mg_vcycle(self._h, _ptr(phi, torch.float64, sh, "phi"), _ptr(rhs, torch.float64, sh, "rhs"),
+                               ctypes.byref(rel), _stream(stream)))
+        return rel.value
+
+    def level_info(self, level):
+        dims = (ctypes.c_int32 * 3)()
+        dx = ctypes.c_double()
+        _check(lib().mg_level_info(self._h, level, dims, ctypes.byref(dx)))
+        return (dims[0], dims[1], dims[2]), dx.value
+
+    def level_copy(self, level, array, tensor, to_hierarchy, stream=None):
+        import torch
+        (nx, ny, nz), _ = self.level_info(level)
+        _check(lib().mg_level_copy(self._h, level, ARRAY[array],
+                                   _ptr(tensor, torch.float64, (nz, ny, nx), array),
+                                   1 if to_hierarchy else 0, _stream(stream)))
+
+    def level_step(self, level, step, arg=0, stream=None):
+        _check(lib().mg_level_step(self._h, level, STEP[step], arg, _stream(stream)))
+
+
+def mg_setup(params: Params, workspace=None) -> Hierarchy:
+    return Hierarchy(params, workspace)
+
+
+def mac_project(h: Hierarchy, *args, **kw):
+    return h.mac_project(*args, **kw)
+
+
+def mg_vcycle(h: Hierarchy, phi, rhs, stream=None):
+    return h.mg_vcycle(phi, rhs, stream)
+
+
+def mg_destroy(h: Hierarchy):
+    h.close()
+
+
+# ---------------------------------------------------------------- problems
+def to_device(prob, device="cuda", phi=True):
+    """Copy an inputs.Problem's host arrays to device tensors."""
+    import torch
+    t = {name: torch.from_numpy(np.ascontiguousarray(getattr(prob, name))).to(device)
+         for name in ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w")}
+    nx, ny, nz = prob.n
+    t["phi"] = torch.zeros((nz, ny, nx), dtype=torch.float64, device=device) if phi else None
+    return SimpleNamespace(**t)
+
+
+def params_of(prob, precision="fp64", rtol=None, max_cycles=None) -> Params:
+    return make_params(prob.n, prob.dx, prob.periodic, prob.pre_sweeps, prob.post_sweeps,
+                       prob.rtol if rtol is None else rtol,
+                       prob.max_cycles if max_cycles is None else max_cycles, precision)
+
+
+def problem_struct(params: Params, d) -> Problem:
+    """mg_problem for device tensors d (a namespace from to_device)."""
+    import torch
+    sh = field_shapes(tuple(params.n))
+    f64 = torch.float64
+    pr = Problem()
+    pr.p = params
+    pr.rho = _ptr(d.rho, f64, sh["rho"], "rho")
+    pr.beta0_cc = _ptr(d.beta0_cc, f64, sh["beta0_cc"], "beta0_cc")
+    pr.beta0_edge = _ptr(d.beta0_edge, f64, sh["beta0_edge"], "beta0_edge")
+    pr.S = _ptr(d.S, f64, sh["S"], "S")
+    pr.u = _ptr(d.u, f64, sh["u"], "u")
+    pr.v = _ptr(d.v, f64, sh["v"], "v")
+    pr.w = _ptr(d.w, f64, sh["w"], "w")
+    pr.phi = _ptr(d.phi, f64, sh["phi"], "phi") if d.phi is not None else None
+    return pr
+
+
+def project_batch(params_list, tensors_list, stream=None):
+    """Solve many problems with shared launches; returns (code, [stats dicts])."""
+    n = len(params_list)
+    arr = (Problem * n)()
+    for i, (p, d) in enumerate(zip(params_list, tensors_list)):
+        arr[i] = problem_struct(p, d)
+    stats = (Stats * max(n, 1))()
+    code = lib().project_batch(n, arr, stats, _stream(stream))
+    return code, [stats[i].as_dict() for i in range(n)]
+
+
+class Server:
+    """serve_create / serve_submit / serve_poll / serve_wait / serve_destroy."""
+
+    def __init__(self, hbm_budget_bytes, max_inflight=64):
+        self._s = ctypes.c_void_p()
+        _check(lib().serve_create(int(hbm_budget_bytes), int(max_inflight), ctypes.byref(self._s)))
+        self._keep = {}
+
+    def submit(self, params: Params, d) -> int:
+        pr = problem_struct(params, d)
+        t = ctypes.c_uint64()
+        _check(lib().serve_submit(self._s, ctypes.byref(pr), ctypes.byref(t)))
+        self._keep[t.value] = d            # keep the buffers alive until done
+        return t.value
+
+    def poll(self, ticket):
+        st = Stats()
+        code = lib().serve_poll(self._s, ticket, ctypes.byref(st))
+        if code == MG_PENDING:
+            return None
+        self._keep.pop(ticket, None)
+        out = st.as_dict()
+        out["code"] = code
+        return out
+
+    def wait(self, ticket):
+        st = Stats()
+        code = lib().serve_wait(self._s, ticket, ctypes.byref(st))
+        self._keep.pop(ticket, None)
+        out = st.as_dict()
+        out["code"] = code
+        return out
+
+    def counters(self):
+        c = (ctypes.c_double * 6)()
+        _check(lib().serve_counters(self._s, c))
+        return {"submitted": c[0], "completed": c[1], "queued": c[2], "inflight": c[3],
+                "resident_bytes": c[4], "peak_inflight": c[5]}
+
+    def close(self):
+        if self._s.value:
+            lib().serve_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+serve_create = Server

@@ -14,3 +14,14 @@ if HERE not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session")
+def mp():
+    """The HIP binding, loaded on a GPU (fails loudly if the library is missing)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_1910_12979_amd import macproj
+    macproj.lib()
+    return macproj
