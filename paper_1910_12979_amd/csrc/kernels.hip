@@ -246,29 +246,80 @@ __global__ void k_rbgs_colour(int nx, int ny, int nz, T h2, T* __restrict__ phi,
     phi[c] = (num - h2 * f[c]) / den;
 }
 
-// (L phi)_c * h^2 ... returned as (sum_f b_f (phi_nb - phi_c)) / h^2.
+// Face coefficients of a cell: stored per-cell low-face arrays (any level).
 template <typename T>
+struct StoredCoeff {
+    const T* bx;
+    const T* by;
+    const T* bz;
+    __device__ inline void get(size_t c, size_t cxp, size_t cyp, size_t czp, int, int, int, int, int, int,
+                               T b[6]) const {
+        b[0] = bx[c];
+        b[1] = bx[cxp];
+        b[2] = by[c];
+        b[3] = by[cyp];
+        b[4] = bz[c];
+        b[5] = bz[czp];
+    }
+};
+
+// Finest level: b = beta0_face / (0.5 (rho_L + rho_R)) recomputed from rho and
+// beta0 with the same expression the coefficient kernel stores.
+struct RhoCoeff {
+    const double* rho;
+    const double* b0c;
+    const double* b0e;
+    int nx, ny, nz, px, py, pz;
+    // low face of the cell at flat index c (coordinates i, j, k) in direction d
+    __device__ inline double low(int d, size_t c, int i, int j, int k) const {
+        const size_t plane = (size_t)nx * ny;
+        const double rc = rho[c];
+        if (d == 0) {
+            if (i > 0) return b0c[k] / (0.5 * (rho[c - 1] + rc));
+            return px ? b0c[k] / (0.5 * (rho[c + (nx - 1)] + rc)) : 0.0;
+        }
+        if (d == 1) {
+            if (j > 0) return b0c[k] / (0.5 * (rho[c - nx] + rc));
+            return py ? b0c[k] / (0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc)) : 0.0;
+        }
+        if (k > 0) return b0e[k] / (0.5 * (rho[c - plane] + rc));
+        return pz ? b0e[0] / (0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc)) : 0.0;
+    }
+    __device__ inline void get(size_t c, size_t cxp, size_t cyp, size_t czp, int i, int j, int k, int ip,
+                               int jp, int kp, double b[6]) const {
+        b[0] = low(0, c, i, j, k);
+        b[1] = low(0, cxp, ip, j, k);
+        b[2] = low(1, c, i, j, k);
+        b[3] = low(1, cyp, i, jp, k);
+        b[4] = low(2, c, i, j, k);
+        b[5] = low(2, czp, i, j, kp);
+    }
+};
+
+// (L phi)_c = (sum_f b_f (phi_nb - phi_c)) / h^2, faces in the fixed order.
+template <typename T, typename C>
 __device__ inline T apply_cell(int i, int j, int k, int nx, int ny, int nz, T h2, const T* __restrict__ phi,
-                               const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz) {
+                               const C& coef) {
     int im = i > 0 ? i - 1 : nx - 1, ip = i < nx - 1 ? i + 1 : 0;
     int jm = j > 0 ? j - 1 : ny - 1, jp = j < ny - 1 ? j + 1 : 0;
     int km = k > 0 ? k - 1 : nz - 1, kp = k < nz - 1 ? k + 1 : 0;
     size_t c = cidx(i, j, k, nx, ny);
+    size_t cxp = cidx(ip, j, k, nx, ny), cyp = cidx(i, jp, k, nx, ny), czp = cidx(i, j, kp, nx, ny);
+    T b[6];
+    coef.get(c, cxp, cyp, czp, i, j, k, ip, jp, kp, b);
     T pc = phi[c];
-    T s = bx[c] * (phi[cidx(im, j, k, nx, ny)] - pc);
-    s = s + bx[cidx(ip, j, k, nx, ny)] * (phi[cidx(ip, j, k, nx, ny)] - pc);
-    s = s + by[c] * (phi[cidx(i, jm, k, nx, ny)] - pc);
-    s = s + by[cidx(i, jp, k, nx, ny)] * (phi[cidx(i, jp, k, nx, ny)] - pc);
-    s = s + bz[c] * (phi[cidx(i, j, km, nx, ny)] - pc);
-    s = s + bz[cidx(i, j, kp, nx, ny)] * (phi[cidx(i, j, kp, nx, ny)] - pc);
+    T s = b[0] * (phi[cidx(im, j, k, nx, ny)] - pc);
+    s = s + b[1] * (phi[cxp] - pc);
+    s = s + b[2] * (phi[cidx(i, jm, k, nx, ny)] - pc);
+    s = s + b[3] * (phi[cyp] - pc);
+    s = s + b[4] * (phi[cidx(i, j, km, nx, ny)] - pc);
+    s = s + b[5] * (phi[czp] - pc);
     return s / h2;
 }
 
-template <typename T>
+template <typename T, typename Coef>
 __global__ void k_resid_restrict(int nx, int ny, int nz, T h2, const T* __restrict__ phi,
-                                 const T* __restrict__ f, const T* __restrict__ bx,
-                                 const T* __restrict__ by, const T* __restrict__ bz, T* __restrict__ fc,
-                                 T* __restrict__ phic) {
+                                 const T* __restrict__ f, Coef coef, T* __restrict__ fc, T* __restrict__ phic) {
     int cx = nx / 2, cy = ny / 2, cz = nz / 2;
     int I = blockIdx.x * blockDim.x + threadIdx.x;
     int J = blockIdx.y * blockDim.y + threadIdx.y;
@@ -279,7 +330,7 @@ __global__ void k_resid_restrict(int nx, int ny, int nz, T h2, const T* __restri
         for (int dj = 0; dj < 2; ++dj)
             for (int di = 0; di < 2; ++di) {
                 int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-                T r = f[cidx(i, j, k, nx, ny)] - apply_cell<T>(i, j, k, nx, ny, nz, h2, phi, bx, by, bz);
+                T r = f[cidx(i, j, k, nx, ny)] - apply_cell<T>(i, j, k, nx, ny, nz, h2, phi, coef);
                 s = s + r;
             }
     size_t C = cidx(I, J, K, cx, cy);
@@ -297,10 +348,9 @@ __global__ void k_prolong(int nx, int ny, int nz, T* __restrict__ phi, const T* 
     phi[c] = phi[c] + phic[cidx(i / 2, j / 2, k / 2, nx / 2, ny / 2)];
 }
 
-template <typename T>
+template <typename T, typename Coef>
 __global__ __launch_bounds__(kBlock) void k_resid_norm(int nx, int ny, int nz, T h2, const T* __restrict__ phi,
-                                                       const T* __restrict__ f, const T* __restrict__ bx,
-                                                       const T* __restrict__ by, const T* __restrict__ bz,
+                                                       const T* __restrict__ f, Coef coef,
                                                        double* __restrict__ r_out, double* __restrict__ partials) {
     const size_t N = (size_t)nx * ny * nz;
     double s = 0.0, mx = 0.0, nonfin = 0.0;
@@ -308,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(int nx, int ny, int nz, T
         int i = (int)(c % nx);
         int j = (int)((c / nx) % ny);
         int k = (int)(c / ((size_t)nx * ny));
-        double r = (double)(f[c] - apply_cell<T>(i, j, k, nx, ny, nz, h2, phi, bx, by, bz));
+        double r = (double)(f[c] - apply_cell<T>(i, j, k, nx, ny, nz, h2, phi, coef));
         if (r_out) r_out[c] = r;
         if (!finite_d(r)) nonfin += 1.0;
         s += r * r;
@@ -566,8 +616,9 @@ template <typename T>
 hipError_t launch_resid_restrict(const Shape& fine, double h, const T* phi, const T* f, const T* bx,
                                  const T* by, const T* bz, T* fc, T* phic, hipStream_t st) {
     Launch3 L = cell_launch(fine.nx / 2, fine.ny / 2, fine.nz / 2);
-    hipLaunchKernelGGL(k_resid_restrict<T>, L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz, (T)(h * h), phi,
-                       f, bx, by, bz, fc, phic);
+    StoredCoeff<T> coef{bx, by, bz};
+    hipLaunchKernelGGL((k_resid_restrict<T, StoredCoeff<T>>), L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz,
+                       (T)(h * h), phi, f, coef, fc, phic);
     return hipGetLastError();
 }
 
@@ -582,8 +633,9 @@ template <typename T>
 hipError_t launch_resid_norm(const Shape& s, double h, const T* phi, const T* f, const T* bx, const T* by,
                              const T* bz, double* partials, int* nparts, hipStream_t st) {
     int nb = partial_blocks(s.N());
-    hipLaunchKernelGGL(k_resid_norm<T>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, (T)(h * h), phi, f,
-                       bx, by, bz, (double*)nullptr, partials);
+    StoredCoeff<T> coef{bx, by, bz};
+    hipLaunchKernelGGL((k_resid_norm<T, StoredCoeff<T>>), dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz,
+                       (T)(h * h), phi, f, coef, (double*)nullptr, partials);
     *nparts = nb;
     return hipGetLastError();
 }
@@ -592,9 +644,30 @@ hipError_t launch_resid_store(const Shape& s, double h, const double* phi, const
                               const double* bx, const double* by, const double* bz, double* r,
                               double* partials, int* nparts, hipStream_t st) {
     int nb = partial_blocks(s.N());
-    hipLaunchKernelGGL(k_resid_norm<double>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, h * h, phi, f,
-                       bx, by, bz, r, partials);
+    StoredCoeff<double> coef{bx, by, bz};
+    hipLaunchKernelGGL((k_resid_norm<double, StoredCoeff<double>>), dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny,
+                       s.nz, h * h, phi, f, coef, r, partials);
     *nparts = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_norm_rho(const Shape& s, double h, const RhoArgs& ra, const double* phi,
+                                 const double* f, double* r_out, double* partials, int* nparts,
+                                 hipStream_t st) {
+    int nb = partial_blocks(s.N());
+    RhoCoeff coef{ra.rho, ra.b0c, ra.b0e, s.nx, s.ny, s.nz, ra.px, ra.py, ra.pz};
+    hipLaunchKernelGGL((k_resid_norm<double, RhoCoeff>), dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz,
+                       h * h, phi, f, coef, r_out, partials);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_restrict_rho(const Shape& fine, double h, const RhoArgs& ra, const double* phi,
+                                     const double* f, double* fc, double* phic, hipStream_t st) {
+    Launch3 L = cell_launch(fine.nx / 2, fine.ny / 2, fine.nz / 2);
+    RhoCoeff coef{ra.rho, ra.b0c, ra.b0e, fine.nx, fine.ny, fine.nz, ra.px, ra.py, ra.pz};
+    hipLaunchKernelGGL((k_resid_restrict<double, RhoCoeff>), L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz,
+                       h * h, phi, f, coef, fc, phic);
     return hipGetLastError();
 }
 

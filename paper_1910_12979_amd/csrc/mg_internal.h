@@ -35,11 +35,21 @@ struct Level {
     double h = 0.0;
     LevelArrays<double> d;   // FP64 arrays
     LevelArrays<float> s;    // FP32 mirrors (mixed precision only)
+    double* phi2_d = nullptr;  // second phi buffer (out-of-place sweeps swap with d.phi)
+    float* phi2_s = nullptr;
 };
 
 struct Shape {
     int nx, ny, nz;
     size_t N() const { return (size_t)nx * ny * nz; }
+};
+
+// Finest-level coefficient source: rho, beta0 and the periodic flags.
+struct RhoArgs {
+    const double* rho;
+    const double* b0c;
+    const double* b0e;
+    int px, py, pz;
 };
 
 // ---- kernel launchers (kernels.hip) ---------------------------------------
@@ -82,6 +92,13 @@ template <typename T>
 hipError_t launch_resid_norm(const Shape& s, double h, const T* phi, const T* f, const T* bx,
                              const T* by, const T* bz, double* partials, int* nparts,
                              hipStream_t st);
+// Finest level, coefficients recomputed from rho: residual partial rows (r
+// stored when r_out != nullptr) and fused residual + restriction.
+hipError_t launch_resid_norm_rho(const Shape& s, double h, const RhoArgs& ra, const double* phi,
+                                 const double* f, double* r_out, double* partials, int* nparts,
+                                 hipStream_t st);
+hipError_t launch_resid_restrict_rho(const Shape& fine, double h, const RhoArgs& ra, const double* phi,
+                                     const double* f, double* fc, double* phic, hipStream_t st);
 // Coarsest level: build M = -A + c 1 1^T from the coefficients and invert it
 // in place (one workgroup).  minv holds N*N doubles.
 hipError_t launch_coarse_setup(const Shape& s, double h, const double* bx, const double* by,
@@ -108,11 +125,11 @@ hipError_t launch_copy(double* dst, const double* src, size_t n, hipStream_t st)
 hipError_t launch_resid_store(const Shape& s, double h, const double* phi, const double* f,
                               const double* bx, const double* by, const double* bz, double* r,
                               double* partials, int* nparts, hipStream_t st);
-// r32 = (float)(r * scale).
-hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* scale_inv,
+// r32 = (float)(r / *rmax), rmax = max |r| (a device scalar).
+hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* rmax,
                          hipStream_t st);
-// phi += (double)e32 * (*scale_inv).
-hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const double* scale_inv,
+// phi += (double)e32 * (*rmax).
+hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const double* rmax,
                              hipStream_t st);
 // FP32 copies of the coefficients.
 hipError_t launch_coeff_to_f32(const double* a, float* b, size_t n, hipStream_t st);

@@ -31,6 +31,10 @@ struct mg_hierarchy {
     double* host = nullptr;       // pinned mirror of scal
     double* minv = nullptr;       // inverse of the coarsest-level matrix
     double* r64 = nullptr;        // FP64 residual (mixed precision)
+    double* rho_own = nullptr;    // copies made by mg_set_coefficients
+    double* b0c_own = nullptr;
+    double* b0e_own = nullptr;
+    mg::RhoArgs rho{};            // finest-level coefficient source of the current solve
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 

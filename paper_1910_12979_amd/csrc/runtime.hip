@@ -15,6 +15,7 @@
 
 #include "mg_internal.h"
 #include "runtime.h"
+#include "sweep.h"
 
 namespace mg {
 
@@ -92,8 +93,11 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
         d.bx = (double*)take(N * 8);
         d.by = (double*)take(N * 8);
         d.bz = (double*)take(N * 8);
+        double* phi2_d = (double*)take(N * 8);
+        float* phi2_s = nullptr;
         LevelArrays<float> s;
         if (mixed) {
+            phi2_s = (float*)take(N * 4);
             s.phi = (float*)take(N * 4);
             s.f = (float*)take(N * 4);
             s.bx = (float*)take(N * 4);
@@ -103,6 +107,8 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
         if (H) {
             H->lev[l].d = d;
             H->lev[l].s = s;
+            H->lev[l].phi2_d = phi2_d;
+            H->lev[l].phi2_s = phi2_s;
         }
     }
     size_t Nc = (size_t)(p->n[0] >> (nl - 1)) * (p->n[1] >> (nl - 1)) * (p->n[2] >> (nl - 1));
@@ -110,12 +116,19 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
     double* partials = (double*)take((size_t)2048 * kReduceWidth * 8);
     double* scal = (double*)take(64 * 8);
     double* r64 = nullptr;
-    if (mixed) r64 = (double*)take((size_t)p->n[0] * p->n[1] * p->n[2] * 8);
+    size_t N0 = (size_t)p->n[0] * p->n[1] * p->n[2];
+    if (mixed) r64 = (double*)take(N0 * 8);
+    double* rho_own = (double*)take(N0 * 8);
+    double* b0c_own = (double*)take((size_t)p->n[2] * 8);
+    double* b0e_own = (double*)take((size_t)(p->n[2] + 1) * 8);
     if (H) {
         H->minv = minv;
         H->partials = partials;
         H->scal = scal;
         H->r64 = r64;
+        H->rho_own = rho_own;
+        H->b0c_own = b0c_own;
+        H->b0e_own = b0e_own;
     }
     return off;
 }
@@ -247,49 +260,116 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
     return MG_OK;
 }
 
-// V-cycle from level l on the FP64 arrays.
-static int vcycle64(mg_hierarchy* H, int l, hipStream_t st) {
+// Sweeps on level l.  `first` selects what the first sweep reads as its
+// input: kInPlain (phi as stored), kInZero (phi = 0, nothing read) or
+// kInProlong (phi + P phi_{l+1}).  Levels large enough for the fused
+// out-of-place sweep ping-pong between the two phi buffers; smaller levels
+// use the per-colour kernels in place.
+template <typename T>
+static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st) {
+    constexpr bool dbl = std::is_same<T, double>::value;
     Level& F = H->lev[l];
-    if (l == H->nlev - 1) {
-        HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st));
+    LevelArrays<T>* A;
+    T** alt;
+    if constexpr (dbl) {
+        A = &F.d;
+        alt = &F.phi2_d;
+    } else {
+        A = &F.s;
+        alt = &F.phi2_s;
+    }
+    const T* phic = nullptr;
+    if (l + 1 < H->nlev) {
+        if constexpr (dbl) phic = H->lev[l + 1].d.phi;
+        else phic = H->lev[l + 1].s.phi;
+    }
+    Shape s = shape_of(F);
+    if (first == kInProlong && nsweeps == 0) {
+        HIPCHK(launch_prolong<T>(s, A->phi, phic, st));
         return MG_OK;
     }
-    Level& C = H->lev[l + 1];
-    Shape s = shape_of(F);
-    HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, H->p.pre_sweeps, st));
-    HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f, C.d.phi, st));
-    int rc = vcycle64(H, l + 1, st);
-    if (rc) return rc;
-    HIPCHK(launch_prolong<double>(s, F.d.phi, C.d.phi, st));
-    HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, H->p.post_sweeps, st));
+    if (!sweep_fusable<T>(F.nx, F.ny, F.nz)) {
+        if (first == kInProlong) HIPCHK(launch_prolong<T>(s, A->phi, phic, st));
+        if (first == kInZero) HIPCHK(launch_fill<T>(A->phi, F.N, T(0), st));
+        HIPCHK(launch_rbgs<T>(s, F.h, A->phi, A->f, A->bx, A->by, A->bz, nsweeps, st));
+        return MG_OK;
+    }
+    const bool use_rho = dbl && l == 0 && H->rho.rho != nullptr;
+    for (int k = 0; k < nsweeps; ++k) {
+        SweepArgs<T> a{};
+        a.nx = F.nx;
+        a.ny = F.ny;
+        a.nz = F.nz;
+        a.px = H->px;
+        a.py = H->py;
+        a.pz = H->pz;
+        a.tz = 0;
+        a.h2 = (T)(F.h * F.h);
+        a.phi_in = A->phi;
+        a.phi_out = *alt;
+        a.f = A->f;
+        a.phic = phic;
+        a.bx = A->bx;
+        a.by = A->by;
+        a.bz = A->bz;
+        a.rho = H->rho.rho;
+        a.b0c = H->rho.b0c;
+        a.b0e = H->rho.b0e;
+        HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain, sweep_config_for(F.nx, F.ny, F.nz), st));
+        std::swap(A->phi, *alt);
+    }
     return MG_OK;
 }
 
-// V-cycle from level l on the FP32 arrays; the coarsest solve runs in FP64.
-static int vcycle32(mg_hierarchy* H, int l, hipStream_t st) {
+// r_l = f_l - L phi_l restricted into f_{l+1}; phi_{l+1} = 0.
+template <typename T>
+static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
     Level& F = H->lev[l];
-    if (l == H->nlev - 1) {
-        HIPCHK(launch_coarse_solve_f32((int)F.N, H->minv, F.s.f, F.s.phi, st));
-        return MG_OK;
-    }
     Level& C = H->lev[l + 1];
     Shape s = shape_of(F);
-    HIPCHK(launch_rbgs<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, H->p.pre_sweeps, st));
-    HIPCHK(launch_resid_restrict<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, C.s.f, C.s.phi, st));
-    int rc = vcycle32(H, l + 1, st);
-    if (rc) return rc;
-    HIPCHK(launch_prolong<float>(s, F.s.phi, C.s.phi, st));
-    HIPCHK(launch_rbgs<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, H->p.post_sweeps, st));
+    if constexpr (std::is_same<T, double>::value) {
+        if (l == 0 && H->rho.rho) {
+            HIPCHK(launch_resid_restrict_rho(s, F.h, H->rho, F.d.phi, F.d.f, C.d.f, C.d.phi, st));
+            return MG_OK;
+        }
+        HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f, C.d.phi, st));
+    } else {
+        HIPCHK(launch_resid_restrict<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, C.s.f, C.s.phi, st));
+    }
     return MG_OK;
 }
 
-int vcycle_from(mg_hierarchy* H, int l, hipStream_t st) { return vcycle64(H, l, st); }
+// V-cycle from level l (FP64 or FP32 arrays; the coarsest solve is FP64).
+template <typename T>
+static int vcycle(mg_hierarchy* H, int l, hipStream_t st) {
+    Level& F = H->lev[l];
+    if (l == H->nlev - 1) {
+        if constexpr (std::is_same<T, double>::value)
+            HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st));
+        else
+            HIPCHK(launch_coarse_solve_f32((int)F.N, H->minv, F.s.f, F.s.phi, st));
+        return MG_OK;
+    }
+    int rc = smooth<T>(H, l, H->p.pre_sweeps, l == 0 ? kInPlain : kInZero, st);
+    if (rc) return rc;
+    rc = resid_restrict<T>(H, l, st);
+    if (rc) return rc;
+    rc = vcycle<T>(H, l + 1, st);
+    if (rc) return rc;
+    return smooth<T>(H, l, H->p.post_sweeps, kInProlong, st);
+}
 
-// Relative residual of level 0 (FP64) into host[kSlotRes*4..]; returns status.
+static int vcycle64(mg_hierarchy* H, int l, hipStream_t st) { return vcycle<double>(H, l, st); }
+static int vcycle32(mg_hierarchy* H, int l, hipStream_t st) { return vcycle<float>(H, l, st); }
+
+// Relative residual of level 0 (FP64) into host[kSlotRes*4..]; r stored in
+// r_store when given.
 static int level0_residual(mg_hierarchy* H, double* r_store, hipStream_t st) {
     Level& L0 = H->lev[0];
     int np = 0;
-    if (r_store) {
+    if (H->rho.rho) {
+        HIPCHK(launch_resid_norm_rho(shape_of(L0), L0.h, H->rho, L0.d.phi, L0.d.f, r_store, H->partials, &np, st));
+    } else if (r_store) {
         HIPCHK(launch_resid_store(shape_of(L0), L0.h, L0.d.phi, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, r_store,
                                   H->partials, &np, st));
     } else {
@@ -362,8 +442,9 @@ static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStrea
     return status;
 }
 
-int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
-            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st) {
+static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
+                        const double* S, double* u, double* v, double* w, double* phi_out, mg_stats* stats,
+                        hipStream_t st) {
     if (!H || !rho || !b0c || !b0e || !S || !u || !v || !w) {
         set_error("null argument to mac_project");
         return MG_ERR_INVALID_ARG;
@@ -375,6 +456,13 @@ int project(mg_hierarchy* H, const double* rho, const double* b0c, const double*
     S_->nlevels = H->nlev;
     HIPCHK(hipEventRecord(H->ev0, st));
     Level& L0 = H->lev[0];
+    // the fused finest-level sweep reads rho as 16-byte pairs
+    const double* rho_src = rho;
+    if (((uintptr_t)rho & 15) != 0) {
+        HIPCHK(launch_copy(H->rho_own, rho, L0.N, st));
+        rho_src = H->rho_own;
+    }
+    H->rho = RhoArgs{rho_src, b0c, b0e, H->px, H->py, H->pz};
     int rc = build_coefficients(H, rho, b0c, b0e, S, u, v, w, st);
     if (rc) return rc;
     rc = read_scalars(H, kSlotRhs * kReduceWidth, kReduceWidth, st);
@@ -435,6 +523,15 @@ int project(mg_hierarchy* H, const double* rho, const double* b0c, const double*
     S_->status = status;
     if (status == MG_ERR_NOT_CONVERGED) set_error("maximum number of cycles reached");
     return status;
+}
+
+int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
+            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st) {
+    int rc = project_impl(H, rho, b0c, b0e, S, u, v, w, phi_out, stats, st);
+    // the caller's rho may not outlive the call: later mg_vcycle / step calls
+    // use the stored finest-level coefficients (bit-identical values)
+    if (H) H->rho = RhoArgs{};
+    return rc;
 }
 
 int vcycle_api(mg_hierarchy* H, double* phi, const double* rhs, double* rel_out, hipStream_t st) {
@@ -501,21 +598,24 @@ int level_step(mg_hierarchy* H, int l, int step, int arg, hipStream_t st) {
     Shape s = shape_of(F);
     bool has_coarse = l + 1 < H->nlev;
     switch (step) {
-        case MG_STEP_SMOOTH:
+        case MG_STEP_SMOOTH: {
             if (!has_coarse) break;
-            HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, arg, st));
+            int rc = smooth<double>(H, l, arg, kInPlain, st);
+            if (rc) return rc;
             break;
+        }
         case MG_STEP_RESID_RESTRICT:
         case MG_STEP_DOWN: {
             if (!has_coarse) {
                 set_error("no coarser level");
                 return MG_ERR_INVALID_ARG;
             }
-            Level& C = H->lev[l + 1];
-            if (step == MG_STEP_DOWN)
-                HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, arg, st));
-            HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f,
-                                                 C.d.phi, st));
+            if (step == MG_STEP_DOWN) {
+                int rc = smooth<double>(H, l, arg, kInPlain, st);
+                if (rc) return rc;
+            }
+            int rc = resid_restrict<double>(H, l, st);
+            if (rc) return rc;
             break;
         }
         case MG_STEP_PROLONG:
@@ -524,10 +624,8 @@ int level_step(mg_hierarchy* H, int l, int step, int arg, hipStream_t st) {
                 set_error("no coarser level");
                 return MG_ERR_INVALID_ARG;
             }
-            Level& C = H->lev[l + 1];
-            HIPCHK(launch_prolong<double>(s, F.d.phi, C.d.phi, st));
-            if (step == MG_STEP_UP)
-                HIPCHK(launch_rbgs<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, arg, st));
+            int rc = smooth<double>(H, l, step == MG_STEP_UP ? arg : 0, kInProlong, st);
+            if (rc) return rc;
             break;
         }
         case MG_STEP_COARSE:
@@ -620,7 +718,14 @@ int mg_set_coefficients(mg_handle h, const double* rho, const double* beta0_cc, 
         return MG_ERR_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
-    int rc = build_coefficients(h, rho, beta0_cc, beta0_edge, nullptr, nullptr, nullptr, nullptr, st);
+    // keep private copies: later mg_vcycle / step calls recompute the
+    // finest-level coefficients from them
+    const int nz = h->p.n[2];
+    HIPCHK(launch_copy(h->rho_own, rho, h->lev[0].N, st));
+    HIPCHK(launch_copy(h->b0c_own, beta0_cc, (size_t)nz, st));
+    HIPCHK(launch_copy(h->b0e_own, beta0_edge, (size_t)nz + 1, st));
+    h->rho = RhoArgs{h->rho_own, h->b0c_own, h->b0e_own, h->px, h->py, h->pz};
+    int rc = build_coefficients(h, h->rho_own, h->b0c_own, h->b0e_own, nullptr, nullptr, nullptr, nullptr, st);
     if (rc) return rc;
     rc = read_scalars(h, kSlotRhs * kReduceWidth, kReduceWidth, st);
     if (rc) return rc;
@@ -672,6 +777,15 @@ int mg_level_copy(mg_handle h, int32_t level, int32_t array, void* buffer, int32
 
 int mg_level_step(mg_handle h, int32_t level, int32_t step, int32_t arg, void* stream) {
     return level_step(h, level, step, arg, (hipStream_t)stream);
+}
+
+int mg_tune_sweep(int32_t cfg) {
+    if (cfg < -1 || cfg >= kNumSweepCfg) {
+        set_error("sweep configuration out of range");
+        return MG_ERR_INVALID_ARG;
+    }
+    sweep_force_config(cfg);
+    return MG_OK;
 }
 
 const char* mg_strerror(int code) {

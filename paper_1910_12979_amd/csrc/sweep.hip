@@ -1,0 +1,407 @@
+// Fused red-black Gauss-Seidel sweep for gfx950.
+//
+// One launch performs a whole sweep (red cells, then black cells) out of
+// place: phi_out = RBGS(phi_in).  A workgroup owns a TX x TY column tile and
+// marches through a chunk of z planes.  Per plane, the red update is computed
+// on the tile plus a one-cell ring (redundantly with the neighbouring tiles)
+// so the black update of every tile cell finds all four in-plane red
+// neighbours locally; phi_in is only read, so neighbouring workgroups never
+// race.  In-plane neighbours come from LDS planes, z-neighbours from
+// registers that slide with the march.
+//
+// Each thread owns an x-pair of cells (even x, odd x).  At every plane one
+// cell of a pair is red and the other black, so the red stage and the black
+// stage each update exactly one cell per thread (no lane divergence), and
+// pairs move as 16-byte loads and stores.  Global loads run two planes ahead
+// of their use through a small register queue so HBM latency is hidden
+// behind the work of the planes in between.
+//
+// Coefficient source: on the finest level the face coefficients
+// b = beta0_face / (0.5 (rho_L + rho_R)) are recomputed from rho and beta0
+// (8 bytes per cell instead of 24), with the same expression as everywhere
+// else so the values are bit-identical to stored ones; coarser levels read
+// their stored (averaged) coefficients.
+//
+// Input variants: phi_in = 0 (first pre-sweep on a coarse level), phi_in as
+// stored, or phi_in + P phi_coarse (first post-sweep: the prolongation is
+// folded into the load).
+//
+// The per-cell update order is the same as the reference definition:
+//   num = bxl*phi(x-1) + bxh*phi(x+1) + byl*phi(y-1) + byh*phi(y+1)
+//       + bzl*phi(z-1) + bzh*phi(z+1);  den = bxl+bxh+byl+byh+bzl+bzh;
+//   phi = (num - h^2 f) / den.
+#include <hip/hip_runtime.h>
+
+#include "mg_internal.h"
+#include "sweep.h"
+
+namespace mg {
+namespace {
+
+constexpr int kNumXcd = 8;
+
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+    using type = double2;
+};
+template <>
+struct V2<float> {
+    using type = float2;
+};
+
+template <typename T>
+__device__ inline void ld2(const T* p, T& a, T& b) {
+    typename V2<T>::type v = *reinterpret_cast<const typename V2<T>::type*>(p);
+    a = v.x;
+    b = v.y;
+}
+
+template <typename T>
+__device__ inline void st2(T* p, T a, T b) {
+    typename V2<T>::type v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<typename V2<T>::type*>(p) = v;
+}
+
+__device__ inline int wrap3(int g, int n) {
+    if (g < 0) g += n;
+    if (g >= n) g -= n;
+    if (g >= n) g -= n;
+    return g;
+}
+
+// Map a launch-order block id to a tile id so that each XCD (blocks are
+// dealt round-robin across the 8 XCDs) works on a contiguous range of tiles
+// and their shared halos stay in that XCD's L2.
+__device__ inline int xcd_tile(int b, int total) {
+    if (total % kNumXcd != 0) return b;
+    return (b % kNumXcd) * (total / kNumXcd) + b / kNumXcd;
+}
+
+template <typename T, int TX, int TY, bool kRho, int kIn>
+__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> a) {
+    constexpr int WX = TX + 4, WY = TY + 4, WP = WX / 2;   // ring-2 window, pairs per row
+    constexpr int NB = kSweepTZMax + 6;                    // beta0 planes staged per chunk
+    __shared__ T sphi[WY][WX];                // phi_in, current plane
+    __shared__ T sR[2][WY][WX];               // red-stage values, planes t and t-1
+    __shared__ T sbx[3][WY][WX];              // low x-face coefficients, planes t+1, t, t-1
+    __shared__ T sby[3][WY][WX];
+    __shared__ T srho[kRho ? WY : 1][kRho ? WX : 1];
+    __shared__ double sb0c[kRho ? NB : 1], sb0e[kRho ? NB : 1];
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % a.ntx;
+    const int ty = (tile / a.ntx) % a.nty;
+    const int tz = tile / (a.ntx * a.nty);
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = tz * a.tz;
+    const int z1 = min(z0 + a.tz, nz);
+    const int zb = z0 - 2;                    // first plane touched
+
+    const int lp = threadIdx.x % WP;
+    const int ly = threadIdx.x / WP;
+    const int lx0 = 2 * lp;
+    const int gx0 = x0 - 2 + lx0;             // even; the pair never straddles the wrap
+    const int gy = y0 - 2 + ly;
+    const int gxw = wrap3(gx0, nx);
+    const int gyw = wrap3(gy, ny);
+    const bool row_r1 = ly >= 1 && ly < WY - 1;
+    const bool r1c0 = row_r1 && lp >= 1;            // even cell inside the ring-1 window
+    const bool r1c1 = row_r1 && lp < WP - 1;        // odd cell
+    const bool writes = ly >= 2 && ly < WY - 2 && lp >= 1 && lp <= WP - 2 && gx0 < nx && gy < ny;
+    const size_t plane = (size_t)nx * ny;
+    const size_t col = (size_t)gyw * nx + gxw;
+    const T h2 = a.h2;
+    const T half = T(0.5);
+
+    size_t ccol = 0;
+    if (kIn == kInProlong) ccol = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
+
+    auto load_phi = [&](int t, T& v0, T& v1) {
+        if (kIn == kInZero) {
+            v0 = T(0);
+            v1 = T(0);
+            return;
+        }
+        int tw = wrap3(t, nz);
+        ld2(a.phi_in + (size_t)tw * plane + col, v0, v1);
+        if (kIn == kInProlong) {
+            T c = a.phic[(size_t)(tw >> 1) * (plane >> 2) + ccol];
+            v0 = v0 + c;
+            v1 = v1 + c;
+        }
+    };
+    auto load_f = [&](int t, T& v0, T& v1) {
+        int tw = wrap3(t, nz);
+        ld2(a.f + (size_t)tw * plane + col, v0, v1);
+    };
+    // rho (finest level) or the stored low z-face coefficient of plane t
+    auto load_q = [&](int t, T& v0, T& v1) {
+        int tw = wrap3(t, nz);
+        if (kRho) ld2((const T*)a.rho + (size_t)tw * plane + col, v0, v1);
+        else ld2(a.bz + (size_t)tw * plane + col, v0, v1);
+    };
+    // low z-face coefficient of plane t from the queue values of planes t-1, t
+    auto zface = [&](int t, T q_below, T q_here) -> T {
+        if (!kRho) return q_here;
+        int tw = wrap3(t, nz);
+        T b0 = (T)sb0e[t - zb];
+        if (tw == 0) return a.pz ? b0 / (half * (q_below + q_here)) : T(0);
+        return b0 / (half * (q_below + q_here));
+    };
+
+    // ---- prologue
+    if (kRho) {
+        for (int q = threadIdx.x; q < NB && zb + q <= z1 + 3; q += blockDim.x) {
+            int qw = wrap3(zb + q, nz);
+            sb0c[q] = a.b0c[qw];
+            sb0e[q] = a.b0e[qw];
+        }
+    }
+    // Loads in flight: step s issues plane s+3 (phi, rho or stored bz, stored
+    // bx/by) and plane s+2 (f) into one of two register sets, and step s+2
+    // consumes that set before re-issuing into it, so every load has two
+    // plane-steps of work to arrive.  Loads are always issued (clamped to the
+    // last plane the chunk needs; those reloads hit in cache) so the sets are
+    // plain load results the compiler never has to merge or copy early.
+    struct Fly {
+        T p0, p1;      // phi_in
+        T q0, q1;      // rho (or stored bz)
+        T f0, f1;      // f
+        T x0, x1;      // stored bx (coarse levels)
+        T y0, y1;      // stored by
+    };
+    auto issue = [&](int s, Fly& X) {
+        const int tq = min(s + 3, z1 + 1);
+        load_phi(tq, X.p0, X.p1);
+        load_q(tq, X.q0, X.q1);
+        if (!kRho) {
+            int tw = wrap3(min(s + 3, z1), nz);
+            ld2(a.bx + (size_t)tw * plane + col, X.x0, X.x1);
+            ld2(a.by + (size_t)tw * plane + col, X.y0, X.y1);
+        }
+        load_f(min(s + 2, z1), X.f0, X.f1);
+    };
+    Fly A, B;
+    issue(z0 - 3, A);                                  // consumed by step z0-1
+    issue(z0 - 2, B);                                  // consumed by step z0
+    // window before the first step's rotation
+    T Pm0 = T(0), Pm1 = T(0), Pc0, Pc1, Pp0, Pp1;
+    load_phi(z0 - 2, Pc0, Pc1);
+    load_phi(z0 - 1, Pp0, Pp1);
+    T Rc0, Rc1, Rp0, Rp1;
+    load_q(z0 - 2, Rc0, Rc1);
+    load_q(z0 - 1, Rp0, Rp1);
+    T Fm0 = T(0), Fm1 = T(0), Fc0 = T(0), Fc1 = T(0);
+    T cx0 = T(0), cx1 = T(0), cy0 = T(0), cy1 = T(0);  // stored x/y coefficients of plane t+1
+    if (!kRho) {
+        int tw = wrap3(z0 - 1, nz);
+        T t0, t1;
+        ld2(a.bx + (size_t)tw * plane + col, t0, t1);
+        sbx[(z0 - 1 + 3) % 3][ly][lx0] = t0;
+        sbx[(z0 - 1 + 3) % 3][ly][lx0 + 1] = t1;
+        ld2(a.by + (size_t)tw * plane + col, t0, t1);
+        sby[(z0 - 1 + 3) % 3][ly][lx0] = t0;
+        sby[(z0 - 1 + 3) % 3][ly][lx0 + 1] = t1;
+    }
+    __syncthreads();                                   // beta0 staged
+    T bm0 = T(0), bm1 = T(0), bc0 = T(0), bc1 = T(0);
+    T bp0 = zface(z0 - 1, Rc0, Rp0), bp1 = zface(z0 - 1, Rc1, Rp1);   // low face of plane z0-1
+
+    // x/y low-face coefficients of plane t into LDS slot s from the staged rho plane
+    auto rho_coeffs = [&](int t, int s) {
+        T b0 = (T)sb0c[t - zb];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int lx = lx0 + c;
+            const T rc = srho[ly][lx];
+            T cx = T(0), cy = T(0);
+            const bool xwall = (gxw + c == 0) && !a.px;
+            if (lx > 0 && !xwall) cx = b0 / (half * (srho[ly][lx - 1] + rc));
+            if (ly > 0 && !(gyw == 0 && !a.py)) cy = b0 / (half * (srho[ly - 1][lx] + rc));
+            sbx[s][ly][lx] = cx;
+            sby[s][ly][lx] = cy;
+        }
+    };
+    if (kRho) {
+        srho[ly][lx0] = Rp0;                           // rho of plane z0-1
+        srho[ly][lx0 + 1] = Rp1;
+        __syncthreads();
+        rho_coeffs(z0 - 1, (z0 - 1 + 3) % 3);
+        __syncthreads();                               // srho is rewritten in the first step
+    }
+
+    T Rmm = T(0), Rm = T(0);
+    auto step = [&](int t, Fly& X) {
+        // 0. slide the z window, taking in the set issued two steps ago:
+        //    phi[t+1], rho[t+1] (or bz[t+1]), f[t], bx/by[t+1]; then re-issue
+        Fm0 = Fc0; Fm1 = Fc1;
+        Fc0 = X.f0; Fc1 = X.f1;
+        Pm0 = Pc0; Pm1 = Pc1;
+        Pc0 = Pp0; Pc1 = Pp1;
+        Pp0 = X.p0; Pp1 = X.p1;
+        Rc0 = Rp0; Rc1 = Rp1;
+        Rp0 = X.q0; Rp1 = X.q1;
+        bm0 = bc0; bm1 = bc1;
+        bc0 = bp0; bc1 = bp1;
+        bp0 = zface(t + 1, Rc0, Rp0);
+        bp1 = zface(t + 1, Rc1, Rp1);
+        if (!kRho) {
+            cx0 = X.x0; cx1 = X.x1;
+            cy0 = X.y0; cy1 = X.y1;
+        }
+        issue(t, X);                             // consumed by step t+2
+        const int s_t = (t + 3) % 3, s_p = (t + 4) % 3, s_m = (t + 2) % 3;
+        const int rsel = (gy + t) & 1;           // red cell of the pair at plane t (black at t-1)
+        // 1. stage phi_in of plane t, and rho of plane t+1
+        sphi[ly][lx0] = Pc0;
+        sphi[ly][lx0 + 1] = Pc1;
+        if (kRho) {
+            srho[ly][lx0] = Rp0;
+            srho[ly][lx0 + 1] = Rp1;
+        }
+        __syncthreads();
+        // 2. x/y coefficients of plane t+1 (read after the next barrier)
+        if (t + 1 <= z1) {
+            if (kRho) {
+                rho_coeffs(t + 1, s_p);
+            } else {
+                sbx[s_p][ly][lx0] = cx0;
+                sbx[s_p][ly][lx0 + 1] = cx1;
+                sby[s_p][ly][lx0] = cy0;
+                sby[s_p][ly][lx0 + 1] = cy1;
+            }
+        }
+        // 3. red update at plane t on the tile plus one ring
+        const int lxr = lx0 + rsel;
+        T Rcur = rsel ? Pc1 : Pc0;
+        if (rsel ? r1c1 : r1c0) {
+            const T bxl = sbx[s_t][ly][lxr], bxh = sbx[s_t][ly][lxr + 1];
+            const T byl = sby[s_t][ly][lxr], byh = sby[s_t][ly + 1][lxr];
+            const T bzl = rsel ? bc1 : bc0, bzh = rsel ? bp1 : bp0;
+            T num = bxl * sphi[ly][lxr - 1];
+            num = num + bxh * sphi[ly][lxr + 1];
+            num = num + byl * sphi[ly - 1][lxr];
+            num = num + byh * sphi[ly + 1][lxr];
+            num = num + bzl * (rsel ? Pm1 : Pm0);
+            num = num + bzh * (rsel ? Pp1 : Pp0);
+            T den = bxl + bxh;
+            den = den + byl;
+            den = den + byh;
+            den = den + bzl;
+            den = den + bzh;
+            Rcur = (num - h2 * (rsel ? Fc1 : Fc0)) / den;
+        }
+        sR[(t + 4) & 1][ly][lxr] = Rcur;
+        __syncthreads();
+        // 4. black update at plane t-1 on the tile; write the pair of plane t-1
+        const int tb = t - 1;
+        if (tb >= z0 && writes) {
+            const int sb = (tb + 4) & 1;
+            const int lxb = lx0 + rsel;
+            const T bxl = sbx[s_m][ly][lxb], bxh = sbx[s_m][ly][lxb + 1];
+            const T byl = sby[s_m][ly][lxb], byh = sby[s_m][ly + 1][lxb];
+            const T bzl = rsel ? bm1 : bm0, bzh = rsel ? bc1 : bc0;
+            T num = bxl * sR[sb][ly][lxb - 1];
+            num = num + bxh * sR[sb][ly][lxb + 1];
+            num = num + byl * sR[sb][ly - 1][lxb];
+            num = num + byh * sR[sb][ly + 1][lxb];
+            num = num + bzl * Rmm;
+            num = num + bzh * Rcur;
+            T den = bxl + bxh;
+            den = den + byl;
+            den = den + byh;
+            den = den + bzl;
+            den = den + bzh;
+            const T blk = (num - h2 * (rsel ? Fm1 : Fm0)) / den;
+            T* dst = a.phi_out + (size_t)tb * plane + col;
+            if (rsel) st2(dst, Rm, blk);
+            else st2(dst, blk, Rm);
+        }
+        Rmm = Rm;
+        Rm = Rcur;
+    };
+    int t = z0 - 1;
+    for (; t + 1 <= z1; t += 2) {
+        step(t, A);
+        step(t + 1, B);
+    }
+    if (t <= z1) step(t, A);
+}
+
+template <typename T, int TX, int TY, bool kRho, int kIn>
+hipError_t launch_t(const SweepArgs<T>& a0, int tzc, hipStream_t st) {
+    SweepArgs<T> a = a0;
+    a.tz = tzc;
+    a.ntx = (a.nx + TX - 1) / TX;
+    a.nty = (a.ny + TY - 1) / TY;
+    int ntz = (a.nz + tzc - 1) / tzc;
+    int blocks = a.ntx * a.nty * ntz;
+    hipLaunchKernelGGL((k_sweep<T, TX, TY, kRho, kIn>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_mode(const SweepArgs<T>& a, bool use_rho, int in_mode, int tzc, hipStream_t st) {
+    if (use_rho) {
+        if constexpr (std::is_same<T, double>::value) {
+            switch (in_mode) {
+                case kInZero: return launch_t<T, TX, TY, true, kInZero>(a, tzc, st);
+                case kInPlain: return launch_t<T, TX, TY, true, kInPlain>(a, tzc, st);
+                default: return launch_t<T, TX, TY, true, kInProlong>(a, tzc, st);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+    switch (in_mode) {
+        case kInZero: return launch_t<T, TX, TY, false, kInZero>(a, tzc, st);
+        case kInPlain: return launch_t<T, TX, TY, false, kInPlain>(a, tzc, st);
+        default: return launch_t<T, TX, TY, false, kInProlong>(a, tzc, st);
+    }
+}
+
+int g_forced_cfg = -1;    // set by the tuner (-1: per-shape choice)
+
+}  // namespace
+
+void sweep_force_config(int cfg) { g_forced_cfg = cfg; }
+
+int sweep_config_for(int nx, int ny, int nz) {
+    if (g_forced_cfg >= 0 && g_forced_cfg < kNumSweepCfg) {
+        const SweepCfg& c = kSweepCfgs[g_forced_cfg];
+        if (nx >= c.tx && ny >= c.ty) return g_forced_cfg;
+    }
+    (void)nz;
+    if (nx >= 32 && ny >= 8) return 0;
+    return 5;
+}
+
+template <typename T>
+bool sweep_fusable(int nx, int ny, int nz) {
+    return nx >= kSweepTX && ny >= kSweepTY && nz >= 4 && nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0;
+}
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cfg, hipStream_t st) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
+    switch (cfg) {
+        case 0: return launch_mode<T, 32, 8>(a, use_rho, in_mode, c.tz, st);
+        case 1: return launch_mode<T, 32, 8>(a, use_rho, in_mode, c.tz, st);
+        case 2: return launch_mode<T, 64, 8>(a, use_rho, in_mode, c.tz, st);
+        case 3: return launch_mode<T, 32, 16>(a, use_rho, in_mode, c.tz, st);
+        case 4: return launch_mode<T, 64, 4>(a, use_rho, in_mode, c.tz, st);
+        default: return launch_mode<T, 32, 4>(a, use_rho, in_mode, c.tz, st);
+    }
+}
+
+template bool sweep_fusable<double>(int, int, int);
+template bool sweep_fusable<float>(int, int, int);
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, bool, int, int, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, bool, int, int, hipStream_t);
+
+}  // namespace mg

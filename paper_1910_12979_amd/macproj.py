@@ -96,12 +96,18 @@ def lib():
         L.serve_wait.argtypes = [vp, ctypes.c_uint64, S]
         L.serve_counters.argtypes = [vp, ctypes.POINTER(d)]
         L.serve_destroy.argtypes = [vp]
+        L.mg_tune_sweep.argtypes = [i32]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
         L.mg_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
+
+
+def mg_tune_sweep(cfg: int):
+    """Force a fused-sweep tile configuration (-1: per-shape default)."""
+    _check(lib().mg_tune_sweep(int(cfg)))
 
 
 def last_error() -> str:

@@ -167,23 +167,28 @@ def test_step_coefficients_all_levels(mp):
         assert rel(gz, OH.get(l, "bz")[:-1]) <= 1e-15
 
 
-@pytest.mark.parametrize("per", [(True, True, False), (False, False, False), (True, True, True)])
-def test_step_smooth_restrict_prolong_coarse(mp, per):
-    prob = I.make_problem((32, 16, 24), H=0.2, rho_noise=0.1, seed=12, periodic=per, dx=1 / 32)
+@pytest.mark.parametrize("shape,per", [
+    ((32, 16, 24), (True, True, False)),
+    ((32, 16, 24), (False, False, False)),
+    ((32, 16, 24), (True, True, True)),
+    ((64, 32, 48), (True, True, False)),     # fused sweeps on levels 0 (rho) and 1 (stored)
+    ((72, 40, 48), (False, True, False)),    # ragged fused tiles in x, y and z
+])
+def test_step_smooth_restrict_prolong_coarse(mp, shape, per):
+    prob = I.make_problem(shape, H=0.2, rho_noise=0.1, seed=12, periodic=per, dx=1 / shape[0])
     H, OH = _step_setup(mp, prob)
     rng = np.random.default_rng(7)
-    phi0 = rng.standard_normal((24, 16, 32))
-    f0 = rng.standard_normal((24, 16, 32))
-    f0 -= f0.mean()
+    nx0, ny0, nz0 = shape
     for l in (0, 1):
         (nx, ny, nz), _ = H.level_info(l)
-        phi_l = rng.standard_normal((nz, ny, nx)) if l else phi0
-        f_l = rng.standard_normal((nz, ny, nx)) if l else f0
+        phi_l = rng.standard_normal((nz, ny, nx))
+        f_l = rng.standard_normal((nz, ny, nx))
         _put(H, l, "phi", phi_l); _put(H, l, "f", f_l)
         OH.set(l, "phi", phi_l); OH.set(l, "f", f_l)
-        H.level_step(l, "smooth", 1)
-        OH.smooth(l, 1)
-        assert rel(_get(H, l, "phi"), OH.get(l, "phi")) <= 1e-13
+        H.level_step(l, "smooth", 2)
+        OH.smooth(l, 2)
+        g, o = _get(H, l, "phi"), OH.get(l, "phi")
+        assert rel(g, o) <= 1e-13, (l, rel(g, o), np.max(np.abs(g - o)))
         H.level_step(l, "resid_restrict")
         OH.resid_restrict(l)
         assert rel(_get(H, l + 1, "f"), OH.get(l + 1, "f")) <= 1e-13
@@ -193,6 +198,9 @@ def test_step_smooth_restrict_prolong_coarse(mp, per):
         H.level_step(l, "prolong")
         OH.prolong(l)
         assert rel(_get(H, l, "phi"), OH.get(l, "phi")) <= 1e-14
+        H.level_step(l, "up", 1)
+        OH.prolong(l); OH.smooth(l, 1)
+        assert rel(_get(H, l, "phi"), OH.get(l, "phi")) <= 1e-13
     Lc = H.nlevels - 1
     (nx, ny, nz), _ = H.level_info(Lc)
     fc = rng.standard_normal((nz, ny, nx))
