@@ -372,16 +372,20 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(int nx, int ny, int nz, T
 // of -A) and inverts it in place by Gauss-Jordan elimination (M is SPD, so
 // no pivoting is needed).  The per-cycle solve is then a mat-vec.
 // ---------------------------------------------------------------------------
+template <bool kLds>
 __global__ __launch_bounds__(kBlock) void k_coarse_setup(int nx, int ny, int nz, double h,
                                                          const double* __restrict__ bx,
                                                          const double* __restrict__ by,
                                                          const double* __restrict__ bz,
-                                                         double* __restrict__ M) {
+                                                         double* __restrict__ Mg) {
+    constexpr int kLdsN = 64;
+    __shared__ double Ms[kLds ? kLdsN * kLdsN : 1];
     __shared__ double fac[kCoarseMax];
     __shared__ double shift;
     const int n = nx * ny * nz;
+    double* M = kLds ? Ms : Mg;
     const double ih2 = 1.0 / (h * h);
-    for (size_t e = threadIdx.x; e < (size_t)n * n; e += kBlock) M[e] = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += kBlock) M[e] = 0.0;
     __syncthreads();
     for (int c = threadIdx.x; c < n; c += kBlock) {
         int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
@@ -390,9 +394,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_setup(int nx, int ny, int nz,
         int km = k > 0 ? k - 1 : nz - 1, kp = k < nz - 1 ? k + 1 : 0;
         double b[6] = {bx[c], bx[cidx(ip, j, k, nx, ny)], by[c], by[cidx(i, jp, k, nx, ny)],
                        bz[c], bz[cidx(i, j, kp, nx, ny)]};
-        size_t nb[6] = {cidx(im, j, k, nx, ny), cidx(ip, j, k, nx, ny), cidx(i, jm, k, nx, ny),
-                        cidx(i, jp, k, nx, ny), cidx(i, j, km, nx, ny), cidx(i, j, kp, nx, ny)};
-        double* row = M + (size_t)c * n;
+        int nb[6] = {(int)cidx(im, j, k, nx, ny), (int)cidx(ip, j, k, nx, ny), (int)cidx(i, jm, k, nx, ny),
+                     (int)cidx(i, jp, k, nx, ny), (int)cidx(i, j, km, nx, ny), (int)cidx(i, j, kp, nx, ny)};
+        double* row = M + c * n;
         for (int q = 0; q < 6; ++q) {
             if (b[q] == 0.0) continue;      // wall face: no coupling
             row[c] += b[q] * ih2;
@@ -402,29 +406,31 @@ __global__ __launch_bounds__(kBlock) void k_coarse_setup(int nx, int ny, int nz,
     __syncthreads();
     if (threadIdx.x == 0) {
         double d = 0.0;
-        for (int c = 0; c < n; ++c) d += M[(size_t)c * n + c];
+        for (int c = 0; c < n; ++c) d += M[c * n + c];
         shift = d / n;
     }
     __syncthreads();
-    for (size_t e = threadIdx.x; e < (size_t)n * n; e += kBlock) M[e] += shift;
+    for (int e = threadIdx.x; e < n * n; e += kBlock) M[e] += shift;
     __syncthreads();
-    // in-place Gauss-Jordan inversion
+    // in-place Gauss-Jordan inversion (M is SPD: no pivoting)
     for (int p = 0; p < n; ++p) {
-        double piv = M[(size_t)p * n + p];
+        const double piv = M[p * n + p];
         __syncthreads();
         for (int jj = threadIdx.x; jj < n; jj += kBlock)
-            M[(size_t)p * n + jj] = (jj == p) ? 1.0 / piv : M[(size_t)p * n + jj] / piv;
-        for (int ii = threadIdx.x; ii < n; ii += kBlock) fac[ii] = (ii == p) ? 0.0 : M[(size_t)ii * n + p];
+            M[p * n + jj] = (jj == p) ? 1.0 / piv : M[p * n + jj] / piv;
+        for (int ii = threadIdx.x; ii < n; ii += kBlock) fac[ii] = (ii == p) ? 0.0 : M[ii * n + p];
         __syncthreads();
         for (int ii = threadIdx.x; ii < n; ii += kBlock)
-            if (ii != p) M[(size_t)ii * n + p] = 0.0;
+            if (ii != p) M[ii * n + p] = 0.0;
         __syncthreads();
-        for (size_t e = threadIdx.x; e < (size_t)n * n; e += kBlock) {
-            int ii = (int)(e / n), jj = (int)(e % n);
-            if (ii != p) M[e] -= fac[ii] * M[(size_t)p * n + jj];
+        for (int e = threadIdx.x; e < n * n; e += kBlock) {
+            const int ii = e / n, jj = e - ii * n;
+            if (ii != p) M[e] -= fac[ii] * M[p * n + jj];
         }
         __syncthreads();
     }
+    if (kLds)
+        for (int e = threadIdx.x; e < n * n; e += kBlock) Mg[e] = Ms[e];
 }
 
 template <typename T>
@@ -673,7 +679,10 @@ hipError_t launch_resid_restrict_rho(const Shape& fine, double h, const RhoArgs&
 
 hipError_t launch_coarse_setup(const Shape& s, double h, const double* bx, const double* by,
                                const double* bz, double* minv, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse_setup, dim3(1), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, h, bx, by, bz, minv);
+    if (s.N() <= 64)
+        hipLaunchKernelGGL(k_coarse_setup<true>, dim3(1), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, h, bx, by, bz, minv);
+    else
+        hipLaunchKernelGGL(k_coarse_setup<false>, dim3(1), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, h, bx, by, bz, minv);
     return hipGetLastError();
 }
 

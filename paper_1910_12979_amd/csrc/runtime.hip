@@ -113,7 +113,10 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
     }
     size_t Nc = (size_t)(p->n[0] >> (nl - 1)) * (p->n[1] >> (nl - 1)) * (p->n[2] >> (nl - 1));
     double* minv = (double*)take(Nc * Nc * 8);
-    double* partials = (double*)take((size_t)2048 * kReduceWidth * 8);
+    size_t rows = 2048;
+    for (int c = 0; c < kNumSweepCfg; ++c)
+        rows = std::max(rows, (size_t)sweep_tiles(p->n[0], p->n[1], p->n[2], c));
+    double* partials = (double*)take(rows * kReduceWidth * 8);
     double* scal = (double*)take(64 * 8);
     double* r64 = nullptr;
     size_t N0 = (size_t)p->n[0] * p->n[1] * p->n[2];
@@ -329,7 +332,26 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
     Shape s = shape_of(F);
     if constexpr (std::is_same<T, double>::value) {
         if (l == 0 && H->rho.rho) {
-            HIPCHK(launch_resid_restrict_rho(s, F.h, H->rho, F.d.phi, F.d.f, C.d.f, C.d.phi, st));
+            if (sweep_fusable<double>(F.nx, F.ny, F.nz)) {
+                SweepArgs<double> a{};
+                a.nx = F.nx;
+                a.ny = F.ny;
+                a.nz = F.nz;
+                a.px = H->px;
+                a.py = H->py;
+                a.pz = H->pz;
+                a.h2 = F.h * F.h;
+                a.phi_in = F.d.phi;
+                a.f = F.d.f;
+                a.rho = H->rho.rho;
+                a.b0c = H->rho.b0c;
+                a.b0e = H->rho.b0e;
+                a.fc = C.d.f;
+                a.phic_out = C.d.phi;
+                HIPCHK(launch_resid_restrict_tiled(a, sweep_config_for(F.nx, F.ny, F.nz), st));
+            } else {
+                HIPCHK(launch_resid_restrict_rho(s, F.h, H->rho, F.d.phi, F.d.f, C.d.f, C.d.phi, st));
+            }
             return MG_OK;
         }
         HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f, C.d.phi, st));
@@ -341,7 +363,7 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
 
 // V-cycle from level l (FP64 or FP32 arrays; the coarsest solve is FP64).
 template <typename T>
-static int vcycle(mg_hierarchy* H, int l, hipStream_t st) {
+static int vcycle(mg_hierarchy* H, int l, hipStream_t st, int pre_done = 0) {
     Level& F = H->lev[l];
     if (l == H->nlev - 1) {
         if constexpr (std::is_same<T, double>::value)
@@ -350,7 +372,7 @@ static int vcycle(mg_hierarchy* H, int l, hipStream_t st) {
             HIPCHK(launch_coarse_solve_f32((int)F.N, H->minv, F.s.f, F.s.phi, st));
         return MG_OK;
     }
-    int rc = smooth<T>(H, l, H->p.pre_sweeps, l == 0 ? kInPlain : kInZero, st);
+    int rc = smooth<T>(H, l, H->p.pre_sweeps - pre_done, (l == 0 || pre_done > 0) ? kInPlain : kInZero, st);
     if (rc) return rc;
     rc = resid_restrict<T>(H, l, st);
     if (rc) return rc;
@@ -388,6 +410,42 @@ double model_bytes(const mg_params& p, int cycles, int mixed) {
 }
 
 // Solve on level 0 after f (mean-removed) and the coefficients are in place.
+// Residual norm of the current finest-level phi measured by a speculative
+// first pre-sweep: the sweep reads phi, f and rho anyway, so it also writes
+// per-tile partial sums of r = f - L phi(input).  The sweep is out of place;
+// its output is taken (buffers swapped) only if another cycle follows.
+static int speculative_sweep_norm(mg_hierarchy* H, bool* taken_out, double fnorm, double* rel,
+                                  double* nonfinite, hipStream_t st) {
+    Level& L0 = H->lev[0];
+    SweepArgs<double> a{};
+    a.nx = L0.nx;
+    a.ny = L0.ny;
+    a.nz = L0.nz;
+    a.px = H->px;
+    a.py = H->py;
+    a.pz = H->pz;
+    a.h2 = L0.h * L0.h;
+    a.phi_in = L0.d.phi;
+    a.phi_out = L0.phi2_d;
+    a.f = L0.d.f;
+    a.rho = H->rho.rho;
+    a.b0c = H->rho.b0c;
+    a.b0e = H->rho.b0e;
+    a.partials = H->partials;
+    int np = 0;
+    HIPCHK(launch_sweep_norm(a, sweep_config_for(L0.nx, L0.ny, L0.nz), &np, st));
+    int rc = reduce_to(H, np, kSlotRes, st);
+    if (rc) return rc;
+    rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
+    if (rc) return rc;
+    const double* r = H->host + kSlotRes * kReduceWidth;
+    *rel = std::sqrt(r[0]) / fnorm;
+    *nonfinite = r[3];
+    *taken_out = false;
+    return MG_OK;
+}
+
+// Solve on level 0 after f (mean-removed) and the coefficients are in place.
 static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStream_t st) {
     Level& L0 = H->lev[0];
     HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
@@ -398,42 +456,77 @@ static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStrea
         stats->resid_hist[0] = 1.0;
         stats->hist_len = 1;
     }
-    const bool mixed = H->p.precision == MG_MIXED;
-    if (H->p.rtol >= 1.0) status = MG_OK;
-    if (mixed) {
-        // phi = 0, so the FP64 residual is f itself
-        int rc = level0_residual(H, H->r64, st);
-        if (rc) return rc;
-    }
-    while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
-        if (!mixed) {
-            int rc = vcycle64(H, 0, st);
-            if (rc) return rc;
-        } else {
-            // correction from an FP32 cycle on the scaled FP64 residual r64
-            double rmax = H->host[kSlotRes * kReduceWidth + 2];
-            if (!(rmax > 0.0)) break;
-            HIPCHK(launch_to_f32(H->r64, L0.s.f, L0.N, H->scal + kSlotRes * kReduceWidth + 2, st));
-            HIPCHK(launch_fill<float>(L0.s.phi, L0.N, 0.0f, st));
-            int rc = vcycle32(H, 0, st);
-            if (rc) return rc;
-            HIPCHK(launch_accumulate(L0.d.phi, L0.s.phi, L0.N, H->scal + kSlotRes * kReduceWidth + 2, st));
-        }
-        ++cycles;
-        int rc = level0_residual(H, mixed ? H->r64 : nullptr, st);
-        if (rc) return rc;
-        const double* r = H->host + kSlotRes * kReduceWidth;
-        rel = std::sqrt(r[0]) / fnorm;
+    auto record = [&](double r) {
         if (stats && cycles < MG_HIST_MAX) {
-            stats->resid_hist[cycles] = rel;
+            stats->resid_hist[cycles] = r;
             stats->hist_len = cycles + 1;
         }
-        if (r[3] > 0.0 || !std::isfinite(rel)) {
-            status = MG_ERR_NONFINITE;
-            set_error("non-finite residual during the solve");
-            break;
+    };
+    const bool mixed = H->p.precision == MG_MIXED;
+    if (H->p.rtol >= 1.0) status = MG_OK;
+    const bool fused_norm = !mixed && H->rho.rho && H->p.pre_sweeps >= 1 && H->nlev > 1 &&
+                            sweep_fusable<double>(L0.nx, L0.ny, L0.nz);
+    if (fused_norm) {
+        while (status == MG_ERR_NOT_CONVERGED) {
+            int pre_done = 0;
+            if (cycles > 0) {
+                bool taken = false;
+                double nonfin = 0.0;
+                int rc = speculative_sweep_norm(H, &taken, fnorm, &rel, &nonfin, st);
+                if (rc) return rc;
+                record(rel);
+                if (nonfin > 0.0 || !std::isfinite(rel)) {
+                    status = MG_ERR_NONFINITE;
+                    set_error("non-finite residual during the solve");
+                    break;
+                }
+                if (rel <= H->p.rtol) {
+                    status = MG_OK;
+                    break;
+                }
+                if (cycles >= H->p.max_cycles) break;
+                std::swap(L0.d.phi, L0.phi2_d);     // keep the sweep: it is the next cycle's first
+                pre_done = 1;
+            } else if (H->p.max_cycles == 0) {
+                break;
+            }
+            int rc = vcycle<double>(H, 0, st, pre_done);
+            if (rc) return rc;
+            ++cycles;
         }
-        if (rel <= H->p.rtol) status = MG_OK;
+    } else {
+        if (mixed) {
+            // phi = 0, so the FP64 residual is f itself
+            int rc = level0_residual(H, H->r64, st);
+            if (rc) return rc;
+        }
+        while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
+            if (!mixed) {
+                int rc = vcycle64(H, 0, st);
+                if (rc) return rc;
+            } else {
+                // correction from an FP32 cycle on the scaled FP64 residual r64
+                double rmax = H->host[kSlotRes * kReduceWidth + 2];
+                if (!(rmax > 0.0)) break;
+                HIPCHK(launch_to_f32(H->r64, L0.s.f, L0.N, H->scal + kSlotRes * kReduceWidth + 2, st));
+                HIPCHK(launch_fill<float>(L0.s.phi, L0.N, 0.0f, st));
+                int rc = vcycle32(H, 0, st);
+                if (rc) return rc;
+                HIPCHK(launch_accumulate(L0.d.phi, L0.s.phi, L0.N, H->scal + kSlotRes * kReduceWidth + 2, st));
+            }
+            ++cycles;
+            int rc = level0_residual(H, mixed ? H->r64 : nullptr, st);
+            if (rc) return rc;
+            const double* r = H->host + kSlotRes * kReduceWidth;
+            rel = std::sqrt(r[0]) / fnorm;
+            record(rel);
+            if (r[3] > 0.0 || !std::isfinite(rel)) {
+                status = MG_ERR_NONFINITE;
+                set_error("non-finite residual during the solve");
+                break;
+            }
+            if (rel <= H->p.rtol) status = MG_OK;
+        }
     }
     if (stats) {
         stats->cycles = cycles;

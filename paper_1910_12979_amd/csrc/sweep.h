@@ -21,6 +21,7 @@ constexpr SweepCfg kSweepCfgs[kNumSweepCfg] = {
     {32, 8, 32}, {32, 8, 64}, {64, 8, 32}, {32, 16, 32}, {64, 4, 64}, {32, 4, 64}};
 
 enum { kInZero = 0, kInPlain = 1, kInProlong = 2 };
+enum { kOpSweep = 0, kOpSweepNorm = 1, kOpResidRestrict = 2 };
 
 template <typename T>
 struct SweepArgs {
@@ -39,6 +40,9 @@ struct SweepArgs {
     const double* rho;         // finest level: coefficients from rho and beta0
     const double* b0c;
     const double* b0e;
+    double* partials;          // residual-norm rows (kOpSweepNorm), one per tile
+    T* fc;                     // coarse right-hand side (kOpResidRestrict)
+    T* phic_out;               // coarse phi, zeroed (kOpResidRestrict)
 };
 
 template <typename T>
@@ -46,6 +50,29 @@ bool sweep_fusable(int nx, int ny, int nz);
 
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cfg, hipStream_t st);
+
+// Finest-level sweep of phi_in (as stored, coefficients from rho) that also
+// writes, per tile, the partial row {sum r^2, 0, max |r|, #non-finite} of
+// the residual r = f - L phi_in of its INPUT.  *nparts = rows written.
+hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st);
+
+// Finest level (coefficients from rho): f_c = R (f - L phi), phi_c = 0, using
+// the sweep's tiles (each face coefficient computed once per cell).  Needs
+// even tile origins, which every configuration has.
+hipError_t launch_resid_restrict_tiled(const SweepArgs<double>& a, int cfg, hipStream_t st);
+
+// Batched form (one launch, many problems): descriptor i (device) is problem
+// i's SweepArgs with tz/ntx/nty filled (sweep_geometry), prefix (device,
+// nprob+1 entries) its first tile; `op` is kOpSweep, kOpSweepNorm (rho only,
+// plain input) or kOpResidRestrict.  Only configuration 0 (32x8x32).
+template <typename T>
+hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
+                              int in_mode, int op, int cfg, hipStream_t st);
+void sweep_geometry(SweepArgs<double>& a, int cfg);
+void sweep_geometry(SweepArgs<float>& a, int cfg);
+
+// Number of tiles (= partial rows) a sweep of this shape launches with cfg.
+int sweep_tiles(int nx, int ny, int nz, int cfg);
 
 // Configuration used for a level of shape nx x ny x nz (autotuned choice or default).
 int sweep_config_for(int nx, int ny, int nz);

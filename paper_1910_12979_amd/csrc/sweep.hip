@@ -81,8 +81,12 @@ __device__ inline int xcd_tile(int b, int total) {
     return (b % kNumXcd) * (total / kNumXcd) + b / kNumXcd;
 }
 
-template <typename T, int TX, int TY, bool kRho, int kIn>
-__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> a) {
+// The body of one tile: shared by the single-problem kernel and the batched
+// kernel, so a problem's values do not depend on how it was launched.
+template <typename T, int TX, int TY, bool kRho, int kIn, int kOp>
+__device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile) {
+    constexpr bool kNorm = kOp == kOpSweepNorm;    // sweep + residual norm of its input
+    constexpr bool kRR = kOp == kOpResidRestrict;  // residual + restriction only (no sweep)
     constexpr int WX = TX + 4, WY = TY + 4, WP = WX / 2;   // ring-2 window, pairs per row
     constexpr int NB = kSweepTZMax + 6;                    // beta0 planes staged per chunk
     __shared__ T sphi[WY][WX];                // phi_in, current plane
@@ -93,7 +97,6 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> 
     __shared__ double sb0c[kRho ? NB : 1], sb0e[kRho ? NB : 1];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % a.ntx;
     const int ty = (tile / a.ntx) % a.nty;
     const int tz = tile / (a.ntx * a.nty);
@@ -236,6 +239,31 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> 
     }
 
     T Rmm = T(0), Rm = T(0);
+    // residual of phi_in (kNorm): r = f - (sum_f b (phi_nb - phi_c)) / h^2 in
+    // the reference face order, for both cells of a tile pair at plane t
+    double nrm2 = 0.0, nmax = 0.0, nbad = 0.0;
+    auto resid_at = [&](int c, int s_t, T pm, T pc, T pp, T bzl, T bzh, T fc) -> T {
+        const int lx = lx0 + c;
+        T r = sbx[s_t][ly][lx] * (sphi[ly][lx - 1] - pc);
+        r = r + sbx[s_t][ly][lx + 1] * (sphi[ly][lx + 1] - pc);
+        r = r + sby[s_t][ly][lx] * (sphi[ly - 1][lx] - pc);
+        r = r + sby[s_t][ly + 1][lx] * (sphi[ly + 1][lx] - pc);
+        r = r + bzl * (pm - pc);
+        r = r + bzh * (pp - pc);
+        return fc - r / h2;
+    };
+    auto resid_in = [&](int c, int s_t, T pm, T pc, T pp, T bzl, T bzh, T fc) {
+        const double res = (double)resid_at(c, s_t, pm, pc, pp, bzl, bzh, fc);
+        if (!isfinite(res)) nbad += 1.0;
+        nrm2 += res * res;
+        nmax = fmax(nmax, fabs(res));
+    };
+    // restriction (kRR): the even-row thread of each 2x2 column block sums the
+    // 8 children in the reference order (x fastest, then y, then z)
+    T racc = T(0);
+    const bool rrow = (ly & 1) == 0;           // gy = y0 - 2 + ly is even
+    const size_t ccols = (size_t)(nx >> 1) * (ny >> 1);
+    const size_t cc = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
     auto step = [&](int t, Fly& X) {
         // 0. slide the z window, taking in the set issued two steps ago:
         //    phi[t+1], rho[t+1] (or bz[t+1]), f[t], bx/by[t+1]; then re-issue
@@ -279,7 +307,7 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> 
         // 3. red update at plane t on the tile plus one ring
         const int lxr = lx0 + rsel;
         T Rcur = rsel ? Pc1 : Pc0;
-        if (rsel ? r1c1 : r1c0) {
+        if (!kRR && (rsel ? r1c1 : r1c0)) {
             const T bxl = sbx[s_t][ly][lxr], bxh = sbx[s_t][ly][lxr + 1];
             const T byl = sby[s_t][ly][lxr], byh = sby[s_t][ly + 1][lxr];
             const T bzl = rsel ? bc1 : bc0, bzh = rsel ? bp1 : bp0;
@@ -296,8 +324,31 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> 
             den = den + bzh;
             Rcur = (num - h2 * (rsel ? Fc1 : Fc0)) / den;
         }
-        sR[(t + 4) & 1][ly][lxr] = Rcur;
+        if (!kRR) sR[(t + 4) & 1][ly][lxr] = Rcur;
+        if (kNorm && t >= z0 && t < z1 && writes) {
+            resid_in(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
+            resid_in(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
+        }
+        if (kRR && t >= z0 && t < z1 && writes) {
+            sR[0][ly][lx0] = resid_at(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
+            sR[0][ly][lx0 + 1] = resid_at(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
+        }
         __syncthreads();
+        if (kRR) {
+            if (t >= z0 && t < z1 && writes && rrow) {
+                if (((t - z0) & 1) == 0) racc = T(0);
+                racc = racc + sR[0][ly][lx0];
+                racc = racc + sR[0][ly][lx0 + 1];
+                racc = racc + sR[0][ly + 1][lx0];
+                racc = racc + sR[0][ly + 1][lx0 + 1];
+                if (((t - z0) & 1) == 1) {
+                    const size_t ci = (size_t)(t >> 1) * ccols + cc;
+                    a.fc[ci] = T(0.125) * racc;
+                    a.phic_out[ci] = T(0);
+                }
+            }
+            return;
+        }
         // 4. black update at plane t-1 on the tile; write the pair of plane t-1
         const int tb = t - 1;
         if (tb >= z0 && writes) {
@@ -331,17 +382,81 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> 
         step(t + 1, B);
     }
     if (t <= z1) step(t, A);
+    if (kNorm) {
+        // fixed-order block reduction into this tile's partial row
+        __shared__ double red[3][256];
+        const int nt = blockDim.x;
+        for (int i = threadIdx.x; i < 256; i += nt) {     // every slot, also when nt < 256
+            red[0][i] = 0.0;
+            red[1][i] = 0.0;
+            red[2][i] = 0.0;
+        }
+        __syncthreads();
+        for (int k = 0; k < nt; k += 256) {
+            if (threadIdx.x >= k && threadIdx.x < k + 256) {
+                const int i = threadIdx.x - k;
+                red[0][i] += nrm2;
+                red[1][i] = fmax(red[1][i], nmax);
+                red[2][i] += nbad;
+            }
+            __syncthreads();
+        }
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + w];
+                red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+                red[2][threadIdx.x] += red[2][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double* row = a.partials + (size_t)tile * kReduceWidth;
+            row[0] = red[0][0];
+            row[1] = 0.0;
+            row[2] = red[1][0];
+            row[3] = red[2][0];
+        }
+    }
 }
 
-template <typename T, int TX, int TY, bool kRho, int kIn>
-hipError_t launch_t(const SweepArgs<T>& a0, int tzc, hipStream_t st) {
+template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
+__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> a) {
+    sweep_body<T, TX, TY, kRho, kIn, kOp>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Batched form: problem p owns tiles [prefix[p], prefix[p+1]) of the launch.
+template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
+__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep_multi(const SweepArgs<T>* __restrict__ descs,
+                                                                         const int* __restrict__ prefix, int nprob) {
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    int lo = 0, hi = nprob;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    const SweepArgs<T> a = descs[lo];
+    sweep_body<T, TX, TY, kRho, kIn, kOp>(a, b - prefix[lo]);
+}
+
+template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
+hipError_t launch_multi_t(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep_multi<T, TX, TY, kRho, kIn, kOp>), dim3(tiles), dim3((TX / 2 + 2) * (TY + 4)), 0,
+                       st, d, prefix, nprob);
+    return hipGetLastError();
+}
+
+template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
+hipError_t launch_t(const SweepArgs<T>& a0, int tzc, hipStream_t st, int* nblocks = nullptr) {
     SweepArgs<T> a = a0;
     a.tz = tzc;
     a.ntx = (a.nx + TX - 1) / TX;
     a.nty = (a.ny + TY - 1) / TY;
     int ntz = (a.nz + tzc - 1) / tzc;
     int blocks = a.ntx * a.nty * ntz;
-    hipLaunchKernelGGL((k_sweep<T, TX, TY, kRho, kIn>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0, st, a);
+    if (nblocks) *nblocks = blocks;
+    hipLaunchKernelGGL((k_sweep<T, TX, TY, kRho, kIn, kOp>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0,
+                       st, a);
     return hipGetLastError();
 }
 
@@ -399,9 +514,85 @@ hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cf
     }
 }
 
+hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
+    constexpr int N = kOpSweepNorm;
+    switch (cfg) {
+        case 0: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 1: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 2: return launch_t<double, 64, 8, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 3: return launch_t<double, 32, 16, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 4: return launch_t<double, 64, 4, true, kInPlain, N>(a, c.tz, st, nparts);
+        default: return launch_t<double, 32, 4, true, kInPlain, N>(a, c.tz, st, nparts);
+    }
+}
+
+hipError_t launch_resid_restrict_tiled(const SweepArgs<double>& a, int cfg, hipStream_t st) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
+    constexpr int R = kOpResidRestrict;
+    switch (cfg) {
+        case 0: return launch_t<double, 32, 8, true, kInPlain, R>(a, c.tz, st);
+        case 1: return launch_t<double, 32, 8, true, kInPlain, R>(a, c.tz, st);
+        case 2: return launch_t<double, 64, 8, true, kInPlain, R>(a, c.tz, st);
+        case 3: return launch_t<double, 32, 16, true, kInPlain, R>(a, c.tz, st);
+        case 4: return launch_t<double, 64, 4, true, kInPlain, R>(a, c.tz, st);
+        default: return launch_t<double, 32, 4, true, kInPlain, R>(a, c.tz, st);
+    }
+}
+
+template <typename T>
+hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
+                              int in_mode, int op, int cfg, hipStream_t st) {
+    if (tiles <= 0) return hipSuccess;
+    if (cfg != 0) return hipErrorInvalidValue;      // batches use the 32x8 tile shape
+    if (use_rho) {
+        if constexpr (std::is_same<T, double>::value) {
+            if (op == kOpSweepNorm) return launch_multi_t<T, 32, 8, true, kInPlain, kOpSweepNorm>(d, prefix, nprob, tiles, st);
+            if (op == kOpResidRestrict)
+                return launch_multi_t<T, 32, 8, true, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
+            switch (in_mode) {
+                case kInZero: return launch_multi_t<T, 32, 8, true, kInZero>(d, prefix, nprob, tiles, st);
+                case kInPlain: return launch_multi_t<T, 32, 8, true, kInPlain>(d, prefix, nprob, tiles, st);
+                default: return launch_multi_t<T, 32, 8, true, kInProlong>(d, prefix, nprob, tiles, st);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+    if (op == kOpResidRestrict) return launch_multi_t<T, 32, 8, false, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
+    switch (in_mode) {
+        case kInZero: return launch_multi_t<T, 32, 8, false, kInZero>(d, prefix, nprob, tiles, st);
+        case kInPlain: return launch_multi_t<T, 32, 8, false, kInPlain>(d, prefix, nprob, tiles, st);
+        default: return launch_multi_t<T, 32, 8, false, kInProlong>(d, prefix, nprob, tiles, st);
+    }
+}
+
+void sweep_geometry(SweepArgs<double>& a, int cfg) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    a.tz = c.tz;
+    a.ntx = (a.nx + c.tx - 1) / c.tx;
+    a.nty = (a.ny + c.ty - 1) / c.ty;
+}
+void sweep_geometry(SweepArgs<float>& a, int cfg) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    a.tz = c.tz;
+    a.ntx = (a.nx + c.tx - 1) / c.tx;
+    a.nty = (a.ny + c.ty - 1) / c.ty;
+}
+
+int sweep_tiles(int nx, int ny, int nz, int cfg) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    return ((nx + c.tx - 1) / c.tx) * ((ny + c.ty - 1) / c.ty) * ((nz + c.tz - 1) / c.tz);
+}
+
 template bool sweep_fusable<double>(int, int, int);
 template bool sweep_fusable<float>(int, int, int);
 template hipError_t launch_sweep<double>(const SweepArgs<double>&, bool, int, int, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs<float>&, bool, int, int, hipStream_t);
+template hipError_t launch_sweep_multi<double>(const SweepArgs<double>*, const int*, int, int, bool, int, int, int,
+                                               hipStream_t);
+template hipError_t launch_sweep_multi<float>(const SweepArgs<float>*, const int*, int, int, bool, int, int, int,
+                                              hipStream_t);
 
 }  // namespace mg
