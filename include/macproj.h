@@ -207,11 +207,19 @@ int serve_counters(void* server, double out[6]);
 /* Finish all tickets and release the server. */
 int serve_destroy(void* server);
 
-/* Tuning: force fused-sweep tile configuration cfg (0..5: 32x8x32, 32x8x64,
- * 64x8x32, 32x16x32, 64x4x64, 32x4x64 cells per workgroup tile x planes per
- * chunk) on every level that fits it; -1 restores the per-shape default.
+/* Tuning: force fused-sweep tile configuration cfg (0..7: 32x8x32, 32x8x64,
+ * 64x8x32, 32x16x32, 64x4x64, 32x4x64, 32x8x16, 32x8x8 cells per workgroup
+ * tile x planes per chunk) on every level that fits it; -1 restores the
+ * per-shape default.
  * Process-wide; results do not depend on it (the sweep is exact per cell). */
 int mg_tune_sweep(int32_t cfg);
+
+/* Autotune: time every fused-sweep configuration that fits each level of h
+ * (`reps` sweeps each, on `stream`) and keep the fastest per level shape in a
+ * process-wide table used by every later solve of that shape.  Needs
+ * coefficients (mg_set_coefficients or mac_project); overwrites the
+ * hierarchy's own level arrays, never caller data.  Blocks until done. */
+int mg_autotune(mg_handle h, int32_t reps, void* stream);
 
 const char* mg_strerror(int code);
 const char* mg_last_error(void);

@@ -16,6 +16,7 @@
 
 #include <cmath>
 
+#include "devmath.h"
 #include "mg_internal.h"
 
 namespace mg {
@@ -108,17 +109,17 @@ __global__ __launch_bounds__(kBlock) void k_coeff_rhs(
         if (!(rc > 0.0) || !(bk > 0.0) || !(bek > 0.0)) bad = 1.0;
         // x-low face i
         double cx;
-        if (i > 0) cx = bk / (0.5 * (rho[c - 1] + rc));
-        else cx = px ? bk / (0.5 * (rho[c + (nx - 1)] + rc)) : 0.0;
+        if (i > 0) cx = qdiv(bk, 0.5 * (rho[c - 1] + rc));
+        else cx = px ? qdiv(bk, 0.5 * (rho[c + (nx - 1)] + rc)) : 0.0;
         // y-low face j
         double cy;
-        if (j > 0) cy = bk / (0.5 * (rho[c - nx] + rc));
-        else cy = py ? bk / (0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc)) : 0.0;
+        if (j > 0) cy = qdiv(bk, 0.5 * (rho[c - nx] + rc));
+        else cy = py ? qdiv(bk, 0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc)) : 0.0;
         // z-low face k (periodic: face 0 uses beta0_edge[0])
         double cz;
         size_t plane = (size_t)nx * ny;
-        if (k > 0) cz = bek / (0.5 * (rho[c - plane] + rc));
-        else cz = pz ? b0e[0] / (0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc)) : 0.0;
+        if (k > 0) cz = qdiv(bek, 0.5 * (rho[c - plane] + rc));
+        else cz = pz ? qdiv(b0e[0], 0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc)) : 0.0;
         bx[c] = cx;
         by[c] = cy;
         bz[c] = cz;
@@ -243,7 +244,7 @@ __global__ void k_rbgs_colour(int nx, int ny, int nz, T h2, T* __restrict__ phi,
     den = den + byh;
     den = den + bzl;
     den = den + bzh;
-    phi[c] = (num - h2 * f[c]) / den;
+    phi[c] = qdiv(num - h2 * f[c], den);
 }
 
 // Face coefficients of a cell: stored per-cell low-face arrays (any level).
@@ -275,15 +276,15 @@ struct RhoCoeff {
         const size_t plane = (size_t)nx * ny;
         const double rc = rho[c];
         if (d == 0) {
-            if (i > 0) return b0c[k] / (0.5 * (rho[c - 1] + rc));
-            return px ? b0c[k] / (0.5 * (rho[c + (nx - 1)] + rc)) : 0.0;
+            if (i > 0) return qdiv(b0c[k], 0.5 * (rho[c - 1] + rc));
+            return px ? qdiv(b0c[k], 0.5 * (rho[c + (nx - 1)] + rc)) : 0.0;
         }
         if (d == 1) {
-            if (j > 0) return b0c[k] / (0.5 * (rho[c - nx] + rc));
-            return py ? b0c[k] / (0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc)) : 0.0;
+            if (j > 0) return qdiv(b0c[k], 0.5 * (rho[c - nx] + rc));
+            return py ? qdiv(b0c[k], 0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc)) : 0.0;
         }
-        if (k > 0) return b0e[k] / (0.5 * (rho[c - plane] + rc));
-        return pz ? b0e[0] / (0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc)) : 0.0;
+        if (k > 0) return qdiv(b0e[k], 0.5 * (rho[c - plane] + rc));
+        return pz ? qdiv(b0e[0], 0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc)) : 0.0;
     }
     __device__ inline void get(size_t c, size_t cxp, size_t cyp, size_t czp, int i, int j, int k, int ip,
                                int jp, int kp, double b[6]) const {
@@ -314,7 +315,7 @@ __device__ inline T apply_cell(int i, int j, int k, int nx, int ny, int nz, T h2
     s = s + b[3] * (phi[cyp] - pc);
     s = s + b[4] * (phi[cidx(i, j, km, nx, ny)] - pc);
     s = s + b[5] * (phi[czp] - pc);
-    return s / h2;
+    return s * (T(1) / h2);
 }
 
 template <typename T, typename Coef>
@@ -748,5 +749,176 @@ hipError_t launch_coeff_to_f32(const double* a, float* b, size_t n, hipStream_t 
 MG_INST(double)
 MG_INST(float)
 #undef MG_INST
+
+}  // namespace mg
+
+// ============================================================================
+// Batched (multi-problem) forms of the small-level kernels.  Problem p owns
+// blocks [d[p].block0, d[p+1].block0) of a launch; each thread evaluates the
+// same per-cell expression as the single-problem kernel, so a problem's
+// values do not depend on what it was launched with.
+// ============================================================================
+namespace mg {
+namespace {
+
+__device__ inline int find_problem(const CellDesc* __restrict__ d, int nprob, int b) {
+    int lo = 0, hi = nprob;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (d[mid].block0 <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// one colour of a red-black sweep; threads cover (nx/2) x ny x nz
+__global__ __launch_bounds__(256) void k_rbgs_colour_multi(const CellDesc* __restrict__ d, int nprob, int colour) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const CellDesc c = d[p];
+    const long long t = (long long)(blockIdx.x - c.block0) * 256 + threadIdx.x;
+    const int hx = c.nx / 2;
+    if (t >= (long long)hx * c.ny * c.nz) return;
+    const int ih = (int)(t % hx);
+    const int j = (int)((t / hx) % c.ny);
+    const int k = (int)(t / ((long long)hx * c.ny));
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int i = 2 * ih + ((j + k + colour) & 1);
+    if (i >= nx) return;
+    int im = i > 0 ? i - 1 : nx - 1, ip = i < nx - 1 ? i + 1 : 0;
+    int jm = j > 0 ? j - 1 : ny - 1, jp = j < ny - 1 ? j + 1 : 0;
+    int km = k > 0 ? k - 1 : nz - 1, kp = k < nz - 1 ? k + 1 : 0;
+    double* phi = c.phi;
+    const size_t cc = cidx(i, j, k, nx, ny);
+    const double bxl = c.bx[cc], bxh = c.bx[cidx(ip, j, k, nx, ny)];
+    const double byl = c.by[cc], byh = c.by[cidx(i, jp, k, nx, ny)];
+    const double bzl = c.bz[cc], bzh = c.bz[cidx(i, j, kp, nx, ny)];
+    double num = bxl * phi[cidx(im, j, k, nx, ny)];
+    num = num + bxh * phi[cidx(ip, j, k, nx, ny)];
+    num = num + byl * phi[cidx(i, jm, k, nx, ny)];
+    num = num + byh * phi[cidx(i, jp, k, nx, ny)];
+    num = num + bzl * phi[cidx(i, j, km, nx, ny)];
+    num = num + bzh * phi[cidx(i, j, kp, nx, ny)];
+    double den = bxl + bxh;
+    den = den + byl;
+    den = den + byh;
+    den = den + bzl;
+    den = den + bzh;
+    phi[cc] = qdiv(num - c.h2 * c.f[cc], den);
+}
+
+// f_c = R (f - L phi), phi_c = 0 with stored coefficients; threads cover coarse cells
+__global__ __launch_bounds__(256) void k_resid_restrict_multi(const CellDesc* __restrict__ d, int nprob) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const CellDesc c = d[p];
+    const int cx = c.nx / 2, cy = c.ny / 2, cz = c.nz / 2;
+    const long long t = (long long)(blockIdx.x - c.block0) * 256 + threadIdx.x;
+    if (t >= (long long)cx * cy * cz) return;
+    const int I = (int)(t % cx), J = (int)((t / cx) % cy), K = (int)(t / ((long long)cx * cy));
+    StoredCoeff<double> coef{c.bx, c.by, c.bz};
+    double s = 0.0;
+    for (int dk = 0; dk < 2; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                const double r = c.f[cidx(i, j, k, c.nx, c.ny)] -
+                                 apply_cell<double>(i, j, k, c.nx, c.ny, c.nz, c.h2, c.phi, coef);
+                s = s + r;
+            }
+    const size_t C = cidx(I, J, K, cx, cy);
+    c.fc[C] = 0.125 * s;
+    c.phic[C] = 0.0;
+}
+
+// phi += P phic; threads cover fine cells
+__global__ __launch_bounds__(256) void k_prolong_multi(const CellDesc* __restrict__ d, int nprob) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const CellDesc c = d[p];
+    const long long t = (long long)(blockIdx.x - c.block0) * 256 + threadIdx.x;
+    if (t >= (long long)c.nx * c.ny * c.nz) return;
+    const int i = (int)(t % c.nx), j = (int)((t / c.nx) % c.ny), k = (int)(t / ((long long)c.nx * c.ny));
+    const size_t cc = cidx(i, j, k, c.nx, c.ny);
+    c.phi[cc] = c.phi[cc] + c.phic[cidx(i / 2, j / 2, k / 2, c.nx / 2, c.ny / 2)];
+}
+
+// one block per problem: coarsest solve, same code as the single-problem kernel
+__global__ __launch_bounds__(kBlock) void k_coarse_solve_multi(const CellDesc* __restrict__ d) {
+    const CellDesc c = d[blockIdx.x];
+    __shared__ double rhs[kCoarseMax];
+    __shared__ double x[kCoarseMax];
+    __shared__ double mean;
+    const int n = c.nx * c.ny * c.nz;
+    for (int q = threadIdx.x; q < n; q += kBlock) rhs[q] = c.f[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < n; ++q) s += rhs[q];
+        mean = s / n;
+    }
+    __syncthreads();
+    const double m = mean;
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += kBlock) rhs[q] = -(rhs[q] - m);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += kBlock) {
+        const double* row = c.minv + (size_t)r * n;
+        double s = 0.0;
+        for (int q = 0; q < n; ++q) s += row[q] * rhs[q];
+        x[r] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < n; ++q) s += x[q];
+        mean = s / n;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += kBlock) c.phi[q] = x[q] - mean;
+}
+
+// one block per problem: the single-problem k_reduce on each problem's rows
+__global__ __launch_bounds__(kBlock) void k_reduce_multi(const ReduceDesc* __restrict__ d) {
+    const ReduceDesc r = d[blockIdx.x];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int q = threadIdx.x; q < r.nparts; q += kBlock) {
+        const double* p = r.partials + (size_t)q * kReduceWidth;
+        a0 += p[0];
+        a1 += p[1];
+        a2 = fmax(a2, p[2]);
+        a3 += p[3];
+    }
+    block_reduce_row(a0, a1, a2, a3, r.out);
+}
+
+}  // namespace
+
+hipError_t launch_rbgs_multi(const CellDesc* d, int nprob, int blocks, int colour, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rbgs_colour_multi, dim3(blocks), dim3(256), 0, st, d, nprob, colour);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_restrict_multi(const CellDesc* d, int nprob, int blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid_restrict_multi, dim3(blocks), dim3(256), 0, st, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_multi(const CellDesc* d, int nprob, int blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong_multi, dim3(blocks), dim3(256), 0, st, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve_multi(const CellDesc* d, int nprob, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_solve_multi, dim3(nprob), dim3(kBlock), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_multi(const ReduceDesc* d, int nprob, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_multi, dim3(nprob), dim3(kBlock), 0, st, d);
+    return hipGetLastError();
+}
 
 }  // namespace mg

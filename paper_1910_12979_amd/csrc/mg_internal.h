@@ -139,4 +139,31 @@ hipError_t launch_coarse_solve_f32(int N, const double* minv, const float* f, fl
 
 int num_blocks_for_partials(const Shape& s);
 
+// ---- batched forms (one launch, many problems) ------------------------------
+// One problem at one level for the batched small-level kernels; block0 is the
+// problem's first block in the launch (ascending over the table).
+struct CellDesc {
+    int nx, ny, nz;
+    int block0;
+    double h2;
+    double* phi;
+    const double* f;
+    const double* bx;
+    const double* by;
+    const double* bz;
+    double* fc;              // restriction: coarse f
+    double* phic;            // restriction: coarse phi (zeroed) / prolongation source
+    const double* minv;      // coarsest solve
+};
+struct ReduceDesc {
+    const double* partials;
+    int nparts;
+    double* out;             // 4 doubles
+};
+hipError_t launch_rbgs_multi(const CellDesc* d, int nprob, int blocks, int colour, hipStream_t st);
+hipError_t launch_resid_restrict_multi(const CellDesc* d, int nprob, int blocks, hipStream_t st);
+hipError_t launch_prolong_multi(const CellDesc* d, int nprob, int blocks, hipStream_t st);
+hipError_t launch_coarse_solve_multi(const CellDesc* d, int nprob, hipStream_t st);
+hipError_t launch_reduce_multi(const ReduceDesc* d, int nprob, hipStream_t st);
+
 }  // namespace mg

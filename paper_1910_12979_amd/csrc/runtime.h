@@ -49,4 +49,6 @@ int destroy(mg_hierarchy* H);
 int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
             double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st);
 double model_bytes(const mg_params& p, int cycles, int mixed);
+int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
+                       const double* S, const double* u, const double* v, const double* w, hipStream_t st);
 }  // namespace mg

@@ -318,7 +318,7 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
         a.rho = H->rho.rho;
         a.b0c = H->rho.b0c;
         a.b0e = H->rho.b0e;
-        HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain, sweep_config_for(F.nx, F.ny, F.nz), st));
+        HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain, sweep_config_for(F.nx, F.ny, F.nz, use_rho), st));
         std::swap(A->phi, *alt);
     }
     return MG_OK;
@@ -348,7 +348,7 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
                 a.b0e = H->rho.b0e;
                 a.fc = C.d.f;
                 a.phic_out = C.d.phi;
-                HIPCHK(launch_resid_restrict_tiled(a, sweep_config_for(F.nx, F.ny, F.nz), st));
+                HIPCHK(launch_resid_restrict_tiled(a, sweep_config_for(F.nx, F.ny, F.nz, true), st));
             } else {
                 HIPCHK(launch_resid_restrict_rho(s, F.h, H->rho, F.d.phi, F.d.f, C.d.f, C.d.phi, st));
             }
@@ -433,7 +433,7 @@ static int speculative_sweep_norm(mg_hierarchy* H, bool* taken_out, double fnorm
     a.b0e = H->rho.b0e;
     a.partials = H->partials;
     int np = 0;
-    HIPCHK(launch_sweep_norm(a, sweep_config_for(L0.nx, L0.ny, L0.nz), &np, st));
+    HIPCHK(launch_sweep_norm(a, sweep_config_for(L0.nx, L0.ny, L0.nz, true), &np, st));
     int rc = reduce_to(H, np, kSlotRes, st);
     if (rc) return rc;
     rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
@@ -743,6 +743,11 @@ int level_step(mg_hierarchy* H, int l, int step, int arg, hipStream_t st) {
 // ============================================================================
 using namespace mg;
 
+namespace {
+int g_forced_cfg_mirror = -1;     // the value last set through mg_tune_sweep
+int g_forced_for_tuner() { return g_forced_cfg_mirror; }
+}  // namespace
+
 extern "C" {
 
 void mg_default_params(mg_params* p, int32_t nx, int32_t ny, int32_t nz, double dx) {
@@ -872,12 +877,58 @@ int mg_level_step(mg_handle h, int32_t level, int32_t step, int32_t arg, void* s
     return level_step(h, level, step, arg, (hipStream_t)stream);
 }
 
+int mg_autotune(mg_handle h, int32_t reps, void* stream) {
+    if (!h || reps < 1) {
+        set_error("bad mg_autotune arguments");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (!h->coeffs_valid) {
+        set_error("mg_autotune needs coefficients (mg_set_coefficients or mac_project first)");
+        return MG_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int saved = g_forced_for_tuner();
+    int rc = MG_OK;
+    for (int l = 0; l + 1 < h->nlev && rc == MG_OK; ++l) {
+        Level& F = h->lev[l];
+        if (!sweep_fusable<double>(F.nx, F.ny, F.nz)) break;
+        const bool rho = l == 0 && h->rho.rho != nullptr;
+        float best = 1e30f;
+        int best_cfg = -1;
+        for (int c = 0; c < kNumSweepCfg && rc == MG_OK; ++c) {
+            if (!sweep_cfg_fits(F.nx, F.ny, c)) continue;
+            sweep_force_config(c);
+            rc = smooth<double>(h, l, 1, kInPlain, st);          // warm
+            if (rc) break;
+            hipEventRecord(e0, st);
+            rc = smooth<double>(h, l, reps, kInPlain, st);
+            hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = MG_ERR_HIP;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_cfg = c;
+            }
+        }
+        if (best_cfg >= 0) sweep_record_tuned(F.nx, F.ny, F.nz, rho, best_cfg);
+    }
+    sweep_force_config(saved);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
 int mg_tune_sweep(int32_t cfg) {
     if (cfg < -1 || cfg >= kNumSweepCfg) {
         set_error("sweep configuration out of range");
         return MG_ERR_INVALID_ARG;
     }
     sweep_force_config(cfg);
+    g_forced_cfg_mirror = cfg;
     return MG_OK;
 }
 

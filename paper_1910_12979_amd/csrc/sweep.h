@@ -16,9 +16,9 @@ constexpr int kSweepTZMax = 64;  // largest z-chunk
 struct SweepCfg {
     int tx, ty, tz;
 };
-constexpr int kNumSweepCfg = 6;
+constexpr int kNumSweepCfg = 8;
 constexpr SweepCfg kSweepCfgs[kNumSweepCfg] = {
-    {32, 8, 32}, {32, 8, 64}, {64, 8, 32}, {32, 16, 32}, {64, 4, 64}, {32, 4, 64}};
+    {32, 8, 32}, {32, 8, 64}, {64, 8, 32}, {32, 16, 32}, {64, 4, 64}, {32, 4, 64}, {32, 8, 16}, {32, 8, 8}};
 
 enum { kInZero = 0, kInPlain = 1, kInProlong = 2 };
 enum { kOpSweep = 0, kOpSweepNorm = 1, kOpResidRestrict = 2 };
@@ -64,7 +64,7 @@ hipError_t launch_resid_restrict_tiled(const SweepArgs<double>& a, int cfg, hipS
 // Batched form (one launch, many problems): descriptor i (device) is problem
 // i's SweepArgs with tz/ntx/nty filled (sweep_geometry), prefix (device,
 // nprob+1 entries) its first tile; `op` is kOpSweep, kOpSweepNorm (rho only,
-// plain input) or kOpResidRestrict.  Only configuration 0 (32x8x32).
+// plain input) or kOpResidRestrict.  Tile shapes 32x8, 64x8 and 32x4.
 template <typename T>
 hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
                               int in_mode, int op, int cfg, hipStream_t st);
@@ -74,8 +74,14 @@ void sweep_geometry(SweepArgs<float>& a, int cfg);
 // Number of tiles (= partial rows) a sweep of this shape launches with cfg.
 int sweep_tiles(int nx, int ny, int nz, int cfg);
 
-// Configuration used for a level of shape nx x ny x nz (autotuned choice or default).
-int sweep_config_for(int nx, int ny, int nz);
+// Configuration used for a level of shape nx x ny x nz whose coefficients come
+// from rho (finest level) or are stored: forced, autotuned, else a measured
+// default.  A deterministic function of the shape, so a problem's tiles (and
+// the order of its per-tile norm rows) are the same in solo and batched runs.
+int sweep_config_for(int nx, int ny, int nz, bool rho);
+bool sweep_cfg_fits(int nx, int ny, int cfg);
+void sweep_record_tuned(int nx, int ny, int nz, bool rho, int cfg);
+int sweep_tuned_count();
 // Force one configuration for every level that fits it (-1 restores the default).
 void sweep_force_config(int cfg);
 

@@ -32,6 +32,10 @@
 //   phi = (num - h^2 f) / den.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
+#include "devmath.h"
 #include "mg_internal.h"
 #include "sweep.h"
 
@@ -119,6 +123,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const size_t plane = (size_t)nx * ny;
     const size_t col = (size_t)gyw * nx + gxw;
     const T h2 = a.h2;
+    const T ih2 = T(1) / a.h2;
     const T half = T(0.5);
 
     size_t ccol = 0;
@@ -151,10 +156,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     // low z-face coefficient of plane t from the queue values of planes t-1, t
     auto zface = [&](int t, T q_below, T q_here) -> T {
         if (!kRho) return q_here;
-        int tw = wrap3(t, nz);
-        T b0 = (T)sb0e[t - zb];
-        if (tw == 0) return a.pz ? b0 / (half * (q_below + q_here)) : T(0);
-        return b0 / (half * (q_below + q_here));
+        const T b = qdiv((T)sb0e[t - zb], half * (q_below + q_here));
+        return (wrap3(t, nz) == 0 && !a.pz) ? T(0) : b;     // solid wall: no flux
     };
 
     // ---- prologue
@@ -222,12 +225,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         for (int c = 0; c < 2; ++c) {
             const int lx = lx0 + c;
             const T rc = srho[ly][lx];
-            T cx = T(0), cy = T(0);
+            // the window's first row/column has no low neighbour and is never read
+            const T cx = qdiv(b0, half * (srho[ly][lx > 0 ? lx - 1 : 0] + rc));
+            const T cy = qdiv(b0, half * (srho[ly > 0 ? ly - 1 : 0][lx] + rc));
             const bool xwall = (gxw + c == 0) && !a.px;
-            if (lx > 0 && !xwall) cx = b0 / (half * (srho[ly][lx - 1] + rc));
-            if (ly > 0 && !(gyw == 0 && !a.py)) cy = b0 / (half * (srho[ly - 1][lx] + rc));
-            sbx[s][ly][lx] = cx;
-            sby[s][ly][lx] = cy;
+            const bool ywall = gyw == 0 && !a.py;
+            sbx[s][ly][lx] = xwall ? T(0) : cx;
+            sby[s][ly][lx] = ywall ? T(0) : cy;
         }
     };
     if (kRho) {
@@ -250,7 +254,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         r = r + sby[s_t][ly + 1][lx] * (sphi[ly + 1][lx] - pc);
         r = r + bzl * (pm - pc);
         r = r + bzh * (pp - pc);
-        return fc - r / h2;
+        return fc - r * ih2;
     };
     auto resid_in = [&](int c, int s_t, T pm, T pc, T pp, T bzl, T bzh, T fc) {
         const double res = (double)resid_at(c, s_t, pm, pc, pp, bzl, bzh, fc);
@@ -322,7 +326,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + byh;
             den = den + bzl;
             den = den + bzh;
-            Rcur = (num - h2 * (rsel ? Fc1 : Fc0)) / den;
+            Rcur = qdiv(num - h2 * (rsel ? Fc1 : Fc0), den);
         }
         if (!kRR) sR[(t + 4) & 1][ly][lxr] = Rcur;
         if (kNorm && t >= z0 && t < z1 && writes) {
@@ -368,7 +372,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + byh;
             den = den + bzl;
             den = den + bzh;
-            const T blk = (num - h2 * (rsel ? Fm1 : Fm0)) / den;
+            const T blk = qdiv(num - h2 * (rsel ? Fm1 : Fm0), den);
             T* dst = a.phi_out + (size_t)tb * plane + col;
             if (rsel) st2(dst, Rm, blk);
             else st2(dst, blk, Rm);
@@ -479,19 +483,55 @@ hipError_t launch_mode(const SweepArgs<T>& a, bool use_rho, int in_mode, int tzc
     }
 }
 
-int g_forced_cfg = -1;    // set by the tuner (-1: per-shape choice)
+int g_forced_cfg = -1;    // set by mg_tune_sweep (-1: per-shape choice)
+
+// Autotuned choices, keyed by level shape and coefficient source.
+struct TuneKey {
+    int nx, ny, nz, rho;
+    bool operator<(const TuneKey& o) const {
+        if (nx != o.nx) return nx < o.nx;
+        if (ny != o.ny) return ny < o.ny;
+        if (nz != o.nz) return nz < o.nz;
+        return rho < o.rho;
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
 
 }  // namespace
 
 void sweep_force_config(int cfg) { g_forced_cfg = cfg; }
 
-int sweep_config_for(int nx, int ny, int nz) {
-    if (g_forced_cfg >= 0 && g_forced_cfg < kNumSweepCfg) {
-        const SweepCfg& c = kSweepCfgs[g_forced_cfg];
-        if (nx >= c.tx && ny >= c.ty) return g_forced_cfg;
+void sweep_record_tuned(int nx, int ny, int nz, bool rho, int cfg) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[TuneKey{nx, ny, nz, rho ? 1 : 0}] = cfg;
+}
+
+int sweep_tuned_count() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return (int)g_tuned.size();
+}
+
+bool sweep_cfg_fits(int nx, int ny, int cfg) {
+    return cfg >= 0 && cfg < kNumSweepCfg && nx >= kSweepCfgs[cfg].tx && ny >= kSweepCfgs[cfg].ty;
+}
+
+int sweep_config_for(int nx, int ny, int nz, bool rho) {
+    if (g_forced_cfg >= 0 && sweep_cfg_fits(nx, ny, g_forced_cfg)) return g_forced_cfg;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(TuneKey{nx, ny, nz, rho ? 1 : 0});
+        if (it != g_tuned.end()) return it->second;
     }
-    (void)nz;
-    if (nx >= 32 && ny >= 8) return 0;
+    // untuned shapes: choices measured on MI355X for cubic levels (64x8 tiles
+    // on the largest boxes, then 32x8 tiles with shallower z-chunks so small
+    // levels still fill the 256 CUs)
+    const double cells = (double)nx * ny * nz;
+    if (nx >= 64 && cells >= 8.0e6) return 2;
+    if (nx >= 32 && ny >= 8) {
+        if (cells >= 1.0e6) return 6;
+        return 7;
+    }
     return 5;
 }
 
@@ -510,7 +550,8 @@ hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cf
         case 2: return launch_mode<T, 64, 8>(a, use_rho, in_mode, c.tz, st);
         case 3: return launch_mode<T, 32, 16>(a, use_rho, in_mode, c.tz, st);
         case 4: return launch_mode<T, 64, 4>(a, use_rho, in_mode, c.tz, st);
-        default: return launch_mode<T, 32, 4>(a, use_rho, in_mode, c.tz, st);
+        case 5: return launch_mode<T, 32, 4>(a, use_rho, in_mode, c.tz, st);
+        default: return launch_mode<T, 32, 8>(a, use_rho, in_mode, c.tz, st);
     }
 }
 
@@ -524,7 +565,8 @@ hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, h
         case 2: return launch_t<double, 64, 8, true, kInPlain, N>(a, c.tz, st, nparts);
         case 3: return launch_t<double, 32, 16, true, kInPlain, N>(a, c.tz, st, nparts);
         case 4: return launch_t<double, 64, 4, true, kInPlain, N>(a, c.tz, st, nparts);
-        default: return launch_t<double, 32, 4, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 5: return launch_t<double, 32, 4, true, kInPlain, N>(a, c.tz, st, nparts);
+        default: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
     }
 }
 
@@ -538,7 +580,34 @@ hipError_t launch_resid_restrict_tiled(const SweepArgs<double>& a, int cfg, hipS
         case 2: return launch_t<double, 64, 8, true, kInPlain, R>(a, c.tz, st);
         case 3: return launch_t<double, 32, 16, true, kInPlain, R>(a, c.tz, st);
         case 4: return launch_t<double, 64, 4, true, kInPlain, R>(a, c.tz, st);
-        default: return launch_t<double, 32, 4, true, kInPlain, R>(a, c.tz, st);
+        case 5: return launch_t<double, 32, 4, true, kInPlain, R>(a, c.tz, st);
+        default: return launch_t<double, 32, 8, true, kInPlain, R>(a, c.tz, st);
+    }
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_multi_mode(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
+                             int in_mode, int op, hipStream_t st) {
+    if (use_rho) {
+        if constexpr (std::is_same<T, double>::value) {
+            if (op == kOpSweepNorm)
+                return launch_multi_t<T, TX, TY, true, kInPlain, kOpSweepNorm>(d, prefix, nprob, tiles, st);
+            if (op == kOpResidRestrict)
+                return launch_multi_t<T, TX, TY, true, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
+            switch (in_mode) {
+                case kInZero: return launch_multi_t<T, TX, TY, true, kInZero>(d, prefix, nprob, tiles, st);
+                case kInPlain: return launch_multi_t<T, TX, TY, true, kInPlain>(d, prefix, nprob, tiles, st);
+                default: return launch_multi_t<T, TX, TY, true, kInProlong>(d, prefix, nprob, tiles, st);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+    if (op == kOpResidRestrict)
+        return launch_multi_t<T, TX, TY, false, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
+    switch (in_mode) {
+        case kInZero: return launch_multi_t<T, TX, TY, false, kInZero>(d, prefix, nprob, tiles, st);
+        case kInPlain: return launch_multi_t<T, TX, TY, false, kInPlain>(d, prefix, nprob, tiles, st);
+        default: return launch_multi_t<T, TX, TY, false, kInProlong>(d, prefix, nprob, tiles, st);
     }
 }
 
@@ -546,26 +615,11 @@ template <typename T>
 hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
                               int in_mode, int op, int cfg, hipStream_t st) {
     if (tiles <= 0) return hipSuccess;
-    if (cfg != 0) return hipErrorInvalidValue;      // batches use the 32x8 tile shape
-    if (use_rho) {
-        if constexpr (std::is_same<T, double>::value) {
-            if (op == kOpSweepNorm) return launch_multi_t<T, 32, 8, true, kInPlain, kOpSweepNorm>(d, prefix, nprob, tiles, st);
-            if (op == kOpResidRestrict)
-                return launch_multi_t<T, 32, 8, true, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
-            switch (in_mode) {
-                case kInZero: return launch_multi_t<T, 32, 8, true, kInZero>(d, prefix, nprob, tiles, st);
-                case kInPlain: return launch_multi_t<T, 32, 8, true, kInPlain>(d, prefix, nprob, tiles, st);
-                default: return launch_multi_t<T, 32, 8, true, kInProlong>(d, prefix, nprob, tiles, st);
-            }
-        }
-        return hipErrorInvalidValue;
-    }
-    if (op == kOpResidRestrict) return launch_multi_t<T, 32, 8, false, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
-    switch (in_mode) {
-        case kInZero: return launch_multi_t<T, 32, 8, false, kInZero>(d, prefix, nprob, tiles, st);
-        case kInPlain: return launch_multi_t<T, 32, 8, false, kInPlain>(d, prefix, nprob, tiles, st);
-        default: return launch_multi_t<T, 32, 8, false, kInProlong>(d, prefix, nprob, tiles, st);
-    }
+    const SweepCfg& c = kSweepCfgs[cfg];
+    if (c.tx == 32 && c.ty == 8) return launch_multi_mode<T, 32, 8>(d, prefix, nprob, tiles, use_rho, in_mode, op, st);
+    if (c.tx == 64 && c.ty == 8) return launch_multi_mode<T, 64, 8>(d, prefix, nprob, tiles, use_rho, in_mode, op, st);
+    if (c.tx == 32 && c.ty == 4) return launch_multi_mode<T, 32, 4>(d, prefix, nprob, tiles, use_rho, in_mode, op, st);
+    return hipErrorInvalidValue;      // other tile shapes are single-problem only
 }
 
 void sweep_geometry(SweepArgs<double>& a, int cfg) {

@@ -97,6 +97,7 @@ def lib():
         L.serve_counters.argtypes = [vp, ctypes.POINTER(d)]
         L.serve_destroy.argtypes = [vp]
         L.mg_tune_sweep.argtypes = [i32]
+        L.mg_autotune.argtypes = [vp, i32, vp]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -231,6 +232,10 @@ class Hierarchy:
                                ctypes.byref(rel), _stream(stream)))
         return rel.value
 
+    def mg_autotune(self, reps=10, stream=None):
+        """Pick the fastest sweep tile configuration per level shape."""
+        _check(lib().mg_autotune(self._h, int(reps), _stream(stream)))
+
     def level_info(self, level):
         dims = (ctypes.c_int32 * 3)()
         dx = ctypes.c_double()
@@ -319,6 +324,10 @@ class Server:
         self._keep = {}
 
     def submit(self, params: Params, d) -> int:
+        """Queue a projection of the tensors in d; they must stay alive (this
+        object keeps a reference) until the ticket completes."""
+        import torch
+        torch.cuda.current_stream().synchronize()      # inputs ready for the server's stream
         pr = problem_struct(params, d)
         t = ctypes.c_uint64()
         _check(lib().serve_submit(self._s, ctypes.byref(pr), ctypes.byref(t)))

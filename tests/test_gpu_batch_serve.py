@@ -1,0 +1,137 @@
+"""Batched and served projections (GPU): each result must be the one the
+single-problem path gives for that problem alone, bit for bit (same kernels,
+same per-problem tiles and reduction order), and the single-problem path is
+itself checked against the oracle elsewhere; a few problems are re-checked
+against the oracle here too."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1910_12979_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def solo(mp, prob):
+    H = mp.Hierarchy(mp.params_of(prob))
+    d = mp.to_device(prob)
+    st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi,
+                       allow=(0, -1, -3, -4, -5))
+    torch.cuda.synchronize()
+    H.close()
+    return st, {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+
+
+def same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("phi", "u", "v", "w"))
+
+
+def mixed_problems(count, seed=3, edges=(32, 48, 64, 96, 128)):
+    return [I.make_problem(e, H=H, rho_noise=0.01, seed=s)
+            for e, H, s in I.mixed_batch_specs(count, seed=seed, edges=edges)]
+
+
+def test_batch_matches_single_problem_bitwise(mp):
+    probs = [I.make_problem(32, seed=1), I.make_problem(48, H=0.2, seed=2),
+             I.make_problem((40, 24, 56), seed=3, dx=1 / 40), I.make_problem(64, H=0.1, seed=4),
+             I.make_problem((64, 32, 32), seed=5, periodic=(False, True, False), dx=1 / 64),
+             I.make_problem(16, seed=6),                        # not batchable: solved alone inside
+             I.make_problem(64, seed=7, rtol=1e-8)]
+    ref = [solo(mp, p) for p in probs]
+    devs = [mp.to_device(p) for p in probs]
+    code, stats = mp.project_batch([mp.params_of(p) for p in probs], devs)
+    torch.cuda.synchronize()
+    assert code == 0
+    for p, (st0, out0), st, d in zip(probs, ref, stats, devs):
+        out = {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+        assert st["status_name"] == "OK"
+        assert st["cycles"] == st0["cycles"] and st["rel_resid"] == st0["rel_resid"]
+        assert same(out, out0), p.n
+
+
+def test_batch_isolates_failing_problems(mp):
+    good = I.make_problem(32, seed=11)
+    bad_rhs = I.make_problem(32, seed=12); bad_rhs.w[0, 3, 3] = 1.0
+    bad_nan = I.make_problem(48, seed=13); bad_nan.S[1, 1, 1] = np.nan
+    short = I.make_problem(64, seed=14, max_cycles=2)
+    probs = [good, bad_rhs, bad_nan, short]
+    ref = [solo(mp, p) for p in probs]
+    devs = [mp.to_device(p) for p in probs]
+    code, stats = mp.project_batch([mp.params_of(p) for p in probs], devs)
+    torch.cuda.synchronize()
+    assert [s["status_name"] for s in stats] == ["OK", "INCOMPATIBLE_RHS", "NONFINITE", "NOT_CONVERGED"]
+    assert code != 0
+    for i in (0, 3):
+        out = {k: getattr(devs[i], k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+        assert same(out, ref[i][1])
+    assert stats[3]["cycles"] == 2
+
+
+def test_batch_of_64_uneven_boxes_full_size(mp):
+    """The 64-problem batch (edges 32..128): every problem bitwise equal to
+    its single-problem solve; four of them checked against the oracle."""
+    probs = mixed_problems(64)
+    devs = [mp.to_device(p) for p in probs]
+    code, stats = mp.project_batch([mp.params_of(p) for p in probs], devs)
+    torch.cuda.synchronize()
+    assert code == 0 and all(s["status_name"] == "OK" and s["rel_resid"] <= 1e-10 for s in stats)
+    outs = [{k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")} for d in devs]
+    del devs
+    for i in range(0, 64, 4):
+        st0, out0 = solo(mp, probs[i])
+        assert same(outs[i], out0), (i, probs[i].n)
+        assert stats[i]["cycles"] == st0["cycles"]
+    for i in (0, 1, 2, 3):
+        ref = O.mac_project(probs[i], mode="definition")
+        assert rel(outs[i]["phi"], ref["phi"]) <= 1e-9
+
+
+def test_server_results_equal_single_problem(mp):
+    probs = [I.make_problem(e, H=0.1 + 0.05 * k, seed=100 + k, rtol=(1e-8 if k % 2 else 1e-10))
+             for k, e in enumerate((32, 64, 32, 48, 64, 32, 96, 32))]
+    ref = [solo(mp, p) for p in probs]
+    S = mp.Server(hbm_budget_bytes=8 << 30, max_inflight=16)
+    devs = [mp.to_device(p) for p in probs]
+    tickets = []
+    for k, (p, d) in enumerate(zip(probs, devs)):
+        tickets.append(S.submit(mp.params_of(p), d))
+        if k == 3:
+            time.sleep(0.002)               # later requests arrive while the first are running
+    res = [S.wait(t) for t in tickets]
+    c = S.counters()
+    S.close()
+    assert c["completed"] == len(probs) and c["peak_inflight"] >= 2
+    for p, d, r, (st0, out0) in zip(probs, devs, res, ref):
+        assert r["status_name"] == "OK" and r["cycles"] == st0["cycles"]
+        out = {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+        assert same(out, out0), p.n
+
+
+def test_server_budget_and_failures(mp):
+    small = I.make_problem(32, seed=201)
+    big = I.make_problem(64, seed=202)
+    budget = mp.mg_workspace_bytes(mp.params_of(small)) + 1024     # room for one 32^3 at a time
+    S = mp.Server(hbm_budget_bytes=budget, max_inflight=8)
+    with pytest.raises(mp.MGError) as e:
+        S.submit(mp.params_of(big), mp.to_device(big))
+    assert e.value.name == "BUDGET"
+    bad = I.make_problem(32, seed=203); bad.w[0, 1, 1] = 2.0
+    probs = [small, bad, I.make_problem(32, seed=204)]
+    ref = [solo(mp, p) for p in probs]
+    devs = [mp.to_device(p) for p in probs]
+    ts = [S.submit(mp.params_of(p), d) for p, d in zip(probs, devs)]
+    res = [S.wait(t) for t in ts]
+    c = S.counters()
+    S.close()
+    assert [r["status_name"] for r in res] == ["OK", "INCOMPATIBLE_RHS", "OK"]
+    assert c["peak_inflight"] == 1 and c["resident_bytes"] <= budget
+    for i in (0, 2):
+        out = {k: getattr(devs[i], k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+        assert same(out, ref[i][1])
