@@ -1,24 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark: variable-coefficient MAC-projection solves/s on one MI355X.
 
-Workload: the 256^3 steeply stratified box (periodic x,y, solid walls in z,
-beta0 = exp(-z/0.1), rho = beta0 (1 + 0.01 N(0,1)), S = 0.1 N(0,1) with its
-beta0-weighted mean removed, U ~ N(0,1)), FP64, V(2,2) red-black GS cycles
-to a 1e-10 relative residual.  One step = one whole projection (coefficients,
-right-hand side, V-cycles, velocity correction) of the same input; the input
-velocity is restored from a device copy before each step (a device-to-device
-copy inside the timed region).  Inputs are resident in HBM before timing.
+Headline workload: the 256^3 steeply stratified box (periodic x,y, solid
+walls in z, beta0 = exp(-z/0.1), rho = beta0 (1 + 0.01 N(0,1)), S = 0.1 N(0,1)
+with its beta0-weighted mean removed, U ~ N(0,1)), FP64, V(2,2) red-black GS
+cycles to a 1e-10 relative residual.  One step = one whole projection
+(coefficients, right-hand side, V-cycles, velocity correction) of the same
+input; the input velocity is restored from a device copy before each step (a
+device-to-device copy inside the timed region).  Inputs are resident in HBM
+before timing.
 
-Also reported: the same box in mixed precision (FP32 cycles with FP64
-iterative refinement), the smoother's roofline figure measured with HIP
-events, per-step latency percentiles, and the FP64 CPU oracle timed on the
-host cores on whole solves of the same box (about 10 s of CPU work).
+Also reported on the same JSON line:
+  * roofline: the finest-level fused sweep (the dominant kernel), its launch
+    duration measured with HIP events on the stream it runs on, against the
+    8 TB/s HBM peak; `traffic` is the counter-measured HBM bytes per launch
+    when they were taken on the current sweep source, else null;
+  * mixed: the same box in mixed precision (FP32 cycles with FP64 iterative
+    refinement) and its phi difference from the FP64 GPU solve;
+  * batch: 64 independent boxes with edges from {32,48,64,96,128} solved by
+    project_batch, against the same problems solved one by one;
+  * serve: Poisson request streams of {32,64,128,256}^3 boxes through the
+    continuous-batching server, solves/s with p50/p99 latency per rate;
+  * cpu_baseline: the FP64 CPU oracle timed on the host cores on whole
+    solves of the headline box (about 10 s of CPU work).
 
 Prints one JSON line.  `--gpus` above 1 is refused: this path runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +46,14 @@ HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_CELL = 32.0
 SWEEP_BYTES_STORED_COEFF = 48.0
 
+# HBM bytes per finest-level sweep launch at 256^3, from two rocprofv3 --pmc
+# passes over this script (FETCH_SIZE, then WRITE_SIZE), each scaled by what
+# the same counter reads for a plain device copy of known size.  Valid only
+# for the sweep source it was taken on (SHA-1 of the files below) and tile.
+SWEEP_SOURCES = ("paper_1910_12979_amd/csrc/sweep.hip", "paper_1910_12979_amd/csrc/sweep.h",
+                 "paper_1910_12979_amd/csrc/devmath.h")
+SWEEP_TRAFFIC = None   # {"sha1": ..., "tile": [tx, ty, tz], "n": 256, "read": B, "write": B}
+
 
 def percentile(xs, q):
     xs = sorted(xs)
@@ -42,6 +61,293 @@ def percentile(xs, q):
         return None
     k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
     return xs[k]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sweep_source_sha1():
+    h = hashlib.sha1()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+class Restorable:
+    """A device problem plus copies of its input velocity."""
+
+    def __init__(self, macproj, prob, dev):
+        self.prob = prob
+        self.d = macproj.to_device(prob, dev)
+        self.u0, self.v0, self.w0 = self.d.u.clone(), self.d.v.clone(), self.d.w.clone()
+
+    def restore(self):
+        self.d.u.copy_(self.u0)
+        self.d.v.copy_(self.v0)
+        self.d.w.copy_(self.w0)
+
+
+def fp64_leg(args, torch, macproj, R):
+    d = R.d
+    H = macproj.Hierarchy(macproj.params_of(R.prob))
+
+    def step():
+        R.restore()
+        return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+
+    log(f"{args.n}^3 FP64 warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    lat, stats = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        stats.append(step())          # returns after the solve's final status is on the host
+        lat.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for st in stats:
+        assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+    return H, elapsed, lat, stats
+
+
+def smoother_leg(args, torch, H, R):
+    """Finest-level fused sweep: HIP events on the stream it is launched on."""
+    d = R.d
+    stream = torch.cuda.current_stream()
+    N = args.n ** 3
+    tile = H.sweep_config(0)
+    H.set_coefficients(d.rho, d.beta0_cc, d.beta0_edge)    # finest level reads rho, as in the solve
+    H.level_step(0, "smooth", 1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        H.level_step(0, "smooth", 1)                         # one launch = one red+black sweep
+    e1.record(stream)
+    e1.synchronize()
+    launch_ms = e0.elapsed_time(e1) / args.kernel_reps
+    launch_bytes = SWEEP_BYTES_PER_CELL * N
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+
+    # a plain device copy of the same field size on the same stream: the
+    # practical HBM ceiling for a read+write stream, and the counter
+    # calibration kernel for the traffic figures
+    a = torch.empty(N, dtype=torch.float64, device=d.rho.device).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        b.copy_(a)
+    e1.record(stream)
+    e1.synchronize()
+    copy_ms = e0.elapsed_time(e1) / args.kernel_reps
+    del a, b
+
+    traffic = None
+    sha = sweep_source_sha1()
+    if (SWEEP_TRAFFIC and SWEEP_TRAFFIC["sha1"] == sha and tile is not None
+            and list(SWEEP_TRAFFIC["tile"]) == list(tile[:3]) and SWEEP_TRAFFIC["n"] == args.n):
+        traffic = SWEEP_TRAFFIC["read"] + SWEEP_TRAFFIC["write"]
+    tx, ty, tz = tile[:3] if tile else (0, 0, 0)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"mg::k_sweep<double, {tx}, {ty}, true, 1, 0> (finest level, coefficients from rho, "
+                      f"one red+black sweep per launch, {tx}x{ty}-cell tiles, {tz}-plane z-chunks)",
+            "launch_ms": launch_ms, "bytes_per_launch": launch_bytes,
+            "bytes_per_cell": SWEEP_BYTES_PER_CELL,
+            "achieved_at_48B_per_cell": SWEEP_BYTES_STORED_COEFF * N / (launch_ms * 1e-3) / 1e9,
+            "copy_GBs": 2 * 8 * N / (copy_ms * 1e-3) / 1e9,
+            "sweep_source_sha1": sha}
+
+
+def mixed_leg(args, torch, macproj, R, phi64):
+    d = R.d
+    Hm = macproj.Hierarchy(macproj.params_of(R.prob, precision="mixed"))
+
+    def step():
+        R.restore()
+        return Hm.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+
+    log(f"mixed precision {args.mixed_steps} steps")
+    step()
+    torch.cuda.synchronize()
+    lat, mst = [], []
+    tm0 = time.perf_counter()
+    for _ in range(args.mixed_steps):
+        ts = time.perf_counter()
+        mst.append(step())
+        lat.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - tm0
+    for st in mst:
+        assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+    diff = float(torch.linalg.norm(d.phi - phi64) / torch.linalg.norm(phi64))
+    Hm.close()
+    return {"value": args.mixed_steps / tm, "unit": "solves/s", "ms_per_step": tm * 1e3 / args.mixed_steps,
+            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+            "refinement_steps": mst[-1]["cycles"], "rel_resid": mst[-1]["rel_resid"],
+            "phi_rel_diff_vs_fp64_gpu": diff}
+
+
+def batch_leg(args, torch, macproj, inputs, dev):
+    """64 independent uneven boxes: one project_batch call against one
+    mac_project call per problem (hierarchies kept, as the batch keeps them)."""
+    specs = inputs.mixed_batch_specs(64)
+    log("batch: generating 64 problems")
+    rs = [Restorable(macproj, inputs.make_problem(e, H=H, rho_noise=0.01, seed=s), dev) for e, H, s in specs]
+    params = [macproj.params_of(r.prob) for r in rs]
+    cells = sum(r.prob.ncells for r in rs)
+    tuned = []
+    if args.autotune:
+        for e in sorted({e for e, _, _ in specs}):
+            r = next(r for r in rs if r.prob.n[0] == e)
+            Ht = macproj.Hierarchy(macproj.params_of(r.prob))
+            Ht.set_coefficients(r.d.rho, r.d.beta0_cc, r.d.beta0_edge)
+            Ht.mg_autotune(reps=5)
+            tuned.append({"edge": e, "level0_tile": Ht.sweep_config(0)})
+            Ht.close()
+
+    def run_batch():
+        for r in rs:
+            r.restore()
+        code, st = macproj.project_batch(params, [r.d for r in rs])
+        assert code == 0 and all(s["status_name"] == "OK" and s["rel_resid"] <= 1e-10 for s in st), code
+        return st
+
+    log(f"batch: {args.batch_reps} x project_batch(64)")
+    run_batch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_reps):
+        st = run_batch()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.batch_reps
+    phis = [r.d.phi.clone() for r in rs]
+
+    log("batch: the same 64 problems one by one")
+    hs = [macproj.Hierarchy(p) for p in params]
+
+    def run_solo():
+        for r in rs:
+            r.restore()
+        out = []
+        for h, r in zip(hs, rs):
+            d = r.d
+            out.append(h.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi))
+        return out
+
+    run_solo()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_reps):
+        so = run_solo()
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / args.batch_reps
+    identical = all(torch.equal(p, r.d.phi) for p, r in zip(phis, rs))
+    for h in hs:
+        h.close()
+    del rs, phis
+    return {"problems": 64, "cells": cells, "precision": "fp64",
+            "value": 64 / tb, "unit": "solves/s", "ms_per_batch": tb * 1e3,
+            "one_by_one": {"value": 64 / ts, "ms_per_batch": ts * 1e3},
+            "speedup_vs_one_by_one": ts / tb,
+            "cycles_total": sum(s["cycles"] for s in st), "cycles_one_by_one": sum(s["cycles"] for s in so),
+            "phi_identical_to_one_by_one": identical, "autotuned": tuned}
+
+
+def serve_leg(args, torch, macproj, inputs, dev):
+    """Open-loop Poisson arrivals through the continuous-batching server.
+    Each size has a few buffer sets (distinct problems); a request takes a
+    free set of its size, has its velocity restored and is submitted at its
+    arrival time.  Latency = (submission delay past the arrival time) +
+    the server's submit-to-done time."""
+    pools = {32: 12, 64: 10, 128: 6, 256: 3}
+    log("serve: generating buffer sets")
+    sets = {}
+    for e, m in pools.items():
+        sets[e] = [Restorable(macproj, inputs.make_problem(e, H=0.08 + 0.42 * (k + 0.5) / m, rho_noise=0.01,
+                                                             seed=50000 + 100 * e + k), dev) for k in range(m)]
+    torch.cuda.synchronize()
+    out = []
+    for rate in args.serve_rates:
+        reqs = inputs.serving_requests(args.serve_requests, rate)
+        S = macproj.Server(hbm_budget_bytes=200 << 30, max_inflight=64)
+        busy = {e: [None] * len(v) for e, v in sets.items()}   # ticket holding each set
+        done = {}
+
+        def finish(t):
+            if t not in done:
+                done[t] = S.wait(t)
+
+        def free_set(e):
+            for k, t in enumerate(busy[e]):
+                if t is None:
+                    return k
+                if t in done:
+                    return k
+                r = S.poll(t)
+                if r is not None:
+                    done[t] = r
+                    return k
+            k = min(range(len(busy[e])), key=lambda i: busy[e][i])   # oldest ticket of this size
+            finish(busy[e][k])
+            return k
+
+        log(f"serve: {len(reqs)} requests at {rate} req/s")
+        tickets = []
+        t0 = time.perf_counter()
+        for (ta, e, H, tol, _seed) in reqs:
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            k = free_set(e)
+            r = sets[e][k]
+            r.restore()
+            p = macproj.params_of(r.prob, rtol=tol)
+            delay = max(0.0, time.perf_counter() - t0 - ta)
+            t = S.submit(p, r.d)
+            busy[e][k] = t
+            tickets.append((t, delay, e, tol))
+        for t, _, _, _ in tickets:
+            finish(t)
+        t_end = time.perf_counter() - t0
+        c = S.counters()
+        S.close()
+        lat = []
+        for t, delay, e, tol in tickets:
+            st = done[t]
+            assert st["status_name"] == "OK" and st["rel_resid"] <= tol, (e, st)
+            lat.append(delay * 1e3 + st["ms_total"])
+        mix = {e: sum(1 for _, _, ee, _ in tickets if ee == e) for e in pools}
+        out.append({"rate": rate, "requests": len(reqs), "solves_per_s": len(reqs) / t_end,
+                    "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                    "peak_inflight": c["peak_inflight"], "mix": mix})
+    del sets
+    return {"budget_bytes": 200 << 30, "max_inflight": 64, "precision": "fp64", "rates": out}
+
+
+def cpu_leg(args, prob):
+    log("CPU oracle baseline")
+    from oracle import oracle as orc
+    solves = 0
+    tc0 = time.perf_counter()
+    while True:                       # whole solves until ~10 s of CPU work (at most 8)
+        ref = orc.mac_project(prob)
+        assert ref["status"] == 0
+        solves += 1
+        tc = time.perf_counter() - tc0
+        if tc >= 10.0 or solves >= 8:
+            break
+    return {"value": solves / tc, "unit": "solves/s", "cores": orc.max_threads(), "kind": "oracle",
+            "sample": f"{solves} full {args.n}^3 FP64 projections of the same box (algorithm mode, "
+                      f"{ref['cycles']} V-cycles each), {tc:.1f} s wall"}
 
 
 def main():
@@ -52,6 +358,10 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--mixed-steps", type=int, default=5)
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--batch-reps", type=int, default=3, help="0 skips the batch leg")
+    ap.add_argument("--autotune", type=int, default=1, help="autotune the batch's shapes first")
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[100.0, 400.0, 2000.0])
+    ap.add_argument("--serve-requests", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -60,7 +370,6 @@ def main():
               "--gpus N with N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1910_12979_amd import inputs, macproj
@@ -72,99 +381,23 @@ def main():
     dev = "cuda:0"
     n = args.n
     prob = inputs.STEEP_256(n=n)
-    d = macproj.to_device(prob, dev)
-    u0, v0, w0 = d.u.clone(), d.v.clone(), d.w.clone()
-    H = macproj.Hierarchy(macproj.params_of(prob))
-    stream = torch.cuda.current_stream()
+    R = Restorable(macproj, prob, dev)
 
-    def step(h):
-        d.u.copy_(u0)
-        d.v.copy_(v0)
-        d.w.copy_(w0)
-        return h.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
-
-    print(f"[bench] {n}^3 FP64 warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step(H)
-    torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    lat = []
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        st = step(H)
-        lat.append((time.perf_counter() - ts) * 1e3)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    for st in stats:
-        assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+    H, elapsed, lat, stats = fp64_leg(args, torch, macproj, R)
     value = args.steps / elapsed
     cycles = stats[-1]["cycles"]
-    phi64 = d.phi.clone()
-
-    # --- smoother roofline: HIP events around level-0 sweeps on this stream
-    print("[bench] smoother kernel timing", file=sys.stderr, flush=True)
-    N = n ** 3
-    H.set_coefficients(d.rho, d.beta0_cc, d.beta0_edge)    # finest level reads rho, as in the solve
-    H.level_step(0, "smooth", 1)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_reps):
-        H.level_step(0, "smooth", 1)
-    e1.record(stream)
-    e1.synchronize()
-    launch_ms = e0.elapsed_time(e1) / args.kernel_reps   # one launch = one whole sweep
-    launch_bytes = SWEEP_BYTES_PER_CELL * N
-    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
-    achieved_stored = SWEEP_BYTES_STORED_COEFF * N / (launch_ms * 1e-3) / 1e9
+    phi64 = R.d.phi.clone()
+    log("smoother kernel timing")
+    roofline = smoother_leg(args, torch, H, R)
     H.close()
 
-    # --- mixed precision on the same box
-    mixed = None
-    if args.mixed_steps > 0:
-        print(f"[bench] mixed precision {args.mixed_steps} steps", file=sys.stderr, flush=True)
-        Hm = macproj.Hierarchy(macproj.params_of(prob, precision="mixed"))
-        step(Hm)
-        torch.cuda.synchronize()
-        tm0 = time.perf_counter()
-        mst = []
-        for _ in range(args.mixed_steps):
-            mst.append(step(Hm))
-        torch.cuda.synchronize()
-        tm1 = time.perf_counter()
-        for st in mst:
-            assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
-        diff = float(torch.linalg.norm(d.phi - phi64) / torch.linalg.norm(phi64))
-        mixed = {"value": args.mixed_steps / (tm1 - tm0), "unit": "solves/s",
-                 "ms_per_step": (tm1 - tm0) * 1e3 / args.mixed_steps,
-                 "refinement_steps": mst[-1]["cycles"], "rel_resid": mst[-1]["rel_resid"],
-                 "phi_rel_diff_vs_fp64_gpu": diff}
-        Hm.close()
+    mixed = mixed_leg(args, torch, macproj, R, phi64) if args.mixed_steps > 0 else None
+    del phi64
+    batch = batch_leg(args, torch, macproj, inputs, dev) if args.batch_reps > 0 else None
+    serve = serve_leg(args, torch, macproj, inputs, dev) if args.serve_rates else None
+    cpu = None if args.no_cpu_baseline else cpu_leg(args, prob)
 
-    # --- CPU oracle on the host cores: one FP64 solve of the same box
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        from oracle import oracle as orc
-        solves = 0
-        tc0 = time.perf_counter()
-        while True:                       # whole solves until ~10 s of CPU work (at most 8)
-            ref = orc.mac_project(prob)
-            assert ref["status"] == 0
-            solves += 1
-            tc = time.perf_counter() - tc0
-            if tc >= 10.0 or solves >= 8:
-                break
-        cpu = {"value": solves / tc, "unit": "solves/s", "cores": orc.max_threads(), "kind": "oracle",
-               "sample": f"{solves} full {n}^3 FP64 projections of the same box (algorithm mode, "
-                         f"{ref['cycles']} V-cycles each), {tc:.1f} s wall"}
-
-    model_bytes = N * (156.0 + cycles * 326.0)
+    model_bytes = n ** 3 * (156.0 + cycles * 326.0)
     out = {
         "metric": "MAC-projection solves/s at 256^3 to 1e-10 resid, mixed vs FP64; p99 latency",
         "value": value,
@@ -182,13 +415,11 @@ def main():
                                f"FP64 V(2,2) red-black GS multigrid to 1e-10",
                    "n": n, "rtol": 1e-10, "precision": "fp64", "cycles": cycles},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep<double, 32, 8, true, 1> (finest level, one red+black sweep per launch)",
-                     "launch_ms": launch_ms, "bytes_per_launch": launch_bytes,
-                     "achieved_at_48B_per_cell": achieved_stored},
+        "roofline": roofline,
         "model_roofline_frac": value * model_bytes / (HBM_PEAK_GBS * 1e9),
         "mixed": mixed,
+        "batch": batch,
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

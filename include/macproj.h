@@ -221,6 +221,12 @@ int mg_tune_sweep(int32_t cfg);
  * hierarchy's own level arrays, never caller data.  Blocks until done. */
 int mg_autotune(mg_handle h, int32_t reps, void* stream);
 
+/* Fused-sweep tile used on level l of h: tile[0..2] = cells per workgroup
+ * tile in x, y and planes per z-chunk, tile[3] = configuration index (as for
+ * mg_tune_sweep).  All four are -1 for a level the fused sweep does not cover
+ * (it then runs one kernel per colour). */
+int mg_sweep_config(mg_handle h, int32_t level, int32_t tile[4]);
+
 const char* mg_strerror(int code);
 const char* mg_last_error(void);
 

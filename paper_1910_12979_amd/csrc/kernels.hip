@@ -540,6 +540,11 @@ __global__ void k_accumulate(double* __restrict__ phi, const float* __restrict__
         phi[e] = phi[e] + (double)e32[e] * s;
 }
 
+__global__ void k_scale_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t n, double s) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        b[e] = (float)(a[e] * s);
+}
+
 __global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, size_t n) {
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
         b[e] = (float)a[e];
@@ -726,6 +731,11 @@ hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* sc
 hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const double* scale_inv,
                              hipStream_t st) {
     hipLaunchKernelGGL(k_accumulate, dim3(stream_blocks(n)), dim3(kBlock), 0, st, phi, e32, n, scale_inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_to_f32(const double* a, float* b, size_t n, double s, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_to_f32, dim3(stream_blocks(n)), dim3(kBlock), 0, st, a, b, n, s);
     return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ struct mg_hierarchy {
     double* host = nullptr;       // pinned mirror of scal
     double* minv = nullptr;       // inverse of the coarsest-level matrix
     double* r64 = nullptr;        // FP64 residual (mixed precision)
+    float* rho32 = nullptr;       // FP32 copy of rho (mixed precision, fused finest level)
+    bool rho32_on = false;        // rho32 holds the current solve's rho
     double* rho_own = nullptr;    // copies made by mg_set_coefficients
     double* b0c_own = nullptr;
     double* b0e_own = nullptr;

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -120,7 +121,11 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
     double* scal = (double*)take(64 * 8);
     double* r64 = nullptr;
     size_t N0 = (size_t)p->n[0] * p->n[1] * p->n[2];
-    if (mixed) r64 = (double*)take(N0 * 8);
+    float* rho32 = nullptr;
+    if (mixed) {
+        r64 = (double*)take(N0 * 8);
+        rho32 = (float*)take(N0 * 4);
+    }
     double* rho_own = (double*)take(N0 * 8);
     double* b0c_own = (double*)take((size_t)p->n[2] * 8);
     double* b0e_own = (double*)take((size_t)(p->n[2] + 1) * 8);
@@ -129,6 +134,7 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
         H->partials = partials;
         H->scal = scal;
         H->r64 = r64;
+        H->rho32 = rho32;
         H->rho_own = rho_own;
         H->b0c_own = b0c_own;
         H->b0e_own = b0e_own;
@@ -297,7 +303,8 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
         HIPCHK(launch_rbgs<T>(s, F.h, A->phi, A->f, A->bx, A->by, A->bz, nsweeps, st));
         return MG_OK;
     }
-    const bool use_rho = dbl && l == 0 && H->rho.rho != nullptr;
+    // finest level: coefficients from rho (FP64) or its FP32 copy (mixed solve)
+    const bool use_rho = l == 0 && (dbl ? H->rho.rho != nullptr : H->rho32_on);
     for (int k = 0; k < nsweeps; ++k) {
         SweepArgs<T> a{};
         a.nx = F.nx;
@@ -315,7 +322,8 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
         a.bx = A->bx;
         a.by = A->by;
         a.bz = A->bz;
-        a.rho = H->rho.rho;
+        if constexpr (dbl) a.rho = H->rho.rho;
+        else a.rho = H->rho32;
         a.b0c = H->rho.b0c;
         a.b0e = H->rho.b0e;
         HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain, sweep_config_for(F.nx, F.ny, F.nz, use_rho), st));
@@ -356,14 +364,35 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
         }
         HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f, C.d.phi, st));
     } else {
+        if (l == 0 && H->rho32_on) {
+            SweepArgs<float> a{};
+            a.nx = F.nx;
+            a.ny = F.ny;
+            a.nz = F.nz;
+            a.px = H->px;
+            a.py = H->py;
+            a.pz = H->pz;
+            a.h2 = (float)(F.h * F.h);
+            a.phi_in = F.s.phi;
+            a.f = F.s.f;
+            a.rho = H->rho32;
+            a.b0c = H->rho.b0c;
+            a.b0e = H->rho.b0e;
+            a.fc = C.s.f;
+            a.phic_out = C.s.phi;
+            HIPCHK(launch_resid_restrict_tiled<float>(a, sweep_config_for(F.nx, F.ny, F.nz, true), st));
+            return MG_OK;
+        }
         HIPCHK(launch_resid_restrict<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, C.s.f, C.s.phi, st));
     }
     return MG_OK;
 }
 
 // V-cycle from level l (FP64 or FP32 arrays; the coarsest solve is FP64).
+// Coarse levels start from phi = 0; level 0 from its stored phi unless
+// zero_start (the mixed solve's correction cycle).
 template <typename T>
-static int vcycle(mg_hierarchy* H, int l, hipStream_t st, int pre_done = 0) {
+static int vcycle(mg_hierarchy* H, int l, hipStream_t st, int pre_done = 0, bool zero_start = false) {
     Level& F = H->lev[l];
     if (l == H->nlev - 1) {
         if constexpr (std::is_same<T, double>::value)
@@ -372,7 +401,8 @@ static int vcycle(mg_hierarchy* H, int l, hipStream_t st, int pre_done = 0) {
             HIPCHK(launch_coarse_solve_f32((int)F.N, H->minv, F.s.f, F.s.phi, st));
         return MG_OK;
     }
-    int rc = smooth<T>(H, l, H->p.pre_sweeps - pre_done, (l == 0 || pre_done > 0) ? kInPlain : kInZero, st);
+    const bool from_zero = l > 0 ? pre_done == 0 : zero_start;
+    int rc = smooth<T>(H, l, H->p.pre_sweeps - pre_done, from_zero ? kInZero : kInPlain, st);
     if (rc) return rc;
     rc = resid_restrict<T>(H, l, st);
     if (rc) return rc;
@@ -445,6 +475,79 @@ static int speculative_sweep_norm(mg_hierarchy* H, bool* taken_out, double fnorm
     return MG_OK;
 }
 
+// Power of two nearest 1 / rms(r), the scale of the FP32 residual: the
+// scaled values are O(1) and scaling by 2^k is exact in both directions.
+static double residual_scale(double norm2_sqrt, size_t n) {
+    const double rms = norm2_sqrt / std::sqrt((double)n);
+    if (!(rms > 0.0) || !std::isfinite(rms)) return 1.0;
+    return std::ldexp(1.0, -std::ilogb(rms));
+}
+
+// Mixed-precision solve on a fusable finest level (Sec. 3 multigrid used as
+// the inner solver of iterative refinement): each iteration runs one FP32
+// V-cycle from zero on the scaled FP64 residual, then one FP64 refinement
+// kernel adds the correction to phi, recomputes r = f - L phi with exact FP64
+// coefficients from rho, measures its norm and writes the next FP32 residual.
+// The FP32 finest-level sweeps recompute their coefficients from an FP32
+// copy of rho.
+static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_out, double* rel_out,
+                                    const std::function<void(int, double)>& record, hipStream_t st) {
+    Level& L0 = H->lev[0];
+    HIPCHK(launch_coeff_to_f32(H->rho.rho, H->rho32, L0.N, st));
+    H->rho32_on = true;
+    HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
+    double s = residual_scale(fnorm, L0.N);                  // residual = f while phi = 0
+    HIPCHK(launch_scale_to_f32(L0.d.f, L0.s.f, L0.N, s, st));
+    const int cfg = sweep_config_for(L0.nx, L0.ny, L0.nz, true);
+    int status = MG_ERR_NOT_CONVERGED, cycles = 0;
+    double rel = 1.0;
+    while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
+        int rc = vcycle<float>(H, 0, st, 0, true);
+        if (rc) return rc;
+        SweepArgs<double> a{};
+        a.nx = L0.nx;
+        a.ny = L0.ny;
+        a.nz = L0.nz;
+        a.px = H->px;
+        a.py = H->py;
+        a.pz = H->pz;
+        a.h2 = L0.h * L0.h;
+        a.phi_in = L0.d.phi;
+        a.phi_out = L0.phi2_d;
+        a.f = L0.d.f;
+        a.rho = H->rho.rho;
+        a.b0c = H->rho.b0c;
+        a.b0e = H->rho.b0e;
+        a.partials = H->partials;
+        a.corr = L0.s.phi;
+        a.cscale = 1.0 / s;                                   // exact: s is a power of two
+        const double s_next = residual_scale(rel * fnorm, L0.N);
+        a.r32 = L0.s.f;
+        a.rscale = s_next;
+        int np = 0;
+        HIPCHK(launch_refine(a, cfg, &np, st));
+        std::swap(L0.d.phi, L0.phi2_d);
+        s = s_next;
+        rc = reduce_to(H, np, kSlotRes, st);
+        if (rc) return rc;
+        rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
+        if (rc) return rc;
+        ++cycles;
+        const double* r = H->host + kSlotRes * kReduceWidth;
+        rel = std::sqrt(r[0]) / fnorm;
+        record(cycles, rel);
+        if (r[3] > 0.0 || !std::isfinite(rel)) {
+            status = MG_ERR_NONFINITE;
+            set_error("non-finite residual during the solve");
+            break;
+        }
+        if (rel <= H->p.rtol) status = MG_OK;
+    }
+    *cycles_out = cycles;
+    *rel_out = rel;
+    return status;
+}
+
 // Solve on level 0 after f (mean-removed) and the coefficients are in place.
 static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStream_t st) {
     Level& L0 = H->lev[0];
@@ -464,9 +567,19 @@ static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStrea
     };
     const bool mixed = H->p.precision == MG_MIXED;
     if (H->p.rtol >= 1.0) status = MG_OK;
-    const bool fused_norm = !mixed && H->rho.rho && H->p.pre_sweeps >= 1 && H->nlev > 1 &&
-                            sweep_fusable<double>(L0.nx, L0.ny, L0.nz);
-    if (fused_norm) {
+    const bool fused = H->rho.rho && H->p.pre_sweeps >= 1 && H->nlev > 1 &&
+                       sweep_fusable<double>(L0.nx, L0.ny, L0.nz);
+    const bool fused_norm = !mixed && fused;
+    if (mixed && fused && status == MG_ERR_NOT_CONVERGED) {
+        auto rec = [&](int c, double r) {
+            if (stats && c < MG_HIST_MAX) {
+                stats->resid_hist[c] = r;
+                stats->hist_len = c + 1;
+            }
+        };
+        status = solve_level0_mixed_fused(H, fnorm, &cycles, &rel, rec, st);
+        if (status != MG_OK && status != MG_ERR_NOT_CONVERGED && status != MG_ERR_NONFINITE) return status;
+    } else if (fused_norm) {
         while (status == MG_ERR_NOT_CONVERGED) {
             int pre_done = 0;
             if (cycles > 0) {
@@ -621,6 +734,7 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
 int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
             double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st) {
     int rc = project_impl(H, rho, b0c, b0e, S, u, v, w, phi_out, stats, st);
+    if (H) H->rho32_on = false;
     // the caller's rho may not outlive the call: later mg_vcycle / step calls
     // use the stored finest-level coefficients (bit-identical values)
     if (H) H->rho = RhoArgs{};
@@ -929,6 +1043,24 @@ int mg_tune_sweep(int32_t cfg) {
     }
     sweep_force_config(cfg);
     g_forced_cfg_mirror = cfg;
+    return MG_OK;
+}
+
+int mg_sweep_config(mg_handle h, int32_t level, int32_t tile[4]) {
+    if (!h || !tile || level < 0 || level >= h->nlev) {
+        set_error("bad mg_sweep_config arguments");
+        return MG_ERR_INVALID_ARG;
+    }
+    tile[0] = tile[1] = tile[2] = tile[3] = -1;
+    const Level& F = h->lev[level];
+    const bool dbl = h->p.precision == MG_FP64;
+    const bool fusable = dbl ? sweep_fusable<double>(F.nx, F.ny, F.nz) : sweep_fusable<float>(F.nx, F.ny, F.nz);
+    if (level + 1 >= h->nlev || !fusable) return MG_OK;
+    const int c = sweep_config_for(F.nx, F.ny, F.nz, dbl && level == 0);
+    tile[0] = kSweepCfgs[c].tx;
+    tile[1] = kSweepCfgs[c].ty;
+    tile[2] = kSweepCfgs[c].tz;
+    tile[3] = c;
     return MG_OK;
 }
 

@@ -20,8 +20,8 @@ constexpr int kNumSweepCfg = 8;
 constexpr SweepCfg kSweepCfgs[kNumSweepCfg] = {
     {32, 8, 32}, {32, 8, 64}, {64, 8, 32}, {32, 16, 32}, {64, 4, 64}, {32, 4, 64}, {32, 8, 16}, {32, 8, 8}};
 
-enum { kInZero = 0, kInPlain = 1, kInProlong = 2 };
-enum { kOpSweep = 0, kOpSweepNorm = 1, kOpResidRestrict = 2 };
+enum { kInZero = 0, kInPlain = 1, kInProlong = 2, kInCorrect = 3 };
+enum { kOpSweep = 0, kOpSweepNorm = 1, kOpResidRestrict = 2, kOpRefine = 3 };
 
 template <typename T>
 struct SweepArgs {
@@ -37,12 +37,16 @@ struct SweepArgs {
     const T* bx;               // stored coefficients (coarse levels)
     const T* by;
     const T* bz;
-    const double* rho;         // finest level: coefficients from rho and beta0
+    const T* rho;              // finest level: coefficients from rho and beta0
     const double* b0c;
     const double* b0e;
-    double* partials;          // residual-norm rows (kOpSweepNorm), one per tile
+    double* partials;          // residual-norm rows (kOpSweepNorm, kOpRefine), one per tile
     T* fc;                     // coarse right-hand side (kOpResidRestrict)
     T* phic_out;               // coarse phi, zeroed (kOpResidRestrict)
+    const float* corr;         // kInCorrect: input is phi_in + cscale * corr
+    double cscale;
+    float* r32;                // kOpRefine: r32 = (float)(rscale * (f - L phi))
+    double rscale;
 };
 
 template <typename T>
@@ -59,7 +63,14 @@ hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, h
 // Finest level (coefficients from rho): f_c = R (f - L phi), phi_c = 0, using
 // the sweep's tiles (each face coefficient computed once per cell).  Needs
 // even tile origins, which every configuration has.
-hipError_t launch_resid_restrict_tiled(const SweepArgs<double>& a, int cfg, hipStream_t st);
+template <typename T>
+hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, int cfg, hipStream_t st);
+
+// Refinement step of the mixed-precision solve (finest level, FP64,
+// coefficients from rho): phi_out = phi_in + cscale * corr; per tile the
+// partial row {sum r^2, 0, max |r|, #non-finite} of r = f - L phi_out; and
+// r32 = (float)(rscale * r).  *nparts = rows written.
+hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st);
 
 // Batched form (one launch, many problems): descriptor i (device) is problem
 // i's SweepArgs with tz/ntx/nty filled (sweep_geometry), prefix (device,

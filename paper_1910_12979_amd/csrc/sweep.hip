@@ -91,6 +91,7 @@ template <typename T, int TX, int TY, bool kRho, int kIn, int kOp>
 __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile) {
     constexpr bool kNorm = kOp == kOpSweepNorm;    // sweep + residual norm of its input
     constexpr bool kRR = kOp == kOpResidRestrict;  // residual + restriction only (no sweep)
+    constexpr bool kIR = kOp == kOpRefine;         // corrected phi + scaled residual + norm (no sweep)
     constexpr int WX = TX + 4, WY = TY + 4, WP = WX / 2;   // ring-2 window, pairs per row
     constexpr int NB = kSweepTZMax + 6;                    // beta0 planes staged per chunk
     __shared__ T sphi[WY][WX];                // phi_in, current plane
@@ -125,6 +126,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const T h2 = a.h2;
     const T ih2 = T(1) / a.h2;
     const T half = T(0.5);
+    const T cscale = (T)a.cscale;
 
     size_t ccol = 0;
     if (kIn == kInProlong) ccol = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
@@ -142,6 +144,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             v0 = v0 + c;
             v1 = v1 + c;
         }
+        if (kIn == kInCorrect) {
+            float e0, e1;
+            ld2(a.corr + (size_t)tw * plane + col, e0, e1);
+            v0 = v0 + cscale * (T)e0;
+            v1 = v1 + cscale * (T)e1;
+        }
     };
     auto load_f = [&](int t, T& v0, T& v1) {
         int tw = wrap3(t, nz);
@@ -150,7 +158,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     // rho (finest level) or the stored low z-face coefficient of plane t
     auto load_q = [&](int t, T& v0, T& v1) {
         int tw = wrap3(t, nz);
-        if (kRho) ld2((const T*)a.rho + (size_t)tw * plane + col, v0, v1);
+        if (kRho) ld2(a.rho + (size_t)tw * plane + col, v0, v1);
         else ld2(a.bz + (size_t)tw * plane + col, v0, v1);
     };
     // low z-face coefficient of plane t from the queue values of planes t-1, t
@@ -311,7 +319,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         // 3. red update at plane t on the tile plus one ring
         const int lxr = lx0 + rsel;
         T Rcur = rsel ? Pc1 : Pc0;
-        if (!kRR && (rsel ? r1c1 : r1c0)) {
+        if (!kRR && !kIR && (rsel ? r1c1 : r1c0)) {
             const T bxl = sbx[s_t][ly][lxr], bxh = sbx[s_t][ly][lxr + 1];
             const T byl = sby[s_t][ly][lxr], byh = sby[s_t][ly + 1][lxr];
             const T bzl = rsel ? bc1 : bc0, bzh = rsel ? bp1 : bp0;
@@ -328,7 +336,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + bzh;
             Rcur = qdiv(num - h2 * (rsel ? Fc1 : Fc0), den);
         }
-        if (!kRR) sR[(t + 4) & 1][ly][lxr] = Rcur;
+        if (!kRR && !kIR) sR[(t + 4) & 1][ly][lxr] = Rcur;
         if (kNorm && t >= z0 && t < z1 && writes) {
             resid_in(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
             resid_in(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
@@ -337,7 +345,21 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             sR[0][ly][lx0] = resid_at(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
             sR[0][ly][lx0 + 1] = resid_at(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
         }
+        if (kIR && t >= z0 && t < z1 && writes) {
+            const T r0 = resid_at(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
+            const T r1 = resid_at(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
+            const double d0 = (double)r0, d1 = (double)r1;
+            if (!isfinite(d0)) nbad += 1.0;
+            if (!isfinite(d1)) nbad += 1.0;
+            nrm2 += d0 * d0;
+            nrm2 += d1 * d1;
+            nmax = fmax(nmax, fmax(fabs(d0), fabs(d1)));
+            const size_t o = (size_t)t * plane + col;
+            st2(a.phi_out + o, Pc0, Pc1);
+            st2(a.r32 + o, (float)(a.rscale * d0), (float)(a.rscale * d1));
+        }
         __syncthreads();
+        if (kIR) return;
         if (kRR) {
             if (t >= z0 && t < z1 && writes && rrow) {
                 if (((t - z0) & 1) == 0) racc = T(0);
@@ -386,7 +408,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         step(t + 1, B);
     }
     if (t <= z1) step(t, A);
-    if (kNorm) {
+    if (kNorm || kIR) {
         // fixed-order block reduction into this tile's partial row
         __shared__ double red[3][256];
         const int nt = blockDim.x;
@@ -467,14 +489,11 @@ hipError_t launch_t(const SweepArgs<T>& a0, int tzc, hipStream_t st, int* nblock
 template <typename T, int TX, int TY>
 hipError_t launch_mode(const SweepArgs<T>& a, bool use_rho, int in_mode, int tzc, hipStream_t st) {
     if (use_rho) {
-        if constexpr (std::is_same<T, double>::value) {
-            switch (in_mode) {
-                case kInZero: return launch_t<T, TX, TY, true, kInZero>(a, tzc, st);
-                case kInPlain: return launch_t<T, TX, TY, true, kInPlain>(a, tzc, st);
-                default: return launch_t<T, TX, TY, true, kInProlong>(a, tzc, st);
-            }
+        switch (in_mode) {
+            case kInZero: return launch_t<T, TX, TY, true, kInZero>(a, tzc, st);
+            case kInPlain: return launch_t<T, TX, TY, true, kInPlain>(a, tzc, st);
+            default: return launch_t<T, TX, TY, true, kInProlong>(a, tzc, st);
         }
-        return hipErrorInvalidValue;
     }
     switch (in_mode) {
         case kInZero: return launch_t<T, TX, TY, false, kInZero>(a, tzc, st);
@@ -570,18 +589,34 @@ hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, h
     }
 }
 
-hipError_t launch_resid_restrict_tiled(const SweepArgs<double>& a, int cfg, hipStream_t st) {
+template <typename T>
+hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, int cfg, hipStream_t st) {
     const SweepCfg& c = kSweepCfgs[cfg];
     if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
     constexpr int R = kOpResidRestrict;
     switch (cfg) {
-        case 0: return launch_t<double, 32, 8, true, kInPlain, R>(a, c.tz, st);
-        case 1: return launch_t<double, 32, 8, true, kInPlain, R>(a, c.tz, st);
-        case 2: return launch_t<double, 64, 8, true, kInPlain, R>(a, c.tz, st);
-        case 3: return launch_t<double, 32, 16, true, kInPlain, R>(a, c.tz, st);
-        case 4: return launch_t<double, 64, 4, true, kInPlain, R>(a, c.tz, st);
-        case 5: return launch_t<double, 32, 4, true, kInPlain, R>(a, c.tz, st);
-        default: return launch_t<double, 32, 8, true, kInPlain, R>(a, c.tz, st);
+        case 0: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
+        case 1: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
+        case 2: return launch_t<T, 64, 8, true, kInPlain, R>(a, c.tz, st);
+        case 3: return launch_t<T, 32, 16, true, kInPlain, R>(a, c.tz, st);
+        case 4: return launch_t<T, 64, 4, true, kInPlain, R>(a, c.tz, st);
+        case 5: return launch_t<T, 32, 4, true, kInPlain, R>(a, c.tz, st);
+        default: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
+    }
+}
+
+hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
+    constexpr int R = kOpRefine, I = kInCorrect;
+    switch (cfg) {
+        case 0: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
+        case 1: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
+        case 2: return launch_t<double, 64, 8, true, I, R>(a, c.tz, st, nparts);
+        case 3: return launch_t<double, 32, 16, true, I, R>(a, c.tz, st, nparts);
+        case 4: return launch_t<double, 64, 4, true, I, R>(a, c.tz, st, nparts);
+        case 5: return launch_t<double, 32, 4, true, I, R>(a, c.tz, st, nparts);
+        default: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
     }
 }
 
@@ -644,6 +679,8 @@ template bool sweep_fusable<double>(int, int, int);
 template bool sweep_fusable<float>(int, int, int);
 template hipError_t launch_sweep<double>(const SweepArgs<double>&, bool, int, int, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs<float>&, bool, int, int, hipStream_t);
+template hipError_t launch_resid_restrict_tiled<double>(const SweepArgs<double>&, int, hipStream_t);
+template hipError_t launch_resid_restrict_tiled<float>(const SweepArgs<float>&, int, hipStream_t);
 template hipError_t launch_sweep_multi<double>(const SweepArgs<double>*, const int*, int, int, bool, int, int, int,
                                                hipStream_t);
 template hipError_t launch_sweep_multi<float>(const SweepArgs<float>*, const int*, int, int, bool, int, int, int,

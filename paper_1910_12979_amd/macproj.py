@@ -98,6 +98,7 @@ def lib():
         L.serve_destroy.argtypes = [vp]
         L.mg_tune_sweep.argtypes = [i32]
         L.mg_autotune.argtypes = [vp, i32, vp]
+        L.mg_sweep_config.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -235,6 +236,12 @@ class Hierarchy:
     def mg_autotune(self, reps=10, stream=None):
         """Pick the fastest sweep tile configuration per level shape."""
         _check(lib().mg_autotune(self._h, int(reps), _stream(stream)))
+
+    def sweep_config(self, level):
+        """Fused-sweep tile (tx, ty, tz, index) of a level, or None if unfused."""
+        t = (ctypes.c_int32 * 4)()
+        _check(lib().mg_sweep_config(self._h, level, t))
+        return None if t[3] < 0 else (t[0], t[1], t[2], t[3])
 
     def level_info(self, level):
         dims = (ctypes.c_int32 * 3)()
