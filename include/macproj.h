@@ -207,10 +207,10 @@ int serve_counters(void* server, double out[6]);
 /* Finish all tickets and release the server. */
 int serve_destroy(void* server);
 
-/* Tuning: force fused-sweep tile configuration cfg (0..7: 32x8x32, 32x8x64,
- * 64x8x32, 32x16x32, 64x4x64, 32x4x64, 32x8x16, 32x8x8 cells per workgroup
- * tile x planes per chunk) on every level that fits it; -1 restores the
- * per-shape default.
+/* Tuning: force fused-sweep tile configuration cfg (0..8: 32x8x32, 32x8x64,
+ * 64x8x32, 32x16x32, 64x4x64, 32x4x64, 32x8x16, 32x8x8, 64x8x64 cells per
+ * workgroup tile x planes per chunk) on every level that fits it; -1 restores
+ * the per-shape default.
  * Process-wide; results do not depend on it (the sweep is exact per cell). */
 int mg_tune_sweep(int32_t cfg);
 
@@ -220,6 +220,15 @@ int mg_tune_sweep(int32_t cfg);
  * coefficients (mg_set_coefficients or mac_project); overwrites the
  * hierarchy's own level arrays, never caller data.  Blocks until done. */
 int mg_autotune(mg_handle h, int32_t reps, void* stream);
+
+/* Replayable cycles: with enable = 1 (the default) an FP64 solve captures
+ * one V-cycle plus the following residual-norm sweep as a hipGraph on the
+ * hierarchy's own stream the first time it needs it, and replays it for the
+ * later cycles and solves whose buffers, coefficient source, sweep counts
+ * and tile choices match (at most two captures are kept per hierarchy).
+ * Results are identical either way; 0 runs every cycle as separate launches
+ * on the caller's stream. */
+int mg_set_graphs(mg_handle h, int32_t enable);
 
 /* Fused-sweep tile used on level l of h: tile[0..2] = cells per workgroup
  * tile in x, y and planes per z-chunk, tile[3] = configuration index (as for

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "mg_internal.h"
 
@@ -38,6 +39,17 @@ struct mg_hierarchy {
     double* b0e_own = nullptr;
     mg::RhoArgs rho{};            // finest-level coefficient source of the current solve
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // Replayable V-cycles (FP64 solve): one cycle plus the next residual
+    // norm captured as a hipGraph, keyed by everything baked into it.
+    bool graphs_on = true;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev = nullptr;
+    struct CycleGraph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<uintptr_t> key;                 // pointers and settings at capture
+        std::vector<double*> post_phi, post_phi2;   // level phi buffers after the cycle
+    } graph[2];
+    int graph_next = 0;                             // slot replaced by the next capture
 };
 
 namespace mg {

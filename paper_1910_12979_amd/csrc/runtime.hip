@@ -218,6 +218,10 @@ int destroy(mg_hierarchy* H) {
     if (H->host) hipHostFree(H->host);
     hipEventDestroy(H->ev0);
     hipEventDestroy(H->ev1);
+    for (auto& g : H->graph)
+        if (g.exec) hipGraphExecDestroy(g.exec);
+    if (H->gstream) hipStreamDestroy(H->gstream);
+    if (H->gev) hipEventDestroy(H->gev);
     delete H;
     return MG_OK;
 }
@@ -439,13 +443,13 @@ double model_bytes(const mg_params& p, int cycles, int mixed) {
     return N * (192.0 + cycles * 199.0);
 }
 
-// Solve on level 0 after f (mean-removed) and the coefficients are in place.
 // Residual norm of the current finest-level phi measured by a speculative
 // first pre-sweep: the sweep reads phi, f and rho anyway, so it also writes
-// per-tile partial sums of r = f - L phi(input).  The sweep is out of place;
-// its output is taken (buffers swapped) only if another cycle follows.
-static int speculative_sweep_norm(mg_hierarchy* H, bool* taken_out, double fnorm, double* rel,
-                                  double* nonfinite, hipStream_t st) {
+// per-tile partial sums of r = f - L phi(input).  The sweep is out of place
+// (into phi2); its output is taken (buffers swapped) only if another cycle
+// follows.  Enqueues the sweep, the reduction and the copy of the norm row to
+// pinned host memory; the caller synchronises.
+static int enqueue_sweep_norm(mg_hierarchy* H, hipStream_t st) {
     Level& L0 = H->lev[0];
     SweepArgs<double> a{};
     a.nx = L0.nx;
@@ -466,12 +470,103 @@ static int speculative_sweep_norm(mg_hierarchy* H, bool* taken_out, double fnorm
     HIPCHK(launch_sweep_norm(a, sweep_config_for(L0.nx, L0.ny, L0.nz, true), &np, st));
     int rc = reduce_to(H, np, kSlotRes, st);
     if (rc) return rc;
-    rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
-    if (rc) return rc;
-    const double* r = H->host + kSlotRes * kReduceWidth;
-    *rel = std::sqrt(r[0]) / fnorm;
-    *nonfinite = r[3];
-    *taken_out = false;
+    HIPCHK(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
+                          kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
+    return MG_OK;
+}
+
+// Everything a captured cycle bakes in: coefficient source, sweep counts,
+// tile choices and the level buffers it starts from.
+static std::vector<uintptr_t> graph_key(const mg_hierarchy* H) {
+    std::vector<uintptr_t> k;
+    k.push_back((uintptr_t)H->rho.rho);
+    k.push_back((uintptr_t)H->rho.b0c);
+    k.push_back((uintptr_t)H->rho.b0e);
+    k.push_back((uintptr_t)H->p.pre_sweeps);
+    k.push_back((uintptr_t)H->p.post_sweeps);
+    k.push_back((uintptr_t)sweep_tune_epoch());
+    for (int l = 0; l < H->nlev; ++l) {
+        k.push_back((uintptr_t)H->lev[l].d.phi);
+        k.push_back((uintptr_t)H->lev[l].phi2_d);
+    }
+    return k;
+}
+
+// A captured cycle is replayable when every level's phi buffers end each
+// cycle where they started (an even number of out-of-place sweeps per cycle
+// on every level, the taken speculative sweep included).
+static bool graphs_usable(const mg_hierarchy* H) {
+    return H->graphs_on && H->p.precision == MG_FP64 && ((H->p.pre_sweeps + H->p.post_sweeps) % 2) == 0;
+}
+
+// One V-cycle after a taken speculative sweep, then the next speculative
+// sweep-norm, with the norm row on the host when this returns.  Replays a
+// captured hipGraph of exactly this work when one matches the current
+// state, else captures one (or runs eagerly when graphs are off).  Graph
+// work runs on the hierarchy's own stream (the caller's may be the legacy
+// stream, which cannot be captured); *on_graph records that the caller's
+// stream must later wait for it.
+static int cycle_and_norm(mg_hierarchy* H, hipStream_t st, bool* on_graph) {
+    if (!graphs_usable(H)) {
+        int rc = vcycle<double>(H, 0, st, 1);
+        if (rc) return rc;
+        rc = enqueue_sweep_norm(H, st);
+        if (rc) return rc;
+        HIPCHK(hipStreamSynchronize(st));
+        return MG_OK;
+    }
+    if (!H->gstream) {
+        HIPCHK(hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&H->gev, hipEventDisableTiming));
+    }
+    hipStream_t gs = H->gstream;
+    if (!*on_graph) {                       // order after the caller's earlier work
+        HIPCHK(hipEventRecord(H->gev, st));
+        HIPCHK(hipStreamWaitEvent(gs, H->gev, 0));
+        *on_graph = true;
+    }
+    const std::vector<uintptr_t> key = graph_key(H);
+    mg_hierarchy::CycleGraph* g = nullptr;
+    for (auto& c : H->graph)
+        if (c.exec && c.key == key) g = &c;
+    if (!g) {
+        g = &H->graph[H->graph_next];
+        H->graph_next = (H->graph_next + 1) % 2;
+        if (g->exec) {
+            hipGraphExecDestroy(g->exec);
+            g->exec = nullptr;
+        }
+        HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+        int rc = vcycle<double>(H, 0, gs, 1);
+        if (rc == MG_OK) rc = enqueue_sweep_norm(H, gs);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(gs, &graph);
+        if (rc) {
+            if (graph) hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g->exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate", __LINE__);
+        }
+        g->key = key;
+        g->post_phi.resize(H->nlev);
+        g->post_phi2.resize(H->nlev);
+        for (int l = 0; l < H->nlev; ++l) {         // capture left the host pointers as after the cycle
+            g->post_phi[l] = H->lev[l].d.phi;
+            g->post_phi2[l] = H->lev[l].phi2_d;
+        }
+    } else {
+        for (int l = 0; l < H->nlev; ++l) {
+            H->lev[l].d.phi = g->post_phi[l];
+            H->lev[l].phi2_d = g->post_phi2[l];
+        }
+    }
+    HIPCHK(hipGraphLaunch(g->exec, gs));
+    HIPCHK(hipStreamSynchronize(gs));
     return MG_OK;
 }
 
@@ -580,32 +675,37 @@ static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStrea
         status = solve_level0_mixed_fused(H, fnorm, &cycles, &rel, rec, st);
         if (status != MG_OK && status != MG_ERR_NOT_CONVERGED && status != MG_ERR_NONFINITE) return status;
     } else if (fused_norm) {
+        bool on_graph = false;
         while (status == MG_ERR_NOT_CONVERGED) {
-            int pre_done = 0;
-            if (cycles > 0) {
-                bool taken = false;
-                double nonfin = 0.0;
-                int rc = speculative_sweep_norm(H, &taken, fnorm, &rel, &nonfin, st);
-                if (rc) return rc;
-                record(rel);
-                if (nonfin > 0.0 || !std::isfinite(rel)) {
-                    status = MG_ERR_NONFINITE;
-                    set_error("non-finite residual during the solve");
-                    break;
-                }
-                if (rel <= H->p.rtol) {
-                    status = MG_OK;
-                    break;
-                }
-                if (cycles >= H->p.max_cycles) break;
-                std::swap(L0.d.phi, L0.phi2_d);     // keep the sweep: it is the next cycle's first
-                pre_done = 1;
-            } else if (H->p.max_cycles == 0) {
-                break;
+            int rc;
+            if (cycles == 0) {
+                if (H->p.max_cycles == 0) break;
+                rc = vcycle<double>(H, 0, st, 0);
+                if (rc == MG_OK) rc = enqueue_sweep_norm(H, st);
+                if (rc == MG_OK && hipStreamSynchronize(st) != hipSuccess) rc = MG_ERR_HIP;
+            } else {
+                std::swap(L0.d.phi, L0.phi2_d);     // keep the sweep: it is this cycle's first
+                rc = cycle_and_norm(H, st, &on_graph);
             }
-            int rc = vcycle<double>(H, 0, st, pre_done);
             if (rc) return rc;
             ++cycles;
+            const double* r = H->host + kSlotRes * kReduceWidth;
+            rel = std::sqrt(r[0]) / fnorm;
+            record(rel);
+            if (r[3] > 0.0 || !std::isfinite(rel)) {
+                status = MG_ERR_NONFINITE;
+                set_error("non-finite residual during the solve");
+                break;
+            }
+            if (rel <= H->p.rtol) {
+                status = MG_OK;
+                break;
+            }
+            if (cycles >= H->p.max_cycles) break;
+        }
+        if (on_graph) {                              // the caller's stream continues after the graph work
+            HIPCHK(hipEventRecord(H->gev, H->gstream));
+            HIPCHK(hipStreamWaitEvent(st, H->gev, 0));
         }
     } else {
         if (mixed) {
@@ -1043,6 +1143,15 @@ int mg_tune_sweep(int32_t cfg) {
     }
     sweep_force_config(cfg);
     g_forced_cfg_mirror = cfg;
+    return MG_OK;
+}
+
+int mg_set_graphs(mg_handle h, int32_t enable) {
+    if (!h) {
+        set_error("null handle");
+        return MG_ERR_INVALID_ARG;
+    }
+    h->graphs_on = enable != 0;
     return MG_OK;
 }
 

@@ -16,9 +16,10 @@ constexpr int kSweepTZMax = 64;  // largest z-chunk
 struct SweepCfg {
     int tx, ty, tz;
 };
-constexpr int kNumSweepCfg = 8;
+constexpr int kNumSweepCfg = 9;
 constexpr SweepCfg kSweepCfgs[kNumSweepCfg] = {
-    {32, 8, 32}, {32, 8, 64}, {64, 8, 32}, {32, 16, 32}, {64, 4, 64}, {32, 4, 64}, {32, 8, 16}, {32, 8, 8}};
+    {32, 8, 32}, {32, 8, 64}, {64, 8, 32}, {32, 16, 32}, {64, 4, 64},
+    {32, 4, 64}, {32, 8, 16}, {32, 8, 8},  {64, 8, 64}};
 
 enum { kInZero = 0, kInPlain = 1, kInProlong = 2, kInCorrect = 3 };
 enum { kOpSweep = 0, kOpSweepNorm = 1, kOpResidRestrict = 2, kOpRefine = 3 };
@@ -95,5 +96,8 @@ void sweep_record_tuned(int nx, int ny, int nz, bool rho, int cfg);
 int sweep_tuned_count();
 // Force one configuration for every level that fits it (-1 restores the default).
 void sweep_force_config(int cfg);
+// Incremented whenever a forced or tuned configuration changes (captured
+// launches are only valid for the epoch they were recorded in).
+unsigned sweep_tune_epoch();
 
 }  // namespace mg

@@ -516,14 +516,25 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tuned;
+unsigned g_tune_epoch = 0;
 
 }  // namespace
 
-void sweep_force_config(int cfg) { g_forced_cfg = cfg; }
+void sweep_force_config(int cfg) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_forced_cfg = cfg;
+    ++g_tune_epoch;
+}
 
 void sweep_record_tuned(int nx, int ny, int nz, bool rho, int cfg) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[TuneKey{nx, ny, nz, rho ? 1 : 0}] = cfg;
+    ++g_tune_epoch;
+}
+
+unsigned sweep_tune_epoch() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune_epoch;
 }
 
 int sweep_tuned_count() {
@@ -567,6 +578,7 @@ hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cf
         case 0: return launch_mode<T, 32, 8>(a, use_rho, in_mode, c.tz, st);
         case 1: return launch_mode<T, 32, 8>(a, use_rho, in_mode, c.tz, st);
         case 2: return launch_mode<T, 64, 8>(a, use_rho, in_mode, c.tz, st);
+        case 8: return launch_mode<T, 64, 8>(a, use_rho, in_mode, c.tz, st);
         case 3: return launch_mode<T, 32, 16>(a, use_rho, in_mode, c.tz, st);
         case 4: return launch_mode<T, 64, 4>(a, use_rho, in_mode, c.tz, st);
         case 5: return launch_mode<T, 32, 4>(a, use_rho, in_mode, c.tz, st);
@@ -582,6 +594,7 @@ hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, h
         case 0: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
         case 1: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
         case 2: return launch_t<double, 64, 8, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 8: return launch_t<double, 64, 8, true, kInPlain, N>(a, c.tz, st, nparts);
         case 3: return launch_t<double, 32, 16, true, kInPlain, N>(a, c.tz, st, nparts);
         case 4: return launch_t<double, 64, 4, true, kInPlain, N>(a, c.tz, st, nparts);
         case 5: return launch_t<double, 32, 4, true, kInPlain, N>(a, c.tz, st, nparts);
@@ -598,6 +611,7 @@ hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, int cfg, hipStream
         case 0: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
         case 1: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
         case 2: return launch_t<T, 64, 8, true, kInPlain, R>(a, c.tz, st);
+        case 8: return launch_t<T, 64, 8, true, kInPlain, R>(a, c.tz, st);
         case 3: return launch_t<T, 32, 16, true, kInPlain, R>(a, c.tz, st);
         case 4: return launch_t<T, 64, 4, true, kInPlain, R>(a, c.tz, st);
         case 5: return launch_t<T, 32, 4, true, kInPlain, R>(a, c.tz, st);
@@ -613,6 +627,7 @@ hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipSt
         case 0: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
         case 1: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
         case 2: return launch_t<double, 64, 8, true, I, R>(a, c.tz, st, nparts);
+        case 8: return launch_t<double, 64, 8, true, I, R>(a, c.tz, st, nparts);
         case 3: return launch_t<double, 32, 16, true, I, R>(a, c.tz, st, nparts);
         case 4: return launch_t<double, 64, 4, true, I, R>(a, c.tz, st, nparts);
         case 5: return launch_t<double, 32, 4, true, I, R>(a, c.tz, st, nparts);

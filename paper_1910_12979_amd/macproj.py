@@ -99,6 +99,7 @@ def lib():
         L.mg_tune_sweep.argtypes = [i32]
         L.mg_autotune.argtypes = [vp, i32, vp]
         L.mg_sweep_config.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.mg_set_graphs.argtypes = [vp, i32]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -236,6 +237,10 @@ class Hierarchy:
     def mg_autotune(self, reps=10, stream=None):
         """Pick the fastest sweep tile configuration per level shape."""
         _check(lib().mg_autotune(self._h, int(reps), _stream(stream)))
+
+    def set_graphs(self, enable: bool):
+        """Replay captured V-cycles (default on) or launch every cycle eagerly."""
+        _check(lib().mg_set_graphs(self._h, 1 if enable else 0))
 
     def sweep_config(self, level):
         """Fused-sweep tile (tx, ty, tz, index) of a level, or None if unfused."""

@@ -230,6 +230,92 @@ def test_step_fused_down_up_match_separate(mp):
     assert rel(_get(H, 0, "phi"), OH.get(0, "phi")) <= 1e-13
 
 
+def test_every_tile_config_gives_the_same_sweep(mp):
+    """Each fused-sweep tile configuration (forced through mg_tune_sweep) must
+    give the default configuration's sweeps and residual+restriction bit for
+    bit (the update of a cell does not depend on the tiling), on a shape with
+    ragged tiles in x, y and z, on the rho level and a stored-coefficient one;
+    the default result itself is checked against the oracle."""
+    prob = I.make_problem((96, 40, 48), H=0.2, rho_noise=0.1, seed=15, dx=1 / 96)
+    H, OH = _step_setup(mp, prob)
+    rng = np.random.default_rng(10)
+    phi0 = rng.standard_normal((48, 40, 96))
+    f0 = rng.standard_normal((48, 40, 96))
+    f0 -= f0.mean()
+    e1 = rng.standard_normal((24, 20, 48))
+
+    def run():
+        _put(H, 0, "phi", phi0); _put(H, 0, "f", f0)
+        H.level_step(0, "down", 2)
+        out = [_get(H, 0, "phi"), _get(H, 1, "f")]
+        _put(H, 1, "phi", e1)
+        H.level_step(1, "smooth", 3)
+        out.append(_get(H, 1, "phi"))
+        return out
+
+    base = run()
+    OH.set(0, "phi", phi0); OH.set(0, "f", f0)
+    OH.smooth(0, 2); OH.resid_restrict(0)
+    assert rel(base[0], OH.get(0, "phi")) <= 1e-13
+    assert rel(base[1], OH.get(1, "f")) <= 1e-13
+    try:
+        for cfg in range(9):
+            mp.mg_tune_sweep(cfg)
+            got = run()
+            for a, b in zip(got, base):
+                assert np.array_equal(a, b), cfg
+    finally:
+        mp.mg_tune_sweep(-1)
+
+
+def test_graph_replays_match_eager(mp):
+    """Solves whose later cycles replay a captured hipGraph give the eager
+    solve's results bit for bit: over several solves in a row (replays across
+    solves, with eager work in between), for a second problem (new buffers:
+    a new capture), with V(2,1) (odd sweep count: no capture) and with a
+    forced tile configuration (a new capture)."""
+    probs = [I.make_problem((64, 48, 32), H=0.15, seed=41),
+             I.make_problem((64, 48, 32), H=0.3, seed=42, rtol=1e-9)]
+    He = mp.Hierarchy(mp.params_of(probs[0]))
+    He.set_graphs(False)
+    Hg = mp.Hierarchy(mp.params_of(probs[0]))
+
+    def solve(H, prob):
+        d = mp.to_device(prob)
+        st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+        torch.cuda.synchronize()
+        return st, {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+
+    def check(prob):
+        st0, out0 = solve(He, prob)
+        for _ in range(3):
+            st1, out1 = solve(Hg, prob)
+            assert st1["cycles"] == st0["cycles"] and st1["rel_resid"] == st0["rel_resid"]
+            assert st1["hist"] == st0["hist"]
+            assert same_out(out1, out0)
+        return st0
+
+    try:
+        st = check(probs[0])
+        assert st["cycles"] >= 4 and st["status_name"] == "OK"
+        check(probs[1])
+        for H in (He, Hg):
+            H.set_params(mp.make_params((64, 48, 32), 1 / 64, post_sweeps=1))
+        check(probs[0])
+        for H in (He, Hg):
+            H.set_params(mp.params_of(probs[0]))
+        mp.mg_tune_sweep(0)
+        check(probs[0])
+    finally:
+        mp.mg_tune_sweep(-1)
+        He.close()
+        Hg.close()
+
+
+def same_out(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("phi", "u", "v", "w"))
+
+
 def test_step_vcycle(mp):
     prob = I.make_problem(32, H=0.1, seed=14)
     H, OH = _step_setup(mp, prob)
@@ -280,6 +366,22 @@ def test_mixed_precision_64(mp):
     prob = I.make_problem(64, H=0.15, rho_noise=0.05, seed=22)
     st, out = run_gpu(mp, prob, precision="mixed")
     check_against_definition(prob, st, out)
+
+
+@pytest.mark.parametrize("shape,per", [
+    ((40, 24, 56), (True, True, False)),     # ragged tiles in x, y and z
+    ((64, 32, 48), (False, False, False)),   # walls everywhere
+    ((32, 16, 32), (True, True, True)),      # fully periodic
+    ((6, 10, 14), (True, True, False)),      # below the fused sweep's minimum tile
+])
+def test_mixed_precision_shapes(mp, shape, per):
+    """Mixed precision (FP32 cycles, FP64 refinement) against the exact
+    discrete solution, and its iteration count against the FP64 cycles."""
+    prob = I.make_problem(shape, H=0.2, rho_noise=0.05, seed=31, periodic=per)
+    st, out = run_gpu(mp, prob, precision="mixed")
+    check_against_definition(prob, st, out)
+    st64, _ = run_gpu(mp, prob)
+    assert st["cycles"] <= st64["cycles"] + 2, (st["cycles"], st64["cycles"])
 
 
 def test_mixed_precision_512_full_size(mp):
