@@ -52,7 +52,8 @@ SWEEP_KERNEL_BYTES_PER_CELL = 32.0
 # for the sweep source it was taken on (SHA-1 of the files below) and tile.
 SWEEP_SOURCES = ("paper_1910_12979_amd/csrc/sweep.hip", "paper_1910_12979_amd/csrc/sweep.h",
                  "paper_1910_12979_amd/csrc/devmath.h")
-SWEEP_TRAFFIC = None   # {"sha1": ..., "tile": [tx, ty, tz], "n": 256, "read": B, "write": B}
+SWEEP_TRAFFIC = {"sha1": "9c812f20e3b20c99c22ab9b015087119ce8d7978", "tile": [64, 8, 32], "n": 256,
+                 "read": 470919155, "write": 134217832}
 
 
 def percentile(xs, q):
