@@ -230,6 +230,12 @@ int mg_autotune(mg_handle h, int32_t reps, void* stream);
  * on the caller's stream. */
 int mg_set_graphs(mg_handle h, int32_t enable);
 
+/* Bottom of the V-cycle: with enable = 1 (the default) the levels below the
+ * ones the fused sweep covers (when their phi and f fit in 88 KB of LDS) run
+ * as one 1024-thread workgroup per V-cycle instead of one launch per step
+ * and level.  Results are identical either way. */
+int mg_set_bottom(mg_handle h, int32_t enable);
+
 /* Fused-sweep tile used on level l of h: tile[0..2] = cells per workgroup
  * tile in x, y and planes per z-chunk, tile[3] = configuration index (as for
  * mg_tune_sweep).  All four are -1 for a level the fused sweep does not cover

@@ -327,34 +327,51 @@ int multi_norm_sweep(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st)
 // One V-cycle for every job in `jobs` (each at its own depth).  pre_done[i]
 // finest-level pre-sweeps were already run by the speculative norm sweep.
 int multi_vcycle(std::vector<mg_hierarchy*>& hs, const std::vector<int>& pre_done, Staging& S, hipStream_t st) {
+    // levels each problem runs level by level: down to its bottom-solver
+    // level, else down to (excluding) its coarsest
+    std::vector<int> stop(hs.size());
     int lmax = 0;
-    for (auto* H : hs) lmax = std::max(lmax, H->nlev);
-    for (int l = 0; l + 1 < lmax; ++l) {
+    for (size_t i = 0; i < hs.size(); ++i) {
+        const int b = bottom_start<double>(hs[i]);
+        stop[i] = b > 0 ? b : hs[i]->nlev - 1;
+        lmax = std::max(lmax, stop[i]);
+    }
+    for (int l = 0; l < lmax; ++l) {
         std::vector<Item> items;
         for (size_t i = 0; i < hs.size(); ++i) {
             mg_hierarchy* H = hs[i];
-            if (l + 1 >= H->nlev) continue;
+            if (l >= stop[i]) continue;
             items.push_back(Item{H, l, H->p.pre_sweeps - (l == 0 ? pre_done[i] : 0)});
         }
-        if (l == 0) {
-            // finest level: plain input; the rest of the levels start from zero
-            std::vector<Item> a;
-            for (auto& it : items) a.push_back(it);
-            int rc = multi_smooth(a, kInPlain, S, st);
-            if (rc) return rc;
-        } else {
-            int rc = multi_smooth(items, kInZero, S, st);
-            if (rc) return rc;
-        }
-        int rc = multi_resid_restrict(items, S, st);
+        // finest level: plain input; the other levels start from zero
+        int rc = multi_smooth(items, l == 0 ? kInPlain : kInZero, S, st);
+        if (rc) return rc;
+        rc = multi_resid_restrict(items, S, st);
         if (rc) return rc;
     }
-    int rc = multi_coarse(hs, S, st);
+    std::vector<mg_hierarchy*> direct;
+    std::vector<BottomArgs<double>> bottoms;
+    for (size_t i = 0; i < hs.size(); ++i) {
+        if (stop[i] == hs[i]->nlev - 1) {
+            direct.push_back(hs[i]);
+        } else {
+            BottomArgs<double> a;
+            bottom_args<double>(hs[i], stop[i], a);
+            bottoms.push_back(a);
+        }
+    }
+    int rc = multi_coarse(direct, S, st);
     if (rc) return rc;
-    for (int l = lmax - 2; l >= 0; --l) {
+    if (!bottoms.empty()) {
+        void* dd = nullptr;
+        rc = S.push(bottoms.data(), bottoms.size() * sizeof(BottomArgs<double>), st, &dd);
+        if (rc) return rc;
+        BHIP(launch_bottom_multi((const BottomArgs<double>*)dd, (int)bottoms.size(), st));
+    }
+    for (int l = lmax - 1; l >= 0; --l) {
         std::vector<Item> items;
-        for (auto* H : hs)
-            if (l + 1 < H->nlev) items.push_back(Item{H, l, H->p.post_sweeps});
+        for (size_t i = 0; i < hs.size(); ++i)
+            if (l < stop[i]) items.push_back(Item{hs[i], l, hs[i]->p.post_sweeps});
         rc = multi_smooth(items, kInProlong, S, st);
         if (rc) return rc;
     }

@@ -52,6 +52,39 @@ struct RhoArgs {
     int px, py, pz;
 };
 
+// ---- bottom of the V-cycle in one workgroup (bottom.hip) -------------------
+// Levels below the fused-sweep ones, from the first such level (phi = 0, f
+// given) down to the coarsest and back, with phi and f of every bottom level
+// in LDS.  Same per-cell arithmetic as the per-level kernels.
+constexpr int kMaxBottomLevels = 8;
+constexpr size_t kBottomLdsBytes = 88 * 1024;   // phi and f of every bottom level
+
+template <typename T>
+struct BottomLevel {
+    int nx, ny, nz;
+    int off;            // LDS offset (elements): phi at off, f at off + nx*ny*nz
+    T h2;
+    const T* bx;        // stored low-face coefficients (global)
+    const T* by;
+    const T* bz;
+};
+
+template <typename T>
+struct BottomArgs {
+    int nlev;           // bottom levels; the last one is solved directly
+    int pre, post;      // sweeps before / after the coarse correction
+    const double* minv; // inverse of the coarsest-level matrix
+    const T* f;         // right-hand side of the first bottom level (global)
+    T* phi;             // its phi (global), written
+    BottomLevel<T> lev[kMaxBottomLevels];
+};
+
+template <typename T>
+hipError_t launch_bottom(const BottomArgs<T>& a, hipStream_t st);
+// One workgroup per problem; d is device memory.
+template <typename T>
+hipError_t launch_bottom_multi(const BottomArgs<T>* d, int nprob, hipStream_t st);
+
 // ---- kernel launchers (kernels.hip) ---------------------------------------
 // All launch on `stream` and return hipGetLastError().
 

@@ -42,6 +42,7 @@ struct mg_hierarchy {
     // Replayable V-cycles (FP64 solve): one cycle plus the next residual
     // norm captured as a hipGraph, keyed by everything baked into it.
     bool graphs_on = true;
+    bool bottom_on = true;      // levels below the fused ones in one workgroup launch
     hipStream_t gstream = nullptr;
     hipEvent_t gev = nullptr;
     struct CycleGraph {
@@ -63,6 +64,12 @@ int destroy(mg_hierarchy* H);
 int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
             double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st);
 double model_bytes(const mg_params& p, int cycles, int mixed);
+// First level run by the one-workgroup bottom solver (phi and f of it and of
+// every coarser level fit in its LDS), or -1.
+template <typename T>
+int bottom_start(const mg_hierarchy* H);
+template <typename T>
+void bottom_args(mg_hierarchy* H, int l, BottomArgs<T>& a);
 int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
                        const double* S, const double* u, const double* v, const double* w, hipStream_t st);
 }  // namespace mg

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "mg_internal.h"
 #include "runtime.h"
@@ -392,12 +393,71 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
     return MG_OK;
 }
 
+template <typename T>
+int bottom_start(const mg_hierarchy* H) {
+    if (!H->bottom_on) return -1;
+    int L = -1;
+    for (int l = 1; l + 1 < H->nlev; ++l) {
+        const Level& F = H->lev[l];
+        if (!sweep_fusable<T>(F.nx, F.ny, F.nz)) {
+            L = l;
+            break;
+        }
+    }
+    if (L < 0 || H->nlev - L > kMaxBottomLevels) return -1;
+    size_t bytes = 0;
+    for (int l = L; l < H->nlev; ++l) bytes += 2 * H->lev[l].N * sizeof(T);
+    return bytes <= kBottomLdsBytes ? L : -1;
+}
+
+template <typename T>
+void bottom_args(mg_hierarchy* H, int l, BottomArgs<T>& a) {
+    constexpr bool dbl = std::is_same<T, double>::value;
+    a = BottomArgs<T>{};
+    a.nlev = H->nlev - l;
+    a.pre = H->p.pre_sweeps;
+    a.post = H->p.post_sweeps;
+    a.minv = H->minv;
+    int off = 0;
+    for (int b = 0; b < a.nlev; ++b) {
+        Level& F = H->lev[l + b];
+        const LevelArrays<T>* A;
+        if constexpr (dbl) A = &F.d;
+        else A = &F.s;
+        BottomLevel<T>& v = a.lev[b];
+        v.nx = F.nx;
+        v.ny = F.ny;
+        v.nz = F.nz;
+        v.off = off;
+        v.h2 = (T)(F.h * F.h);
+        v.bx = A->bx;
+        v.by = A->by;
+        v.bz = A->bz;
+        off += 2 * (int)F.N;
+        if (b == 0) {
+            a.f = A->f;
+            a.phi = A->phi;
+        }
+    }
+}
+
+template int bottom_start<double>(const mg_hierarchy*);
+template int bottom_start<float>(const mg_hierarchy*);
+template void bottom_args<double>(mg_hierarchy*, int, BottomArgs<double>&);
+template void bottom_args<float>(mg_hierarchy*, int, BottomArgs<float>&);
+
 // V-cycle from level l (FP64 or FP32 arrays; the coarsest solve is FP64).
 // Coarse levels start from phi = 0; level 0 from its stored phi unless
 // zero_start (the mixed solve's correction cycle).
 template <typename T>
 static int vcycle(mg_hierarchy* H, int l, hipStream_t st, int pre_done = 0, bool zero_start = false) {
     Level& F = H->lev[l];
+    if (l > 0 && l == bottom_start<T>(H)) {          // this level and every coarser one in one launch
+        BottomArgs<T> a;
+        bottom_args<T>(H, l, a);
+        HIPCHK(launch_bottom<T>(a, st));
+        return MG_OK;
+    }
     if (l == H->nlev - 1) {
         if constexpr (std::is_same<T, double>::value)
             HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st));
@@ -485,6 +545,7 @@ static std::vector<uintptr_t> graph_key(const mg_hierarchy* H) {
     k.push_back((uintptr_t)H->p.pre_sweeps);
     k.push_back((uintptr_t)H->p.post_sweeps);
     k.push_back((uintptr_t)sweep_tune_epoch());
+    k.push_back((uintptr_t)H->bottom_on);
     for (int l = 0; l < H->nlev; ++l) {
         k.push_back((uintptr_t)H->lev[l].d.phi);
         k.push_back((uintptr_t)H->lev[l].phi2_d);
@@ -1143,6 +1204,15 @@ int mg_tune_sweep(int32_t cfg) {
     }
     sweep_force_config(cfg);
     g_forced_cfg_mirror = cfg;
+    return MG_OK;
+}
+
+int mg_set_bottom(mg_handle h, int32_t enable) {
+    if (!h) {
+        set_error("null handle");
+        return MG_ERR_INVALID_ARG;
+    }
+    h->bottom_on = enable != 0;
     return MG_OK;
 }
 

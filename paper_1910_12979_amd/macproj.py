@@ -100,6 +100,7 @@ def lib():
         L.mg_autotune.argtypes = [vp, i32, vp]
         L.mg_sweep_config.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.mg_set_graphs.argtypes = [vp, i32]
+        L.mg_set_bottom.argtypes = [vp, i32]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -241,6 +242,10 @@ class Hierarchy:
     def set_graphs(self, enable: bool):
         """Replay captured V-cycles (default on) or launch every cycle eagerly."""
         _check(lib().mg_set_graphs(self._h, 1 if enable else 0))
+
+    def set_bottom(self, enable: bool):
+        """Coarse levels in one workgroup launch (default on) or per-level launches."""
+        _check(lib().mg_set_bottom(self._h, 1 if enable else 0))
 
     def sweep_config(self, level):
         """Fused-sweep tile (tx, ty, tz, index) of a level, or None if unfused."""

@@ -312,6 +312,30 @@ def test_graph_replays_match_eager(mp):
         Hg.close()
 
 
+@pytest.mark.parametrize("shape,per,prec", [
+    ((32, 32, 32), (True, True, False), "fp64"),
+    ((64, 32, 48), (False, False, False), "fp64"),
+    ((64, 64, 64), (True, True, True), "mixed"),
+    ((128, 64, 32), (True, True, False), "mixed"),
+])
+def test_bottom_solver_matches_per_level_launches(mp, shape, per, prec):
+    """The one-workgroup bottom of the V-cycle gives the per-level launches'
+    solve bit for bit (same cycles, residual history, phi and U)."""
+    prob = I.make_problem(shape, H=0.2, rho_noise=0.05, seed=43, periodic=per)
+    res = []
+    for on in (False, True):
+        H = mp.Hierarchy(mp.params_of(prob, precision=prec))
+        H.set_bottom(on)
+        d = mp.to_device(prob)
+        st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+        torch.cuda.synchronize()
+        res.append((st, {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}))
+        H.close()
+    (s0, o0), (s1, o1) = res
+    assert s0["status_name"] == "OK" and s1["cycles"] == s0["cycles"] and s1["hist"] == s0["hist"]
+    assert same_out(o1, o0)
+
+
 def same_out(a, b):
     return all(np.array_equal(a[k], b[k]) for k in ("phi", "u", "v", "w"))
 
