@@ -21,6 +21,14 @@ __device__ __forceinline__ double qdiv(double x, double y) {
     return fma(r, rem, q);
 }
 
-__device__ __forceinline__ float qdiv(float x, float y) { return x / y; }
+// FP32 (the inner cycle of the mixed-precision solve, whose error the FP64
+// refinement removes): hardware reciprocal with one Newton step, then one
+// multiply; a few ulp at most instead of the correctly rounded sequence.
+__device__ __forceinline__ float qdiv(float x, float y) {
+    float r = __builtin_amdgcn_rcpf(y);
+    const float e = __builtin_fmaf(-y, r, 1.0f);
+    r = __builtin_fmaf(r, e, r);
+    return x * r;
+}
 
 }  // namespace mg

@@ -57,8 +57,9 @@ template <typename T>
 hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cfg, hipStream_t st);
 
 // Finest-level sweep of phi_in (as stored, coefficients from rho) that also
-// writes, per tile, the partial row {sum r^2, 0, max |r|, #non-finite} of
-// the residual r = f - L phi_in of its INPUT.  *nparts = rows written.
+// writes, per tile, the partial row {sum r^2, 0, 0, 0} of the residual
+// r = f - L phi_in of its INPUT (a non-finite r makes the sum non-finite).
+// *nparts = rows written.
 hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st);
 
 // Finest level (coefficients from rho): f_c = R (f - L phi), phi_c = 0, using
@@ -69,7 +70,7 @@ hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, int cfg, hipStream
 
 // Refinement step of the mixed-precision solve (finest level, FP64,
 // coefficients from rho): phi_out = phi_in + cscale * corr; per tile the
-// partial row {sum r^2, 0, max |r|, #non-finite} of r = f - L phi_out; and
+// partial row {sum r^2, 0, 0, 0} of r = f - L phi_out; and
 // r32 = (float)(rscale * r).  *nparts = rows written.
 hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st);
 

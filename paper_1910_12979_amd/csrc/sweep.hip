@@ -253,7 +253,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     T Rmm = T(0), Rm = T(0);
     // residual of phi_in (kNorm): r = f - (sum_f b (phi_nb - phi_c)) / h^2 in
     // the reference face order, for both cells of a tile pair at plane t
-    double nrm2 = 0.0, nmax = 0.0, nbad = 0.0;
+    // only the sum of squares is kept: a non-finite residual makes it non-finite
+    double nrm2 = 0.0;
     auto resid_at = [&](int c, int s_t, T pm, T pc, T pp, T bzl, T bzh, T fc) -> T {
         const int lx = lx0 + c;
         T r = sbx[s_t][ly][lx] * (sphi[ly][lx - 1] - pc);
@@ -264,11 +265,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         r = r + bzh * (pp - pc);
         return fc - r * ih2;
     };
-    auto resid_in = [&](int c, int s_t, T pm, T pc, T pp, T bzl, T bzh, T fc) {
-        const double res = (double)resid_at(c, s_t, pm, pc, pp, bzl, bzh, fc);
-        if (!isfinite(res)) nbad += 1.0;
+    auto accumulate = [&](T r) {
+        const double res = (double)r;
         nrm2 += res * res;
-        nmax = fmax(nmax, fabs(res));
     };
     // restriction (kRR): the even-row thread of each 2x2 column block sums the
     // 8 children in the reference order (x fastest, then y, then z)
@@ -319,6 +318,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         // 3. red update at plane t on the tile plus one ring
         const int lxr = lx0 + rsel;
         T Rcur = rsel ? Pc1 : Pc0;
+        T rred = T(0);                           // kNorm: residual of phi_in at the red cell
         if (!kRR && !kIR && (rsel ? r1c1 : r1c0)) {
             const T bxl = sbx[s_t][ly][lxr], bxh = sbx[s_t][ly][lxr + 1];
             const T byl = sby[s_t][ly][lxr], byh = sby[s_t][ly + 1][lxr];
@@ -334,12 +334,18 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + byh;
             den = den + bzl;
             den = den + bzh;
+            const T pin = Rcur;
             Rcur = qdiv(num - h2 * (rsel ? Fc1 : Fc0), den);
+            // the update solves den phi_new = num - h^2 f, so f - L phi_in =
+            // den (phi_in - phi_new) / h^2 (exact up to rounding)
+            if (kNorm) rred = den * (pin - Rcur) * ih2;
         }
         if (!kRR && !kIR) sR[(t + 4) & 1][ly][lxr] = Rcur;
         if (kNorm && t >= z0 && t < z1 && writes) {
-            resid_in(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
-            resid_in(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
+            accumulate(rred);
+            const int cb = 1 - rsel;             // black cell of the pair: full evaluation
+            accumulate(resid_at(cb, s_t, cb ? Pm1 : Pm0, cb ? Pc1 : Pc0, cb ? Pp1 : Pp0, cb ? bc1 : bc0,
+                                cb ? bp1 : bp0, cb ? Fc1 : Fc0));
         }
         if (kRR && t >= z0 && t < z1 && writes) {
             sR[0][ly][lx0] = resid_at(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
@@ -349,11 +355,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             const T r0 = resid_at(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
             const T r1 = resid_at(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
             const double d0 = (double)r0, d1 = (double)r1;
-            if (!isfinite(d0)) nbad += 1.0;
-            if (!isfinite(d1)) nbad += 1.0;
             nrm2 += d0 * d0;
             nrm2 += d1 * d1;
-            nmax = fmax(nmax, fmax(fabs(d0), fabs(d1)));
             const size_t o = (size_t)t * plane + col;
             st2(a.phi_out + o, Pc0, Pc1);
             st2(a.r32 + o, (float)(a.rscale * d0), (float)(a.rscale * d1));
@@ -410,49 +413,47 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     if (t <= z1) step(t, A);
     if (kNorm || kIR) {
         // fixed-order block reduction into this tile's partial row
-        __shared__ double red[3][256];
+        __shared__ double red[256];
         const int nt = blockDim.x;
-        for (int i = threadIdx.x; i < 256; i += nt) {     // every slot, also when nt < 256
-            red[0][i] = 0.0;
-            red[1][i] = 0.0;
-            red[2][i] = 0.0;
-        }
+        for (int i = threadIdx.x; i < 256; i += nt) red[i] = 0.0;   // every slot, also when nt < 256
         __syncthreads();
         for (int k = 0; k < nt; k += 256) {
-            if (threadIdx.x >= k && threadIdx.x < k + 256) {
-                const int i = threadIdx.x - k;
-                red[0][i] += nrm2;
-                red[1][i] = fmax(red[1][i], nmax);
-                red[2][i] += nbad;
-            }
+            if (threadIdx.x >= k && threadIdx.x < k + 256) red[threadIdx.x - k] += nrm2;
             __syncthreads();
         }
         for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                red[0][threadIdx.x] += red[0][threadIdx.x + w];
-                red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
-                red[2][threadIdx.x] += red[2][threadIdx.x + w];
-            }
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
         if (threadIdx.x == 0) {
             double* row = a.partials + (size_t)tile * kReduceWidth;
-            row[0] = red[0][0];
+            row[0] = red[0];
             row[1] = 0.0;
-            row[2] = red[1][0];
-            row[3] = red[2][0];
+            row[2] = 0.0;
+            row[3] = 0.0;
         }
     }
 }
 
+// The finest-level prolongation and residual-norm variants are held to 128
+// VGPRs (4 waves per SIMD), so that two 64x8-tile workgroups (7 waves each)
+// or four 32x8 ones share a CU; left alone the compiler gives them a few more
+// registers, which halves the workgroups per CU.  (Capping the stored-
+// coefficient variants too makes them spill, which costs more.)
+template <bool kRho, int kIn, int kOp>
+struct SweepWaves {
+    static constexpr int value = (kRho && (kIn == kInProlong || kOp == kOpSweepNorm)) ? 4 : 1;
+};
+#define MG_SWEEP_WAVES __attribute__((amdgpu_waves_per_eu(SweepWaves<kRho, kIn, kOp>::value)))
+
 template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
-__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep(SweepArgs<T> a) {
+__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES void k_sweep(SweepArgs<T> a) {
     sweep_body<T, TX, TY, kRho, kIn, kOp>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched form: problem p owns tiles [prefix[p], prefix[p+1]) of the launch.
 template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
-__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) void k_sweep_multi(const SweepArgs<T>* __restrict__ descs,
+__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES void k_sweep_multi(const SweepArgs<T>* __restrict__ descs,
                                                                          const int* __restrict__ prefix, int nprob) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     int lo = 0, hi = nprob;
