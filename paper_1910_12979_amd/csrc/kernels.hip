@@ -373,22 +373,26 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(int nx, int ny, int nz, T
 // of -A) and inverts it in place by Gauss-Jordan elimination (M is SPD, so
 // no pivoting is needed).  The per-cycle solve is then a mat-vec.
 // ---------------------------------------------------------------------------
+constexpr int kSetupThreads = 1024;
+constexpr int kSetupLdsN = 128;      // matrices up to this order are inverted in LDS
+
 template <bool kLds>
-__global__ __launch_bounds__(kBlock) void k_coarse_setup(int nx, int ny, int nz, double h,
-                                                         const double* __restrict__ bx,
-                                                         const double* __restrict__ by,
-                                                         const double* __restrict__ bz,
-                                                         double* __restrict__ Mg) {
-    constexpr int kLdsN = 64;
-    __shared__ double Ms[kLds ? kLdsN * kLdsN : 1];
-    __shared__ double fac[kCoarseMax];
+__global__ __launch_bounds__(kSetupThreads) void k_coarse_setup(int nx, int ny, int nz, double h,
+                                                                const double* __restrict__ bx,
+                                                                const double* __restrict__ by,
+                                                                const double* __restrict__ bz,
+                                                                double* __restrict__ Mg) {
+    __shared__ double Ms[kLds ? kSetupLdsN * kSetupLdsN : 1];
+    __shared__ double fac[kCoarseMax];      // column p before the elimination step
+    __shared__ double prow[kCoarseMax];     // row p before the elimination step
     __shared__ double shift;
     const int n = nx * ny * nz;
+    const int tid = threadIdx.x, nt = blockDim.x;
     double* M = kLds ? Ms : Mg;
     const double ih2 = 1.0 / (h * h);
-    for (int e = threadIdx.x; e < n * n; e += kBlock) M[e] = 0.0;
+    for (int e = tid; e < n * n; e += nt) M[e] = 0.0;
     __syncthreads();
-    for (int c = threadIdx.x; c < n; c += kBlock) {
+    for (int c = tid; c < n; c += nt) {
         int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
         int im = i > 0 ? i - 1 : nx - 1, ip = i < nx - 1 ? i + 1 : 0;
         int jm = j > 0 ? j - 1 : ny - 1, jp = j < ny - 1 ? j + 1 : 0;
@@ -405,33 +409,43 @@ __global__ __launch_bounds__(kBlock) void k_coarse_setup(int nx, int ny, int nz,
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double d = 0.0;
         for (int c = 0; c < n; ++c) d += M[c * n + c];
         shift = d / n;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += kBlock) M[e] += shift;
-    __syncthreads();
-    // in-place Gauss-Jordan inversion (M is SPD: no pivoting)
+    for (int e = tid; e < n * n; e += nt) M[e] += shift;
+    // In-place Gauss-Jordan inversion (M is SPD: no pivoting).  Thread tid
+    // owns column jj = tid % n of rows tid / n, tid / n + nt / n, ...; per
+    // pivot p: row p becomes row p / M_pp (with 1 / M_pp in column p), every
+    // other row i subtracts M_ip times the new row p (column p: -M_ip / M_pp).
+    const int jj = tid % n;
+    const int rstep = nt / n;
+    const int r0 = tid / n;
     for (int p = 0; p < n; ++p) {
-        const double piv = M[p * n + p];
-        __syncthreads();
-        for (int jj = threadIdx.x; jj < n; jj += kBlock)
-            M[p * n + jj] = (jj == p) ? 1.0 / piv : M[p * n + jj] / piv;
-        for (int ii = threadIdx.x; ii < n; ii += kBlock) fac[ii] = (ii == p) ? 0.0 : M[ii * n + p];
-        __syncthreads();
-        for (int ii = threadIdx.x; ii < n; ii += kBlock)
-            if (ii != p) M[ii * n + p] = 0.0;
-        __syncthreads();
-        for (int e = threadIdx.x; e < n * n; e += kBlock) {
-            const int ii = e / n, jj = e - ii * n;
-            if (ii != p) M[e] -= fac[ii] * M[p * n + jj];
+        __syncthreads();                     // previous step complete
+        for (int e = tid; e < n; e += nt) {
+            fac[e] = M[e * n + p];
+            prow[e] = M[p * n + e];
         }
         __syncthreads();
+        const double inv = 1.0 / fac[p];
+        const double np = jj == p ? inv : prow[jj] * inv;     // new row p, column jj
+        if (r0 < rstep) {
+            for (int ii = r0; ii < n; ii += rstep) {
+                if (ii == p) {
+                    M[p * n + jj] = np;
+                } else {
+                    const double old = jj == p ? 0.0 : M[ii * n + jj];
+                    M[ii * n + jj] = old - fac[ii] * np;
+                }
+            }
+        }
     }
+    __syncthreads();
     if (kLds)
-        for (int e = threadIdx.x; e < n * n; e += kBlock) Mg[e] = Ms[e];
+        for (int e = tid; e < n * n; e += nt) Mg[e] = Ms[e];
 }
 
 template <typename T>
@@ -538,6 +552,20 @@ __global__ void k_accumulate(double* __restrict__ phi, const float* __restrict__
     const double s = scale_inv[0];
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
         phi[e] = phi[e] + (double)e32[e] * s;
+}
+
+// Mixed precision, after the residual of iteration k is reduced into
+// res[0] = sum r^2: scales[0] <- scales[1] (the scale the FP32 residual now
+// holds), scales[1] <- the power of two nearest 1/rms(r) (1 for a zero or
+// non-finite residual), the scale for the next FP32 residual.
+__global__ void k_next_scale(const double* __restrict__ res, double* __restrict__ scales, double n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double rms = sqrt(res[0] / n);
+        double s = 1.0;
+        if (rms > 0.0 && isfinite(rms)) s = ldexp(1.0, -ilogb(rms));
+        scales[0] = scales[1];
+        scales[1] = s;
+    }
 }
 
 __global__ void k_scale_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t n, double s) {
@@ -685,10 +713,13 @@ hipError_t launch_resid_restrict_rho(const Shape& fine, double h, const RhoArgs&
 
 hipError_t launch_coarse_setup(const Shape& s, double h, const double* bx, const double* by,
                                const double* bz, double* minv, hipStream_t st) {
-    if (s.N() <= 64)
-        hipLaunchKernelGGL(k_coarse_setup<true>, dim3(1), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, h, bx, by, bz, minv);
+    if (s.N() > (size_t)kCoarseMax) return hipErrorInvalidValue;
+    if (s.N() <= (size_t)kSetupLdsN)
+        hipLaunchKernelGGL(k_coarse_setup<true>, dim3(1), dim3(kSetupThreads), 0, st, s.nx, s.ny, s.nz, h, bx, by, bz,
+                           minv);
     else
-        hipLaunchKernelGGL(k_coarse_setup<false>, dim3(1), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, h, bx, by, bz, minv);
+        hipLaunchKernelGGL(k_coarse_setup<false>, dim3(1), dim3(kSetupThreads), 0, st, s.nx, s.ny, s.nz, h, bx, by,
+                           bz, minv);
     return hipGetLastError();
 }
 
@@ -731,6 +762,11 @@ hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* sc
 hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const double* scale_inv,
                              hipStream_t st) {
     hipLaunchKernelGGL(k_accumulate, dim3(stream_blocks(n)), dim3(kBlock), 0, st, phi, e32, n, scale_inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_next_scale(const double* res, double* scales, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_next_scale, dim3(1), dim3(64), 0, st, res, scales, (double)n);
     return hipGetLastError();
 }
 

@@ -166,6 +166,8 @@ hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const doub
                              hipStream_t st);
 // FP32 copies of the coefficients.
 hipError_t launch_coeff_to_f32(const double* a, float* b, size_t n, hipStream_t st);
+// scales[0] <- scales[1]; scales[1] <- power of two nearest 1/rms (res[0] = sum r^2 over n)
+hipError_t launch_next_scale(const double* res, double* scales, size_t n, hipStream_t st);
 // b = (float)(s * a)
 hipError_t launch_scale_to_f32(const double* a, float* b, size_t n, double s, hipStream_t st);
 // Coarsest level in FP32 cycles: phi32 = (float) solve((double) f32).

@@ -15,6 +15,7 @@ constexpr int kSlotRhs = 0;    // {sum f, sum |f|, bad rho/beta0, #non-finite}
 constexpr int kSlotNorm = 1;   // {||f||^2 after mean removal, ...}
 constexpr int kSlotRes = 2;    // {||r||^2, -, max |r|, #non-finite}
 constexpr int kSlotPhi = 3;    // {sum phi, ...}
+constexpr int kSlotScale = 4;  // mixed precision: {scale of the FP32 residual, scale for the next}
 }  // namespace mg
 
 struct mg_hierarchy {
@@ -48,7 +49,7 @@ struct mg_hierarchy {
     struct CycleGraph {
         hipGraphExec_t exec = nullptr;
         std::vector<uintptr_t> key;                 // pointers and settings at capture
-        std::vector<double*> post_phi, post_phi2;   // level phi buffers after the cycle
+        std::vector<void*> post_phi, post_phi2;     // level phi buffers (FP64, then FP32) after it
     } graph[2];
     int graph_next = 0;                             // slot replaced by the next capture
 };

@@ -535,10 +535,12 @@ static int enqueue_sweep_norm(mg_hierarchy* H, hipStream_t st) {
     return MG_OK;
 }
 
-// Everything a captured cycle bakes in: coefficient source, sweep counts,
-// tile choices and the level buffers it starts from.
-static std::vector<uintptr_t> graph_key(const mg_hierarchy* H) {
+// Everything a captured iteration bakes in: coefficient source, sweep
+// counts, tile choices, the kind of iteration and the level buffers it
+// starts from.
+static std::vector<uintptr_t> graph_key(const mg_hierarchy* H, int kind) {
     std::vector<uintptr_t> k;
+    k.push_back((uintptr_t)kind);
     k.push_back((uintptr_t)H->rho.rho);
     k.push_back((uintptr_t)H->rho.b0c);
     k.push_back((uintptr_t)H->rho.b0e);
@@ -549,29 +551,34 @@ static std::vector<uintptr_t> graph_key(const mg_hierarchy* H) {
     for (int l = 0; l < H->nlev; ++l) {
         k.push_back((uintptr_t)H->lev[l].d.phi);
         k.push_back((uintptr_t)H->lev[l].phi2_d);
+        k.push_back((uintptr_t)H->lev[l].s.phi);
+        k.push_back((uintptr_t)H->lev[l].phi2_s);
     }
     return k;
 }
 
-// A captured cycle is replayable when every level's phi buffers end each
-// cycle where they started (an even number of out-of-place sweeps per cycle
-// on every level, the taken speculative sweep included).
+// A captured iteration is replayable when every level's phi buffers come
+// back to where they started within two iterations (an even number of
+// out-of-place sweeps per level and cycle; the finest FP64 level may swap
+// once per iteration, which two cached captures cover).
 static bool graphs_usable(const mg_hierarchy* H) {
-    return H->graphs_on && H->p.precision == MG_FP64 && ((H->p.pre_sweeps + H->p.post_sweeps) % 2) == 0;
+    return H->graphs_on && ((H->p.pre_sweeps + H->p.post_sweeps) % 2) == 0;
 }
 
-// One V-cycle after a taken speculative sweep, then the next speculative
-// sweep-norm, with the norm row on the host when this returns.  Replays a
-// captured hipGraph of exactly this work when one matches the current
+enum { kIterFp64 = 1, kIterMixed = 2 };
+
+// One solver iteration whose last step copies the norm row to pinned host
+// memory; the norm is on the host when this returns.  `enqueue` puts the
+// iteration's work on a stream and makes the host-side buffer swaps.  Replays
+// a captured hipGraph of exactly this work when one matches the current
 // state, else captures one (or runs eagerly when graphs are off).  Graph
 // work runs on the hierarchy's own stream (the caller's may be the legacy
 // stream, which cannot be captured); *on_graph records that the caller's
 // stream must later wait for it.
-static int cycle_and_norm(mg_hierarchy* H, hipStream_t st, bool* on_graph) {
+template <typename F>
+static int run_iteration(mg_hierarchy* H, hipStream_t st, bool* on_graph, int kind, F&& enqueue) {
     if (!graphs_usable(H)) {
-        int rc = vcycle<double>(H, 0, st, 1);
-        if (rc) return rc;
-        rc = enqueue_sweep_norm(H, st);
+        int rc = enqueue(st);
         if (rc) return rc;
         HIPCHK(hipStreamSynchronize(st));
         return MG_OK;
@@ -586,7 +593,7 @@ static int cycle_and_norm(mg_hierarchy* H, hipStream_t st, bool* on_graph) {
         HIPCHK(hipStreamWaitEvent(gs, H->gev, 0));
         *on_graph = true;
     }
-    const std::vector<uintptr_t> key = graph_key(H);
+    const std::vector<uintptr_t> key = graph_key(H, kind);
     mg_hierarchy::CycleGraph* g = nullptr;
     for (auto& c : H->graph)
         if (c.exec && c.key == key) g = &c;
@@ -598,8 +605,7 @@ static int cycle_and_norm(mg_hierarchy* H, hipStream_t st, bool* on_graph) {
             g->exec = nullptr;
         }
         HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
-        int rc = vcycle<double>(H, 0, gs, 1);
-        if (rc == MG_OK) rc = enqueue_sweep_norm(H, gs);
+        int rc = enqueue(gs);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(gs, &graph);
         if (rc) {
@@ -614,21 +620,35 @@ static int cycle_and_norm(mg_hierarchy* H, hipStream_t st, bool* on_graph) {
             return hip_fail(e, "hipGraphInstantiate", __LINE__);
         }
         g->key = key;
-        g->post_phi.resize(H->nlev);
-        g->post_phi2.resize(H->nlev);
-        for (int l = 0; l < H->nlev; ++l) {         // capture left the host pointers as after the cycle
+        g->post_phi.resize(2 * H->nlev);
+        g->post_phi2.resize(2 * H->nlev);
+        for (int l = 0; l < H->nlev; ++l) {         // capture left the host pointers as after the iteration
             g->post_phi[l] = H->lev[l].d.phi;
             g->post_phi2[l] = H->lev[l].phi2_d;
+            g->post_phi[H->nlev + l] = H->lev[l].s.phi;
+            g->post_phi2[H->nlev + l] = H->lev[l].phi2_s;
         }
     } else {
         for (int l = 0; l < H->nlev; ++l) {
-            H->lev[l].d.phi = g->post_phi[l];
-            H->lev[l].phi2_d = g->post_phi2[l];
+            H->lev[l].d.phi = (double*)g->post_phi[l];
+            H->lev[l].phi2_d = (double*)g->post_phi2[l];
+            H->lev[l].s.phi = (float*)g->post_phi[H->nlev + l];
+            H->lev[l].phi2_s = (float*)g->post_phi2[H->nlev + l];
         }
     }
     HIPCHK(hipGraphLaunch(g->exec, gs));
     HIPCHK(hipStreamSynchronize(gs));
     return MG_OK;
+}
+
+// FP64: one V-cycle after a taken speculative sweep, then the next
+// speculative sweep-norm.
+static int cycle_and_norm(mg_hierarchy* H, hipStream_t st, bool* on_graph) {
+    return run_iteration(H, st, on_graph, kIterFp64, [H](hipStream_t s) {
+        int rc = vcycle<double>(H, 0, s, 1);
+        if (rc) return rc;
+        return enqueue_sweep_norm(H, s);
+    });
 }
 
 // Power of two nearest 1 / rms(r), the scale of the FP32 residual: the
@@ -643,22 +663,27 @@ static double residual_scale(double norm2_sqrt, size_t n) {
 // the inner solver of iterative refinement): each iteration runs one FP32
 // V-cycle from zero on the scaled FP64 residual, then one FP64 refinement
 // kernel adds the correction to phi, recomputes r = f - L phi with exact FP64
-// coefficients from rho, measures its norm and writes the next FP32 residual.
-// The FP32 finest-level sweeps recompute their coefficients from an FP32
-// copy of rho.
+// coefficients from rho, writes its per-tile norm rows and the next FP32
+// residual; a one-thread kernel then advances the two device-side scales
+// (the residual's, and the power of two nearest 1/rms(r) for the next).  The
+// FP32 finest-level sweeps recompute their coefficients from an FP32 copy of
+// rho.  Iterations after the first replay a captured graph.
 static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_out, double* rel_out,
                                     const std::function<void(int, double)>& record, hipStream_t st) {
     Level& L0 = H->lev[0];
     HIPCHK(launch_coeff_to_f32(H->rho.rho, H->rho32, L0.N, st));
     H->rho32_on = true;
     HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
-    double s = residual_scale(fnorm, L0.N);                  // residual = f while phi = 0
-    HIPCHK(launch_scale_to_f32(L0.d.f, L0.s.f, L0.N, s, st));
+    const double s0 = residual_scale(fnorm, L0.N);           // residual = f while phi = 0
+    HIPCHK(launch_scale_to_f32(L0.d.f, L0.s.f, L0.N, s0, st));
+    double* scales = H->scal + kSlotScale * kReduceWidth;
+    H->host[kSlotScale * kReduceWidth] = s0;
+    H->host[kSlotScale * kReduceWidth + 1] = s0;
+    HIPCHK(hipMemcpyAsync(scales, H->host + kSlotScale * kReduceWidth, 2 * sizeof(double), hipMemcpyHostToDevice,
+                          st));
     const int cfg = sweep_config_for(L0.nx, L0.ny, L0.nz, true);
-    int status = MG_ERR_NOT_CONVERGED, cycles = 0;
-    double rel = 1.0;
-    while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
-        int rc = vcycle<float>(H, 0, st, 0, true);
+    auto iteration = [H, &L0, cfg, scales](hipStream_t s) {
+        int rc = vcycle<float>(H, 0, s, 0, true);
         if (rc) return rc;
         SweepArgs<double> a{};
         a.nx = L0.nx;
@@ -676,17 +701,23 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
         a.b0e = H->rho.b0e;
         a.partials = H->partials;
         a.corr = L0.s.phi;
-        a.cscale = 1.0 / s;                                   // exact: s is a power of two
-        const double s_next = residual_scale(rel * fnorm, L0.N);
         a.r32 = L0.s.f;
-        a.rscale = s_next;
+        a.scales = scales;
         int np = 0;
-        HIPCHK(launch_refine(a, cfg, &np, st));
+        HIPCHK(launch_refine(a, cfg, &np, s));
         std::swap(L0.d.phi, L0.phi2_d);
-        s = s_next;
-        rc = reduce_to(H, np, kSlotRes, st);
+        rc = reduce_to(H, np, kSlotRes, s);
         if (rc) return rc;
-        rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
+        HIPCHK(launch_next_scale(H->scal + kSlotRes * kReduceWidth, scales, L0.N, s));
+        HIPCHK(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
+                              kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, s));
+        return (int)MG_OK;
+    };
+    int status = MG_ERR_NOT_CONVERGED, cycles = 0;
+    double rel = 1.0;
+    bool on_graph = false;
+    while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
+        int rc = run_iteration(H, st, &on_graph, kIterMixed, iteration);
         if (rc) return rc;
         ++cycles;
         const double* r = H->host + kSlotRes * kReduceWidth;
@@ -698,6 +729,10 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
             break;
         }
         if (rel <= H->p.rtol) status = MG_OK;
+    }
+    if (on_graph) {                                  // the caller's stream continues after the graph work
+        HIPCHK(hipEventRecord(H->gev, H->gstream));
+        HIPCHK(hipStreamWaitEvent(st, H->gev, 0));
     }
     *cycles_out = cycles;
     *rel_out = rel;

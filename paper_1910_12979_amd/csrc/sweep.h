@@ -44,10 +44,9 @@ struct SweepArgs {
     double* partials;          // residual-norm rows (kOpSweepNorm, kOpRefine), one per tile
     T* fc;                     // coarse right-hand side (kOpResidRestrict)
     T* phic_out;               // coarse phi, zeroed (kOpResidRestrict)
-    const float* corr;         // kInCorrect: input is phi_in + cscale * corr
-    double cscale;
-    float* r32;                // kOpRefine: r32 = (float)(rscale * (f - L phi))
-    double rscale;
+    const float* corr;         // kInCorrect: input is phi_in + corr / scales[0]
+    float* r32;                // kOpRefine: r32 = (float)(scales[1] * (f - L phi))
+    const double* scales;      // device {scale of corr's right-hand side, scale for r32}
 };
 
 template <typename T>
@@ -69,9 +68,11 @@ template <typename T>
 hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, int cfg, hipStream_t st);
 
 // Refinement step of the mixed-precision solve (finest level, FP64,
-// coefficients from rho): phi_out = phi_in + cscale * corr; per tile the
+// coefficients from rho): phi_out = phi_in + corr / scales[0]; per tile the
 // partial row {sum r^2, 0, 0, 0} of r = f - L phi_out; and
-// r32 = (float)(rscale * r).  *nparts = rows written.
+// r32 = (float)(scales[1] * r).  The scales are powers of two read from
+// device memory, so a captured launch stays valid as they change.
+// *nparts = rows written.
 hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st);
 
 // Batched form (one launch, many problems): descriptor i (device) is problem

@@ -126,7 +126,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const T h2 = a.h2;
     const T ih2 = T(1) / a.h2;
     const T half = T(0.5);
-    const T cscale = (T)a.cscale;
+    const T cscale = kIn == kInCorrect ? (T)(1.0 / a.scales[0]) : T(0);    // exact: a power of two
 
     size_t ccol = 0;
     if (kIn == kInProlong) ccol = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
@@ -255,6 +255,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     // the reference face order, for both cells of a tile pair at plane t
     // only the sum of squares is kept: a non-finite residual makes it non-finite
     double nrm2 = 0.0;
+    const double rscale = kIR ? a.scales[1] : 0.0;
     auto resid_at = [&](int c, int s_t, T pm, T pc, T pp, T bzl, T bzh, T fc) -> T {
         const int lx = lx0 + c;
         T r = sbx[s_t][ly][lx] * (sphi[ly][lx - 1] - pc);
@@ -359,7 +360,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             nrm2 += d1 * d1;
             const size_t o = (size_t)t * plane + col;
             st2(a.phi_out + o, Pc0, Pc1);
-            st2(a.r32 + o, (float)(a.rscale * d0), (float)(a.rscale * d1));
+            st2(a.r32 + o, (float)(rscale * d0), (float)(rscale * d1));
         }
         __syncthreads();
         if (kIR) return;

@@ -312,6 +312,33 @@ def test_graph_replays_match_eager(mp):
         Hg.close()
 
 
+def test_graph_replays_match_eager_mixed(mp):
+    """Mixed precision: iterations replayed from the two captured graphs (the
+    finest FP64 phi alternates buffers) equal the eager solve bit for bit,
+    over several solves in a row."""
+    prob = I.make_problem((64, 64, 32), H=0.12, rho_noise=0.05, seed=44)
+    He = mp.Hierarchy(mp.params_of(prob, precision="mixed"))
+    He.set_graphs(False)
+    Hg = mp.Hierarchy(mp.params_of(prob, precision="mixed"))
+
+    def solve(H):
+        d = mp.to_device(prob)
+        st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+        torch.cuda.synchronize()
+        return st, {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+
+    try:
+        st0, out0 = solve(He)
+        assert st0["status_name"] == "OK" and st0["cycles"] >= 4
+        for _ in range(3):
+            st1, out1 = solve(Hg)
+            assert st1["cycles"] == st0["cycles"] and st1["hist"] == st0["hist"]
+            assert same_out(out1, out0)
+    finally:
+        He.close()
+        Hg.close()
+
+
 @pytest.mark.parametrize("shape,per,prec", [
     ((32, 32, 32), (True, True, False), "fp64"),
     ((64, 32, 48), (False, False, False), "fp64"),
