@@ -231,7 +231,7 @@ int mg_autotune(mg_handle h, int32_t reps, void* stream);
 int mg_set_graphs(mg_handle h, int32_t enable);
 
 /* Bottom of the V-cycle: with enable = 1 (the default) the levels below the
- * ones the fused sweep covers (when their phi and f fit in 88 KB of LDS) run
+ * ones the fused sweep covers (when their phi and f fit in 136 KB of LDS) run
  * as one 1024-thread workgroup per V-cycle instead of one launch per step
  * and level.  Results are identical either way. */
 int mg_set_bottom(mg_handle h, int32_t enable);

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <vector>
 
 #include "batch.h"
@@ -379,12 +380,215 @@ int multi_vcycle(std::vector<mg_hierarchy*>& hs, const std::vector<int>& pre_don
 }
 
 // ---------------------------------------------------------------------------
+// mixed precision: one FP32 V-cycle from zero on every problem's scaled
+// residual (fused levels and the one-workgroup bottom), then the FP64
+// refinement kernel, the norm rows and the next residual scales
+// ---------------------------------------------------------------------------
+namespace {
+
+SweepArgs<float> sweep_args_f32(mg_hierarchy* H, int l) {
+    Level& F = H->lev[l];
+    SweepArgs<float> a{};
+    a.nx = F.nx;
+    a.ny = F.ny;
+    a.nz = F.nz;
+    a.px = H->px;
+    a.py = H->py;
+    a.pz = H->pz;
+    a.h2 = (float)(F.h * F.h);
+    a.phi_in = F.s.phi;
+    a.phi_out = F.phi2_s;
+    a.f = F.s.f;
+    a.phic = l + 1 < H->nlev ? H->lev[l + 1].s.phi : nullptr;
+    a.bx = F.s.bx;
+    a.by = F.s.by;
+    a.bz = F.s.bz;
+    a.rho = l == 0 ? H->rho32 : nullptr;
+    a.b0c = H->rho.b0c;
+    a.b0e = H->rho.b0e;
+    if (l + 1 < H->nlev) {
+        a.fc = H->lev[l + 1].s.f;
+        a.phic_out = H->lev[l + 1].s.phi;
+    }
+    return a;
+}
+
+// One launch per tile configuration of `op` over the given descriptors: the
+// batched kernel where the tile shape has one, else one launch per problem.
+template <typename T>
+int launch_group(std::vector<SweepArgs<T>>& args, const std::vector<int>& cfgs, bool use_rho, int in_mode, int op,
+                 Staging& S, hipStream_t st) {
+    std::map<int, std::vector<size_t>> by_cfg;
+    for (size_t i = 0; i < args.size(); ++i) by_cfg[cfgs[i]].push_back(i);
+    for (auto& kv : by_cfg) {
+        const int cfg = kv.first;
+        if (!multi_tile_shape(cfg)) {
+            for (size_t i : kv.second) {
+                if (op == kOpSweep) {
+                    BHIP(launch_sweep<T>(args[i], use_rho, in_mode, cfg, st));
+                } else if (op == kOpResidRestrict) {
+                    BHIP(launch_resid_restrict_tiled<T>(args[i], cfg, st));
+                } else {
+                    if constexpr (std::is_same<T, double>::value) {
+                        int np = 0;
+                        BHIP(launch_refine(args[i], cfg, &np, st));
+                    }
+                }
+            }
+            continue;
+        }
+        std::vector<SweepArgs<T>> descs;
+        std::vector<int> prefix(1, 0);
+        for (size_t i : kv.second) {
+            SweepArgs<T> a = args[i];
+            sweep_geometry(a, cfg);
+            descs.push_back(a);
+            prefix.push_back(prefix.back() + sweep_tiles(a.nx, a.ny, a.nz, cfg));
+        }
+        void* dd = nullptr;
+        void* dp = nullptr;
+        int rc = S.push(descs.data(), descs.size() * sizeof(SweepArgs<T>), st, &dd);
+        if (rc) return rc;
+        rc = S.push(prefix.data(), prefix.size() * sizeof(int), st, &dp);
+        if (rc) return rc;
+        BHIP(launch_sweep_multi<T>((const SweepArgs<T>*)dd, (const int*)dp, (int)descs.size(), prefix.back(), use_rho,
+                                   in_mode, op, cfg, st));
+    }
+    return MG_OK;
+}
+
+// FP32 V-cycle from zero on every problem (all of whose levels above the
+// bottom are fused-sweep levels), the batched form of vcycle<float> with a
+// zero start.
+int multi_vcycle_f32(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
+    std::vector<int> stop(hs.size());
+    int lmax = 0;
+    for (size_t i = 0; i < hs.size(); ++i) {
+        stop[i] = bottom_start<float>(hs[i]);
+        lmax = std::max(lmax, stop[i]);
+    }
+    auto sweeps = [&](int l, bool post, int first) -> int {
+        int maxk = 0;
+        for (size_t i = 0; i < hs.size(); ++i)
+            if (l < stop[i]) maxk = std::max(maxk, post ? hs[i]->p.post_sweeps : hs[i]->p.pre_sweeps);
+        for (int k = 0; k < maxk; ++k) {
+            std::vector<SweepArgs<float>> args;
+            std::vector<int> cfgs;
+            std::vector<mg_hierarchy*> who;
+            for (size_t i = 0; i < hs.size(); ++i) {
+                mg_hierarchy* H = hs[i];
+                if (l >= stop[i] || k >= (post ? H->p.post_sweeps : H->p.pre_sweeps)) continue;
+                const Level& F = H->lev[l];
+                args.push_back(sweep_args_f32(H, l));
+                cfgs.push_back(sweep_config_for(F.nx, F.ny, F.nz, l == 0));
+                who.push_back(H);
+            }
+            if (args.empty()) continue;
+            int rc = launch_group<float>(args, cfgs, l == 0, k == 0 ? first : (int)kInPlain, kOpSweep, S, st);
+            if (rc) return rc;
+            for (auto* H : who) std::swap(H->lev[l].s.phi, H->lev[l].phi2_s);
+        }
+        return MG_OK;        // (batched mixed problems have post-sweeps: the prolongation is folded in)
+    };
+    for (int l = 0; l < lmax; ++l) {
+        int rc = sweeps(l, false, kInZero);
+        if (rc) return rc;
+        std::vector<SweepArgs<float>> args;
+        std::vector<int> cfgs;
+        for (size_t i = 0; i < hs.size(); ++i) {
+            if (l >= stop[i]) continue;
+            const Level& F = hs[i]->lev[l];
+            args.push_back(sweep_args_f32(hs[i], l));
+            cfgs.push_back(sweep_config_for(F.nx, F.ny, F.nz, l == 0));
+        }
+        rc = launch_group<float>(args, cfgs, l == 0, kInPlain, kOpResidRestrict, S, st);
+        if (rc) return rc;
+    }
+    std::vector<BottomArgs<float>> bottoms;
+    for (size_t i = 0; i < hs.size(); ++i) {
+        BottomArgs<float> a;
+        bottom_args<float>(hs[i], stop[i], a);
+        bottoms.push_back(a);
+    }
+    void* dd = nullptr;
+    int rc = S.push(bottoms.data(), bottoms.size() * sizeof(BottomArgs<float>), st, &dd);
+    if (rc) return rc;
+    BHIP(launch_bottom_multi((const BottomArgs<float>*)dd, (int)bottoms.size(), st));
+    for (int l = lmax - 1; l >= 0; --l) {
+        rc = sweeps(l, true, kInProlong);
+        if (rc) return rc;
+    }
+    return MG_OK;
+}
+
+// FP64 refinement of every problem: phi += e32 / scale, residual, FP32
+// residual for the next cycle, norm rows reduced, scales advanced, norm row
+// copied to pinned host memory.
+int multi_refine(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
+    std::vector<SweepArgs<double>> args;
+    std::vector<int> cfgs;
+    std::vector<ReduceDesc> rd;
+    std::vector<ScaleDesc> sd;
+    for (auto* H : hs) {
+        Level& L0 = H->lev[0];
+        SweepArgs<double> a{};
+        a.nx = L0.nx;
+        a.ny = L0.ny;
+        a.nz = L0.nz;
+        a.px = H->px;
+        a.py = H->py;
+        a.pz = H->pz;
+        a.h2 = L0.h * L0.h;
+        a.phi_in = L0.d.phi;
+        a.phi_out = L0.phi2_d;
+        a.f = L0.d.f;
+        a.rho = H->rho.rho;
+        a.b0c = H->rho.b0c;
+        a.b0e = H->rho.b0e;
+        a.partials = H->partials;
+        a.corr = L0.s.phi;
+        a.r32 = L0.s.f;
+        a.scales = H->scal + kSlotScale * kReduceWidth;
+        const int cfg = sweep_config_for(L0.nx, L0.ny, L0.nz, true);
+        args.push_back(a);
+        cfgs.push_back(cfg);
+        rd.push_back(ReduceDesc{H->partials, sweep_tiles(L0.nx, L0.ny, L0.nz, cfg), H->scal + kSlotRes * kReduceWidth});
+        sd.push_back(ScaleDesc{H->scal + kSlotRes * kReduceWidth, H->scal + kSlotScale * kReduceWidth, (double)L0.N});
+    }
+    int rc = launch_group<double>(args, cfgs, true, kInCorrect, kOpRefine, S, st);
+    if (rc) return rc;
+    for (auto* H : hs) std::swap(H->lev[0].d.phi, H->lev[0].phi2_d);
+    void* dd = nullptr;
+    rc = S.push(rd.data(), rd.size() * sizeof(ReduceDesc), st, &dd);
+    if (rc) return rc;
+    BHIP(launch_reduce_multi((const ReduceDesc*)dd, (int)rd.size(), st));
+    rc = S.push(sd.data(), sd.size() * sizeof(ScaleDesc), st, &dd);
+    if (rc) return rc;
+    BHIP(launch_next_scale_multi((const ScaleDesc*)dd, (int)sd.size(), st));
+    for (auto* H : hs)
+        BHIP(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
+                            kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
+    return MG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // jobs
 // ---------------------------------------------------------------------------
 bool batchable(const mg_hierarchy* H) {
     const Level& L0 = H->lev[0];
-    return H->p.precision == MG_FP64 && H->p.pre_sweeps >= 1 && H->nlev > 1 &&
-           sweep_fusable<double>(L0.nx, L0.ny, L0.nz);
+    if (H->p.pre_sweeps < 1 || H->nlev < 2 || !sweep_fusable<double>(L0.nx, L0.ny, L0.nz)) return false;
+    if (H->p.precision == MG_FP64) return true;
+    // mixed precision: every FP32 level above the one-workgroup bottom is a
+    // fused-sweep level (the batched FP32 cycle has no per-cell kernels), and
+    // every prolongation is folded into a post-sweep
+    if (H->p.post_sweeps < 1) return false;
+    const int b = bottom_start<float>(H);
+    if (b <= 0) return false;
+    for (int l = 0; l < b; ++l)
+        if (!sweep_fusable<float>(H->lev[l].nx, H->lev[l].ny, H->lev[l].nz)) return false;
+    return true;
 }
 
 static void fail_job(Job& j, int status, const char* why) {
@@ -469,6 +673,17 @@ int Engine::setup_new(std::vector<Job*>& fresh, hipStream_t st) {
         j->rel = 1.0;
         j->st.resid_hist[0] = 1.0;
         j->st.hist_len = 1;
+        if (H->p.precision == MG_MIXED) {
+            // FP32 rho for the finest FP32 sweeps; FP32 residual = s0 f while phi = 0
+            BHIP(launch_coeff_to_f32(H->rho.rho, H->rho32, L0.N, st));
+            H->rho32_on = true;
+            const double s0 = residual_scale(j->fnorm, L0.N);
+            BHIP(launch_scale_to_f32(L0.d.f, L0.s.f, L0.N, s0, st));
+            H->host[kSlotScale * kReduceWidth] = s0;
+            H->host[kSlotScale * kReduceWidth + 1] = s0;
+            BHIP(hipMemcpyAsync(H->scal + kSlotScale * kReduceWidth, H->host + kSlotScale * kReduceWidth,
+                                2 * sizeof(double), hipMemcpyHostToDevice, st));
+        }
         j->status = MG_ERR_NOT_CONVERGED;
         j->stage = (H->p.rtol >= 1.0) ? Job::kFinish : Job::kSolve;
         if (H->p.rtol >= 1.0) j->status = MG_OK;
@@ -482,24 +697,29 @@ int Engine::round(std::vector<Job*>& jobs, hipStream_t st) {
     std::vector<Job*> solving;
     for (Job* j : jobs)
         if (j->stage == Job::kSolve) solving.push_back(j);
-    // stop tests (speculative first pre-sweeps)
+    // stop tests: FP64 jobs measure the residual of their last cycle with a
+    // speculative first pre-sweep; mixed jobs' last refinement left it on the
+    // host already
     std::vector<mg_hierarchy*> tested;
-    std::vector<Job*> tested_jobs;
+    bool mixed_tested = false;
     for (Job* j : solving)
         if (j->cycles > 0) {
-            tested.push_back(j->H);
-            tested_jobs.push_back(j);
+            if (j->H->p.precision == MG_MIXED) mixed_tested = true;
+            else tested.push_back(j->H);
         }
     if (!tested.empty()) {
         int rc = multi_norm_sweep(tested, staging, st);
         if (rc) return rc;
+    }
+    if (!tested.empty() || mixed_tested) {
         BHIP(hipStreamSynchronize(st));
         staging.off = 0;
     }
-    std::vector<mg_hierarchy*> run;
+    std::vector<mg_hierarchy*> run, run_mixed;
     std::vector<int> pre_done;
     for (Job* j : solving) {
         mg_hierarchy* H = j->H;
+        const bool mixed = H->p.precision == MG_MIXED;
         int pd = 0;
         if (j->cycles > 0) {
             const double* r = H->host + kSlotRes * kReduceWidth;
@@ -523,21 +743,33 @@ int Engine::round(std::vector<Job*>& jobs, hipStream_t st) {
                 j->stage = Job::kFinish;
                 continue;
             }
-            std::swap(H->lev[0].d.phi, H->lev[0].phi2_d);   // keep the speculative sweep
-            pd = 1;
+            if (!mixed) {
+                std::swap(H->lev[0].d.phi, H->lev[0].phi2_d);   // keep the speculative sweep
+                pd = 1;
+            }
         } else if (H->p.max_cycles == 0) {
             j->stage = Job::kFinish;
             continue;
         }
-        run.push_back(H);
-        pre_done.push_back(pd);
+        if (mixed) {
+            run_mixed.push_back(H);
+        } else {
+            run.push_back(H);
+            pre_done.push_back(pd);
+        }
     }
     if (!run.empty()) {
         int rc = multi_vcycle(run, pre_done, staging, st);
         if (rc) return rc;
-        for (Job* j : solving)
-            if (j->stage == Job::kSolve) ++j->cycles;
     }
+    if (!run_mixed.empty()) {
+        int rc = multi_vcycle_f32(run_mixed, staging, st);
+        if (rc) return rc;
+        rc = multi_refine(run_mixed, staging, st);
+        if (rc) return rc;
+    }
+    for (Job* j : solving)
+        if (j->stage == Job::kSolve) ++j->cycles;
     // finish: mean removal of phi and the velocity correction
     std::vector<Job*> fin;
     for (Job* j : jobs)
@@ -563,10 +795,11 @@ int Engine::round(std::vector<Job*>& jobs, hipStream_t st) {
             j->st.cycles = j->cycles;
             j->st.rel_resid = j->cycles > 0 ? j->rel : j->st.resid_hist[0];
             if (j->st.hist_len == 1 && j->st.resid_hist[0] == 0.0) j->st.rel_resid = 0.0;
-            j->st.bytes_model = model_bytes(H->p, j->cycles, 0);
+            j->st.bytes_model = model_bytes(H->p, j->cycles, H->p.precision == MG_MIXED);
             j->st.status = j->status;
             j->stage = Job::kDone;
             H->rho = RhoArgs{};
+            H->rho32_on = false;
         }
     }
     return MG_OK;

@@ -558,14 +558,22 @@ __global__ void k_accumulate(double* __restrict__ phi, const float* __restrict__
 // res[0] = sum r^2: scales[0] <- scales[1] (the scale the FP32 residual now
 // holds), scales[1] <- the power of two nearest 1/rms(r) (1 for a zero or
 // non-finite residual), the scale for the next FP32 residual.
+__device__ inline void next_scale(const double* res, double* scales, double n) {
+    const double rms = sqrt(res[0] / n);
+    double s = 1.0;
+    if (rms > 0.0 && isfinite(rms)) s = ldexp(1.0, -ilogb(rms));
+    scales[0] = scales[1];
+    scales[1] = s;
+}
+
 __global__ void k_next_scale(const double* __restrict__ res, double* __restrict__ scales, double n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const double rms = sqrt(res[0] / n);
-        double s = 1.0;
-        if (rms > 0.0 && isfinite(rms)) s = ldexp(1.0, -ilogb(rms));
-        scales[0] = scales[1];
-        scales[1] = s;
-    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) next_scale(res, scales, n);
+}
+
+// Batched form: one thread per problem.
+__global__ void k_next_scale_multi(const ScaleDesc* __restrict__ d, int nprob) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) next_scale(d[p].res, d[p].scales, d[p].n);
 }
 
 __global__ void k_scale_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t n, double s) {
@@ -762,6 +770,12 @@ hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* sc
 hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const double* scale_inv,
                              hipStream_t st) {
     hipLaunchKernelGGL(k_accumulate, dim3(stream_blocks(n)), dim3(kBlock), 0, st, phi, e32, n, scale_inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_next_scale_multi(const ScaleDesc* d, int nprob, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_next_scale_multi, dim3((nprob + 63) / 64), dim3(64), 0, st, d, nprob);
     return hipGetLastError();
 }
 

@@ -57,7 +57,7 @@ struct RhoArgs {
 // given) down to the coarsest and back, with phi and f of every bottom level
 // in LDS.  Same per-cell arithmetic as the per-level kernels.
 constexpr int kMaxBottomLevels = 8;
-constexpr size_t kBottomLdsBytes = 88 * 1024;   // phi and f of every bottom level
+constexpr size_t kBottomLdsBytes = 136 * 1024;  // phi and f of every bottom level
 
 template <typename T>
 struct BottomLevel {
@@ -202,5 +202,12 @@ hipError_t launch_resid_restrict_multi(const CellDesc* d, int nprob, int blocks,
 hipError_t launch_prolong_multi(const CellDesc* d, int nprob, int blocks, hipStream_t st);
 hipError_t launch_coarse_solve_multi(const CellDesc* d, int nprob, hipStream_t st);
 hipError_t launch_reduce_multi(const ReduceDesc* d, int nprob, hipStream_t st);
+// Mixed precision: the scale update of launch_next_scale for many problems.
+struct ScaleDesc {
+    const double* res;       // reduced residual row (sum r^2 first)
+    double* scales;          // {scale of the FP32 residual, scale for the next}
+    double n;                // cells
+};
+hipError_t launch_next_scale_multi(const ScaleDesc* d, int nprob, hipStream_t st);
 
 }  // namespace mg

@@ -69,6 +69,9 @@ double model_bytes(const mg_params& p, int cycles, int mixed);
 // every coarser level fit in its LDS), or -1.
 template <typename T>
 int bottom_start(const mg_hierarchy* H);
+// Mixed precision: the power of two nearest 1/rms of a residual of 2-norm
+// norm2_sqrt over n cells (1 for a zero or non-finite norm).
+double residual_scale(double norm2_sqrt, size_t n);
 template <typename T>
 void bottom_args(mg_hierarchy* H, int l, BottomArgs<T>& a);
 int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,

@@ -653,7 +653,7 @@ static int cycle_and_norm(mg_hierarchy* H, hipStream_t st, bool* on_graph) {
 
 // Power of two nearest 1 / rms(r), the scale of the FP32 residual: the
 // scaled values are O(1) and scaling by 2^k is exact in both directions.
-static double residual_scale(double norm2_sqrt, size_t n) {
+double residual_scale(double norm2_sqrt, size_t n) {
     const double rms = norm2_sqrt / std::sqrt((double)n);
     if (!(rms > 0.0) || !std::isfinite(rms)) return 1.0;
     return std::ldexp(1.0, -std::ilogb(rms));

@@ -77,8 +77,9 @@ hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipSt
 
 // Batched form (one launch, many problems): descriptor i (device) is problem
 // i's SweepArgs with tz/ntx/nty filled (sweep_geometry), prefix (device,
-// nprob+1 entries) its first tile; `op` is kOpSweep, kOpSweepNorm (rho only,
-// plain input) or kOpResidRestrict.  Tile shapes 32x8, 64x8 and 32x4.
+// nprob+1 entries) its first tile; `op` is kOpSweep, kOpResidRestrict, or
+// (FP64 with rho only) kOpSweepNorm (plain input) or kOpRefine (corrected
+// input).  Tile shapes 32x8, 64x8 and 32x4.
 template <typename T>
 hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
                               int in_mode, int op, int cfg, hipStream_t st);

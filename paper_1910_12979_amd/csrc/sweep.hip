@@ -92,13 +92,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     constexpr bool kNorm = kOp == kOpSweepNorm;    // sweep + residual norm of its input
     constexpr bool kRR = kOp == kOpResidRestrict;  // residual + restriction only (no sweep)
     constexpr bool kIR = kOp == kOpRefine;         // corrected phi + scaled residual + norm (no sweep)
+    constexpr bool kGS = !kRR && !kIR;             // red/black updates
     constexpr int WX = TX + 4, WY = TY + 4, WP = WX / 2;   // ring-2 window, pairs per row
     constexpr int NB = kSweepTZMax + 6;                    // beta0 planes staged per chunk
-    __shared__ T sphi[WY][WX];                // phi_in, current plane
-    __shared__ T sR[2][WY][WX];               // red-stage values, planes t and t-1
-    __shared__ T sbx[3][WY][WX];              // low x-face coefficients, planes t+1, t, t-1
+    // Every LDS plane is double-buffered or tripled so that one barrier per
+    // plane step suffices: a step reads what the previous step wrote and
+    // writes buffers no one reads before the next barrier.
+    __shared__ T sphi[2][WY][WX];                   // phi_in: plane t (read), t+1 (staged)
+    __shared__ __align__(16) T sR[2][WY][WX];       // red values (kRR: residuals), planes t, t-1
+    __shared__ T sbx[3][WY][WX];                    // low x-face coefficients, planes t+1, t, t-1
     __shared__ T sby[3][WY][WX];
-    __shared__ T srho[kRho ? WY : 1][kRho ? WX : 1];
+    __shared__ T srho[kRho ? 2 : 1][kRho ? WY : 1][kRho ? WX : 1];   // rho: t+1 (read), t+2 (staged)
     __shared__ double sb0c[kRho ? NB : 1], sb0e[kRho ? NB : 1];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -176,8 +180,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             sb0e[q] = a.b0e[qw];
         }
     }
-    // Loads in flight: step s issues plane s+3 (phi, rho or stored bz, stored
-    // bx/by) and plane s+2 (f) into one of two register sets, and step s+2
+    // Loads in flight: step s issues plane s+3 (phi, stored bx/by), s+4 (rho
+    // or stored bz) and s+2 (f) into one of two register sets, and step s+2
     // consumes that set before re-issuing into it, so every load has two
     // plane-steps of work to arrive.  Loads are always issued (clamped to the
     // last plane the chunk needs; those reloads hit in cache) so the sets are
@@ -190,9 +194,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         T y0, y1;      // stored by
     };
     auto issue = [&](int s, Fly& X) {
-        const int tq = min(s + 3, z1 + 1);
-        load_phi(tq, X.p0, X.p1);
-        load_q(tq, X.q0, X.q1);
+        load_phi(min(s + 3, z1 + 1), X.p0, X.p1);
+        load_q(min(s + 4, z1 + 1), X.q0, X.q1);
         if (!kRho) {
             int tw = wrap3(min(s + 3, z1), nz);
             ld2(a.bx + (size_t)tw * plane + col, X.x0, X.x1);
@@ -207,12 +210,43 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     T Pm0 = T(0), Pm1 = T(0), Pc0, Pc1, Pp0, Pp1;
     load_phi(z0 - 2, Pc0, Pc1);
     load_phi(z0 - 1, Pp0, Pp1);
-    T Rc0, Rc1, Rp0, Rp1;
+    T Rc0, Rc1, Rp0, Rp1, Rq0, Rq1;                    // rho (or bz) of planes t, t+1, t+2 after a rotation
     load_q(z0 - 2, Rc0, Rc1);
     load_q(z0 - 1, Rp0, Rp1);
+    load_q(z0, Rq0, Rq1);
     T Fm0 = T(0), Fm1 = T(0), Fc0 = T(0), Fc1 = T(0);
     T cx0 = T(0), cx1 = T(0), cy0 = T(0), cy1 = T(0);  // stored x/y coefficients of plane t+1
-    if (!kRho) {
+
+    // x/y low-face coefficients of plane t into LDS slot s from the staged rho
+    // plane (buffer b); (r0, r1) is the thread's own pair of that plane
+    auto rho_coeffs = [&](int t, int s, int b, T r0, T r1) {
+        const T b0 = (T)sb0c[t - zb];
+        const T rc[2] = {r0, r1};
+        // the window's first row/column has no low neighbour and is never read
+        const T rl[2] = {srho[b][ly][lx0 > 0 ? lx0 - 1 : 0], r0};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int lx = lx0 + c;
+            const T cx = qdiv(b0, half * (rl[c] + rc[c]));
+            const T cy = qdiv(b0, half * (srho[b][ly > 0 ? ly - 1 : 0][lx] + rc[c]));
+            const bool xwall = (gxw + c == 0) && !a.px;
+            const bool ywall = gyw == 0 && !a.py;
+            sbx[s][ly][lx] = xwall ? T(0) : cx;
+            sby[s][ly][lx] = ywall ? T(0) : cy;
+        }
+    };
+    // LDS before the first step (t = z0-1): phi_in of z0-1, coefficients of
+    // z0-1, rho of z0
+    sphi[(z0 - 1) & 1][ly][lx0] = Pp0;
+    sphi[(z0 - 1) & 1][ly][lx0 + 1] = Pp1;
+    if (kRho) {
+        srho[(z0 - 1) & 1][ly][lx0] = Rp0;
+        srho[(z0 - 1) & 1][ly][lx0 + 1] = Rp1;
+        __syncthreads();                               // beta0 and rho of z0-1 staged
+        rho_coeffs(z0 - 1, (z0 - 1 + 3) % 3, (z0 - 1) & 1, Rp0, Rp1);
+        srho[z0 & 1][ly][lx0] = Rq0;
+        srho[z0 & 1][ly][lx0 + 1] = Rq1;
+    } else {
         int tw = wrap3(z0 - 1, nz);
         T t0, t1;
         ld2(a.bx + (size_t)tw * plane + col, t0, t1);
@@ -222,46 +256,22 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         sby[(z0 - 1 + 3) % 3][ly][lx0] = t0;
         sby[(z0 - 1 + 3) % 3][ly][lx0 + 1] = t1;
     }
-    __syncthreads();                                   // beta0 staged
     T bm0 = T(0), bm1 = T(0), bc0 = T(0), bc1 = T(0);
     T bp0 = zface(z0 - 1, Rc0, Rp0), bp1 = zface(z0 - 1, Rc1, Rp1);   // low face of plane z0-1
-
-    // x/y low-face coefficients of plane t into LDS slot s from the staged rho plane
-    auto rho_coeffs = [&](int t, int s) {
-        T b0 = (T)sb0c[t - zb];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int lx = lx0 + c;
-            const T rc = srho[ly][lx];
-            // the window's first row/column has no low neighbour and is never read
-            const T cx = qdiv(b0, half * (srho[ly][lx > 0 ? lx - 1 : 0] + rc));
-            const T cy = qdiv(b0, half * (srho[ly > 0 ? ly - 1 : 0][lx] + rc));
-            const bool xwall = (gxw + c == 0) && !a.px;
-            const bool ywall = gyw == 0 && !a.py;
-            sbx[s][ly][lx] = xwall ? T(0) : cx;
-            sby[s][ly][lx] = ywall ? T(0) : cy;
-        }
-    };
-    if (kRho) {
-        srho[ly][lx0] = Rp0;                           // rho of plane z0-1
-        srho[ly][lx0 + 1] = Rp1;
-        __syncthreads();
-        rho_coeffs(z0 - 1, (z0 - 1 + 3) % 3);
-        __syncthreads();                               // srho is rewritten in the first step
-    }
+    __syncthreads();
 
     T Rmm = T(0), Rm = T(0);
-    // residual of phi_in (kNorm): r = f - (sum_f b (phi_nb - phi_c)) / h^2 in
-    // the reference face order, for both cells of a tile pair at plane t
+    // residual of phi_in (kNorm, kRR) or of the corrected phi (kIR):
+    // r = f - (sum_f b (phi_nb - phi_c)) / h^2 in the reference face order
     // only the sum of squares is kept: a non-finite residual makes it non-finite
     double nrm2 = 0.0;
     const double rscale = kIR ? a.scales[1] : 0.0;
-    auto resid_at = [&](int c, int s_t, T pm, T pc, T pp, T bzl, T bzh, T fc) -> T {
+    auto resid_at = [&](int c, int s_t, int b, T pm, T pc, T pp, T bzl, T bzh, T fc) -> T {
         const int lx = lx0 + c;
-        T r = sbx[s_t][ly][lx] * (sphi[ly][lx - 1] - pc);
-        r = r + sbx[s_t][ly][lx + 1] * (sphi[ly][lx + 1] - pc);
-        r = r + sby[s_t][ly][lx] * (sphi[ly - 1][lx] - pc);
-        r = r + sby[s_t][ly + 1][lx] * (sphi[ly + 1][lx] - pc);
+        T r = sbx[s_t][ly][lx] * (sphi[b][ly][lx - 1] - pc);
+        r = r + sbx[s_t][ly][lx + 1] * (sphi[b][ly][lx + 1] - pc);
+        r = r + sby[s_t][ly][lx] * (sphi[b][ly - 1][lx] - pc);
+        r = r + sby[s_t][ly + 1][lx] * (sphi[b][ly + 1][lx] - pc);
         r = r + bzl * (pm - pc);
         r = r + bzh * (pp - pc);
         return fc - r * ih2;
@@ -278,14 +288,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const size_t cc = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
     auto step = [&](int t, Fly& X) {
         // 0. slide the z window, taking in the set issued two steps ago:
-        //    phi[t+1], rho[t+1] (or bz[t+1]), f[t], bx/by[t+1]; then re-issue
+        //    phi[t+1], rho[t+2] (or bz[t+2]), f[t], bx/by[t+1]; then re-issue
         Fm0 = Fc0; Fm1 = Fc1;
         Fc0 = X.f0; Fc1 = X.f1;
         Pm0 = Pc0; Pm1 = Pc1;
         Pc0 = Pp0; Pc1 = Pp1;
         Pp0 = X.p0; Pp1 = X.p1;
         Rc0 = Rp0; Rc1 = Rp1;
-        Rp0 = X.q0; Rp1 = X.q1;
+        Rp0 = Rq0; Rp1 = Rq1;
+        Rq0 = X.q0; Rq1 = X.q1;
         bm0 = bc0; bm1 = bc1;
         bc0 = bp0; bc1 = bp1;
         bp0 = zface(t + 1, Rc0, Rp0);
@@ -296,19 +307,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         }
         issue(t, X);                             // consumed by step t+2
         const int s_t = (t + 3) % 3, s_p = (t + 4) % 3, s_m = (t + 2) % 3;
+        const int cur = t & 1, nxt = (t + 1) & 1;
         const int rsel = (gy + t) & 1;           // red cell of the pair at plane t (black at t-1)
-        // 1. stage phi_in of plane t, and rho of plane t+1
-        sphi[ly][lx0] = Pc0;
-        sphi[ly][lx0 + 1] = Pc1;
-        if (kRho) {
-            srho[ly][lx0] = Rp0;
-            srho[ly][lx0 + 1] = Rp1;
-        }
-        __syncthreads();
-        // 2. x/y coefficients of plane t+1 (read after the next barrier)
+        // 1. x/y coefficients of plane t+1 (read by the next step)
         if (t + 1 <= z1) {
             if (kRho) {
-                rho_coeffs(t + 1, s_p);
+                rho_coeffs(t + 1, s_p, nxt, Rp0, Rp1);
             } else {
                 sbx[s_p][ly][lx0] = cx0;
                 sbx[s_p][ly][lx0 + 1] = cx1;
@@ -316,18 +320,18 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
                 sby[s_p][ly][lx0 + 1] = cy1;
             }
         }
-        // 3. red update at plane t on the tile plus one ring
+        // 2. red update at plane t on the tile plus one ring
         const int lxr = lx0 + rsel;
         T Rcur = rsel ? Pc1 : Pc0;
         T rred = T(0);                           // kNorm: residual of phi_in at the red cell
-        if (!kRR && !kIR && (rsel ? r1c1 : r1c0)) {
+        if (kGS && (rsel ? r1c1 : r1c0)) {
             const T bxl = sbx[s_t][ly][lxr], bxh = sbx[s_t][ly][lxr + 1];
             const T byl = sby[s_t][ly][lxr], byh = sby[s_t][ly + 1][lxr];
             const T bzl = rsel ? bc1 : bc0, bzh = rsel ? bp1 : bp0;
-            T num = bxl * sphi[ly][lxr - 1];
-            num = num + bxh * sphi[ly][lxr + 1];
-            num = num + byl * sphi[ly - 1][lxr];
-            num = num + byh * sphi[ly + 1][lxr];
+            T num = bxl * sphi[cur][ly][lxr - 1];
+            num = num + bxh * sphi[cur][ly][lxr + 1];
+            num = num + byl * sphi[cur][ly - 1][lxr];
+            num = num + byh * sphi[cur][ly + 1][lxr];
             num = num + bzl * (rsel ? Pm1 : Pm0);
             num = num + bzh * (rsel ? Pp1 : Pp0);
             T den = bxl + bxh;
@@ -341,20 +345,20 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             // den (phi_in - phi_new) / h^2 (exact up to rounding)
             if (kNorm) rred = den * (pin - Rcur) * ih2;
         }
-        if (!kRR && !kIR) sR[(t + 4) & 1][ly][lxr] = Rcur;
+        if (kGS) sR[cur][ly][lxr] = Rcur;
         if (kNorm && t >= z0 && t < z1 && writes) {
             accumulate(rred);
             const int cb = 1 - rsel;             // black cell of the pair: full evaluation
-            accumulate(resid_at(cb, s_t, cb ? Pm1 : Pm0, cb ? Pc1 : Pc0, cb ? Pp1 : Pp0, cb ? bc1 : bc0,
+            accumulate(resid_at(cb, s_t, cur, cb ? Pm1 : Pm0, cb ? Pc1 : Pc0, cb ? Pp1 : Pp0, cb ? bc1 : bc0,
                                 cb ? bp1 : bp0, cb ? Fc1 : Fc0));
         }
         if (kRR && t >= z0 && t < z1 && writes) {
-            sR[0][ly][lx0] = resid_at(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
-            sR[0][ly][lx0 + 1] = resid_at(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
+            sR[cur][ly][lx0] = resid_at(0, s_t, cur, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
+            sR[cur][ly][lx0 + 1] = resid_at(1, s_t, cur, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
         }
         if (kIR && t >= z0 && t < z1 && writes) {
-            const T r0 = resid_at(0, s_t, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
-            const T r1 = resid_at(1, s_t, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
+            const T r0 = resid_at(0, s_t, cur, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
+            const T r1 = resid_at(1, s_t, cur, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
             const double d0 = (double)r0, d1 = (double)r1;
             nrm2 += d0 * d0;
             nrm2 += d1 * d1;
@@ -362,27 +366,24 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             st2(a.phi_out + o, Pc0, Pc1);
             st2(a.r32 + o, (float)(rscale * d0), (float)(rscale * d1));
         }
-        __syncthreads();
-        if (kIR) return;
-        if (kRR) {
-            if (t >= z0 && t < z1 && writes && rrow) {
-                if (((t - z0) & 1) == 0) racc = T(0);
-                racc = racc + sR[0][ly][lx0];
-                racc = racc + sR[0][ly][lx0 + 1];
-                racc = racc + sR[0][ly + 1][lx0];
-                racc = racc + sR[0][ly + 1][lx0 + 1];
-                if (((t - z0) & 1) == 1) {
-                    const size_t ci = (size_t)(t >> 1) * ccols + cc;
-                    a.fc[ci] = T(0.125) * racc;
-                    a.phic_out[ci] = T(0);
-                }
+        // 3. (kRR) restriction of plane t-1, whose residuals the previous step wrote
+        const int tb = t - 1;
+        if (kRR && tb >= z0 && tb < z1 && writes && rrow) {
+            const int pb = tb & 1;
+            if (((tb - z0) & 1) == 0) racc = T(0);
+            racc = racc + sR[pb][ly][lx0];
+            racc = racc + sR[pb][ly][lx0 + 1];
+            racc = racc + sR[pb][ly + 1][lx0];
+            racc = racc + sR[pb][ly + 1][lx0 + 1];
+            if (((tb - z0) & 1) == 1) {
+                const size_t ci = (size_t)(tb >> 1) * ccols + cc;
+                a.fc[ci] = T(0.125) * racc;
+                a.phic_out[ci] = T(0);
             }
-            return;
         }
         // 4. black update at plane t-1 on the tile; write the pair of plane t-1
-        const int tb = t - 1;
-        if (tb >= z0 && writes) {
-            const int sb = (tb + 4) & 1;
+        if (kGS && tb >= z0 && writes) {
+            const int sb = tb & 1;
             const int lxb = lx0 + rsel;
             const T bxl = sbx[s_m][ly][lxb], bxh = sbx[s_m][ly][lxb + 1];
             const T byl = sby[s_m][ly][lxb], byh = sby[s_m][ly + 1][lxb];
@@ -405,6 +406,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         }
         Rmm = Rm;
         Rm = Rcur;
+        // 5. stage phi_in of plane t+1 and rho of plane t+2 for the next step
+        if (t + 1 <= z1) {
+            sphi[nxt][ly][lx0] = Pp0;
+            sphi[nxt][ly][lx0 + 1] = Pp1;
+            if (kRho) {
+                srho[cur][ly][lx0] = Rq0;
+                srho[cur][ly][lx0 + 1] = Rq1;
+            }
+        }
+        __syncthreads();
     };
     int t = z0 - 1;
     for (; t + 1 <= z1; t += 2) {
@@ -413,8 +424,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     }
     if (t <= z1) step(t, A);
     if (kNorm || kIR) {
-        // fixed-order block reduction into this tile's partial row
-        __shared__ double red[256];
+        // fixed-order block reduction into this tile's partial row (in the
+        // red-value buffer, free after the last step's barrier)
+        double* red = reinterpret_cast<double*>(&sR[0][0][0]);
+        static_assert(sizeof(sR) >= 256 * sizeof(double), "reduction buffer");
         const int nt = blockDim.x;
         for (int i = threadIdx.x; i < 256; i += nt) red[i] = 0.0;   // every slot, also when nt < 256
         __syncthreads();
@@ -436,16 +449,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     }
 }
 
-// The finest-level prolongation and residual-norm variants are held to 128
-// VGPRs (4 waves per SIMD), so that two 64x8-tile workgroups (7 waves each)
-// or four 32x8 ones share a CU; left alone the compiler gives them a few more
-// registers, which halves the workgroups per CU.  (Capping the stored-
-// coefficient variants too makes them spill, which costs more.)
-template <bool kRho, int kIn, int kOp>
+// 64x8-tile FP64 variants are held to 128 VGPRs (4 waves per SIMD), so that
+// two of their workgroups (7 waves and 79 KB of LDS each) share a CU; left
+// alone the compiler gives several of them a few more registers, which
+// halves the workgroups per CU.  Smaller tiles are limited by LDS first.
+template <typename T, int TX, int TY>
 struct SweepWaves {
-    static constexpr int value = (kRho && (kIn == kInProlong || kOp == kOpSweepNorm)) ? 4 : 1;
+    static constexpr int value = (sizeof(T) == 8 && TX == 64 && TY == 8) ? 4 : 1;
 };
-#define MG_SWEEP_WAVES __attribute__((amdgpu_waves_per_eu(SweepWaves<kRho, kIn, kOp>::value)))
+#define MG_SWEEP_WAVES __attribute__((amdgpu_waves_per_eu(SweepWaves<T, TX, TY>::value)))
 
 template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
 __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES void k_sweep(SweepArgs<T> a) {
@@ -644,15 +656,18 @@ hipError_t launch_multi_mode(const SweepArgs<T>* d, const int* prefix, int nprob
         if constexpr (std::is_same<T, double>::value) {
             if (op == kOpSweepNorm)
                 return launch_multi_t<T, TX, TY, true, kInPlain, kOpSweepNorm>(d, prefix, nprob, tiles, st);
-            if (op == kOpResidRestrict)
-                return launch_multi_t<T, TX, TY, true, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
-            switch (in_mode) {
-                case kInZero: return launch_multi_t<T, TX, TY, true, kInZero>(d, prefix, nprob, tiles, st);
-                case kInPlain: return launch_multi_t<T, TX, TY, true, kInPlain>(d, prefix, nprob, tiles, st);
-                default: return launch_multi_t<T, TX, TY, true, kInProlong>(d, prefix, nprob, tiles, st);
-            }
+            if (op == kOpRefine)
+                return launch_multi_t<T, TX, TY, true, kInCorrect, kOpRefine>(d, prefix, nprob, tiles, st);
+        } else {
+            if (op == kOpSweepNorm || op == kOpRefine) return hipErrorInvalidValue;
         }
-        return hipErrorInvalidValue;
+        if (op == kOpResidRestrict)
+            return launch_multi_t<T, TX, TY, true, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
+        switch (in_mode) {
+            case kInZero: return launch_multi_t<T, TX, TY, true, kInZero>(d, prefix, nprob, tiles, st);
+            case kInPlain: return launch_multi_t<T, TX, TY, true, kInPlain>(d, prefix, nprob, tiles, st);
+            default: return launch_multi_t<T, TX, TY, true, kInProlong>(d, prefix, nprob, tiles, st);
+        }
     }
     if (op == kOpResidRestrict)
         return launch_multi_t<T, TX, TY, false, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
