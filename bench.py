@@ -52,8 +52,8 @@ SWEEP_KERNEL_BYTES_PER_CELL = 32.0
 # for the sweep source it was taken on (SHA-1 of the files below) and tile.
 SWEEP_SOURCES = ("paper_1910_12979_amd/csrc/sweep.hip", "paper_1910_12979_amd/csrc/sweep.h",
                  "paper_1910_12979_amd/csrc/devmath.h")
-SWEEP_TRAFFIC = {"sha1": "9c812f20e3b20c99c22ab9b015087119ce8d7978", "tile": [64, 8, 32], "n": 256,
-                 "read": 470919155, "write": 134217832}
+SWEEP_TRAFFIC = {"sha1": "78059ccf8ca229f6a211a5f517a99c4c7a15c44a", "tile": [64, 8, 32], "n": 256,
+                 "read": 471647189, "write": 134218357}
 
 
 def percentile(xs, q):
@@ -149,7 +149,19 @@ def smoother_leg(args, torch, H, R):
     e1.record(stream)
     e1.synchronize()
     copy_ms = e0.elapsed_time(e1) / args.kernel_reps
-    del a, b
+    # three reads and one write over 4 arrays of the same size (more than the
+    # 256 MB last-level cache holds): the stream pattern of the sweep itself
+    c = torch.empty_like(a).fill_(2.0)
+    o = torch.empty_like(a)
+    torch.addcmul(a, b, c, out=o)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        torch.addcmul(a, b, c, out=o)
+    e1.record(stream)
+    e1.synchronize()
+    stream_ms = e0.elapsed_time(e1) / args.kernel_reps
+    del a, b, c, o
 
     traffic = None
     sha = sweep_source_sha1()
@@ -166,6 +178,7 @@ def smoother_leg(args, torch, H, R):
             "kernel_bytes_per_cell": SWEEP_KERNEL_BYTES_PER_CELL,
             "achieved_at_kernel_bytes": SWEEP_KERNEL_BYTES_PER_CELL * N / (launch_ms * 1e-3) / 1e9,
             "copy_GBs": 2 * 8 * N / (copy_ms * 1e-3) / 1e9,
+            "stream_3r1w_GBs": 4 * 8 * N / (stream_ms * 1e-3) / 1e9,
             "sweep_source_sha1": sha}
 
 
@@ -200,11 +213,11 @@ def mixed_leg(args, torch, macproj, R, phi64):
 
 def batch_leg(args, torch, macproj, inputs, dev):
     """64 independent uneven boxes: one project_batch call against one
-    mac_project call per problem (hierarchies kept, as the batch keeps them)."""
+    mac_project call per problem (hierarchies kept, as the batch keeps them),
+    in mixed precision (FP32 cycles, FP64 refinement) and in FP64."""
     specs = inputs.mixed_batch_specs(64)
     log("batch: generating 64 problems")
     rs = [Restorable(macproj, inputs.make_problem(e, H=H, rho_noise=0.01, seed=s), dev) for e, H, s in specs]
-    params = [macproj.params_of(r.prob) for r in rs]
     cells = sum(r.prob.ncells for r in rs)
     tuned = []
     if args.autotune:
@@ -215,53 +228,57 @@ def batch_leg(args, torch, macproj, inputs, dev):
             Ht.mg_autotune(reps=5)
             tuned.append({"edge": e, "level0_tile": Ht.sweep_config(0)})
             Ht.close()
+    out = {"problems": 64, "cells": cells, "autotuned": tuned}
+    for prec in ("mixed", "fp64"):
+        params = [macproj.params_of(r.prob, precision=prec) for r in rs]
 
-    def run_batch():
-        for r in rs:
-            r.restore()
-        code, st = macproj.project_batch(params, [r.d for r in rs])
-        assert code == 0 and all(s["status_name"] == "OK" and s["rel_resid"] <= 1e-10 for s in st), code
-        return st
+        def run_batch():
+            for r in rs:
+                r.restore()
+            code, st = macproj.project_batch(params, [r.d for r in rs])
+            assert code == 0 and all(s["status_name"] == "OK" and s["rel_resid"] <= 1e-10 for s in st), code
+            return st
 
-    log(f"batch: {args.batch_reps} x project_batch(64)")
-    run_batch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.batch_reps):
-        st = run_batch()
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / args.batch_reps
-    phis = [r.d.phi.clone() for r in rs]
+        log(f"batch ({prec}): {args.batch_reps} x project_batch(64)")
+        run_batch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_reps):
+            st = run_batch()
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / args.batch_reps
+        phis = [r.d.phi.clone() for r in rs]
 
-    log("batch: the same 64 problems one by one")
-    hs = [macproj.Hierarchy(p) for p in params]
+        log(f"batch ({prec}): the same 64 problems one by one")
+        hs = [macproj.Hierarchy(p) for p in params]
 
-    def run_solo():
-        for r in rs:
-            r.restore()
-        out = []
-        for h, r in zip(hs, rs):
-            d = r.d
-            out.append(h.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi))
-        return out
+        def run_solo():
+            for r in rs:
+                r.restore()
+            res = []
+            for h, r in zip(hs, rs):
+                d = r.d
+                res.append(h.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi))
+            return res
 
-    run_solo()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.batch_reps):
-        so = run_solo()
-    torch.cuda.synchronize()
-    ts = (time.perf_counter() - t0) / args.batch_reps
-    identical = all(torch.equal(p, r.d.phi) for p, r in zip(phis, rs))
-    for h in hs:
-        h.close()
-    del rs, phis
-    return {"problems": 64, "cells": cells, "precision": "fp64",
-            "value": 64 / tb, "unit": "solves/s", "ms_per_batch": tb * 1e3,
-            "one_by_one": {"value": 64 / ts, "ms_per_batch": ts * 1e3},
-            "speedup_vs_one_by_one": ts / tb,
-            "cycles_total": sum(s["cycles"] for s in st), "cycles_one_by_one": sum(s["cycles"] for s in so),
-            "phi_identical_to_one_by_one": identical, "autotuned": tuned}
+        run_solo()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_reps):
+            so = run_solo()
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t0) / args.batch_reps
+        identical = all(torch.equal(p, r.d.phi) for p, r in zip(phis, rs))
+        for h in hs:
+            h.close()
+        del phis
+        out[prec] = {"value": 64 / tb, "unit": "solves/s", "ms_per_batch": tb * 1e3,
+                     "one_by_one": {"value": 64 / ts, "ms_per_batch": ts * 1e3},
+                     "speedup_vs_one_by_one": ts / tb,
+                     "cycles_total": sum(s["cycles"] for s in st), "cycles_one_by_one": sum(s["cycles"] for s in so),
+                     "phi_identical_to_one_by_one": identical}
+    del rs
+    return out
 
 
 def serve_leg(args, torch, macproj, inputs, dev):
