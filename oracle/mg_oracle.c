@@ -8,8 +8,9 @@
  *
  * What it computes (arXiv:1910.12979, Sec. 2 and Sec. 3):
  *   the divergence constraint  div(beta0 U) = beta0 S   (Sec. 2, constraint
- *   equation, with the d p0/dt term folded into the caller's S) is enforced by
- *   a projection: solve
+ *   equation, with the d p0/dt term folded into the caller's S, or given per
+ *   layer as w0 = dp0/dt / (Gamma1 p0): orc_rhs_w0, orc_mac_project_w0) is
+ *   enforced by a projection: solve
  *       div((beta0/rho) grad phi) = div(beta0 U) - beta0 S          (1)
  *   by geometric multigrid (Sec. 3: multigrid solvers for the projections) and
  *   correct U -= (1/rho) grad phi on every non-wall face, which is the
@@ -26,6 +27,10 @@
  *       (L phi)_c = h^-2 sum_faces b_f (phi_nb - phi_c),  L phi = f.
  *   The solution is unique up to a constant; the oracle returns the zero-mean
  *   one.
+ *
+ * beta0 from the base-state pressure (Sec. 2, definition of beta0):
+ *   orc_beta0_from_p0 integrates (1/(Gamma1 p0)) dp0/dr layer by layer with
+ *   Gamma1 constant in a layer, exactly ln(p0(b)/p0(a))/Gamma1 over [a, b].
  *
  * Multigrid (V-cycle, as the algorithm is stated for this reference):
  *   nu1 red-black Gauss-Seidel sweeps (red = (i+j+k) even, updated first),
@@ -186,9 +191,13 @@ int orc_face_coeffs(int nx, int ny, int nz, int px, int py, int pz,
 /* Right-hand side f = D(beta0 U) - beta0 S  (MAC divergence).          */
 /* In a periodic direction the high face of the last cell is face 0.  */
 /* ------------------------------------------------------------------ */
-int orc_rhs(int nx, int ny, int nz, int px, int py, int pz, double h,
-            const double* b0c, const double* b0e,
-            const double* u, const double* v, const double* w, const double* S, double* f) {
+/* Full right-hand side of the constraint (Sec. 2, constraint equation):
+ *   f = D(beta0 U) - beta0 (S - w0[k]),  w0[k] = (1/(Gamma1 p0)) dp0/dt of
+ * layer k (orc_dp0_term).  w0 == NULL: the dp0/dt term is folded into S. */
+int orc_rhs_w0(int nx, int ny, int nz, int px, int py, int pz, double h,
+               const double* b0c, const double* b0e,
+               const double* u, const double* v, const double* w, const double* S, const double* w0,
+               double* f) {
     olev L;
     wrap_level(&L, nx, ny, nz, px, py, pz, h, NULL, NULL, NULL);
     for (int k = 0; k < nz; ++k)
@@ -205,8 +214,51 @@ int orc_rhs(int nx, int ny, int nz, int px, int py, int pz, double h,
                 else { wh = w[FZI(&L, i, j, k + 1)]; bh = b0e[k + 1]; }
                 if (k == 0 && pz) bl = b0e[0];
                 double div = (b0c[k] * (uh - ul) + b0c[k] * (vh - vl) + (bh * wh - bl * wl)) / h;
-                f[CI(&L, i, j, k)] = div - b0c[k] * S[CI(&L, i, j, k)];
+                double src = S[CI(&L, i, j, k)];
+                if (w0) src = src - w0[k];
+                f[CI(&L, i, j, k)] = div - b0c[k] * src;
             }
+    return ORC_OK;
+}
+
+int orc_rhs(int nx, int ny, int nz, int px, int py, int pz, double h,
+            const double* b0c, const double* b0e,
+            const double* u, const double* v, const double* w, const double* S, double* f) {
+    return orc_rhs_w0(nx, ny, nz, px, py, pz, h, b0c, b0e, u, v, w, S, NULL, f);
+}
+
+/* ------------------------------------------------------------------ */
+/* Base state (Sec. 2, definition of beta0): with r the height z,      */
+/*   beta0(r) = rho0(0) exp( int_0^r (1/(Gamma1 p0)) dp0/dr' dr' ).    */
+/* Reading: Gamma1 is constant within a layer, so over any part [a,b]  */
+/* of layer k the integral is exactly ln(p0(b)/p0(a)) / Gamma1[k].     */
+/* p0e: p0 at the nz+1 z faces (face 0 is r = 0), p0c: at the layer    */
+/* centres.  beta0 at faces and centres follows by summing the layer   */
+/* integrals from the bottom.                                          */
+/* ------------------------------------------------------------------ */
+int orc_beta0_from_p0(int nz, double rho0_base, const double* p0e, const double* p0c, const double* g1c,
+                      double* b0c, double* b0e) {
+    if (nz < 1 || !(rho0_base > 0.0)) return ORC_ERR_INVALID;
+    for (int k = 0; k <= nz; ++k)
+        if (!(p0e[k] > 0.0) || !isfinite(p0e[k])) return ORC_ERR_INVALID;
+    for (int k = 0; k < nz; ++k)
+        if (!(p0c[k] > 0.0) || !(g1c[k] > 0.0) || !isfinite(p0c[k]) || !isfinite(g1c[k])) return ORC_ERR_INVALID;
+    double acc = 0.0;            /* integral from r = 0 to face k */
+    for (int k = 0; k < nz; ++k) {
+        b0e[k] = rho0_base * exp(acc);
+        b0c[k] = rho0_base * exp(acc + log(p0c[k] / p0e[k]) / g1c[k]);
+        acc += log(p0e[k + 1] / p0e[k]) / g1c[k];
+    }
+    b0e[nz] = rho0_base * exp(acc);
+    return ORC_OK;
+}
+
+/* The dp0/dt term of the constraint per layer: w0[k] = dp0dt[k] / (Gamma1[k] p0[k]). */
+int orc_dp0_term(int nz, const double* p0c, const double* g1c, const double* dp0dt, double* w0) {
+    for (int k = 0; k < nz; ++k) {
+        if (!(p0c[k] > 0.0) || !(g1c[k] > 0.0)) return ORC_ERR_INVALID;
+        w0[k] = dp0dt[k] / (g1c[k] * p0c[k]);
+    }
     return ORC_OK;
 }
 
@@ -628,11 +680,11 @@ void orc_correct(int nx, int ny, int nz, int px, int py, int pz, double h,
 /* stats: [0] cycles, [1] rel residual, [2] mean removed from f,       */
 /*        [3] sum f, [4] sum |f|, [5] ||f||_2 (after mean removal)     */
 /* ------------------------------------------------------------------ */
-int orc_mac_project(int nx, int ny, int nz, int px, int py, int pz, double h,
-                    const double* rho, const double* b0c, const double* b0e, const double* S,
-                    double* u, double* v, double* w, double* phi_out,
-                    double rtol, int max_cycles, int nu1, int nu2, int mode,
-                    double* hist, int hist_len, double* stats) {
+int orc_mac_project_w0(int nx, int ny, int nz, int px, int py, int pz, double h,
+                       const double* rho, const double* b0c, const double* b0e, const double* S,
+                       const double* w0, double* u, double* v, double* w, double* phi_out,
+                       double rtol, int max_cycles, int nu1, int nu2, int mode,
+                       double* hist, int hist_len, double* stats) {
     size_t N = (size_t)nx * ny * nz;
     for (size_t c = 0; c < N; ++c)
         if (!isfinite(rho[c]) || !isfinite(S[c])) return ORC_ERR_NONFINITE;
@@ -648,7 +700,7 @@ int orc_mac_project(int nx, int ny, int nz, int px, int py, int pz, double h,
     double* f = (double*)malloc(N * sizeof(double));
     if (!bx || !by || !bz || !f) { free(bx); free(by); free(bz); free(f); return ORC_ERR_OOM; }
     orc_face_coeffs(nx, ny, nz, px, py, pz, rho, b0c, b0e, bx, by, bz);
-    orc_rhs(nx, ny, nz, px, py, pz, h, b0c, b0e, u, v, w, S, f);
+    orc_rhs_w0(nx, ny, nz, px, py, pz, h, b0c, b0e, u, v, w, S, w0, f);
     double sf = 0.0, saf = 0.0;
     for (size_t c = 0; c < N; ++c) { sf += f[c]; saf += fabs(f[c]); }
     stats[3] = sf; stats[4] = saf;
@@ -676,6 +728,15 @@ int orc_mac_project(int nx, int ny, int nz, int px, int py, int pz, double h,
 done:
     free(bx); free(by); free(bz); free(f);
     return status;
+}
+
+int orc_mac_project(int nx, int ny, int nz, int px, int py, int pz, double h,
+                    const double* rho, const double* b0c, const double* b0e, const double* S,
+                    double* u, double* v, double* w, double* phi_out,
+                    double rtol, int max_cycles, int nu1, int nu2, int mode,
+                    double* hist, int hist_len, double* stats) {
+    return orc_mac_project_w0(nx, ny, nz, px, py, pz, h, rho, b0c, b0e, S, NULL, u, v, w, phi_out, rtol,
+                              max_cycles, nu1, nu2, mode, hist, hist_len, stats);
 }
 
 int orc_max_threads(void) {

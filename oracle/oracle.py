@@ -57,6 +57,11 @@ def lib():
         i, d = ctypes.c_int, ctypes.c_double
         L.orc_face_coeffs.argtypes = [i, i, i, i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_rhs.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_rhs_w0.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_beta0_from_p0.argtypes = [i, d, _dp, _dp, _dp, _dp, _dp]
+        L.orc_dp0_term.argtypes = [i, _dp, _dp, _dp, _dp]
+        L.orc_mac_project_w0.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                         d, i, i, i, i, _dp, i, _dp]
         L.orc_apply.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp]
         L.orc_residual.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_rbgs.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, i]
@@ -110,12 +115,44 @@ def face_coeffs(n, periodic, rho, b0c, b0e):
     return bx, by, bz
 
 
-def rhs(n, periodic, h, b0c, b0e, u, v, w, S):
-    """f = D(beta0 U) - beta0 S (before mean removal)."""
+def rhs(n, periodic, h, b0c, b0e, u, v, w, S, w0=None):
+    """f = D(beta0 U) - beta0 (S - w0[k]) (before mean removal); w0 = None
+    leaves the dp0/dt term folded into S."""
     nx, ny, nz = n
     f = np.empty((nz, ny, nx))
-    lib().orc_rhs(*_shape_args(n, periodic), h, _p(b0c), _p(b0e), _p(u), _p(v), _p(w), _p(S), _p(f))
+    if w0 is None:
+        lib().orc_rhs(*_shape_args(n, periodic), h, _p(b0c), _p(b0e), _p(u), _p(v), _p(w), _p(S), _p(f))
+    else:
+        w0 = np.ascontiguousarray(w0, dtype=np.float64)
+        lib().orc_rhs_w0(*_shape_args(n, periodic), h, _p(b0c), _p(b0e), _p(u), _p(v), _p(w), _p(S), _p(w0),
+                         _p(f))
     return f
+
+
+def beta0_from_p0(rho0_base, p0_edge, p0_cc, gamma1_cc):
+    """beta0 at layer centres and z faces from p0 (faces and centres) and the
+    layer Gamma1 (Sec. 2, definition of beta0; see mg_oracle.c)."""
+    nz = len(p0_cc)
+    b0c = np.empty(nz)
+    b0e = np.empty(nz + 1)
+    st = lib().orc_beta0_from_p0(nz, float(rho0_base), _p(np.ascontiguousarray(p0_edge, dtype=np.float64)),
+                                 _p(np.ascontiguousarray(p0_cc, dtype=np.float64)),
+                                 _p(np.ascontiguousarray(gamma1_cc, dtype=np.float64)), _p(b0c), _p(b0e))
+    if st != 0:
+        raise ValueError(f"orc_beta0_from_p0: {STATUS.get(st, st)}")
+    return b0c, b0e
+
+
+def dp0_term(p0_cc, gamma1_cc, dp0dt_cc):
+    """w0[k] = dp0dt[k] / (Gamma1[k] p0[k]), the dp0/dt term of the constraint per layer."""
+    nz = len(p0_cc)
+    w0 = np.empty(nz)
+    st = lib().orc_dp0_term(nz, _p(np.ascontiguousarray(p0_cc, dtype=np.float64)),
+                            _p(np.ascontiguousarray(gamma1_cc, dtype=np.float64)),
+                            _p(np.ascontiguousarray(dp0dt_cc, dtype=np.float64)), _p(w0))
+    if st != 0:
+        raise ValueError(f"orc_dp0_term: {STATUS.get(st, st)}")
+    return w0
 
 
 def apply(n, periodic, h, coeffs, phi):
@@ -220,12 +257,28 @@ class Hierarchy:
         return st, phi, hist[: cyc.value + 1]
 
 
+def mac_project_full(prob, mode="algorithm", rtol=None, max_cycles=None):
+    """The projection of a problem whose base state is given as p0 and
+    Gamma1 (inputs.make_full_problem): beta0 from p0, the dp0/dt term of the
+    constraint, then the projection with the full right-hand side.  Returns
+    mac_project's dict plus beta0_cc, beta0_edge and w0."""
+    b0c, b0e = beta0_from_p0(prob.rho0_base, prob.p0_edge, prob.p0_cc, prob.gamma1_cc)
+    w0 = dp0_term(prob.p0_cc, prob.gamma1_cc, prob.dp0dt_cc)
+    out = _project(prob, b0c, b0e, w0, mode, rtol, max_cycles, None, None)
+    out.update(beta0_cc=b0c, beta0_edge=b0e, w0=w0)
+    return out
+
+
 def mac_project(prob, mode="algorithm", rtol=None, max_cycles=None, nu1=None, nu2=None):
     """The whole projection on host copies of ``prob`` (an inputs.Problem).
 
     Returns a dict with status, phi (zero mean), corrected u/v/w, the residual
     history and the RHS statistics.
     """
+    return _project(prob, prob.beta0_cc, prob.beta0_edge, None, mode, rtol, max_cycles, nu1, nu2)
+
+
+def _project(prob, b0c, b0e, w0, mode, rtol, max_cycles, nu1, nu2):
     n, per = prob.n, prob.periodic
     rtol = prob.rtol if rtol is None else rtol
     max_cycles = (prob.max_cycles if mode == "algorithm" else 200) if max_cycles is None else max_cycles
@@ -236,10 +289,11 @@ def mac_project(prob, mode="algorithm", rtol=None, max_cycles=None, nu1=None, nu
     phi = np.zeros((nz, ny, nx))
     hist = np.full(max_cycles + 1, np.nan)
     stats = np.zeros(8)
-    st = lib().orc_mac_project(*_shape_args(n, per), prob.dx, _p(prob.rho), _p(prob.beta0_cc),
-                               _p(prob.beta0_edge), _p(prob.S), _p(u), _p(v), _p(w), _p(phi),
-                               rtol, max_cycles, nu1, nu2, 1 if mode == "definition" else 0,
-                               _p(hist), len(hist), _p(stats))
+    w0p = _p(np.ascontiguousarray(w0, dtype=np.float64)) if w0 is not None else None
+    st = lib().orc_mac_project_w0(*_shape_args(n, per), prob.dx, _p(prob.rho), _p(b0c), _p(b0e), _p(prob.S),
+                                  w0p, _p(u), _p(v), _p(w), _p(phi),
+                                  rtol, max_cycles, nu1, nu2, 1 if mode == "definition" else 0,
+                                  _p(hist), len(hist), _p(stats))
     cycles = int(stats[0])
     return {"status": st, "status_name": STATUS.get(st, str(st)), "phi": phi, "u": u, "v": v, "w": w,
             "cycles": cycles, "hist": hist[: cycles + 1], "rel_resid": stats[1],

@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "make_problem", "stratified_base_state",
-    "mixed_batch_specs", "serving_requests",
+    "make_full_problem", "mixed_batch_specs", "serving_requests",
     "SMALL_BOX", "STEEP_256", "MIXED_512",
 ]
 
@@ -54,6 +54,14 @@ class Problem:
     post_sweeps: int = 2
     seed: int = 0
     H: float = 0.3
+    # base state given as p0 and Gamma1 instead of beta0 (make_full_problem):
+    # beta0 and the dp0/dt term of the constraint are then computed by the
+    # method; beta0_cc / beta0_edge are None
+    rho0_base: float | None = None
+    p0_cc: np.ndarray | None = None       # (nz,)
+    p0_edge: np.ndarray | None = None     # (nz+1,)
+    gamma1_cc: np.ndarray | None = None   # (nz,)
+    dp0dt_cc: np.ndarray | None = None    # (nz,)
 
     @property
     def ncells(self) -> int:
@@ -62,8 +70,10 @@ class Problem:
 
     def copy(self) -> "Problem":
         out = dataclasses.replace(self)
-        for name in ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w"):
-            setattr(out, name, getattr(self, name).copy())
+        for name in ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w",
+                     "p0_cc", "p0_edge", "gamma1_cc", "dp0dt_cc"):
+            a = getattr(self, name)
+            setattr(out, name, None if a is None else a.copy())
         return out
 
 
@@ -141,6 +151,59 @@ def make_problem(n, *, H=0.3, rho_noise=0.01, S_kind="random", S_amp=0.1,
     return Problem(n=(nx, ny, nz), dx=float(dx), periodic=periodic, rho=rho,
                    beta0_cc=b0c, beta0_edge=b0e, S=np.ascontiguousarray(S),
                    u=u, v=v, w=w, rtol=rtol, max_cycles=max_cycles, seed=seed, H=H)
+
+
+def make_full_problem(n, *, Hp=0.25, gamma1=(5.0 / 3.0, 1.3), rho0_base=1.0, rho_noise=0.01, S_amp=0.1,
+                      q_amp=0.05, seed=0, dx=None, periodic=(True, True, False), rtol=1e-10,
+                      max_cycles=100) -> Problem:
+    """A problem whose base state is given the way the method carries it:
+    p0 and the layer Gamma1, from which beta0 follows (Sec. 2, definition of
+    beta0), plus dp0/dt, which enters the constraint's right-hand side.
+
+    p0 = exp(-z/Hp) at the z faces and layer centres; Gamma1 varies linearly
+    over the layers from gamma1[0] at the bottom to gamma1[1] at the top;
+    rho = exp(-z/(Gm Hp)) (1 + rho_noise N(0,1)) with Gm the mean of the two
+    Gamma1 values.  S = S' + q_k: S' = S_amp N(0,1) with each layer's mean
+    removed, q_k = q_amp cos(pi z_k) a layer-mean expansion, and dp0/dt_k =
+    q_k Gamma1_k p0_k, so that the dp0/dt term takes up the layer-mean
+    expansion (as the base state's pressure change does in the method) and the
+    constraint is solvable whatever beta0 the base state gives.  Draw order as
+    make_problem: rho noise, S' noise, u, v, w.
+    """
+    if isinstance(n, int):
+        n = (n, n, n)
+    nx, ny, nz = (int(a) for a in n)
+    if dx is None:
+        dx = 1.0 / nx
+    periodic = tuple(bool(p) for p in periodic)
+    rng = np.random.default_rng(seed)
+    zc = (np.arange(nz, dtype=np.float64) + 0.5) * dx
+    ze = np.arange(nz + 1, dtype=np.float64) * dx
+    p0c, p0e = np.exp(-zc / Hp), np.exp(-ze / Hp)
+    frac = (np.arange(nz, dtype=np.float64) + 0.5) / nz
+    g1 = gamma1[0] + (gamma1[1] - gamma1[0]) * frac
+    gm = 0.5 * (gamma1[0] + gamma1[1])
+    xi_rho = rng.standard_normal((nz, ny, nx))
+    rho = rho0_base * np.exp(-zc / (gm * Hp))[:, None, None] * (1.0 + rho_noise * xi_rho)
+    Sp = S_amp * rng.standard_normal((nz, ny, nx))
+    Sp -= Sp.mean(axis=(1, 2), keepdims=True)
+    q = q_amp * np.cos(np.pi * zc)
+    S = Sp + q[:, None, None]
+    dp0dt = q * g1 * p0c
+    u = np.zeros((nz, ny, nx + 1))
+    v = np.zeros((nz, ny + 1, nx))
+    w = np.zeros((nz + 1, ny, nx))
+    u[:, :, :nx] = rng.standard_normal((nz, ny, nx))
+    v[:, :ny, :] = rng.standard_normal((nz, ny, nx))
+    if nz > 1:
+        w[1:nz] = rng.standard_normal((nz - 1, ny, nx))
+    if periodic[2]:
+        w[0] = rng.standard_normal((ny, nx))
+    _fill_faces(u, v, w, periodic)
+    return Problem(n=(nx, ny, nz), dx=float(dx), periodic=periodic, rho=rho,
+                   beta0_cc=None, beta0_edge=None, S=np.ascontiguousarray(S),
+                   u=u, v=v, w=w, rtol=rtol, max_cycles=max_cycles, seed=seed, H=Hp,
+                   rho0_base=float(rho0_base), p0_cc=p0c, p0_edge=p0e, gamma1_cc=g1, dp0dt_cc=dp0dt)
 
 
 # Named workloads (unit box, periodic in x and y, solid walls in z).

@@ -383,3 +383,74 @@ def test_oracle_error_codes():
     z = I.make_problem(8, S_kind="zero", vel_scale=0.0, seed=1)
     r = O.mac_project(z)
     assert r["status"] == 0 and r["cycles"] == 0 and np.all(r["phi"] == 0.0)
+
+
+# ------------------------------------------- base state and the dp0/dt term
+def _levels(nz, dx=None):
+    dx = 1.0 / nz if dx is None else dx
+    return (np.arange(nz) + 0.5) * dx, np.arange(nz + 1) * dx
+
+
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.2])
+def test_beta0_isothermal_closed_form(gamma):
+    """p0 = P exp(-z/Hp) with constant Gamma1: beta0 = rho0(0) exp(-z/(Gamma1 Hp))
+    (Sec. 2, definition of beta0, integrated by hand)."""
+    nz, Hp, rho0 = 64, 0.2, 3.0
+    zc, ze = _levels(nz)
+    b0c, b0e = O.beta0_from_p0(rho0, 7.0 * np.exp(-ze / Hp), 7.0 * np.exp(-zc / Hp), np.full(nz, gamma))
+    assert rel(b0c, rho0 * np.exp(-zc / (gamma * Hp))) < 1e-13
+    assert rel(b0e, rho0 * np.exp(-ze / (gamma * Hp))) < 1e-13
+
+
+def test_beta0_two_layer_closed_form():
+    """Gamma1 = g1 below z = 1/2 and g2 above, exponential p0: beta0 decays with
+    scale g1 Hp, then g2 Hp, and is continuous at z = 1/2."""
+    nz, Hp, g1, g2 = 32, 0.3, 1.4, 1.9
+    zc, ze = _levels(nz)
+    gam = np.where(zc < 0.5, g1, g2)
+    b0c, b0e = O.beta0_from_p0(1.0, np.exp(-ze / Hp), np.exp(-zc / Hp), gam)
+    def exact(z):
+        return np.where(z <= 0.5, np.exp(-z / (g1 * Hp)), np.exp(-0.5 / (g1 * Hp) - (z - 0.5) / (g2 * Hp)))
+    assert rel(b0c, exact(zc)) < 1e-13
+    assert rel(b0e, exact(ze)) < 1e-13
+
+
+def test_beta0_polytrope_closed_form():
+    """Non-exponential p0 = (1 - z/L)^m with constant Gamma1:
+    beta0 = rho0(0) (p0(z)/p0(0))^(1/Gamma1)."""
+    nz, L, m, gamma = 48, 1.7, 2.5, 5.0 / 3.0
+    zc, ze = _levels(nz)
+    b0c, b0e = O.beta0_from_p0(2.0, (1 - ze / L) ** m, (1 - zc / L) ** m, np.full(nz, gamma))
+    assert rel(b0c, 2.0 * (1 - zc / L) ** (m / gamma)) < 1e-13
+    assert rel(b0e, 2.0 * (1 - ze / L) ** (m / gamma)) < 1e-13
+
+
+def test_dp0_term_enters_like_a_layer_shift_of_S():
+    """f with the dp0/dt term equals f of S - w0[k] (the folded form), bit for
+    bit, and w0 = dp0/dt / (Gamma1 p0) layer by layer."""
+    p = I.make_full_problem((6, 4, 8), seed=9, dx=0.125)
+    b0c, b0e = O.beta0_from_p0(p.rho0_base, p.p0_edge, p.p0_cc, p.gamma1_cc)
+    w0 = O.dp0_term(p.p0_cc, p.gamma1_cc, p.dp0dt_cc)
+    assert np.allclose(w0 * p.gamma1_cc * p.p0_cc, p.dp0dt_cc, rtol=1e-15, atol=0)
+    f1 = O.rhs(p.n, p.periodic, p.dx, b0c, b0e, p.u, p.v, p.w, p.S, w0=w0)
+    f2 = O.rhs(p.n, p.periodic, p.dx, b0c, b0e, p.u, p.v, p.w, p.S - w0[:, None, None])
+    assert np.array_equal(f1, f2)
+
+
+@pytest.mark.parametrize("per", [(True, True, False), (False, False, False)])
+def test_full_constraint_after_projection(per):
+    """With beta0 from p0 and the dp0/dt term, the projected velocity satisfies
+    D(beta0 U) = beta0 (S - dp0/dt / (Gamma1 p0)) to the solver's tolerance (Sec. 2,
+    constraint equation), and the generated problem is solvable only with the
+    term's sign as in the constraint (the opposite sign is rejected)."""
+    p = I.make_full_problem(16, seed=12, periodic=per)
+    res = O.mac_project_full(p, mode="definition")
+    assert res["status"] == 0, res["status_name"]
+    f = O.rhs(p.n, per, p.dx, res["beta0_cc"], res["beta0_edge"], p.u, p.v, p.w, p.S, w0=res["w0"])
+    after = O.rhs(p.n, per, p.dx, res["beta0_cc"], res["beta0_edge"], res["u"], res["v"], res["w"], p.S,
+                  w0=res["w0"])
+    assert abs(f.sum()) <= 1e-12 * np.abs(f).sum()
+    assert np.linalg.norm(after - after.mean()) <= 1e-12 * np.linalg.norm(f)
+    q = p.copy()
+    q.dp0dt_cc = -p.dp0dt_cc
+    assert O.mac_project_full(q)["status_name"] == "INCOMPATIBLE_RHS"
