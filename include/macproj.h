@@ -155,6 +155,30 @@ int mac_project(mg_handle h, const double* rho, const double* beta0_cc,
  * *rel_resid_out (nullable) = ||rhs - L phi||_2 / ||rhs||_2 afterwards. */
 int mg_vcycle(mg_handle h, double* phi, const double* rhs, double* rel_resid_out, void* stream);
 
+/* ---- base state given as p0 and Gamma1 ---------------------------------- */
+
+/* beta0 from the base-state pressure (Sec. 2, definition of beta0): with r
+ * the height z, beta0(r) = rho0_base exp(integral from 0 to r of
+ * (1/(Gamma1 p0)) dp0/dr').  Gamma1 is taken constant within each of the nz
+ * layers, so the integral over any part [a, b] of layer k is exactly
+ * ln(p0(b)/p0(a)) / Gamma1[k].  Device arrays: p0_edge (nz+1, at z = k dx;
+ * face 0 is r = 0), p0_cc and gamma1_cc (nz, layer centres); outputs
+ * beta0_cc (nz) and beta0_edge (nz+1), caller-owned.  Stream-ordered:
+ * returns after enqueueing one small kernel.  Non-positive or non-finite p0
+ * or Gamma1 give non-finite beta0, which mac_project then rejects
+ * (MG_ERR_NONFINITE). */
+int mg_beta0_from_p0(int32_t nz, double rho0_base, const double* p0_edge, const double* p0_cc,
+                     const double* gamma1_cc, double* beta0_cc, double* beta0_edge, void* stream);
+
+/* mac_project with the full right-hand side of the constraint (Sec. 2):
+ * f = D(beta0 U) - beta0 (S - w0[k]), w0[k] = dp0dt_cc[k] / (gamma1_cc[k]
+ * p0_cc[k]) per layer, instead of a dp0/dt term folded into S.  p0_cc,
+ * gamma1_cc, dp0dt_cc: device arrays of nz layer values.  Everything else
+ * (arguments, statuses, blocking) as mac_project. */
+int mac_project_full(mg_handle h, const double* rho, const double* beta0_cc, const double* beta0_edge,
+                     const double* S, const double* p0_cc, const double* gamma1_cc, const double* dp0dt_cc,
+                     double* u, double* v, double* w, double* phi, mg_stats* stats, void* stream);
+
 /* ---- single steps of the cycle, for step-by-step verification ---------- */
 typedef enum {
     MG_STEP_SMOOTH = 0,          /* `arg` red-black GS sweeps on level l (phi_l, f_l) */

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_coeff_rhs(
     const double* __restrict__ b0c, const double* __restrict__ b0e, const double* __restrict__ S,
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     double* __restrict__ bx, double* __restrict__ by, double* __restrict__ bz,
-    double* __restrict__ f, double* __restrict__ partials) {
+    double* __restrict__ f, double* __restrict__ partials, const double* __restrict__ w0) {
     const size_t N = (size_t)nx * ny * nz;
     double sf = 0.0, saf = 0.0, bad = 0.0, nonfin = 0.0;
     for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock) {
@@ -143,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_coeff_rhs(
             }
             if (k == 0 && pz) bl = b0e[0];
             double sc = S[c];
+            if (w0) sc = sc - w0[k];         // the dp0/dt term of the constraint, per layer
             if (!finite_d(ul) || !finite_d(uh) || !finite_d(vl) || !finite_d(vh) ||
                 !finite_d(wl) || !finite_d(wh) || !finite_d(sc))
                 nonfin += 1.0;
@@ -558,6 +559,50 @@ __global__ void k_accumulate(double* __restrict__ phi, const float* __restrict__
 // res[0] = sum r^2: scales[0] <- scales[1] (the scale the FP32 residual now
 // holds), scales[1] <- the power of two nearest 1/rms(r) (1 for a zero or
 // non-finite residual), the scale for the next FP32 residual.
+// ---------------------------------------------------------------------------
+// Base state (Sec. 2, definition of beta0): with r the height z, beta0 is
+// rho0(0) exp of the integral of (1/(Gamma1 p0)) dp0/dr from the bottom.
+// Gamma1 is constant in a layer, so the integral over any part [a, b] of
+// layer k is ln(p0(b)/p0(a)) / Gamma1[k].  One workgroup: the per-layer
+// logarithms in parallel (into the outputs), one thread sums them from the
+// bottom in order, then the exponentials in parallel.  Non-positive or
+// non-finite p0 / Gamma1 give non-finite beta0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_beta0_from_p0(int nz, double rho0, const double* __restrict__ p0e,
+                                                        const double* __restrict__ p0c,
+                                                        const double* __restrict__ g1c, double* __restrict__ b0c,
+                                                        double* __restrict__ b0e) {
+    for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+        const double g = g1c[k];
+        const double ok = (p0e[k] > 0.0 && p0e[k + 1] > 0.0 && p0c[k] > 0.0 && g > 0.0) ? 1.0 : NAN;
+        b0e[k] = ok * (log(p0e[k + 1] / p0e[k]) / g);     // layer integral
+        b0c[k] = ok * (log(p0c[k] / p0e[k]) / g);         // bottom face to the centre
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;                                  // integral from r = 0 to face k
+        for (int k = 0; k < nz; ++k) {
+            const double layer = b0e[k];
+            b0e[k] = acc;
+            acc += layer;
+        }
+        b0e[nz] = acc;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k <= nz; k += blockDim.x) {
+        const double below = b0e[k];
+        if (k < nz) b0c[k] = rho0 * exp(below + b0c[k]);
+        b0e[k] = rho0 * exp(below);
+    }
+}
+
+// w0[k] = dp0dt[k] / (Gamma1[k] p0[k]), the dp0/dt term of the constraint per layer
+__global__ void k_dp0_term(int nz, const double* __restrict__ p0c, const double* __restrict__ g1c,
+                           const double* __restrict__ dp0dt, double* __restrict__ w0) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nz) w0[k] = dp0dt[k] / (g1c[k] * p0c[k]);
+}
+
 __device__ inline void next_scale(const double* res, double* scales, double n) {
     const double rms = sqrt(res[0] / n);
     double s = 1.0;
@@ -601,10 +646,10 @@ int num_blocks_for_partials(const Shape& s) { return partial_blocks(s.N()); }
 hipError_t launch_coeff_rhs(const Shape& s, int px, int py, int pz, double h, const double* rho,
                             const double* b0c, const double* b0e, const double* S, const double* u,
                             const double* v, const double* w, double* bx, double* by, double* bz,
-                            double* f, double* partials, int* nparts, hipStream_t st) {
+                            double* f, double* partials, int* nparts, hipStream_t st, const double* w0) {
     int nb = partial_blocks(s.N());
     hipLaunchKernelGGL(k_coeff_rhs<true>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, px, py, pz, h,
-                       rho, b0c, b0e, S, u, v, w, bx, by, bz, f, partials);
+                       rho, b0c, b0e, S, u, v, w, bx, by, bz, f, partials, w0);
     *nparts = nb;
     return hipGetLastError();
 }
@@ -614,7 +659,8 @@ hipError_t launch_coeff(const Shape& s, int px, int py, int pz, const double* rh
                         int* nparts, hipStream_t st) {
     int nb = partial_blocks(s.N());
     hipLaunchKernelGGL(k_coeff_rhs<false>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, px, py, pz, 1.0,
-                       rho, b0c, b0e, nullptr, nullptr, nullptr, nullptr, bx, by, bz, nullptr, partials);
+                       rho, b0c, b0e, nullptr, nullptr, nullptr, nullptr, bx, by, bz, nullptr, partials,
+                       (const double*)nullptr);
     *nparts = nb;
     return hipGetLastError();
 }
@@ -770,6 +816,18 @@ hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* sc
 hipError_t launch_accumulate(double* phi, const float* e32, size_t n, const double* scale_inv,
                              hipStream_t st) {
     hipLaunchKernelGGL(k_accumulate, dim3(stream_blocks(n)), dim3(kBlock), 0, st, phi, e32, n, scale_inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta0_from_p0(int nz, double rho0, const double* p0e, const double* p0c, const double* g1c,
+                                double* b0c, double* b0e, hipStream_t st) {
+    hipLaunchKernelGGL(k_beta0_from_p0, dim3(1), dim3(1024), 0, st, nz, rho0, p0e, p0c, g1c, b0c, b0e);
+    return hipGetLastError();
+}
+
+hipError_t launch_dp0_term(int nz, const double* p0c, const double* g1c, const double* dp0dt, double* w0,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_dp0_term, dim3((nz + 255) / 256), dim3(256), 0, st, nz, p0c, g1c, dp0dt, w0);
     return hipGetLastError();
 }
 

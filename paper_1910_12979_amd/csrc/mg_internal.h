@@ -94,7 +94,13 @@ hipError_t launch_coeff_rhs(const Shape& s, int px, int py, int pz, double h,
                             const double* rho, const double* b0c, const double* b0e,
                             const double* S, const double* u, const double* v, const double* w,
                             double* bx, double* by, double* bz, double* f,
-                            double* partials, int* nparts, hipStream_t st);
+                            double* partials, int* nparts, hipStream_t st, const double* w0 = nullptr);
+// beta0 at layer centres and z faces from p0 (faces, centres) and the layer
+// Gamma1 (one workgroup); w0[k] = dp0dt[k] / (Gamma1[k] p0[k]).
+hipError_t launch_beta0_from_p0(int nz, double rho0, const double* p0e, const double* p0c, const double* g1c,
+                                double* b0c, double* b0e, hipStream_t st);
+hipError_t launch_dp0_term(int nz, const double* p0c, const double* g1c, const double* dp0dt, double* w0,
+                           hipStream_t st);
 // Coefficients only (no right-hand side).  Partials as above (sum f = 0).
 hipError_t launch_coeff(const Shape& s, int px, int py, int pz, const double* rho,
                         const double* b0c, const double* b0e, double* bx, double* by,

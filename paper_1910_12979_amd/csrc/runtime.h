@@ -38,6 +38,7 @@ struct mg_hierarchy {
     double* rho_own = nullptr;    // copies made by mg_set_coefficients
     double* b0c_own = nullptr;
     double* b0e_own = nullptr;
+    double* w0 = nullptr;         // per-layer dp0/dt term (mac_project_full)
     mg::RhoArgs rho{};            // finest-level coefficient source of the current solve
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // Replayable V-cycles (FP64 solve): one cycle plus the next residual
@@ -63,7 +64,8 @@ size_t workspace_bytes(const mg_params* p);
 int setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_hierarchy** out);
 int destroy(mg_hierarchy* H);
 int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
-            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st);
+            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st,
+            const double* w0 = nullptr);
 double model_bytes(const mg_params& p, int cycles, int mixed);
 // First level run by the one-workgroup bottom solver (phi and f of it and of
 // every coarser level fit in its LDS), or -1.
@@ -75,5 +77,6 @@ double residual_scale(double norm2_sqrt, size_t n);
 template <typename T>
 void bottom_args(mg_hierarchy* H, int l, BottomArgs<T>& a);
 int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
-                       const double* S, const double* u, const double* v, const double* w, hipStream_t st);
+                       const double* S, const double* u, const double* v, const double* w, hipStream_t st,
+                       const double* w0 = nullptr);
 }  // namespace mg

@@ -130,6 +130,7 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
     double* rho_own = (double*)take(N0 * 8);
     double* b0c_own = (double*)take((size_t)p->n[2] * 8);
     double* b0e_own = (double*)take((size_t)(p->n[2] + 1) * 8);
+    double* w0 = (double*)take((size_t)p->n[2] * 8);
     if (H) {
         H->minv = minv;
         H->partials = partials;
@@ -139,6 +140,7 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
         H->rho_own = rho_own;
         H->b0c_own = b0c_own;
         H->b0e_own = b0e_own;
+        H->w0 = w0;
     }
     return off;
 }
@@ -243,12 +245,12 @@ static int read_scalars(mg_hierarchy* H, int first, int count, hipStream_t st) {
 
 int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
                        const double* S, const double* u, const double* v, const double* w,
-                       hipStream_t st) {
+                       hipStream_t st, const double* w0) {
     Level& L0 = H->lev[0];
     int np = 0;
     if (S) {
         HIPCHK(launch_coeff_rhs(shape_of(L0), H->px, H->py, H->pz, L0.h, rho, b0c, b0e, S, u, v, w, L0.d.bx,
-                                L0.d.by, L0.d.bz, L0.d.f, H->partials, &np, st));
+                                L0.d.by, L0.d.bz, L0.d.f, H->partials, &np, st, w0));
     } else {
         HIPCHK(launch_coeff(shape_of(L0), H->px, H->py, H->pz, rho, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
                             H->partials, &np, st));
@@ -846,7 +848,7 @@ static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStrea
 
 static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
                         const double* S, double* u, double* v, double* w, double* phi_out, mg_stats* stats,
-                        hipStream_t st) {
+                        hipStream_t st, const double* w0) {
     if (!H || !rho || !b0c || !b0e || !S || !u || !v || !w) {
         set_error("null argument to mac_project");
         return MG_ERR_INVALID_ARG;
@@ -865,7 +867,7 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         rho_src = H->rho_own;
     }
     H->rho = RhoArgs{rho_src, b0c, b0e, H->px, H->py, H->pz};
-    int rc = build_coefficients(H, rho, b0c, b0e, S, u, v, w, st);
+    int rc = build_coefficients(H, rho, b0c, b0e, S, u, v, w, st, w0);
     if (rc) return rc;
     rc = read_scalars(H, kSlotRhs * kReduceWidth, kReduceWidth, st);
     if (rc) return rc;
@@ -928,8 +930,8 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
 }
 
 int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
-            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st) {
-    int rc = project_impl(H, rho, b0c, b0e, S, u, v, w, phi_out, stats, st);
+            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st, const double* w0) {
+    int rc = project_impl(H, rho, b0c, b0e, S, u, v, w, phi_out, stats, st, w0);
     if (H) H->rho32_on = false;
     // the caller's rho may not outlive the call: later mg_vcycle / step calls
     // use the stored finest-level coefficients (bit-identical values)
@@ -1160,6 +1162,37 @@ int mac_project(mg_handle h, const double* rho, const double* beta0_cc, const do
         set_error("internal error in mac_project");
         return MG_ERR_HIP;
     }
+}
+
+int mac_project_full(mg_handle h, const double* rho, const double* beta0_cc, const double* beta0_edge,
+                     const double* S, const double* p0_cc, const double* gamma1_cc, const double* dp0dt_cc,
+                     double* u, double* v, double* w, double* phi, mg_stats* stats, void* stream) {
+    if (!h || !p0_cc || !gamma1_cc || !dp0dt_cc) {
+        set_error("null argument to mac_project_full");
+        return MG_ERR_INVALID_ARG;
+    }
+    try {
+        hipStream_t st = (hipStream_t)stream;
+        const hipError_t e = launch_dp0_term(h->p.n[2], p0_cc, gamma1_cc, dp0dt_cc, h->w0, st);
+        if (e != hipSuccess) return hip_fail(e, "launch_dp0_term", __LINE__);
+        return project(h, rho, beta0_cc, beta0_edge, S, u, v, w, phi, stats, st, h->w0);
+    } catch (...) {
+        set_error("internal error in mac_project_full");
+        return MG_ERR_HIP;
+    }
+}
+
+int mg_beta0_from_p0(int32_t nz, double rho0_base, const double* p0_edge, const double* p0_cc,
+                     const double* gamma1_cc, double* beta0_cc, double* beta0_edge, void* stream) {
+    if (nz < 1 || !(rho0_base > 0.0) || !std::isfinite(rho0_base) || !p0_edge || !p0_cc || !gamma1_cc ||
+        !beta0_cc || !beta0_edge) {
+        set_error("bad mg_beta0_from_p0 arguments");
+        return MG_ERR_INVALID_ARG;
+    }
+    const hipError_t e = launch_beta0_from_p0(nz, rho0_base, p0_edge, p0_cc, gamma1_cc, beta0_cc, beta0_edge,
+                                              (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch_beta0_from_p0", __LINE__);
+    return MG_OK;
 }
 
 int mg_vcycle(mg_handle h, double* phi, const double* rhs, double* rel_resid_out, void* stream) {

@@ -101,6 +101,8 @@ def lib():
         L.mg_sweep_config.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.mg_set_graphs.argtypes = [vp, i32]
         L.mg_set_bottom.argtypes = [vp, i32]
+        L.mg_beta0_from_p0.argtypes = [i32, d, vp, vp, vp, vp, vp, vp]
+        L.mac_project_full.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -227,6 +229,28 @@ class Hierarchy:
         out["code"] = code
         return out
 
+    def mac_project_full(self, rho, beta0_cc, beta0_edge, S, p0_cc, gamma1_cc, dp0dt_cc, u, v, w, phi=None,
+                         stream=None, allow=(MG_OK,)):
+        """mac_project with the dp0/dt term of the constraint given per layer
+        (p0, Gamma1 and dp0/dt at the layer centres)."""
+        import torch
+        sh = field_shapes(self.n)
+        f64 = torch.float64
+        nz = self.n[2]
+        st = Stats()
+        code = lib().mac_project_full(self._h, _ptr(rho, f64, sh["rho"], "rho"),
+                                      _ptr(beta0_cc, f64, sh["beta0_cc"], "beta0_cc"),
+                                      _ptr(beta0_edge, f64, sh["beta0_edge"], "beta0_edge"),
+                                      _ptr(S, f64, sh["S"], "S"), _ptr(p0_cc, f64, (nz,), "p0_cc"),
+                                      _ptr(gamma1_cc, f64, (nz,), "gamma1_cc"),
+                                      _ptr(dp0dt_cc, f64, (nz,), "dp0dt_cc"), _ptr(u, f64, sh["u"], "u"),
+                                      _ptr(v, f64, sh["v"], "v"), _ptr(w, f64, sh["w"], "w"),
+                                      _ptr(phi, f64, sh["phi"], "phi"), ctypes.byref(st), _stream(stream))
+        _check(code, allow)
+        out = st.as_dict()
+        out["code"] = code
+        return out
+
     def mg_vcycle(self, phi, rhs, stream=None):
         import torch
         sh = field_shapes(self.n)["phi"]
@@ -287,11 +311,29 @@ def mg_destroy(h: Hierarchy):
 
 
 # ---------------------------------------------------------------- problems
-def to_device(prob, device="cuda", phi=True):
-    """Copy an inputs.Problem's host arrays to device tensors."""
+def mg_beta0_from_p0(rho0_base, p0_edge, p0_cc, gamma1_cc, stream=None):
+    """beta0 at layer centres and z faces from p0 and the layer Gamma1, on the
+    device of p0_cc (new tensors, filled on the stream)."""
     import torch
-    t = {name: torch.from_numpy(np.ascontiguousarray(getattr(prob, name))).to(device)
-         for name in ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w")}
+    nz = p0_cc.shape[0]
+    f64 = torch.float64
+    b0c = torch.empty(nz, dtype=f64, device=p0_cc.device)
+    b0e = torch.empty(nz + 1, dtype=f64, device=p0_cc.device)
+    _check(lib().mg_beta0_from_p0(nz, float(rho0_base), _ptr(p0_edge, f64, (nz + 1,), "p0_edge"),
+                                  _ptr(p0_cc, f64, (nz,), "p0_cc"), _ptr(gamma1_cc, f64, (nz,), "gamma1_cc"),
+                                  _ptr(b0c, f64, (nz,), "beta0_cc"), _ptr(b0e, f64, (nz + 1,), "beta0_edge"),
+                                  _stream(stream)))
+    return b0c, b0e
+
+
+def to_device(prob, device="cuda", phi=True):
+    """Copy an inputs.Problem's host arrays to device tensors (base-state
+    arrays that the problem does not carry stay None)."""
+    import torch
+    names = ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w", "p0_cc", "p0_edge", "gamma1_cc", "dp0dt_cc")
+    t = {name: (torch.from_numpy(np.ascontiguousarray(getattr(prob, name))).to(device)
+                if getattr(prob, name, None) is not None else None)
+         for name in names}
     nx, ny, nz = prob.n
     t["phi"] = torch.zeros((nz, ny, nx), dtype=torch.float64, device=device) if phi else None
     return SimpleNamespace(**t)
