@@ -21,6 +21,8 @@ Also reported on the same JSON line:
     project_batch, against the same problems solved one by one;
   * serve: Poisson request streams of {32,64,128,256}^3 boxes through the
     continuous-batching server, solves/s with p50/p99 latency per rate;
+  * full_rhs: the box with its base state given as p0 and Gamma1 (beta0
+    computed on the device each step, dp0/dt term in the right-hand side);
   * cpu_baseline: the FP64 CPU oracle timed on the host cores on whole
     solves of the headline box (about 10 s of CPU work).
 
@@ -352,6 +354,35 @@ def serve_leg(args, torch, macproj, inputs, dev):
     return {"budget_bytes": 200 << 30, "max_inflight": 64, "precision": "fp64", "rates": out}
 
 
+def full_leg(args, torch, macproj, inputs, dev):
+    """The same box size with the base state given as p0 and Gamma1: each step
+    computes beta0 on the device and projects with the dp0/dt term in the
+    right-hand side (FP64)."""
+    log(f"full right-hand side: {args.full_steps} steps")
+    prob = inputs.make_full_problem(args.n, seed=5)
+    R = Restorable(macproj, prob, dev)
+    d = R.d
+    H = macproj.Hierarchy(macproj.params_of(prob))
+
+    def step():
+        R.restore()
+        b0c, b0e = macproj.mg_beta0_from_p0(prob.rho0_base, d.p0_edge, d.p0_cc, d.gamma1_cc)
+        return H.mac_project_full(d.rho, b0c, b0e, d.S, d.p0_cc, d.gamma1_cc, d.dp0dt_cc, d.u, d.v, d.w, d.phi)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.full_steps):
+        st = step()
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+    H.close()
+    return {"value": args.full_steps / tf, "unit": "solves/s", "ms_per_step": tf * 1e3 / args.full_steps,
+            "cycles": st["cycles"], "workload": f"{args.n}^3, p0 = exp(-z/0.25), Gamma1 1.67 -> 1.3, "
+                                                "beta0 computed on the device each step, dp0/dt term in f"}
+
+
 def cpu_leg(args, prob):
     log("CPU oracle baseline")
     from oracle import oracle as orc
@@ -381,6 +412,7 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, help="autotune the batch's shapes first")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[100.0, 400.0, 2000.0])
     ap.add_argument("--serve-requests", type=int, default=150)
+    ap.add_argument("--full-steps", type=int, default=5, help="0 skips the p0/Gamma1 base-state leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -414,6 +446,7 @@ def main():
     del phi64
     batch = batch_leg(args, torch, macproj, inputs, dev) if args.batch_reps > 0 else None
     serve = serve_leg(args, torch, macproj, inputs, dev) if args.serve_rates else None
+    full = full_leg(args, torch, macproj, inputs, dev) if args.full_steps > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_leg(args, prob)
 
     model_bytes = n ** 3 * (156.0 + cycles * 326.0)
@@ -439,6 +472,7 @@ def main():
         "mixed": mixed,
         "batch": batch,
         "serve": serve,
+        "full_rhs": full,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
