@@ -231,10 +231,10 @@ int serve_counters(void* server, double out[6]);
 /* Finish all tickets and release the server. */
 int serve_destroy(void* server);
 
-/* Tuning: force fused-sweep tile configuration cfg (0..8: 32x8x32, 32x8x64,
- * 64x8x32, 32x16x32, 64x4x64, 32x4x64, 32x8x16, 32x8x8, 64x8x64 cells per
- * workgroup tile x planes per chunk) on every level that fits it; -1 restores
- * the per-shape default.
+/* Tuning: force fused-sweep tile configuration cfg (0..11: 32x8x32, 32x8x64,
+ * 64x8x32, 32x16x32, 64x4x64, 32x4x64, 32x8x16, 32x8x8, 64x8x64, 64x16x32,
+ * 32x32x32, 64x16x64 cells per workgroup tile x planes per chunk) on every
+ * level that fits it; -1 restores the per-shape default.
  * Process-wide; results do not depend on it (the sweep is exact per cell). */
 int mg_tune_sweep(int32_t cfg);
 

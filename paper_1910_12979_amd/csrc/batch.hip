@@ -480,7 +480,7 @@ int multi_vcycle_f32(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st)
                 if (l >= stop[i] || k >= (post ? H->p.post_sweeps : H->p.pre_sweeps)) continue;
                 const Level& F = H->lev[l];
                 args.push_back(sweep_args_f32(H, l));
-                cfgs.push_back(sweep_config_for(F.nx, F.ny, F.nz, l == 0));
+                cfgs.push_back(sweep_config_for(F.nx, F.ny, F.nz, l == 0, false));
                 who.push_back(H);
             }
             if (args.empty()) continue;
@@ -499,7 +499,7 @@ int multi_vcycle_f32(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st)
             if (l >= stop[i]) continue;
             const Level& F = hs[i]->lev[l];
             args.push_back(sweep_args_f32(hs[i], l));
-            cfgs.push_back(sweep_config_for(F.nx, F.ny, F.nz, l == 0));
+            cfgs.push_back(sweep_config_for(F.nx, F.ny, F.nz, l == 0, false));
         }
         rc = launch_group<float>(args, cfgs, l == 0, kInPlain, kOpResidRestrict, S, st);
         if (rc) return rc;

@@ -333,7 +333,8 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
         else a.rho = H->rho32;
         a.b0c = H->rho.b0c;
         a.b0e = H->rho.b0e;
-        HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain, sweep_config_for(F.nx, F.ny, F.nz, use_rho), st));
+        HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain,
+                               sweep_config_for(F.nx, F.ny, F.nz, use_rho, dbl), st));
         std::swap(A->phi, *alt);
     }
     return MG_OK;
@@ -387,7 +388,7 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
             a.b0e = H->rho.b0e;
             a.fc = C.s.f;
             a.phic_out = C.s.phi;
-            HIPCHK(launch_resid_restrict_tiled<float>(a, sweep_config_for(F.nx, F.ny, F.nz, true), st));
+            HIPCHK(launch_resid_restrict_tiled<float>(a, sweep_config_for(F.nx, F.ny, F.nz, true, false), st));
             return MG_OK;
         }
         HIPCHK(launch_resid_restrict<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, C.s.f, C.s.phi, st));
@@ -1257,7 +1258,7 @@ int mg_autotune(mg_handle h, int32_t reps, void* stream) {
                 best_cfg = c;
             }
         }
-        if (best_cfg >= 0) sweep_record_tuned(F.nx, F.ny, F.nz, rho, best_cfg);
+        if (best_cfg >= 0) sweep_record_tuned(F.nx, F.ny, F.nz, rho, true, best_cfg);
     }
     sweep_force_config(saved);
     hipEventDestroy(e0);
@@ -1303,7 +1304,7 @@ int mg_sweep_config(mg_handle h, int32_t level, int32_t tile[4]) {
     const bool dbl = h->p.precision == MG_FP64;
     const bool fusable = dbl ? sweep_fusable<double>(F.nx, F.ny, F.nz) : sweep_fusable<float>(F.nx, F.ny, F.nz);
     if (level + 1 >= h->nlev || !fusable) return MG_OK;
-    const int c = sweep_config_for(F.nx, F.ny, F.nz, dbl && level == 0);
+    const int c = sweep_config_for(F.nx, F.ny, F.nz, level == 0, dbl);
     tile[0] = kSweepCfgs[c].tx;
     tile[1] = kSweepCfgs[c].ty;
     tile[2] = kSweepCfgs[c].tz;

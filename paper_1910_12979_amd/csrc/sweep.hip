@@ -520,12 +520,13 @@ int g_forced_cfg = -1;    // set by mg_tune_sweep (-1: per-shape choice)
 
 // Autotuned choices, keyed by level shape and coefficient source.
 struct TuneKey {
-    int nx, ny, nz, rho;
+    int nx, ny, nz, rho, dbl;
     bool operator<(const TuneKey& o) const {
         if (nx != o.nx) return nx < o.nx;
         if (ny != o.ny) return ny < o.ny;
         if (nz != o.nz) return nz < o.nz;
-        return rho < o.rho;
+        if (rho != o.rho) return rho < o.rho;
+        return dbl < o.dbl;
     }
 };
 std::mutex g_tune_mu;
@@ -540,9 +541,9 @@ void sweep_force_config(int cfg) {
     ++g_tune_epoch;
 }
 
-void sweep_record_tuned(int nx, int ny, int nz, bool rho, int cfg) {
+void sweep_record_tuned(int nx, int ny, int nz, bool rho, bool dbl, int cfg) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[TuneKey{nx, ny, nz, rho ? 1 : 0}] = cfg;
+    g_tuned[TuneKey{nx, ny, nz, rho ? 1 : 0, dbl ? 1 : 0}] = cfg;
     ++g_tune_epoch;
 }
 
@@ -560,17 +561,24 @@ bool sweep_cfg_fits(int nx, int ny, int cfg) {
     return cfg >= 0 && cfg < kNumSweepCfg && nx >= kSweepCfgs[cfg].tx && ny >= kSweepCfgs[cfg].ty;
 }
 
-int sweep_config_for(int nx, int ny, int nz, bool rho) {
+int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl) {
     if (g_forced_cfg >= 0 && sweep_cfg_fits(nx, ny, g_forced_cfg)) return g_forced_cfg;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find(TuneKey{nx, ny, nz, rho ? 1 : 0});
+        auto it = g_tuned.find(TuneKey{nx, ny, nz, rho ? 1 : 0, dbl ? 1 : 0});
         if (it != g_tuned.end()) return it->second;
     }
-    // untuned shapes: choices measured on MI355X for cubic levels (64x8 tiles
-    // on the largest boxes, then 32x8 tiles with shallower z-chunks so small
-    // levels still fill the 256 CUs)
+    // untuned shapes: choices measured on MI355X for cubic levels.  On the
+    // largest boxes 64x16-cell tiles (the halo share of the loads and of the
+    // redundant red updates is a third lower than with 64x8 tiles): FP64
+    // with 64-plane chunks (one 132 KB workgroup per CU), FP32 with 32-plane
+    // chunks; then 32x8 tiles with shallower z-chunks so small levels still
+    // fill the 256 CUs.
     const double cells = (double)nx * ny * nz;
+    if (nx >= 64 && ny >= 16 && cells >= 8.0e6) {
+        if (dbl && nz >= 64) return 11;
+        if (!dbl) return 9;
+    }
     if (nx >= 64 && cells >= 8.0e6) return 2;
     if (nx >= 32 && ny >= 8) {
         if (cells >= 1.0e6) return 6;
@@ -593,6 +601,9 @@ hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cf
         case 1: return launch_mode<T, 32, 8>(a, use_rho, in_mode, c.tz, st);
         case 2: return launch_mode<T, 64, 8>(a, use_rho, in_mode, c.tz, st);
         case 8: return launch_mode<T, 64, 8>(a, use_rho, in_mode, c.tz, st);
+        case 9: return launch_mode<T, 64, 16>(a, use_rho, in_mode, c.tz, st);
+        case 10: return launch_mode<T, 32, 32>(a, use_rho, in_mode, c.tz, st);
+        case 11: return launch_mode<T, 64, 16>(a, use_rho, in_mode, c.tz, st);
         case 3: return launch_mode<T, 32, 16>(a, use_rho, in_mode, c.tz, st);
         case 4: return launch_mode<T, 64, 4>(a, use_rho, in_mode, c.tz, st);
         case 5: return launch_mode<T, 32, 4>(a, use_rho, in_mode, c.tz, st);
@@ -609,6 +620,9 @@ hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, h
         case 1: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
         case 2: return launch_t<double, 64, 8, true, kInPlain, N>(a, c.tz, st, nparts);
         case 8: return launch_t<double, 64, 8, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 9: return launch_t<double, 64, 16, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 10: return launch_t<double, 32, 32, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 11: return launch_t<double, 64, 16, true, kInPlain, N>(a, c.tz, st, nparts);
         case 3: return launch_t<double, 32, 16, true, kInPlain, N>(a, c.tz, st, nparts);
         case 4: return launch_t<double, 64, 4, true, kInPlain, N>(a, c.tz, st, nparts);
         case 5: return launch_t<double, 32, 4, true, kInPlain, N>(a, c.tz, st, nparts);
@@ -626,6 +640,9 @@ hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, int cfg, hipStream
         case 1: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
         case 2: return launch_t<T, 64, 8, true, kInPlain, R>(a, c.tz, st);
         case 8: return launch_t<T, 64, 8, true, kInPlain, R>(a, c.tz, st);
+        case 9: return launch_t<T, 64, 16, true, kInPlain, R>(a, c.tz, st);
+        case 10: return launch_t<T, 32, 32, true, kInPlain, R>(a, c.tz, st);
+        case 11: return launch_t<T, 64, 16, true, kInPlain, R>(a, c.tz, st);
         case 3: return launch_t<T, 32, 16, true, kInPlain, R>(a, c.tz, st);
         case 4: return launch_t<T, 64, 4, true, kInPlain, R>(a, c.tz, st);
         case 5: return launch_t<T, 32, 4, true, kInPlain, R>(a, c.tz, st);
@@ -642,6 +659,9 @@ hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipSt
         case 1: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
         case 2: return launch_t<double, 64, 8, true, I, R>(a, c.tz, st, nparts);
         case 8: return launch_t<double, 64, 8, true, I, R>(a, c.tz, st, nparts);
+        case 9: return launch_t<double, 64, 16, true, I, R>(a, c.tz, st, nparts);
+        case 10: return launch_t<double, 32, 32, true, I, R>(a, c.tz, st, nparts);
+        case 11: return launch_t<double, 64, 16, true, I, R>(a, c.tz, st, nparts);
         case 3: return launch_t<double, 32, 16, true, I, R>(a, c.tz, st, nparts);
         case 4: return launch_t<double, 64, 4, true, I, R>(a, c.tz, st, nparts);
         case 5: return launch_t<double, 32, 4, true, I, R>(a, c.tz, st, nparts);
