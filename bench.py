@@ -54,8 +54,8 @@ SWEEP_KERNEL_BYTES_PER_CELL = 32.0
 # for the sweep source it was taken on (SHA-1 of the files below) and tile.
 SWEEP_SOURCES = ("paper_1910_12979_amd/csrc/sweep.hip", "paper_1910_12979_amd/csrc/sweep.h",
                  "paper_1910_12979_amd/csrc/devmath.h")
-SWEEP_TRAFFIC = {"sha1": "78059ccf8ca229f6a211a5f517a99c4c7a15c44a", "tile": [64, 8, 32], "n": 256,
-                 "read": 471647189, "write": 134218357}
+SWEEP_TRAFFIC = {"sha1": "2c04967fb76c7eda5ebcbfc51c7cddf2a901d39d", "tile": [64, 16, 64], "n": 256,
+                 "read": 436922244, "write": 134217728}
 
 
 def percentile(xs, q):
