@@ -28,6 +28,26 @@
  *   The solution is unique up to a constant; the oracle returns the zero-mean
  *   one.
  *
+ * Outflow boundaries (the *_gen functions): a side may instead carry
+ *   phi = 0 on its faces (Dirichlet).  The boundary face's coefficient is
+ *   beta0_face / rho of the one adjacent cell, and the face enters the operator
+ *   through the ghost value -phi_c (phi is zero half a cell away), i.e. as
+ *   b (-phi_c - phi_c).  With any outflow side the operator is non-singular:
+ *   no compatibility condition, no mean removal of f or phi, and the coarsest
+ *   level is solved with -A itself.  Outflow faces are corrected like interior
+ *   faces, U -= (phi_c - phi_ghost)/h / rho_face with rho_face = rho of the
+ *   adjacent cell (interior faces: the mean of the two cells).
+ *
+ * beta0 on a radial profile (the *_gen functions, spherical base state):
+ *   the profile gives beta0 at radii r_m = (m + 1/2) dr, m = 0..nr-1, about a
+ *   centre c; beta0 at any point x is the linear interpolation in r = |x - c|
+ *   between the two nearest profile radii, held constant below r_0 and above
+ *   r_{nr-1}.  Face coefficients use beta0 at the face centre, beta0 S uses it
+ *   at the cell centre, and the divergence weights every face velocity with
+ *   its own face value:
+ *       f = ((bxh uh - bxl ul) + (byh vh - byl vl) + (bzh wh - bzl wl)) / h
+ *           - beta0_c S.
+ *
  * beta0 from the base-state pressure (Sec. 2, definition of beta0):
  *   orc_beta0_from_p0 integrates (1/(Gamma1 p0)) dp0/dr layer by layer with
  *   Gamma1 constant in a layer, exactly ln(p0(b)/p0(a))/Gamma1 over [a, b].
@@ -68,6 +88,7 @@
 typedef struct {
     int nx, ny, nz;
     int px, py, pz;      /* 1 = periodic, 0 = solid walls on both sides */
+    int dir[6];          /* outflow (phi = 0) sides: x low, x high, y low, y high, z low, z high */
     double h;
     double *bx, *by, *bz; /* full face arrays: (nz,ny,nx+1), (nz,ny+1,nx), (nz+1,ny,nx) */
     double *phi, *f, *r;  /* cell arrays (nz,ny,nx) */
@@ -78,6 +99,7 @@ typedef struct {
     olev lev[MAXLEV];
     double *chol;        /* coarsest-level Cholesky factor (lower, row-major) */
     int ncoarse;
+    int singular;        /* no outflow side: solution defined up to a constant */
 } omg;
 
 static inline size_t CI(const olev* L, int i, int j, int k) {
@@ -96,29 +118,39 @@ static inline size_t ncell(const olev* L) { return (size_t)L->nx * L->ny * L->nz
 
 /*
  * The faces of cell (i,j,k) that carry flux, in the fixed order x-low, x-high,
- * y-low, y-high, z-low, z-high: coefficient b[] and neighbour cell index nb[].
+ * y-low, y-high, z-low, z-high: coefficient b[], neighbour cell index nb[] and
+ * ghost[] = 1 for an outflow boundary face (its neighbour value is -phi_c).
  * A wall face is left out.  Returns the number of faces listed.
  */
-static int cell_faces(const olev* L, int i, int j, int k, double b[6], size_t nb[6]) {
+static int cell_faces(const olev* L, int i, int j, int k, double b[6], size_t nb[6], int ghost[6]) {
     int m = 0;
+    size_t c = CI(L, i, j, k);
+#define FACE(bv, nbv, g) do { b[m] = (bv); nb[m] = (nbv); ghost[m] = (g); ++m; } while (0)
     /* x-low: face i */
-    if (i > 0) { b[m] = L->bx[FXI(L, i, j, k)]; nb[m++] = CI(L, i - 1, j, k); }
-    else if (L->px) { b[m] = L->bx[FXI(L, 0, j, k)]; nb[m++] = CI(L, L->nx - 1, j, k); }
+    if (i > 0) FACE(L->bx[FXI(L, i, j, k)], CI(L, i - 1, j, k), 0);
+    else if (L->px) FACE(L->bx[FXI(L, 0, j, k)], CI(L, L->nx - 1, j, k), 0);
+    else if (L->dir[0]) FACE(L->bx[FXI(L, 0, j, k)], c, 1);
     /* x-high: face i+1 */
-    if (i < L->nx - 1) { b[m] = L->bx[FXI(L, i + 1, j, k)]; nb[m++] = CI(L, i + 1, j, k); }
-    else if (L->px) { b[m] = L->bx[FXI(L, L->nx, j, k)]; nb[m++] = CI(L, 0, j, k); }
+    if (i < L->nx - 1) FACE(L->bx[FXI(L, i + 1, j, k)], CI(L, i + 1, j, k), 0);
+    else if (L->px) FACE(L->bx[FXI(L, L->nx, j, k)], CI(L, 0, j, k), 0);
+    else if (L->dir[1]) FACE(L->bx[FXI(L, L->nx, j, k)], c, 1);
     /* y-low */
-    if (j > 0) { b[m] = L->by[FYI(L, i, j, k)]; nb[m++] = CI(L, i, j - 1, k); }
-    else if (L->py) { b[m] = L->by[FYI(L, i, 0, k)]; nb[m++] = CI(L, i, L->ny - 1, k); }
+    if (j > 0) FACE(L->by[FYI(L, i, j, k)], CI(L, i, j - 1, k), 0);
+    else if (L->py) FACE(L->by[FYI(L, i, 0, k)], CI(L, i, L->ny - 1, k), 0);
+    else if (L->dir[2]) FACE(L->by[FYI(L, i, 0, k)], c, 1);
     /* y-high */
-    if (j < L->ny - 1) { b[m] = L->by[FYI(L, i, j + 1, k)]; nb[m++] = CI(L, i, j + 1, k); }
-    else if (L->py) { b[m] = L->by[FYI(L, i, L->ny, k)]; nb[m++] = CI(L, i, 0, k); }
+    if (j < L->ny - 1) FACE(L->by[FYI(L, i, j + 1, k)], CI(L, i, j + 1, k), 0);
+    else if (L->py) FACE(L->by[FYI(L, i, L->ny, k)], CI(L, i, 0, k), 0);
+    else if (L->dir[3]) FACE(L->by[FYI(L, i, L->ny, k)], c, 1);
     /* z-low */
-    if (k > 0) { b[m] = L->bz[FZI(L, i, j, k)]; nb[m++] = CI(L, i, j, k - 1); }
-    else if (L->pz) { b[m] = L->bz[FZI(L, i, j, 0)]; nb[m++] = CI(L, i, j, L->nz - 1); }
+    if (k > 0) FACE(L->bz[FZI(L, i, j, k)], CI(L, i, j, k - 1), 0);
+    else if (L->pz) FACE(L->bz[FZI(L, i, j, 0)], CI(L, i, j, L->nz - 1), 0);
+    else if (L->dir[4]) FACE(L->bz[FZI(L, i, j, 0)], c, 1);
     /* z-high */
-    if (k < L->nz - 1) { b[m] = L->bz[FZI(L, i, j, k + 1)]; nb[m++] = CI(L, i, j, k + 1); }
-    else if (L->pz) { b[m] = L->bz[FZI(L, i, j, L->nz)]; nb[m++] = CI(L, i, j, 0); }
+    if (k < L->nz - 1) FACE(L->bz[FZI(L, i, j, k + 1)], CI(L, i, j, k + 1), 0);
+    else if (L->pz) FACE(L->bz[FZI(L, i, j, L->nz)], CI(L, i, j, 0), 0);
+    else if (L->dir[5]) FACE(L->bz[FZI(L, i, j, L->nz)], c, 1);
+#undef FACE
     return m;
 }
 
@@ -126,10 +158,14 @@ static int cell_faces(const olev* L, int i, int j, int k, double b[6], size_t nb
 static double apply_cell(const olev* L, const double* phi, int i, int j, int k) {
     double b[6];
     size_t nb[6];
-    int m = cell_faces(L, i, j, k, b, nb);
+    int ghost[6];
+    int m = cell_faces(L, i, j, k, b, nb, ghost);
     double pc = phi[CI(L, i, j, k)];
     double s = 0.0;
-    for (int q = 0; q < m; ++q) s += b[q] * (phi[nb[q]] - pc);
+    for (int q = 0; q < m; ++q) {
+        double pn = ghost[q] ? -pc : phi[nb[q]];
+        s += b[q] * (pn - pc);
+    }
     return s / (L->h * L->h);
 }
 
@@ -140,6 +176,35 @@ static void wrap_level(olev* L, int nx, int ny, int nz, int px, int py, int pz, 
     L->px = px; L->py = py; L->pz = pz;
     L->h = h;
     L->bx = bx; L->by = by; L->bz = bz;
+}
+
+/* Side codes of the *_gen functions, per side (x low, x high, y low, y high,
+ * z low, z high): 0 periodic, 1 solid wall, 2 outflow.  A periodic direction
+ * has code 0 on both sides. */
+#define SIDE_PERIODIC 0
+#define SIDE_WALL 1
+#define SIDE_OUTFLOW 2
+
+static int sides_valid(const int* side) {
+    for (int d = 0; d < 3; ++d) {
+        int lo = side[2 * d], hi = side[2 * d + 1];
+        if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return 0;
+        if ((lo == SIDE_PERIODIC) != (hi == SIDE_PERIODIC)) return 0;
+    }
+    return 1;
+}
+
+static void wrap_level_gen(olev* L, int nx, int ny, int nz, const int* side, double h,
+                           double* bx, double* by, double* bz) {
+    wrap_level(L, nx, ny, nz, side[0] == SIDE_PERIODIC, side[2] == SIDE_PERIODIC, side[4] == SIDE_PERIODIC, h,
+               bx, by, bz);
+    for (int q = 0; q < 6; ++q) L->dir[q] = side[q] == SIDE_OUTFLOW;
+}
+
+static int any_outflow(const int* side) {
+    for (int q = 0; q < 6; ++q)
+        if (side[q] == SIDE_OUTFLOW) return 1;
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -304,11 +369,17 @@ static void rbgs_level(const olev* L, double* phi, const double* f, int nsweeps)
                         if (((i + j + k) & 1) != colour) continue;
                         double b[6];
                         size_t nb[6];
-                        int m = cell_faces(L, i, j, k, b, nb);
+                        int ghost[6];
+                        int m = cell_faces(L, i, j, k, b, nb, ghost);
                         double num = 0.0, den = 0.0;
                         for (int q = 0; q < m; ++q) {
-                            num += b[q] * phi[nb[q]];
-                            den += b[q];
+                            if (ghost[q]) {
+                                /* b (-phi - phi): the face moves 2b to the diagonal */
+                                den += 2.0 * b[q];
+                            } else {
+                                num += b[q] * phi[nb[q]];
+                                den += b[q];
+                            }
                         }
                         size_t c = CI(L, i, j, k);
                         phi[c] = (num - h2 * f[c]) / den;
@@ -377,7 +448,7 @@ static void coarsen_coeffs(const olev* F, olev* C) {
 /* ------------------------------------------------------------------ */
 /* Coarsest level: dense Cholesky of M = -A + c 1 1^T.                 */
 /* ------------------------------------------------------------------ */
-static int coarse_factor(const olev* L, double** out) {
+static int coarse_factor(const olev* L, int singular, double** out) {
     int n = (int)ncell(L);
     double* M = (double*)calloc((size_t)n * n, sizeof(double));
     if (!M) return ORC_ERR_OOM;
@@ -387,17 +458,24 @@ static int coarse_factor(const olev* L, double** out) {
             for (int i = 0; i < L->nx; ++i) {
                 double b[6];
                 size_t nb[6];
-                int m = cell_faces(L, i, j, k, b, nb);
+                int ghost[6];
+                int m = cell_faces(L, i, j, k, b, nb, ghost);
                 size_t c = CI(L, i, j, k);
                 for (int q = 0; q < m; ++q) {
-                    M[c * n + c] += b[q] * ih2;
-                    M[c * n + nb[q]] -= b[q] * ih2;
+                    if (ghost[q]) {
+                        M[c * n + c] += 2.0 * b[q] * ih2;
+                    } else {
+                        M[c * n + c] += b[q] * ih2;
+                        M[c * n + nb[q]] -= b[q] * ih2;
+                    }
                 }
             }
-    double dsum = 0.0;
-    for (int c = 0; c < n; ++c) dsum += M[(size_t)c * n + c];
-    double shift = dsum / n;
-    for (size_t e = 0; e < (size_t)n * n; ++e) M[e] += shift;
+    if (singular) {
+        double dsum = 0.0;
+        for (int c = 0; c < n; ++c) dsum += M[(size_t)c * n + c];
+        double shift = dsum / n;
+        for (size_t e = 0; e < (size_t)n * n; ++e) M[e] += shift;
+    }
     /* in-place Cholesky, lower triangle: M = G G^T */
     for (int j = 0; j < n; ++j) {
         double d = M[(size_t)j * n + j];
@@ -415,10 +493,12 @@ static int coarse_factor(const olev* L, double** out) {
     return ORC_OK;
 }
 
-static void coarse_solve(const double* G, int n, const double* f, double* x) {
+static void coarse_solve(const double* G, int n, int singular, const double* f, double* x) {
     double mf = 0.0;
-    for (int c = 0; c < n; ++c) mf += f[c];
-    mf /= n;
+    if (singular) {
+        for (int c = 0; c < n; ++c) mf += f[c];
+        mf /= n;
+    }
     /* forward: G y = -(f - mean f) */
     for (int i = 0; i < n; ++i) {
         double s = -(f[i] - mf);
@@ -431,10 +511,12 @@ static void coarse_solve(const double* G, int n, const double* f, double* x) {
         for (int p = i + 1; p < n; ++p) s -= G[(size_t)p * n + i] * x[p];
         x[i] = s / G[(size_t)i * n + i];
     }
-    double mx = 0.0;
-    for (int c = 0; c < n; ++c) mx += x[c];
-    mx /= n;
-    for (int c = 0; c < n; ++c) x[c] -= mx;
+    if (singular) {
+        double mx = 0.0;
+        for (int c = 0; c < n; ++c) mx += x[c];
+        mx /= n;
+        for (int c = 0; c < n; ++c) x[c] -= mx;
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -473,19 +555,20 @@ int orc_num_levels(int nx, int ny, int nz) {
     return n;
 }
 
-/* Build the hierarchy from level-0 full face arrays (copied). */
-void* orc_mg_create(int nx, int ny, int nz, int px, int py, int pz, double h,
-                    const double* bx, const double* by, const double* bz, int* status) {
+/* Build the hierarchy from level-0 full face arrays (copied); side codes as
+ * for the *_gen functions. */
+void* orc_mg_create_gen(int nx, int ny, int nz, const int* side, double h,
+                        const double* bx, const double* by, const double* bz, int* status) {
+    if (!sides_valid(side)) { *status = ORC_ERR_INVALID; return NULL; }
     int nl = orc_num_levels(nx, ny, nz);
     if (nl == 0) { *status = ORC_ERR_SIZE; return NULL; }
     omg* M = (omg*)calloc(1, sizeof(omg));
     if (!M) { *status = ORC_ERR_OOM; return NULL; }
     M->nlev = nl;
+    M->singular = !any_outflow(side);
     for (int l = 0; l < nl; ++l) {
         olev* L = &M->lev[l];
-        L->nx = nx >> l; L->ny = ny >> l; L->nz = nz >> l;
-        L->px = px; L->py = py; L->pz = pz;
-        L->h = h * (double)(1 << l);
+        wrap_level_gen(L, nx >> l, ny >> l, nz >> l, side, h * (double)(1 << l), NULL, NULL, NULL);
         if (alloc_level(L) != ORC_OK) { orc_mg_destroy(M); *status = ORC_ERR_OOM; return NULL; }
     }
     olev* L0 = &M->lev[0];
@@ -494,10 +577,23 @@ void* orc_mg_create(int nx, int ny, int nz, int px, int py, int pz, double h,
     memcpy(L0->bz, bz, sizeof(double) * (size_t)(nz + 1) * ny * nx);
     for (int l = 0; l + 1 < nl; ++l) coarsen_coeffs(&M->lev[l], &M->lev[l + 1]);
     M->ncoarse = (int)ncell(&M->lev[nl - 1]);
-    int st = coarse_factor(&M->lev[nl - 1], &M->chol);
+    int st = coarse_factor(&M->lev[nl - 1], M->singular, &M->chol);
     if (st != ORC_OK) { orc_mg_destroy(M); *status = st; return NULL; }
     *status = ORC_OK;
     return M;
+}
+
+static void sides_of(int px, int py, int pz, int side[6]) {
+    int p[3] = {px, py, pz};
+    for (int d = 0; d < 3; ++d) side[2 * d] = side[2 * d + 1] = p[d] ? SIDE_PERIODIC : SIDE_WALL;
+}
+
+/* Build the hierarchy from level-0 full face arrays (copied). */
+void* orc_mg_create(int nx, int ny, int nz, int px, int py, int pz, double h,
+                    const double* bx, const double* by, const double* bz, int* status) {
+    int side[6];
+    sides_of(px, py, pz, side);
+    return orc_mg_create_gen(nx, ny, nz, side, h, bx, by, bz, status);
 }
 
 int orc_mg_nlevels(void* hv) { return ((omg*)hv)->nlev; }
@@ -552,7 +648,7 @@ void orc_mg_prolong(void* hv, int l) {
 void orc_mg_coarse(void* hv) {
     omg* M = (omg*)hv;
     olev* L = &M->lev[M->nlev - 1];
-    coarse_solve(M->chol, M->ncoarse, L->f, L->phi);
+    coarse_solve(M->chol, M->ncoarse, M->singular, L->f, L->phi);
 }
 
 static void vcycle(omg* M, int l, int nu1, int nu2) {
@@ -581,7 +677,7 @@ static double norm2(const double* a, size_t n) {
  *   mode 1 ("definition"): iterate to stagnation (relative residual <= 1e-13
  *          or no new minimum over 3 cycles); returns the best iterate.
  * hist[c] = relative residual after c cycles (hist[0] = 1).  On exit phi has
- * zero mean.  Returns ORC_OK, ORC_ERR_NOT_CONVERGED or ORC_ERR_NONFINITE.
+ * zero mean (singular operator) or is returned as computed (outflow sides).  Returns ORC_OK, ORC_ERR_NOT_CONVERGED or ORC_ERR_NONFINITE.
  */
 int orc_mg_solve(void* hv, const double* f0, double* phi_out, double rtol, int max_cycles,
                  int nu1, int nu2, int mode, double* hist, int hist_len, int* cycles_out) {
@@ -623,8 +719,10 @@ int orc_mg_solve(void* hv, const double* f0, double* phi_out, double rtol, int m
         }
     }
     double m = 0.0;
-    for (size_t e = 0; e < N; ++e) m += L0->phi[e];
-    m /= (double)N;
+    if (M->singular) {
+        for (size_t e = 0; e < N; ++e) m += L0->phi[e];
+        m /= (double)N;
+    }
     for (size_t e = 0; e < N; ++e) phi_out[e] = L0->phi[e] - m;
     *cycles_out = c;
     return status;
@@ -737,6 +835,331 @@ int orc_mac_project(int nx, int ny, int nz, int px, int py, int pz, double h,
                     double* hist, int hist_len, double* stats) {
     return orc_mac_project_w0(nx, ny, nz, px, py, pz, h, rho, b0c, b0e, S, NULL, u, v, w, phi_out, rtol,
                               max_cycles, nu1, nu2, mode, hist, hist_len, stats);
+}
+
+/* ------------------------------------------------------------------ */
+/* General boundaries and base states (outflow sides, radial beta0).   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const double* b0c;       /* plane-parallel: beta0 at layer centres (nz) */
+    const double* b0e;       /*                 and at z faces (nz+1) */
+    int nr;                  /* radial: profile of nr values at r = (m + 1/2) dr */
+    double dr;
+    const double* prof;      /* NULL: plane-parallel */
+    double c[3];             /* centre of the radial profile */
+    double h;
+} obeta;
+
+static void obeta_init(obeta* B, const double* b0c, const double* b0e, int nr, double dr, const double* prof,
+                       const double* centre, double h) {
+    B->b0c = b0c; B->b0e = b0e; B->nr = nr; B->dr = dr; B->prof = prof; B->h = h;
+    B->c[0] = centre ? centre[0] : 0.0;
+    B->c[1] = centre ? centre[1] : 0.0;
+    B->c[2] = centre ? centre[2] : 0.0;
+}
+
+/* beta0 at distance r from the centre: linear in r between the two nearest
+ * profile radii, constant below the first and above the last. */
+static double radial_beta0(const obeta* B, double r) {
+    double s = r / B->dr - 0.5;
+    if (!(s > 0.0)) return B->prof[0];
+    if (s >= (double)(B->nr - 1)) return B->prof[B->nr - 1];
+    int m = (int)s;
+    double t = s - (double)m;
+    return B->prof[m] + t * (B->prof[m + 1] - B->prof[m]);
+}
+
+static double radial_at(const obeta* B, double x, double y, double z) {
+    double dx = x - B->c[0], dy = y - B->c[1], dz = z - B->c[2];
+    return radial_beta0(B, sqrt(dx * dx + dy * dy + dz * dz));
+}
+
+/* beta0 at the centre of cell (i,j,k). */
+static double beta0_cell(const obeta* B, int i, int j, int k) {
+    if (!B->prof) return B->b0c[k];
+    return radial_at(B, (i + 0.5) * B->h, (j + 0.5) * B->h, (k + 0.5) * B->h);
+}
+
+/* beta0 at face f of direction d (0 x, 1 y, 2 z) in row/column (a, b): the
+ * face at coordinate f h along d, the cell centres of (a, b) across it
+ * (x faces: a = j, b = k; y faces: a = i, b = k; z faces: a = i, b = j). */
+static double beta0_face(const obeta* B, int d, int f, int a, int b) {
+    if (!B->prof) return d == 2 ? B->b0e[f] : B->b0c[b];
+    double h = B->h;
+    if (d == 0) return radial_at(B, f * h, (a + 0.5) * h, (b + 0.5) * h);
+    if (d == 1) return radial_at(B, (a + 0.5) * h, f * h, (b + 0.5) * h);
+    return radial_at(B, (a + 0.5) * h, (b + 0.5) * h, f * h);
+}
+
+/* beta0 at cell centres (the radial mapping alone). */
+void orc_map_radial(int nx, int ny, int nz, double h, int nr, double dr, const double* prof,
+                    const double* centre, double* out) {
+    obeta B;
+    obeta_init(&B, NULL, NULL, nr, dr, prof, centre, h);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) out[((size_t)k * ny + j) * nx + i] = beta0_cell(&B, i, j, k);
+}
+
+/* Face coefficients with per-side boundaries: interior and periodic faces
+ * beta0_face / (0.5 (rho_L + rho_R)) (in a periodic direction face n is face
+ * 0), outflow faces beta0_face / rho of the adjacent cell, walls 0. */
+static void face_coeffs_gen(int nx, int ny, int nz, const int* side, const obeta* B, const double* rho,
+                            double* bx, double* by, double* bz) {
+    olev L;
+    wrap_level_gen(&L, nx, ny, nz, side, B->h, bx, by, bz);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                double b;
+                if (i > 0 && i < nx) {
+                    b = beta0_face(B, 0, i, j, k) / (0.5 * (rho[CI(&L, i - 1, j, k)] + rho[CI(&L, i, j, k)]));
+                } else if (L.px) {
+                    b = beta0_face(B, 0, 0, j, k) / (0.5 * (rho[CI(&L, nx - 1, j, k)] + rho[CI(&L, 0, j, k)]));
+                } else if (i == 0 && side[0] == SIDE_OUTFLOW) {
+                    b = beta0_face(B, 0, 0, j, k) / rho[CI(&L, 0, j, k)];
+                } else if (i == nx && side[1] == SIDE_OUTFLOW) {
+                    b = beta0_face(B, 0, nx, j, k) / rho[CI(&L, nx - 1, j, k)];
+                } else {
+                    b = 0.0;
+                }
+                bx[FXI(&L, i, j, k)] = b;
+            }
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double b;
+                if (j > 0 && j < ny) {
+                    b = beta0_face(B, 1, j, i, k) / (0.5 * (rho[CI(&L, i, j - 1, k)] + rho[CI(&L, i, j, k)]));
+                } else if (L.py) {
+                    b = beta0_face(B, 1, 0, i, k) / (0.5 * (rho[CI(&L, i, ny - 1, k)] + rho[CI(&L, i, 0, k)]));
+                } else if (j == 0 && side[2] == SIDE_OUTFLOW) {
+                    b = beta0_face(B, 1, 0, i, k) / rho[CI(&L, i, 0, k)];
+                } else if (j == ny && side[3] == SIDE_OUTFLOW) {
+                    b = beta0_face(B, 1, ny, i, k) / rho[CI(&L, i, ny - 1, k)];
+                } else {
+                    b = 0.0;
+                }
+                by[FYI(&L, i, j, k)] = b;
+            }
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double b;
+                if (k > 0 && k < nz) {
+                    b = beta0_face(B, 2, k, i, j) / (0.5 * (rho[CI(&L, i, j, k - 1)] + rho[CI(&L, i, j, k)]));
+                } else if (L.pz) {
+                    b = beta0_face(B, 2, 0, i, j) / (0.5 * (rho[CI(&L, i, j, nz - 1)] + rho[CI(&L, i, j, 0)]));
+                } else if (k == 0 && side[4] == SIDE_OUTFLOW) {
+                    b = beta0_face(B, 2, 0, i, j) / rho[CI(&L, i, j, 0)];
+                } else if (k == nz && side[5] == SIDE_OUTFLOW) {
+                    b = beta0_face(B, 2, nz, i, j) / rho[CI(&L, i, j, nz - 1)];
+                } else {
+                    b = 0.0;
+                }
+                bz[FZI(&L, i, j, k)] = b;
+            }
+}
+
+int orc_face_coeffs_gen(int nx, int ny, int nz, const int* side, double h, const double* rho,
+                        const double* b0c, const double* b0e, int nr, double dr, const double* prof,
+                        const double* centre, double* bx, double* by, double* bz) {
+    if (!sides_valid(side)) return ORC_ERR_INVALID;
+    obeta B;
+    obeta_init(&B, b0c, b0e, nr, dr, prof, centre, h);
+    face_coeffs_gen(nx, ny, nz, side, &B, rho, bx, by, bz);
+    return ORC_OK;
+}
+
+/* f = D(beta0 U) - beta0_c (S - w0[k]) with every face velocity weighted by
+ * its own face's beta0 (in a periodic direction face n is face 0). */
+static void rhs_gen(int nx, int ny, int nz, const int* side, const obeta* B, const double* u, const double* v,
+                    const double* w, const double* S, const double* w0, double* f) {
+    olev L;
+    wrap_level_gen(&L, nx, ny, nz, side, B->h, NULL, NULL, NULL);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int ih = (i == nx - 1 && L.px) ? 0 : i + 1;
+                int jh = (j == ny - 1 && L.py) ? 0 : j + 1;
+                int kh = (k == nz - 1 && L.pz) ? 0 : k + 1;
+                double fx = beta0_face(B, 0, ih, j, k) * u[FXI(&L, ih, j, k)] - beta0_face(B, 0, i, j, k) * u[FXI(&L, i, j, k)];
+                double fy = beta0_face(B, 1, jh, i, k) * v[FYI(&L, i, jh, k)] - beta0_face(B, 1, j, i, k) * v[FYI(&L, i, j, k)];
+                double fz = beta0_face(B, 2, kh, i, j) * w[FZI(&L, i, j, kh)] - beta0_face(B, 2, k, i, j) * w[FZI(&L, i, j, k)];
+                double src = S[CI(&L, i, j, k)];
+                if (w0) src = src - w0[k];
+                f[CI(&L, i, j, k)] = (fx + fy + fz) / B->h - beta0_cell(B, i, j, k) * src;
+            }
+}
+
+int orc_rhs_gen(int nx, int ny, int nz, const int* side, double h, const double* b0c, const double* b0e, int nr,
+                double dr, const double* prof, const double* centre, const double* u, const double* v,
+                const double* w, const double* S, const double* w0, double* f) {
+    if (!sides_valid(side)) return ORC_ERR_INVALID;
+    obeta B;
+    obeta_init(&B, b0c, b0e, nr, dr, prof, centre, h);
+    rhs_gen(nx, ny, nz, side, &B, u, v, w, S, w0, f);
+    return ORC_OK;
+}
+
+/* Single-level operator, residual and sweeps with per-side boundaries on full
+ * face arrays (outflow faces hold their coefficient, walls anything). */
+void orc_apply_gen(int nx, int ny, int nz, const int* side, double h, const double* bx, const double* by,
+                   const double* bz, const double* phi, double* out) {
+    olev L;
+    wrap_level_gen(&L, nx, ny, nz, side, h, (double*)bx, (double*)by, (double*)bz);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) out[CI(&L, i, j, k)] = apply_cell(&L, phi, i, j, k);
+}
+
+void orc_rbgs_gen(int nx, int ny, int nz, const int* side, double h, const double* bx, const double* by,
+                  const double* bz, double* phi, const double* f, int nsweeps) {
+    olev L;
+    wrap_level_gen(&L, nx, ny, nz, side, h, (double*)bx, (double*)by, (double*)bz);
+    rbgs_level(&L, phi, f, nsweeps);
+}
+
+/* U -= (phi_c - phi_nb) / h / rho_face on every face that is not a wall:
+ * interior and periodic faces with rho_face = 0.5 (rho_L + rho_R), outflow
+ * faces with the ghost value -phi_c and rho_face = rho of the adjacent cell.
+ * Periodic duplicate faces (face n) are refreshed from face 0. */
+static void correct_gen(int nx, int ny, int nz, const int* side, double h, const double* rho, const double* phi,
+                        double* u, double* v, double* w) {
+    olev L;
+    wrap_level_gen(&L, nx, ny, nz, side, h, NULL, NULL, NULL);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            for (int i = 0; i < nx; ++i) {
+                double pc = phi[CI(&L, i, j, k)];
+                if (i > 0 || L.px) {
+                    int im = i > 0 ? i - 1 : nx - 1;
+                    double g = (pc - phi[CI(&L, im, j, k)]) / h;
+                    u[FXI(&L, i, j, k)] -= g / (0.5 * (rho[CI(&L, im, j, k)] + rho[CI(&L, i, j, k)]));
+                } else if (side[0] == SIDE_OUTFLOW) {
+                    double g = (pc - (-pc)) / h;
+                    u[FXI(&L, 0, j, k)] -= g / rho[CI(&L, 0, j, k)];
+                }
+            }
+            if (L.px) u[FXI(&L, nx, j, k)] = u[FXI(&L, 0, j, k)];
+            else if (side[1] == SIDE_OUTFLOW) {
+                double pc = phi[CI(&L, nx - 1, j, k)];
+                double g = ((-pc) - pc) / h;
+                u[FXI(&L, nx, j, k)] -= g / rho[CI(&L, nx - 1, j, k)];
+            }
+        }
+    for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) {
+            for (int j = 0; j < ny; ++j) {
+                double pc = phi[CI(&L, i, j, k)];
+                if (j > 0 || L.py) {
+                    int jm = j > 0 ? j - 1 : ny - 1;
+                    double g = (pc - phi[CI(&L, i, jm, k)]) / h;
+                    v[FYI(&L, i, j, k)] -= g / (0.5 * (rho[CI(&L, i, jm, k)] + rho[CI(&L, i, j, k)]));
+                } else if (side[2] == SIDE_OUTFLOW) {
+                    double g = (pc - (-pc)) / h;
+                    v[FYI(&L, i, 0, k)] -= g / rho[CI(&L, i, 0, k)];
+                }
+            }
+            if (L.py) v[FYI(&L, i, ny, k)] = v[FYI(&L, i, 0, k)];
+            else if (side[3] == SIDE_OUTFLOW) {
+                double pc = phi[CI(&L, i, ny - 1, k)];
+                double g = ((-pc) - pc) / h;
+                v[FYI(&L, i, ny, k)] -= g / rho[CI(&L, i, ny - 1, k)];
+            }
+        }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            for (int k = 0; k < nz; ++k) {
+                double pc = phi[CI(&L, i, j, k)];
+                if (k > 0 || L.pz) {
+                    int km = k > 0 ? k - 1 : nz - 1;
+                    double g = (pc - phi[CI(&L, i, j, km)]) / h;
+                    w[FZI(&L, i, j, k)] -= g / (0.5 * (rho[CI(&L, i, j, km)] + rho[CI(&L, i, j, k)]));
+                } else if (side[4] == SIDE_OUTFLOW) {
+                    double g = (pc - (-pc)) / h;
+                    w[FZI(&L, i, j, 0)] -= g / rho[CI(&L, i, j, 0)];
+                }
+            }
+            if (L.pz) w[FZI(&L, i, j, nz)] = w[FZI(&L, i, j, 0)];
+            else if (side[5] == SIDE_OUTFLOW) {
+                double pc = phi[CI(&L, i, j, nz - 1)];
+                double g = ((-pc) - pc) / h;
+                w[FZI(&L, i, j, nz)] -= g / rho[CI(&L, i, j, nz - 1)];
+            }
+        }
+}
+
+void orc_correct_gen(int nx, int ny, int nz, const int* side, double h, const double* rho, const double* phi,
+                     double* u, double* v, double* w) {
+    correct_gen(nx, ny, nz, side, h, rho, phi, u, v, w);
+}
+
+/* The whole projection with per-side boundaries and a plane-parallel
+ * (b0c, b0e) or radial (prof != NULL) beta0.  Statuses, stats and modes as
+ * orc_mac_project_w0; with an outflow side there is no compatibility check
+ * and neither f nor phi has its mean removed (stats[2] = 0). */
+int orc_mac_project_gen(int nx, int ny, int nz, const int* side, double h, const double* rho,
+                        const double* b0c, const double* b0e, int nr, double dr, const double* prof,
+                        const double* centre, const double* S, const double* w0, double* u, double* v,
+                        double* w, double* phi_out, double rtol, int max_cycles, int nu1, int nu2, int mode,
+                        double* hist, int hist_len, double* stats) {
+    if (!sides_valid(side)) return ORC_ERR_INVALID;
+    size_t N = (size_t)nx * ny * nz;
+    for (size_t c = 0; c < N; ++c)
+        if (!isfinite(rho[c]) || !isfinite(S[c])) return ORC_ERR_NONFINITE;
+    for (size_t c = 0; c < N; ++c)
+        if (!(rho[c] > 0.0)) return ORC_ERR_INVALID;
+    if (prof) {
+        if (nr < 1 || !(dr > 0.0)) return ORC_ERR_INVALID;
+        for (int m = 0; m < nr; ++m) {
+            if (!isfinite(prof[m])) return ORC_ERR_NONFINITE;
+            if (!(prof[m] > 0.0)) return ORC_ERR_INVALID;
+        }
+    }
+    size_t nbx = (size_t)nz * ny * (nx + 1), nby = (size_t)nz * (ny + 1) * nx, nbz = (size_t)(nz + 1) * ny * nx;
+    for (size_t e = 0; e < nbx; ++e) if (!isfinite(u[e])) return ORC_ERR_NONFINITE;
+    for (size_t e = 0; e < nby; ++e) if (!isfinite(v[e])) return ORC_ERR_NONFINITE;
+    for (size_t e = 0; e < nbz; ++e) if (!isfinite(w[e])) return ORC_ERR_NONFINITE;
+    obeta B;
+    obeta_init(&B, b0c, b0e, nr, dr, prof, centre, h);
+    double* bx = (double*)malloc(nbx * sizeof(double));
+    double* by = (double*)malloc(nby * sizeof(double));
+    double* bz = (double*)malloc(nbz * sizeof(double));
+    double* f = (double*)malloc(N * sizeof(double));
+    if (!bx || !by || !bz || !f) { free(bx); free(by); free(bz); free(f); return ORC_ERR_OOM; }
+    face_coeffs_gen(nx, ny, nz, side, &B, rho, bx, by, bz);
+    rhs_gen(nx, ny, nz, side, &B, u, v, w, S, w0, f);
+    double sf = 0.0, saf = 0.0;
+    for (size_t c = 0; c < N; ++c) { sf += f[c]; saf += fabs(f[c]); }
+    stats[3] = sf; stats[4] = saf;
+    stats[2] = 0.0;
+    int status;
+    if (!any_outflow(side)) {
+        if (fabs(sf) > 1e-8 * saf) {
+            status = ORC_ERR_INCOMPATIBLE;
+            goto done;
+        }
+        double mean = sf / (double)N;
+        for (size_t c = 0; c < N; ++c) f[c] -= mean;
+        stats[2] = mean;
+    }
+    stats[5] = norm2(f, N);
+    {
+        int st = 0;
+        void* M = orc_mg_create_gen(nx, ny, nz, side, h, bx, by, bz, &st);
+        if (!M) { status = st; goto done; }
+        int cyc = 0;
+        status = orc_mg_solve(M, f, phi_out, rtol, max_cycles, nu1, nu2, mode, hist, hist_len, &cyc);
+        stats[0] = cyc;
+        stats[1] = (cyc < hist_len) ? hist[cyc] : NAN;
+        orc_mg_destroy(M);
+    }
+    if (status == ORC_OK || status == ORC_ERR_NOT_CONVERGED)
+        correct_gen(nx, ny, nz, side, h, rho, phi_out, u, v, w);
+done:
+    free(bx); free(by); free(bz); free(f);
+    return status;
 }
 
 int orc_max_threads(void) {

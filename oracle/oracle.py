@@ -82,6 +82,17 @@ def lib():
         L.orc_mac_project.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                                       d, i, i, i, i, _dp, i, _dp]
         L.orc_max_threads.argtypes = []
+        ip6 = ctypes.POINTER(ctypes.c_int)
+        L.orc_map_radial.argtypes = [i, i, i, d, i, d, _dp, _dp, _dp]
+        L.orc_face_coeffs_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, i, d, _dp, _dp, _dp, _dp, _dp]
+        L.orc_rhs_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_apply_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, _dp, _dp]
+        L.orc_rbgs_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, _dp, _dp, i]
+        L.orc_correct_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, _dp, _dp]
+        L.orc_mg_create_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, _ip]
+        L.orc_mg_create_gen.restype = ctypes.c_void_p
+        L.orc_mac_project_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, i, d, _dp, _dp, _dp, _dp, _dp, _dp,
+                                          _dp, _dp, d, i, i, i, i, _dp, i, _dp]
         _lib = L
     return _lib
 
@@ -95,6 +106,92 @@ def _shape_args(n, periodic):
     nx, ny, nz = n
     px, py, pz = (1 if p else 0 for p in periodic)
     return nx, ny, nz, px, py, pz
+
+
+SIDE_PERIODIC, SIDE_WALL, SIDE_OUTFLOW = 0, 1, 2
+
+
+def side_codes(periodic, outflow=None):
+    """Per-side codes (x low, x high, y low, y high, z low, z high): 0
+    periodic, 1 solid wall, 2 outflow (phi = 0).  ``outflow`` is None or six
+    booleans; a periodic direction ignores it."""
+    outflow = (False,) * 6 if outflow is None else tuple(bool(o) for o in outflow)
+    codes = []
+    for d in range(3):
+        for e in range(2):
+            if periodic[d]:
+                codes.append(SIDE_PERIODIC)
+            else:
+                codes.append(SIDE_OUTFLOW if outflow[2 * d + e] else SIDE_WALL)
+    return (ctypes.c_int * 6)(*codes)
+
+
+def _opt(a):
+    return None if a is None else _p(np.ascontiguousarray(a, dtype=np.float64))
+
+
+def _radial_args(radial):
+    """(nr, dr, profile, centre) for a radial beta0 given as (profile, dr,
+    centre); zeros / None for a plane-parallel one."""
+    if radial is None:
+        return 0, 0.0, None, None
+    prof, dr, centre = radial
+    prof = np.ascontiguousarray(prof, dtype=np.float64)
+    return len(prof), float(dr), _p(prof), _p(np.ascontiguousarray(centre, dtype=np.float64))
+
+
+def map_radial(n, h, prof, dr, centre):
+    """beta0 of a radial profile at the cell centres (nz, ny, nx)."""
+    nx, ny, nz = n
+    out = np.empty((nz, ny, nx))
+    prof = np.ascontiguousarray(prof, dtype=np.float64)
+    lib().orc_map_radial(nx, ny, nz, h, len(prof), float(dr), _p(prof),
+                         _p(np.ascontiguousarray(centre, dtype=np.float64)), _p(out))
+    return out
+
+
+def face_coeffs_gen(n, sides, h, rho, b0c=None, b0e=None, radial=None):
+    """Full face arrays with per-side boundaries (``sides`` from side_codes)
+    and a plane-parallel (b0c, b0e) or radial (profile, dr, centre) beta0."""
+    nx, ny, nz = n
+    bx = np.empty((nz, ny, nx + 1))
+    by = np.empty((nz, ny + 1, nx))
+    bz = np.empty((nz + 1, ny, nx))
+    st = lib().orc_face_coeffs_gen(nx, ny, nz, sides, h, _p(rho), _opt(b0c), _opt(b0e), *_radial_args(radial),
+                                   _p(bx), _p(by), _p(bz))
+    assert st == 0
+    return bx, by, bz
+
+
+def rhs_gen(n, sides, h, u, v, w, S, b0c=None, b0e=None, radial=None, w0=None):
+    """f = D(beta0 U) - beta0 (S - w0) with each face velocity weighted by its
+    own face's beta0."""
+    nx, ny, nz = n
+    f = np.empty((nz, ny, nx))
+    st = lib().orc_rhs_gen(nx, ny, nz, sides, h, _opt(b0c), _opt(b0e), *_radial_args(radial), _p(u), _p(v),
+                           _p(w), _p(S), _opt(w0), _p(f))
+    assert st == 0
+    return f
+
+
+def apply_gen(n, sides, h, coeffs, phi):
+    bx, by, bz = coeffs
+    out = np.empty_like(phi)
+    lib().orc_apply_gen(*n, sides, h, _p(bx), _p(by), _p(bz), _p(phi), _p(out))
+    return out
+
+
+def rbgs_gen(n, sides, h, coeffs, phi, f, nsweeps=1):
+    bx, by, bz = coeffs
+    out = np.ascontiguousarray(phi, dtype=np.float64).copy()
+    lib().orc_rbgs_gen(*n, sides, h, _p(bx), _p(by), _p(bz), _p(out), _p(f), nsweeps)
+    return out
+
+
+def correct_gen(n, sides, h, rho, phi, u, v, w):
+    u, v, w = u.copy(), v.copy(), w.copy()
+    lib().orc_correct_gen(*n, sides, h, _p(rho), _p(phi), _p(u), _p(v), _p(w))
+    return u, v, w
 
 
 def num_levels(n) -> int:
@@ -190,13 +287,13 @@ def correct(n, periodic, h, b0c, b0e, coeffs, phi, u, v, w):
 class Hierarchy:
     """The oracle's multigrid hierarchy, exposing every step of the V-cycle."""
 
-    def __init__(self, n, periodic, h, coeffs):
+    def __init__(self, n, periodic, h, coeffs, outflow=None):
         self.n = tuple(n)
         self.periodic = tuple(periodic)
         bx, by, bz = (np.ascontiguousarray(c) for c in coeffs)
         st = ctypes.c_int(0)
-        self._h = lib().orc_mg_create(*_shape_args(n, periodic), h, _p(bx), _p(by), _p(bz),
-                                      ctypes.byref(st))
+        self._h = lib().orc_mg_create_gen(*self.n, side_codes(periodic, outflow), h, _p(bx), _p(by), _p(bz),
+                                          ctypes.byref(st))
         if not self._h:
             raise RuntimeError(f"oracle hierarchy: {STATUS.get(st.value, st.value)}")
         self.nlevels = lib().orc_mg_nlevels(self._h)
@@ -272,10 +369,44 @@ def mac_project_full(prob, mode="algorithm", rtol=None, max_cycles=None):
 def mac_project(prob, mode="algorithm", rtol=None, max_cycles=None, nu1=None, nu2=None):
     """The whole projection on host copies of ``prob`` (an inputs.Problem).
 
-    Returns a dict with status, phi (zero mean), corrected u/v/w, the residual
-    history and the RHS statistics.
+    Returns a dict with status, phi (zero mean unless a side is an outflow),
+    corrected u/v/w, the residual history and the RHS statistics.  Problems
+    with outflow sides or a radial beta0 take the general-boundary path.
     """
+    if is_general(prob):
+        return _project_gen(prob, mode, rtol, max_cycles, nu1, nu2)
     return _project(prob, prob.beta0_cc, prob.beta0_edge, None, mode, rtol, max_cycles, nu1, nu2)
+
+
+def is_general(prob):
+    return any(getattr(prob, "outflow", None) or ()) or getattr(prob, "beta0_r", None) is not None
+
+
+def prob_radial(prob):
+    if getattr(prob, "beta0_r", None) is None:
+        return None
+    return prob.beta0_r, prob.dr_base, prob.centre
+
+
+def _project_gen(prob, mode, rtol, max_cycles, nu1, nu2, w0=None):
+    n = prob.n
+    rtol = prob.rtol if rtol is None else rtol
+    max_cycles = (prob.max_cycles if mode == "algorithm" else 200) if max_cycles is None else max_cycles
+    nu1 = prob.pre_sweeps if nu1 is None else nu1
+    nu2 = prob.post_sweeps if nu2 is None else nu2
+    u, v, w = prob.u.copy(), prob.v.copy(), prob.w.copy()
+    nx, ny, nz = n
+    phi = np.zeros((nz, ny, nx))
+    hist = np.full(max_cycles + 1, np.nan)
+    stats = np.zeros(8)
+    st = lib().orc_mac_project_gen(nx, ny, nz, side_codes(prob.periodic, prob.outflow), prob.dx, _p(prob.rho),
+                                   _opt(prob.beta0_cc), _opt(prob.beta0_edge), *_radial_args(prob_radial(prob)),
+                                   _p(prob.S), _opt(w0), _p(u), _p(v), _p(w), _p(phi), rtol, max_cycles, nu1,
+                                   nu2, 1 if mode == "definition" else 0, _p(hist), len(hist), _p(stats))
+    cycles = int(stats[0])
+    return {"status": st, "status_name": STATUS.get(st, str(st)), "phi": phi, "u": u, "v": v, "w": w,
+            "cycles": cycles, "hist": hist[: cycles + 1], "rel_resid": stats[1],
+            "mean_removed": stats[2], "sum_f": stats[3], "sum_abs_f": stats[4], "norm_f": stats[5]}
 
 
 def _project(prob, b0c, b0e, w0, mode, rtol, max_cycles, nu1, nu2):

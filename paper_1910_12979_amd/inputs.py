@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "make_problem", "stratified_base_state",
-    "make_full_problem", "mixed_batch_specs", "serving_requests",
+    "make_full_problem", "make_star_problem", "mixed_batch_specs", "serving_requests",
     "SMALL_BOX", "STEEP_256", "MIXED_512",
 ]
 
@@ -62,6 +62,14 @@ class Problem:
     p0_edge: np.ndarray | None = None     # (nz+1,)
     gamma1_cc: np.ndarray | None = None   # (nz,)
     dp0dt_cc: np.ndarray | None = None    # (nz,)
+    # outflow sides (phi = 0 on the boundary faces): x low, x high, y low,
+    # y high, z low, z high; only for non-periodic directions
+    outflow: tuple = (False, False, False, False, False, False)
+    # radial base state (make_star_problem): beta0_r[m] at r = (m + 1/2)
+    # dr_base from centre; beta0_cc / beta0_edge are then None
+    beta0_r: np.ndarray | None = None
+    dr_base: float | None = None
+    centre: tuple | None = None
 
     @property
     def ncells(self) -> int:
@@ -71,7 +79,7 @@ class Problem:
     def copy(self) -> "Problem":
         out = dataclasses.replace(self)
         for name in ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w",
-                     "p0_cc", "p0_edge", "gamma1_cc", "dp0dt_cc"):
+                     "p0_cc", "p0_edge", "gamma1_cc", "dp0dt_cc", "beta0_r"):
             a = getattr(self, name)
             setattr(out, name, None if a is None else a.copy())
         return out
@@ -103,15 +111,34 @@ def _fill_faces(u, v, w, periodic):
         w[-1] = 0.0
 
 
+def _draw_outflow_faces(rng, u, v, w, periodic, outflow, vel_scale):
+    """Normal velocities of the outflow boundary faces (drawn after every
+    other field, side by side in the order x low, x high, ..., z high)."""
+    for q in range(6):
+        d, hi = divmod(q, 2)
+        if periodic[d] or not outflow[q]:
+            continue
+        if d == 0:
+            u[:, :, -1 if hi else 0] = vel_scale * rng.standard_normal(u.shape[:2])
+        elif d == 1:
+            v[:, -1 if hi else 0, :] = vel_scale * rng.standard_normal((v.shape[0], v.shape[2]))
+        else:
+            w[-1 if hi else 0] = vel_scale * rng.standard_normal(w.shape[1:])
+
+
 def make_problem(n, *, H=0.3, rho_noise=0.01, S_kind="random", S_amp=0.1,
                  seed=0, dx=None, periodic=(True, True, False), rtol=1e-10,
-                 max_cycles=100, vel_scale=1.0) -> Problem:
+                 max_cycles=100, vel_scale=1.0, outflow=None) -> Problem:
     """Draw one seeded problem.
 
     ``n`` is an int (cubic box) or an ``(nx, ny, nz)`` tuple.  ``dx`` defaults
     to ``1/nx`` (the unit box for cubic grids).  ``S_kind`` is ``"random"``
     (S_amp * N(0,1) with the beta0-weighted mean removed), ``"sine"``
     (sin(2 pi x) sin(2 pi y) cos(pi z) at cell centres) or ``"zero"``.
+    ``outflow``: six booleans (x low, x high, ..., z high) marking sides of
+    non-periodic directions as outflow (phi = 0) instead of solid walls; their
+    boundary-face velocities are drawn last, so the other fields are those of
+    the same seed without outflow sides.
     """
     if isinstance(n, int):
         n = (n, n, n)
@@ -148,9 +175,12 @@ def make_problem(n, *, H=0.3, rho_noise=0.01, S_kind="random", S_amp=0.1,
         # periodic z: face 0 is a real face, drawn after the interior faces
         w[0] = vel_scale * rng.standard_normal((ny, nx))
     _fill_faces(u, v, w, periodic)
+    outflow = (False,) * 6 if outflow is None else tuple(bool(o) for o in outflow)
+    _draw_outflow_faces(rng, u, v, w, periodic, outflow, vel_scale)
     return Problem(n=(nx, ny, nz), dx=float(dx), periodic=periodic, rho=rho,
                    beta0_cc=b0c, beta0_edge=b0e, S=np.ascontiguousarray(S),
-                   u=u, v=v, w=w, rtol=rtol, max_cycles=max_cycles, seed=seed, H=H)
+                   u=u, v=v, w=w, rtol=rtol, max_cycles=max_cycles, seed=seed, H=H,
+                   outflow=outflow)
 
 
 def make_full_problem(n, *, Hp=0.25, gamma1=(5.0 / 3.0, 1.3), rho0_base=1.0, rho_noise=0.01, S_amp=0.1,
@@ -204,6 +234,55 @@ def make_full_problem(n, *, Hp=0.25, gamma1=(5.0 / 3.0, 1.3), rho0_base=1.0, rho
                    beta0_cc=None, beta0_edge=None, S=np.ascontiguousarray(S),
                    u=u, v=v, w=w, rtol=rtol, max_cycles=max_cycles, seed=seed, H=Hp,
                    rho0_base=float(rho0_base), p0_cc=p0c, p0_edge=p0e, gamma1_cc=g1, dp0dt_cc=dp0dt)
+
+
+def make_star_problem(n, *, Hr=0.15, rho_noise=0.01, S_amp=0.1, seed=0, dx=None, centre=None,
+                      dr_per_dx=0.5, outflow=(True,) * 6, rtol=1e-10, max_cycles=100) -> Problem:
+    """A star-like box: the base state is a function of the radius from a
+    centre (spherical base state), the domain boundaries are outflow sides.
+
+    beta0_r[m] = exp(-r_m/Hr) at r_m = (m + 1/2) dr, dr = dr_per_dx * dx,
+    with enough points to reach every corner of the box; rho =
+    exp(-r_c/Hr) (1 + rho_noise N(0,1)) with r_c the distance of each cell
+    centre from ``centre`` (default: the middle of the box); S = S_amp N(0,1);
+    every face velocity N(0,1), then zero on wall sides.  Draw order: rho
+    noise, S noise, u (all nx+1 faces), v, w.
+    """
+    if isinstance(n, int):
+        n = (n, n, n)
+    nx, ny, nz = (int(a) for a in n)
+    if dx is None:
+        dx = 1.0 / nx
+    outflow = tuple(bool(o) for o in outflow)
+    rng = np.random.default_rng(seed)
+    ext = np.array([nx, ny, nz], dtype=np.float64) * dx
+    c = 0.5 * ext if centre is None else np.asarray(centre, dtype=np.float64)
+    dr = dr_per_dx * dx
+    rmax = float(np.sqrt(np.sum(np.maximum(c, ext - c) ** 2)))
+    nr = int(np.ceil(rmax / dr)) + 2
+    rr = (np.arange(nr, dtype=np.float64) + 0.5) * dr
+    prof = np.exp(-rr / Hr)
+    x, y, z = domain_centres((nx, ny, nz), dx)
+    rc = np.sqrt((z[:, None, None] - c[2]) ** 2 + (y[None, :, None] - c[1]) ** 2 + (x[None, None, :] - c[0]) ** 2)
+    rho = np.exp(-rc / Hr) * (1.0 + rho_noise * rng.standard_normal((nz, ny, nx)))
+    S = S_amp * rng.standard_normal((nz, ny, nx))
+    u = rng.standard_normal((nz, ny, nx + 1))
+    v = rng.standard_normal((nz, ny + 1, nx))
+    w = rng.standard_normal((nz + 1, ny, nx))
+    for q in range(6):
+        if outflow[q]:
+            continue
+        d, hi = divmod(q, 2)
+        if d == 0:
+            u[:, :, -1 if hi else 0] = 0.0
+        elif d == 1:
+            v[:, -1 if hi else 0, :] = 0.0
+        else:
+            w[-1 if hi else 0] = 0.0
+    return Problem(n=(nx, ny, nz), dx=float(dx), periodic=(False, False, False), rho=rho,
+                   beta0_cc=None, beta0_edge=None, S=np.ascontiguousarray(S), u=u, v=v, w=w,
+                   rtol=rtol, max_cycles=max_cycles, seed=seed, H=Hr, outflow=outflow,
+                   beta0_r=prof, dr_base=float(dr), centre=tuple(float(a) for a in c))
 
 
 # Named workloads (unit box, periodic in x and y, solid walls in z).
