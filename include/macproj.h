@@ -22,6 +22,19 @@
  * direction face n duplicates face 0: it is ignored on input and overwritten
  * with face 0 on output.
  *
+ * Outflow sides (MG_BC_OUTFLOW, MG_BC_WALL_OUTFLOW, MG_BC_OUTFLOW_WALL): phi =
+ * 0 on the side's faces.  A boundary face's coefficient is beta0_face / rho of
+ * its one cell and it enters the operator with the ghost value -phi_c
+ * (b (-phi_c - phi_c)); its normal velocity takes part in div(beta0 U) as
+ * given and is corrected like an interior face's, with rho_face = rho of the
+ * cell.  With any outflow side the operator is non-singular: there is no
+ * compatibility check, f and phi keep their means (stats mean_removed and
+ * phi_mean are 0), and the coarsest level is solved with -A itself.  Problems
+ * with outflow sides (and any solve with a plane-parallel or radial beta0 on
+ * such a box) use the general-boundary kernels: interior faces U -= (1/rho_f)
+ * grad phi with rho_f = 0.5 (rho_L + rho_R), and the divergence weights every
+ * face velocity with its own face's beta0.
+ *
  * Multigrid: V(pre, post) cycles of red-black Gauss-Seidel (red =
  * (i+j+k) even, first), 8-cell-average restriction, piecewise-constant
  * prolongation, coarse coefficients = mean of the 4 coincident fine faces,
@@ -67,13 +80,21 @@ typedef enum {
     MG_ERR_BUSY = -9              /* no free slot right now (non-blocking submit) */
 } mg_status;
 
-typedef enum { MG_BC_PERIODIC = 0, MG_BC_WALL = 1 } mg_bc;
+/* Per direction: both sides periodic, both solid walls, both outflow, or a
+ * wall on the low side and an outflow on the high side (and the reverse). */
+typedef enum {
+    MG_BC_PERIODIC = 0,
+    MG_BC_WALL = 1,
+    MG_BC_OUTFLOW = 2,
+    MG_BC_WALL_OUTFLOW = 3,
+    MG_BC_OUTFLOW_WALL = 4
+} mg_bc;
 typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
 
 typedef struct {
     int32_t n[3];            /* nx, ny, nz (cells) */
     double  dx;              /* uniform cubic spacing */
-    int32_t bc[3];           /* per direction, both sides: MG_BC_PERIODIC or MG_BC_WALL */
+    int32_t bc[3];           /* per direction: an mg_bc */
     int32_t pre_sweeps;      /* red-black GS sweeps before restriction (default 2) */
     int32_t post_sweeps;     /* sweeps after prolongation (default 2) */
     double  rtol;            /* relative L2 residual target (default 1e-10) */
@@ -179,6 +200,31 @@ int mac_project_full(mg_handle h, const double* rho, const double* beta0_cc, con
                      const double* S, const double* p0_cc, const double* gamma1_cc, const double* dp0dt_cc,
                      double* u, double* v, double* w, double* phi, mg_stats* stats, void* stream);
 
+/* ---- spherical base state ------------------------------------------------ */
+
+/* mac_project with beta0 a function of the radius from a centre (the
+ * spherical base state of a star, Sec. 2, beta0 definition, with r the
+ * distance from the star's centre): beta0_r (device, nr values) holds beta0 at
+ * r_m = (m + 1/2) dr, m = 0..nr-1; beta0 at any point x is the linear
+ * interpolation in r = |x - centre| between the two nearest r_m, held at
+ * beta0_r[0] below r_0 and at beta0_r[nr-1] above r_{nr-1}.  centre (host, 3
+ * values) is in the units of dx with the box's low corner at the origin; cell
+ * (i,j,k) is centred at ((i+1/2) dx, (j+1/2) dx, (k+1/2) dx).  Face
+ * coefficients use beta0 at the face centre, the beta0 S term beta0 at the cell
+ * centre, and every face velocity of div(beta0 U) its own face's beta0.  Any
+ * boundary types; arguments, statuses and blocking as mac_project
+ * (beta0_r <= 0 somewhere: MG_ERR_INVALID_ARG; non-finite: MG_ERR_NONFINITE). */
+int mac_project_radial(mg_handle h, const double* rho, int32_t nr, double dr, const double* beta0_r,
+                       const double centre[3], const double* S, double* u, double* v, double* w,
+                       double* phi, mg_stats* stats, void* stream);
+
+/* The radial mapping alone: beta0_out (device, nz*ny*nx, C order) = beta0 of
+ * the profile at every cell centre of an nx*ny*nz box of spacing dx, as
+ * mac_project_radial evaluates it.  Stream-ordered: returns after enqueueing
+ * one kernel. */
+int mg_map_radial(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t nr, double dr,
+                  const double* beta0_r, const double centre[3], double* beta0_out, void* stream);
+
 /* ---- single steps of the cycle, for step-by-step verification ---------- */
 typedef enum {
     MG_STEP_SMOOTH = 0,          /* `arg` red-black GS sweeps on level l (phi_l, f_l) */
@@ -198,12 +244,15 @@ int mg_level_info(mg_handle h, int32_t level, int32_t dims[3], double* dx);
  * enqueued on `stream`
  * (to_hierarchy = 1: buffer -> hierarchy).  Cell arrays are (nz,ny,nx); the
  * coefficient arrays hold, per cell, the coefficient of its LOW face in that
- * direction (face n of a periodic direction is face 0; walls hold 0). */
+ * direction (face n of a periodic direction is face 0; walls and outflow
+ * sides hold 0 there: outflow boundary faces are kept separately). */
 int mg_level_copy(mg_handle h, int32_t level, int32_t array, void* buffer,
                   int32_t to_hierarchy, void* stream);
 
 /* Run one step (mg_step) on level l.  Like mg_level_copy, stream-ordered:
- * returns after enqueueing the work on `stream`. */
+ * returns after enqueueing the work on `stream`.  On a box with outflow sides
+ * the steps take their boundary faces from the last mg_set_coefficients or
+ * projection. */
 int mg_level_step(mg_handle h, int32_t level, int32_t step, int32_t arg, void* stream);
 
 /* ---- batches and serving ------------------------------------------------ */

@@ -56,6 +56,7 @@ __device__ void b_colour(const BottomLevel<T>& lv, T* P, const T* F, int colour)
         den = den + byh;
         den = den + bzl;
         den = den + bzh;
+        if (lv.has_bnd) den = den + bnd_diag(lv.bnd, i, j, k, nx, ny, nz);
         P[c] = qdiv(num - h2 * F[c], den);
     }
     __syncthreads();
@@ -77,6 +78,7 @@ __device__ inline T b_apply(const BottomLevel<T>& lv, const T* P, int i, int j, 
     s = s + lv.by[cyp] * (P[cyp] - pc);
     s = s + lv.bz[c] * (P[bidx(i, j, km, nx, ny)] - pc);
     s = s + lv.bz[czp] * (P[czp] - pc);
+    if (lv.has_bnd) s = s - bnd_diag(lv.bnd, i, j, k, nx, ny, nz) * pc;
     return s * (T(1) / lv.h2);
 }
 
@@ -118,17 +120,20 @@ __device__ void b_prolong(const BottomLevel<T>& lv, T* P, const T* cP) {
     __syncthreads();
 }
 
-// Coarsest level: remove mean(f), x = Minv (-f'), remove mean(x).  Serial
-// sums and row dot products in the same order as the coarse-solve kernel.
+// Coarsest level: remove mean(f), x = Minv (-f'), remove mean(x) (without
+// the mean removals when an outflow side makes the operator non-singular).
+// Serial sums and row dot products in the same order as the coarse-solve
+// kernel.
 template <typename T>
-__device__ void b_coarse(int n, const double* __restrict__ minv, const T* F, T* P, double* rhs, double* x,
-                         double* mean) {
+__device__ void b_coarse(int n, int singular, const double* __restrict__ minv, const T* F, T* P, double* rhs,
+                         double* x, double* mean) {
     for (int c = threadIdx.x; c < n; c += blockDim.x) rhs[c] = (double)F[c];
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int c = 0; c < n; ++c) s += rhs[c];
-        *mean = s / n;
+        if (singular)
+            for (int c = 0; c < n; ++c) s += rhs[c];
+        *mean = singular ? s / n : 0.0;
     }
     __syncthreads();
     const double m = *mean;
@@ -144,8 +149,9 @@ __device__ void b_coarse(int n, const double* __restrict__ minv, const T* F, T* 
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int c = 0; c < n; ++c) s += x[c];
-        *mean = s / n;
+        if (singular)
+            for (int c = 0; c < n; ++c) s += x[c];
+        *mean = singular ? s / n : 0.0;
     }
     __syncthreads();
     for (int c = threadIdx.x; c < n; c += blockDim.x) P[c] = (T)(x[c] - *mean);
@@ -181,7 +187,7 @@ __device__ void bottom_body(const BottomArgs<T>& A) {
     }
     {
         const BottomLevel<T>& c = A.lev[nb - 1];
-        b_coarse(c.nx * c.ny * c.nz, A.minv, Fof(nb - 1), Pof(nb - 1), rhs, x, &mean);
+        b_coarse(c.nx * c.ny * c.nz, A.singular, A.minv, Fof(nb - 1), Pof(nb - 1), rhs, x, &mean);
     }
     for (int b = nb - 2; b >= 0; --b) {
         b_prolong(A.lev[b], Pof(b), Pof(b + 1));

@@ -220,7 +220,7 @@ __global__ void k_avg_coeff(int nx, int ny, int nz, const T* __restrict__ bx, co
 template <typename T>
 __global__ void k_rbgs_colour(int nx, int ny, int nz, T h2, T* __restrict__ phi, const T* __restrict__ f,
                               const T* __restrict__ bx, const T* __restrict__ by,
-                              const T* __restrict__ bz, int colour) {
+                              const T* __restrict__ bz, int colour, Bnd<T> bnd, int has_bnd) {
     int ih = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y * blockDim.y + threadIdx.y;
     int k = blockIdx.z * blockDim.z + threadIdx.z;
@@ -245,6 +245,7 @@ __global__ void k_rbgs_colour(int nx, int ny, int nz, T h2, T* __restrict__ phi,
     den = den + byh;
     den = den + bzl;
     den = den + bzh;
+    if (has_bnd) den = den + bnd_diag(bnd, i, j, k, nx, ny, nz);
     phi[c] = qdiv(num - h2 * f[c], den);
 }
 
@@ -254,6 +255,8 @@ struct StoredCoeff {
     const T* bx;
     const T* by;
     const T* bz;
+    Bnd<T> bnd;          // outflow boundary faces (has_bnd != 0)
+    int has_bnd;
     __device__ inline void get(size_t c, size_t cxp, size_t cyp, size_t czp, int, int, int, int, int, int,
                                T b[6]) const {
         b[0] = bx[c];
@@ -272,6 +275,8 @@ struct RhoCoeff {
     const double* b0c;
     const double* b0e;
     int nx, ny, nz, px, py, pz;
+    Bnd<double> bnd;     // outflow boundary faces (has_bnd != 0)
+    int has_bnd;
     // low face of the cell at flat index c (coordinates i, j, k) in direction d
     __device__ inline double low(int d, size_t c, int i, int j, int k) const {
         const size_t plane = (size_t)nx * ny;
@@ -316,6 +321,7 @@ __device__ inline T apply_cell(int i, int j, int k, int nx, int ny, int nz, T h2
     s = s + b[3] * (phi[cyp] - pc);
     s = s + b[4] * (phi[cidx(i, j, km, nx, ny)] - pc);
     s = s + b[5] * (phi[czp] - pc);
+    if (coef.has_bnd) s = s - bnd_diag(coef.bnd, i, j, k, nx, ny, nz) * pc;
     return s * (T(1) / h2);
 }
 
@@ -382,7 +388,8 @@ __global__ __launch_bounds__(kSetupThreads) void k_coarse_setup(int nx, int ny, 
                                                                 const double* __restrict__ bx,
                                                                 const double* __restrict__ by,
                                                                 const double* __restrict__ bz,
-                                                                double* __restrict__ Mg) {
+                                                                double* __restrict__ Mg, Bnd<double> bnd,
+                                                                int has_bnd, int singular) {
     __shared__ double Ms[kLds ? kSetupLdsN * kSetupLdsN : 1];
     __shared__ double fac[kCoarseMax];      // column p before the elimination step
     __shared__ double prow[kCoarseMax];     // row p before the elimination step
@@ -408,15 +415,18 @@ __global__ __launch_bounds__(kSetupThreads) void k_coarse_setup(int nx, int ny, 
             row[c] += b[q] * ih2;
             row[nb[q]] -= b[q] * ih2;
         }
+        if (has_bnd) row[c] += bnd_diag(bnd, i, j, k, nx, ny, nz) * ih2;   // outflow faces
     }
     __syncthreads();
-    if (tid == 0) {
-        double d = 0.0;
-        for (int c = 0; c < n; ++c) d += M[c * n + c];
-        shift = d / n;
+    if (singular) {      // constant null space: M = -A + c 1 1^T, c the mean diagonal
+        if (tid == 0) {
+            double d = 0.0;
+            for (int c = 0; c < n; ++c) d += M[c * n + c];
+            shift = d / n;
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += nt) M[e] += shift;
     }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += nt) M[e] += shift;
     // In-place Gauss-Jordan inversion (M is SPD: no pivoting).  Thread tid
     // owns column jj = tid % n of rows tid / n, tid / n + nt / n, ...; per
     // pivot p: row p becomes row p / M_pp (with 1 / M_pp in column p), every
@@ -451,7 +461,8 @@ __global__ __launch_bounds__(kSetupThreads) void k_coarse_setup(int nx, int ny, 
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __restrict__ Minv,
-                                                         const T* __restrict__ f, T* __restrict__ phi) {
+                                                         const T* __restrict__ f, T* __restrict__ phi,
+                                                         int singular) {
     __shared__ double rhs[kCoarseMax];
     __shared__ double x[kCoarseMax];
     __shared__ double mean;
@@ -459,8 +470,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int c = 0; c < n; ++c) s += rhs[c];
-        mean = s / n;
+        if (singular)
+            for (int c = 0; c < n; ++c) s += rhs[c];
+        mean = singular ? s / n : 0.0;
     }
     __syncthreads();
     double m = mean;
@@ -476,8 +488,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int c = 0; c < n; ++c) s += x[c];
-        mean = s / n;
+        if (singular)
+            for (int c = 0; c < n; ++c) s += x[c];
+        mean = singular ? s / n : 0.0;
     }
     __syncthreads();
     for (int c = threadIdx.x; c < n; c += kBlock) phi[c] = (T)(x[c] - mean);
@@ -527,6 +540,197 @@ __global__ void k_correct(int nx, int ny, int nz, int px, int py, int pz, double
         w[e] = wn;
         if (pz && k == 0) w[e + (size_t)nz * plane] = wn;
     }
+}
+
+// ---------------------------------------------------------------------------
+// General boundaries and base states: outflow sides (phi = 0 on the boundary
+// faces) and a radial beta0.
+// ---------------------------------------------------------------------------
+enum { kSidePeriodic = 0, kSideWall = 1, kSideOutflow = 2 };
+
+// beta0 at a point: plane-parallel layers or the radial profile (linear in r
+// between the profile radii (m + 1/2) dr, constant beyond the ends).
+struct Beta0At {
+    const GenArgs& a;
+    __device__ double radial(double x, double y, double z) const {
+        const double dx = x - a.cx, dy = y - a.cy, dz = z - a.cz;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double s = r / a.dr - 0.5;
+        if (!(s > 0.0)) return a.prof[0];
+        if (s >= (double)(a.nr - 1)) return a.prof[a.nr - 1];
+        const int m = (int)s;
+        const double t = s - (double)m;
+        return a.prof[m] + t * (a.prof[m + 1] - a.prof[m]);
+    }
+    __device__ double cell(int i, int j, int k) const {
+        if (!a.prof) return a.b0c[k];
+        return radial((i + 0.5) * a.h, (j + 0.5) * a.h, (k + 0.5) * a.h);
+    }
+    // face f of direction x / y / z with the cell centres of the other two indices
+    __device__ double fx(int f, int j, int k) const {
+        if (!a.prof) return a.b0c[k];
+        return radial(f * a.h, (j + 0.5) * a.h, (k + 0.5) * a.h);
+    }
+    __device__ double fy(int f, int i, int k) const {
+        if (!a.prof) return a.b0c[k];
+        return radial((i + 0.5) * a.h, f * a.h, (k + 0.5) * a.h);
+    }
+    __device__ double fz(int f, int i, int j) const {
+        if (!a.prof) return a.b0e[f];
+        return radial((i + 0.5) * a.h, (j + 0.5) * a.h, f * a.h);
+    }
+};
+
+template <bool kRhs>
+__global__ __launch_bounds__(kBlock) void k_coeff_rhs_gen(GenArgs a) {
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const double* __restrict__ rho = a.rho;
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t plane = (size_t)nx * ny;
+    const Beta0At B{a};
+    const bool px = a.side[0] == kSidePeriodic, py = a.side[2] == kSidePeriodic, pz = a.side[4] == kSidePeriodic;
+    double sf = 0.0, saf = 0.0, bad = 0.0, nonfin = 0.0;
+    const size_t tid = (size_t)blockIdx.x * kBlock + threadIdx.x, stride = (size_t)gridDim.x * kBlock;
+    if (a.prof)                                  // the whole profile must be usable
+        for (size_t m = tid; m < (size_t)a.nr; m += stride) {
+            if (!finite_d(a.prof[m])) nonfin += 1.0;
+            if (!(a.prof[m] > 0.0)) bad = 1.0;
+        }
+    for (size_t c = tid; c < N; c += stride) {
+        const int i = (int)(c % nx);
+        const int j = (int)((c / nx) % ny);
+        const int k = (int)(c / plane);
+        const double rc = rho[c];
+        const double bc = B.cell(i, j, k);
+        if (!finite_d(rc) || !finite_d(bc)) nonfin += 1.0;
+        if (!(rc > 0.0) || !(bc > 0.0)) bad = 1.0;
+        const double bxl = B.fx(i, j, k), byl = B.fy(j, i, k), bzl = B.fz(k, i, j);
+        // low faces: interior, periodic wrap, or 0 (wall / outflow side)
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+        if (i > 0) cx = qdiv(bxl, 0.5 * (rho[c - 1] + rc));
+        else if (px) cx = qdiv(bxl, 0.5 * (rho[c + (nx - 1)] + rc));
+        if (j > 0) cy = qdiv(byl, 0.5 * (rho[c - nx] + rc));
+        else if (py) cy = qdiv(byl, 0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc));
+        if (k > 0) cz = qdiv(bzl, 0.5 * (rho[c - plane] + rc));
+        else if (pz) cz = qdiv(bzl, 0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc));
+        a.bx[c] = cx;
+        a.by[c] = cy;
+        a.bz[c] = cz;
+        // outflow boundary faces: beta0_face / rho of this cell
+        if (i == 0 && a.bnd[0]) a.bnd[0][(size_t)k * ny + j] = qdiv(bxl, rc);
+        if (i == nx - 1 && a.bnd[1]) a.bnd[1][(size_t)k * ny + j] = qdiv(B.fx(nx, j, k), rc);
+        if (j == 0 && a.bnd[2]) a.bnd[2][(size_t)k * nx + i] = qdiv(byl, rc);
+        if (j == ny - 1 && a.bnd[3]) a.bnd[3][(size_t)k * nx + i] = qdiv(B.fy(ny, i, k), rc);
+        if (k == 0 && a.bnd[4]) a.bnd[4][(size_t)j * nx + i] = qdiv(bzl, rc);
+        if (k == nz - 1 && a.bnd[5]) a.bnd[5][(size_t)j * nx + i] = qdiv(B.fz(nz, i, j), rc);
+        if (kRhs) {
+            // high faces (periodic: face n is face 0)
+            const int ih = (i == nx - 1 && px) ? 0 : i + 1;
+            const int jh = (j == ny - 1 && py) ? 0 : j + 1;
+            const int kh = (k == nz - 1 && pz) ? 0 : k + 1;
+            const size_t ub = ((size_t)k * ny + j) * (nx + 1);
+            const double ul = a.u[ub + i], uh = a.u[ub + ih];
+            const size_t vb = (size_t)k * (ny + 1) * nx + i;
+            const double vl = a.v[vb + (size_t)j * nx], vh = a.v[vb + (size_t)jh * nx];
+            const size_t wc = (size_t)j * nx + i;
+            const double wl = a.w[(size_t)k * plane + wc], wh = a.w[(size_t)kh * plane + wc];
+            double sc = a.S[c];
+            if (a.w0) sc = sc - a.w0[k];         // the dp0/dt term of the constraint, per layer
+            if (!finite_d(ul) || !finite_d(uh) || !finite_d(vl) || !finite_d(vh) || !finite_d(wl) ||
+                !finite_d(wh) || !finite_d(sc))
+                nonfin += 1.0;
+            const double fxs = B.fx(ih, j, k) * uh - bxl * ul;
+            const double fys = B.fy(jh, i, k) * vh - byl * vl;
+            const double fzs = B.fz(kh, i, j) * wh - bzl * wl;
+            const double fc = (fxs + fys + fzs) / a.h - bc * sc;
+            a.f[c] = fc;
+            sf += fc;
+            saf += fabs(fc);
+        }
+    }
+    block_reduce_row(sf, saf, bad, nonfin, a.partials + (size_t)blockIdx.x * kReduceWidth);
+}
+
+__global__ __launch_bounds__(kBlock) void k_map_radial(GenArgs a, double* __restrict__ out) {
+    const size_t N = (size_t)a.nx * a.ny * a.nz;
+    const Beta0At B{a};
+    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock) {
+        const int i = (int)(c % a.nx);
+        const int j = (int)((c / a.nx) % a.ny);
+        const int k = (int)(c / ((size_t)a.nx * a.ny));
+        out[c] = B.cell(i, j, k);
+    }
+}
+
+// One thread per cell: its low faces, and its high faces on outflow sides.
+__global__ void k_correct_gen(GenArgs a, const double* __restrict__ phi, const double* __restrict__ phi_sum,
+                              double* __restrict__ u, double* __restrict__ v, double* __restrict__ w,
+                              double* __restrict__ phi_out) {
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= nx || j >= ny || k >= nz) return;
+    const size_t N = (size_t)nx * ny * nz;
+    const double m = phi_sum ? phi_sum[0] / (double)N : 0.0;
+    const size_t c = cidx(i, j, k, nx, ny);
+    const size_t plane = (size_t)nx * ny;
+    const double pc = phi[c] - m;
+    const double rc = a.rho[c];
+    const double h = a.h;
+    if (phi_out) phi_out[c] = pc;
+    const bool px = a.side[0] == kSidePeriodic, py = a.side[2] == kSidePeriodic, pz = a.side[4] == kSidePeriodic;
+    {   // x faces
+        const size_t e = ((size_t)k * ny + j) * (nx + 1) + i;
+        if (i > 0 || px) {
+            const size_t cm = cidx(i > 0 ? i - 1 : nx - 1, j, k, nx, ny);
+            const double g = (pc - (phi[cm] - m)) / h;
+            const double un = u[e] - g / (0.5 * (a.rho[cm] + rc));
+            u[e] = un;
+            if (px && i == 0) u[e + nx] = un;
+        } else if (a.side[0] == kSideOutflow) {
+            u[e] = u[e] - ((pc - (-pc)) / h) / rc;
+        }
+        if (i == nx - 1 && a.side[1] == kSideOutflow) u[e + 1] = u[e + 1] - (((-pc) - pc) / h) / rc;
+    }
+    {   // y faces
+        const size_t e = ((size_t)k * (ny + 1) + j) * nx + i;
+        if (j > 0 || py) {
+            const size_t cm = cidx(i, j > 0 ? j - 1 : ny - 1, k, nx, ny);
+            const double g = (pc - (phi[cm] - m)) / h;
+            const double vn = v[e] - g / (0.5 * (a.rho[cm] + rc));
+            v[e] = vn;
+            if (py && j == 0) v[e + (size_t)ny * nx] = vn;
+        } else if (a.side[2] == kSideOutflow) {
+            v[e] = v[e] - ((pc - (-pc)) / h) / rc;
+        }
+        if (j == ny - 1 && a.side[3] == kSideOutflow) v[e + nx] = v[e + nx] - (((-pc) - pc) / h) / rc;
+    }
+    {   // z faces
+        const size_t e = (size_t)k * plane + (size_t)j * nx + i;
+        if (k > 0 || pz) {
+            const size_t cm = cidx(i, j, k > 0 ? k - 1 : nz - 1, nx, ny);
+            const double g = (pc - (phi[cm] - m)) / h;
+            const double wn = w[e] - g / (0.5 * (a.rho[cm] + rc));
+            w[e] = wn;
+            if (pz && k == 0) w[e + (size_t)nz * plane] = wn;
+        } else if (a.side[4] == kSideOutflow) {
+            w[e] = w[e] - ((pc - (-pc)) / h) / rc;
+        }
+        if (k == nz - 1 && a.side[5] == kSideOutflow) w[e + plane] = w[e + plane] - (((-pc) - pc) / h) / rc;
+    }
+}
+
+// Coarse boundary faces of one side: cf[A + B*ca] = mean of the fine faces
+// (2A, 2B), (2A+1, 2B), (2A, 2B+1), (2A+1, 2B+1) (first index fastest).
+template <typename T>
+__global__ void k_avg_bnd(int fa, int fb, const T* __restrict__ ff, T* __restrict__ cf) {
+    const int ca = fa / 2, cb = fb / 2;
+    const int A = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Bq = blockIdx.y * blockDim.y + threadIdx.y;
+    if (A >= ca || Bq >= cb) return;
+    const size_t r0 = (size_t)(2 * Bq) * fa, r1 = r0 + fa;
+    cf[(size_t)Bq * ca + A] = T(0.25) * (ff[r0 + 2 * A] + ff[r0 + 2 * A + 1] + ff[r1 + 2 * A] + ff[r1 + 2 * A + 1]);
 }
 
 template <typename T>
@@ -695,22 +899,35 @@ hipError_t launch_avg_coeff(const Shape& fine, const T* bx, const T* by, const T
 }
 
 template <typename T>
+inline void set_bnd(Bnd<T>& dst, int& has, const Bnd<T>* src) {
+    has = 0;
+    for (int q = 0; q < 6; ++q) {
+        dst.s[q] = src ? src->s[q] : nullptr;
+        if (dst.s[q]) has = 1;
+    }
+}
+
+template <typename T>
 hipError_t launch_rbgs(const Shape& s, double h, T* phi, const T* f, const T* bx, const T* by,
-                       const T* bz, int nsweeps, hipStream_t st) {
-    Launch3 L = cell_launch(s.nx / 2, s.ny, s.nz);
+                       const T* bz, int nsweeps, hipStream_t st, const Bnd<T>* bnd) {
+    Launch3 L = cell_launch((s.nx + 1) / 2, s.ny, s.nz);
     T h2 = (T)(h * h);
+    Bnd<T> b;
+    int has = 0;
+    set_bnd(b, has, bnd);
     for (int sw = 0; sw < nsweeps; ++sw)
         for (int colour = 0; colour < 2; ++colour)
             hipLaunchKernelGGL(k_rbgs_colour<T>, L.grid, L.block, 0, st, s.nx, s.ny, s.nz, h2, phi, f, bx, by,
-                               bz, colour);
+                               bz, colour, b, has);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_resid_restrict(const Shape& fine, double h, const T* phi, const T* f, const T* bx,
-                                 const T* by, const T* bz, T* fc, T* phic, hipStream_t st) {
+                                 const T* by, const T* bz, T* fc, T* phic, hipStream_t st, const Bnd<T>* bnd) {
     Launch3 L = cell_launch(fine.nx / 2, fine.ny / 2, fine.nz / 2);
     StoredCoeff<T> coef{bx, by, bz};
+    set_bnd(coef.bnd, coef.has_bnd, bnd);
     hipLaunchKernelGGL((k_resid_restrict<T, StoredCoeff<T>>), L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz,
                        (T)(h * h), phi, f, coef, fc, phic);
     return hipGetLastError();
@@ -725,9 +942,10 @@ hipError_t launch_prolong(const Shape& fine, T* phi, const T* phic, hipStream_t 
 
 template <typename T>
 hipError_t launch_resid_norm(const Shape& s, double h, const T* phi, const T* f, const T* bx, const T* by,
-                             const T* bz, double* partials, int* nparts, hipStream_t st) {
+                             const T* bz, double* partials, int* nparts, hipStream_t st, const Bnd<T>* bnd) {
     int nb = partial_blocks(s.N());
     StoredCoeff<T> coef{bx, by, bz};
+    set_bnd(coef.bnd, coef.has_bnd, bnd);
     hipLaunchKernelGGL((k_resid_norm<T, StoredCoeff<T>>), dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz,
                        (T)(h * h), phi, f, coef, (double*)nullptr, partials);
     *nparts = nb;
@@ -736,9 +954,10 @@ hipError_t launch_resid_norm(const Shape& s, double h, const T* phi, const T* f,
 
 hipError_t launch_resid_store(const Shape& s, double h, const double* phi, const double* f,
                               const double* bx, const double* by, const double* bz, double* r,
-                              double* partials, int* nparts, hipStream_t st) {
+                              double* partials, int* nparts, hipStream_t st, const Bnd<double>* bnd) {
     int nb = partial_blocks(s.N());
     StoredCoeff<double> coef{bx, by, bz};
+    set_bnd(coef.bnd, coef.has_bnd, bnd);
     hipLaunchKernelGGL((k_resid_norm<double, StoredCoeff<double>>), dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny,
                        s.nz, h * h, phi, f, coef, r, partials);
     *nparts = nb;
@@ -747,9 +966,10 @@ hipError_t launch_resid_store(const Shape& s, double h, const double* phi, const
 
 hipError_t launch_resid_norm_rho(const Shape& s, double h, const RhoArgs& ra, const double* phi,
                                  const double* f, double* r_out, double* partials, int* nparts,
-                                 hipStream_t st) {
+                                 hipStream_t st, const Bnd<double>* bnd) {
     int nb = partial_blocks(s.N());
     RhoCoeff coef{ra.rho, ra.b0c, ra.b0e, s.nx, s.ny, s.nz, ra.px, ra.py, ra.pz};
+    set_bnd(coef.bnd, coef.has_bnd, bnd);
     hipLaunchKernelGGL((k_resid_norm<double, RhoCoeff>), dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz,
                        h * h, phi, f, coef, r_out, partials);
     *nparts = nb;
@@ -757,33 +977,76 @@ hipError_t launch_resid_norm_rho(const Shape& s, double h, const RhoArgs& ra, co
 }
 
 hipError_t launch_resid_restrict_rho(const Shape& fine, double h, const RhoArgs& ra, const double* phi,
-                                     const double* f, double* fc, double* phic, hipStream_t st) {
+                                     const double* f, double* fc, double* phic, hipStream_t st,
+                                     const Bnd<double>* bnd) {
     Launch3 L = cell_launch(fine.nx / 2, fine.ny / 2, fine.nz / 2);
     RhoCoeff coef{ra.rho, ra.b0c, ra.b0e, fine.nx, fine.ny, fine.nz, ra.px, ra.py, ra.pz};
+    set_bnd(coef.bnd, coef.has_bnd, bnd);
     hipLaunchKernelGGL((k_resid_restrict<double, RhoCoeff>), L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz,
                        h * h, phi, f, coef, fc, phic);
     return hipGetLastError();
 }
 
 hipError_t launch_coarse_setup(const Shape& s, double h, const double* bx, const double* by,
-                               const double* bz, double* minv, hipStream_t st) {
+                               const double* bz, double* minv, hipStream_t st, const Bnd<double>* bnd,
+                               int singular) {
     if (s.N() > (size_t)kCoarseMax) return hipErrorInvalidValue;
+    Bnd<double> b;
+    int has = 0;
+    set_bnd(b, has, bnd);
     if (s.N() <= (size_t)kSetupLdsN)
         hipLaunchKernelGGL(k_coarse_setup<true>, dim3(1), dim3(kSetupThreads), 0, st, s.nx, s.ny, s.nz, h, bx, by, bz,
-                           minv);
+                           minv, b, has, singular);
     else
         hipLaunchKernelGGL(k_coarse_setup<false>, dim3(1), dim3(kSetupThreads), 0, st, s.nx, s.ny, s.nz, h, bx, by,
-                           bz, minv);
+                           bz, minv, b, has, singular);
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_solve(int N, const double* minv, const double* f, double* phi, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse_solve<double>, dim3(1), dim3(kBlock), 0, st, N, minv, f, phi);
+hipError_t launch_coarse_solve(int N, const double* minv, const double* f, double* phi, hipStream_t st,
+                               int singular) {
+    hipLaunchKernelGGL(k_coarse_solve<double>, dim3(1), dim3(kBlock), 0, st, N, minv, f, phi, singular);
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_solve_f32(int N, const double* minv, const float* f, float* phi, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse_solve<float>, dim3(1), dim3(kBlock), 0, st, N, minv, f, phi);
+hipError_t launch_coarse_solve_f32(int N, const double* minv, const float* f, float* phi, hipStream_t st,
+                                   int singular) {
+    hipLaunchKernelGGL(k_coarse_solve<float>, dim3(1), dim3(kBlock), 0, st, N, minv, f, phi, singular);
+    return hipGetLastError();
+}
+
+hipError_t launch_coeff_rhs_gen(const GenArgs& a, int* nparts, hipStream_t st) {
+    const Shape s{a.nx, a.ny, a.nz};
+    int nb = partial_blocks(s.N());
+    if (a.S) hipLaunchKernelGGL(k_coeff_rhs_gen<true>, dim3(nb), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL(k_coeff_rhs_gen<false>, dim3(nb), dim3(kBlock), 0, st, a);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_map_radial(const GenArgs& a, double* out, hipStream_t st) {
+    const size_t N = (size_t)a.nx * a.ny * a.nz;
+    hipLaunchKernelGGL(k_map_radial, dim3(stream_blocks(N)), dim3(kBlock), 0, st, a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct_gen(const GenArgs& a, const double* phi, const double* phi_sum, double* u, double* v,
+                              double* w, double* phi_out, hipStream_t st) {
+    Launch3 L = cell_launch(a.nx, a.ny, a.nz);
+    hipLaunchKernelGGL(k_correct_gen, L.grid, L.block, 0, st, a, phi, phi_sum, u, v, w, phi_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_avg_bnd(const Shape& fine, const Bnd<T>& fb, T* const cb[6], hipStream_t st) {
+    for (int q = 0; q < 6; ++q) {
+        if (!fb.s[q] || !cb[q]) continue;
+        const int fa = q < 2 ? fine.ny : fine.nx;        // first (fastest) index of the side array
+        const int fbn = q < 4 ? fine.nz : fine.ny;       // second index
+        dim3 block(32, 8);
+        dim3 grid((fa / 2 + 31) / 32, (fbn / 2 + 7) / 8);
+        hipLaunchKernelGGL(k_avg_bnd<T>, grid, block, 0, st, fa, fbn, fb.s[q], cb[q]);
+    }
     return hipGetLastError();
 }
 
@@ -857,12 +1120,14 @@ hipError_t launch_coeff_to_f32(const double* a, float* b, size_t n, hipStream_t 
     template hipError_t launch_avg_coeff<T>(const Shape&, const T*, const T*, const T*, T*, T*, T*,      \
                                             hipStream_t);                                                \
     template hipError_t launch_rbgs<T>(const Shape&, double, T*, const T*, const T*, const T*, const T*, \
-                                       int, hipStream_t);                                                \
+                                       int, hipStream_t, const Bnd<T>*);                                 \
     template hipError_t launch_resid_restrict<T>(const Shape&, double, const T*, const T*, const T*,     \
-                                                 const T*, const T*, T*, T*, hipStream_t);               \
+                                                 const T*, const T*, T*, T*, hipStream_t, const Bnd<T>*); \
     template hipError_t launch_prolong<T>(const Shape&, T*, const T*, hipStream_t);                      \
     template hipError_t launch_resid_norm<T>(const Shape&, double, const T*, const T*, const T*,         \
-                                             const T*, const T*, double*, int*, hipStream_t);            \
+                                             const T*, const T*, double*, int*, hipStream_t,             \
+                                             const Bnd<T>*);                                             \
+    template hipError_t launch_avg_bnd<T>(const Shape&, const Bnd<T>&, T* const*, hipStream_t);         \
     template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);
 MG_INST(double)
 MG_INST(float)

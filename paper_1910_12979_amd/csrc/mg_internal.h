@@ -29,6 +29,36 @@ struct LevelArrays {
     T* bz = nullptr;
 };
 
+// Outflow sides of a level (phi = 0 on their boundary faces): for each side
+// (x low, x high, y low, y high, z low, z high) the coefficient of the
+// boundary face of every cell on that side, or null for a periodic or wall
+// side.  x sides are indexed [k][j], y sides [k][i], z sides [j][i].
+template <typename T>
+struct Bnd {
+    const T* s[6];
+};
+
+// Extra diagonal of cell (i,j,k) from its outflow boundary faces.  The face
+// lies half a cell from the centre and its ghost value is -phi_c, so each
+// contributes b (-phi_c - phi_c): 2 b on the diagonal, nothing to the
+// neighbour sum.  Sides summed in the fixed order above, then doubled.
+template <typename T>
+__device__ inline T bnd_diag(const Bnd<T>& B, int i, int j, int k, int nx, int ny, int nz) {
+    T d = T(0);
+    if (i == 0 && B.s[0]) d = d + B.s[0][(size_t)k * ny + j];
+    if (i == nx - 1 && B.s[1]) d = d + B.s[1][(size_t)k * ny + j];
+    if (j == 0 && B.s[2]) d = d + B.s[2][(size_t)k * nx + i];
+    if (j == ny - 1 && B.s[3]) d = d + B.s[3][(size_t)k * nx + i];
+    if (k == 0 && B.s[4]) d = d + B.s[4][(size_t)j * nx + i];
+    if (k == nz - 1 && B.s[5]) d = d + B.s[5][(size_t)j * nx + i];
+    return d + d;
+}
+
+// Cells on side q of an nx x ny x nz level (the size of its boundary array).
+inline size_t bnd_count(int q, int nx, int ny, int nz) {
+    return q < 2 ? (size_t)ny * nz : q < 4 ? (size_t)nx * nz : (size_t)nx * ny;
+}
+
 struct Level {
     int nx = 0, ny = 0, nz = 0;
     size_t N = 0;
@@ -37,6 +67,11 @@ struct Level {
     LevelArrays<float> s;    // FP32 mirrors (mixed precision only)
     double* phi2_d = nullptr;  // second phi buffer (out-of-place sweeps swap with d.phi)
     float* phi2_s = nullptr;
+    double* bnd_d[6] = {};   // outflow boundary-face coefficients (null: not an outflow side)
+    float* bnd_s[6] = {};    // FP32 mirrors (mixed precision only)
+    bool has_bnd = false;
+    Bnd<double> bnd64() const { return Bnd<double>{{bnd_d[0], bnd_d[1], bnd_d[2], bnd_d[3], bnd_d[4], bnd_d[5]}}; }
+    Bnd<float> bnd32() const { return Bnd<float>{{bnd_s[0], bnd_s[1], bnd_s[2], bnd_s[3], bnd_s[4], bnd_s[5]}}; }
 };
 
 struct Shape {
@@ -67,12 +102,15 @@ struct BottomLevel {
     const T* bx;        // stored low-face coefficients (global)
     const T* by;
     const T* bz;
+    int has_bnd;        // outflow sides present
+    Bnd<T> bnd;
 };
 
 template <typename T>
 struct BottomArgs {
     int nlev;           // bottom levels; the last one is solved directly
     int pre, post;      // sweeps before / after the coarse correction
+    int singular;       // no outflow side: coarsest solve with mean removals
     const double* minv; // inverse of the coarsest-level matrix
     const T* f;         // right-hand side of the first bottom level (global)
     T* phi;             // its phi (global), written
@@ -87,6 +125,54 @@ hipError_t launch_bottom_multi(const BottomArgs<T>* d, int nprob, hipStream_t st
 
 // ---- kernel launchers (kernels.hip) ---------------------------------------
 // All launch on `stream` and return hipGetLastError().
+
+// General boundaries and base states (outflow sides, radial beta0).  side[q]
+// per side (x low, x high, y low, y high, z low, z high): 0 periodic, 1 wall,
+// 2 outflow.  beta0: plane-parallel (b0c, b0e) or, with prof != null, the
+// radial profile prof[m] at r = (m + 1/2) dr about (cx, cy, cz), linear in r
+// between profile points and constant beyond the ends.
+struct GenArgs {
+    int nx, ny, nz;
+    int side[6];
+    double h;
+    const double* rho;
+    const double* b0c;
+    const double* b0e;
+    int nr;
+    double dr;
+    const double* prof;
+    double cx, cy, cz;
+    const double* S;         // null: coefficients only
+    const double* u;
+    const double* v;
+    const double* w;
+    const double* w0;        // per-layer dp0/dt term (plane-parallel), nullable
+    double* bx;
+    double* by;
+    double* bz;
+    double* bnd[6];          // outflow boundary-face coefficients (null for other sides)
+    double* f;
+    double* partials;
+};
+// Level-0 coefficients (low faces: interior and periodic faces beta0_face /
+// (0.5 (rho_L + rho_R)), walls and outflow sides 0; outflow boundary faces
+// beta0_face / rho_cell into bnd), the right-hand side f = D(beta0 U) -
+// beta0_c (S - w0) with every face velocity weighted by its own face's beta0,
+// and partial rows as launch_coeff_rhs.
+hipError_t launch_coeff_rhs_gen(const GenArgs& a, int* nparts, hipStream_t st);
+// beta0 of the radial profile at the cell centres (nx*ny*nz, C order).
+hipError_t launch_map_radial(const GenArgs& a, double* out, hipStream_t st);
+// Velocity correction with general sides: U -= (phi_c - phi_nb) / h / rho_face
+// on interior, periodic and outflow faces (outflow: ghost -phi_c, rho_face =
+// rho_cell), the potential phi - mean (mean = *phi_sum / N, or 0 with
+// phi_sum = null); periodic duplicate faces refreshed; phi_out (nullable) =
+// phi - mean.
+hipError_t launch_correct_gen(const GenArgs& a, const double* phi, const double* phi_sum, double* u,
+                              double* v, double* w, double* phi_out, hipStream_t st);
+// Coarse boundary-face coefficients: mean of the 2x2 fine faces of each
+// outflow side (same order as the interior faces).
+template <typename T>
+hipError_t launch_avg_bnd(const Shape& fine, const Bnd<T>& fb, T* const cb[6], hipStream_t st);
 
 // Level-0 coefficients and right-hand side, plus per-block partial sums
 // {sum f, sum |f|, #non-finite inputs, #non-positive rho/beta0}.
@@ -117,12 +203,12 @@ hipError_t launch_avg_coeff(const Shape& fine, const T* bx, const T* by, const T
 // One red-black GS sweep (red then black), in place.
 template <typename T>
 hipError_t launch_rbgs(const Shape& s, double h, T* phi, const T* f, const T* bx,
-                       const T* by, const T* bz, int nsweeps, hipStream_t st);
+                       const T* by, const T* bz, int nsweeps, hipStream_t st, const Bnd<T>* bnd = nullptr);
 // f_c = R (f - L phi); phi_c = 0.
 template <typename T>
 hipError_t launch_resid_restrict(const Shape& fine, double h, const T* phi, const T* f,
                                  const T* bx, const T* by, const T* bz, T* fc, T* phic,
-                                 hipStream_t st);
+                                 hipStream_t st, const Bnd<T>* bnd = nullptr);
 // phi += P phic.
 template <typename T>
 hipError_t launch_prolong(const Shape& fine, T* phi, const T* phic, hipStream_t st);
@@ -130,21 +216,25 @@ hipError_t launch_prolong(const Shape& fine, T* phi, const T* phic, hipStream_t 
 template <typename T>
 hipError_t launch_resid_norm(const Shape& s, double h, const T* phi, const T* f, const T* bx,
                              const T* by, const T* bz, double* partials, int* nparts,
-                             hipStream_t st);
+                             hipStream_t st, const Bnd<T>* bnd = nullptr);
 // Finest level, coefficients recomputed from rho: residual partial rows (r
 // stored when r_out != nullptr) and fused residual + restriction.
 hipError_t launch_resid_norm_rho(const Shape& s, double h, const RhoArgs& ra, const double* phi,
                                  const double* f, double* r_out, double* partials, int* nparts,
-                                 hipStream_t st);
+                                 hipStream_t st, const Bnd<double>* bnd = nullptr);
 hipError_t launch_resid_restrict_rho(const Shape& fine, double h, const RhoArgs& ra, const double* phi,
-                                     const double* f, double* fc, double* phic, hipStream_t st);
-// Coarsest level: build M = -A + c 1 1^T from the coefficients and invert it
-// in place (one workgroup).  minv holds N*N doubles.
+                                     const double* f, double* fc, double* phic, hipStream_t st,
+                                     const Bnd<double>* bnd = nullptr);
+// Coarsest level: build M = -A + c 1 1^T (singular operator) or M = -A
+// (outflow sides, bnd given) from the coefficients and invert it in place
+// (one workgroup).  minv holds N*N doubles.
 hipError_t launch_coarse_setup(const Shape& s, double h, const double* bx, const double* by,
-                               const double* bz, double* minv, hipStream_t st);
-// Coarsest level: phi = zero-mean solution of L phi = f (f's mean removed first).
+                               const double* bz, double* minv, hipStream_t st,
+                               const Bnd<double>* bnd = nullptr, int singular = 1);
+// Coarsest level: phi = zero-mean solution of L phi = f (f's mean removed
+// first); with singular = 0 plainly phi = M^-1 (-f).
 hipError_t launch_coarse_solve(int N, const double* minv, const double* f, double* phi,
-                               hipStream_t st);
+                               hipStream_t st, int singular = 1);
 // Partial rows {sum phi, 0, 0, 0}.
 hipError_t launch_sum(const Shape& s, const double* a, double* partials, int* nparts,
                       hipStream_t st);
@@ -163,7 +253,7 @@ hipError_t launch_copy(double* dst, const double* src, size_t n, hipStream_t st)
 // r = f - L phi (FP64), partial rows {sum r^2, max|r|, #nonfinite, 0}; r stored.
 hipError_t launch_resid_store(const Shape& s, double h, const double* phi, const double* f,
                               const double* bx, const double* by, const double* bz, double* r,
-                              double* partials, int* nparts, hipStream_t st);
+                              double* partials, int* nparts, hipStream_t st, const Bnd<double>* bnd = nullptr);
 // r32 = (float)(r / *rmax), rmax = max |r| (a device scalar).
 hipError_t launch_to_f32(const double* r, float* r32, size_t n, const double* rmax,
                          hipStream_t st);
@@ -178,7 +268,7 @@ hipError_t launch_next_scale(const double* res, double* scales, size_t n, hipStr
 hipError_t launch_scale_to_f32(const double* a, float* b, size_t n, double s, hipStream_t st);
 // Coarsest level in FP32 cycles: phi32 = (float) solve((double) f32).
 hipError_t launch_coarse_solve_f32(int N, const double* minv, const float* f, float* phi,
-                                   hipStream_t st);
+                                   hipStream_t st, int singular = 1);
 
 int num_blocks_for_partials(const Shape& s);
 

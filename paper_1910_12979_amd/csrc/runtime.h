@@ -23,6 +23,9 @@ struct mg_hierarchy {
     int device = 0;
     int nlev = 0;
     int px = 0, py = 0, pz = 0;
+    int side[6] = {};              // per side: 0 periodic, 1 wall, 2 outflow (x low, x high, ..., z high)
+    bool outflow = false;          // some side is an outflow side
+    bool singular = true;          // no outflow side: phi defined up to a constant
     mg::Level lev[mg::kMaxLevels];
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -56,6 +59,16 @@ struct mg_hierarchy {
 };
 
 namespace mg {
+// Radial base state of a solve: beta0 profile prof[m] at r = (m + 1/2) dr
+// about c (prof == nullptr: plane-parallel beta0).
+struct Radial {
+    int nr = 0;
+    double dr = 0.0;
+    const double* prof = nullptr;
+    double c[3] = {0.0, 0.0, 0.0};
+};
+// Per-side codes (x low, x high, ..., z high) of mg_params::bc.
+void sides_from_bc(const mg_params* p, int side[6]);
 void set_error(const std::string& s);
 int hip_fail(hipError_t e, const char* what, int line);
 int count_levels(int nx, int ny, int nz);
@@ -65,7 +78,7 @@ int setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_hierarchy** o
 int destroy(mg_hierarchy* H);
 int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
             double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st,
-            const double* w0 = nullptr);
+            const double* w0 = nullptr, const Radial* rad = nullptr);
 double model_bytes(const mg_params& p, int cycles, int mixed);
 // First level run by the one-workgroup bottom solver (phi and f of it and of
 // every coarser level fit in its LDS), or -1.
@@ -78,5 +91,5 @@ template <typename T>
 void bottom_args(mg_hierarchy* H, int l, BottomArgs<T>& a);
 int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
                        const double* S, const double* u, const double* v, const double* w, hipStream_t st,
-                       const double* w0 = nullptr);
+                       const double* w0 = nullptr, const Radial* rad = nullptr);
 }  // namespace mg

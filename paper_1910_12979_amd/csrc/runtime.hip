@@ -46,6 +46,21 @@ int count_levels(int nx, int ny, int nz) {
     return n;
 }
 
+void sides_from_bc(const mg_params* p, int side[6]) {
+    for (int d = 0; d < 3; ++d) {
+        int lo = 1, hi = 1;                        // walls
+        switch (p->bc[d]) {
+            case MG_BC_PERIODIC: lo = hi = 0; break;
+            case MG_BC_OUTFLOW: lo = hi = 2; break;
+            case MG_BC_WALL_OUTFLOW: hi = 2; break;
+            case MG_BC_OUTFLOW_WALL: lo = 2; break;
+            default: break;
+        }
+        side[2 * d] = lo;
+        side[2 * d + 1] = hi;
+    }
+}
+
 int validate_params(const mg_params* p) {
     if (!p) {
         set_error("null params");
@@ -56,8 +71,9 @@ int validate_params(const mg_params* p) {
         return MG_ERR_INVALID_ARG;
     }
     for (int d = 0; d < 3; ++d)
-        if (p->bc[d] != MG_BC_PERIODIC && p->bc[d] != MG_BC_WALL) {
-            set_error("bc must be MG_BC_PERIODIC or MG_BC_WALL");
+        if (p->bc[d] < MG_BC_PERIODIC || p->bc[d] > MG_BC_OUTFLOW_WALL) {
+            set_error("bc must be one of MG_BC_PERIODIC, MG_BC_WALL, MG_BC_OUTFLOW, MG_BC_WALL_OUTFLOW, "
+                      "MG_BC_OUTFLOW_WALL");
             return MG_ERR_INVALID_ARG;
         }
     if (p->pre_sweeps < 0 || p->post_sweeps < 0 || p->max_cycles < 0 || p->max_cycles > 100000 ||
@@ -106,11 +122,28 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
             s.by = (float*)take(N * 4);
             s.bz = (float*)take(N * 4);
         }
+        // outflow sides: boundary-face coefficients of the level
+        int side[6];
+        sides_from_bc(p, side);
+        double* bd[6] = {};
+        float* bs[6] = {};
+        for (int q = 0; q < 6; ++q) {
+            if (side[q] != 2) continue;
+            const size_t nb = bnd_count(q, p->n[0] >> l, p->n[1] >> l, p->n[2] >> l);
+            bd[q] = (double*)take(nb * 8);
+            if (mixed) bs[q] = (float*)take(nb * 4);
+        }
         if (H) {
             H->lev[l].d = d;
             H->lev[l].s = s;
             H->lev[l].phi2_d = phi2_d;
             H->lev[l].phi2_s = phi2_s;
+            H->lev[l].has_bnd = false;
+            for (int q = 0; q < 6; ++q) {
+                H->lev[l].bnd_d[q] = bd[q];
+                H->lev[l].bnd_s[q] = bs[q];
+                if (bd[q]) H->lev[l].has_bnd = true;
+            }
         }
     }
     size_t Nc = (size_t)(p->n[0] >> (nl - 1)) * (p->n[1] >> (nl - 1)) * (p->n[2] >> (nl - 1));
@@ -173,6 +206,11 @@ int setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_hierarchy** o
     H->px = p->bc[0] == MG_BC_PERIODIC;
     H->py = p->bc[1] == MG_BC_PERIODIC;
     H->pz = p->bc[2] == MG_BC_PERIODIC;
+    sides_from_bc(p, H->side);
+    H->outflow = false;
+    for (int q = 0; q < 6; ++q)
+        if (H->side[q] == 2) H->outflow = true;
+    H->singular = !H->outflow;
     H->nlev = count_levels(p->n[0], p->n[1], p->n[2]);
     hipGetDevice(&H->device);
     if (workspace) {
@@ -243,12 +281,52 @@ static int read_scalars(mg_hierarchy* H, int first, int count, hipStream_t st) {
     return MG_OK;
 }
 
+// Arguments of the general-boundary kernels for level 0 of H.
+static GenArgs gen_args(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
+                        const Radial* rad) {
+    GenArgs g{};
+    Level& L0 = H->lev[0];
+    g.nx = L0.nx;
+    g.ny = L0.ny;
+    g.nz = L0.nz;
+    for (int q = 0; q < 6; ++q) {
+        g.side[q] = H->side[q];
+        g.bnd[q] = L0.bnd_d[q];
+    }
+    g.h = L0.h;
+    g.rho = rho;
+    g.b0c = b0c;
+    g.b0e = b0e;
+    if (rad && rad->prof) {
+        g.nr = rad->nr;
+        g.dr = rad->dr;
+        g.prof = rad->prof;
+        g.cx = rad->c[0];
+        g.cy = rad->c[1];
+        g.cz = rad->c[2];
+    }
+    g.bx = L0.d.bx;
+    g.by = L0.d.by;
+    g.bz = L0.d.bz;
+    g.f = L0.d.f;
+    g.partials = H->partials;
+    return g;
+}
+
 int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
                        const double* S, const double* u, const double* v, const double* w,
-                       hipStream_t st, const double* w0) {
+                       hipStream_t st, const double* w0, const Radial* rad) {
     Level& L0 = H->lev[0];
     int np = 0;
-    if (S) {
+    if (H->outflow || (rad && rad->prof)) {
+        GenArgs g = gen_args(H, rho, b0c, b0e, rad);
+        g.S = S;
+        g.u = u;
+        g.v = v;
+        g.w = w;
+        g.w0 = w0;
+        HIPCHK(launch_coeff_rhs_gen(g, &np, st));
+    } else if (S) {
         HIPCHK(launch_coeff_rhs(shape_of(L0), H->px, H->py, H->pz, L0.h, rho, b0c, b0e, S, u, v, w, L0.d.bx,
                                 L0.d.by, L0.d.bz, L0.d.f, H->partials, &np, st, w0));
     } else {
@@ -261,15 +339,20 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
         Level& F = H->lev[l];
         Level& C = H->lev[l + 1];
         HIPCHK(launch_avg_coeff<double>(shape_of(F), F.d.bx, F.d.by, F.d.bz, C.d.bx, C.d.by, C.d.bz, st));
+        if (F.has_bnd) HIPCHK(launch_avg_bnd<double>(shape_of(F), F.bnd64(), C.bnd_d, st));
     }
     Level& Lc = H->lev[H->nlev - 1];
-    HIPCHK(launch_coarse_setup(shape_of(Lc), Lc.h, Lc.d.bx, Lc.d.by, Lc.d.bz, H->minv, st));
+    const Bnd<double> cb = Lc.bnd64();
+    HIPCHK(launch_coarse_setup(shape_of(Lc), Lc.h, Lc.d.bx, Lc.d.by, Lc.d.bz, H->minv, st,
+                               Lc.has_bnd ? &cb : nullptr, H->singular ? 1 : 0));
     if (H->p.precision == MG_MIXED) {
         for (int l = 0; l < H->nlev; ++l) {
             Level& L = H->lev[l];
             HIPCHK(launch_coeff_to_f32(L.d.bx, L.s.bx, L.N, st));
             HIPCHK(launch_coeff_to_f32(L.d.by, L.s.by, L.N, st));
             HIPCHK(launch_coeff_to_f32(L.d.bz, L.s.bz, L.N, st));
+            for (int q = 0; q < 6; ++q)
+                if (L.bnd_d[q]) HIPCHK(launch_coeff_to_f32(L.bnd_d[q], L.bnd_s[q], bnd_count(q, L.nx, L.ny, L.nz), st));
         }
     }
     H->coeffs_valid = true;
@@ -300,6 +383,9 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
         else phic = H->lev[l + 1].s.phi;
     }
     Shape s = shape_of(F);
+    Bnd<T> bnd;
+    if constexpr (dbl) bnd = F.bnd64();
+    else bnd = F.bnd32();
     if (first == kInProlong && nsweeps == 0) {
         HIPCHK(launch_prolong<T>(s, A->phi, phic, st));
         return MG_OK;
@@ -307,7 +393,7 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
     if (!sweep_fusable<T>(F.nx, F.ny, F.nz)) {
         if (first == kInProlong) HIPCHK(launch_prolong<T>(s, A->phi, phic, st));
         if (first == kInZero) HIPCHK(launch_fill<T>(A->phi, F.N, T(0), st));
-        HIPCHK(launch_rbgs<T>(s, F.h, A->phi, A->f, A->bx, A->by, A->bz, nsweeps, st));
+        HIPCHK(launch_rbgs<T>(s, F.h, A->phi, A->f, A->bx, A->by, A->bz, nsweeps, st, &bnd));
         return MG_OK;
     }
     // finest level: coefficients from rho (FP64) or its FP32 copy (mixed solve)
@@ -333,6 +419,8 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
         else a.rho = H->rho32;
         a.b0c = H->rho.b0c;
         a.b0e = H->rho.b0e;
+        a.has_bnd = F.has_bnd ? 1 : 0;
+        a.bnd = bnd;
         HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain,
                                sweep_config_for(F.nx, F.ny, F.nz, use_rho, dbl), st));
         std::swap(A->phi, *alt);
@@ -346,6 +434,8 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
     Level& F = H->lev[l];
     Level& C = H->lev[l + 1];
     Shape s = shape_of(F);
+    const Bnd<double> b64 = F.bnd64();
+    const Bnd<float> b32 = F.bnd32();
     if constexpr (std::is_same<T, double>::value) {
         if (l == 0 && H->rho.rho) {
             if (sweep_fusable<double>(F.nx, F.ny, F.nz)) {
@@ -364,13 +454,16 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
                 a.b0e = H->rho.b0e;
                 a.fc = C.d.f;
                 a.phic_out = C.d.phi;
+                a.has_bnd = F.has_bnd ? 1 : 0;
+                a.bnd = b64;
                 HIPCHK(launch_resid_restrict_tiled(a, sweep_config_for(F.nx, F.ny, F.nz, true), st));
             } else {
-                HIPCHK(launch_resid_restrict_rho(s, F.h, H->rho, F.d.phi, F.d.f, C.d.f, C.d.phi, st));
+                HIPCHK(launch_resid_restrict_rho(s, F.h, H->rho, F.d.phi, F.d.f, C.d.f, C.d.phi, st, &b64));
             }
             return MG_OK;
         }
-        HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f, C.d.phi, st));
+        HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f, C.d.phi, st,
+                                             &b64));
     } else {
         if (l == 0 && H->rho32_on) {
             SweepArgs<float> a{};
@@ -388,10 +481,13 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
             a.b0e = H->rho.b0e;
             a.fc = C.s.f;
             a.phic_out = C.s.phi;
+            a.has_bnd = F.has_bnd ? 1 : 0;
+            a.bnd = b32;
             HIPCHK(launch_resid_restrict_tiled<float>(a, sweep_config_for(F.nx, F.ny, F.nz, true, false), st));
             return MG_OK;
         }
-        HIPCHK(launch_resid_restrict<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, C.s.f, C.s.phi, st));
+        HIPCHK(launch_resid_restrict<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, C.s.f, C.s.phi, st,
+                                            &b32));
     }
     return MG_OK;
 }
@@ -420,6 +516,7 @@ void bottom_args(mg_hierarchy* H, int l, BottomArgs<T>& a) {
     a.nlev = H->nlev - l;
     a.pre = H->p.pre_sweeps;
     a.post = H->p.post_sweeps;
+    a.singular = H->singular ? 1 : 0;
     a.minv = H->minv;
     int off = 0;
     for (int b = 0; b < a.nlev; ++b) {
@@ -436,6 +533,9 @@ void bottom_args(mg_hierarchy* H, int l, BottomArgs<T>& a) {
         v.bx = A->bx;
         v.by = A->by;
         v.bz = A->bz;
+        v.has_bnd = F.has_bnd ? 1 : 0;
+        if constexpr (dbl) v.bnd = F.bnd64();
+        else v.bnd = F.bnd32();
         off += 2 * (int)F.N;
         if (b == 0) {
             a.f = A->f;
@@ -462,10 +562,11 @@ static int vcycle(mg_hierarchy* H, int l, hipStream_t st, int pre_done = 0, bool
         return MG_OK;
     }
     if (l == H->nlev - 1) {
+        const int sing = H->singular ? 1 : 0;
         if constexpr (std::is_same<T, double>::value)
-            HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st));
+            HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st, sing));
         else
-            HIPCHK(launch_coarse_solve_f32((int)F.N, H->minv, F.s.f, F.s.phi, st));
+            HIPCHK(launch_coarse_solve_f32((int)F.N, H->minv, F.s.f, F.s.phi, st, sing));
         return MG_OK;
     }
     const bool from_zero = l > 0 ? pre_done == 0 : zero_start;
@@ -486,14 +587,16 @@ static int vcycle32(mg_hierarchy* H, int l, hipStream_t st) { return vcycle<floa
 static int level0_residual(mg_hierarchy* H, double* r_store, hipStream_t st) {
     Level& L0 = H->lev[0];
     int np = 0;
+    const Bnd<double> b64 = L0.bnd64();
     if (H->rho.rho) {
-        HIPCHK(launch_resid_norm_rho(shape_of(L0), L0.h, H->rho, L0.d.phi, L0.d.f, r_store, H->partials, &np, st));
+        HIPCHK(launch_resid_norm_rho(shape_of(L0), L0.h, H->rho, L0.d.phi, L0.d.f, r_store, H->partials, &np, st,
+                                     &b64));
     } else if (r_store) {
         HIPCHK(launch_resid_store(shape_of(L0), L0.h, L0.d.phi, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, r_store,
-                                  H->partials, &np, st));
+                                  H->partials, &np, st, &b64));
     } else {
         HIPCHK(launch_resid_norm<double>(shape_of(L0), L0.h, L0.d.phi, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz,
-                                         H->partials, &np, st));
+                                         H->partials, &np, st, &b64));
     }
     int rc = reduce_to(H, np, kSlotRes, st);
     if (rc) return rc;
@@ -529,6 +632,8 @@ static int enqueue_sweep_norm(mg_hierarchy* H, hipStream_t st) {
     a.b0c = H->rho.b0c;
     a.b0e = H->rho.b0e;
     a.partials = H->partials;
+    a.has_bnd = L0.has_bnd ? 1 : 0;
+    a.bnd = L0.bnd64();
     int np = 0;
     HIPCHK(launch_sweep_norm(a, sweep_config_for(L0.nx, L0.ny, L0.nz, true), &np, st));
     int rc = reduce_to(H, np, kSlotRes, st);
@@ -706,6 +811,8 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
         a.corr = L0.s.phi;
         a.r32 = L0.s.f;
         a.scales = scales;
+        a.has_bnd = L0.has_bnd ? 1 : 0;
+        a.bnd = L0.bnd64();
         int np = 0;
         HIPCHK(launch_refine(a, cfg, &np, s));
         std::swap(L0.d.phi, L0.phi2_d);
@@ -849,8 +956,9 @@ static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStrea
 
 static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
                         const double* S, double* u, double* v, double* w, double* phi_out, mg_stats* stats,
-                        hipStream_t st, const double* w0) {
-    if (!H || !rho || !b0c || !b0e || !S || !u || !v || !w) {
+                        hipStream_t st, const double* w0, const Radial* rad) {
+    const bool radial = rad && rad->prof;
+    if (!H || !rho || (!radial && (!b0c || !b0e)) || !S || !u || !v || !w) {
         set_error("null argument to mac_project");
         return MG_ERR_INVALID_ARG;
     }
@@ -867,8 +975,10 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         HIPCHK(launch_copy(H->rho_own, rho, L0.N, st));
         rho_src = H->rho_own;
     }
-    H->rho = RhoArgs{rho_src, b0c, b0e, H->px, H->py, H->pz};
-    int rc = build_coefficients(H, rho, b0c, b0e, S, u, v, w, st, w0);
+    // plane-parallel beta0: the finest-level sweeps recompute their
+    // coefficients from rho; a radial beta0 leaves them to the stored ones
+    H->rho = radial ? RhoArgs{} : RhoArgs{rho_src, b0c, b0e, H->px, H->py, H->pz};
+    int rc = build_coefficients(H, rho, b0c, b0e, S, u, v, w, st, w0, rad);
     if (rc) return rc;
     rc = read_scalars(H, kSlotRhs * kReduceWidth, kReduceWidth, st);
     if (rc) return rc;
@@ -884,7 +994,9 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         set_error("rho and beta0 must be positive");
         return S_->status = MG_ERR_INVALID_ARG;
     }
-    if (std::fabs(sf) > 1e-8 * saf) {
+    // an outflow side makes the operator non-singular: any f is admissible
+    // and neither f nor phi has its mean removed
+    if (H->singular && std::fabs(sf) > 1e-8 * saf) {
         set_error("incompatible right-hand side: |sum f| > 1e-8 sum |f|");
         return S_->status = MG_ERR_INCOMPATIBLE_RHS;
     }
@@ -894,7 +1006,7 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         S_->hist_len = 1;
         S_->resid_hist[0] = 0.0;
     } else {
-        double mean = sf / (double)L0.N;
+        double mean = H->singular ? sf / (double)L0.N : 0.0;
         S_->mean_removed = mean;
         int np = 0;
         HIPCHK(launch_shift_norm(shape_of(L0), L0.d.f, mean, H->partials, &np, st));
@@ -912,15 +1024,28 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         }
     }
     int np = 0;
-    HIPCHK(launch_sum(shape_of(L0), L0.d.phi, H->partials, &np, st));
-    rc = reduce_to(H, np, kSlotPhi, st);
-    if (rc) return rc;
-    HIPCHK(launch_correct(shape_of(L0), H->px, H->py, H->pz, L0.h, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
-                          L0.d.phi, H->scal + kSlotPhi * kReduceWidth, u, v, w, phi_out, st));
+    if (H->singular) {
+        HIPCHK(launch_sum(shape_of(L0), L0.d.phi, H->partials, &np, st));
+        rc = reduce_to(H, np, kSlotPhi, st);
+        if (rc) return rc;
+    }
+    if (H->outflow || radial) {
+        const GenArgs g = gen_args(H, rho, b0c, b0e, rad);
+        HIPCHK(launch_correct_gen(g, L0.d.phi, H->singular ? H->scal + kSlotPhi * kReduceWidth : nullptr, u, v, w,
+                                  phi_out, st));
+    } else {
+        HIPCHK(launch_correct(shape_of(L0), H->px, H->py, H->pz, L0.h, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
+                              L0.d.phi, H->scal + kSlotPhi * kReduceWidth, u, v, w, phi_out, st));
+    }
     HIPCHK(hipEventRecord(H->ev1, st));
-    rc = read_scalars(H, kSlotPhi * kReduceWidth, kReduceWidth, st);
-    if (rc) return rc;
-    S_->phi_mean = H->host[kSlotPhi * kReduceWidth] / (double)L0.N;
+    if (H->singular) {
+        rc = read_scalars(H, kSlotPhi * kReduceWidth, kReduceWidth, st);
+        if (rc) return rc;
+        S_->phi_mean = H->host[kSlotPhi * kReduceWidth] / (double)L0.N;
+    } else {
+        HIPCHK(hipStreamSynchronize(st));
+        S_->phi_mean = 0.0;
+    }
     float ms = 0.f;
     hipEventElapsedTime(&ms, H->ev0, H->ev1);
     S_->ms_total = ms;
@@ -931,8 +1056,9 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
 }
 
 int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
-            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st, const double* w0) {
-    int rc = project_impl(H, rho, b0c, b0e, S, u, v, w, phi_out, stats, st, w0);
+            double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st, const double* w0,
+            const Radial* rad) {
+    int rc = project_impl(H, rho, b0c, b0e, S, u, v, w, phi_out, stats, st, w0, rad);
     if (H) H->rho32_on = false;
     // the caller's rho may not outlive the call: later mg_vcycle / step calls
     // use the stored finest-level coefficients (bit-identical values)
@@ -1039,8 +1165,12 @@ int level_step(mg_hierarchy* H, int l, int step, int arg, hipStream_t st) {
                 set_error("MG_STEP_COARSE needs the coarsest level");
                 return MG_ERR_INVALID_ARG;
             }
-            HIPCHK(launch_coarse_setup(s, F.h, F.d.bx, F.d.by, F.d.bz, H->minv, st));
-            HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st));
+            {
+                const Bnd<double> cb = F.bnd64();
+                HIPCHK(launch_coarse_setup(s, F.h, F.d.bx, F.d.by, F.d.bz, H->minv, st, F.has_bnd ? &cb : nullptr,
+                                           H->singular ? 1 : 0));
+                HIPCHK(launch_coarse_solve((int)F.N, H->minv, F.d.f, F.d.phi, st, H->singular ? 1 : 0));
+            }
             break;
         default:
             set_error("unknown step");
@@ -1193,6 +1323,58 @@ int mg_beta0_from_p0(int32_t nz, double rho0_base, const double* p0_edge, const 
     const hipError_t e = launch_beta0_from_p0(nz, rho0_base, p0_edge, p0_cc, gamma1_cc, beta0_cc, beta0_edge,
                                               (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch_beta0_from_p0", __LINE__);
+    return MG_OK;
+}
+
+static int radial_args(int32_t nr, double dr, const double* beta0_r, const double centre[3], Radial* r) {
+    if (nr < 1 || !(dr > 0.0) || !std::isfinite(dr) || !beta0_r || !centre || !std::isfinite(centre[0]) ||
+        !std::isfinite(centre[1]) || !std::isfinite(centre[2])) {
+        set_error("bad radial base state arguments");
+        return MG_ERR_INVALID_ARG;
+    }
+    r->nr = nr;
+    r->dr = dr;
+    r->prof = beta0_r;
+    for (int d = 0; d < 3; ++d) r->c[d] = centre[d];
+    return MG_OK;
+}
+
+int mac_project_radial(mg_handle h, const double* rho, int32_t nr, double dr, const double* beta0_r,
+                       const double centre[3], const double* S, double* u, double* v, double* w, double* phi,
+                       mg_stats* stats, void* stream) {
+    Radial r;
+    int rc = radial_args(nr, dr, beta0_r, centre, &r);
+    if (rc) return rc;
+    try {
+        return project(h, rho, nullptr, nullptr, S, u, v, w, phi, stats, (hipStream_t)stream, nullptr, &r);
+    } catch (...) {
+        set_error("internal error in mac_project_radial");
+        return MG_ERR_HIP;
+    }
+}
+
+int mg_map_radial(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t nr, double dr, const double* beta0_r,
+                  const double centre[3], double* beta0_out, void* stream) {
+    Radial r;
+    int rc = radial_args(nr, dr, beta0_r, centre, &r);
+    if (rc) return rc;
+    if (nx < 1 || ny < 1 || nz < 1 || !(dx > 0.0) || !beta0_out) {
+        set_error("bad mg_map_radial arguments");
+        return MG_ERR_INVALID_ARG;
+    }
+    GenArgs g{};
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.h = dx;
+    g.nr = r.nr;
+    g.dr = r.dr;
+    g.prof = r.prof;
+    g.cx = r.c[0];
+    g.cy = r.c[1];
+    g.cz = r.c[2];
+    const hipError_t e = launch_map_radial(g, beta0_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch_map_radial", __LINE__);
     return MG_OK;
 }
 

@@ -5,6 +5,8 @@
 
 #include <type_traits>
 
+#include "mg_internal.h"
+
 namespace mg {
 
 constexpr int kSweepTX = 32;     // smallest tile width (x) of any configuration
@@ -47,6 +49,8 @@ struct SweepArgs {
     const float* corr;         // kInCorrect: input is phi_in + corr / scales[0]
     float* r32;                // kOpRefine: r32 = (float)(scales[1] * (f - L phi))
     const double* scales;      // device {scale of corr's right-hand side, scale for r32}
+    int has_bnd;               // outflow sides: their boundary faces add to the diagonal
+    Bnd<T> bnd;
 };
 
 template <typename T>

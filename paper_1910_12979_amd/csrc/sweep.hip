@@ -87,7 +87,7 @@ __device__ inline int xcd_tile(int b, int total) {
 
 // The body of one tile: shared by the single-problem kernel and the batched
 // kernel, so a problem's values do not depend on how it was launched.
-template <typename T, int TX, int TY, bool kRho, int kIn, int kOp>
+template <typename T, int TX, int TY, bool kRho, int kIn, int kOp, bool kBnd>
 __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile) {
     constexpr bool kNorm = kOp == kOpSweepNorm;    // sweep + residual norm of its input
     constexpr bool kRR = kOp == kOpResidRestrict;  // residual + restriction only (no sweep)
@@ -131,6 +131,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const T ih2 = T(1) / a.h2;
     const T half = T(0.5);
     const T cscale = kIn == kInCorrect ? (T)(1.0 / a.scales[0]) : T(0);    // exact: a power of two
+    // outflow sides (kBnd): extra diagonal of cell c of the pair at plane t
+    auto bdiag = [&](int c, int t) -> T { return bnd_diag(a.bnd, gxw + c, gyw, wrap3(t, nz), nx, ny, nz); };
 
     size_t ccol = 0;
     if (kIn == kInProlong) ccol = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
@@ -266,7 +268,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     // only the sum of squares is kept: a non-finite residual makes it non-finite
     double nrm2 = 0.0;
     const double rscale = kIR ? a.scales[1] : 0.0;
-    auto resid_at = [&](int c, int s_t, int b, T pm, T pc, T pp, T bzl, T bzh, T fc) -> T {
+    auto resid_at = [&](int c, int t, int s_t, int b, T pm, T pc, T pp, T bzl, T bzh, T fc) -> T {
         const int lx = lx0 + c;
         T r = sbx[s_t][ly][lx] * (sphi[b][ly][lx - 1] - pc);
         r = r + sbx[s_t][ly][lx + 1] * (sphi[b][ly][lx + 1] - pc);
@@ -274,6 +276,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         r = r + sby[s_t][ly + 1][lx] * (sphi[b][ly + 1][lx] - pc);
         r = r + bzl * (pm - pc);
         r = r + bzh * (pp - pc);
+        if constexpr (kBnd) r = r - bdiag(c, t) * pc;
         return fc - r * ih2;
     };
     auto accumulate = [&](T r) {
@@ -339,6 +342,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + byh;
             den = den + bzl;
             den = den + bzh;
+            if constexpr (kBnd) den = den + bdiag(rsel, t);
             const T pin = Rcur;
             Rcur = qdiv(num - h2 * (rsel ? Fc1 : Fc0), den);
             // the update solves den phi_new = num - h^2 f, so f - L phi_in =
@@ -349,16 +353,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         if (kNorm && t >= z0 && t < z1 && writes) {
             accumulate(rred);
             const int cb = 1 - rsel;             // black cell of the pair: full evaluation
-            accumulate(resid_at(cb, s_t, cur, cb ? Pm1 : Pm0, cb ? Pc1 : Pc0, cb ? Pp1 : Pp0, cb ? bc1 : bc0,
+            accumulate(resid_at(cb, t, s_t, cur, cb ? Pm1 : Pm0, cb ? Pc1 : Pc0, cb ? Pp1 : Pp0, cb ? bc1 : bc0,
                                 cb ? bp1 : bp0, cb ? Fc1 : Fc0));
         }
         if (kRR && t >= z0 && t < z1 && writes) {
-            sR[cur][ly][lx0] = resid_at(0, s_t, cur, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
-            sR[cur][ly][lx0 + 1] = resid_at(1, s_t, cur, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
+            sR[cur][ly][lx0] = resid_at(0, t, s_t, cur, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
+            sR[cur][ly][lx0 + 1] = resid_at(1, t, s_t, cur, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
         }
         if (kIR && t >= z0 && t < z1 && writes) {
-            const T r0 = resid_at(0, s_t, cur, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
-            const T r1 = resid_at(1, s_t, cur, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
+            const T r0 = resid_at(0, t, s_t, cur, Pm0, Pc0, Pp0, bc0, bp0, Fc0);
+            const T r1 = resid_at(1, t, s_t, cur, Pm1, Pc1, Pp1, bc1, bp1, Fc1);
             const double d0 = (double)r0, d1 = (double)r1;
             nrm2 += d0 * d0;
             nrm2 += d1 * d1;
@@ -399,6 +403,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + byh;
             den = den + bzl;
             den = den + bzh;
+            if constexpr (kBnd) den = den + bdiag(rsel, tb);
             const T blk = qdiv(num - h2 * (rsel ? Fm1 : Fm0), den);
             T* dst = a.phi_out + (size_t)tb * plane + col;
             if (rsel) st2(dst, Rm, blk);
@@ -453,20 +458,23 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
 // two of their workgroups (7 waves and 79 KB of LDS each) share a CU; left
 // alone the compiler gives several of them a few more registers, which
 // halves the workgroups per CU.  Smaller tiles are limited by LDS first.
-template <typename T, int TX, int TY>
+// The outflow-side variants (kBnd) need more registers and are left alone.
+template <typename T, int TX, int TY, bool kBnd>
 struct SweepWaves {
-    static constexpr int value = (sizeof(T) == 8 && TX == 64 && TY == 8) ? 4 : 1;
+    static constexpr int value = (sizeof(T) == 8 && TX == 64 && TY == 8 && !kBnd) ? 4 : 1;
 };
-#define MG_SWEEP_WAVES __attribute__((amdgpu_waves_per_eu(SweepWaves<T, TX, TY>::value)))
+#define MG_SWEEP_WAVES(B) __attribute__((amdgpu_waves_per_eu(SweepWaves<T, TX, TY, B>::value)))
 
-template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
-__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES void k_sweep(SweepArgs<T> a) {
-    sweep_body<T, TX, TY, kRho, kIn, kOp>(a, xcd_tile(blockIdx.x, gridDim.x));
+// kBnd: the level has outflow sides (their boundary faces add to the
+// diagonal); a separate instantiation so the other kernels carry none of it.
+template <typename T, int TX, int TY, bool kRho, int kIn, int kOp, bool kBnd>
+__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(kBnd) void k_sweep(SweepArgs<T> a) {
+    sweep_body<T, TX, TY, kRho, kIn, kOp, kBnd>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched form: problem p owns tiles [prefix[p], prefix[p+1]) of the launch.
 template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
-__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES void k_sweep_multi(const SweepArgs<T>* __restrict__ descs,
+__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(false) void k_sweep_multi(const SweepArgs<T>* __restrict__ descs,
                                                                          const int* __restrict__ prefix, int nprob) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     int lo = 0, hi = nprob;
@@ -476,7 +484,7 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES void k_swee
         else hi = mid;
     }
     const SweepArgs<T> a = descs[lo];
-    sweep_body<T, TX, TY, kRho, kIn, kOp>(a, b - prefix[lo]);
+    sweep_body<T, TX, TY, kRho, kIn, kOp, false>(a, b - prefix[lo]);   // batches have no outflow sides
 }
 
 template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
@@ -495,8 +503,12 @@ hipError_t launch_t(const SweepArgs<T>& a0, int tzc, hipStream_t st, int* nblock
     int ntz = (a.nz + tzc - 1) / tzc;
     int blocks = a.ntx * a.nty * ntz;
     if (nblocks) *nblocks = blocks;
-    hipLaunchKernelGGL((k_sweep<T, TX, TY, kRho, kIn, kOp>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0,
-                       st, a);
+    if (a.has_bnd)
+        hipLaunchKernelGGL((k_sweep<T, TX, TY, kRho, kIn, kOp, true>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)),
+                           0, st, a);
+    else
+        hipLaunchKernelGGL((k_sweep<T, TX, TY, kRho, kIn, kOp, false>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)),
+                           0, st, a);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "libmacproj.so")
 MG_OK, MG_PENDING = 0, 1
 STATUS = {0: "OK", 1: "PENDING", -1: "INVALID_ARG", -2: "BAD_SIZE", -3: "INCOMPATIBLE_RHS",
           -4: "NOT_CONVERGED", -5: "NONFINITE", -6: "OOM", -7: "HIP", -8: "BUDGET", -9: "BUSY"}
-MG_BC_PERIODIC, MG_BC_WALL = 0, 1
+MG_BC_PERIODIC, MG_BC_WALL, MG_BC_OUTFLOW, MG_BC_WALL_OUTFLOW, MG_BC_OUTFLOW_WALL = 0, 1, 2, 3, 4
 MG_FP64, MG_MIXED = 0, 1
 STEP = {"smooth": 0, "resid_restrict": 1, "prolong": 2, "coarse": 3, "down": 4, "up": 5}
 ARRAY = {"phi": 0, "f": 1, "bx": 2, "by": 3, "bz": 4}
@@ -103,6 +103,9 @@ def lib():
         L.mg_set_bottom.argtypes = [vp, i32]
         L.mg_beta0_from_p0.argtypes = [i32, d, vp, vp, vp, vp, vp, vp]
         L.mac_project_full.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
+        d3 = ctypes.POINTER(d)
+        L.mac_project_radial.argtypes = [vp, vp, i32, d, vp, d3, vp, vp, vp, vp, vp, S, vp]
+        L.mg_map_radial.argtypes = [i32, i32, i32, d, i32, d, vp, d3, vp, vp]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -148,13 +151,24 @@ def _ptr(t, dtype=None, shape=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def bc_code(periodic_d, out_lo, out_hi):
+    """mg_bc of one direction from its periodic flag and outflow flags."""
+    if periodic_d:
+        return MG_BC_PERIODIC
+    return {(False, False): MG_BC_WALL, (True, True): MG_BC_OUTFLOW,
+            (False, True): MG_BC_WALL_OUTFLOW, (True, False): MG_BC_OUTFLOW_WALL}[(bool(out_lo), bool(out_hi))]
+
+
 def make_params(n, dx, periodic=(True, True, False), pre_sweeps=2, post_sweeps=2, rtol=1e-10,
-                max_cycles=100, precision="fp64") -> Params:
+                max_cycles=100, precision="fp64", outflow=None) -> Params:
+    """``outflow``: None or six booleans (x low, x high, ..., z high) marking
+    sides of non-periodic directions as outflow sides (phi = 0)."""
     p = Params()
     nx, ny, nz = n
     lib().mg_default_params(ctypes.byref(p), nx, ny, nz, float(dx))
+    outflow = (False,) * 6 if outflow is None else tuple(outflow)
     for d in range(3):
-        p.bc[d] = MG_BC_PERIODIC if periodic[d] else MG_BC_WALL
+        p.bc[d] = bc_code(periodic[d], outflow[2 * d], outflow[2 * d + 1])
     p.pre_sweeps, p.post_sweeps = pre_sweeps, post_sweeps
     p.rtol, p.max_cycles = float(rtol), int(max_cycles)
     p.precision = MG_MIXED if precision in ("mixed", MG_MIXED) else MG_FP64
@@ -251,6 +265,25 @@ class Hierarchy:
         out["code"] = code
         return out
 
+    def mac_project_radial(self, rho, beta0_r, dr, centre, S, u, v, w, phi=None, stream=None, allow=(MG_OK,)):
+        """mac_project with beta0 given as a radial profile beta0_r (device,
+        values at r = (m + 1/2) dr) about ``centre`` (3 floats)."""
+        import torch
+        sh = field_shapes(self.n)
+        f64 = torch.float64
+        st = Stats()
+        nr = int(beta0_r.shape[0])
+        c = (ctypes.c_double * 3)(*[float(x) for x in centre])
+        code = lib().mac_project_radial(self._h, _ptr(rho, f64, sh["rho"], "rho"), nr, float(dr),
+                                        _ptr(beta0_r, f64, (nr,), "beta0_r"), c, _ptr(S, f64, sh["S"], "S"),
+                                        _ptr(u, f64, sh["u"], "u"), _ptr(v, f64, sh["v"], "v"),
+                                        _ptr(w, f64, sh["w"], "w"), _ptr(phi, f64, sh["phi"], "phi"),
+                                        ctypes.byref(st), _stream(stream))
+        _check(code, allow)
+        out = st.as_dict()
+        out["code"] = code
+        return out
+
     def mg_vcycle(self, phi, rhs, stream=None):
         import torch
         sh = field_shapes(self.n)["phi"]
@@ -326,11 +359,26 @@ def mg_beta0_from_p0(rho0_base, p0_edge, p0_cc, gamma1_cc, stream=None):
     return b0c, b0e
 
 
+def mg_map_radial(n, dx, beta0_r, dr, centre, stream=None):
+    """beta0 of a radial profile at the cell centres of an n box (a new
+    device tensor (nz, ny, nx), filled on the stream)."""
+    import torch
+    nx, ny, nz = n
+    f64 = torch.float64
+    nr = int(beta0_r.shape[0])
+    out = torch.empty((nz, ny, nx), dtype=f64, device=beta0_r.device)
+    c = (ctypes.c_double * 3)(*[float(x) for x in centre])
+    _check(lib().mg_map_radial(nx, ny, nz, float(dx), nr, float(dr), _ptr(beta0_r, f64, (nr,), "beta0_r"), c,
+                               _ptr(out, f64, (nz, ny, nx), "beta0_out"), _stream(stream)))
+    return out
+
+
 def to_device(prob, device="cuda", phi=True):
     """Copy an inputs.Problem's host arrays to device tensors (base-state
     arrays that the problem does not carry stay None)."""
     import torch
-    names = ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w", "p0_cc", "p0_edge", "gamma1_cc", "dp0dt_cc")
+    names = ("rho", "beta0_cc", "beta0_edge", "S", "u", "v", "w", "p0_cc", "p0_edge", "gamma1_cc", "dp0dt_cc",
+             "beta0_r")
     t = {name: (torch.from_numpy(np.ascontiguousarray(getattr(prob, name))).to(device)
                 if getattr(prob, name, None) is not None else None)
          for name in names}
@@ -342,7 +390,8 @@ def to_device(prob, device="cuda", phi=True):
 def params_of(prob, precision="fp64", rtol=None, max_cycles=None) -> Params:
     return make_params(prob.n, prob.dx, prob.periodic, prob.pre_sweeps, prob.post_sweeps,
                        prob.rtol if rtol is None else rtol,
-                       prob.max_cycles if max_cycles is None else max_cycles, precision)
+                       prob.max_cycles if max_cycles is None else max_cycles, precision,
+                       outflow=getattr(prob, "outflow", None))
 
 
 def problem_struct(params: Params, d) -> Problem:
