@@ -383,6 +383,37 @@ def full_leg(args, torch, macproj, inputs, dev):
                                                 "beta0 computed on the device each step, dp0/dt term in f"}
 
 
+def star_leg(args, torch, macproj, inputs, dev):
+    """A star-like box of the same size: beta0 a function of the radius from
+    the box centre (radial profile, mapped onto faces and cells on the
+    device), every side an outflow side (phi = 0), FP64 and mixed precision."""
+    prob = inputs.make_star_problem(args.n, Hr=0.1, rho_noise=0.01, seed=6)
+    R = Restorable(macproj, prob, dev)
+    d = R.d
+    out = {"workload": f"{args.n}^3, beta0 = exp(-r/0.1) on a radial profile of {len(prob.beta0_r)} points "
+                       f"(dr = dx/2) about the box centre, outflow on all six sides, rtol 1e-10"}
+    for prec in ("fp64", "mixed"):
+        log(f"star box ({prec}): {args.star_steps} steps")
+        H = macproj.Hierarchy(macproj.params_of(prob, precision=prec))
+
+        def step():
+            R.restore()
+            return H.mac_project_radial(d.rho, d.beta0_r, prob.dr_base, prob.centre, d.S, d.u, d.v, d.w, d.phi)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.star_steps):
+            st = step()
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+        H.close()
+        out[prec] = {"value": args.star_steps / ts, "unit": "solves/s", "ms_per_step": ts * 1e3 / args.star_steps,
+                     "cycles": st["cycles"], "rel_resid": st["rel_resid"]}
+    return out
+
+
 def cpu_leg(args, prob):
     log("CPU oracle baseline")
     from oracle import oracle as orc
@@ -413,6 +444,7 @@ def main():
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[100.0, 400.0, 2000.0])
     ap.add_argument("--serve-requests", type=int, default=150)
     ap.add_argument("--full-steps", type=int, default=5, help="0 skips the p0/Gamma1 base-state leg")
+    ap.add_argument("--star-steps", type=int, default=5, help="0 skips the radial-base-state outflow leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -447,6 +479,7 @@ def main():
     batch = batch_leg(args, torch, macproj, inputs, dev) if args.batch_reps > 0 else None
     serve = serve_leg(args, torch, macproj, inputs, dev) if args.serve_rates else None
     full = full_leg(args, torch, macproj, inputs, dev) if args.full_steps > 0 else None
+    star = star_leg(args, torch, macproj, inputs, dev) if args.star_steps > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_leg(args, prob)
 
     model_bytes = n ** 3 * (156.0 + cycles * 326.0)
@@ -473,6 +506,7 @@ def main():
         "batch": batch,
         "serve": serve,
         "full_rhs": full,
+        "star_outflow": star,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -126,9 +126,9 @@ int launch_fused(std::vector<Item>& grp, bool use_rho, int in_mode, int op, Stag
                     BHIP(launch_sweep<double>(a, use_rho, in_mode, cfg, st));
                 } else if (op == kOpSweepNorm) {
                     int np = 0;
-                    BHIP(launch_sweep_norm(a, cfg, &np, st));
+                    BHIP(launch_sweep_norm(a, use_rho, cfg, &np, st));
                 } else {
-                    BHIP(launch_resid_restrict_tiled(a, cfg, st));
+                    BHIP(launch_resid_restrict_tiled(a, use_rho, cfg, st));
                 }
             }
             continue;
@@ -427,11 +427,11 @@ int launch_group(std::vector<SweepArgs<T>>& args, const std::vector<int>& cfgs, 
                 if (op == kOpSweep) {
                     BHIP(launch_sweep<T>(args[i], use_rho, in_mode, cfg, st));
                 } else if (op == kOpResidRestrict) {
-                    BHIP(launch_resid_restrict_tiled<T>(args[i], cfg, st));
+                    BHIP(launch_resid_restrict_tiled<T>(args[i], use_rho, cfg, st));
                 } else {
                     if constexpr (std::is_same<T, double>::value) {
                         int np = 0;
-                        BHIP(launch_refine(args[i], cfg, &np, st));
+                        BHIP(launch_refine(args[i], use_rho, cfg, &np, st));
                     }
                 }
             }

@@ -437,8 +437,9 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
     const Bnd<double> b64 = F.bnd64();
     const Bnd<float> b32 = F.bnd32();
     if constexpr (std::is_same<T, double>::value) {
-        if (l == 0 && H->rho.rho) {
-            if (sweep_fusable<double>(F.nx, F.ny, F.nz)) {
+        const bool rho0 = l == 0 && H->rho.rho;
+        if (l == 0 && sweep_fusable<double>(F.nx, F.ny, F.nz)) {
+            {   // finest level: the sweep's tiles, coefficients from rho or stored
                 SweepArgs<double> a{};
                 a.nx = F.nx;
                 a.ny = F.ny;
@@ -452,14 +453,19 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
                 a.rho = H->rho.rho;
                 a.b0c = H->rho.b0c;
                 a.b0e = H->rho.b0e;
+                a.bx = F.d.bx;
+                a.by = F.d.by;
+                a.bz = F.d.bz;
                 a.fc = C.d.f;
                 a.phic_out = C.d.phi;
                 a.has_bnd = F.has_bnd ? 1 : 0;
                 a.bnd = b64;
-                HIPCHK(launch_resid_restrict_tiled(a, sweep_config_for(F.nx, F.ny, F.nz, true), st));
-            } else {
-                HIPCHK(launch_resid_restrict_rho(s, F.h, H->rho, F.d.phi, F.d.f, C.d.f, C.d.phi, st, &b64));
+                HIPCHK(launch_resid_restrict_tiled(a, rho0, sweep_config_for(F.nx, F.ny, F.nz, rho0), st));
             }
+            return MG_OK;
+        }
+        if (rho0) {
+            HIPCHK(launch_resid_restrict_rho(s, F.h, H->rho, F.d.phi, F.d.f, C.d.f, C.d.phi, st, &b64));
             return MG_OK;
         }
         HIPCHK(launch_resid_restrict<double>(s, F.h, F.d.phi, F.d.f, F.d.bx, F.d.by, F.d.bz, C.d.f, C.d.phi, st,
@@ -483,7 +489,7 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
             a.phic_out = C.s.phi;
             a.has_bnd = F.has_bnd ? 1 : 0;
             a.bnd = b32;
-            HIPCHK(launch_resid_restrict_tiled<float>(a, sweep_config_for(F.nx, F.ny, F.nz, true, false), st));
+            HIPCHK(launch_resid_restrict_tiled<float>(a, true, sweep_config_for(F.nx, F.ny, F.nz, true, false), st));
             return MG_OK;
         }
         HIPCHK(launch_resid_restrict<float>(s, F.h, F.s.phi, F.s.f, F.s.bx, F.s.by, F.s.bz, C.s.f, C.s.phi, st,
@@ -631,11 +637,15 @@ static int enqueue_sweep_norm(mg_hierarchy* H, hipStream_t st) {
     a.rho = H->rho.rho;
     a.b0c = H->rho.b0c;
     a.b0e = H->rho.b0e;
+    a.bx = L0.d.bx;
+    a.by = L0.d.by;
+    a.bz = L0.d.bz;
     a.partials = H->partials;
     a.has_bnd = L0.has_bnd ? 1 : 0;
     a.bnd = L0.bnd64();
+    const bool rho0 = H->rho.rho != nullptr;
     int np = 0;
-    HIPCHK(launch_sweep_norm(a, sweep_config_for(L0.nx, L0.ny, L0.nz, true), &np, st));
+    HIPCHK(launch_sweep_norm(a, rho0, sweep_config_for(L0.nx, L0.ny, L0.nz, rho0), &np, st));
     int rc = reduce_to(H, np, kSlotRes, st);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
@@ -779,8 +789,9 @@ double residual_scale(double norm2_sqrt, size_t n) {
 static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_out, double* rel_out,
                                     const std::function<void(int, double)>& record, hipStream_t st) {
     Level& L0 = H->lev[0];
-    HIPCHK(launch_coeff_to_f32(H->rho.rho, H->rho32, L0.N, st));
-    H->rho32_on = true;
+    const bool rho0 = H->rho.rho != nullptr;      // else stored finest-level coefficients (radial beta0)
+    if (rho0) HIPCHK(launch_coeff_to_f32(H->rho.rho, H->rho32, L0.N, st));
+    H->rho32_on = rho0;
     HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
     const double s0 = residual_scale(fnorm, L0.N);           // residual = f while phi = 0
     HIPCHK(launch_scale_to_f32(L0.d.f, L0.s.f, L0.N, s0, st));
@@ -789,8 +800,8 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
     H->host[kSlotScale * kReduceWidth + 1] = s0;
     HIPCHK(hipMemcpyAsync(scales, H->host + kSlotScale * kReduceWidth, 2 * sizeof(double), hipMemcpyHostToDevice,
                           st));
-    const int cfg = sweep_config_for(L0.nx, L0.ny, L0.nz, true);
-    auto iteration = [H, &L0, cfg, scales](hipStream_t s) {
+    const int cfg = sweep_config_for(L0.nx, L0.ny, L0.nz, rho0);
+    auto iteration = [H, &L0, cfg, scales, rho0](hipStream_t s) {
         int rc = vcycle<float>(H, 0, s, 0, true);
         if (rc) return rc;
         SweepArgs<double> a{};
@@ -808,13 +819,16 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
         a.b0c = H->rho.b0c;
         a.b0e = H->rho.b0e;
         a.partials = H->partials;
+        a.bx = L0.d.bx;
+        a.by = L0.d.by;
+        a.bz = L0.d.bz;
         a.corr = L0.s.phi;
         a.r32 = L0.s.f;
         a.scales = scales;
         a.has_bnd = L0.has_bnd ? 1 : 0;
         a.bnd = L0.bnd64();
         int np = 0;
-        HIPCHK(launch_refine(a, cfg, &np, s));
+        HIPCHK(launch_refine(a, rho0, cfg, &np, s));
         std::swap(L0.d.phi, L0.phi2_d);
         rc = reduce_to(H, np, kSlotRes, s);
         if (rc) return rc;
@@ -868,8 +882,7 @@ static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStrea
     };
     const bool mixed = H->p.precision == MG_MIXED;
     if (H->p.rtol >= 1.0) status = MG_OK;
-    const bool fused = H->rho.rho && H->p.pre_sweeps >= 1 && H->nlev > 1 &&
-                       sweep_fusable<double>(L0.nx, L0.ny, L0.nz);
+    const bool fused = H->p.pre_sweeps >= 1 && H->nlev > 1 && sweep_fusable<double>(L0.nx, L0.ny, L0.nz);
     const bool fused_norm = !mixed && fused;
     if (mixed && fused && status == MG_ERR_NOT_CONVERGED) {
         auto rec = [&](int c, double r) {

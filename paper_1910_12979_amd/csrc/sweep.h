@@ -59,25 +59,24 @@ bool sweep_fusable(int nx, int ny, int nz);
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cfg, hipStream_t st);
 
-// Finest-level sweep of phi_in (as stored, coefficients from rho) that also
-// writes, per tile, the partial row {sum r^2, 0, 0, 0} of the residual
-// r = f - L phi_in of its INPUT (a non-finite r makes the sum non-finite).
-// *nparts = rows written.
-hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st);
+// Finest-level sweep of phi_in (as stored; coefficients from rho, or stored
+// with use_rho = false) that also writes, per tile, the partial row
+// {sum r^2, 0, 0, 0} of the residual r = f - L phi_in of its INPUT (a
+// non-finite r makes the sum non-finite).  *nparts = rows written.
+hipError_t launch_sweep_norm(const SweepArgs<double>& a, bool use_rho, int cfg, int* nparts, hipStream_t st);
 
-// Finest level (coefficients from rho): f_c = R (f - L phi), phi_c = 0, using
-// the sweep's tiles (each face coefficient computed once per cell).  Needs
-// even tile origins, which every configuration has.
+// Finest level: f_c = R (f - L phi), phi_c = 0, using the sweep's tiles (each
+// face coefficient computed or read once per cell).  Needs even tile
+// origins, which every configuration has.
 template <typename T>
-hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, int cfg, hipStream_t st);
+hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, bool use_rho, int cfg, hipStream_t st);
 
-// Refinement step of the mixed-precision solve (finest level, FP64,
-// coefficients from rho): phi_out = phi_in + corr / scales[0]; per tile the
-// partial row {sum r^2, 0, 0, 0} of r = f - L phi_out; and
-// r32 = (float)(scales[1] * r).  The scales are powers of two read from
-// device memory, so a captured launch stays valid as they change.
-// *nparts = rows written.
-hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st);
+// Refinement step of the mixed-precision solve (finest level, FP64):
+// phi_out = phi_in + corr / scales[0]; per tile the partial row
+// {sum r^2, 0, 0, 0} of r = f - L phi_out; and r32 = (float)(scales[1] * r).
+// The scales are powers of two read from device memory, so a captured launch
+// stays valid as they change.  *nparts = rows written.
+hipError_t launch_refine(const SweepArgs<double>& a, bool use_rho, int cfg, int* nparts, hipStream_t st);
 
 // Batched form (one launch, many problems): descriptor i (device) is problem
 // i's SweepArgs with tz/ntx/nty filled (sweep_geometry), prefix (device,

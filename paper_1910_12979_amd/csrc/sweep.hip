@@ -131,8 +131,28 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const T ih2 = T(1) / a.h2;
     const T half = T(0.5);
     const T cscale = kIn == kInCorrect ? (T)(1.0 / a.scales[0]) : T(0);    // exact: a power of two
-    // outflow sides (kBnd): extra diagonal of cell c of the pair at plane t
-    auto bdiag = [&](int c, int t) -> T { return bnd_diag(a.bnd, gxw + c, gyw, wrap3(t, nz), nx, ny, nz); };
+    // outflow sides (kBnd): extra diagonal of cell c of the pair at plane t,
+    // the sum of bnd_diag in the same side order.  The x/y boundary faces a
+    // thread's cells touch are fixed for the whole march (x low only for the
+    // even cell, x high only for the odd one: nx is even); z boundary faces
+    // only occur on the first and last plane (uniform over the workgroup).
+    int bxy = 0;
+    if constexpr (kBnd)
+        bxy = ((gxw == 0 && a.bnd.s[0]) ? 1 : 0) | ((gxw + 1 == nx - 1 && a.bnd.s[1]) ? 2 : 0) |
+              ((gyw == 0 && a.bnd.s[2]) ? 4 : 0) | ((gyw == ny - 1 && a.bnd.s[3]) ? 8 : 0);
+    auto bdiag = [&](int c, int t) -> T {
+        const int tw = wrap3(t, nz);
+        T d = T(0);
+        if (bxy) {
+            if (c == 0 && (bxy & 1)) d = d + a.bnd.s[0][(size_t)tw * ny + gyw];
+            if (c == 1 && (bxy & 2)) d = d + a.bnd.s[1][(size_t)tw * ny + gyw];
+            if (bxy & 4) d = d + a.bnd.s[2][(size_t)tw * nx + gxw + c];
+            if (bxy & 8) d = d + a.bnd.s[3][(size_t)tw * nx + gxw + c];
+        }
+        if (tw == 0 && a.bnd.s[4]) d = d + a.bnd.s[4][(size_t)gyw * nx + gxw + c];
+        if (tw == nz - 1 && a.bnd.s[5]) d = d + a.bnd.s[5][(size_t)gyw * nx + gxw + c];
+        return d + d;
+    };
 
     size_t ccol = 0;
     if (kIn == kInProlong) ccol = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
@@ -623,62 +643,81 @@ hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cf
     }
 }
 
-hipError_t launch_sweep_norm(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st) {
+template <bool kRho>
+hipError_t launch_sweep_norm_t(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st) {
     const SweepCfg& c = kSweepCfgs[cfg];
-    if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
     constexpr int N = kOpSweepNorm;
     switch (cfg) {
-        case 0: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 1: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 2: return launch_t<double, 64, 8, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 8: return launch_t<double, 64, 8, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 9: return launch_t<double, 64, 16, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 10: return launch_t<double, 32, 32, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 11: return launch_t<double, 64, 16, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 3: return launch_t<double, 32, 16, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 4: return launch_t<double, 64, 4, true, kInPlain, N>(a, c.tz, st, nparts);
-        case 5: return launch_t<double, 32, 4, true, kInPlain, N>(a, c.tz, st, nparts);
-        default: return launch_t<double, 32, 8, true, kInPlain, N>(a, c.tz, st, nparts);
+        case 0: return launch_t<double, 32, 8, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 1: return launch_t<double, 32, 8, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 2: return launch_t<double, 64, 8, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 8: return launch_t<double, 64, 8, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 9: return launch_t<double, 64, 16, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 10: return launch_t<double, 32, 32, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 11: return launch_t<double, 64, 16, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 3: return launch_t<double, 32, 16, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 4: return launch_t<double, 64, 4, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 5: return launch_t<double, 32, 4, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        default: return launch_t<double, 32, 8, kRho, kInPlain, N>(a, c.tz, st, nparts);
+    }
+}
+
+hipError_t launch_sweep_norm(const SweepArgs<double>& a, bool use_rho, int cfg, int* nparts, hipStream_t st) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
+    return use_rho ? launch_sweep_norm_t<true>(a, cfg, nparts, st) : launch_sweep_norm_t<false>(a, cfg, nparts, st);
+}
+
+template <typename T, bool kRho>
+hipError_t launch_resid_restrict_tiled_t(const SweepArgs<T>& a, int cfg, hipStream_t st) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    constexpr int R = kOpResidRestrict;
+    switch (cfg) {
+        case 0: return launch_t<T, 32, 8, kRho, kInPlain, R>(a, c.tz, st);
+        case 1: return launch_t<T, 32, 8, kRho, kInPlain, R>(a, c.tz, st);
+        case 2: return launch_t<T, 64, 8, kRho, kInPlain, R>(a, c.tz, st);
+        case 8: return launch_t<T, 64, 8, kRho, kInPlain, R>(a, c.tz, st);
+        case 9: return launch_t<T, 64, 16, kRho, kInPlain, R>(a, c.tz, st);
+        case 10: return launch_t<T, 32, 32, kRho, kInPlain, R>(a, c.tz, st);
+        case 11: return launch_t<T, 64, 16, kRho, kInPlain, R>(a, c.tz, st);
+        case 3: return launch_t<T, 32, 16, kRho, kInPlain, R>(a, c.tz, st);
+        case 4: return launch_t<T, 64, 4, kRho, kInPlain, R>(a, c.tz, st);
+        case 5: return launch_t<T, 32, 4, kRho, kInPlain, R>(a, c.tz, st);
+        default: return launch_t<T, 32, 8, kRho, kInPlain, R>(a, c.tz, st);
     }
 }
 
 template <typename T>
-hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, int cfg, hipStream_t st) {
+hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, bool use_rho, int cfg, hipStream_t st) {
     const SweepCfg& c = kSweepCfgs[cfg];
     if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
-    constexpr int R = kOpResidRestrict;
+    return use_rho ? launch_resid_restrict_tiled_t<T, true>(a, cfg, st)
+                   : launch_resid_restrict_tiled_t<T, false>(a, cfg, st);
+}
+
+template <bool kRho>
+hipError_t launch_refine_t(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st) {
+    const SweepCfg& c = kSweepCfgs[cfg];
+    constexpr int R = kOpRefine, I = kInCorrect;
     switch (cfg) {
-        case 0: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
-        case 1: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
-        case 2: return launch_t<T, 64, 8, true, kInPlain, R>(a, c.tz, st);
-        case 8: return launch_t<T, 64, 8, true, kInPlain, R>(a, c.tz, st);
-        case 9: return launch_t<T, 64, 16, true, kInPlain, R>(a, c.tz, st);
-        case 10: return launch_t<T, 32, 32, true, kInPlain, R>(a, c.tz, st);
-        case 11: return launch_t<T, 64, 16, true, kInPlain, R>(a, c.tz, st);
-        case 3: return launch_t<T, 32, 16, true, kInPlain, R>(a, c.tz, st);
-        case 4: return launch_t<T, 64, 4, true, kInPlain, R>(a, c.tz, st);
-        case 5: return launch_t<T, 32, 4, true, kInPlain, R>(a, c.tz, st);
-        default: return launch_t<T, 32, 8, true, kInPlain, R>(a, c.tz, st);
+        case 0: return launch_t<double, 32, 8, kRho, I, R>(a, c.tz, st, nparts);
+        case 1: return launch_t<double, 32, 8, kRho, I, R>(a, c.tz, st, nparts);
+        case 2: return launch_t<double, 64, 8, kRho, I, R>(a, c.tz, st, nparts);
+        case 8: return launch_t<double, 64, 8, kRho, I, R>(a, c.tz, st, nparts);
+        case 9: return launch_t<double, 64, 16, kRho, I, R>(a, c.tz, st, nparts);
+        case 10: return launch_t<double, 32, 32, kRho, I, R>(a, c.tz, st, nparts);
+        case 11: return launch_t<double, 64, 16, kRho, I, R>(a, c.tz, st, nparts);
+        case 3: return launch_t<double, 32, 16, kRho, I, R>(a, c.tz, st, nparts);
+        case 4: return launch_t<double, 64, 4, kRho, I, R>(a, c.tz, st, nparts);
+        case 5: return launch_t<double, 32, 4, kRho, I, R>(a, c.tz, st, nparts);
+        default: return launch_t<double, 32, 8, kRho, I, R>(a, c.tz, st, nparts);
     }
 }
 
-hipError_t launch_refine(const SweepArgs<double>& a, int cfg, int* nparts, hipStream_t st) {
+hipError_t launch_refine(const SweepArgs<double>& a, bool use_rho, int cfg, int* nparts, hipStream_t st) {
     const SweepCfg& c = kSweepCfgs[cfg];
     if (a.nx < c.tx || a.ny < c.ty) return hipErrorInvalidValue;
-    constexpr int R = kOpRefine, I = kInCorrect;
-    switch (cfg) {
-        case 0: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
-        case 1: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
-        case 2: return launch_t<double, 64, 8, true, I, R>(a, c.tz, st, nparts);
-        case 8: return launch_t<double, 64, 8, true, I, R>(a, c.tz, st, nparts);
-        case 9: return launch_t<double, 64, 16, true, I, R>(a, c.tz, st, nparts);
-        case 10: return launch_t<double, 32, 32, true, I, R>(a, c.tz, st, nparts);
-        case 11: return launch_t<double, 64, 16, true, I, R>(a, c.tz, st, nparts);
-        case 3: return launch_t<double, 32, 16, true, I, R>(a, c.tz, st, nparts);
-        case 4: return launch_t<double, 64, 4, true, I, R>(a, c.tz, st, nparts);
-        case 5: return launch_t<double, 32, 4, true, I, R>(a, c.tz, st, nparts);
-        default: return launch_t<double, 32, 8, true, I, R>(a, c.tz, st, nparts);
-    }
+    return use_rho ? launch_refine_t<true>(a, cfg, nparts, st) : launch_refine_t<false>(a, cfg, nparts, st);
 }
 
 template <typename T, int TX, int TY>
@@ -743,8 +782,8 @@ template bool sweep_fusable<double>(int, int, int);
 template bool sweep_fusable<float>(int, int, int);
 template hipError_t launch_sweep<double>(const SweepArgs<double>&, bool, int, int, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs<float>&, bool, int, int, hipStream_t);
-template hipError_t launch_resid_restrict_tiled<double>(const SweepArgs<double>&, int, hipStream_t);
-template hipError_t launch_resid_restrict_tiled<float>(const SweepArgs<float>&, int, hipStream_t);
+template hipError_t launch_resid_restrict_tiled<double>(const SweepArgs<double>&, bool, int, hipStream_t);
+template hipError_t launch_resid_restrict_tiled<float>(const SweepArgs<float>&, bool, int, hipStream_t);
 template hipError_t launch_sweep_multi<double>(const SweepArgs<double>*, const int*, int, int, bool, int, int, int,
                                                hipStream_t);
 template hipError_t launch_sweep_multi<float>(const SweepArgs<float>*, const int*, int, int, bool, int, int, int,
