@@ -721,6 +721,17 @@ __global__ void k_correct_gen(GenArgs a, const double* __restrict__ phi, const d
     }
 }
 
+// Per-cell boundary diagonal of a level (bnd_diag of every cell, zero away
+// from the outflow sides), read by the fused sweeps.
+template <typename T>
+__global__ void k_bnd_diag3(int nx, int ny, int nz, Bnd<T> bnd, T* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= nx || j >= ny || k >= nz) return;
+    out[cidx(i, j, k, nx, ny)] = bnd_diag(bnd, i, j, k, nx, ny, nz);
+}
+
 // Coarse boundary faces of one side: cf[A + B*ca] = mean of the fine faces
 // (2A, 2B), (2A+1, 2B), (2A, 2B+1), (2A+1, 2B+1) (first index fastest).
 template <typename T>
@@ -1038,6 +1049,13 @@ hipError_t launch_correct_gen(const GenArgs& a, const double* phi, const double*
 }
 
 template <typename T>
+hipError_t launch_bnd_diag3(const Shape& s, const Bnd<T>& bnd, T* out, hipStream_t st) {
+    Launch3 L = cell_launch(s.nx, s.ny, s.nz);
+    hipLaunchKernelGGL(k_bnd_diag3<T>, L.grid, L.block, 0, st, s.nx, s.ny, s.nz, bnd, out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_avg_bnd(const Shape& fine, const Bnd<T>& fb, T* const cb[6], hipStream_t st) {
     for (int q = 0; q < 6; ++q) {
         if (!fb.s[q] || !cb[q]) continue;
@@ -1128,6 +1146,7 @@ hipError_t launch_coeff_to_f32(const double* a, float* b, size_t n, hipStream_t 
                                              const T*, const T*, double*, int*, hipStream_t,             \
                                              const Bnd<T>*);                                             \
     template hipError_t launch_avg_bnd<T>(const Shape&, const Bnd<T>&, T* const*, hipStream_t);         \
+    template hipError_t launch_bnd_diag3<T>(const Shape&, const Bnd<T>&, T*, hipStream_t);              \
     template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);
 MG_INST(double)
 MG_INST(float)

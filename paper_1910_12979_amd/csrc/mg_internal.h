@@ -69,6 +69,8 @@ struct Level {
     float* phi2_s = nullptr;
     double* bnd_d[6] = {};   // outflow boundary-face coefficients (null: not an outflow side)
     float* bnd_s[6] = {};    // FP32 mirrors (mixed precision only)
+    double* dg_d = nullptr;  // per-cell boundary diagonal (outflow sides), FP64
+    float* dg_s = nullptr;   // and from the FP32 boundary faces (mixed precision)
     bool has_bnd = false;
     Bnd<double> bnd64() const { return Bnd<double>{{bnd_d[0], bnd_d[1], bnd_d[2], bnd_d[3], bnd_d[4], bnd_d[5]}}; }
     Bnd<float> bnd32() const { return Bnd<float>{{bnd_s[0], bnd_s[1], bnd_s[2], bnd_s[3], bnd_s[4], bnd_s[5]}}; }
@@ -173,6 +175,9 @@ hipError_t launch_correct_gen(const GenArgs& a, const double* phi, const double*
 // outflow side (same order as the interior faces).
 template <typename T>
 hipError_t launch_avg_bnd(const Shape& fine, const Bnd<T>& fb, T* const cb[6], hipStream_t st);
+// out[c] = bnd_diag of every cell (the per-cell boundary diagonal).
+template <typename T>
+hipError_t launch_bnd_diag3(const Shape& s, const Bnd<T>& bnd, T* out, hipStream_t st);
 
 // Level-0 coefficients and right-hand side, plus per-block partial sums
 // {sum f, sum |f|, #non-finite inputs, #non-positive rho/beta0}.

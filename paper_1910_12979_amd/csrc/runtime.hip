@@ -127,11 +127,17 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
         sides_from_bc(p, side);
         double* bd[6] = {};
         float* bs[6] = {};
+        double* dgd = nullptr;
+        float* dgs = nullptr;
         for (int q = 0; q < 6; ++q) {
             if (side[q] != 2) continue;
             const size_t nb = bnd_count(q, p->n[0] >> l, p->n[1] >> l, p->n[2] >> l);
             bd[q] = (double*)take(nb * 8);
             if (mixed) bs[q] = (float*)take(nb * 4);
+            if (!dgd) {
+                dgd = (double*)take(N * 8);
+                if (mixed) dgs = (float*)take(N * 4);
+            }
         }
         if (H) {
             H->lev[l].d = d;
@@ -139,6 +145,8 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
             H->lev[l].phi2_d = phi2_d;
             H->lev[l].phi2_s = phi2_s;
             H->lev[l].has_bnd = false;
+            H->lev[l].dg_d = dgd;
+            H->lev[l].dg_s = dgs;
             for (int q = 0; q < 6; ++q) {
                 H->lev[l].bnd_d[q] = bd[q];
                 H->lev[l].bnd_s[q] = bs[q];
@@ -353,7 +361,12 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
             HIPCHK(launch_coeff_to_f32(L.d.bz, L.s.bz, L.N, st));
             for (int q = 0; q < 6; ++q)
                 if (L.bnd_d[q]) HIPCHK(launch_coeff_to_f32(L.bnd_d[q], L.bnd_s[q], bnd_count(q, L.nx, L.ny, L.nz), st));
+            if (L.has_bnd) HIPCHK(launch_bnd_diag3<float>(shape_of(L), L.bnd32(), L.dg_s, st));
         }
+    }
+    for (int l = 0; l < H->nlev; ++l) {
+        Level& L = H->lev[l];
+        if (L.has_bnd) HIPCHK(launch_bnd_diag3<double>(shape_of(L), L.bnd64(), L.dg_d, st));
     }
     H->coeffs_valid = true;
     return MG_OK;
@@ -421,6 +434,8 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
         a.b0e = H->rho.b0e;
         a.has_bnd = F.has_bnd ? 1 : 0;
         a.bnd = bnd;
+        if constexpr (dbl) a.dg = F.dg_d;
+        else a.dg = F.dg_s;
         HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain,
                                sweep_config_for(F.nx, F.ny, F.nz, use_rho, dbl), st));
         std::swap(A->phi, *alt);
@@ -460,6 +475,7 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
                 a.phic_out = C.d.phi;
                 a.has_bnd = F.has_bnd ? 1 : 0;
                 a.bnd = b64;
+                a.dg = F.dg_d;
                 HIPCHK(launch_resid_restrict_tiled(a, rho0, sweep_config_for(F.nx, F.ny, F.nz, rho0), st));
             }
             return MG_OK;
@@ -489,6 +505,7 @@ static int resid_restrict(mg_hierarchy* H, int l, hipStream_t st) {
             a.phic_out = C.s.phi;
             a.has_bnd = F.has_bnd ? 1 : 0;
             a.bnd = b32;
+            a.dg = F.dg_s;
             HIPCHK(launch_resid_restrict_tiled<float>(a, true, sweep_config_for(F.nx, F.ny, F.nz, true, false), st));
             return MG_OK;
         }
@@ -643,6 +660,7 @@ static int enqueue_sweep_norm(mg_hierarchy* H, hipStream_t st) {
     a.partials = H->partials;
     a.has_bnd = L0.has_bnd ? 1 : 0;
     a.bnd = L0.bnd64();
+    a.dg = L0.dg_d;
     const bool rho0 = H->rho.rho != nullptr;
     int np = 0;
     HIPCHK(launch_sweep_norm(a, rho0, sweep_config_for(L0.nx, L0.ny, L0.nz, rho0), &np, st));
@@ -827,6 +845,7 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
         a.scales = scales;
         a.has_bnd = L0.has_bnd ? 1 : 0;
         a.bnd = L0.bnd64();
+        a.dg = L0.dg_d;
         int np = 0;
         HIPCHK(launch_refine(a, rho0, cfg, &np, s));
         std::swap(L0.d.phi, L0.phi2_d);

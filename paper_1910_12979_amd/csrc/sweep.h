@@ -50,7 +50,8 @@ struct SweepArgs {
     float* r32;                // kOpRefine: r32 = (float)(scales[1] * (f - L phi))
     const double* scales;      // device {scale of corr's right-hand side, scale for r32}
     int has_bnd;               // outflow sides: their boundary faces add to the diagonal
-    Bnd<T> bnd;
+    Bnd<T> bnd;                // which sides are outflow sides (non-null)
+    const T* dg;               // per-cell boundary diagonal (bnd_diag of every cell)
 };
 
 template <typename T>

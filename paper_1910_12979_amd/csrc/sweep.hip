@@ -131,28 +131,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const T ih2 = T(1) / a.h2;
     const T half = T(0.5);
     const T cscale = kIn == kInCorrect ? (T)(1.0 / a.scales[0]) : T(0);    // exact: a power of two
-    // outflow sides (kBnd): extra diagonal of cell c of the pair at plane t,
-    // the sum of bnd_diag in the same side order.  The x/y boundary faces a
-    // thread's cells touch are fixed for the whole march (x low only for the
-    // even cell, x high only for the odd one: nx is even); z boundary faces
-    // only occur on the first and last plane (uniform over the workgroup).
-    int bxy = 0;
+    // outflow sides (kBnd): the level's per-cell boundary diagonal a.dg (zero
+    // away from the outflow sides) is read, like f, two plane steps ahead of
+    // its use, and only by threads whose cells can touch an outflow side:
+    // x/y sides are fixed for the march (x low only for the even cell, x high
+    // only for the odd one: nx is even), z sides occur on the first and last
+    // plane only (uniform over the workgroup).
+    bool bl = false;
     if constexpr (kBnd)
-        bxy = ((gxw == 0 && a.bnd.s[0]) ? 1 : 0) | ((gxw + 1 == nx - 1 && a.bnd.s[1]) ? 2 : 0) |
-              ((gyw == 0 && a.bnd.s[2]) ? 4 : 0) | ((gyw == ny - 1 && a.bnd.s[3]) ? 8 : 0);
-    auto bdiag = [&](int c, int t) -> T {
-        const int tw = wrap3(t, nz);
-        T d = T(0);
-        if (bxy) {
-            if (c == 0 && (bxy & 1)) d = d + a.bnd.s[0][(size_t)tw * ny + gyw];
-            if (c == 1 && (bxy & 2)) d = d + a.bnd.s[1][(size_t)tw * ny + gyw];
-            if (bxy & 4) d = d + a.bnd.s[2][(size_t)tw * nx + gxw + c];
-            if (bxy & 8) d = d + a.bnd.s[3][(size_t)tw * nx + gxw + c];
-        }
-        if (tw == 0 && a.bnd.s[4]) d = d + a.bnd.s[4][(size_t)gyw * nx + gxw + c];
-        if (tw == nz - 1 && a.bnd.s[5]) d = d + a.bnd.s[5][(size_t)gyw * nx + gxw + c];
-        return d + d;
-    };
+        bl = (gxw == 0 && a.bnd.s[0]) || (gxw + 1 == nx - 1 && a.bnd.s[1]) || (gyw == 0 && a.bnd.s[2]) ||
+             (gyw == ny - 1 && a.bnd.s[3]);
+    auto zbnd = [&](int tw) -> bool { return (tw == 0 && a.bnd.s[4]) || (tw == nz - 1 && a.bnd.s[5]); };
 
     size_t ccol = 0;
     if (kIn == kInProlong) ccol = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
@@ -214,6 +203,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         T f0, f1;      // f
         T x0, x1;      // stored bx (coarse levels)
         T y0, y1;      // stored by
+        T g0, g1;      // boundary diagonal (kBnd)
     };
     auto issue = [&](int s, Fly& X) {
         load_phi(min(s + 3, z1 + 1), X.p0, X.p1);
@@ -224,6 +214,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             ld2(a.by + (size_t)tw * plane + col, X.y0, X.y1);
         }
         load_f(min(s + 2, z1), X.f0, X.f1);
+        if constexpr (kBnd) {
+            const int tw = wrap3(min(s + 2, z1), nz);
+            X.g0 = T(0);
+            X.g1 = T(0);
+            if (bl || zbnd(tw)) ld2(a.dg + (size_t)tw * plane + col, X.g0, X.g1);
+        }
     };
     Fly A, B;
     issue(z0 - 3, A);                                  // consumed by step z0-1
@@ -237,6 +233,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     load_q(z0 - 1, Rp0, Rp1);
     load_q(z0, Rq0, Rq1);
     T Fm0 = T(0), Fm1 = T(0), Fc0 = T(0), Fc1 = T(0);
+    T Gm0 = T(0), Gm1 = T(0), Gc0 = T(0), Gc1 = T(0);  // boundary diagonal of planes t-1, t (kBnd)
     T cx0 = T(0), cx1 = T(0), cy0 = T(0), cy1 = T(0);  // stored x/y coefficients of plane t+1
 
     // x/y low-face coefficients of plane t into LDS slot s from the staged rho
@@ -296,7 +293,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         r = r + sby[s_t][ly + 1][lx] * (sphi[b][ly + 1][lx] - pc);
         r = r + bzl * (pm - pc);
         r = r + bzh * (pp - pc);
-        if constexpr (kBnd) r = r - bdiag(c, t) * pc;
+        if constexpr (kBnd) r = r - (c ? Gc1 : Gc0) * pc;
         return fc - r * ih2;
     };
     auto accumulate = [&](T r) {
@@ -314,6 +311,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         //    phi[t+1], rho[t+2] (or bz[t+2]), f[t], bx/by[t+1]; then re-issue
         Fm0 = Fc0; Fm1 = Fc1;
         Fc0 = X.f0; Fc1 = X.f1;
+        if constexpr (kBnd) {
+            Gm0 = Gc0; Gm1 = Gc1;
+            Gc0 = X.g0; Gc1 = X.g1;
+        }
         Pm0 = Pc0; Pm1 = Pc1;
         Pc0 = Pp0; Pc1 = Pp1;
         Pp0 = X.p0; Pp1 = X.p1;
@@ -362,7 +363,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + byh;
             den = den + bzl;
             den = den + bzh;
-            if constexpr (kBnd) den = den + bdiag(rsel, t);
+            if constexpr (kBnd) den = den + (rsel ? Gc1 : Gc0);
             const T pin = Rcur;
             Rcur = qdiv(num - h2 * (rsel ? Fc1 : Fc0), den);
             // the update solves den phi_new = num - h^2 f, so f - L phi_in =
@@ -423,7 +424,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + byh;
             den = den + bzl;
             den = den + bzh;
-            if constexpr (kBnd) den = den + bdiag(rsel, tb);
+            if constexpr (kBnd) den = den + (rsel ? Gm1 : Gm0);
             const T blk = qdiv(num - h2 * (rsel ? Fm1 : Fm0), den);
             T* dst = a.phi_out + (size_t)tb * plane + col;
             if (rsel) st2(dst, Rm, blk);
