@@ -27,6 +27,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mg_oracle.c")
+_SRC_NODAL = os.path.join(_HERE, "nodal_oracle.c")
 _LIB = os.path.join(_HERE, "libmgoracle.so")
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BAD_SIZE", -3: "INCOMPATIBLE_RHS",
@@ -42,7 +43,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas",
-               _SRC, "-o", _LIB + ".tmp", "-lm"]
+               _SRC, _SRC_NODAL, "-o", _LIB + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -51,7 +52,8 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                      os.path.getmtime(_SRC_NODAL)):
             build()
         L = ctypes.CDLL(_LIB)
         i, d = ctypes.c_int, ctypes.c_double
@@ -91,6 +93,25 @@ def lib():
         L.orc_correct_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, _dp, _dp]
         L.orc_mg_create_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, _ip]
         L.orc_mg_create_gen.restype = ctypes.c_void_p
+        L.nod_num_levels.argtypes = [i, i, i, i, i, i]
+        L.nod_sigma.argtypes = [i, i, i, _dp, _dp, _dp]
+        L.nod_apply.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp]
+        L.nod_gs.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, i]
+        L.nod_rhs.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.nod_correct.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp]
+        L.nod_project.argtypes = [i, i, i, i, i, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, d, i, i, i, i, _dp, i,
+                                  _dp]
+        L.nod_mg_create.argtypes = [i, i, i, i, i, i, d, _dp, _ip]
+        L.nod_mg_create.restype = ctypes.c_void_p
+        L.nod_mg_destroy.argtypes = [ctypes.c_void_p]
+        L.nod_mg_nlevels.argtypes = [ctypes.c_void_p]
+        L.nod_mg_level_info.argtypes = [ctypes.c_void_p, i, _ip]
+        L.nod_mg_io.argtypes = [ctypes.c_void_p, i, i, _dp, i]
+        L.nod_mg_smooth.argtypes = [ctypes.c_void_p, i, i]
+        L.nod_mg_resid_restrict.argtypes = [ctypes.c_void_p, i]
+        L.nod_mg_prolong.argtypes = [ctypes.c_void_p, i]
+        L.nod_mg_coarse.argtypes = [ctypes.c_void_p]
+        L.nod_mg_solve.argtypes = [ctypes.c_void_p, _dp, _dp, d, i, i, i, i, _dp, i, _ip]
         L.orc_mac_project_gen.argtypes = [i, i, i, ip6, d, _dp, _dp, _dp, i, d, _dp, _dp, _dp, _dp, _dp, _dp,
                                           _dp, _dp, d, i, i, i, i, _dp, i, _dp]
         _lib = L
@@ -429,3 +450,134 @@ def _project(prob, b0c, b0e, w0, mode, rtol, max_cycles, nu1, nu2):
     return {"status": st, "status_name": STATUS.get(st, str(st)), "phi": phi, "u": u, "v": v, "w": w,
             "cycles": cycles, "hist": hist[: cycles + 1], "rel_resid": stats[1],
             "mean_removed": stats[2], "sum_f": stats[3], "sum_abs_f": stats[4], "norm_f": stats[5]}
+
+
+# ---------------------------------------------------------------- nodal
+# The nodal (cell-velocity) projection: phi on the cell corners, cell-centred
+# velocities (see nodal_oracle.c for the discretisation).
+
+def node_dims(n, periodic):
+    """Node counts (Nx, Ny, Nz): n in a periodic direction, n + 1 otherwise."""
+    return tuple(int(n[d]) + (0 if periodic[d] else 1) for d in range(3))
+
+
+def nodal_num_levels(n, periodic):
+    return lib().nod_num_levels(*_shape_args(n, periodic))
+
+
+def nodal_sigma(rho, b0c):
+    nz, ny, nx = rho.shape
+    sig = np.empty_like(rho)
+    lib().nod_sigma(nx, ny, nz, _p(rho), _p(np.ascontiguousarray(b0c, dtype=np.float64)), _p(sig))
+    return sig
+
+
+def nodal_apply(n, periodic, h, sig, phi):
+    Nx, Ny, Nz = node_dims(n, periodic)
+    out = np.empty((Nz, Ny, Nx))
+    lib().nod_apply(*_shape_args(n, periodic), h, _p(sig), _p(np.ascontiguousarray(phi, dtype=np.float64)), _p(out))
+    return out
+
+
+def nodal_gs(n, periodic, h, sig, phi, f, nsweeps=1):
+    out = np.ascontiguousarray(phi, dtype=np.float64).copy()
+    lib().nod_gs(*_shape_args(n, periodic), h, _p(sig), _p(out), _p(np.ascontiguousarray(f, dtype=np.float64)),
+                 nsweeps)
+    return out
+
+
+def nodal_rhs(n, periodic, h, b0c, uc, vc, wc, S):
+    Nx, Ny, Nz = node_dims(n, periodic)
+    f = np.empty((Nz, Ny, Nx))
+    lib().nod_rhs(*_shape_args(n, periodic), h, _p(np.ascontiguousarray(b0c, dtype=np.float64)), _p(uc), _p(vc),
+                  _p(wc), _p(S), _p(f))
+    return f
+
+
+def nodal_correct(n, periodic, h, rho, phi, uc, vc, wc):
+    uc, vc, wc = uc.copy(), vc.copy(), wc.copy()
+    lib().nod_correct(*_shape_args(n, periodic), h, _p(rho), _p(np.ascontiguousarray(phi, dtype=np.float64)),
+                      _p(uc), _p(vc), _p(wc))
+    return uc, vc, wc
+
+
+class NodalHierarchy:
+    """The oracle's nodal multigrid hierarchy, exposing every step."""
+
+    def __init__(self, n, periodic, h, sig):
+        self.n = tuple(n)
+        self.periodic = tuple(periodic)
+        st = ctypes.c_int(0)
+        self._h = lib().nod_mg_create(*_shape_args(n, periodic), h, _p(np.ascontiguousarray(sig)),
+                                      ctypes.byref(st))
+        if not self._h:
+            raise RuntimeError(f"nodal oracle hierarchy: {STATUS.get(st.value, st.value)}")
+        self.nlevels = lib().nod_mg_nlevels(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().nod_mg_destroy(self._h)
+            self._h = None
+
+    def dims(self, l):
+        d = (ctypes.c_int * 6)()
+        lib().nod_mg_level_info(self._h, l, d)
+        return (d[0], d[1], d[2]), (d[3], d[4], d[5])
+
+    _WHICH = {"phi": 0, "f": 1, "r": 2, "sigma": 3}
+
+    def _shape(self, l, which):
+        (Nx, Ny, Nz), (nx, ny, nz) = self.dims(l)
+        return (nz, ny, nx) if which == "sigma" else (Nz, Ny, Nx)
+
+    def get(self, l, which):
+        out = np.empty(self._shape(l, which))
+        assert lib().nod_mg_io(self._h, l, self._WHICH[which], _p(out), 0) == 0
+        return out
+
+    def set(self, l, which, arr):
+        arr = np.ascontiguousarray(arr, dtype=np.float64)
+        assert arr.shape == self._shape(l, which)
+        assert lib().nod_mg_io(self._h, l, self._WHICH[which], _p(arr), 1) == 0
+
+    def smooth(self, l, nsweeps):
+        lib().nod_mg_smooth(self._h, l, nsweeps)
+
+    def resid_restrict(self, l):
+        lib().nod_mg_resid_restrict(self._h, l)
+
+    def prolong(self, l):
+        lib().nod_mg_prolong(self._h, l)
+
+    def coarse(self):
+        lib().nod_mg_coarse(self._h)
+
+    def solve(self, f, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, mode="algorithm"):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        phi = np.empty_like(f)
+        hist = np.full(max_cycles + 1, np.nan)
+        cyc = ctypes.c_int(0)
+        st = lib().nod_mg_solve(self._h, _p(f), _p(phi), rtol, max_cycles, nu1, nu2,
+                                1 if mode == "definition" else 0, _p(hist), len(hist), ctypes.byref(cyc))
+        return st, phi, hist[: cyc.value + 1]
+
+
+def nodal_project(prob, mode="algorithm", rtol=None, max_cycles=None, nu1=None, nu2=None):
+    """The nodal projection of an inputs.NodalProblem (host copies)."""
+    n, per = prob.n, prob.periodic
+    rtol = prob.rtol if rtol is None else rtol
+    max_cycles = (prob.max_cycles if mode == "algorithm" else 200) if max_cycles is None else max_cycles
+    nu1 = prob.pre_sweeps if nu1 is None else nu1
+    nu2 = prob.post_sweeps if nu2 is None else nu2
+    uc, vc, wc = prob.uc.copy(), prob.vc.copy(), prob.wc.copy()
+    Nx, Ny, Nz = node_dims(n, per)
+    phi = np.zeros((Nz, Ny, Nx))
+    hist = np.full(max_cycles + 1, np.nan)
+    stats = np.zeros(8)
+    st = lib().nod_project(*_shape_args(n, per), prob.dx, _p(prob.rho), _p(prob.beta0_cc), _p(prob.S), _p(uc),
+                           _p(vc), _p(wc), _p(phi), rtol, max_cycles, nu1, nu2, 1 if mode == "definition" else 0,
+                           _p(hist), len(hist), _p(stats))
+    cycles = int(stats[0])
+    return {"status": st, "status_name": STATUS.get(st, str(st)), "phi": phi, "u": uc, "v": vc, "w": wc,
+            "cycles": cycles, "hist": hist[: cycles + 1], "rel_resid": stats[1], "mean_removed": stats[2],
+            "sum_f": stats[3], "sum_abs_f": stats[4], "norm_f": stats[5]}

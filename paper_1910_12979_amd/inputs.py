@@ -31,6 +31,7 @@ import numpy as np
 __all__ = [
     "Problem", "make_problem", "stratified_base_state",
     "make_full_problem", "make_star_problem", "mixed_batch_specs", "serving_requests",
+    "NodalProblem", "make_nodal_problem",
     "SMALL_BOX", "STEEP_256", "MIXED_512",
 ]
 
@@ -283,6 +284,60 @@ def make_star_problem(n, *, Hr=0.15, rho_noise=0.01, S_amp=0.1, seed=0, dx=None,
                    beta0_cc=None, beta0_edge=None, S=np.ascontiguousarray(S), u=u, v=v, w=w,
                    rtol=rtol, max_cycles=max_cycles, seed=seed, H=Hr, outflow=outflow,
                    beta0_r=prof, dr_base=float(dr), centre=tuple(float(a) for a in c))
+
+
+@dataclasses.dataclass
+class NodalProblem:
+    """One nodal (cell-velocity) projection problem: cell-centred rho, S and
+    velocity components uc, vc, wc, all (nz, ny, nx); beta0 at the layer
+    centres (nz,).  phi lives on the nodes."""
+    n: tuple
+    dx: float
+    periodic: tuple
+    rho: np.ndarray
+    beta0_cc: np.ndarray
+    S: np.ndarray
+    uc: np.ndarray
+    vc: np.ndarray
+    wc: np.ndarray
+    rtol: float = 1e-10
+    max_cycles: int = 100
+    pre_sweeps: int = 2
+    post_sweeps: int = 2
+    seed: int = 0
+    H: float = 0.3
+
+    def copy(self) -> "NodalProblem":
+        out = dataclasses.replace(self)
+        for name in ("rho", "beta0_cc", "S", "uc", "vc", "wc"):
+            setattr(out, name, getattr(self, name).copy())
+        return out
+
+
+def make_nodal_problem(n, *, H=0.3, rho_noise=0.01, S_amp=0.1, seed=0, dx=None, periodic=(True, True, False),
+                       rtol=1e-10, max_cycles=100, vel_scale=1.0) -> NodalProblem:
+    """Draw one seeded nodal-projection problem: beta0 = exp(-z/H) at the
+    layer centres, rho = beta0 (1 + rho_noise N(0,1)), S = S_amp N(0,1) with
+    its beta0-weighted mean removed, uc, vc, wc ~ vel_scale N(0,1).  Draw
+    order: rho noise, S noise, uc, vc, wc."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    nx, ny, nz = (int(a) for a in n)
+    if dx is None:
+        dx = 1.0 / nx
+    periodic = tuple(bool(p) for p in periodic)
+    rng = np.random.default_rng(seed)
+    b0c, _ = stratified_base_state(nz, dx, H)
+    rho = b0c[:, None, None] * (1.0 + rho_noise * rng.standard_normal((nz, ny, nx)))
+    S = S_amp * rng.standard_normal((nz, ny, nx))
+    wts = np.broadcast_to(b0c[:, None, None], S.shape)
+    S -= float(np.sum(wts * S) / np.sum(wts))
+    uc = vel_scale * rng.standard_normal((nz, ny, nx))
+    vc = vel_scale * rng.standard_normal((nz, ny, nx))
+    wc = vel_scale * rng.standard_normal((nz, ny, nx))
+    return NodalProblem(n=(nx, ny, nz), dx=float(dx), periodic=periodic, rho=rho, beta0_cc=b0c,
+                        S=np.ascontiguousarray(S), uc=uc, vc=vc, wc=wc, rtol=rtol, max_cycles=max_cycles,
+                        seed=seed, H=H)
 
 
 # Named workloads (unit box, periodic in x and y, solid walls in z).
