@@ -225,6 +225,56 @@ int mac_project_radial(mg_handle h, const double* rho, int32_t nr, double dr, co
 int mg_map_radial(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t nr, double dr,
                   const double* beta0_r, const double centre[3], double* beta0_out, void* stream);
 
+/* ---- nodal (cell-velocity) projection ----------------------------------- */
+
+/* The other projection of the paper's second-order projection method (Sec. 3):
+ * the cell-centred velocities are projected onto the same constraint
+ * div(beta0 U) = beta0 S (Sec. 2), with the potential phi on the nodes (cell
+ * corners).  Trilinear elements with the cell coefficient sigma = beta0/rho;
+ * divided by the node volume h^3:
+ *   (L phi)_n = 1/(12 h^2) sum_{cells c at n} sigma_c (sum of phi over the 4
+ *               corners of c across a face or the body diagonal from n
+ *               - 4 phi_n)
+ *   f_n = 1/(4h) sum_c beta0_c (+-u_c +- v_c +- w_c) - 1/8 sum_c beta0_c S_c
+ *   (+ for a cell on the high side of the node in that direction),
+ * L phi = f solved by multigrid (Gauss-Seidel over the 8 node parity classes
+ * in the order (I mod 2) + 2 (J mod 2) + 4 (K mod 2), full-weighting
+ * restriction, trilinear prolongation, coarse sigma the mean of the 8 fine
+ * cells, exact coarsest solve on at most 512 nodes), then U_c -= (G phi)_c /
+ * rho_c with G the cell's mean gradient of phi.  The projection is
+ * approximate: L is not D sigma G, so the corrected velocity meets the
+ * constraint to truncation error.  Boundaries: periodic (node n is node 0) or
+ * solid wall (natural: wall nodes are unknowns); FP64.
+ * Layout: rho, S, uc, vc, wc (nz, ny, nx) cells; beta0_cc (nz); phi nodes
+ * (Nz, Ny, Nx) with N = n (periodic) or n + 1 (walls), C order.  Device
+ * pointers, caller-owned. */
+typedef struct nodal_hierarchy* nodal_handle;
+
+/* Levels for params (0: not solvable: bc other than periodic/wall, or the
+ * coarsest level would exceed 512 nodes). */
+int32_t nodal_num_levels_for(const mg_params* p);
+/* Allocate a nodal hierarchy (p->precision must be MG_FP64). */
+int nodal_setup(const mg_params* p, nodal_handle* out);
+int nodal_destroy(nodal_handle h);
+/* The whole nodal projection: coefficients and right-hand side,
+ * compatibility check (|sum f| <= 1e-8 sum |f|) and mean removal, V-cycles to
+ * rtol, zero-mean phi (nullable output), correction of uc, vc, wc in place.
+ * Blocks until done; statuses as mac_project. */
+int nodal_project(nodal_handle h, const double* rho, const double* beta0_cc, const double* S, double* uc,
+                  double* vc, double* wc, double* phi, mg_stats* stats, void* stream);
+/* Coefficients only (for the single steps below). */
+int nodal_set_coefficients(nodal_handle h, const double* rho, const double* beta0_cc, void* stream);
+typedef enum { MG_NOD_PHI = 0, MG_NOD_F = 1, MG_NOD_SIGMA = 2 } mg_nodal_array;
+/* dims = {Nx, Ny, Nz, nx, ny, nz} of level l; *dx its spacing. */
+int nodal_level_info(nodal_handle h, int32_t level, int32_t dims[6], double* dx);
+/* Copy a level array (nodes: phi, f; cells: sigma) to or from a device
+ * buffer, stream-ordered. */
+int nodal_level_copy(nodal_handle h, int32_t level, int32_t array, void* buffer, int32_t to_hierarchy,
+                     void* stream);
+/* One step on level l: MG_STEP_SMOOTH (arg sweeps), MG_STEP_RESID_RESTRICT,
+ * MG_STEP_PROLONG, MG_STEP_COARSE (coarsest level).  Stream-ordered. */
+int nodal_level_step(nodal_handle h, int32_t level, int32_t step, int32_t arg, void* stream);
+
 /* ---- single steps of the cycle, for step-by-step verification ---------- */
 typedef enum {
     MG_STEP_SMOOTH = 0,          /* `arg` red-black GS sweeps on level l (phi_l, f_l) */

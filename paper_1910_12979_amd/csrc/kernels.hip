@@ -16,6 +16,7 @@
 
 #include <cmath>
 
+#include "dense.h"
 #include "devmath.h"
 #include "mg_internal.h"
 
@@ -427,34 +428,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_coarse_setup(int nx, int ny, 
         __syncthreads();
         for (int e = tid; e < n * n; e += nt) M[e] += shift;
     }
-    // In-place Gauss-Jordan inversion (M is SPD: no pivoting).  Thread tid
-    // owns column jj = tid % n of rows tid / n, tid / n + nt / n, ...; per
-    // pivot p: row p becomes row p / M_pp (with 1 / M_pp in column p), every
-    // other row i subtracts M_ip times the new row p (column p: -M_ip / M_pp).
-    const int jj = tid % n;
-    const int rstep = nt / n;
-    const int r0 = tid / n;
-    for (int p = 0; p < n; ++p) {
-        __syncthreads();                     // previous step complete
-        for (int e = tid; e < n; e += nt) {
-            fac[e] = M[e * n + p];
-            prow[e] = M[p * n + e];
-        }
-        __syncthreads();
-        const double inv = 1.0 / fac[p];
-        const double np = jj == p ? inv : prow[jj] * inv;     // new row p, column jj
-        if (r0 < rstep) {
-            for (int ii = r0; ii < n; ii += rstep) {
-                if (ii == p) {
-                    M[p * n + jj] = np;
-                } else {
-                    const double old = jj == p ? 0.0 : M[ii * n + jj];
-                    M[ii * n + jj] = old - fac[ii] * np;
-                }
-            }
-        }
-    }
-    __syncthreads();
+    gj_invert(M, n, fac, prow);
     if (kLds)
         for (int e = tid; e < n * n; e += nt) Mg[e] = Ms[e];
 }

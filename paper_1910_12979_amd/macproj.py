@@ -106,6 +106,15 @@ def lib():
         d3 = ctypes.POINTER(d)
         L.mac_project_radial.argtypes = [vp, vp, i32, d, vp, d3, vp, vp, vp, vp, vp, S, vp]
         L.mg_map_radial.argtypes = [i32, i32, i32, d, i32, d, vp, d3, vp, vp]
+        L.nodal_num_levels_for.argtypes = [P]
+        L.nodal_num_levels_for.restype = i32
+        L.nodal_setup.argtypes = [P, ctypes.POINTER(vp)]
+        L.nodal_destroy.argtypes = [vp]
+        L.nodal_project.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
+        L.nodal_set_coefficients.argtypes = [vp, vp, vp, vp]
+        L.nodal_level_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(d)]
+        L.nodal_level_copy.argtypes = [vp, i32, i32, vp, i32, vp]
+        L.nodal_level_step.argtypes = [vp, i32, i32, i32, vp]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -480,3 +489,80 @@ class Server:
 
 
 serve_create = Server
+
+
+# ---------------------------------------------------------------- nodal projection
+NODAL_ARRAY = {"phi": 0, "f": 1, "sigma": 2}
+
+
+def node_dims(n, periodic):
+    """Node counts (Nx, Ny, Nz): n in a periodic direction, n + 1 at walls."""
+    return tuple(int(n[d]) + (0 if periodic[d] else 1) for d in range(3))
+
+
+class NodalHierarchy:
+    """A nodal_setup handle (nodal projection of cell-centred velocities)."""
+
+    def __init__(self, params: Params):
+        self.params = params
+        self.n = tuple(params.n)
+        self.periodic = tuple(params.bc[d] == MG_BC_PERIODIC for d in range(3))
+        self._h = ctypes.c_void_p()
+        _check(lib().nodal_setup(ctypes.byref(params), ctypes.byref(self._h)))
+        self.nlevels = lib().nodal_num_levels_for(ctypes.byref(params))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().nodal_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def project(self, rho, beta0_cc, S, uc, vc, wc, phi=None, stream=None, allow=(MG_OK,)):
+        import torch
+        nx, ny, nz = self.n
+        cell = (nz, ny, nx)
+        f64 = torch.float64
+        st = Stats()
+        code = lib().nodal_project(self._h, _ptr(rho, f64, cell, "rho"), _ptr(beta0_cc, f64, (nz,), "beta0_cc"),
+                                   _ptr(S, f64, cell, "S"), _ptr(uc, f64, cell, "uc"), _ptr(vc, f64, cell, "vc"),
+                                   _ptr(wc, f64, cell, "wc"),
+                                   _ptr(phi, f64, node_dims(self.n, self.periodic)[::-1], "phi"),
+                                   ctypes.byref(st), _stream(stream))
+        _check(code, allow)
+        out = st.as_dict()
+        out["code"] = code
+        return out
+
+    def set_coefficients(self, rho, beta0_cc, stream=None):
+        import torch
+        nx, ny, nz = self.n
+        _check(lib().nodal_set_coefficients(self._h, _ptr(rho, torch.float64, (nz, ny, nx), "rho"),
+                                            _ptr(beta0_cc, torch.float64, (nz,), "beta0_cc"), _stream(stream)))
+
+    def level_info(self, level):
+        dims = (ctypes.c_int32 * 6)()
+        dx = ctypes.c_double()
+        _check(lib().nodal_level_info(self._h, level, dims, ctypes.byref(dx)))
+        return (dims[0], dims[1], dims[2]), (dims[3], dims[4], dims[5]), dx.value
+
+    def level_copy(self, level, array, tensor, to_hierarchy, stream=None):
+        _check(lib().nodal_level_copy(self._h, level, NODAL_ARRAY[array], _ptr(tensor, name=array),
+                                      1 if to_hierarchy else 0, _stream(stream)))
+
+    def level_step(self, level, step, arg=0, stream=None):
+        _check(lib().nodal_level_step(self._h, level, STEP[step], arg, _stream(stream)))
+
+
+def nodal_to_device(prob, device="cuda", phi=True):
+    """Device tensors of an inputs.NodalProblem."""
+    import torch
+    t = {name: torch.from_numpy(np.ascontiguousarray(getattr(prob, name))).to(device)
+         for name in ("rho", "beta0_cc", "S", "uc", "vc", "wc")}
+    Nx, Ny, Nz = node_dims(prob.n, prob.periodic)
+    t["phi"] = torch.zeros((Nz, Ny, Nx), dtype=torch.float64, device=device) if phi else None
+    return SimpleNamespace(**t)

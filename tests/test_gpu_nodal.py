@@ -1,0 +1,153 @@
+"""GPU parity of the nodal (cell-velocity) projection against the FP64 CPU
+oracle: phi within 1e-9 (relative L2, zero mean) of the oracle's exact
+discrete solution with the GPU residual <= rtol, the correction exact
+(<= 1e-12) given the GPU's phi, U within max(1e-9, 3 x the oracle's own
+algorithm-mode deviation) of the exact projection, single steps <= 1e-13.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1910_12979_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def run_gpu(mp, prob, rtol=None, allow=(0,)):
+    params = mp.make_params(prob.n, prob.dx, prob.periodic, rtol=prob.rtol if rtol is None else rtol)
+    H = mp.NodalHierarchy(params)
+    d = mp.nodal_to_device(prob)
+    st = H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi, allow=allow)
+    torch.cuda.synchronize()
+    out = {"phi": d.phi.cpu().numpy(), "u": d.uc.cpu().numpy(), "v": d.vc.cpu().numpy(), "w": d.wc.cpu().numpy()}
+    H.close()
+    return st, out
+
+
+def check(prob, st, out):
+    ref = O.nodal_project(prob, mode="definition")
+    alg = O.nodal_project(prob)
+    assert ref["status"] == 0 and alg["status"] == 0
+    assert st["status_name"] == "OK", st
+    assert st["rel_resid"] <= prob.rtol
+    assert abs(out["phi"].mean()) <= 1e-12 * np.max(np.abs(out["phi"]))
+    e_alg_phi = rel(alg["phi"], ref["phi"])
+    assert rel(out["phi"], ref["phi"]) <= max(1e-9, 3 * e_alg_phi)
+    u_c = O.nodal_correct(prob.n, prob.periodic, prob.dx, prob.rho, out["phi"], prob.uc, prob.vc, prob.wc)
+    for name, exact in zip(("u", "v", "w"), u_c):
+        assert rel(out[name], exact) <= 1e-12, name
+        e_alg = rel(alg[name], ref[name])
+        assert rel(out[name], ref[name]) <= max(1e-9, 3 * e_alg), name
+    sig = O.nodal_sigma(prob.rho, prob.beta0_cc)
+    f = O.nodal_rhs(prob.n, prob.periodic, prob.dx, prob.beta0_cc, prob.uc, prob.vc, prob.wc, prob.S)
+    f -= f.mean()
+    r = f - O.nodal_apply(prob.n, prob.periodic, prob.dx, sig, out["phi"])
+    assert np.linalg.norm(r) <= 1.05 * prob.rtol * np.linalg.norm(f)
+    return ref, alg
+
+
+@pytest.mark.parametrize("n,per,seed", [
+    ((16, 16, 16), (True, True, False), 1),
+    ((24, 16, 32), (False, False, False), 2),
+    ((32, 32, 32), (True, False, True), 3),
+    ((64, 64, 64), (True, True, False), 4),
+    ((6, 10, 14), (True, True, False), 5),        # two levels
+    ((4, 4, 4), (False, False, False), 6),        # direct solve only (125 nodes)
+])
+def test_nodal_projection_matches_oracle(mp, n, per, seed):
+    prob = I.make_nodal_problem(n, H=0.2, rho_noise=0.05, seed=seed, periodic=per)
+    st, out = run_gpu(mp, prob)
+    ref, alg = check(prob, st, out)
+    assert abs(st["cycles"] - alg["cycles"]) <= 1
+    if st["cycles"] == alg["cycles"]:
+        assert rel(out["phi"], alg["phi"]) <= 1e-11
+
+
+def test_nodal_errors(mp):
+    p = I.make_nodal_problem(16, seed=9)
+    q = p.copy(); q.S = q.S + 0.3
+    st, _ = run_gpu(mp, q, allow=(-3,))
+    assert st["status_name"] == "INCOMPATIBLE_RHS"
+    q = p.copy(); q.rho[1, 1, 1] = -1.0
+    st, _ = run_gpu(mp, q, allow=(-1,))
+    assert st["status_name"] == "INVALID_ARG"
+    q = p.copy(); q.uc[0, 0, 0] = np.nan
+    st, _ = run_gpu(mp, q, allow=(-5,))
+    assert st["status_name"] == "NONFINITE"
+    with pytest.raises(mp.MGError):
+        mp.NodalHierarchy(mp.make_params((16, 16, 16), 1 / 16, outflow=(False,) * 5 + (True,)))
+
+
+def _get(H, l, name):
+    (Nx, Ny, Nz), (nx, ny, nz), _ = H.level_info(l)
+    shape = (nz, ny, nx) if name == "sigma" else (Nz, Ny, Nx)
+    t = torch.empty(shape, dtype=torch.float64, device="cuda")
+    H.level_copy(l, name, t, to_hierarchy=False)
+    return t.cpu().numpy()
+
+
+def _put(H, l, name, a):
+    H.level_copy(l, name, torch.from_numpy(np.ascontiguousarray(a)).cuda(), to_hierarchy=True)
+
+
+@pytest.mark.parametrize("n,per", [((32, 16, 24), (True, True, False)), ((16, 24, 16), (False, False, False)),
+                                   ((16, 16, 32), (True, False, True))])
+def test_nodal_steps_match_oracle(mp, n, per):
+    prob = I.make_nodal_problem(n, H=0.2, rho_noise=0.1, seed=12, periodic=per)
+    H = mp.NodalHierarchy(mp.make_params(n, prob.dx, per))
+    d = mp.nodal_to_device(prob)
+    H.set_coefficients(d.rho, d.beta0_cc)
+    sig = O.nodal_sigma(prob.rho, prob.beta0_cc)
+    OH = O.NodalHierarchy(n, per, prob.dx, sig)
+    assert H.nlevels == OH.nlevels
+    for l in range(H.nlevels):
+        assert rel(_get(H, l, "sigma"), OH.get(l, "sigma")) <= 1e-15
+    rng = np.random.default_rng(3)
+    for l in (0, 1):
+        (Nx, Ny, Nz), _, _ = H.level_info(l)
+        phi_l = rng.standard_normal((Nz, Ny, Nx))
+        f_l = rng.standard_normal((Nz, Ny, Nx))
+        _put(H, l, "phi", phi_l); _put(H, l, "f", f_l)
+        OH.set(l, "phi", phi_l); OH.set(l, "f", f_l)
+        H.level_step(l, "smooth", 2)
+        OH.smooth(l, 2)
+        assert rel(_get(H, l, "phi"), OH.get(l, "phi")) <= 1e-13, l
+        H.level_step(l, "resid_restrict")
+        OH.resid_restrict(l)
+        assert rel(_get(H, l + 1, "f"), OH.get(l + 1, "f")) <= 1e-13, l
+        assert np.all(_get(H, l + 1, "phi") == 0.0)
+        e = rng.standard_normal(OH.get(l + 1, "phi").shape)
+        _put(H, l + 1, "phi", e); OH.set(l + 1, "phi", e)
+        H.level_step(l, "prolong")
+        OH.prolong(l)
+        assert rel(_get(H, l, "phi"), OH.get(l, "phi")) <= 1e-14, l
+    Lc = H.nlevels - 1
+    (Nx, Ny, Nz), _, _ = H.level_info(Lc)
+    fc = rng.standard_normal((Nz, Ny, Nx))
+    fc -= fc.mean()
+    _put(H, Lc, "f", fc); OH.set(Lc, "f", fc)
+    H.level_step(Lc, "coarse")
+    OH.coarse()
+    assert rel(_get(H, Lc, "phi"), OH.get(Lc, "phi")) <= 1e-12
+    H.close()
+
+
+def test_nodal_128_full_residual(mp):
+    """A 128^3 steep box: the GPU result satisfies the discrete nodal system to
+    rtol, evaluated by the oracle's operator in FP64."""
+    prob = I.make_nodal_problem(128, H=0.1, rho_noise=0.01, seed=20)
+    st, out = run_gpu(mp, prob)
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10
+    sig = O.nodal_sigma(prob.rho, prob.beta0_cc)
+    f = O.nodal_rhs(prob.n, prob.periodic, prob.dx, prob.beta0_cc, prob.uc, prob.vc, prob.wc, prob.S)
+    f -= f.mean()
+    r = f - O.nodal_apply(prob.n, prob.periodic, prob.dx, sig, out["phi"])
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(f)
+    u_c = O.nodal_correct(prob.n, prob.periodic, prob.dx, prob.rho, out["phi"], prob.uc, prob.vc, prob.wc)
+    for name, exact in zip(("u", "v", "w"), u_c):
+        assert rel(out[name], exact) <= 1e-12, name
