@@ -414,6 +414,44 @@ def star_leg(args, torch, macproj, inputs, dev):
     return out
 
 
+def nodal_leg(args, torch, macproj, inputs, dev):
+    """The nodal (cell-velocity) projection of the same box size: phi on the
+    nodes, cell-centred velocities, FP64."""
+    prob = inputs.make_nodal_problem(args.n, H=0.1, rho_noise=0.01, seed=7)
+    d = macproj.nodal_to_device(prob, dev)
+    u0, v0, w0 = d.uc.clone(), d.vc.clone(), d.wc.clone()
+    H = macproj.NodalHierarchy(macproj.make_params(prob.n, prob.dx, prob.periodic))
+    log(f"nodal projection: {args.nodal_steps} steps")
+
+    def step():
+        d.uc.copy_(u0); d.vc.copy_(v0); d.wc.copy_(w0)
+        return H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.nodal_steps):
+        st = step()
+    torch.cuda.synchronize()
+    tn = time.perf_counter() - t0
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+    # one Gauss-Seidel sweep of the finest level (8 parity-class launches)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    H.level_step(0, "smooth", 1)
+    e0.record()
+    H.level_step(0, "smooth", args.kernel_reps)
+    e1.record()
+    torch.cuda.synchronize()
+    sweep_ms = e0.elapsed_time(e1) / args.kernel_reps
+    H.close()
+    nodes = (args.n ** 2) * (args.n + 1)
+    return {"value": args.nodal_steps / tn, "unit": "solves/s", "ms_per_step": tn * 1e3 / args.nodal_steps,
+            "cycles": st["cycles"], "rel_resid": st["rel_resid"],
+            "fine_sweep_ms": sweep_ms,
+            "fine_sweep_GBs_at_24B_per_node": 24.0 * nodes / (sweep_ms * 1e-3) / 1e9,
+            "workload": f"{args.n}^3 cells ({nodes} nodes), beta0 = exp(-z/0.1), periodic x,y, walls z, rtol 1e-10"}
+
+
 def cpu_leg(args, prob):
     log("CPU oracle baseline")
     from oracle import oracle as orc
@@ -445,6 +483,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=150)
     ap.add_argument("--full-steps", type=int, default=5, help="0 skips the p0/Gamma1 base-state leg")
     ap.add_argument("--star-steps", type=int, default=5, help="0 skips the radial-base-state outflow leg")
+    ap.add_argument("--nodal-steps", type=int, default=3, help="0 skips the nodal-projection leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -480,6 +519,7 @@ def main():
     serve = serve_leg(args, torch, macproj, inputs, dev) if args.serve_rates else None
     full = full_leg(args, torch, macproj, inputs, dev) if args.full_steps > 0 else None
     star = star_leg(args, torch, macproj, inputs, dev) if args.star_steps > 0 else None
+    nodal = nodal_leg(args, torch, macproj, inputs, dev) if args.nodal_steps > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_leg(args, prob)
 
     model_bytes = n ** 3 * (156.0 + cycles * 326.0)
@@ -507,6 +547,7 @@ def main():
         "serve": serve,
         "full_rhs": full,
         "star_outflow": star,
+        "nodal": nodal,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

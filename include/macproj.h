@@ -237,8 +237,8 @@ int mg_map_radial(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t nr, dou
  *               - 4 phi_n)
  *   f_n = 1/(4h) sum_c beta0_c (+-u_c +- v_c +- w_c) - 1/8 sum_c beta0_c S_c
  *   (+ for a cell on the high side of the node in that direction),
- * L phi = f solved by multigrid (Gauss-Seidel over the 8 node parity classes
- * in the order (I mod 2) + 2 (J mod 2) + 4 (K mod 2), full-weighting
+ * L phi = f solved by multigrid (four-colour Gauss-Seidel, colour (J mod 2)
+ * + 2 (K mod 2) in the order 0..3, full-weighting
  * restriction, trilinear prolongation, coarse sigma the mean of the 8 fine
  * cells, exact coarsest solve on at most 512 nodes), then U_c -= (G phi)_c /
  * rho_c with G the cell's mean gradient of phi.  The projection is
@@ -264,6 +264,10 @@ int nodal_project(nodal_handle h, const double* rho, const double* beta0_cc, con
                   double* vc, double* wc, double* phi, mg_stats* stats, void* stream);
 /* Coefficients only (for the single steps below). */
 int nodal_set_coefficients(nodal_handle h, const double* rho, const double* beta0_cc, void* stream);
+/* enable = 1 (the default): the V-cycle and the residual norm after it run as
+ * one captured hipGraph replayed every cycle (all buffers are fixed);
+ * results are identical either way. */
+int nodal_set_graphs(nodal_handle h, int32_t enable);
 typedef enum { MG_NOD_PHI = 0, MG_NOD_F = 1, MG_NOD_SIGMA = 2 } mg_nodal_array;
 /* dims = {Nx, Ny, Nz, nx, ny, nz} of level l; *dx its spacing. */
 int nodal_level_info(nodal_handle h, int32_t level, int32_t dims[6], double* dx);

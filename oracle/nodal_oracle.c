@@ -33,10 +33,13 @@
  *   L differs from D sigma G (the projection is approximate, the velocity it
  *   returns satisfies the constraint to truncation error, not to round-off).
  *
- * Multigrid (V-cycle): colour-by-parity Gauss-Seidel on the 8 node classes
- *   (I mod 2, J mod 2, K mod 2), in the order c = (I mod 2) + 2 (J mod 2) +
- *   4 (K mod 2) = 0..7 (two nodes of one class never share a cell, so each
- *   class is a Jacobi step of a true Gauss-Seidel sweep); residual
+ * Multigrid (V-cycle): four-colour Gauss-Seidel, colour c = (J mod 2) +
+ *   2 (K mod 2) visited in the order 0, 1, 2, 3.  Two nodes are coupled only
+ *   when they differ by one in at least two coordinates (the edge weight is
+ *   zero), so at least one of J, K differs by one and the colours differ (for
+ *   even node counts also across a periodic wrap): each colour is a Jacobi
+ *   step of a true Gauss-Seidel sweep, and every x-row has one colour;
+ *   residual
  *   restricted by full weighting f_C = 1/8 sum_d prod_i (1 - |d_i|/2)
  *   r_{2C+d} (d in {-1,0,1}^3, existing fine nodes only), coarse phi = 0;
  *   trilinear prolongation; coarse sigma = mean of the 8 fine cells, spacing
@@ -146,16 +149,16 @@ static double apply_node(const nlev* L, const double* phi, int I, int J, int K) 
     return s / (12.0 * L->h * L->h);
 }
 
-/* One Gauss-Seidel sweep: the 8 parity classes in order. */
+/* One Gauss-Seidel sweep: the 4 colours (J mod 2) + 2 (K mod 2) in order. */
 static void gs_level(const nlev* L, double* phi, const double* f, int nsweeps) {
     const int Nn[3] = {L->Nx, L->Ny, L->Nz}, nc[3] = {L->nx, L->ny, L->nz};
     const double h2 = L->h * L->h;
     for (int sw = 0; sw < nsweeps; ++sw)
-        for (int col = 0; col < 8; ++col)
+        for (int col = 0; col < 4; ++col)
             for (int K = 0; K < L->Nz; ++K)
                 for (int J = 0; J < L->Ny; ++J)
                     for (int I = 0; I < L->Nx; ++I) {
-                        if ((I & 1) + 2 * (J & 1) + 4 * (K & 1) != col) continue;
+                        if ((J & 1) + 2 * (K & 1) != col) continue;
                         const int X[3] = {I, J, K};
                         double num = 0.0, den = 0.0;
                         for (int sz = 0; sz < 2; ++sz)

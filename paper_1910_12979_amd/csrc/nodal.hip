@@ -14,9 +14,10 @@
 // wall is a natural boundary (its nodes are unknowns, only existing cells
 // contribute); in a periodic direction node n is node 0.
 //
-// Multigrid: Gauss-Seidel over the 8 node parity classes in the order
-// (I mod 2) + 2 (J mod 2) + 4 (K mod 2) = 0..7 (one launch per class: two
-// nodes of a class never share a cell); residual, full-weighting
+// Multigrid: four-colour Gauss-Seidel, colour (J mod 2) + 2 (K mod 2) in the
+// order 0..3 (one launch per colour: coupled nodes differ by one in at least
+// two coordinates, so in J or K, and their colours differ; each x-row has one
+// colour, so a launch reads and writes whole rows); residual, full-weighting
 // restriction 1/8 sum_d prod(1 - |d_i|/2) r_{2C+d}; trilinear prolongation;
 // coarse sigma the mean of the 8 fine cells; exact coarsest solve (at most
 // 512 nodes) by the dense inverse of -A + c 1 1^T.  Every per-node
@@ -73,39 +74,69 @@ __device__ inline size_t cidx3(const NodLevel& L, int i, int j, int k) {
     return ((size_t)k * L.ny + j) * L.nx + i;
 }
 
-// num = sum_c sigma_c sum_{4 far corners} phi, den = 4 sum_c sigma_c, in the
-// oracle's order (cells sz, sy, sx; corners mz, my, mx).
-__device__ inline void nod_stencil(const NodLevel& L, const double* __restrict__ phi, int I, int J, int K,
-                                   double& num, double& den) {
-    const int X[3] = {I, J, K};
-    const int Nn[3] = {L.Nx, L.Ny, L.Nz}, nc[3] = {L.nx, L.ny, L.nz}, per[3] = {L.px, L.py, L.pz};
+// Neighbour and cell indices of node coordinate X along one direction:
+// nodes X-1 / X+1 (m[0], m[1]) and the cells on its low / high side (c[0],
+// c[1], e[s] = whether that cell exists).
+struct NodAxis {
+    int m[2], c[2];
+    bool e[2];
+};
+
+__device__ inline NodAxis nod_axis(int X, int N, int n, int per) {
+    NodAxis a;
+    if (per) {
+        a.m[0] = X > 0 ? X - 1 : N - 1;
+        a.m[1] = X + 1 < N ? X + 1 : 0;
+        a.c[0] = X > 0 ? X - 1 : n - 1;
+        a.c[1] = X;
+        a.e[0] = a.e[1] = true;
+    } else {
+        a.m[0] = X - 1;
+        a.m[1] = X + 1;
+        a.c[0] = X - 1;
+        a.c[1] = X;
+        a.e[0] = X >= 1;
+        a.e[1] = X < n;
+    }
+    return a;
+}
+
+// num = sum_c sigma_c sum_{4 far corners} phi, den = 4 sum_c sigma_c over
+// the existing cells at node (I, J, K), in the oracle's order (cells sz, sy,
+// sx; far corners of the cell on side (sx, sy, sz): x+y, x+z, y+z, x+y+z
+// moved), with per-axis index tables.
+__device__ inline void nod_stencil_fast(const NodLevel& L, const double* __restrict__ phi, int I, int J, int K,
+                                        double& num, double& den) {
+    const NodAxis ax = nod_axis(I, L.Nx, L.nx, L.px);
+    const NodAxis ay = nod_axis(J, L.Ny, L.ny, L.py);
+    const NodAxis az = nod_axis(K, L.Nz, L.nz, L.pz);
+    const long long Nx = L.Nx, NxNy = (long long)L.Nx * L.Ny;
+    const long long nx = L.nx, nxny = (long long)L.nx * L.ny;
     num = 0.0;
     den = 0.0;
-    for (int sz = 0; sz < 2; ++sz)
-        for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz) {
+        if (!az.e[sz]) continue;
+        const long long zc = az.c[sz] * nxny, zo = az.m[sz] * NxNy, z0 = K * NxNy;
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            if (!ay.e[sy]) continue;
+            const long long yc = ay.c[sy] * nx, yo = ay.m[sy] * Nx, y0 = J * Nx;
+#pragma unroll
             for (int sx = 0; sx < 2; ++sx) {
-                const int S[3] = {sx, sy, sz};
-                int c[3];
-                bool ok = true;
-                for (int d = 0; d < 3; ++d) {
-                    c[d] = nod_cell(X[d], S[d], nc[d], per[d]);
-                    if (c[d] < 0) ok = false;
-                }
-                if (!ok) continue;
-                const double sig = L.sig[cidx3(L, c[0], c[1], c[2])];
+                if (!ax.e[sx]) continue;
+                const double sig = L.sig[zc + yc + ax.c[sx]];
+                const long long xo = ax.m[sx];
                 double acc = 0.0;
-                for (int mz = 0; mz < 2; ++mz)
-                    for (int my = 0; my < 2; ++my)
-                        for (int mx = 0; mx < 2; ++mx) {
-                            if (mx + my + mz < 2) continue;
-                            const int M[3] = {mx, my, mz};
-                            int m[3];
-                            for (int d = 0; d < 3; ++d) m[d] = nod_node(X[d], M[d] ? (S[d] ? 1 : -1) : 0, Nn[d], per[d]);
-                            acc += phi[nidx(L, m[0], m[1], m[2])];
-                        }
+                acc += phi[z0 + yo + xo];
+                acc += phi[zo + y0 + xo];
+                acc += phi[zo + yo + I];
+                acc += phi[zo + yo + xo];
                 num += sig * acc;
                 den += 4.0 * sig;
             }
+        }
+    }
 }
 
 __device__ inline void block_row(double v0, double v1, double v2, double v3, double* out) {
@@ -192,15 +223,15 @@ __global__ __launch_bounds__(kNodBlock) void k_nod_rhs(NodLevel L, const double*
     block_row(sf, saf, 0.0, 0.0, partials + (size_t)blockIdx.x * kReduceWidth);
 }
 
-// One parity class of the Gauss-Seidel sweep; thread (ti, tj, tk) owns node
-// (2 ti + (col & 1), 2 tj + ((col >> 1) & 1), 2 tk + (col >> 2)).
+// One colour of the Gauss-Seidel sweep; thread (I, tj, tk) owns node
+// (I, 2 tj + (col & 1), 2 tk + (col >> 1)).
 __global__ void k_nod_gs(NodLevel L, int col) {
-    const int I = 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x) + (col & 1);
-    const int J = 2 * (int)(blockIdx.y * blockDim.y + threadIdx.y) + ((col >> 1) & 1);
-    const int K = 2 * (int)(blockIdx.z * blockDim.z + threadIdx.z) + (col >> 2);
+    const int I = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int J = 2 * (int)(blockIdx.y * blockDim.y + threadIdx.y) + (col & 1);
+    const int K = 2 * (int)(blockIdx.z * blockDim.z + threadIdx.z) + (col >> 1);
     if (I >= L.Nx || J >= L.Ny || K >= L.Nz) return;
     double num, den;
-    nod_stencil(L, L.phi, I, J, K, num, den);
+    nod_stencil_fast(L, L.phi, I, J, K, num, den);
     const size_t n = nidx(L, I, J, K);
     L.phi[n] = (num - 12.0 * (L.h * L.h) * L.f[n]) / den;
 }
@@ -208,34 +239,35 @@ __global__ void k_nod_gs(NodLevel L, int col) {
 // (L phi)_n = 1/(12 h^2) sum_c sigma_c (far corners - 4 phi_n), per cell in
 // the oracle's order.
 __device__ inline double nod_apply(const NodLevel& L, const double* __restrict__ phi, int I, int J, int K) {
-    const int X[3] = {I, J, K};
-    const int Nn[3] = {L.Nx, L.Ny, L.Nz}, nc[3] = {L.nx, L.ny, L.nz}, per[3] = {L.px, L.py, L.pz};
-    const double pn = phi[nidx(L, I, J, K)];
+    const NodAxis ax = nod_axis(I, L.Nx, L.nx, L.px);
+    const NodAxis ay = nod_axis(J, L.Ny, L.ny, L.py);
+    const NodAxis az = nod_axis(K, L.Nz, L.nz, L.pz);
+    const long long Nx = L.Nx, NxNy = (long long)L.Nx * L.Ny;
+    const long long nx = L.nx, nxny = (long long)L.nx * L.ny;
+    const double pn = phi[K * NxNy + J * Nx + I];
     double s = 0.0;
-    for (int sz = 0; sz < 2; ++sz)
-        for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz) {
+        if (!az.e[sz]) continue;
+        const long long zc = az.c[sz] * nxny, zo = az.m[sz] * NxNy, z0 = K * NxNy;
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            if (!ay.e[sy]) continue;
+            const long long yc = ay.c[sy] * nx, yo = ay.m[sy] * Nx, y0 = J * Nx;
+#pragma unroll
             for (int sx = 0; sx < 2; ++sx) {
-                const int S[3] = {sx, sy, sz};
-                int c[3];
-                bool ok = true;
-                for (int d = 0; d < 3; ++d) {
-                    c[d] = nod_cell(X[d], S[d], nc[d], per[d]);
-                    if (c[d] < 0) ok = false;
-                }
-                if (!ok) continue;
-                const double sig = L.sig[cidx3(L, c[0], c[1], c[2])];
+                if (!ax.e[sx]) continue;
+                const double sig = L.sig[zc + yc + ax.c[sx]];
+                const long long xo = ax.m[sx];
                 double acc = 0.0;
-                for (int mz = 0; mz < 2; ++mz)
-                    for (int my = 0; my < 2; ++my)
-                        for (int mx = 0; mx < 2; ++mx) {
-                            if (mx + my + mz < 2) continue;
-                            const int M[3] = {mx, my, mz};
-                            int m[3];
-                            for (int d = 0; d < 3; ++d) m[d] = nod_node(X[d], M[d] ? (S[d] ? 1 : -1) : 0, Nn[d], per[d]);
-                            acc += phi[nidx(L, m[0], m[1], m[2])];
-                        }
+                acc += phi[z0 + yo + xo];
+                acc += phi[zo + y0 + xo];
+                acc += phi[zo + yo + I];
+                acc += phi[zo + yo + xo];
                 s += sig * (acc - 4.0 * pn);
             }
+        }
+    }
     return s / (12.0 * L.h * L.h);
 }
 
@@ -450,6 +482,15 @@ struct nodal_hierarchy {
     double* host = nullptr;
     bool coeffs_valid = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // One V-cycle plus the finest residual norm (copied to host) as a
+    // replayable hipGraph on the hierarchy's own stream; every buffer is
+    // fixed, so one capture serves every cycle of every solve with the same
+    // sweep counts.
+    bool graphs_on = true;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev = nullptr;
+    hipGraphExec_t cycle_exec = nullptr;
+    int cycle_pre = -1, cycle_post = -1;
 };
 
 namespace {
@@ -485,10 +526,10 @@ int nod_reduce(nodal_hierarchy* H, int nparts, int slot, hipStream_t st) {
 
 int nod_smooth(nodal_hierarchy* H, int l, int nsweeps, hipStream_t st) {
     const NodLevel& L = H->lev[l];
-    const dim3 block(32, 4, 2);
-    const dim3 grid = grid3((L.Nx + 1) / 2, (L.Ny + 1) / 2, (L.Nz + 1) / 2, block);
+    const dim3 block(64, 2, 2);
+    const dim3 grid = grid3(L.Nx, (L.Ny + 1) / 2, (L.Nz + 1) / 2, block);
     for (int s = 0; s < nsweeps; ++s)
-        for (int col = 0; col < 8; ++col) hipLaunchKernelGGL(k_nod_gs, grid, block, 0, st, L, col);
+        for (int col = 0; col < 4; ++col) hipLaunchKernelGGL(k_nod_gs, grid, block, 0, st, L, col);
     NHIP(hipGetLastError());
     return MG_OK;
 }
@@ -600,13 +641,58 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
     S_->hist_len = 1;
     if (fnorm > 0.0 && H->p.rtol < 1.0) {
         status = MG_ERR_NOT_CONVERGED;
-        while (cycles < H->p.max_cycles) {
-            rc = nod_vcycle(H, 0, st);
-            if (rc) return S_->status = rc;
-            hipLaunchKernelGGL(k_nod_resid, dim3(nb), dim3(kNodBlock), 0, st, L0, H->partials);
+        bool on_graph = false;
+        auto cycle = [&](hipStream_t s) -> int {
+            int r2 = nod_vcycle(H, 0, s);
+            if (r2) return r2;
+            hipLaunchKernelGGL(k_nod_resid, dim3(nb), dim3(kNodBlock), 0, s, L0, H->partials);
             NHIP(hipGetLastError());
-            rc = nod_reduce(H, nb, kSlotRes, st);
-            if (rc) return S_->status = rc;
+            NHIP(launch_reduce(H->partials, nb, H->scal + kSlotRes * kReduceWidth, s));
+            NHIP(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
+                                kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, s));
+            return MG_OK;
+        };
+        while (cycles < H->p.max_cycles) {
+            if (H->graphs_on) {
+                if (!H->gstream) {
+                    NHIP(hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking));
+                    NHIP(hipEventCreateWithFlags(&H->gev, hipEventDisableTiming));
+                }
+                if (!on_graph) {                    // after the caller's earlier work
+                    NHIP(hipEventRecord(H->gev, st));
+                    NHIP(hipStreamWaitEvent(H->gstream, H->gev, 0));
+                    on_graph = true;
+                }
+                if (!H->cycle_exec || H->cycle_pre != H->p.pre_sweeps || H->cycle_post != H->p.post_sweeps) {
+                    if (H->cycle_exec) {
+                        hipGraphExecDestroy(H->cycle_exec);
+                        H->cycle_exec = nullptr;
+                    }
+                    NHIP(hipStreamBeginCapture(H->gstream, hipStreamCaptureModeRelaxed));
+                    int r2 = cycle(H->gstream);
+                    hipGraph_t g = nullptr;
+                    hipError_t e = hipStreamEndCapture(H->gstream, &g);
+                    if (r2) {
+                        if (g) hipGraphDestroy(g);
+                        return S_->status = r2;
+                    }
+                    if (e != hipSuccess) return S_->status = hip_fail(e, "hipStreamEndCapture", __LINE__);
+                    e = hipGraphInstantiate(&H->cycle_exec, g, nullptr, nullptr, 0);
+                    hipGraphDestroy(g);
+                    if (e != hipSuccess) {
+                        H->cycle_exec = nullptr;
+                        return S_->status = hip_fail(e, "hipGraphInstantiate", __LINE__);
+                    }
+                    H->cycle_pre = H->p.pre_sweeps;
+                    H->cycle_post = H->p.post_sweeps;
+                }
+                NHIP(hipGraphLaunch(H->cycle_exec, H->gstream));
+                NHIP(hipStreamSynchronize(H->gstream));
+            } else {
+                rc = cycle(st);
+                if (rc) return S_->status = rc;
+                NHIP(hipStreamSynchronize(st));
+            }
             ++cycles;
             const double* r = H->host + kSlotRes * kReduceWidth;
             rel = std::sqrt(r[0]) / fnorm;
@@ -624,6 +710,10 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
                 break;
             }
         }
+    }
+    if (H->gstream) {                       // the caller's stream continues after the graph work
+        NHIP(hipEventRecord(H->gev, H->gstream));
+        NHIP(hipStreamWaitEvent(st, H->gev, 0));
     }
     S_->cycles = cycles;
     S_->rel_resid = rel;
@@ -740,6 +830,9 @@ int nodal_setup(const mg_params* p, nodal_handle* out) {
 
 int nodal_destroy(nodal_handle h) {
     if (!h) return MG_OK;
+    if (h->cycle_exec) hipGraphExecDestroy(h->cycle_exec);
+    if (h->gstream) hipStreamDestroy(h->gstream);
+    if (h->gev) hipEventDestroy(h->gev);
     if (h->ws) hipFree(h->ws);
     if (h->host) hipHostFree(h->host);
     hipEventDestroy(h->ev0);
@@ -769,6 +862,15 @@ int nodal_set_coefficients(nodal_handle h, const double* rho, const double* beta
         return MG_ERR_INVALID_ARG;
     }
     return nod_coefficients(h, rho, beta0_cc, nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int nodal_set_graphs(nodal_handle h, int32_t enable) {
+    if (!h) {
+        set_error("null handle");
+        return MG_ERR_INVALID_ARG;
+    }
+    h->graphs_on = enable != 0;
+    return MG_OK;
 }
 
 int nodal_level_info(nodal_handle h, int32_t level, int32_t dims[6], double* dx) {

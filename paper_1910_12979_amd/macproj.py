@@ -115,6 +115,7 @@ def lib():
         L.nodal_level_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(d)]
         L.nodal_level_copy.argtypes = [vp, i32, i32, vp, i32, vp]
         L.nodal_level_step.argtypes = [vp, i32, i32, i32, vp]
+        L.nodal_set_graphs.argtypes = [vp, i32]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -537,6 +538,9 @@ class NodalHierarchy:
         out = st.as_dict()
         out["code"] = code
         return out
+
+    def set_graphs(self, enable: bool):
+        _check(lib().nodal_set_graphs(self._h, 1 if enable else 0))
 
     def set_coefficients(self, rho, beta0_cc, stream=None):
         import torch

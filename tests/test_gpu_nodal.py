@@ -151,3 +151,29 @@ def test_nodal_128_full_residual(mp):
     u_c = O.nodal_correct(prob.n, prob.periodic, prob.dx, prob.rho, out["phi"], prob.uc, prob.vc, prob.wc)
     for name, exact in zip(("u", "v", "w"), u_c):
         assert rel(out[name], exact) <= 1e-12, name
+
+
+def test_nodal_graph_replays_equal_eager(mp):
+    """The captured V-cycle replayed over several solves gives the eager
+    launches' results bit for bit."""
+    prob = I.make_nodal_problem((32, 32, 48), H=0.15, rho_noise=0.05, seed=31)
+    params = mp.make_params(prob.n, prob.dx, prob.periodic)
+    outs = []
+    for graphs in (False, True):
+        H = mp.NodalHierarchy(params)
+        H.set_graphs(graphs)
+        res = []
+        for rep in range(3):
+            d = mp.nodal_to_device(prob)
+            st = H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi)
+            torch.cuda.synchronize()
+            res.append((st["cycles"], d.phi.cpu().numpy(), d.uc.cpu().numpy(), d.wc.cpu().numpy()))
+        H.close()
+        outs.append(res)
+    for (c0, *a0), (c1, *a1) in zip(outs[0], outs[1]):
+        assert c0 == c1
+        for x, y in zip(a0, a1):
+            assert np.array_equal(x, y)
+    for c, *a in outs[1][1:]:
+        for x, y in zip(a, outs[1][0][1:]):
+            assert np.array_equal(x, y)
