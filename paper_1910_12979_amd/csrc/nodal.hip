@@ -101,37 +101,63 @@ __device__ inline NodAxis nod_axis(int X, int N, int n, int per) {
     return a;
 }
 
+// The 20 neighbours of node (I, J, K) that the stencil couples (moved in at
+// least two directions), each loaded once: v[dz+1][dy+1][dx+1]; entries
+// whose node does not exist (beyond a wall) are never used and stay 0.
+struct NodNbr {
+    double v[3][3][3];
+};
+
+__device__ inline void nod_load_nbrs(const NodLevel& L, const double* __restrict__ phi, int I, const NodAxis& ax,
+                                     const NodAxis& ay, const NodAxis& az, int J, int K, NodNbr& N) {
+    const long long Nx = L.Nx, NxNy = (long long)L.Nx * L.Ny;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if ((dx != 0) + (dy != 0) + (dz != 0) < 2) continue;
+                const bool ok = (dx == 0 || ax.e[dx > 0]) && (dy == 0 || ay.e[dy > 0]) && (dz == 0 || az.e[dz > 0]);
+                const long long xi = dx == 0 ? I : ax.m[dx > 0];
+                const long long yi = dy == 0 ? J : ay.m[dy > 0];
+                const long long zi = dz == 0 ? K : az.m[dz > 0];
+                N.v[dz + 1][dy + 1][dx + 1] = ok ? phi[zi * NxNy + yi * Nx + xi] : 0.0;
+            }
+}
+
 // num = sum_c sigma_c sum_{4 far corners} phi, den = 4 sum_c sigma_c over
 // the existing cells at node (I, J, K), in the oracle's order (cells sz, sy,
 // sx; far corners of the cell on side (sx, sy, sz): x+y, x+z, y+z, x+y+z
-// moved), with per-axis index tables.
+// moved), with per-axis index tables and each neighbour loaded once.
 __device__ inline void nod_stencil_fast(const NodLevel& L, const double* __restrict__ phi, int I, int J, int K,
                                         double& num, double& den) {
     const NodAxis ax = nod_axis(I, L.Nx, L.nx, L.px);
     const NodAxis ay = nod_axis(J, L.Ny, L.ny, L.py);
     const NodAxis az = nod_axis(K, L.Nz, L.nz, L.pz);
-    const long long Nx = L.Nx, NxNy = (long long)L.Nx * L.Ny;
+    NodNbr N;
+    nod_load_nbrs(L, phi, I, ax, ay, az, J, K, N);
     const long long nx = L.nx, nxny = (long long)L.nx * L.ny;
     num = 0.0;
     den = 0.0;
 #pragma unroll
     for (int sz = 0; sz < 2; ++sz) {
         if (!az.e[sz]) continue;
-        const long long zc = az.c[sz] * nxny, zo = az.m[sz] * NxNy, z0 = K * NxNy;
+        const int oz = sz ? 2 : 0;
 #pragma unroll
         for (int sy = 0; sy < 2; ++sy) {
             if (!ay.e[sy]) continue;
-            const long long yc = ay.c[sy] * nx, yo = ay.m[sy] * Nx, y0 = J * Nx;
+            const int oy = sy ? 2 : 0;
 #pragma unroll
             for (int sx = 0; sx < 2; ++sx) {
                 if (!ax.e[sx]) continue;
-                const double sig = L.sig[zc + yc + ax.c[sx]];
-                const long long xo = ax.m[sx];
+                const int ox = sx ? 2 : 0;
+                const double sig = L.sig[az.c[sz] * nxny + ay.c[sy] * nx + ax.c[sx]];
                 double acc = 0.0;
-                acc += phi[z0 + yo + xo];
-                acc += phi[zo + y0 + xo];
-                acc += phi[zo + yo + I];
-                acc += phi[zo + yo + xo];
+                acc += N.v[1][oy][ox];
+                acc += N.v[oz][1][ox];
+                acc += N.v[oz][oy][1];
+                acc += N.v[oz][oy][ox];
                 num += sig * acc;
                 den += 4.0 * sig;
             }
@@ -242,28 +268,29 @@ __device__ inline double nod_apply(const NodLevel& L, const double* __restrict__
     const NodAxis ax = nod_axis(I, L.Nx, L.nx, L.px);
     const NodAxis ay = nod_axis(J, L.Ny, L.ny, L.py);
     const NodAxis az = nod_axis(K, L.Nz, L.nz, L.pz);
-    const long long Nx = L.Nx, NxNy = (long long)L.Nx * L.Ny;
+    NodNbr N;
+    nod_load_nbrs(L, phi, I, ax, ay, az, J, K, N);
     const long long nx = L.nx, nxny = (long long)L.nx * L.ny;
-    const double pn = phi[K * NxNy + J * Nx + I];
+    const double pn = phi[((long long)K * L.Ny + J) * L.Nx + I];
     double s = 0.0;
 #pragma unroll
     for (int sz = 0; sz < 2; ++sz) {
         if (!az.e[sz]) continue;
-        const long long zc = az.c[sz] * nxny, zo = az.m[sz] * NxNy, z0 = K * NxNy;
+        const int oz = sz ? 2 : 0;
 #pragma unroll
         for (int sy = 0; sy < 2; ++sy) {
             if (!ay.e[sy]) continue;
-            const long long yc = ay.c[sy] * nx, yo = ay.m[sy] * Nx, y0 = J * Nx;
+            const int oy = sy ? 2 : 0;
 #pragma unroll
             for (int sx = 0; sx < 2; ++sx) {
                 if (!ax.e[sx]) continue;
-                const double sig = L.sig[zc + yc + ax.c[sx]];
-                const long long xo = ax.m[sx];
+                const int ox = sx ? 2 : 0;
+                const double sig = L.sig[az.c[sz] * nxny + ay.c[sy] * nx + ax.c[sx]];
                 double acc = 0.0;
-                acc += phi[z0 + yo + xo];
-                acc += phi[zo + y0 + xo];
-                acc += phi[zo + yo + I];
-                acc += phi[zo + yo + xo];
+                acc += N.v[1][oy][ox];
+                acc += N.v[oz][1][ox];
+                acc += N.v[oz][oy][1];
+                acc += N.v[oz][oy][ox];
                 s += sig * (acc - 4.0 * pn);
             }
         }
