@@ -54,8 +54,8 @@ SWEEP_KERNEL_BYTES_PER_CELL = 32.0
 # for the sweep source it was taken on (SHA-1 of the files below) and tile.
 SWEEP_SOURCES = ("paper_1910_12979_amd/csrc/sweep.hip", "paper_1910_12979_amd/csrc/sweep.h",
                  "paper_1910_12979_amd/csrc/devmath.h")
-SWEEP_TRAFFIC = {"sha1": "2c04967fb76c7eda5ebcbfc51c7cddf2a901d39d", "tile": [64, 16, 64], "n": 256,
-                 "read": 436922244, "write": 134217728}
+SWEEP_TRAFFIC = {"sha1": "dc166c0c9e1f76ed27bbb1fa079ba6affa684e2a", "tile": [64, 16, 64], "n": 256,
+                 "read": 436944415, "write": 134217728}
 
 
 def percentile(xs, q):
@@ -173,7 +173,7 @@ def smoother_leg(args, torch, H, R):
     tx, ty, tz = tile[:3] if tile else (0, 0, 0)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": f"mg::k_sweep<double, {tx}, {ty}, true, 1, 0> (finest level, coefficients from rho, "
+            "kernel": f"mg::k_sweep<double, {tx}, {ty}, true, 1, 0, false> (finest level, coefficients from rho, "
                       f"one red+black sweep per launch, {tx}x{ty}-cell tiles, {tz}-plane z-chunks)",
             "launch_ms": launch_ms, "bytes_per_launch": launch_bytes,
             "bytes_per_cell": SWEEP_BYTES_PER_CELL,
