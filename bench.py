@@ -452,6 +452,35 @@ def nodal_leg(args, torch, macproj, inputs, dev):
             "workload": f"{args.n}^3 cells ({nodes} nodes), beta0 = exp(-z/0.1), periodic x,y, walls z, rtol 1e-10"}
 
 
+def boxes_leg(args, torch, macproj, R):
+    """The same 256^3 box with its finest level split into boxes (one ghost
+    layer each, a halo-exchange kernel after every colour), FP64."""
+    d = R.d
+    out = {"workload": f"{args.n}^3 steep-stratification box, finest level as boxes with halo exchange, FP64, "
+                       f"rtol 1e-10"}
+    for b in (args.n // 4, args.n // 2):
+        log(f"multi-box finest level, boxes of {b}^3: {args.boxes_steps} steps")
+        H = macproj.Hierarchy(macproj.params_of(R.prob))
+        H.set_boxes((b, b, b))
+
+        def step():
+            R.restore()
+            return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.boxes_steps):
+            st = step()
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+        H.close()
+        out[f"{b}^3 x {(args.n // b) ** 3}"] = {"value": args.boxes_steps / tb, "unit": "solves/s",
+                                               "ms_per_step": tb * 1e3 / args.boxes_steps, "cycles": st["cycles"]}
+    return out
+
+
 def cpu_leg(args, prob):
     log("CPU oracle baseline")
     from oracle import oracle as orc
@@ -484,6 +513,7 @@ def main():
     ap.add_argument("--full-steps", type=int, default=5, help="0 skips the p0/Gamma1 base-state leg")
     ap.add_argument("--star-steps", type=int, default=5, help="0 skips the radial-base-state outflow leg")
     ap.add_argument("--nodal-steps", type=int, default=3, help="0 skips the nodal-projection leg")
+    ap.add_argument("--boxes-steps", type=int, default=3, help="0 skips the multi-box finest-level leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -520,6 +550,7 @@ def main():
     full = full_leg(args, torch, macproj, inputs, dev) if args.full_steps > 0 else None
     star = star_leg(args, torch, macproj, inputs, dev) if args.star_steps > 0 else None
     nodal = nodal_leg(args, torch, macproj, inputs, dev) if args.nodal_steps > 0 else None
+    boxes = boxes_leg(args, torch, macproj, R) if args.boxes_steps > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_leg(args, prob)
 
     model_bytes = n ** 3 * (156.0 + cycles * 326.0)
@@ -548,6 +579,7 @@ def main():
         "full_rhs": full,
         "star_outflow": star,
         "nodal": nodal,
+        "multi_box": boxes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -363,6 +363,26 @@ int mg_set_graphs(mg_handle h, int32_t enable);
  * and level.  Results are identical either way. */
 int mg_set_bottom(mg_handle h, int32_t enable);
 
+/* Multi-box finest level: the block-structured box layout whose boxes the
+ * method distributes over MPI processes and tiles (Sec. 3), one
+ * process per GPU (Sec. 6), here with every box on one device and the
+ * inter-box halo exchange done by a kernel: box[0..2] = cells per box in
+ * x, y, z, each even, >= 2 and dividing the domain size; the domain is tiled
+ * by n/box boxes, each with its own phi (one ghost layer on its faces), f and
+ * face coefficients.  Every later mac_project on h smooths, restricts and
+ * prolongates the finest level box by box with a halo exchange (ghost faces
+ * from the neighbouring box, the periodic image, or 0 beyond a wall) after
+ * every colour and after each prolongation; levels 1 and coarser are the
+ * single-box levels.  The result agrees with the single-box solve to
+ * rounding (the same per-cell arithmetic; the residual norm and the
+ * restriction may be summed in another order).  box == NULL or {0, 0, 0} returns to a
+ * single box.  Needs FP64 precision, periodic or wall sides and two or more
+ * levels (MG_ERR_INVALID_ARG otherwise).  The boxes' arrays are allocated
+ * here (device memory, freed by mg_destroy or the next mg_set_boxes), about
+ * 5 x 8 bytes per cell plus the ghosts; MG_ERR_HIP if that fails.  Not used
+ * by the batch or serving front ends. */
+int mg_set_boxes(mg_handle h, const int32_t box[3]);
+
 /* Fused-sweep tile used on level l of h: tile[0..2] = cells per workgroup
  * tile in x, y and planes per z-chunk, tile[3] = configuration index (as for
  * mg_tune_sweep).  All four are -1 for a level the fused sweep does not cover

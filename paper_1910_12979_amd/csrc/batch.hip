@@ -579,6 +579,7 @@ int multi_refine(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
 bool batchable(const mg_hierarchy* H) {
     const Level& L0 = H->lev[0];
     if (H->outflow) return false;      // outflow sides: solved one by one (mac_project)
+    if (H->boxes_on) return false;     // multi-box finest level: solved one by one
     if (H->p.pre_sweeps < 1 || H->nlev < 2 || !sweep_fusable<double>(L0.nx, L0.ny, L0.nz)) return false;
     if (H->p.precision == MG_FP64) return true;
     // mixed precision: every FP32 level above the one-workgroup bottom is a

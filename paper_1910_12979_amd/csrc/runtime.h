@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "boxes.h"
 #include "mg_internal.h"
 
 // Slots (rows of 4 doubles) in the device scalar block of a hierarchy.
@@ -56,6 +57,10 @@ struct mg_hierarchy {
         std::vector<void*> post_phi, post_phi2;     // level phi buffers (FP64, then FP32) after it
     } graph[2];
     int graph_next = 0;                             // slot replaced by the next capture
+    // Finest level split into boxes with halo exchange (mg_set_boxes).
+    bool boxes_on = false;
+    mg::BoxSet box{};
+    void* box_mem = nullptr;
 };
 
 namespace mg {

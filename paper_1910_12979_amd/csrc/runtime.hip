@@ -271,6 +271,7 @@ int destroy(mg_hierarchy* H) {
         if (g.exec) hipGraphExecDestroy(g.exec);
     if (H->gstream) hipStreamDestroy(H->gstream);
     if (H->gev) hipEventDestroy(H->gev);
+    if (H->box_mem) hipFree(H->box_mem);
     delete H;
     return MG_OK;
 }
@@ -882,8 +883,61 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
     return status;
 }
 
+// Level-0 solve on the box-split finest level: f and the coefficients are
+// scattered into the boxes, each V-cycle smooths, restricts and prolongates
+// box by box with a halo exchange after every colour and after the
+// prolongation, levels 1 and coarser are the single-box ones, and phi is
+// gathered back into level 0 at the end.
+static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStream_t st) {
+    Level& L0 = H->lev[0];
+    Level& L1 = H->lev[1];
+    const BoxSet& B = H->box;
+    HIPCHK(launch_box_scatter(B, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, st));
+    int status = H->p.rtol >= 1.0 ? MG_OK : MG_ERR_NOT_CONVERGED;
+    int cycles = 0;
+    double rel = 1.0;
+    if (stats) {
+        stats->resid_hist[0] = 1.0;
+        stats->hist_len = 1;
+    }
+    while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
+        HIPCHK(launch_box_smooth(B, L0.h, H->p.pre_sweeps, st));
+        HIPCHK(launch_box_resid_restrict(B, L0.h, L1.d.f, L1.d.phi, st));
+        int rc = vcycle<double>(H, 1, st);
+        if (rc) return rc;
+        HIPCHK(launch_box_prolong(B, L1.d.phi, st));
+        HIPCHK(launch_box_smooth(B, L0.h, H->p.post_sweeps, st));
+        ++cycles;
+        int np = 0;
+        HIPCHK(launch_box_resid_norm(B, L0.h, H->partials, &np, st));
+        rc = reduce_to(H, np, kSlotRes, st);
+        if (rc) return rc;
+        rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
+        if (rc) return rc;
+        const double* r = H->host + kSlotRes * kReduceWidth;
+        rel = std::sqrt(r[0]) / fnorm;
+        if (stats && cycles < MG_HIST_MAX) {
+            stats->resid_hist[cycles] = rel;
+            stats->hist_len = cycles + 1;
+        }
+        if (r[3] > 0.0 || !std::isfinite(rel)) {
+            status = MG_ERR_NONFINITE;
+            set_error("non-finite residual during the solve");
+            break;
+        }
+        if (rel <= H->p.rtol) status = MG_OK;
+    }
+    HIPCHK(launch_box_gather(B, L0.d.phi, st));
+    if (stats) {
+        stats->cycles = cycles;
+        stats->rel_resid = rel;
+    }
+    return status;
+}
+
 // Solve on level 0 after f (mean-removed) and the coefficients are in place.
 static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStream_t st) {
+    if (H->boxes_on) return solve_level0_boxes(H, fnorm, stats, st);
     Level& L0 = H->lev[0];
     HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
     int status = MG_ERR_NOT_CONVERGED;
@@ -1496,6 +1550,70 @@ int mg_set_bottom(mg_handle h, int32_t enable) {
         return MG_ERR_INVALID_ARG;
     }
     h->bottom_on = enable != 0;
+    return MG_OK;
+}
+
+int mg_set_boxes(mg_handle h, const int32_t box[3]) {
+    if (!h) {
+        set_error("null handle");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (!box || (box[0] == 0 && box[1] == 0 && box[2] == 0)) {
+        if (h->box_mem) HIPCHK(hipFree(h->box_mem));
+        h->box_mem = nullptr;
+        h->box = BoxSet{};
+        h->boxes_on = false;
+        return MG_OK;
+    }
+    if (h->outflow || h->p.precision != MG_FP64 || h->nlev < 2) {
+        set_error("a multi-box finest level needs periodic or wall sides, FP64 precision and two or more levels");
+        return MG_ERR_INVALID_ARG;
+    }
+    BoxSet B{};
+    size_t ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int n = h->p.n[d];
+        if (box[d] < 2 || box[d] % 2 != 0 || n % box[d] != 0) {
+            set_error("box sizes must be even, at least 2, and divide the domain size in each direction");
+            return MG_ERR_INVALID_ARG;
+        }
+        B.n[d] = n;
+        B.B[d] = box[d];
+        B.nb[d] = n / box[d];
+        ncell *= (size_t)box[d];
+    }
+    B.per[0] = h->px;
+    B.per[1] = h->py;
+    B.per[2] = h->pz;
+    B.nbox = B.nb[0] * B.nb[1] * B.nb[2];
+    B.face_max = std::max(B.B[1] * B.B[2], std::max(B.B[0] * B.B[2], B.B[0] * B.B[1]));
+    B.phi_stride = (size_t)(B.B[0] + 2) * (B.B[1] + 2) * (B.B[2] + 2);
+    B.f_stride = ncell;
+    B.cx_stride = (size_t)(B.B[0] + 1) * B.B[1] * B.B[2];
+    B.cy_stride = (size_t)B.B[0] * (B.B[1] + 1) * B.B[2];
+    B.cz_stride = (size_t)B.B[0] * B.B[1] * (B.B[2] + 1);
+    if (B.phi_stride >= ((size_t)1 << 31)) {
+        set_error("box too large: (bx+2)(by+2)(bz+2) must stay below 2^31 cells");
+        return MG_ERR_INVALID_ARG;
+    }
+    auto up = [](size_t n) { return (n + 31) / 32 * 32; };     // 256-byte aligned sub-arrays
+    const size_t nb = (size_t)B.nbox;
+    const size_t e_phi = up(B.phi_stride * nb), e_f = up(B.f_stride * nb), e_cx = up(B.cx_stride * nb),
+                 e_cy = up(B.cy_stride * nb), e_cz = up(B.cz_stride * nb);
+    if (h->box_mem) HIPCHK(hipFree(h->box_mem));
+    h->box_mem = nullptr;
+    h->boxes_on = false;
+    void* mem = nullptr;
+    HIPCHK(hipMalloc(&mem, (e_phi + e_f + e_cx + e_cy + e_cz) * sizeof(double)));
+    double* p = static_cast<double*>(mem);
+    B.phi = p;
+    B.f = p + e_phi;
+    B.cx = B.f + e_f;
+    B.cy = B.cx + e_cx;
+    B.cz = B.cy + e_cy;
+    h->box_mem = mem;
+    h->box = B;
+    h->boxes_on = true;
     return MG_OK;
 }
 

@@ -101,6 +101,7 @@ def lib():
         L.mg_sweep_config.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.mg_set_graphs.argtypes = [vp, i32]
         L.mg_set_bottom.argtypes = [vp, i32]
+        L.mg_set_boxes.argtypes = [vp, ctypes.POINTER(i32)]
         L.mg_beta0_from_p0.argtypes = [i32, d, vp, vp, vp, vp, vp, vp]
         L.mac_project_full.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
         d3 = ctypes.POINTER(d)
@@ -313,6 +314,15 @@ class Hierarchy:
     def set_bottom(self, enable: bool):
         """Coarse levels in one workgroup launch (default on) or per-level launches."""
         _check(lib().mg_set_bottom(self._h, 1 if enable else 0))
+
+    def set_boxes(self, box):
+        """Split the finest level into boxes of box = (bx, by, bz) cells with a
+        halo exchange between them; None or (0, 0, 0) for a single box."""
+        if box is None:
+            _check(lib().mg_set_boxes(self._h, None))
+            return
+        t = (ctypes.c_int32 * 3)(*[int(b) for b in box])
+        _check(lib().mg_set_boxes(self._h, t))
 
     def sweep_config(self, level):
         """Fused-sweep tile (tx, ty, tz, index) of a level, or None if unfused."""

@@ -1,0 +1,184 @@
+"""GPU parity of the multi-box finest level (the domain tiled by boxes with a
+halo exchange between them) against the FP64 CPU oracle and against the
+single-box GPU solve.
+
+Bar: the same as the single-box parity tests (phi within 1e-9 of the oracle's
+exact discrete solution with the GPU residual <= rtol; the correction exact
+(<= 1e-12) given the GPU's phi; U within max(1e-9, 3 x the oracle's own
+algorithm-mode deviation)); against the single-box GPU solve: the same cycle
+count and phi, U within 1e-12 (the per-cell arithmetic is the same; only the
+summation order of the residual norm and of the finest-level restriction can
+differ, so the two iterates agree to rounding).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1910_12979_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_gpu(mp, prob, box=None, allow=(0,), H=None):
+    own = H is None
+    if own:
+        H = mp.Hierarchy(mp.params_of(prob))
+        if box is not None:
+            H.set_boxes(box)
+    d = mp.to_device(prob)
+    if prob.beta0_r is not None:
+        st = H.mac_project_radial(d.rho, d.beta0_r, prob.dr_base, prob.centre, d.S, d.u, d.v, d.w, d.phi,
+                                  allow=allow)
+    else:
+        st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi, allow=allow)
+    torch.cuda.synchronize()
+    out = {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+    if own:
+        H.close()
+    return st, out
+
+
+def check_oracle(prob, st, out):
+    ref = O.mac_project(prob, mode="definition")
+    alg = O.mac_project(prob)
+    assert ref["status"] == 0 and alg["status"] == 0
+    assert st["status_name"] == "OK", st
+    assert st["rel_resid"] <= prob.rtol
+    e_alg_phi = rel(alg["phi"], ref["phi"])
+    assert rel(out["phi"], ref["phi"]) <= max(1e-9, 3 * e_alg_phi)
+    sides = O.side_codes(prob.periodic, prob.outflow)
+    rad = O.prob_radial(prob)
+    coeffs = O.face_coeffs_gen(prob.n, sides, prob.dx, prob.rho, prob.beta0_cc, prob.beta0_edge, rad)
+    f = O.rhs_gen(prob.n, sides, prob.dx, prob.u, prob.v, prob.w, prob.S, prob.beta0_cc, prob.beta0_edge, rad)
+    f -= f.mean()
+    u_c = O.correct_gen(prob.n, sides, prob.dx, prob.rho, out["phi"], prob.u, prob.v, prob.w) \
+        if rad is not None else \
+        O.correct(prob.n, prob.periodic, prob.dx, prob.beta0_cc, prob.beta0_edge,
+                  O.face_coeffs(prob.n, prob.periodic, prob.rho, prob.beta0_cc, prob.beta0_edge),
+                  out["phi"], prob.u, prob.v, prob.w)
+    for name, exact in zip(("u", "v", "w"), u_c):
+        assert rel(out[name], exact) <= 1e-12, name
+        assert rel(out[name], ref[name]) <= max(1e-9, 3 * rel(alg[name], ref[name])), name
+    r = f - O.apply_gen(prob.n, sides, prob.dx, coeffs, out["phi"])
+    assert np.linalg.norm(r) <= 1.05 * prob.rtol * np.linalg.norm(f)
+    assert abs(st["cycles"] - alg["cycles"]) <= 1
+
+
+def check_single(mp, prob, st, out):
+    st1, out1 = run_gpu(mp, prob)
+    assert st1["status_name"] == "OK"
+    assert st["cycles"] == st1["cycles"]
+    assert abs(st["rel_resid"] - st1["rel_resid"]) <= 1e-6 * st1["rel_resid"]
+    for k in ("phi", "u", "v", "w"):
+        assert rel(out[k], out1[k]) <= 1e-12, k
+
+
+CASES = [
+    ((32, 32, 32), (True, True, False), (16, 16, 16), 1),     # 8 boxes, walls in z
+    ((40, 24, 56), (True, True, False), (20, 12, 28), 2),     # ragged boxes, 8 of them
+    ((32, 32, 32), (False, False, False), (8, 16, 32), 3),    # walls everywhere, boxes span z
+    ((32, 16, 32), (True, True, True), (16, 16, 16), 4),      # fully periodic, one box in y
+    ((32, 32, 32), (True, False, True), (32, 32, 32), 5),     # one box: it exchanges with itself
+    ((16, 16, 16), (True, True, False), (2, 4, 8), 6),        # 256 tiny boxes
+    ((6, 10, 14), (True, True, False), (2, 10, 14), 7),       # two levels, 105-cell coarsest
+    ((64, 64, 64), (False, True, False), (32, 16, 64), 8),
+]
+
+
+@pytest.mark.parametrize("n,per,box,seed", CASES)
+def test_boxes_match_oracle_and_single_box(mp, n, per, box, seed):
+    prob = I.make_problem(n, H=0.15, rho_noise=0.05, seed=seed, periodic=per, dx=1.0 / n[0])
+    st, out = run_gpu(mp, prob, box=box)
+    check_oracle(prob, st, out)
+    check_single(mp, prob, st, out)
+
+
+def _radial_walls(n, seed):
+    """A radial base state inside solid walls, S shifted so that the
+    right-hand side is compatible (sum of beta0 S over the cells = 0)."""
+    prob = I.make_star_problem(n, Hr=0.2, rho_noise=0.02, seed=seed, outflow=(False,) * 6)
+    b0 = O.map_radial(prob.n, prob.dx, prob.beta0_r, prob.dr_base, prob.centre)
+    prob.S = np.ascontiguousarray(prob.S - np.sum(b0 * prob.S) / np.sum(b0))
+    return prob
+
+
+def test_boxes_radial_base_state(mp):
+    prob = _radial_walls((32, 32, 48), 11)
+    st, out = run_gpu(mp, prob, box=(16, 16, 16))
+    check_oracle(prob, st, out)
+    check_single(mp, prob, st, out)
+
+
+def test_boxes_set_and_reset(mp):
+    """Switching boxes on, changing their size and switching them off on one
+    hierarchy: each solve equals a fresh hierarchy's."""
+    prob = I.make_problem((32, 32, 32), H=0.2, rho_noise=0.05, seed=21)
+    H = mp.Hierarchy(mp.params_of(prob))
+    try:
+        st0, out0 = run_gpu(mp, prob, H=H)
+        for box in ((16, 16, 16), (8, 32, 16)):
+            H.set_boxes(box)
+            st, out = run_gpu(mp, prob, H=H)
+            stf, outf = run_gpu(mp, prob, box=box)
+            assert st["cycles"] == stf["cycles"]
+            for k in out:
+                assert np.array_equal(out[k], outf[k]), k
+                assert rel(out[k], out0[k]) <= 1e-12, k
+        H.set_boxes(None)
+        st, out = run_gpu(mp, prob, H=H)
+        assert st["cycles"] == st0["cycles"]
+        for k in out:
+            assert np.array_equal(out[k], out0[k]), k
+    finally:
+        H.close()
+
+
+def test_boxes_errors(mp):
+    prob = I.make_problem((32, 32, 32), H=0.2, seed=22)
+    H = mp.Hierarchy(mp.params_of(prob))
+    try:
+        for bad in ((3, 16, 16), (12, 16, 16), (0, 16, 16), (64, 16, 16), (16, -2, 16)):
+            with pytest.raises(mp.MGError):
+                H.set_boxes(bad)
+    finally:
+        H.close()
+    H = mp.Hierarchy(mp.params_of(prob, precision="mixed"))
+    try:
+        with pytest.raises(mp.MGError):
+            H.set_boxes((16, 16, 16))
+    finally:
+        H.close()
+    out = I.make_problem((32, 32, 32), H=0.2, seed=22, outflow=(False,) * 5 + (True,))
+    H = mp.Hierarchy(mp.params_of(out))
+    try:
+        with pytest.raises(mp.MGError):
+            H.set_boxes((16, 16, 16))
+    finally:
+        H.close()
+    # an incompatible right-hand side is still caught before the box solve
+    q = prob.copy()
+    q.S = q.S + 0.5
+    st, _ = run_gpu(mp, q, box=(16, 16, 16), allow=(-3,))
+    assert st["status_name"] == "INCOMPATIBLE_RHS"
+
+
+def test_boxes_256_full_size(mp):
+    """The 256^3 steep-stratification box split into 64 boxes of 64^3: the
+    single-box solve's cycles and result, and the discrete system satisfied to
+    rtol (the oracle's operator in FP64)."""
+    prob = I.STEEP_256()
+    st, out = run_gpu(mp, prob, box=(64, 64, 64))
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10
+    check_single(mp, prob, st, out)
+    c = O.face_coeffs(prob.n, prob.periodic, prob.rho, prob.beta0_cc, prob.beta0_edge)
+    f = O.rhs(prob.n, prob.periodic, prob.dx, prob.beta0_cc, prob.beta0_edge, prob.u, prob.v, prob.w, prob.S)
+    f -= f.mean()
+    r = O.residual(prob.n, prob.periodic, prob.dx, c, out["phi"], f)
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(f)
