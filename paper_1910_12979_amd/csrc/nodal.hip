@@ -167,7 +167,7 @@ __device__ inline void nod_stencil_fast(const NodLevel& L, const double* __restr
 
 __device__ inline void block_row(double v0, double v1, double v2, double v3, double* out) {
     __shared__ double sh[4][kNodBlock];
-    const int t = threadIdx.x;
+    const int t = threadIdx.y * blockDim.x + threadIdx.x;
     sh[0][t] = v0;
     sh[1][t] = v1;
     sh[2][t] = v2;
@@ -190,6 +190,13 @@ __device__ inline void block_row(double v0, double v1, double v2, double v3, dou
     }
 }
 
+// Point loops of the reductions: 64 x 4 threads per workgroup over (x, y),
+// the workgroups of a launch striding over x, y and the planes; no
+// per-thread index division.  The partial row of a workgroup is its flat
+// index.
+constexpr int kPtX = 64, kPtY = 4;
+__device__ inline int part_row() { return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x; }
+
 // sigma = beta0 / rho per cell; partial rows {0, 0, bad, #non-finite} of
 // rho, beta0, S and the three velocity components.
 __global__ __launch_bounds__(kNodBlock) void k_nod_sigma(NodLevel L, const double* __restrict__ rho,
@@ -197,18 +204,18 @@ __global__ __launch_bounds__(kNodBlock) void k_nod_sigma(NodLevel L, const doubl
                                                          const double* __restrict__ S, const double* __restrict__ u,
                                                          const double* __restrict__ v, const double* __restrict__ w,
                                                          double* __restrict__ partials) {
-    const size_t N = L.cells();
-    const size_t plane = (size_t)L.nx * L.ny;
     double bad = 0.0, nonfin = 0.0;
-    for (size_t c = (size_t)blockIdx.x * kNodBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kNodBlock) {
-        const int k = (int)(c / plane);
+    for (int k = blockIdx.z; k < L.nz; k += gridDim.z)
+    for (int j = blockIdx.y * kPtY + threadIdx.y; j < L.ny; j += gridDim.y * kPtY)
+    for (int i = blockIdx.x * kPtX + threadIdx.x; i < L.nx; i += gridDim.x * kPtX) {
+        const size_t c = cidx3(L, i, j, k);
         const double r = rho[c], b = b0c[k];
         if (!isfinite(r) || !isfinite(b)) nonfin += 1.0;
         if (S && (!isfinite(S[c]) || !isfinite(u[c]) || !isfinite(v[c]) || !isfinite(w[c]))) nonfin += 1.0;
         if (!(r > 0.0) || !(b > 0.0)) bad = 1.0;
         L.sig[c] = b / r;
     }
-    block_row(0.0, 0.0, bad, nonfin, partials + (size_t)blockIdx.x * kReduceWidth);
+    block_row(0.0, 0.0, bad, nonfin, partials + (size_t)part_row() * kReduceWidth);
 }
 
 // f_n and partial rows {sum f, sum |f|, 0, 0}.
@@ -216,13 +223,12 @@ __global__ __launch_bounds__(kNodBlock) void k_nod_rhs(NodLevel L, const double*
                                                        const double* __restrict__ u, const double* __restrict__ v,
                                                        const double* __restrict__ w, const double* __restrict__ S,
                                                        double* __restrict__ partials) {
-    const size_t NN = L.nodes();
     const int nc[3] = {L.nx, L.ny, L.nz}, per[3] = {L.px, L.py, L.pz};
     double sf = 0.0, saf = 0.0;
-    for (size_t n = (size_t)blockIdx.x * kNodBlock + threadIdx.x; n < NN; n += (size_t)gridDim.x * kNodBlock) {
-        const int I = (int)(n % L.Nx);
-        const int J = (int)((n / L.Nx) % L.Ny);
-        const int K = (int)(n / ((size_t)L.Nx * L.Ny));
+    for (int K = blockIdx.z; K < L.Nz; K += gridDim.z)
+    for (int J = blockIdx.y * kPtY + threadIdx.y; J < L.Ny; J += gridDim.y * kPtY)
+    for (int I = blockIdx.x * kPtX + threadIdx.x; I < L.Nx; I += gridDim.x * kPtX) {
+        const size_t n = nidx(L, I, J, K);
         const int X[3] = {I, J, K};
         double div = 0.0, src = 0.0;
         for (int sz = 0; sz < 2; ++sz)
@@ -246,7 +252,7 @@ __global__ __launch_bounds__(kNodBlock) void k_nod_rhs(NodLevel L, const double*
         sf += fn;
         saf += fabs(fn);
     }
-    block_row(sf, saf, 0.0, 0.0, partials + (size_t)blockIdx.x * kReduceWidth);
+    block_row(sf, saf, 0.0, 0.0, partials + (size_t)part_row() * kReduceWidth);
 }
 
 // One colour of the Gauss-Seidel sweep; thread (I, tj, tk) owns node
@@ -301,19 +307,18 @@ __device__ inline double nod_apply(const NodLevel& L, const double* __restrict__
 // r = f - L phi into L.r; partial rows {sum r^2, 0, max |r|, #non-finite}
 // when partials != null.
 __global__ __launch_bounds__(kNodBlock) void k_nod_resid(NodLevel L, double* __restrict__ partials) {
-    const size_t NN = L.nodes();
     double s = 0.0, mx = 0.0, nonfin = 0.0;
-    for (size_t n = (size_t)blockIdx.x * kNodBlock + threadIdx.x; n < NN; n += (size_t)gridDim.x * kNodBlock) {
-        const int I = (int)(n % L.Nx);
-        const int J = (int)((n / L.Nx) % L.Ny);
-        const int K = (int)(n / ((size_t)L.Nx * L.Ny));
+    for (int K = blockIdx.z; K < L.Nz; K += gridDim.z)
+    for (int J = blockIdx.y * kPtY + threadIdx.y; J < L.Ny; J += gridDim.y * kPtY)
+    for (int I = blockIdx.x * kPtX + threadIdx.x; I < L.Nx; I += gridDim.x * kPtX) {
+        const size_t n = nidx(L, I, J, K);
         const double r = L.f[n] - nod_apply(L, L.phi, I, J, K);
         L.r[n] = r;
         if (!isfinite(r)) nonfin += 1.0;
         s += r * r;
         mx = fmax(mx, fabs(r));
     }
-    if (partials) block_row(s, 0.0, mx, nonfin, partials + (size_t)blockIdx.x * kReduceWidth);
+    if (partials) block_row(s, 0.0, mx, nonfin, partials + (size_t)part_row() * kReduceWidth);
 }
 
 // coarse f = 1/8 sum_d w(d) r_{2C+d} (existing fine nodes), coarse phi = 0.
@@ -481,6 +486,16 @@ __global__ void k_nod_shift_out(size_t n, const double* __restrict__ phi, const 
         out[e] = phi[e] - m;
 }
 
+// Grid of a point loop over an X x Y x Z box: at most 2048 workgroups (the
+// partial rows), the planes shared out among them.
+inline dim3 point_grid(int X, int Y, int Z) {
+    const int gx = std::min((X + kPtX - 1) / kPtX, 2048);
+    const int gy = std::max(1, std::min((Y + kPtY - 1) / kPtY, 2048 / gx));
+    const int gz = std::max(1, std::min(Z, 2048 / (gx * gy)));
+    return dim3(gx, gy, gz);
+}
+inline int grid_blocks(dim3 g) { return (int)(g.x * g.y * g.z); }
+
 inline int nod_partial_blocks(size_t N) {
     size_t b = (N + kNodBlock - 1) / kNodBlock;
     return (int)std::min<size_t>(b, 2048);
@@ -564,8 +579,7 @@ int nod_smooth(nodal_hierarchy* H, int l, int nsweeps, hipStream_t st) {
 int nod_resid_restrict(nodal_hierarchy* H, int l, hipStream_t st) {
     const NodLevel& F = H->lev[l];
     const NodLevel& C = H->lev[l + 1];
-    hipLaunchKernelGGL(k_nod_resid, dim3(nod_partial_blocks(F.nodes())), dim3(kNodBlock), 0, st, F,
-                       (double*)nullptr);
+    hipLaunchKernelGGL(k_nod_resid, point_grid(F.Nx, F.Ny, F.Nz), dim3(kPtX, kPtY), 0, st, F, (double*)nullptr);
     const dim3 block(32, 4, 2);
     hipLaunchKernelGGL(k_nod_restrict, grid3(C.Nx, C.Ny, C.Nz, block), block, 0, st, F, C);
     NHIP(hipGetLastError());
@@ -603,8 +617,9 @@ int nod_vcycle(nodal_hierarchy* H, int l, hipStream_t st) {
 int nod_coefficients(nodal_hierarchy* H, const double* rho, const double* b0c, const double* S, const double* u,
                      const double* v, const double* w, hipStream_t st) {
     const NodLevel& L0 = H->lev[0];
-    const int nb = nod_partial_blocks(L0.cells());
-    hipLaunchKernelGGL(k_nod_sigma, dim3(nb), dim3(kNodBlock), 0, st, L0, rho, b0c, S, u, v, w, H->partials);
+    const dim3 sg = point_grid(L0.nx, L0.ny, L0.nz);
+    const int nb = grid_blocks(sg);
+    hipLaunchKernelGGL(k_nod_sigma, sg, dim3(kPtX, kPtY), 0, st, L0, rho, b0c, S, u, v, w, H->partials);
     NHIP(hipGetLastError());
     int rc = nod_reduce(H, nb, kSlotRhs, st);
     if (rc) return rc;
@@ -637,8 +652,9 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
     if (rc) return S_->status = rc;
     NodLevel& L0 = H->lev[0];
     const size_t NN = L0.nodes();
-    int nb = nod_partial_blocks(NN);
-    hipLaunchKernelGGL(k_nod_rhs, dim3(nb), dim3(kNodBlock), 0, st, L0, b0c, u, v, w, S, H->partials);
+    const dim3 ng = point_grid(L0.Nx, L0.Ny, L0.Nz);
+    const int nb = grid_blocks(ng);
+    hipLaunchKernelGGL(k_nod_rhs, ng, dim3(kPtX, kPtY), 0, st, L0, b0c, u, v, w, S, H->partials);
     NHIP(hipGetLastError());
     rc = nod_reduce(H, nb, kSlotNorm, st);
     if (rc) return S_->status = rc;
@@ -672,7 +688,7 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
         auto cycle = [&](hipStream_t s) -> int {
             int r2 = nod_vcycle(H, 0, s);
             if (r2) return r2;
-            hipLaunchKernelGGL(k_nod_resid, dim3(nb), dim3(kNodBlock), 0, s, L0, H->partials);
+            hipLaunchKernelGGL(k_nod_resid, ng, dim3(kPtX, kPtY), 0, s, L0, H->partials);
             NHIP(hipGetLastError());
             NHIP(launch_reduce(H->partials, nb, H->scal + kSlotRes * kReduceWidth, s));
             NHIP(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
