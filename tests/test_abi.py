@@ -64,3 +64,22 @@ def test_host_side_validation_without_gpu():
     mixed = M.make_params((64, 64, 64), 1 / 64, precision="mixed")
     plain = M.make_params((64, 64, 64), 1 / 64)
     assert M.mg_workspace_bytes(mixed) > M.mg_workspace_bytes(plain)
+
+
+def test_setters_reject_a_null_handle_without_gpu():
+    from paper_1910_12979_amd import macproj as M
+    lib = M.lib()
+    box = (ctypes.c_int32 * 3)(16, 16, 16)
+    assert lib.mg_set_boxes(None, box) == -1
+    assert lib.mg_set_graphs(None, 1) == -1
+    assert lib.mg_set_bottom(None, 1) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; --gpus N > 1 exits with a message
+    before anything touches a device."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
