@@ -182,3 +182,27 @@ def test_boxes_256_full_size(mp):
     f -= f.mean()
     r = O.residual(prob.n, prob.periodic, prob.dx, c, out["phi"], f)
     assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("pre,post", [(1, 1), (3, 1), (0, 2)])
+def test_boxes_other_sweep_counts(mp, pre, post):
+    """Odd and zero sweep counts: the box smoother's colour exchanges keep
+    every ghost current for the residual that follows."""
+    prob = I.make_problem((32, 48, 32), H=0.2, rho_noise=0.05, seed=30 + pre, periodic=(True, False, False),
+                          dx=1.0 / 32)
+    prob.pre_sweeps, prob.post_sweeps = pre, post
+    st, out = run_gpu(mp, prob, box=(16, 16, 8))
+    assert st["status_name"] == "OK"
+    check_single(mp, prob, st, out)
+
+
+def test_boxes_cycle_cap(mp):
+    """max_cycles reached: the same not-converged iterate as the single box."""
+    prob = I.make_problem((32, 32, 32), H=0.15, rho_noise=0.05, seed=33)
+    prob.max_cycles = 2
+    st, out = run_gpu(mp, prob, box=(8, 8, 8), allow=(0, -4))
+    st1, out1 = run_gpu(mp, prob, allow=(0, -4))
+    assert st["status_name"] == "NOT_CONVERGED" and st1["status_name"] == "NOT_CONVERGED"
+    assert st["cycles"] == st1["cycles"] == 2
+    for k in out:
+        assert rel(out[k], out1[k]) <= 1e-12, k
