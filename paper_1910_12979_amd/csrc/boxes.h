@@ -1,14 +1,15 @@
 // Multi-box finest level: layout and launchers (internal, not part of the
 // C ABI).  The finest level of an n0 x n1 x n2 domain is tiled by
 // nb0 x nb1 x nb2 boxes of B0 x B1 x B2 cells (every B_d even, dividing n_d);
-// box b = (kb nb1 + jb) nb0 + ib, x fastest.  Per box, contiguous:
-//   phi  (B0+2)(B1+2)(B2+2)  interior plus one ghost layer on each face
-//   f    B0 B1 B2
-//   cx   (B0+1) B1 B2        x-face coefficients, face f between cells f-1, f
-//   cy   B0 (B1+1) B2
-//   cz   B0 B1 (B2+1)
-// Edge and corner ghosts are never read (the operator is the 7-point one).
-// Offsets inside one box are 32-bit: (B0+2)(B1+2)(B2+2) < 2^31.
+// box b = (kb nb1 + jb) nb0 + ib, x fastest.  Every box array is ghosted:
+// G0 x G1 x G2 cells, G_d = B_d + 2 kBoxGhost, local cell (i, j, k) of the
+// box at ((k + g) G1 + (j + g)) G0 + (i + g), g = kBoxGhost, boxes one after
+// another (stride G0 G1 G2 elements):
+//   phi, phi2  two buffers (the fused sweep is out of place)
+//   f          the right-hand side, ghosts included (the neighbour's value)
+//   cx, cy, cz face coefficients, cell-aligned low faces in the same layout
+// Ghost cells beyond a wall hold phi = f = 0 and coefficient 1 on their
+// faces (finite updates), except the wall face itself, which is 0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,15 +18,19 @@
 
 namespace mg {
 
+constexpr int kBoxGhost = 2;
+
 struct BoxSet {
     int n[3];         // domain cells
     int B[3];         // box cells
     int nb[3];        // boxes per direction
     int per[3];       // periodic directions
+    int G[3];         // ghosted box dims
     int nbox;
-    int face_max;     // largest face (cells) of a box
-    size_t phi_stride, f_stride, cx_stride, cy_stride, cz_stride;
-    double* phi;
+    int fused;        // smoother: fused sweeps (1) or one launch per colour (0)
+    size_t stride;    // elements per box
+    double* phi;      // current phi
+    double* phi2;     // the other buffer
     double* f;
     double* cx;
     double* cy;
@@ -33,14 +38,16 @@ struct BoxSet {
 };
 
 size_t boxset_cells(const BoxSet& B);
-// phi = 0 (ghosts included); f and the face arrays from the global
-// finest-level f and cell-aligned bx, by, bz.
+// phi = phi2 = 0; f and the face arrays of every ghosted box from the global
+// finest-level f and cell-aligned bx, by, bz (periodic images; walls as above).
 hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx, const double* by, const double* bz,
                               hipStream_t st);
-// Every ghost face from the neighbouring boxes (periodic images; 0 beyond walls).
-hipError_t launch_box_exchange(const BoxSet& B, hipStream_t st);
-// nsweeps red-black sweeps, after each colour a halo exchange of that colour.
-hipError_t launch_box_smooth(const BoxSet& B, double h, int nsweeps, hipStream_t st);
+// Every ghost cell of phi (colour 0 / 1: only that colour's; -1: all) from
+// the box that owns its cell (periodic images; 0 beyond walls).
+hipError_t launch_box_exchange(const BoxSet& B, int colour, hipStream_t st);
+// nsweeps red-black sweeps, each followed by a halo exchange (per-colour
+// smoother: after each colour).  Fused sweeps swap B.phi and B.phi2.
+hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st);
 // Restricted residual into the (single-box) next level: fc, phic = 0.
 hipError_t launch_box_resid_restrict(const BoxSet& B, double h, double* fc, double* phic, hipStream_t st);
 // phi += P phic, then a halo exchange.

@@ -1,28 +1,31 @@
 // Multi-box finest level for gfx950: the domain is tiled by a grid of equal
-// boxes, each holding its own phi (with one ghost layer on its faces), f and
-// face coefficients.  Smoothing, residual + restriction, prolongation and
-// the residual norm of the finest level run box by box (all boxes in one
-// launch) with a halo exchange that refills every ghost face from the
-// neighbouring box (or the periodic image, or 0 beyond a wall, where the
-// face coefficient is 0) after each colour.  Levels 1 and coarser are the
+// boxes, each holding its own phi (two buffers), f and face coefficients
+// with a two-cell ghost shell.  Smoothing, residual + restriction,
+// prolongation and the residual norm of the finest level run box by box (all
+// boxes in one launch); a halo exchange refills every ghost cell from the
+// box that owns it (or the periodic image, or 0 beyond a wall) after each
+// sweep and after the prolongation.  Levels 1 and coarser are the
 // hierarchy's single-box levels.  This is the layout of a domain whose boxes
 // are spread over several devices (the exchange then becomes a message),
 // kept on one GPU.
 //
-// Per cell the arithmetic follows the single-box kernels (face order
-// x-low, x-high, y-low, y-high, z-low, z-high; the same division; the same
-// restriction order); only the order in which the residual norm is summed
-// differs.
+// Smoother: boxes of at least 32 x 8 x 4 cells use the fused out-of-place
+// sweep of the single-box finest level on each box interior (its red update
+// on a ring around each tile reads the ghost shell, which is why the shell
+// is two cells deep and holds f and the coefficients too); smaller boxes use
+// one launch per colour with an exchange of that colour in between.  Either
+// way every cell update is the single-box expression, so only the order in
+// which the residual norm is summed differs from the single-box solve.
 //
-// Launch shape: every cell kernel runs 256-thread workgroups over 2-D
-// (x, y) patches of one plane of one box; the flat workgroup index is split
-// into (patch x, patch y, plane, box) with uniform 32-bit arithmetic, so no
-// per-thread 64-bit division is needed.
+// Launch shape of the cell kernels: 256-thread workgroups over 2-D (x, y)
+// patches of one plane of one box; the flat workgroup index is split into
+// (patch x, patch y, plane, box) with uniform 32-bit arithmetic.
 #include <hip/hip_runtime.h>
 
 #include "boxes.h"
 #include "devmath.h"
 #include "mg_internal.h"
+#include "sweep.h"
 
 namespace mg {
 namespace {
@@ -32,6 +35,7 @@ constexpr int kCellTX = 64, kCellTY = 4;     // cell kernels: 64 x 4 cells
 constexpr int kGsTX = 32, kGsTY = 8;         // one colour: 32 x 8 cells of that colour (64 x 8 cells)
 constexpr int kRrTX = 32, kRrTY = 4;         // residual + restriction: 32 x 4 x 2 fine cells
 constexpr int kMaxNormBlocks = 2048;         // partial rows available for the norm
+constexpr int kG = kBoxGhost;
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -61,162 +65,167 @@ __device__ inline void box_coords(const BoxSet& B, int b, int c[3]) {
 
 __device__ inline size_t gidx(int i, int j, int k, int nx, int ny) { return ((size_t)k * ny + j) * nx + i; }
 
-// Per-box views (32-bit offsets inside a box).
+// Per-box view (32-bit offsets inside a box); local cells -kG .. B + kG - 1.
 struct BoxView {
-    double* phi;          // ghosted, (B0+2)(B1+2)(B2+2), origin at local (-1, -1, -1)
+    double* phi;
     const double* f;
     const double* cx;
     const double* cy;
     const double* cz;
     int gx, gxy;          // ghosted row and plane strides
-    int B0, B1;
-    __device__ inline int p(int i, int j, int k) const { return (k + 1) * gxy + (j + 1) * gx + (i + 1); }
-    __device__ inline int c(int i, int j, int k) const { return (k * B1 + j) * B0 + i; }
-    __device__ inline int fx(int f, int j, int k) const { return (k * B1 + j) * (B0 + 1) + f; }
-    __device__ inline int fy(int i, int f, int k) const { return (k * (B1 + 1) + f) * B0 + i; }
-    __device__ inline int fz(int i, int j, int f) const { return (f * B1 + j) * B0 + i; }
+    __device__ inline int p(int i, int j, int k) const { return (k + kG) * gxy + (j + kG) * gx + (i + kG); }
 };
 
 __device__ inline BoxView view(const BoxSet& B, int b) {
+    const size_t o = (size_t)b * B.stride;
     BoxView v;
-    v.phi = B.phi + (size_t)b * B.phi_stride;
-    v.f = B.f + (size_t)b * B.f_stride;
-    v.cx = B.cx + (size_t)b * B.cx_stride;
-    v.cy = B.cy + (size_t)b * B.cy_stride;
-    v.cz = B.cz + (size_t)b * B.cz_stride;
-    v.gx = B.B[0] + 2;
-    v.gxy = (B.B[0] + 2) * (B.B[1] + 2);
-    v.B0 = B.B[0];
-    v.B1 = B.B[1];
+    v.phi = B.phi + o;
+    v.f = B.f + o;
+    v.cx = B.cx + o;
+    v.cy = B.cy + o;
+    v.cz = B.cz + o;
+    v.gx = B.G[0];
+    v.gxy = B.G[0] * B.G[1];
     return v;
 }
 
-// The six stored face coefficients of local cell (i, j, k) (x-low, x-high,
-// y-low, y-high, z-low, z-high).
-__device__ inline void coef6(const BoxView& v, int i, int j, int k, double b[6]) {
-    b[0] = v.cx[v.fx(i, j, k)];
-    b[1] = v.cx[v.fx(i + 1, j, k)];
-    b[2] = v.cy[v.fy(i, j, k)];
-    b[3] = v.cy[v.fy(i, j + 1, k)];
-    b[4] = v.cz[v.fz(i, j, k)];
-    b[5] = v.cz[v.fz(i, j, k + 1)];
-}
-
-// (L phi) at local cell (i, j, k), faces in the fixed order.
-__device__ inline double box_apply(const BoxView& v, int i, int j, int k, double h2) {
-    double b[6];
-    coef6(v, i, j, k, b);
-    const int c = v.p(i, j, k);
+// (L phi) at the cell with ghosted index c, faces in the fixed order
+// (x-low, x-high, y-low, y-high, z-low, z-high).
+__device__ inline double box_apply(const BoxView& v, int c, double h2) {
     const double pc = v.phi[c];
-    double s = b[0] * (v.phi[c - 1] - pc);
-    s = s + b[1] * (v.phi[c + 1] - pc);
-    s = s + b[2] * (v.phi[c - v.gx] - pc);
-    s = s + b[3] * (v.phi[c + v.gx] - pc);
-    s = s + b[4] * (v.phi[c - v.gxy] - pc);
-    s = s + b[5] * (v.phi[c + v.gxy] - pc);
+    double s = v.cx[c] * (v.phi[c - 1] - pc);
+    s = s + v.cx[c + 1] * (v.phi[c + 1] - pc);
+    s = s + v.cy[c] * (v.phi[c - v.gx] - pc);
+    s = s + v.cy[c + v.gx] * (v.phi[c + v.gx] - pc);
+    s = s + v.cz[c] * (v.phi[c - v.gxy] - pc);
+    s = s + v.cz[c + v.gxy] * (v.phi[c + v.gxy] - pc);
     return s * (1.0 / h2);
 }
 
-// phi = 0 everywhere, ghosts included.
-__global__ __launch_bounds__(kBoxBlock) void k_box_zero(BoxSet B) {
-    const size_t n = B.phi_stride * B.nbox;
-    for (size_t e = (size_t)blockIdx.x * kBoxBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBoxBlock)
-        B.phi[e] = 0.0;
+// Global cell of local coordinate L of a box at origin o along direction d:
+// wrapped on a periodic direction; -1 beyond a wall.
+__device__ inline int box_global(const BoxSet& B, int d, int o, int L) {
+    int g = o + L;
+    if (g >= 0 && g < B.n[d]) return g;
+    if (!B.per[d]) return -1;
+    return g < 0 ? g + B.n[d] : g - B.n[d];
 }
 
-// f and the face coefficients of every box from the global level-0 arrays
-// (cell-aligned low faces; face n of a direction is face 0).
+// phi = phi2 = 0; f and the face arrays of every ghosted cell.  One thread
+// per ghosted cell, patches over the ghosted planes.
 __global__ __launch_bounds__(kBoxBlock) void k_box_scatter(BoxSet B, const double* __restrict__ f,
                                                            const double* __restrict__ bx,
                                                            const double* __restrict__ by,
                                                            const double* __restrict__ bz, int gx, int gy) {
-    const Patch q = patch_of(blockIdx.x, gx, gy, B.B[2], kCellTX, kCellTY);
-    const int i = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y, k = q.k;
-    if (i >= B.B[0] || j >= B.B[1]) return;
-    int bc[3];
-    box_coords(B, q.b, bc);
-    const int gi = bc[0] * B.B[0] + i, gj = bc[1] * B.B[1] + j, gk = bc[2] * B.B[2] + k;
-    const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-    BoxView v = view(B, q.b);
-    const size_t g = gidx(gi, gj, gk, nx, ny);
-    B.f[(size_t)q.b * B.f_stride + v.c(i, j, k)] = f[g];
-    double* cx = B.cx + (size_t)q.b * B.cx_stride;
-    double* cy = B.cy + (size_t)q.b * B.cy_stride;
-    double* cz = B.cz + (size_t)q.b * B.cz_stride;
-    cx[v.fx(i, j, k)] = bx[g];
-    cy[v.fy(i, j, k)] = by[g];
-    cz[v.fz(i, j, k)] = bz[g];
-    if (i == B.B[0] - 1) cx[v.fx(i + 1, j, k)] = bx[gidx(gi + 1 < nx ? gi + 1 : 0, gj, gk, nx, ny)];
-    if (j == B.B[1] - 1) cy[v.fy(i, j + 1, k)] = by[gidx(gi, gj + 1 < ny ? gj + 1 : 0, gk, nx, ny)];
-    if (k == B.B[2] - 1) cz[v.fz(i, j, k + 1)] = bz[gidx(gi, gj, gk + 1 < nz ? gk + 1 : 0, nx, ny)];
+    const Patch q = patch_of(blockIdx.x, gx, gy, B.G[2], kCellTX, kCellTY);
+    const int i = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y;
+    if (i >= B.G[0] || j >= B.G[1]) return;
+    const size_t e = (size_t)q.b * B.stride + ((size_t)q.k * B.G[1] + j) * B.G[0] + i;
+    int c[3];
+    box_coords(B, q.b, c);
+    const int L[3] = {i - kG, j - kG, q.k - kG};
+    int g[3];
+    int out = 0, wall_d = -1;                 // directions beyond a wall; the one at a high wall face
+    for (int d = 0; d < 3; ++d) {
+        g[d] = box_global(B, d, c[d] * B.B[d], L[d]);
+        if (g[d] < 0) {
+            ++out;
+            if (c[d] * B.B[d] + L[d] == B.n[d]) wall_d = d;
+        }
+    }
+    B.phi[e] = 0.0;
+    B.phi2[e] = 0.0;
+    double fv = 0.0, cv[3] = {1.0, 1.0, 1.0};
+    if (out == 0) {
+        const size_t gi = gidx(g[0], g[1], g[2], B.n[0], B.n[1]);
+        fv = f[gi];
+        cv[0] = bx[gi];
+        cv[1] = by[gi];
+        cv[2] = bz[gi];
+    } else if (out == 1 && wall_d >= 0) {
+        cv[wall_d] = 0.0;                     // the first cell past a high wall: its low face is the wall
+    }
+    B.f[e] = fv;
+    B.cx[e] = cv[0];
+    B.cy[e] = cv[1];
+    B.cz[e] = cv[2];
 }
 
-// Halo exchange: every ghost face cell of every box from the neighbouring
-// box's boundary cell (the periodic image at the domain edge, 0 beyond a
-// wall).  Workgroup = (chunk of a face, side, box); side 0/1 x low/high,
-// 2/3 y, 4/5 z; the face's cells run over its two other directions, first
-// fastest.  colour 0 / 1: only the ghosts of that colour (the cells the
-// last red or black update changed; a ghost has its source cell's global
-// parity); -1: all.
-__global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, int chunks, int colour) {
-    unsigned t = blockIdx.x;
-    const int chunk = (int)(t % (unsigned)chunks);
-    t /= (unsigned)chunks;
-    const int side = (int)(t % 6u);
-    const int b = (int)(t / 6u);
-    const int d = side >> 1, hi = side & 1;
-    const int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;     // the face's two directions
-    const int nu = B.B[a1], nv = B.B[a2];
-    const int q = chunk * kBoxBlock + (int)threadIdx.x;
-    if (q >= nu * nv) return;
-    int L[3];
-    L[a1] = q % nu;
-    L[a2] = q / nu;
-    L[d] = hi ? B.B[d] : -1;                               // the ghost cell
-    if (colour >= 0 && ((L[0] + L[1] + L[2]) & 1) != colour) return;
+// Halo exchange over the ghost shell of every box: workgroup (chunk,
+// plane, box) treats up to kExChunk shell cells of one ghosted plane (all of
+// a ghost plane, the two-cell border of an interior plane).  colour 0 / 1:
+// only that colour's ghosts (a ghost has the global parity of its cell);
+// -1: all.
+constexpr int kExChunk = 4 * kBoxBlock;
+__global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, int colour, int chunks) {
+    const int G0 = B.G[0], G1 = B.G[1], G2 = B.G[2];
+    const int chunk = (int)(blockIdx.x % (unsigned)chunks);
+    const int kp = (int)((blockIdx.x / (unsigned)chunks) % (unsigned)G2);
+    const int b = (int)(blockIdx.x / ((unsigned)chunks * G2));
+    const int k = kp - kG;
+    const bool ghost_plane = k < 0 || k >= B.B[2];
+    const int ncell = ghost_plane ? G0 * G1 : 2 * kG * G0 + 2 * kG * B.B[1];
     int c[3];
     box_coords(B, b, c);
-    c[d] += hi ? 1 : -1;                                   // the neighbouring box
-    bool wall = false;
-    if (c[d] < 0 || c[d] >= B.nb[d]) {
-        if (B.per[d]) c[d] = c[d] < 0 ? B.nb[d] - 1 : 0;
-        else wall = true;
-    }
     const BoxView v = view(B, b);
-    double val = 0.0;
-    if (!wall) {
-        const int sb = (c[2] * B.nb[1] + c[1]) * B.nb[0] + c[0];
-        int S[3] = {L[0], L[1], L[2]};
-        S[d] = hi ? 0 : B.B[d] - 1;                        // its boundary cell
-        val = B.phi[(size_t)sb * B.phi_stride + v.p(S[0], S[1], S[2])];
+    const int e_end = min(ncell, (chunk + 1) * kExChunk);
+    for (int e = chunk * kExChunk + threadIdx.x; e < e_end; e += kBoxBlock) {
+        int i, j;
+        if (ghost_plane) {
+            i = e % G0 - kG;
+            j = e / G0 - kG;
+        } else if (e < 2 * kG * G0) {         // the ghost rows, whole
+            const int r = e / G0;
+            j = r < kG ? r - kG : B.B[1] + r - kG;
+            i = e % G0 - kG;
+        } else {                              // the ghost columns of the interior rows
+            const int e2 = e - 2 * kG * G0;
+            j = e2 / (2 * kG);
+            const int r = e2 % (2 * kG);
+            i = r < kG ? r - kG : B.B[0] + r - kG;
+        }
+        if (colour >= 0 && ((i + j + k) & 1) != colour) continue;
+        int g[3];
+        const int L[3] = {i, j, k};
+        bool wall = false;
+        for (int d = 0; d < 3; ++d) {
+            g[d] = box_global(B, d, c[d] * B.B[d], L[d]);
+            if (g[d] < 0) wall = true;
+        }
+        double val = 0.0;
+        if (!wall) {
+            const int sb = (g[2] / B.B[2] * B.nb[1] + g[1] / B.B[1]) * B.nb[0] + g[0] / B.B[0];
+            val = B.phi[(size_t)sb * B.stride + v.p(g[0] % B.B[0], g[1] % B.B[1], g[2] % B.B[2])];
+        }
+        v.phi[v.p(i, j, k)] = val;
     }
-    v.phi[v.p(L[0], L[1], L[2])] = val;
 }
 
-// One colour of red-black Gauss-Seidel in every box; red = (i + j + k)
-// even (boxes start at even global coordinates, so the local parity is the
-// global one).
+// One colour of red-black Gauss-Seidel in every box (boxes too small for
+// the fused sweep); red = (i + j + k) even (boxes start at even global
+// coordinates, so the local parity is the global one).
 __global__ __launch_bounds__(kBoxBlock) void k_box_rbgs(BoxSet B, double h2, int colour, int gx, int gy) {
     const Patch q = patch_of(blockIdx.x, gx, gy, B.B[2], kGsTX, kGsTY);
     const int ih = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y, k = q.k;
     if (2 * ih >= B.B[0] || j >= B.B[1]) return;
     const int i = 2 * ih + ((j + k + colour) & 1);
     const BoxView v = view(B, q.b);
-    double b[6];
-    coef6(v, i, j, k, b);
     const int c = v.p(i, j, k);
-    double num = b[0] * v.phi[c - 1];
-    num = num + b[1] * v.phi[c + 1];
-    num = num + b[2] * v.phi[c - v.gx];
-    num = num + b[3] * v.phi[c + v.gx];
-    num = num + b[4] * v.phi[c - v.gxy];
-    num = num + b[5] * v.phi[c + v.gxy];
-    double den = b[0] + b[1];
-    den = den + b[2];
-    den = den + b[3];
-    den = den + b[4];
-    den = den + b[5];
-    v.phi[c] = qdiv(num - h2 * v.f[v.c(i, j, k)], den);
+    const double bxl = v.cx[c], bxh = v.cx[c + 1];
+    const double byl = v.cy[c], byh = v.cy[c + v.gx];
+    const double bzl = v.cz[c], bzh = v.cz[c + v.gxy];
+    double num = bxl * v.phi[c - 1];
+    num = num + bxh * v.phi[c + 1];
+    num = num + byl * v.phi[c - v.gx];
+    num = num + byh * v.phi[c + v.gx];
+    num = num + bzl * v.phi[c - v.gxy];
+    num = num + bzh * v.phi[c + v.gxy];
+    double den = bxl + bxh;
+    den = den + byl;
+    den = den + byh;
+    den = den + bzl;
+    den = den + bzh;
+    v.phi[c] = qdiv(num - h2 * v.f[c], den);
 }
 
 // Coarse (single-box level 1) f = 1/8 sum of the 8 children's residuals
@@ -235,7 +244,10 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_resid_restrict(BoxSet B, doub
     o[2] *= B.B[2];
     const BoxView v = view(B, q.b);
     double rv = 0.0;
-    if (i < B.B[0] && j < B.B[1]) rv = v.f[v.c(i, j, k)] - box_apply(v, i, j, k, h2);
+    if (i < B.B[0] && j < B.B[1]) {
+        const int c = v.p(i, j, k);
+        rv = v.f[c] - box_apply(v, c, h2);
+    }
     r[tz][ty][tx] = rv;
     __syncthreads();
     const int flat = (tz * kRrTY + ty) * kRrTX + tx;
@@ -275,7 +287,8 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_resid_norm(BoxSet B, double h
         const int i = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y;
         if (i >= B.B[0] || j >= B.B[1]) continue;
         const BoxView v = view(B, q.b);
-        const double r = v.f[v.c(i, j, q.k)] - box_apply(v, i, j, q.k, h2);
+        const int c = v.p(i, j, q.k);
+        const double r = v.f[c] - box_apply(v, c, h2);
         if (!isfinite(r)) nonfin += 1.0;
         s += r * r;
         mx = fmax(mx, fabs(r));
@@ -314,7 +327,7 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_gather(BoxSet B, double* __re
     phi[gidx(o[0] * B.B[0] + i, o[1] * B.B[1] + j, o[2] * B.B[2] + k, B.n[0], B.n[1])] = v.phi[v.p(i, j, k)];
 }
 
-// Workgroups of a cell launch (64 x 4 patches, B2 planes per box).
+// Workgroups of a cell launch over the box interiors (64 x 4 patches).
 inline void cell_grid(const BoxSet& B, int& gx, int& gy, unsigned& blocks) {
     gx = cdiv(B.B[0], kCellTX);
     gy = cdiv(B.B[1], kCellTY);
@@ -322,9 +335,9 @@ inline void cell_grid(const BoxSet& B, int& gx, int& gy, unsigned& blocks) {
 }
 
 hipError_t exchange(const BoxSet& B, int colour, hipStream_t st) {
-    const int chunks = cdiv(B.face_max, kBoxBlock);
-    hipLaunchKernelGGL(k_box_exchange, dim3((unsigned)chunks * 6 * B.nbox), dim3(kBoxBlock), 0, st, B, chunks,
-                       colour);
+    const int chunks = cdiv(B.G[0] * B.G[1], kExChunk);
+    hipLaunchKernelGGL(k_box_exchange, dim3((unsigned)chunks * B.G[2] * B.nbox), dim3(kBoxBlock), 0, st, B, colour,
+                       chunks);
     return hipGetLastError();
 }
 
@@ -334,17 +347,41 @@ size_t boxset_cells(const BoxSet& B) { return (size_t)B.B[0] * B.B[1] * B.B[2] *
 
 hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx, const double* by, const double* bz,
                               hipStream_t st) {
-    hipLaunchKernelGGL(k_box_zero, dim3(2048), dim3(kBoxBlock), 0, st, B);
-    int gx, gy;
-    unsigned blocks;
-    cell_grid(B, gx, gy, blocks);
+    const int gx = cdiv(B.G[0], kCellTX), gy = cdiv(B.G[1], kCellTY);
+    const unsigned blocks = (unsigned)gx * gy * B.G[2] * B.nbox;
     hipLaunchKernelGGL(k_box_scatter, dim3(blocks), dim3(kCellTX, kCellTY), 0, st, B, f, bx, by, bz, gx, gy);
     return hipGetLastError();
 }
 
-hipError_t launch_box_exchange(const BoxSet& B, hipStream_t st) { return exchange(B, -1, st); }
+hipError_t launch_box_exchange(const BoxSet& B, int colour, hipStream_t st) { return exchange(B, colour, st); }
 
-hipError_t launch_box_smooth(const BoxSet& B, double h, int nsweeps, hipStream_t st) {
+hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st) {
+    if (B.fused) {
+        SweepArgs<double> a{};
+        a.nx = B.G[0];
+        a.ny = B.G[1];
+        a.nz = B.G[2];
+        a.px = a.py = a.pz = 1;
+        a.ox = a.oy = a.oz = kG;
+        a.ex = B.B[0];
+        a.ey = B.B[1];
+        a.ez = B.B[2];
+        a.h2 = h * h;
+        a.f = B.f;
+        a.bx = B.cx;
+        a.by = B.cy;
+        a.bz = B.cz;
+        for (int s = 0; s < nsweeps; ++s) {
+            a.phi_in = B.phi;
+            a.phi_out = B.phi2;
+            hipError_t e = launch_sweep_boxes(a, B.nbox, B.stride, st);
+            if (e != hipSuccess) return e;
+            std::swap(B.phi, B.phi2);
+            e = exchange(B, -1, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     const int gx = cdiv(B.B[0] / 2, kGsTX), gy = cdiv(B.B[1], kGsTY);
     const unsigned blocks = (unsigned)gx * gy * B.B[2] * B.nbox;
     for (int s = 0; s < nsweeps; ++s)

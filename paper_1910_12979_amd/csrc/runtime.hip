@@ -891,7 +891,7 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
 static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStream_t st) {
     Level& L0 = H->lev[0];
     Level& L1 = H->lev[1];
-    const BoxSet& B = H->box;
+    BoxSet& B = H->box;                          // the fused smoother swaps its phi buffers
     HIPCHK(launch_box_scatter(B, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, st));
     int status = H->p.rtol >= 1.0 ? MG_OK : MG_ERR_NOT_CONVERGED;
     int cycles = 0;
@@ -1570,7 +1570,6 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
         return MG_ERR_INVALID_ARG;
     }
     BoxSet B{};
-    size_t ncell = 1;
     for (int d = 0; d < 3; ++d) {
         const int n = h->p.n[d];
         if (box[d] < 2 || box[d] % 2 != 0 || n % box[d] != 0) {
@@ -1580,37 +1579,31 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
         B.n[d] = n;
         B.B[d] = box[d];
         B.nb[d] = n / box[d];
-        ncell *= (size_t)box[d];
+        B.G[d] = box[d] + 2 * kBoxGhost;
     }
     B.per[0] = h->px;
     B.per[1] = h->py;
     B.per[2] = h->pz;
     B.nbox = B.nb[0] * B.nb[1] * B.nb[2];
-    B.face_max = std::max(B.B[1] * B.B[2], std::max(B.B[0] * B.B[2], B.B[0] * B.B[1]));
-    B.phi_stride = (size_t)(B.B[0] + 2) * (B.B[1] + 2) * (B.B[2] + 2);
-    B.f_stride = ncell;
-    B.cx_stride = (size_t)(B.B[0] + 1) * B.B[1] * B.B[2];
-    B.cy_stride = (size_t)B.B[0] * (B.B[1] + 1) * B.B[2];
-    B.cz_stride = (size_t)B.B[0] * B.B[1] * (B.B[2] + 1);
-    if (B.phi_stride >= ((size_t)1 << 31)) {
-        set_error("box too large: (bx+2)(by+2)(bz+2) must stay below 2^31 cells");
+    B.stride = (size_t)B.G[0] * B.G[1] * B.G[2];
+    B.fused = sweep_boxes_fit(B.B[0], B.B[1], B.B[2]) ? 1 : 0;
+    if (B.stride >= ((size_t)1 << 31)) {
+        set_error("box too large: its ghosted array must stay below 2^31 cells");
         return MG_ERR_INVALID_ARG;
     }
-    auto up = [](size_t n) { return (n + 31) / 32 * 32; };     // 256-byte aligned sub-arrays
-    const size_t nb = (size_t)B.nbox;
-    const size_t e_phi = up(B.phi_stride * nb), e_f = up(B.f_stride * nb), e_cx = up(B.cx_stride * nb),
-                 e_cy = up(B.cy_stride * nb), e_cz = up(B.cz_stride * nb);
+    const size_t e = (B.stride * B.nbox + 31) / 32 * 32;     // 256-byte aligned sub-arrays
     if (h->box_mem) HIPCHK(hipFree(h->box_mem));
     h->box_mem = nullptr;
     h->boxes_on = false;
     void* mem = nullptr;
-    HIPCHK(hipMalloc(&mem, (e_phi + e_f + e_cx + e_cy + e_cz) * sizeof(double)));
+    HIPCHK(hipMalloc(&mem, 6 * e * sizeof(double)));
     double* p = static_cast<double*>(mem);
     B.phi = p;
-    B.f = p + e_phi;
-    B.cx = B.f + e_f;
-    B.cy = B.cx + e_cx;
-    B.cz = B.cy + e_cy;
+    B.phi2 = p + e;
+    B.f = p + 2 * e;
+    B.cx = p + 3 * e;
+    B.cy = p + 4 * e;
+    B.cz = p + 5 * e;
     h->box_mem = mem;
     h->box = B;
     h->boxes_on = true;

@@ -52,6 +52,8 @@ struct SweepArgs {
     int has_bnd;               // outflow sides: their boundary faces add to the diagonal
     Bnd<T> bnd;                // which sides are outflow sides (non-null)
     const T* dg;               // per-cell boundary diagonal (bnd_diag of every cell)
+    int ox, oy, oz;            // launch_sweep_boxes: first cell of a box interior
+    int ex, ey, ez;            // launch_sweep_boxes: box cells
 };
 
 template <typename T>
@@ -89,6 +91,17 @@ hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int* prefix, int npro
                               int in_mode, int op, int cfg, hipStream_t st);
 void sweep_geometry(SweepArgs<double>& a, int cfg);
 void sweep_geometry(SweepArgs<float>& a, int cfg);
+
+// One sweep of every box of a multi-box finest level in one launch: nbox
+// boxes stored bstride elements apart, each a ghosted array of a.nx x a.ny x
+// a.nz cells whose interior (a.ex x a.ey x a.ez cells from (a.ox, a.oy,
+// a.oz), ghost width >= 2) is swept out of place from phi_in to phi_out with
+// stored coefficients (bx, by, bz, cell-aligned low faces in the same
+// layout); the ghosts must hold the neighbouring values, and phi_out's are
+// not written.  hipErrorInvalidValue for a shape it does not cover
+// (sweep_boxes_fit).
+bool sweep_boxes_fit(int bx, int by, int bz);
+hipError_t launch_sweep_boxes(const SweepArgs<double>& a, int nbox, size_t bstride, hipStream_t st);
 
 // Number of tiles (= partial rows) a sweep of this shape launches with cfg.
 int sweep_tiles(int nx, int ny, int nz, int cfg);

@@ -32,6 +32,7 @@
 //   phi = (num - h^2 f) / den.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -87,7 +88,7 @@ __device__ inline int xcd_tile(int b, int total) {
 
 // The body of one tile: shared by the single-problem kernel and the batched
 // kernel, so a problem's values do not depend on how it was launched.
-template <typename T, int TX, int TY, bool kRho, int kIn, int kOp, bool kBnd>
+template <typename T, int TX, int TY, bool kRho, int kIn, int kOp, bool kBnd, bool kBox = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile) {
     constexpr bool kNorm = kOp == kOpSweepNorm;    // sweep + residual norm of its input
     constexpr bool kRR = kOp == kOpResidRestrict;  // residual + restriction only (no sweep)
@@ -109,9 +110,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const int tx = tile % a.ntx;
     const int ty = (tile / a.ntx) % a.nty;
     const int tz = tile / (a.ntx * a.nty);
-    const int x0 = tx * TX, y0 = ty * TY;
-    const int z0 = tz * a.tz;
-    const int z1 = min(z0 + a.tz, nz);
+    // tiles cover ex x ey x ez cells from (ox, oy, oz): the whole level, or
+    // (kBox) the interior of one box inside its ghosted array
+    const int ox = kBox ? a.ox : 0, oy = kBox ? a.oy : 0, oz = kBox ? a.oz : 0;
+    const int ex = kBox ? a.ex : nx, ey = kBox ? a.ey : ny, ez = kBox ? a.ez : nz;
+    const int x0 = ox + tx * TX, y0 = oy + ty * TY;
+    const int z0 = oz + tz * a.tz;
+    const int z1 = min(z0 + a.tz, oz + ez);
     const int zb = z0 - 2;                    // first plane touched
 
     const int lp = threadIdx.x % WP;
@@ -124,7 +129,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const bool row_r1 = ly >= 1 && ly < WY - 1;
     const bool r1c0 = row_r1 && lp >= 1;            // even cell inside the ring-1 window
     const bool r1c1 = row_r1 && lp < WP - 1;        // odd cell
-    const bool writes = ly >= 2 && ly < WY - 2 && lp >= 1 && lp <= WP - 2 && gx0 < nx && gy < ny;
+    const bool writes = ly >= 2 && ly < WY - 2 && lp >= 1 && lp <= WP - 2 && gx0 < ox + ex && gy < oy + ey;
     const size_t plane = (size_t)nx * ny;
     const size_t col = (size_t)gyw * nx + gxw;
     const T h2 = a.h2;
@@ -493,6 +498,27 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(kBnd) void 
     sweep_body<T, TX, TY, kRho, kIn, kOp, kBnd>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// Boxes of one shape stored one after another bstride elements apart, each
+// inside its ghosted array (a.nx, a.ny, a.nz: the ghosted dims; a.ox..:
+// the ghost width; a.ex..: the box cells): workgroup tiles enumerate
+// (box, tile), every box with its own pointers.  Stored coefficients, plain
+// input, one sweep.
+template <int TX, int TY>
+__global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_waves_per_eu(
+    SweepWaves<double, TX, TY, false>::value))) void k_sweep_boxes(SweepArgs<double> a, int tpb, size_t bstride) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int b = t / tpb;
+    const size_t off = (size_t)b * bstride;
+    SweepArgs<double> c = a;
+    c.phi_in = a.phi_in + off;
+    c.phi_out = a.phi_out + off;
+    c.f = a.f + off;
+    c.bx = a.bx + off;
+    c.by = a.by + off;
+    c.bz = a.bz + off;
+    sweep_body<double, TX, TY, false, kInPlain, kOpSweep, false, true>(c, t - b * tpb);
+}
+
 // Batched form: problem p owns tiles [prefix[p], prefix[p+1]) of the launch.
 template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
 __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(false) void k_sweep_multi(const SweepArgs<T>* __restrict__ descs,
@@ -772,6 +798,32 @@ void sweep_geometry(SweepArgs<float>& a, int cfg) {
     a.tz = c.tz;
     a.ntx = (a.nx + c.tx - 1) / c.tx;
     a.nty = (a.ny + c.ty - 1) / c.ty;
+}
+
+bool sweep_boxes_fit(int bx, int by, int bz) {
+    return bx >= kSweepTX && by >= 8 && bz >= 4 && bx % 2 == 0 && by % 2 == 0 && bz % 2 == 0;
+}
+
+hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, int nbox, size_t bstride, hipStream_t st) {
+    SweepArgs<double> a = a0;
+    if (!sweep_boxes_fit(a.ex, a.ey, a.ez) || a.ox < 2 || a.oy < 2 || a.oz < 2 || a.nx < a.ex + 2 * a.ox ||
+        a.ny < a.ey + 2 * a.oy || a.nz < a.ez + 2 * a.oz)
+        return hipErrorInvalidValue;
+    // the finest level's own tile (64 x 16) where the box takes it, else 32 x 8
+    const bool wide = a.ex % 64 == 0 && a.ey % 16 == 0;
+    const int TXc = wide ? 64 : 32, TYc = wide ? 16 : 8;
+    a.tz = std::min(a.ez, kSweepTZMax);
+    a.ntx = (a.ex + TXc - 1) / TXc;
+    a.nty = (a.ey + TYc - 1) / TYc;
+    const int ntz = (a.ez + a.tz - 1) / a.tz;
+    const int tpb = a.ntx * a.nty * ntz;
+    const unsigned blocks = (unsigned)tpb * nbox;
+    if (wide)
+        hipLaunchKernelGGL((k_sweep_boxes<64, 16>), dim3(blocks), dim3((64 / 2 + 2) * (16 + 4)), 0, st, a, tpb,
+                           bstride);
+    else
+        hipLaunchKernelGGL((k_sweep_boxes<32, 8>), dim3(blocks), dim3((32 / 2 + 2) * (8 + 4)), 0, st, a, tpb, bstride);
+    return hipGetLastError();
 }
 
 int sweep_tiles(int nx, int ny, int nz, int cfg) {

@@ -2,6 +2,9 @@
 halo exchange between them) against the FP64 CPU oracle and against the
 single-box GPU solve.
 
+Boxes of 32 x 8 x 4 cells and more run the fused sweep on each box interior
+(two-cell ghost shells), smaller ones one launch per colour.
+
 Bar: the same as the single-box parity tests (phi within 1e-9 of the oracle's
 exact discrete solution with the GPU residual <= rtol; the correction exact
 (<= 1e-12) given the GPU's phi; U within max(1e-9, 3 x the oracle's own
@@ -88,7 +91,10 @@ CASES = [
     ((32, 32, 32), (True, False, True), (32, 32, 32), 5),     # one box: it exchanges with itself
     ((16, 16, 16), (True, True, False), (2, 4, 8), 6),        # 256 tiny boxes
     ((6, 10, 14), (True, True, False), (2, 10, 14), 7),       # two levels, 105-cell coarsest
-    ((64, 64, 64), (False, True, False), (32, 16, 64), 8),
+    ((64, 64, 64), (False, True, False), (32, 16, 64), 8),     # fused sweeps inside the boxes
+    ((64, 32, 32), (True, True, True), (32, 16, 16), 9),       # fused, fully periodic
+    ((96, 48, 40), (False, False, False), (32, 8, 4), 10),     # fused, walls, the smallest fused box
+    ((128, 64, 32), (True, False, False), (64, 32, 16), 11),   # fused with 64-wide tiles
 ]
 
 
@@ -109,9 +115,10 @@ def _radial_walls(n, seed):
     return prob
 
 
-def test_boxes_radial_base_state(mp):
-    prob = _radial_walls((32, 32, 48), 11)
-    st, out = run_gpu(mp, prob, box=(16, 16, 16))
+@pytest.mark.parametrize("n,box", [((32, 32, 48), (16, 16, 16)), ((64, 32, 48), (32, 16, 24))])
+def test_boxes_radial_base_state(mp, n, box):
+    prob = _radial_walls(n, 11)
+    st, out = run_gpu(mp, prob, box=box)
     check_oracle(prob, st, out)
     check_single(mp, prob, st, out)
 
