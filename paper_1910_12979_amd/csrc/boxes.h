@@ -48,6 +48,12 @@ hipError_t launch_box_exchange(const BoxSet& B, int colour, hipStream_t st);
 // nsweeps red-black sweeps, each followed by a halo exchange (per-colour
 // smoother: after each colour).  Fused sweeps swap B.phi and B.phi2.
 hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st);
+// Speculative first sweep of the next cycle (fused smoother, at most
+// kMaxPartialRows tiles in all: box_norm_sweep_fits): phi2 = RBGS(phi)
+// without swapping, and per tile the partial rows {sum r^2, 0, 0, 0} of the
+// residual of phi over the box interiors; *nparts rows.
+bool box_norm_sweep_fits(const BoxSet& B);
+hipError_t launch_box_sweep_norm(const BoxSet& B, double h, double* partials, int* nparts, hipStream_t st);
 // Restricted residual into the (single-box) next level: fc, phic = 0.
 hipError_t launch_box_resid_restrict(const BoxSet& B, double h, double* fc, double* phic, hipStream_t st);
 // phi += P phic, then a halo exchange.

@@ -355,26 +355,32 @@ hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx
 
 hipError_t launch_box_exchange(const BoxSet& B, int colour, hipStream_t st) { return exchange(B, colour, st); }
 
+// Arguments of the fused sweep over every box interior.
+SweepArgs<double> box_sweep_args(const BoxSet& B, double h) {
+    SweepArgs<double> a{};
+    a.nx = B.G[0];
+    a.ny = B.G[1];
+    a.nz = B.G[2];
+    a.px = a.py = a.pz = 1;
+    a.ox = a.oy = a.oz = kG;
+    a.ex = B.B[0];
+    a.ey = B.B[1];
+    a.ez = B.B[2];
+    a.h2 = h * h;
+    a.f = B.f;
+    a.bx = B.cx;
+    a.by = B.cy;
+    a.bz = B.cz;
+    return a;
+}
+
 hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st) {
     if (B.fused) {
-        SweepArgs<double> a{};
-        a.nx = B.G[0];
-        a.ny = B.G[1];
-        a.nz = B.G[2];
-        a.px = a.py = a.pz = 1;
-        a.ox = a.oy = a.oz = kG;
-        a.ex = B.B[0];
-        a.ey = B.B[1];
-        a.ez = B.B[2];
-        a.h2 = h * h;
-        a.f = B.f;
-        a.bx = B.cx;
-        a.by = B.cy;
-        a.bz = B.cz;
+        SweepArgs<double> a = box_sweep_args(B, h);
         for (int s = 0; s < nsweeps; ++s) {
             a.phi_in = B.phi;
             a.phi_out = B.phi2;
-            hipError_t e = launch_sweep_boxes(a, B.nbox, B.stride, st);
+            hipError_t e = launch_sweep_boxes(a, B.nbox, B.stride, nullptr, st);
             if (e != hipSuccess) return e;
             std::swap(B.phi, B.phi2);
             e = exchange(B, -1, st);
@@ -391,6 +397,19 @@ hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st) {
             if (e != hipSuccess) return e;
         }
     return hipGetLastError();
+}
+
+bool box_norm_sweep_fits(const BoxSet& B) {
+    return B.fused && (long long)sweep_boxes_tiles(B.B[0], B.B[1], B.B[2]) * B.nbox <= kMaxPartialRows;
+}
+
+hipError_t launch_box_sweep_norm(const BoxSet& B, double h, double* partials, int* nparts, hipStream_t st) {
+    if (!box_norm_sweep_fits(B)) return hipErrorInvalidValue;
+    SweepArgs<double> a = box_sweep_args(B, h);
+    a.phi_in = B.phi;
+    a.phi_out = B.phi2;
+    a.partials = partials;
+    return launch_sweep_boxes(a, B.nbox, B.stride, nparts, st);
 }
 
 hipError_t launch_box_resid_restrict(const BoxSet& B, double h, double* fc, double* phic, hipStream_t st) {

@@ -900,8 +900,13 @@ static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hi
         stats->resid_hist[0] = 1.0;
         stats->hist_len = 1;
     }
+    // fused box sweeps: the residual norm of each cycle's result comes from
+    // the next cycle's first pre-sweep, run speculatively (its output is
+    // taken only if another cycle follows), as on the single-box level
+    const bool spec = H->p.pre_sweeps >= 1 && box_norm_sweep_fits(B);
+    int pre_done = 0;
     while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
-        HIPCHK(launch_box_smooth(B, L0.h, H->p.pre_sweeps, st));
+        HIPCHK(launch_box_smooth(B, L0.h, H->p.pre_sweeps - pre_done, st));
         HIPCHK(launch_box_resid_restrict(B, L0.h, L1.d.f, L1.d.phi, st));
         int rc = vcycle<double>(H, 1, st);
         if (rc) return rc;
@@ -909,7 +914,8 @@ static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hi
         HIPCHK(launch_box_smooth(B, L0.h, H->p.post_sweeps, st));
         ++cycles;
         int np = 0;
-        HIPCHK(launch_box_resid_norm(B, L0.h, H->partials, &np, st));
+        if (spec) HIPCHK(launch_box_sweep_norm(B, L0.h, H->partials, &np, st));
+        else HIPCHK(launch_box_resid_norm(B, L0.h, H->partials, &np, st));
         rc = reduce_to(H, np, kSlotRes, st);
         if (rc) return rc;
         rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
@@ -925,7 +931,13 @@ static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hi
             set_error("non-finite residual during the solve");
             break;
         }
-        if (rel <= H->p.rtol) status = MG_OK;
+        if (rel <= H->p.rtol) {
+            status = MG_OK;
+        } else if (spec && cycles < H->p.max_cycles) {
+            std::swap(B.phi, B.phi2);                // keep the sweep: it is the next cycle's first
+            HIPCHK(launch_box_exchange(B, -1, st));
+            pre_done = 1;
+        }
     }
     HIPCHK(launch_box_gather(B, L0.d.phi, st));
     if (stats) {

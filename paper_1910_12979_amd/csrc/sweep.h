@@ -12,6 +12,7 @@ namespace mg {
 constexpr int kSweepTX = 32;     // smallest tile width (x) of any configuration
 constexpr int kSweepTY = 4;      // smallest tile height (y)
 constexpr int kSweepTZMax = 64;  // largest z-chunk
+constexpr int kMaxPartialRows = 2048;   // rows of a hierarchy's partial-sum buffer
 
 // Tile configurations of the fused sweep (TX x TY columns, TZ planes per
 // chunk); the autotuner picks one per level shape.
@@ -99,9 +100,13 @@ void sweep_geometry(SweepArgs<float>& a, int cfg);
 // stored coefficients (bx, by, bz, cell-aligned low faces in the same
 // layout); the ghosts must hold the neighbouring values, and phi_out's are
 // not written.  hipErrorInvalidValue for a shape it does not cover
-// (sweep_boxes_fit).
+// (sweep_boxes_fit).  nparts != null: also the per-tile partial rows
+// {sum r^2, 0, 0, 0} of the residual of the INPUT over the box interiors
+// into a.partials (*nparts rows, at most kMaxPartialRows, else
+// hipErrorInvalidValue).
 bool sweep_boxes_fit(int bx, int by, int bz);
-hipError_t launch_sweep_boxes(const SweepArgs<double>& a, int nbox, size_t bstride, hipStream_t st);
+int sweep_boxes_tiles(int bx, int by, int bz);      // tiles per box
+hipError_t launch_sweep_boxes(const SweepArgs<double>& a, int nbox, size_t bstride, int* nparts, hipStream_t st);
 
 // Number of tiles (= partial rows) a sweep of this shape launches with cfg.
 int sweep_tiles(int nx, int ny, int nz, int cfg);

@@ -502,8 +502,10 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(kBnd) void 
 // inside its ghosted array (a.nx, a.ny, a.nz: the ghosted dims; a.ox..:
 // the ghost width; a.ex..: the box cells): workgroup tiles enumerate
 // (box, tile), every box with its own pointers.  Stored coefficients, plain
-// input, one sweep.
-template <int TX, int TY>
+// input, one sweep; kOp = kOpSweepNorm also writes the per-tile partial
+// rows of the residual of its input, box b's after the rows of the boxes
+// before it.
+template <int TX, int TY, int kOp>
 __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_waves_per_eu(
     SweepWaves<double, TX, TY, false>::value))) void k_sweep_boxes(SweepArgs<double> a, int tpb, size_t bstride) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -516,7 +518,8 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_wave
     c.bx = a.bx + off;
     c.by = a.by + off;
     c.bz = a.bz + off;
-    sweep_body<double, TX, TY, false, kInPlain, kOpSweep, false, true>(c, t - b * tpb);
+    if (kOp == kOpSweepNorm) c.partials = a.partials + (size_t)b * tpb * kReduceWidth;
+    sweep_body<double, TX, TY, false, kInPlain, kOp, false, true>(c, t - b * tpb);
 }
 
 // Batched form: problem p owns tiles [prefix[p], prefix[p+1]) of the launch.
@@ -800,11 +803,17 @@ void sweep_geometry(SweepArgs<float>& a, int cfg) {
     a.nty = (a.ny + c.ty - 1) / c.ty;
 }
 
+int sweep_boxes_tiles(int bx, int by, int bz) {
+    const bool wide = bx % 64 == 0 && by % 16 == 0;
+    const int TXc = wide ? 64 : 32, TYc = wide ? 16 : 8, tzc = std::min(bz, kSweepTZMax);
+    return ((bx + TXc - 1) / TXc) * ((by + TYc - 1) / TYc) * ((bz + tzc - 1) / tzc);
+}
+
 bool sweep_boxes_fit(int bx, int by, int bz) {
     return bx >= kSweepTX && by >= 8 && bz >= 4 && bx % 2 == 0 && by % 2 == 0 && bz % 2 == 0;
 }
 
-hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, int nbox, size_t bstride, hipStream_t st) {
+hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, int nbox, size_t bstride, int* nparts, hipStream_t st) {
     SweepArgs<double> a = a0;
     if (!sweep_boxes_fit(a.ex, a.ey, a.ez) || a.ox < 2 || a.oy < 2 || a.oz < 2 || a.nx < a.ex + 2 * a.ox ||
         a.ny < a.ey + 2 * a.oy || a.nz < a.ez + 2 * a.oz)
@@ -818,11 +827,23 @@ hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, int nbox, size_t bstr
     const int ntz = (a.ez + a.tz - 1) / a.tz;
     const int tpb = a.ntx * a.nty * ntz;
     const unsigned blocks = (unsigned)tpb * nbox;
+    if (nparts) {
+        if (blocks > (unsigned)kMaxPartialRows) return hipErrorInvalidValue;
+        *nparts = (int)blocks;
+        if (wide)
+            hipLaunchKernelGGL((k_sweep_boxes<64, 16, kOpSweepNorm>), dim3(blocks), dim3((64 / 2 + 2) * (16 + 4)), 0,
+                               st, a, tpb, bstride);
+        else
+            hipLaunchKernelGGL((k_sweep_boxes<32, 8, kOpSweepNorm>), dim3(blocks), dim3((32 / 2 + 2) * (8 + 4)), 0,
+                               st, a, tpb, bstride);
+        return hipGetLastError();
+    }
     if (wide)
-        hipLaunchKernelGGL((k_sweep_boxes<64, 16>), dim3(blocks), dim3((64 / 2 + 2) * (16 + 4)), 0, st, a, tpb,
-                           bstride);
+        hipLaunchKernelGGL((k_sweep_boxes<64, 16, kOpSweep>), dim3(blocks), dim3((64 / 2 + 2) * (16 + 4)), 0, st, a,
+                           tpb, bstride);
     else
-        hipLaunchKernelGGL((k_sweep_boxes<32, 8>), dim3(blocks), dim3((32 / 2 + 2) * (8 + 4)), 0, st, a, tpb, bstride);
+        hipLaunchKernelGGL((k_sweep_boxes<32, 8, kOpSweep>), dim3(blocks), dim3((32 / 2 + 2) * (8 + 4)), 0, st, a,
+                           tpb, bstride);
     return hipGetLastError();
 }
 
