@@ -381,7 +381,7 @@ int mg_set_bottom(mg_handle h, int32_t enable);
  * in another order).  box == NULL or {0, 0, 0} returns to a single box.
  * Needs FP64 precision, periodic or wall sides and two or more levels
  * (MG_ERR_INVALID_ARG otherwise).  The boxes' arrays are allocated here
- * (device memory, freed by mg_destroy or the next mg_set_boxes), 6 x 8
+ * (device memory, freed by mg_destroy or the next mg_set_boxes), 7 x 8
  * bytes per cell of the ghosted boxes; MG_ERR_HIP if that fails.  Not used
  * by the batch or serving front ends. */
 int mg_set_boxes(mg_handle h, const int32_t box[3]);

@@ -8,8 +8,12 @@
 //   phi, phi2  two buffers (the fused sweep is out of place)
 //   f          the right-hand side, ghosts included (the neighbour's value)
 //   cx, cy, cz face coefficients, cell-aligned low faces in the same layout
-// Ghost cells beyond a wall hold phi = f = 0 and coefficient 1 on their
-// faces (finite updates), except the wall face itself, which is 0.
+//   rho        rho of the ghosted box (plane-parallel beta0: the fused sweep
+//              recomputes the coefficients from it, as on the single box)
+// plus beta0 at the centres and low faces of each box's ghosted planes
+// (b0c, b0e: G2 entries per box).  Ghost cells beyond a wall hold
+// phi = f = 0, rho = 1 and coefficient 1 on their faces (finite updates),
+// except the wall face itself, which is 0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,13 +39,18 @@ struct BoxSet {
     double* cx;
     double* cy;
     double* cz;
+    double* rho;
+    double* b0c;
+    double* b0e;
+    int rho_on;       // this solve's coefficients come from rho (plane-parallel beta0)
 };
 
 size_t boxset_cells(const BoxSet& B);
 // phi = phi2 = 0; f and the face arrays of every ghosted box from the global
 // finest-level f and cell-aligned bx, by, bz (periodic images; walls as above).
+// With rho (global, and b0c, b0e) also the boxes' rho and beta0.
 hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx, const double* by, const double* bz,
-                              hipStream_t st);
+                              const double* rho, const double* b0c, const double* b0e, hipStream_t st);
 // Every ghost cell of phi (colour 0 / 1: only that colour's; -1: all) from
 // the box that owns its cell (periodic images; 0 beyond walls).
 hipError_t launch_box_exchange(const BoxSet& B, int colour, hipStream_t st);

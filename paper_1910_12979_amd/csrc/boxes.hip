@@ -116,7 +116,8 @@ __device__ inline int box_global(const BoxSet& B, int d, int o, int L) {
 __global__ __launch_bounds__(kBoxBlock) void k_box_scatter(BoxSet B, const double* __restrict__ f,
                                                            const double* __restrict__ bx,
                                                            const double* __restrict__ by,
-                                                           const double* __restrict__ bz, int gx, int gy) {
+                                                           const double* __restrict__ bz,
+                                                           const double* __restrict__ rho, int gx, int gy) {
     const Patch q = patch_of(blockIdx.x, gx, gy, B.G[2], kCellTX, kCellTY);
     const int i = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y;
     if (i >= B.G[0] || j >= B.G[1]) return;
@@ -135,10 +136,11 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_scatter(BoxSet B, const doubl
     }
     B.phi[e] = 0.0;
     B.phi2[e] = 0.0;
-    double fv = 0.0, cv[3] = {1.0, 1.0, 1.0};
+    double fv = 0.0, cv[3] = {1.0, 1.0, 1.0}, rv = 1.0;
     if (out == 0) {
         const size_t gi = gidx(g[0], g[1], g[2], B.n[0], B.n[1]);
         fv = f[gi];
+        if (rho) rv = rho[gi];
         cv[0] = bx[gi];
         cv[1] = by[gi];
         cv[2] = bz[gi];
@@ -146,9 +148,31 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_scatter(BoxSet B, const doubl
         cv[wall_d] = 0.0;                     // the first cell past a high wall: its low face is the wall
     }
     B.f[e] = fv;
+    if (rho) B.rho[e] = rv;
     B.cx[e] = cv[0];
     B.cy[e] = cv[1];
     B.cz[e] = cv[2];
+}
+
+// beta0 at the centre and low face of every ghosted plane of every box: the
+// global layer (periodic image; beyond a wall the nearest layer or face).
+__global__ void k_box_beta0(BoxSet B, const double* __restrict__ b0c, const double* __restrict__ b0e) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B.nbox * B.G[2]) return;
+    const int b = e / B.G[2], t = e % B.G[2];
+    const int kb = b / (B.nb[0] * B.nb[1]);
+    int z = kb * B.B[2] + t - kG;
+    const int nz = B.n[2];
+    int zc, ze;
+    if (B.per[2]) {
+        zc = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+        ze = zc;
+    } else {
+        zc = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
+        ze = z < 0 ? 0 : (z > nz ? nz : z);
+    }
+    B.b0c[e] = b0c[zc];
+    B.b0e[e] = b0e[ze];
 }
 
 // Halo exchange over the ghost shell of every box: workgroup (chunk,
@@ -346,10 +370,12 @@ hipError_t exchange(const BoxSet& B, int colour, hipStream_t st) {
 size_t boxset_cells(const BoxSet& B) { return (size_t)B.B[0] * B.B[1] * B.B[2] * B.nbox; }
 
 hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx, const double* by, const double* bz,
-                              hipStream_t st) {
+                              const double* rho, const double* b0c, const double* b0e, hipStream_t st) {
     const int gx = cdiv(B.G[0], kCellTX), gy = cdiv(B.G[1], kCellTY);
     const unsigned blocks = (unsigned)gx * gy * B.G[2] * B.nbox;
-    hipLaunchKernelGGL(k_box_scatter, dim3(blocks), dim3(kCellTX, kCellTY), 0, st, B, f, bx, by, bz, gx, gy);
+    hipLaunchKernelGGL(k_box_scatter, dim3(blocks), dim3(kCellTX, kCellTY), 0, st, B, f, bx, by, bz, rho, gx, gy);
+    if (rho)
+        hipLaunchKernelGGL(k_box_beta0, dim3(cdiv(B.nbox * B.G[2], kBoxBlock)), dim3(kBoxBlock), 0, st, B, b0c, b0e);
     return hipGetLastError();
 }
 
@@ -371,7 +397,22 @@ SweepArgs<double> box_sweep_args(const BoxSet& B, double h) {
     a.bx = B.cx;
     a.by = B.cy;
     a.bz = B.cz;
+    if (B.rho_on) {
+        a.rho = B.rho;
+        a.b0c = B.b0c;
+        a.b0e = B.b0e;
+    }
     return a;
+}
+
+BoxGeom box_geom(const BoxSet& B) {
+    BoxGeom g;
+    for (int d = 0; d < 3; ++d) {
+        g.nb[d] = B.nb[d];
+        g.per[d] = B.per[d];
+    }
+    g.b0stride = B.G[2];
+    return g;
 }
 
 hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st) {
@@ -380,7 +421,7 @@ hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st) {
         for (int s = 0; s < nsweeps; ++s) {
             a.phi_in = B.phi;
             a.phi_out = B.phi2;
-            hipError_t e = launch_sweep_boxes(a, B.nbox, B.stride, nullptr, st);
+            hipError_t e = launch_sweep_boxes(a, box_geom(B), B.nbox, B.stride, nullptr, st);
             if (e != hipSuccess) return e;
             std::swap(B.phi, B.phi2);
             e = exchange(B, -1, st);
@@ -409,7 +450,7 @@ hipError_t launch_box_sweep_norm(const BoxSet& B, double h, double* partials, in
     a.phi_in = B.phi;
     a.phi_out = B.phi2;
     a.partials = partials;
-    return launch_sweep_boxes(a, B.nbox, B.stride, nparts, st);
+    return launch_sweep_boxes(a, box_geom(B), B.nbox, B.stride, nparts, st);
 }
 
 hipError_t launch_box_resid_restrict(const BoxSet& B, double h, double* fc, double* phic, hipStream_t st) {

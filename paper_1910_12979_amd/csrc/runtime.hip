@@ -892,7 +892,8 @@ static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hi
     Level& L0 = H->lev[0];
     Level& L1 = H->lev[1];
     BoxSet& B = H->box;                          // the fused smoother swaps its phi buffers
-    HIPCHK(launch_box_scatter(B, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, st));
+    B.rho_on = H->rho.rho != nullptr;            // plane-parallel beta0: coefficients from rho
+    HIPCHK(launch_box_scatter(B, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, H->rho.rho, H->rho.b0c, H->rho.b0e, st));
     int status = H->p.rtol >= 1.0 ? MG_OK : MG_ERR_NOT_CONVERGED;
     int cycles = 0;
     double rel = 1.0;
@@ -1604,11 +1605,12 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
         return MG_ERR_INVALID_ARG;
     }
     const size_t e = (B.stride * B.nbox + 31) / 32 * 32;     // 256-byte aligned sub-arrays
+    const size_t eb = ((size_t)B.G[2] * B.nbox + 31) / 32 * 32;
     if (h->box_mem) HIPCHK(hipFree(h->box_mem));
     h->box_mem = nullptr;
     h->boxes_on = false;
     void* mem = nullptr;
-    HIPCHK(hipMalloc(&mem, 6 * e * sizeof(double)));
+    HIPCHK(hipMalloc(&mem, (7 * e + 2 * eb) * sizeof(double)));
     double* p = static_cast<double*>(mem);
     B.phi = p;
     B.phi2 = p + e;
@@ -1616,6 +1618,9 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
     B.cx = p + 3 * e;
     B.cy = p + 4 * e;
     B.cz = p + 5 * e;
+    B.rho = p + 6 * e;
+    B.b0c = p + 7 * e;
+    B.b0e = B.b0c + eb;
     h->box_mem = mem;
     h->box = B;
     h->boxes_on = true;

@@ -55,6 +55,7 @@ struct SweepArgs {
     const T* dg;               // per-cell boundary diagonal (bnd_diag of every cell)
     int ox, oy, oz;            // launch_sweep_boxes: first cell of a box interior
     int ex, ey, ez;            // launch_sweep_boxes: box cells
+    int wlo[3], whi[3];        // launch_sweep_boxes with rho: wall faces (low faces of these cells), -1 none
 };
 
 template <typename T>
@@ -104,9 +105,18 @@ void sweep_geometry(SweepArgs<float>& a, int cfg);
 // {sum r^2, 0, 0, 0} of the residual of the INPUT over the box interiors
 // into a.partials (*nparts rows, at most kMaxPartialRows, else
 // hipErrorInvalidValue).
+// With a.rho set the coefficients are recomputed from each box's ghosted rho
+// and its own beta0 (a.b0c, a.b0e: g.b0stride entries per box, one per
+// ghosted plane); g places the domain's walls.
+struct BoxGeom {
+    int nb[3];                 // boxes per direction
+    int per[3];                // periodic directions
+    int b0stride;              // beta0 entries per box
+};
 bool sweep_boxes_fit(int bx, int by, int bz);
 int sweep_boxes_tiles(int bx, int by, int bz);      // tiles per box
-hipError_t launch_sweep_boxes(const SweepArgs<double>& a, int nbox, size_t bstride, int* nparts, hipStream_t st);
+hipError_t launch_sweep_boxes(const SweepArgs<double>& a, const BoxGeom& g, int nbox, size_t bstride, int* nparts,
+                              hipStream_t st);
 
 // Number of tiles (= partial rows) a sweep of this shape launches with cfg.
 int sweep_tiles(int nx, int ny, int nz, int cfg);

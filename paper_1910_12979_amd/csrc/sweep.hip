@@ -185,7 +185,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     auto zface = [&](int t, T q_below, T q_here) -> T {
         if (!kRho) return q_here;
         const T b = qdiv((T)sb0e[t - zb], half * (q_below + q_here));
-        return (wrap3(t, nz) == 0 && !a.pz) ? T(0) : b;     // solid wall: no flux
+        const bool wall = kBox ? (t == a.wlo[2] || t == a.whi[2]) : (wrap3(t, nz) == 0 && !a.pz);
+        return wall ? T(0) : b;                              // solid wall: no flux
     };
 
     // ---- prologue
@@ -253,8 +254,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             const int lx = lx0 + c;
             const T cx = qdiv(b0, half * (rl[c] + rc[c]));
             const T cy = qdiv(b0, half * (srho[b][ly > 0 ? ly - 1 : 0][lx] + rc[c]));
-            const bool xwall = (gxw + c == 0) && !a.px;
-            const bool ywall = gyw == 0 && !a.py;
+            const bool xwall = kBox ? (gxw + c == a.wlo[0] || gxw + c == a.whi[0]) : ((gxw + c == 0) && !a.px);
+            const bool ywall = kBox ? (gyw == a.wlo[1] || gyw == a.whi[1]) : (gyw == 0 && !a.py);
             sbx[s][ly][lx] = xwall ? T(0) : cx;
             sby[s][ly][lx] = ywall ? T(0) : cy;
         }
@@ -504,10 +505,13 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(kBnd) void 
 // (box, tile), every box with its own pointers.  Stored coefficients, plain
 // input, one sweep; kOp = kOpSweepNorm also writes the per-tile partial
 // rows of the residual of its input, box b's after the rows of the boxes
-// before it.
-template <int TX, int TY, int kOp>
+// before it.  kRho: coefficients from the boxes' ghosted rho and per-box
+// beta0 (a.b0c, a.b0e: g.b0stride entries per box, indexed by ghosted
+// plane), with the domain's walls placed per box.
+template <int TX, int TY, int kOp, bool kRho>
 __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_waves_per_eu(
-    SweepWaves<double, TX, TY, false>::value))) void k_sweep_boxes(SweepArgs<double> a, int tpb, size_t bstride) {
+    SweepWaves<double, TX, TY, false>::value))) void k_sweep_boxes(SweepArgs<double> a, BoxGeom g, int tpb,
+                                                                   size_t bstride) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int b = t / tpb;
     const size_t off = (size_t)b * bstride;
@@ -515,11 +519,23 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_wave
     c.phi_in = a.phi_in + off;
     c.phi_out = a.phi_out + off;
     c.f = a.f + off;
-    c.bx = a.bx + off;
-    c.by = a.by + off;
-    c.bz = a.bz + off;
+    if (kRho) {
+        c.rho = a.rho + off;
+        c.b0c = a.b0c + (size_t)b * g.b0stride;
+        c.b0e = a.b0e + (size_t)b * g.b0stride;
+        const int bc[3] = {b % g.nb[0], (b / g.nb[0]) % g.nb[1], b / (g.nb[0] * g.nb[1])};
+        const int E[3] = {a.ex, a.ey, a.ez}, O[3] = {a.ox, a.oy, a.oz};
+        for (int d = 0; d < 3; ++d) {
+            c.wlo[d] = (!g.per[d] && bc[d] == 0) ? O[d] : -1;
+            c.whi[d] = (!g.per[d] && bc[d] == g.nb[d] - 1) ? O[d] + E[d] : -1;
+        }
+    } else {
+        c.bx = a.bx + off;
+        c.by = a.by + off;
+        c.bz = a.bz + off;
+    }
     if (kOp == kOpSweepNorm) c.partials = a.partials + (size_t)b * tpb * kReduceWidth;
-    sweep_body<double, TX, TY, false, kInPlain, kOp, false, true>(c, t - b * tpb);
+    sweep_body<double, TX, TY, kRho, kInPlain, kOp, false, true>(c, t - b * tpb);
 }
 
 // Batched form: problem p owns tiles [prefix[p], prefix[p+1]) of the launch.
@@ -813,7 +829,19 @@ bool sweep_boxes_fit(int bx, int by, int bz) {
     return bx >= kSweepTX && by >= 8 && bz >= 4 && bx % 2 == 0 && by % 2 == 0 && bz % 2 == 0;
 }
 
-hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, int nbox, size_t bstride, int* nparts, hipStream_t st) {
+template <int TX, int TY, int kOp>
+void launch_boxes_t(const SweepArgs<double>& a, const BoxGeom& g, int tpb, size_t bstride, unsigned blocks,
+                    hipStream_t st) {
+    if (a.rho)
+        hipLaunchKernelGGL((k_sweep_boxes<TX, TY, kOp, true>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0, st, a,
+                           g, tpb, bstride);
+    else
+        hipLaunchKernelGGL((k_sweep_boxes<TX, TY, kOp, false>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0, st,
+                           a, g, tpb, bstride);
+}
+
+hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, const BoxGeom& g, int nbox, size_t bstride, int* nparts,
+                              hipStream_t st) {
     SweepArgs<double> a = a0;
     if (!sweep_boxes_fit(a.ex, a.ey, a.ez) || a.ox < 2 || a.oy < 2 || a.oz < 2 || a.nx < a.ex + 2 * a.ox ||
         a.ny < a.ey + 2 * a.oy || a.nz < a.ez + 2 * a.oz)
@@ -830,20 +858,12 @@ hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, int nbox, size_t bstr
     if (nparts) {
         if (blocks > (unsigned)kMaxPartialRows) return hipErrorInvalidValue;
         *nparts = (int)blocks;
-        if (wide)
-            hipLaunchKernelGGL((k_sweep_boxes<64, 16, kOpSweepNorm>), dim3(blocks), dim3((64 / 2 + 2) * (16 + 4)), 0,
-                               st, a, tpb, bstride);
-        else
-            hipLaunchKernelGGL((k_sweep_boxes<32, 8, kOpSweepNorm>), dim3(blocks), dim3((32 / 2 + 2) * (8 + 4)), 0,
-                               st, a, tpb, bstride);
+        if (wide) launch_boxes_t<64, 16, kOpSweepNorm>(a, g, tpb, bstride, blocks, st);
+        else launch_boxes_t<32, 8, kOpSweepNorm>(a, g, tpb, bstride, blocks, st);
         return hipGetLastError();
     }
-    if (wide)
-        hipLaunchKernelGGL((k_sweep_boxes<64, 16, kOpSweep>), dim3(blocks), dim3((64 / 2 + 2) * (16 + 4)), 0, st, a,
-                           tpb, bstride);
-    else
-        hipLaunchKernelGGL((k_sweep_boxes<32, 8, kOpSweep>), dim3(blocks), dim3((32 / 2 + 2) * (8 + 4)), 0, st, a,
-                           tpb, bstride);
+    if (wide) launch_boxes_t<64, 16, kOpSweep>(a, g, tpb, bstride, blocks, st);
+    else launch_boxes_t<32, 8, kOpSweep>(a, g, tpb, bstride, blocks, st);
     return hipGetLastError();
 }
 
