@@ -438,7 +438,7 @@ static int smooth(mg_hierarchy* H, int l, int nsweeps, int first, hipStream_t st
         if constexpr (dbl) a.dg = F.dg_d;
         else a.dg = F.dg_s;
         HIPCHK(launch_sweep<T>(a, use_rho, k == 0 ? first : (int)kInPlain,
-                               sweep_config_for(F.nx, F.ny, F.nz, use_rho, dbl), st));
+                               sweep_config_for(F.nx, F.ny, F.nz, use_rho, dbl, l > 0), st));
         std::swap(A->phi, *alt);
     }
     return MG_OK;
@@ -1524,7 +1524,7 @@ int mg_autotune(mg_handle h, int32_t reps, void* stream) {
         float best = 1e30f;
         int best_cfg = -1;
         for (int c = 0; c < kNumSweepCfg && rc == MG_OK; ++c) {
-            if (!sweep_cfg_fits(F.nx, F.ny, c)) continue;
+            if (!sweep_cfg_fits(F.nx, F.ny, c) || (l == 0 && c >= kFirstCoarseCfg)) continue;
             sweep_force_config(c);
             rc = smooth<double>(h, l, 1, kInPlain, st);          // warm
             if (rc) break;
@@ -1539,7 +1539,7 @@ int mg_autotune(mg_handle h, int32_t reps, void* stream) {
                 best_cfg = c;
             }
         }
-        if (best_cfg >= 0) sweep_record_tuned(F.nx, F.ny, F.nz, rho, true, best_cfg);
+        if (best_cfg >= 0) sweep_record_tuned(F.nx, F.ny, F.nz, rho, true, best_cfg, l > 0);
     }
     sweep_force_config(saved);
     hipEventDestroy(e0);
@@ -1646,7 +1646,7 @@ int mg_sweep_config(mg_handle h, int32_t level, int32_t tile[4]) {
     const bool dbl = h->p.precision == MG_FP64;
     const bool fusable = dbl ? sweep_fusable<double>(F.nx, F.ny, F.nz) : sweep_fusable<float>(F.nx, F.ny, F.nz);
     if (level + 1 >= h->nlev || !fusable) return MG_OK;
-    const int c = sweep_config_for(F.nx, F.ny, F.nz, level == 0, dbl);
+    const int c = sweep_config_for(F.nx, F.ny, F.nz, level == 0, dbl, level > 0);
     tile[0] = kSweepCfgs[c].tx;
     tile[1] = kSweepCfgs[c].ty;
     tile[2] = kSweepCfgs[c].tz;

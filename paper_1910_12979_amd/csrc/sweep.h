@@ -19,10 +19,11 @@ constexpr int kMaxPartialRows = 2048;   // rows of a hierarchy's partial-sum buf
 struct SweepCfg {
     int tx, ty, tz;
 };
-constexpr int kNumSweepCfg = 12;
+constexpr int kNumSweepCfg = 14;
+constexpr int kFirstCoarseCfg = 12;     // 4-plane chunks: coarse levels of a single problem
 constexpr SweepCfg kSweepCfgs[kNumSweepCfg] = {
-    {32, 8, 32}, {32, 8, 64}, {64, 8, 32}, {32, 16, 32}, {64, 4, 64},  {32, 4, 64},
-    {32, 8, 16}, {32, 8, 8},  {64, 8, 64}, {64, 16, 32}, {32, 32, 32}, {64, 16, 64}};
+    {32, 8, 32}, {32, 8, 64}, {64, 8, 32}, {32, 16, 32}, {64, 4, 64},  {32, 4, 64}, {32, 8, 16},
+    {32, 8, 8},  {64, 8, 64}, {64, 16, 32}, {32, 32, 32}, {64, 16, 64}, {32, 8, 4}, {32, 4, 4}};
 
 enum { kInZero = 0, kInPlain = 1, kInProlong = 2, kInCorrect = 3 };
 enum { kOpSweep = 0, kOpSweepNorm = 1, kOpResidRestrict = 2, kOpRefine = 3 };
@@ -122,13 +123,15 @@ hipError_t launch_sweep_boxes(const SweepArgs<double>& a, const BoxGeom& g, int 
 int sweep_tiles(int nx, int ny, int nz, int cfg);
 
 // Configuration used for a level of shape nx x ny x nz whose coefficients come
-// from rho (finest level) or are stored, in FP64 (dbl) or FP32: forced,
-// autotuned, else a measured default.  A deterministic function of these, so
+// from rho (finest level) or are stored, in FP64 (dbl) or FP32, as the
+// finest level of a problem or (coarse) a coarser level of a single-problem
+// V-cycle: forced, autotuned, else a measured default.  Configurations
+// kFirstCoarseCfg and up are only chosen for coarse levels.  A deterministic function of these, so
 // a problem's tiles (and the order of its per-tile norm rows) are the same in
 // solo and batched runs.
-int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl = true);
+int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl = true, bool coarse = false);
 bool sweep_cfg_fits(int nx, int ny, int cfg);
-void sweep_record_tuned(int nx, int ny, int nz, bool rho, bool dbl, int cfg);
+void sweep_record_tuned(int nx, int ny, int nz, bool rho, bool dbl, int cfg, bool coarse);
 int sweep_tuned_count();
 // Force one configuration for every level that fits it (-1 restores the default).
 void sweep_force_config(int cfg);

@@ -598,8 +598,9 @@ int g_forced_cfg = -1;    // set by mg_tune_sweep (-1: per-shape choice)
 
 // Autotuned choices, keyed by level shape and coefficient source.
 struct TuneKey {
-    int nx, ny, nz, rho, dbl;
+    int nx, ny, nz, rho, dbl, coarse;
     bool operator<(const TuneKey& o) const {
+        if (coarse != o.coarse) return coarse < o.coarse;
         if (nx != o.nx) return nx < o.nx;
         if (ny != o.ny) return ny < o.ny;
         if (nz != o.nz) return nz < o.nz;
@@ -619,9 +620,9 @@ void sweep_force_config(int cfg) {
     ++g_tune_epoch;
 }
 
-void sweep_record_tuned(int nx, int ny, int nz, bool rho, bool dbl, int cfg) {
+void sweep_record_tuned(int nx, int ny, int nz, bool rho, bool dbl, int cfg, bool coarse) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[TuneKey{nx, ny, nz, rho ? 1 : 0, dbl ? 1 : 0}] = cfg;
+    g_tuned[TuneKey{nx, ny, nz, rho ? 1 : 0, dbl ? 1 : 0, coarse ? 1 : 0}] = cfg;
     ++g_tune_epoch;
 }
 
@@ -639,11 +640,11 @@ bool sweep_cfg_fits(int nx, int ny, int cfg) {
     return cfg >= 0 && cfg < kNumSweepCfg && nx >= kSweepCfgs[cfg].tx && ny >= kSweepCfgs[cfg].ty;
 }
 
-int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl) {
+int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl, bool coarse) {
     if (g_forced_cfg >= 0 && sweep_cfg_fits(nx, ny, g_forced_cfg)) return g_forced_cfg;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find(TuneKey{nx, ny, nz, rho ? 1 : 0, dbl ? 1 : 0});
+        auto it = g_tuned.find(TuneKey{nx, ny, nz, rho ? 1 : 0, dbl ? 1 : 0, coarse ? 1 : 0});
         if (it != g_tuned.end()) return it->second;
     }
     // untuned shapes: choices measured on MI355X for cubic levels.  On the
@@ -651,7 +652,11 @@ int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl) {
     // redundant red updates is a third lower than with 64x8 tiles): FP64
     // with 64-plane chunks (one 132 KB workgroup per CU), FP32 with 32-plane
     // chunks; then 32x8 tiles with shallower z-chunks so small levels still
-    // fill the 256 CUs.
+    // fill the 256 CUs.  Coarse levels of a single-problem V-cycle go
+    // shallower still (a 64^3 level in 4-plane chunks, a 32^3 level in 32x4
+    // tiles of 4 planes: there the march through the planes, not the bytes,
+    // sets the time); batches, which fill the CUs with many problems, keep
+    // the deeper chunks.
     const double cells = (double)nx * ny * nz;
     if (nx >= 64 && ny >= 16 && cells >= 8.0e6) {
         if (dbl && nz >= 64) return 11;
@@ -660,8 +665,10 @@ int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl) {
     if (nx >= 64 && cells >= 8.0e6) return 2;
     if (nx >= 32 && ny >= 8) {
         if (cells >= 1.0e6) return 6;
-        return 7;
+        if (!coarse) return 7;
+        if (cells >= 1.0e5) return 12;
     }
+    if (coarse && nx >= 32 && ny >= 4 && cells < 1.0e5) return 13;
     return 5;
 }
 
@@ -685,6 +692,7 @@ hipError_t launch_sweep(const SweepArgs<T>& a, bool use_rho, int in_mode, int cf
         case 3: return launch_mode<T, 32, 16>(a, use_rho, in_mode, c.tz, st);
         case 4: return launch_mode<T, 64, 4>(a, use_rho, in_mode, c.tz, st);
         case 5: return launch_mode<T, 32, 4>(a, use_rho, in_mode, c.tz, st);
+        case 13: return launch_mode<T, 32, 4>(a, use_rho, in_mode, c.tz, st);
         default: return launch_mode<T, 32, 8>(a, use_rho, in_mode, c.tz, st);
     }
 }
@@ -704,6 +712,7 @@ hipError_t launch_sweep_norm_t(const SweepArgs<double>& a, int cfg, int* nparts,
         case 3: return launch_t<double, 32, 16, kRho, kInPlain, N>(a, c.tz, st, nparts);
         case 4: return launch_t<double, 64, 4, kRho, kInPlain, N>(a, c.tz, st, nparts);
         case 5: return launch_t<double, 32, 4, kRho, kInPlain, N>(a, c.tz, st, nparts);
+        case 13: return launch_t<double, 32, 4, kRho, kInPlain, N>(a, c.tz, st, nparts);
         default: return launch_t<double, 32, 8, kRho, kInPlain, N>(a, c.tz, st, nparts);
     }
 }
@@ -729,6 +738,7 @@ hipError_t launch_resid_restrict_tiled_t(const SweepArgs<T>& a, int cfg, hipStre
         case 3: return launch_t<T, 32, 16, kRho, kInPlain, R>(a, c.tz, st);
         case 4: return launch_t<T, 64, 4, kRho, kInPlain, R>(a, c.tz, st);
         case 5: return launch_t<T, 32, 4, kRho, kInPlain, R>(a, c.tz, st);
+        case 13: return launch_t<T, 32, 4, kRho, kInPlain, R>(a, c.tz, st);
         default: return launch_t<T, 32, 8, kRho, kInPlain, R>(a, c.tz, st);
     }
 }
@@ -756,6 +766,7 @@ hipError_t launch_refine_t(const SweepArgs<double>& a, int cfg, int* nparts, hip
         case 3: return launch_t<double, 32, 16, kRho, I, R>(a, c.tz, st, nparts);
         case 4: return launch_t<double, 64, 4, kRho, I, R>(a, c.tz, st, nparts);
         case 5: return launch_t<double, 32, 4, kRho, I, R>(a, c.tz, st, nparts);
+        case 13: return launch_t<double, 32, 4, kRho, I, R>(a, c.tz, st, nparts);
         default: return launch_t<double, 32, 8, kRho, I, R>(a, c.tz, st, nparts);
     }
 }

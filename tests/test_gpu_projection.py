@@ -259,7 +259,7 @@ def test_every_tile_config_gives_the_same_sweep(mp):
     assert rel(base[0], OH.get(0, "phi")) <= 1e-13
     assert rel(base[1], OH.get(1, "f")) <= 1e-13
     try:
-        for cfg in range(12):
+        for cfg in range(14):
             mp.mg_tune_sweep(cfg)
             got = run()
             for a, b in zip(got, base):
