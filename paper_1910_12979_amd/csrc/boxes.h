@@ -46,17 +46,20 @@ struct BoxSet {
 };
 
 size_t boxset_cells(const BoxSet& B);
-// phi = phi2 = 0; f and the face arrays of every ghosted box from the global
-// finest-level f and cell-aligned bx, by, bz (periodic images; walls as above).
+// phi = 0 (phi2 is written by a sweep before it is read); f of every
+// ghosted box from the global finest-level f, and with coeffs its face
+// arrays from the cell-aligned bx, by, bz (periodic images; walls as above).
 // With rho (global, and b0c, b0e) also the boxes' rho and beta0.
 hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx, const double* by, const double* bz,
-                              const double* rho, const double* b0c, const double* b0e, hipStream_t st);
+                              const double* rho, const double* b0c, const double* b0e, bool coeffs, hipStream_t st);
 // Every ghost cell of phi (colour 0 / 1: only that colour's; -1: all) from
 // the box that owns its cell (periodic images; 0 beyond walls).
 hipError_t launch_box_exchange(const BoxSet& B, int colour, hipStream_t st);
 // nsweeps red-black sweeps, each followed by a halo exchange (per-colour
-// smoother: after each colour).  Fused sweeps swap B.phi and B.phi2.
-hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st);
+// smoother: after each colour).  Fused sweeps swap B.phi and B.phi2.  With
+// phic (the single coarser level's phi) the sweeps start from phi + P phic:
+// folded into the first fused sweep's load, else a prolongation launch.
+hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st, const double* phic = nullptr);
 // Speculative first sweep of the next cycle (fused smoother, at most
 // kMaxPartialRows tiles in all: box_norm_sweep_fits): phi2 = RBGS(phi)
 // without swapping, and per tile the partial rows {sum r^2, 0, 0, 0} of the

@@ -117,7 +117,8 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_scatter(BoxSet B, const doubl
                                                            const double* __restrict__ bx,
                                                            const double* __restrict__ by,
                                                            const double* __restrict__ bz,
-                                                           const double* __restrict__ rho, int gx, int gy) {
+                                                           const double* __restrict__ rho, int coeffs, int gx,
+                                                           int gy) {
     const Patch q = patch_of(blockIdx.x, gx, gy, B.G[2], kCellTX, kCellTY);
     const int i = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y;
     if (i >= B.G[0] || j >= B.G[1]) return;
@@ -135,7 +136,6 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_scatter(BoxSet B, const doubl
         }
     }
     B.phi[e] = 0.0;
-    B.phi2[e] = 0.0;
     double fv = 0.0, cv[3] = {1.0, 1.0, 1.0}, rv = 1.0;
     if (out == 0) {
         const size_t gi = gidx(g[0], g[1], g[2], B.n[0], B.n[1]);
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_scatter(BoxSet B, const doubl
     }
     B.f[e] = fv;
     if (rho) B.rho[e] = rv;
+    if (!coeffs) return;
     B.cx[e] = cv[0];
     B.cy[e] = cv[1];
     B.cz[e] = cv[2];
@@ -370,10 +371,11 @@ hipError_t exchange(const BoxSet& B, int colour, hipStream_t st) {
 size_t boxset_cells(const BoxSet& B) { return (size_t)B.B[0] * B.B[1] * B.B[2] * B.nbox; }
 
 hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx, const double* by, const double* bz,
-                              const double* rho, const double* b0c, const double* b0e, hipStream_t st) {
+                              const double* rho, const double* b0c, const double* b0e, bool coeffs, hipStream_t st) {
     const int gx = cdiv(B.G[0], kCellTX), gy = cdiv(B.G[1], kCellTY);
     const unsigned blocks = (unsigned)gx * gy * B.G[2] * B.nbox;
-    hipLaunchKernelGGL(k_box_scatter, dim3(blocks), dim3(kCellTX, kCellTY), 0, st, B, f, bx, by, bz, rho, gx, gy);
+    hipLaunchKernelGGL(k_box_scatter, dim3(blocks), dim3(kCellTX, kCellTY), 0, st, B, f, bx, by, bz, rho,
+                       coeffs ? 1 : 0, gx, gy);
     if (rho)
         hipLaunchKernelGGL(k_box_beta0, dim3(cdiv(B.nbox * B.G[2], kBoxBlock)), dim3(kBoxBlock), 0, st, B, b0c, b0e);
     return hipGetLastError();
@@ -415,13 +417,19 @@ BoxGeom box_geom(const BoxSet& B) {
     return g;
 }
 
-hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st) {
+hipError_t launch_box_smooth(BoxSet& B, double h, int nsweeps, hipStream_t st, const double* phic) {
+    if (phic && !(B.fused && nsweeps >= 1)) {
+        hipError_t e = launch_box_prolong(B, phic, st);
+        if (e != hipSuccess) return e;
+        phic = nullptr;
+    }
     if (B.fused) {
         SweepArgs<double> a = box_sweep_args(B, h);
+        a.phic = phic;
         for (int s = 0; s < nsweeps; ++s) {
             a.phi_in = B.phi;
             a.phi_out = B.phi2;
-            hipError_t e = launch_sweep_boxes(a, box_geom(B), B.nbox, B.stride, nullptr, st);
+            hipError_t e = launch_sweep_boxes(a, box_geom(B), B.nbox, B.stride, nullptr, st, s == 0 && phic);
             if (e != hipSuccess) return e;
             std::swap(B.phi, B.phi2);
             e = exchange(B, -1, st);
@@ -454,6 +462,13 @@ hipError_t launch_box_sweep_norm(const BoxSet& B, double h, double* partials, in
 }
 
 hipError_t launch_box_resid_restrict(const BoxSet& B, double h, double* fc, double* phic, hipStream_t st) {
+    if (B.fused) {                            // the fused sweep's tiles, no sweep
+        SweepArgs<double> a = box_sweep_args(B, h);
+        a.phi_in = B.phi;
+        a.fc = fc;
+        a.phic_out = phic;
+        return launch_sweep_boxes(a, box_geom(B), B.nbox, B.stride, nullptr, st, false, true);
+    }
     const int gx = cdiv(B.B[0], kRrTX), gy = cdiv(B.B[1], kRrTY);
     const unsigned blocks = (unsigned)gx * gy * (B.B[2] / 2) * B.nbox;
     hipLaunchKernelGGL(k_box_resid_restrict, dim3(blocks), dim3(kRrTX, kRrTY, 2), 0, st, B, h * h, fc, phic, gx, gy);

@@ -893,7 +893,11 @@ static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hi
     Level& L1 = H->lev[1];
     BoxSet& B = H->box;                          // the fused smoother swaps its phi buffers
     B.rho_on = H->rho.rho != nullptr;            // plane-parallel beta0: coefficients from rho
-    HIPCHK(launch_box_scatter(B, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, H->rho.rho, H->rho.b0c, H->rho.b0e, st));
+    const bool spec = H->p.pre_sweeps >= 1 && box_norm_sweep_fits(B);
+    // the stored face arrays serve the per-colour smoother, the per-cell
+    // residual norm and solves without rho
+    const bool coeffs = !(B.rho_on && B.fused && spec);
+    HIPCHK(launch_box_scatter(B, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, H->rho.rho, H->rho.b0c, H->rho.b0e, coeffs, st));
     int status = H->p.rtol >= 1.0 ? MG_OK : MG_ERR_NOT_CONVERGED;
     int cycles = 0;
     double rel = 1.0;
@@ -904,15 +908,13 @@ static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hi
     // fused box sweeps: the residual norm of each cycle's result comes from
     // the next cycle's first pre-sweep, run speculatively (its output is
     // taken only if another cycle follows), as on the single-box level
-    const bool spec = H->p.pre_sweeps >= 1 && box_norm_sweep_fits(B);
     int pre_done = 0;
     while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
         HIPCHK(launch_box_smooth(B, L0.h, H->p.pre_sweeps - pre_done, st));
         HIPCHK(launch_box_resid_restrict(B, L0.h, L1.d.f, L1.d.phi, st));
         int rc = vcycle<double>(H, 1, st);
         if (rc) return rc;
-        HIPCHK(launch_box_prolong(B, L1.d.phi, st));
-        HIPCHK(launch_box_smooth(B, L0.h, H->p.post_sweeps, st));
+        HIPCHK(launch_box_smooth(B, L0.h, H->p.post_sweeps, st, L1.d.phi));   // prolongation first
         ++cycles;
         int np = 0;
         if (spec) HIPCHK(launch_box_sweep_norm(B, L0.h, H->partials, &np, st));

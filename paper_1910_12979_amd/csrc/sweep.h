@@ -57,6 +57,7 @@ struct SweepArgs {
     int ox, oy, oz;            // launch_sweep_boxes: first cell of a box interior
     int ex, ey, ez;            // launch_sweep_boxes: box cells
     int wlo[3], whi[3];        // launch_sweep_boxes with rho: wall faces (low faces of these cells), -1 none
+    int go[3], gn[3], gp[3];   // launch_sweep_boxes with prolongation: box origin, domain cells, periodic
 };
 
 template <typename T>
@@ -116,8 +117,13 @@ struct BoxGeom {
 };
 bool sweep_boxes_fit(int bx, int by, int bz);
 int sweep_boxes_tiles(int bx, int by, int bz);      // tiles per box
+// prolong: the input is phi_in + P a.phic (a.phic: the domain's single
+// coarser level), the prolongation folded into the load as on a single box.
+// restrict_only: no sweep; the residual of phi_in restricted into the
+// domain's single coarser level (a.fc, a.phic_out = 0), as the tiled
+// single-box residual + restriction does.
 hipError_t launch_sweep_boxes(const SweepArgs<double>& a, const BoxGeom& g, int nbox, size_t bstride, int* nparts,
-                              hipStream_t st);
+                              hipStream_t st, bool prolong = false, bool restrict_only = false);
 
 // Number of tiles (= partial rows) a sweep of this shape launches with cfg.
 int sweep_tiles(int nx, int ny, int nz, int cfg);

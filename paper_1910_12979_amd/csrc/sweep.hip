@@ -148,8 +148,26 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
              (gyw == ny - 1 && a.bnd.s[3]);
     auto zbnd = [&](int tw) -> bool { return (tw == 0 && a.bnd.s[4]) || (tw == nz - 1 && a.bnd.s[5]); };
 
-    size_t ccol = 0;
-    if (kIn == kInProlong) ccol = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
+    // kInProlong: the parent cell on the next coarser level.  In a box
+    // (kBox) the parent of a ghosted cell is that of its global cell (the
+    // periodic image; beyond a wall the nearest cell, whose value meets a
+    // zero wall coefficient), on the single coarser level of the domain.
+    auto gwrap = [](int g, int n, int per) -> int {
+        if (g < 0) return per ? g + n : 0;
+        if (g >= n) return per ? g - n : n - 1;
+        return g;
+    };
+    size_t ccol = 0, cplane = (size_t)(nx >> 1) * (ny >> 1);
+    if (kIn == kInProlong) {
+        if (kBox) {
+            const int X = gwrap(a.go[0] + gxw - ox, a.gn[0], a.gp[0]);
+            const int Y = gwrap(a.go[1] + gyw - oy, a.gn[1], a.gp[1]);
+            ccol = (size_t)(Y >> 1) * (a.gn[0] >> 1) + (X >> 1);
+            cplane = (size_t)(a.gn[0] >> 1) * (a.gn[1] >> 1);
+        } else {
+            ccol = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
+        }
+    }
 
     auto load_phi = [&](int t, T& v0, T& v1) {
         if (kIn == kInZero) {
@@ -160,7 +178,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         int tw = wrap3(t, nz);
         ld2(a.phi_in + (size_t)tw * plane + col, v0, v1);
         if (kIn == kInProlong) {
-            T c = a.phic[(size_t)(tw >> 1) * (plane >> 2) + ccol];
+            const int Z = kBox ? gwrap(a.go[2] + tw - oz, a.gn[2], a.gp[2]) : tw;
+            T c = a.phic[(size_t)(Z >> 1) * (kBox ? cplane : (plane >> 2)) + ccol];
             v0 = v0 + c;
             v1 = v1 + c;
         }
@@ -310,8 +329,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     // 8 children in the reference order (x fastest, then y, then z)
     T racc = T(0);
     const bool rrow = (ly & 1) == 0;           // gy = y0 - 2 + ly is even
-    const size_t ccols = (size_t)(nx >> 1) * (ny >> 1);
-    const size_t cc = (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
+    // the coarse cell (kBox: on the domain's single coarser level; only box
+    // interior cells restrict, so no wrap is needed)
+    const size_t ccols = kBox ? (size_t)(a.gn[0] >> 1) * (a.gn[1] >> 1) : (size_t)(nx >> 1) * (ny >> 1);
+    const size_t cc = kBox ? (size_t)((a.go[1] + gyw - oy) >> 1) * (a.gn[0] >> 1) + ((a.go[0] + gxw - ox) >> 1)
+                           : (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
     auto step = [&](int t, Fly& X) {
         // 0. slide the z window, taking in the set issued two steps ago:
         //    phi[t+1], rho[t+2] (or bz[t+2]), f[t], bx/by[t+1]; then re-issue
@@ -407,7 +429,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             racc = racc + sR[pb][ly + 1][lx0];
             racc = racc + sR[pb][ly + 1][lx0 + 1];
             if (((tb - z0) & 1) == 1) {
-                const size_t ci = (size_t)(tb >> 1) * ccols + cc;
+                const size_t ci = (size_t)((kBox ? a.go[2] + tb - oz : tb) >> 1) * ccols + cc;
                 a.fc[ci] = T(0.125) * racc;
                 a.phic_out[ci] = T(0);
             }
@@ -508,7 +530,7 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(kBnd) void 
 // before it.  kRho: coefficients from the boxes' ghosted rho and per-box
 // beta0 (a.b0c, a.b0e: g.b0stride entries per box, indexed by ghosted
 // plane), with the domain's walls placed per box.
-template <int TX, int TY, int kOp, bool kRho>
+template <int TX, int TY, int kOp, bool kRho, int kIn>
 __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_waves_per_eu(
     SweepWaves<double, TX, TY, false>::value))) void k_sweep_boxes(SweepArgs<double> a, BoxGeom g, int tpb,
                                                                    size_t bstride) {
@@ -519,12 +541,19 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_wave
     c.phi_in = a.phi_in + off;
     c.phi_out = a.phi_out + off;
     c.f = a.f + off;
+    const int bc[3] = {b % g.nb[0], (b / g.nb[0]) % g.nb[1], b / (g.nb[0] * g.nb[1])};
+    const int E[3] = {a.ex, a.ey, a.ez}, O[3] = {a.ox, a.oy, a.oz};
+    if (kIn == kInProlong || kOp == kOpResidRestrict) {
+        for (int d = 0; d < 3; ++d) {
+            c.go[d] = bc[d] * E[d];
+            c.gn[d] = g.nb[d] * E[d];
+            c.gp[d] = g.per[d];
+        }
+    }
     if (kRho) {
         c.rho = a.rho + off;
         c.b0c = a.b0c + (size_t)b * g.b0stride;
         c.b0e = a.b0e + (size_t)b * g.b0stride;
-        const int bc[3] = {b % g.nb[0], (b / g.nb[0]) % g.nb[1], b / (g.nb[0] * g.nb[1])};
-        const int E[3] = {a.ex, a.ey, a.ez}, O[3] = {a.ox, a.oy, a.oz};
         for (int d = 0; d < 3; ++d) {
             c.wlo[d] = (!g.per[d] && bc[d] == 0) ? O[d] : -1;
             c.whi[d] = (!g.per[d] && bc[d] == g.nb[d] - 1) ? O[d] + E[d] : -1;
@@ -535,7 +564,7 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_wave
         c.bz = a.bz + off;
     }
     if (kOp == kOpSweepNorm) c.partials = a.partials + (size_t)b * tpb * kReduceWidth;
-    sweep_body<double, TX, TY, kRho, kInPlain, kOp, false, true>(c, t - b * tpb);
+    sweep_body<double, TX, TY, kRho, kIn, kOp, false, true>(c, t - b * tpb);
 }
 
 // Batched form: problem p owns tiles [prefix[p], prefix[p+1]) of the launch.
@@ -840,19 +869,19 @@ bool sweep_boxes_fit(int bx, int by, int bz) {
     return bx >= kSweepTX && by >= 8 && bz >= 4 && bx % 2 == 0 && by % 2 == 0 && bz % 2 == 0;
 }
 
-template <int TX, int TY, int kOp>
+template <int TX, int TY, int kOp, int kIn>
 void launch_boxes_t(const SweepArgs<double>& a, const BoxGeom& g, int tpb, size_t bstride, unsigned blocks,
                     hipStream_t st) {
     if (a.rho)
-        hipLaunchKernelGGL((k_sweep_boxes<TX, TY, kOp, true>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0, st, a,
-                           g, tpb, bstride);
+        hipLaunchKernelGGL((k_sweep_boxes<TX, TY, kOp, true, kIn>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0,
+                           st, a, g, tpb, bstride);
     else
-        hipLaunchKernelGGL((k_sweep_boxes<TX, TY, kOp, false>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0, st,
-                           a, g, tpb, bstride);
+        hipLaunchKernelGGL((k_sweep_boxes<TX, TY, kOp, false, kIn>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0,
+                           st, a, g, tpb, bstride);
 }
 
 hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, const BoxGeom& g, int nbox, size_t bstride, int* nparts,
-                              hipStream_t st) {
+                              hipStream_t st, bool prolong, bool restrict_only) {
     SweepArgs<double> a = a0;
     if (!sweep_boxes_fit(a.ex, a.ey, a.ez) || a.ox < 2 || a.oy < 2 || a.oz < 2 || a.nx < a.ex + 2 * a.ox ||
         a.ny < a.ey + 2 * a.oy || a.nz < a.ez + 2 * a.oz)
@@ -867,14 +896,25 @@ hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, const BoxGeom& g, int
     const int tpb = a.ntx * a.nty * ntz;
     const unsigned blocks = (unsigned)tpb * nbox;
     if (nparts) {
-        if (blocks > (unsigned)kMaxPartialRows) return hipErrorInvalidValue;
+        if (blocks > (unsigned)kMaxPartialRows || prolong) return hipErrorInvalidValue;
         *nparts = (int)blocks;
-        if (wide) launch_boxes_t<64, 16, kOpSweepNorm>(a, g, tpb, bstride, blocks, st);
-        else launch_boxes_t<32, 8, kOpSweepNorm>(a, g, tpb, bstride, blocks, st);
+        if (wide) launch_boxes_t<64, 16, kOpSweepNorm, kInPlain>(a, g, tpb, bstride, blocks, st);
+        else launch_boxes_t<32, 8, kOpSweepNorm, kInPlain>(a, g, tpb, bstride, blocks, st);
         return hipGetLastError();
     }
-    if (wide) launch_boxes_t<64, 16, kOpSweep>(a, g, tpb, bstride, blocks, st);
-    else launch_boxes_t<32, 8, kOpSweep>(a, g, tpb, bstride, blocks, st);
+    if (restrict_only) {
+        if (prolong || nparts) return hipErrorInvalidValue;
+        if (wide) launch_boxes_t<64, 16, kOpResidRestrict, kInPlain>(a, g, tpb, bstride, blocks, st);
+        else launch_boxes_t<32, 8, kOpResidRestrict, kInPlain>(a, g, tpb, bstride, blocks, st);
+        return hipGetLastError();
+    }
+    if (prolong) {
+        if (wide) launch_boxes_t<64, 16, kOpSweep, kInProlong>(a, g, tpb, bstride, blocks, st);
+        else launch_boxes_t<32, 8, kOpSweep, kInProlong>(a, g, tpb, bstride, blocks, st);
+        return hipGetLastError();
+    }
+    if (wide) launch_boxes_t<64, 16, kOpSweep, kInPlain>(a, g, tpb, bstride, blocks, st);
+    else launch_boxes_t<32, 8, kOpSweep, kInPlain>(a, g, tpb, bstride, blocks, st);
     return hipGetLastError();
 }
 
