@@ -14,6 +14,7 @@
 // (single problem, batched) evaluates them.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "dense.h"
@@ -61,7 +62,7 @@ __device__ inline size_t cidx(int i, int j, int k, int nx, int ny) {
 // summed, [2] max.  Fixed tree order.  Thread 0 writes the row.
 __device__ void block_reduce_row(double v0, double v1, double v2, double v3, double* out) {
     __shared__ double sh[4][kBlock];
-    int t = threadIdx.x;
+    int t = threadIdx.y * blockDim.x + threadIdx.x;      // kBlock threads, 1-D or 2-D
     sh[0][t] = v0;
     sh[1][t] = v1;
     sh[2][t] = v2;
@@ -87,9 +88,11 @@ __device__ void block_reduce_row(double v0, double v1, double v2, double v3, dou
 __device__ inline bool finite_d(double x) { return isfinite(x); }
 
 // ---------------------------------------------------------------------------
-// Level-0 face coefficients (+ optional right-hand side).  Grid-stride over
-// cells so the number of partial rows stays small.
+// Level-0 face coefficients (+ optional right-hand side).  64 x 4 threads per
+// workgroup over (x, y); the workgroups stride over x, y and the planes so
+// the number of partial rows stays small, with no per-cell index division.
 // ---------------------------------------------------------------------------
+constexpr int kPtX = 64, kPtY = 4;
 template <bool kRhs>
 __global__ __launch_bounds__(kBlock) void k_coeff_rhs(
     int nx, int ny, int nz, int px, int py, int pz, double h, const double* __restrict__ rho,
@@ -97,12 +100,11 @@ __global__ __launch_bounds__(kBlock) void k_coeff_rhs(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     double* __restrict__ bx, double* __restrict__ by, double* __restrict__ bz,
     double* __restrict__ f, double* __restrict__ partials, const double* __restrict__ w0) {
-    const size_t N = (size_t)nx * ny * nz;
     double sf = 0.0, saf = 0.0, bad = 0.0, nonfin = 0.0;
-    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock) {
-        int i = (int)(c % nx);
-        int j = (int)((c / nx) % ny);
-        int k = (int)(c / ((size_t)nx * ny));
+    for (int k = blockIdx.z; k < nz; k += gridDim.z)
+    for (int j = blockIdx.y * kPtY + threadIdx.y; j < ny; j += gridDim.y * kPtY)
+    for (int i = blockIdx.x * kPtX + threadIdx.x; i < nx; i += gridDim.x * kPtX) {
+        const size_t c = cidx(i, j, k, nx, ny);
         double rc = rho[c];
         double bk = b0c[k];
         double bek = b0e[k];
@@ -155,7 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_coeff_rhs(
             saf += fabs(fc);
         }
     }
-    block_reduce_row(sf, saf, bad, nonfin, partials + (size_t)blockIdx.x * kReduceWidth);
+    const int row = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_reduce_row(sf, saf, bad, nonfin, partials + (size_t)row * kReduceWidth);
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partials, int nparts,
@@ -832,25 +835,33 @@ inline int stream_blocks(size_t n) {
 // ============================================================================
 int num_blocks_for_partials(const Shape& s) { return partial_blocks(s.N()); }
 
+// Grid of a point loop over a level: at most kMaxPartialBlocks workgroups.
+static dim3 point_grid(const Shape& s) {
+    const int gx = std::min((s.nx + kPtX - 1) / kPtX, kMaxPartialBlocks);
+    const int gy = std::max(1, std::min((s.ny + kPtY - 1) / kPtY, kMaxPartialBlocks / gx));
+    const int gz = std::max(1, std::min(s.nz, kMaxPartialBlocks / (gx * gy)));
+    return dim3(gx, gy, gz);
+}
+
 hipError_t launch_coeff_rhs(const Shape& s, int px, int py, int pz, double h, const double* rho,
                             const double* b0c, const double* b0e, const double* S, const double* u,
                             const double* v, const double* w, double* bx, double* by, double* bz,
                             double* f, double* partials, int* nparts, hipStream_t st, const double* w0) {
-    int nb = partial_blocks(s.N());
-    hipLaunchKernelGGL(k_coeff_rhs<true>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, px, py, pz, h,
+    const dim3 g = point_grid(s);
+    hipLaunchKernelGGL(k_coeff_rhs<true>, g, dim3(kPtX, kPtY), 0, st, s.nx, s.ny, s.nz, px, py, pz, h,
                        rho, b0c, b0e, S, u, v, w, bx, by, bz, f, partials, w0);
-    *nparts = nb;
+    *nparts = (int)(g.x * g.y * g.z);
     return hipGetLastError();
 }
 
 hipError_t launch_coeff(const Shape& s, int px, int py, int pz, const double* rho, const double* b0c,
                         const double* b0e, double* bx, double* by, double* bz, double* partials,
                         int* nparts, hipStream_t st) {
-    int nb = partial_blocks(s.N());
-    hipLaunchKernelGGL(k_coeff_rhs<false>, dim3(nb), dim3(kBlock), 0, st, s.nx, s.ny, s.nz, px, py, pz, 1.0,
+    const dim3 g = point_grid(s);
+    hipLaunchKernelGGL(k_coeff_rhs<false>, g, dim3(kPtX, kPtY), 0, st, s.nx, s.ny, s.nz, px, py, pz, 1.0,
                        rho, b0c, b0e, nullptr, nullptr, nullptr, nullptr, bx, by, bz, nullptr, partials,
                        (const double*)nullptr);
-    *nparts = nb;
+    *nparts = (int)(g.x * g.y * g.z);
     return hipGetLastError();
 }
 
