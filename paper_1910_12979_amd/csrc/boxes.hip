@@ -1,21 +1,25 @@
 // Multi-box finest level for gfx950: the domain is tiled by a grid of equal
-// boxes, each holding its own phi (two buffers), f and face coefficients
-// with a two-cell ghost shell.  Smoothing, residual + restriction,
-// prolongation and the residual norm of the finest level run box by box (all
-// boxes in one launch); a halo exchange refills every ghost cell from the
-// box that owns it (or the periodic image, or 0 beyond a wall) after each
-// sweep and after the prolongation.  Levels 1 and coarser are the
-// hierarchy's single-box levels.  This is the layout of a domain whose boxes
-// are spread over several devices (the exchange then becomes a message),
-// kept on one GPU.
+// boxes, each holding its own phi (two buffers), f, rho and face
+// coefficients with a two-cell ghost shell.  Smoothing, residual +
+// restriction, prolongation and the residual norm of the finest level run
+// box by box (all boxes in one launch); a halo exchange refills every ghost
+// cell from the box that owns it (or the periodic image, or 0 beyond a
+// wall) after each sweep and after an explicit prolongation.  Levels 1 and
+// coarser are the hierarchy's single-box levels.  This is the layout of a
+// domain whose boxes are spread over several devices (the exchange then
+// becomes a message), kept on one GPU.
 //
-// Smoother: boxes of at least 32 x 8 x 4 cells use the fused out-of-place
-// sweep of the single-box finest level on each box interior (its red update
+// Boxes of at least 32 x 8 x 4 cells run the single-box finest-level
+// kernels on each box interior: the fused out-of-place sweep (its red update
 // on a ring around each tile reads the ghost shell, which is why the shell
-// is two cells deep and holds f and the coefficients too); smaller boxes use
-// one launch per colour with an exchange of that colour in between.  Either
-// way every cell update is the single-box expression, so only the order in
-// which the residual norm is summed differs from the single-box solve.
+// is two cells deep and holds f, rho and the coefficients too), with the
+// coefficients recomputed from rho for a plane-parallel beta0, the residual
+// norm folded into a speculative sweep, the prolongation folded into the
+// first post-sweep's load, and the tiled residual + restriction.  Smaller
+// boxes use the per-cell kernels below, one launch per colour with an
+// exchange of that colour in between.  Either way every cell update is the
+// single-box expression, so only the order in which the residual norm and
+// the restriction are summed can differ from the single-box solve.
 //
 // Launch shape of the cell kernels: 256-thread workgroups over 2-D (x, y)
 // patches of one plane of one box; the flat workgroup index is split into
