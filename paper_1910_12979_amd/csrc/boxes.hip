@@ -214,17 +214,24 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, int colour
             i = r < kG ? r - kG : B.B[0] + r - kG;
         }
         if (colour >= 0 && ((i + j + k) & 1) != colour) continue;
-        int g[3];
+        // the owner is the adjacent box in each direction the ghost leaves
+        // (a ghost at most two cells out, boxes at least two cells wide)
         const int L[3] = {i, j, k};
+        int S[3], o[3];
         bool wall = false;
         for (int d = 0; d < 3; ++d) {
-            g[d] = box_global(B, d, c[d] * B.B[d], L[d]);
-            if (g[d] < 0) wall = true;
+            const int step = L[d] < 0 ? -1 : (L[d] >= B.B[d] ? 1 : 0);
+            S[d] = L[d] - step * B.B[d];
+            o[d] = c[d] + step;
+            if (o[d] < 0 || o[d] >= B.nb[d]) {
+                if (B.per[d]) o[d] = o[d] < 0 ? B.nb[d] - 1 : 0;
+                else wall = true;
+            }
         }
         double val = 0.0;
         if (!wall) {
-            const int sb = (g[2] / B.B[2] * B.nb[1] + g[1] / B.B[1]) * B.nb[0] + g[0] / B.B[0];
-            val = B.phi[(size_t)sb * B.stride + v.p(g[0] % B.B[0], g[1] % B.B[1], g[2] % B.B[2])];
+            const int sb = (o[2] * B.nb[1] + o[1]) * B.nb[0] + o[0];
+            val = B.phi[(size_t)sb * B.stride + v.p(S[0], S[1], S[2])];
         }
         v.phi[v.p(i, j, k)] = val;
     }
