@@ -119,24 +119,52 @@ def test_batch_of_64_uneven_boxes_full_size(mp):
 
 
 def test_server_results_equal_single_problem(mp):
+    """Requests of mixed sizes, tolerances and precisions submitted while
+    others run: each served result equals the single-problem solve of the
+    same request bit for bit, and three of them are checked against the
+    oracle's exact discrete solution (definition mode): an FP64 and a
+    mixed-precision request at rtol 1e-10 within 1e-9, and a request at rtol
+    1e-8 within the bar its tolerance allows (3 x the oracle's own
+    deviation when it stops at 1e-8), its residual evaluated by the oracle."""
+    sizes = (32, 64, 32, 48, 64, 32, 96, 32)
     probs = [I.make_problem(e, H=0.1 + 0.05 * k, seed=100 + k, rtol=(1e-8 if k % 2 else 1e-10))
-             for k, e in enumerate((32, 64, 32, 48, 64, 32, 96, 32))]
-    ref = [solo(mp, p) for p in probs]
+             for k, e in enumerate(sizes)]
+    precs = ["mixed" if k in (2, 3, 6) else "fp64" for k in range(len(probs))]
+    ref = [solo(mp, p, prec) for p, prec in zip(probs, precs)]
     S = mp.Server(hbm_budget_bytes=8 << 30, max_inflight=16)
     devs = [mp.to_device(p) for p in probs]
     tickets = []
-    for k, (p, d) in enumerate(zip(probs, devs)):
-        tickets.append(S.submit(mp.params_of(p), d))
+    for k, (p, d, prec) in enumerate(zip(probs, devs, precs)):
+        tickets.append(S.submit(mp.params_of(p, precision=prec), d))
         if k == 3:
             time.sleep(0.002)               # later requests arrive while the first are running
     res = [S.wait(t) for t in tickets]
     c = S.counters()
     S.close()
     assert c["completed"] == len(probs) and c["peak_inflight"] >= 2
-    for p, d, r, (st0, out0) in zip(probs, devs, res, ref):
-        assert r["status_name"] == "OK" and r["cycles"] == st0["cycles"]
+    outs = []
+    for p, d, r, (st0, out0), prec in zip(probs, devs, res, ref, precs):
+        assert r["status_name"] == "OK" and r["rel_resid"] <= p.rtol and r["cycles"] == st0["cycles"]
         out = {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
-        assert same(out, out0), p.n
+        assert same(out, out0), (p.n, prec)
+        outs.append(out)
+    # served results against the oracle
+    for k in (0, 2):                        # rtol 1e-10: FP64 (k = 0) and mixed (k = 2)
+        assert probs[k].rtol == 1e-10
+        d = O.mac_project(probs[k], mode="definition")
+        assert d["status"] == 0
+        assert rel(outs[k]["phi"], d["phi"]) <= 1e-9, (k, precs[k])
+    k = 1                                   # rtol 1e-8, FP64
+    p = probs[k]
+    d = O.mac_project(p, mode="definition")
+    a = O.mac_project(p)                    # the oracle's own iterate at the same 1e-8 stop
+    e_alg = rel(a["phi"], d["phi"])
+    assert rel(outs[k]["phi"], d["phi"]) <= max(1e-9, 3 * e_alg), (rel(outs[k]["phi"], d["phi"]), e_alg)
+    cf = O.face_coeffs(p.n, p.periodic, p.rho, p.beta0_cc, p.beta0_edge)
+    f = O.rhs(p.n, p.periodic, p.dx, p.beta0_cc, p.beta0_edge, p.u, p.v, p.w, p.S)
+    f -= f.mean()
+    r = O.residual(p.n, p.periodic, p.dx, cf, outs[k]["phi"], f)
+    assert np.linalg.norm(r) <= 1.05e-8 * np.linalg.norm(f)
 
 
 def test_server_budget_and_failures(mp):

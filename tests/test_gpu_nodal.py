@@ -68,6 +68,25 @@ def test_nodal_projection_matches_oracle(mp, n, per, seed):
         assert rel(out["phi"], alg["phi"]) <= 1e-11
 
 
+@pytest.mark.parametrize("n,per,seed", [
+    ((32, 32, 32), (True, True, False), 41),
+    ((24, 16, 32), (False, False, False), 42),
+    ((6, 10, 14), (True, True, False), 43),       # two levels
+])
+def test_nodal_strict_at_rtol_1e12(mp, n, per, seed):
+    """Solved to rtol 1e-12, phi and U are within 1e-9 of the oracle's exact
+    discrete solution outright (no allowance for the algorithm's own
+    deviation at the looser stop)."""
+    prob = I.make_nodal_problem(n, H=0.2, rho_noise=0.05, seed=seed, periodic=per)
+    st, out = run_gpu(mp, prob, rtol=1e-12)
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-12
+    ref = O.nodal_project(prob, mode="definition")
+    assert ref["status"] == 0
+    assert rel(out["phi"], ref["phi"]) <= 1e-9, rel(out["phi"], ref["phi"])
+    for name in ("u", "v", "w"):
+        assert rel(out[name], ref[name]) <= 1e-9, (name, rel(out[name], ref[name]))
+
+
 def test_nodal_errors(mp):
     p = I.make_nodal_problem(16, seed=9)
     q = p.copy(); q.S = q.S + 0.3
