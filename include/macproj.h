@@ -392,6 +392,34 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]);
  * (it then runs one kernel per colour). */
 int mg_sweep_config(mg_handle h, int32_t level, int32_t tile[4]);
 
+/* ---- allocation-free projection ------------------------------------------ */
+
+/* Device bytes of the fixed scratch array behind mac_project_static. */
+#define MG_STATIC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): mac_project for the
+ * problem described by *p (shape, dx, bc, sweeps, rtol, max_cycles,
+ * precision), with every multigrid level array, partial-sum row and scalar
+ * in a fixed per-device array of MG_STATIC_SCRATCH_BYTES (32 MiB) instead of
+ * a hierarchy from mg_setup.  Arguments, layout, ownership of the fields,
+ * results, statuses and blocking are those of mac_project; the results equal
+ * mac_project's on a hierarchy set up with the same params.  The call
+ * allocates no device or pinned host memory and creates no events, streams
+ * or graphs: the V-cycles run as separate launches on `stream`, and
+ * stats->ms_total is the host wall time of the call.  Problems whose
+ * mg_workspace_bytes(p) exceeds MG_STATIC_SCRATCH_BYTES (e.g. more than 64^3
+ * cells in a cube) return MG_ERR_BAD_SIZE.  Each device the library runs on
+ * holds the array from module load until the process ends; its device
+ * address is looked up on the first call made with that device current
+ * (devices 0..63).  Every call on a device shares that device's array and
+ * host-side state, so calls that overlap on one device (several threads, or
+ * several streams in flight) race; each call clears the part of the array it
+ * uses before its own work. */
+int mac_project_static(const mg_params* p, const double* rho, const double* beta0_cc,
+                       const double* beta0_edge, const double* S, double* u, double* v, double* w,
+                       double* phi, mg_stats* stats, void* stream);
+
 const char* mg_strerror(int code);
 const char* mg_last_error(void);
 

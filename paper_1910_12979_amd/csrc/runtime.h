@@ -81,6 +81,8 @@ int validate_params(const mg_params* p);
 size_t workspace_bytes(const mg_params* p);
 int setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_hierarchy** out);
 int destroy(mg_hierarchy* H);
+// In-place set-up on caller memory (no allocation, no events, no graphs).
+int setup_static(const mg_params* p, void* ws, size_t ws_bytes, double* host, mg_hierarchy* H);
 int project(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e, const double* S,
             double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st,
             const double* w0 = nullptr, const Radial* rad = nullptr);

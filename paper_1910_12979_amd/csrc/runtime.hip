@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <functional>
 #include <cstdio>
@@ -258,6 +259,47 @@ int setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_hierarchy** o
     hipEventCreate(&H->ev0);
     hipEventCreate(&H->ev1);
     *out = H;
+    return MG_OK;
+}
+
+// A hierarchy laid out in caller memory without allocating anything: *H is
+// reset and filled, ws (device, >= workspace_bytes(p), 256-byte aligned)
+// holds every level array, host (64 doubles, any host memory) receives the
+// scalar readbacks.  No timing events and no captured graphs: the solve runs
+// every cycle as separate launches on the caller's stream.
+int setup_static(const mg_params* p, void* ws, size_t ws_bytes, double* host, mg_hierarchy* H) {
+    int st = validate_params(p);
+    if (st != MG_OK) return st;
+    const size_t need = layout(nullptr, p, nullptr);
+    if (!ws || !host || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) {
+        set_error("static workspace too small or not 256-byte aligned");
+        return MG_ERR_INVALID_ARG;
+    }
+    *H = mg_hierarchy{};
+    H->p = *p;
+    H->px = p->bc[0] == MG_BC_PERIODIC;
+    H->py = p->bc[1] == MG_BC_PERIODIC;
+    H->pz = p->bc[2] == MG_BC_PERIODIC;
+    sides_from_bc(p, H->side);
+    for (int q = 0; q < 6; ++q)
+        if (H->side[q] == 2) H->outflow = true;
+    H->singular = !H->outflow;
+    H->nlev = count_levels(p->n[0], p->n[1], p->n[2]);
+    hipGetDevice(&H->device);
+    H->ws = ws;
+    H->owns_ws = false;
+    H->ws_bytes = need;
+    H->graphs_on = false;
+    layout(H, p, (char*)ws);
+    for (int l = 0; l < H->nlev; ++l) {
+        Level& L = H->lev[l];
+        L.nx = p->n[0] >> l;
+        L.ny = p->n[1] >> l;
+        L.nz = p->n[2] >> l;
+        L.N = (size_t)L.nx * L.ny * L.nz;
+        L.h = p->dx * (double)(1 << l);
+    }
+    H->host = host;
     return MG_OK;
 }
 
@@ -1068,7 +1110,10 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
     mg_stats* S_ = stats ? stats : &local;
     std::memset(S_, 0, sizeof *S_);
     S_->nlevels = H->nlev;
-    HIPCHK(hipEventRecord(H->ev0, st));
+    // device time from events; a hierarchy without events (laid out by
+    // setup_static) reports the host wall time of the call instead
+    const auto t_host0 = std::chrono::steady_clock::now();
+    if (H->ev0) HIPCHK(hipEventRecord(H->ev0, st));
     Level& L0 = H->lev[0];
     // the fused finest-level sweep reads rho as 16-byte pairs
     const double* rho_src = rho;
@@ -1138,7 +1183,7 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         HIPCHK(launch_correct(shape_of(L0), H->px, H->py, H->pz, L0.h, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
                               L0.d.phi, H->scal + kSlotPhi * kReduceWidth, u, v, w, phi_out, st));
     }
-    HIPCHK(hipEventRecord(H->ev1, st));
+    if (H->ev1) HIPCHK(hipEventRecord(H->ev1, st));
     if (H->singular) {
         rc = read_scalars(H, kSlotPhi * kReduceWidth, kReduceWidth, st);
         if (rc) return rc;
@@ -1147,9 +1192,13 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         HIPCHK(hipStreamSynchronize(st));
         S_->phi_mean = 0.0;
     }
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, H->ev0, H->ev1);
-    S_->ms_total = ms;
+    if (H->ev0 && H->ev1) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, H->ev0, H->ev1);
+        S_->ms_total = ms;
+    } else {
+        S_->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
+    }
     S_->bytes_model = model_bytes(H->p, S_->cycles, H->p.precision == MG_MIXED);
     S_->status = status;
     if (status == MG_ERR_NOT_CONVERGED) set_error("maximum number of cycles reached");

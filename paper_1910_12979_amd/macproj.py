@@ -117,6 +117,7 @@ def lib():
         L.nodal_level_copy.argtypes = [vp, i32, i32, vp, i32, vp]
         L.nodal_level_step.argtypes = [vp, i32, i32, i32, vp]
         L.nodal_set_graphs.argtypes = [vp, i32]
+        L.mac_project_static.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -345,6 +346,29 @@ class Hierarchy:
 
     def level_step(self, level, step, arg=0, stream=None):
         _check(lib().mg_level_step(self._h, level, STEP[step], arg, _stream(stream)))
+
+
+STATIC_SCRATCH_BYTES = 32 << 20
+
+
+def mac_project_static(params: Params, rho, beta0_cc, beta0_edge, S, u, v, w, phi=None, stream=None,
+                       allow=(MG_OK,)):
+    """The allocation-free projection (no hierarchy handle: the library's
+    fixed per-device scratch array holds the levels).  Returns the stats dict."""
+    import torch
+    sh = field_shapes(tuple(params.n))
+    f64 = torch.float64
+    st = Stats()
+    code = lib().mac_project_static(ctypes.byref(params), _ptr(rho, f64, sh["rho"], "rho"),
+                                    _ptr(beta0_cc, f64, sh["beta0_cc"], "beta0_cc"),
+                                    _ptr(beta0_edge, f64, sh["beta0_edge"], "beta0_edge"),
+                                    _ptr(S, f64, sh["S"], "S"), _ptr(u, f64, sh["u"], "u"),
+                                    _ptr(v, f64, sh["v"], "v"), _ptr(w, f64, sh["w"], "w"),
+                                    _ptr(phi, f64, sh["phi"], "phi"), ctypes.byref(st), _stream(stream))
+    _check(code, allow)
+    out = st.as_dict()
+    out["code"] = code
+    return out
 
 
 def mg_setup(params: Params, workspace=None) -> Hierarchy:
