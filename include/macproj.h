@@ -323,7 +323,10 @@ int serve_create(size_t hbm_budget_bytes, int32_t max_inflight, void** server);
 /* Queue a problem; never blocks.  The problem's buffers must stay alive until
  * its ticket completes. */
 int serve_submit(void* server, const mg_problem* prob, uint64_t* ticket);
-/* MG_PENDING while the ticket is queued or running; else its final status,
+/* A ticket is released once a poll or wait has returned its final status
+ * (when no other wait is still blocked on it); later calls with it return
+ * MG_ERR_INVALID_ARG.
+ * MG_PENDING while the ticket is queued or running; else its final status,
  * with *out (nullable) filled. */
 int serve_poll(void* server, uint64_t ticket, mg_stats* out);
 /* Block until the ticket completes; returns its status. */

@@ -4,11 +4,20 @@
 // sequence of kernels a single mac_project would run on it (same kernel
 // bodies, same per-problem tile geometry and reduction order), so its result
 // is bit-identical to the single-problem result.  What is shared is the
-// launch: at every step of the V-cycle one launch covers that step for all
-// active problems (their tiles or cells concatenated, a descriptor table
-// telling each workgroup which problem it belongs to).  Problems stop
-// independently; the set of active problems is revisited once per V-cycle,
-// which is also where the serving loop admits new requests.
+// launch: at every step one launch covers that step for all active problems
+// (their tiles, cells or blocks concatenated, a descriptor table telling each
+// workgroup which problem it belongs to) -- the set-up (coefficients,
+// right-hand side, coarse coefficients, coarsest-level inverses, FP32
+// mirrors), every step of the V-cycle, and the finishing correction.
+//
+// Problems stop independently; the active set is revisited once per
+// iteration (a V-cycle plus the speculative sweep that measures its
+// residual, or an FP32 V-cycle plus the FP64 refinement), which is also
+// where the serving loop admits new requests.  An iteration's launches for a
+// given active set are captured once as a hipGraph, with their descriptor
+// tables in an arena owned by that graph, and replayed while the same set
+// (same hierarchies, buffers and settings) recurs; every problem's norm row
+// lands in one gathered block copied to the host once per iteration.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +43,28 @@ namespace mg {
 // ---------------------------------------------------------------------------
 // descriptor staging: pinned host ring mirrored on the device
 // ---------------------------------------------------------------------------
+int Arena::init(size_t bytes) {
+    cap = bytes;
+    off = 0;
+    overflow = false;
+    if (hipHostMalloc((void**)&host, bytes, hipHostMallocDefault) != hipSuccess) {
+        host = nullptr;
+        return MG_ERR_OOM;
+    }
+    if (hipMalloc((void**)&dev, bytes) != hipSuccess) {
+        dev = nullptr;
+        return MG_ERR_OOM;
+    }
+    return MG_OK;
+}
+
+void Arena::release() {
+    if (host) hipHostFree(host);
+    if (dev) hipFree(dev);
+    host = dev = nullptr;
+    cap = off = 0;
+}
+
 int Staging::init(size_t bytes) {
     cap = bytes;
     if (hipHostMalloc((void**)&host, bytes, hipHostMallocDefault) != hipSuccess) return MG_ERR_OOM;
@@ -49,6 +80,20 @@ void Staging::release() {
 
 int Staging::push(const void* src, size_t bytes, hipStream_t st, void** out) {
     const size_t need = (bytes + 255) & ~(size_t)255;
+    if (rec) {
+        // capture: the table goes to the round's arena (uploaded once later);
+        // an arena that is too small marks the capture for a retry
+        if (rec->off + need > rec->cap) {
+            rec->overflow = true;
+            rec->off += need;
+            *out = rec->dev;
+            return MG_OK;
+        }
+        std::memcpy(rec->host + rec->off, src, bytes);
+        *out = rec->dev + rec->off;
+        rec->off += need;
+        return MG_OK;
+    }
     if (off + need > cap) {
         // everything staged so far must have been copied before reuse
         BHIP(hipStreamSynchronize(st));
@@ -221,11 +266,23 @@ int multi_smooth(std::vector<Item>& items, int first, Staging& S, hipStream_t st
     // small levels: prolongation / zero start once, then in-place sweeps
     {
         std::vector<Item*> pro, sm;
+        std::vector<EltDesc> zero;
+        int zb = 0;
         for (Item* it : small) {
             if (it->nsweeps == 0) continue;
             sm.push_back(it);
             if (first == kInProlong) pro.push_back(it);
-            if (first == kInZero) BHIP(launch_fill<double>(it->H->lev[it->l].d.phi, it->H->lev[it->l].N, 0.0, st));
+            if (first == kInZero) {
+                Level& F = it->H->lev[it->l];
+                zero.push_back(EltDesc{kEltFill, zb, F.N, nullptr, F.d.phi, 0.0});
+                zb += elt_blocks(F.N);
+            }
+        }
+        if (!zero.empty()) {
+            void* dd = nullptr;
+            int rc = S.push(zero.data(), zero.size() * sizeof(EltDesc), st, &dd);
+            if (rc) return rc;
+            BHIP(launch_elt_multi((const EltDesc*)dd, (int)zero.size(), zb, st));
         }
         int rc = launch_cells(pro, all_cells,
                               [&](const CellDesc* d, int n, int b) { return launch_prolong_multi(d, n, b, st); }, S, st);
@@ -299,29 +356,25 @@ int multi_coarse(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
 }
 
 // Speculative first pre-sweep with the residual norm of each problem's
-// current finest-level phi; the reduced row lands in host[kSlotRes].
-int multi_norm_sweep(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
+// current finest-level phi; problem i's reduced row lands in its scalar
+// block (kSlotRes) and in row i of `gather`.
+int multi_norm_sweep(std::vector<mg_hierarchy*>& hs, double* gather, Staging& S, hipStream_t st) {
     if (hs.empty()) return MG_OK;
     std::vector<Item> grp;
     for (auto* H : hs) grp.push_back(Item{H, 0, 1});
     int rc = launch_fused(grp, true, kInPlain, kOpSweepNorm, S, st);
     if (rc) return rc;
     std::vector<ReduceDesc> rd;
-    for (auto* H : hs) {
+    for (size_t i = 0; i < hs.size(); ++i) {
+        mg_hierarchy* H = hs[i];
         Level& L0 = H->lev[0];
-        ReduceDesc r;
-        r.partials = H->partials;
-        r.nparts = sweep_tiles(L0.nx, L0.ny, L0.nz, sweep_config_for(L0.nx, L0.ny, L0.nz, true));
-        r.out = H->scal + kSlotRes * kReduceWidth;
-        rd.push_back(r);
+        rd.push_back(ReduceDesc{H->partials, sweep_tiles(L0.nx, L0.ny, L0.nz, sweep_config_for(L0.nx, L0.ny, L0.nz, true)),
+                                H->scal + kSlotRes * kReduceWidth, gather + i * kReduceWidth});
     }
     void* dd = nullptr;
     rc = S.push(rd.data(), rd.size() * sizeof(ReduceDesc), st, &dd);
     if (rc) return rc;
     BHIP(launch_reduce_multi((const ReduceDesc*)dd, (int)rd.size(), st));
-    for (auto* H : hs)
-        BHIP(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
-                            kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
     return MG_OK;
 }
 
@@ -522,14 +575,15 @@ int multi_vcycle_f32(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st)
 }
 
 // FP64 refinement of every problem: phi += e32 / scale, residual, FP32
-// residual for the next cycle, norm rows reduced, scales advanced, norm row
-// copied to pinned host memory.
-int multi_refine(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
+// residual for the next cycle, norm rows reduced (problem i's also into row
+// i of `gather`), scales advanced.
+int multi_refine(std::vector<mg_hierarchy*>& hs, double* gather, Staging& S, hipStream_t st) {
     std::vector<SweepArgs<double>> args;
     std::vector<int> cfgs;
     std::vector<ReduceDesc> rd;
     std::vector<ScaleDesc> sd;
-    for (auto* H : hs) {
+    for (size_t i = 0; i < hs.size(); ++i) {
+        mg_hierarchy* H = hs[i];
         Level& L0 = H->lev[0];
         SweepArgs<double> a{};
         a.nx = L0.nx;
@@ -552,7 +606,8 @@ int multi_refine(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
         const int cfg = sweep_config_for(L0.nx, L0.ny, L0.nz, true);
         args.push_back(a);
         cfgs.push_back(cfg);
-        rd.push_back(ReduceDesc{H->partials, sweep_tiles(L0.nx, L0.ny, L0.nz, cfg), H->scal + kSlotRes * kReduceWidth});
+        rd.push_back(ReduceDesc{H->partials, sweep_tiles(L0.nx, L0.ny, L0.nz, cfg), H->scal + kSlotRes * kReduceWidth,
+                                gather + i * kReduceWidth});
         sd.push_back(ScaleDesc{H->scal + kSlotRes * kReduceWidth, H->scal + kSlotScale * kReduceWidth, (double)L0.N});
     }
     int rc = launch_group<double>(args, cfgs, true, kInCorrect, kOpRefine, S, st);
@@ -565,9 +620,6 @@ int multi_refine(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
     rc = S.push(sd.data(), sd.size() * sizeof(ScaleDesc), st, &dd);
     if (rc) return rc;
     BHIP(launch_next_scale_multi((const ScaleDesc*)dd, (int)sd.size(), st));
-    for (auto* H : hs)
-        BHIP(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
-                            kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
     return MG_OK;
 }
 
@@ -593,56 +645,251 @@ bool batchable(const mg_hierarchy* H) {
     return true;
 }
 
-static void fail_job(Job& j, int status, const char* why) {
+static void fail_job(Job& j, int status) {
     j.st.status = status;
     j.status = status;
     j.stage = Job::kDone;
-    (void)why;
 }
 
-// Coefficients, right-hand side, compatibility and norm of f for new jobs.
+namespace {
+
+constexpr size_t kArenaMin = (size_t)1 << 20;
+constexpr size_t kMaxRoundGraphs = 8;
+constexpr size_t kMaxSeenKeys = 16;
+
+template <typename D>
+int push_table(Staging& S, const std::vector<D>& v, hipStream_t st, const D** out) {
+    void* dd = nullptr;
+    int rc = S.push(v.data(), v.size() * sizeof(D), st, &dd);
+    *out = (const D*)dd;
+    return rc;
+}
+
+// Every phi buffer pointer of H's levels (FP64 pair, FP32 pair per level).
+void phi_state(const mg_hierarchy* H, std::vector<void*>& out) {
+    for (int l = 0; l < H->nlev; ++l) {
+        const Level& L = H->lev[l];
+        out.push_back(L.d.phi);
+        out.push_back(L.phi2_d);
+        out.push_back(L.s.phi);
+        out.push_back(L.phi2_s);
+    }
+}
+
+void set_phi_state(mg_hierarchy* H, const std::vector<void*>& in, size_t& at) {
+    for (int l = 0; l < H->nlev; ++l) {
+        Level& L = H->lev[l];
+        L.d.phi = (double*)in[at++];
+        L.phi2_d = (double*)in[at++];
+        L.s.phi = (float*)in[at++];
+        L.phi2_s = (float*)in[at++];
+    }
+}
+
+// Everything an iteration's launches bake in: the hierarchies in order, their
+// shapes, settings, coefficient sources and current phi buffers, the tile
+// choices and the gathered-row block.
+std::vector<uintptr_t> round_key(const std::vector<mg_hierarchy*>& h64, const std::vector<int>& pre_done,
+                                 const std::vector<mg_hierarchy*>& hm, const double* gather) {
+    std::vector<uintptr_t> k;
+    k.push_back((uintptr_t)sweep_tune_epoch());
+    k.push_back((uintptr_t)gather);
+    auto one = [&k](const mg_hierarchy* H, uintptr_t tag) {
+        k.push_back(tag);
+        k.push_back((uintptr_t)H);
+        k.push_back((uintptr_t)H->ws);
+        for (int d = 0; d < 3; ++d) k.push_back((uintptr_t)H->p.n[d]);
+        k.push_back((uintptr_t)H->nlev);
+        k.push_back((uintptr_t)H->p.pre_sweeps);
+        k.push_back((uintptr_t)H->p.post_sweeps);
+        k.push_back((uintptr_t)H->bottom_on);
+        k.push_back((uintptr_t)H->rho.rho);
+        k.push_back((uintptr_t)H->rho.b0c);
+        k.push_back((uintptr_t)H->rho.b0e);
+        k.push_back((uintptr_t)H->rho32_on);
+        std::vector<void*> ph;
+        phi_state(H, ph);
+        for (void* q : ph) k.push_back((uintptr_t)q);
+    };
+    for (size_t i = 0; i < h64.size(); ++i) one(h64[i], 0x100 + (uintptr_t)pre_done[i]);
+    for (auto* H : hm) one(H, 0x200);
+    return k;
+}
+
+}  // namespace
+
+int Engine::ensure_gather(int rows) {
+    if (rows <= grows) return MG_OK;
+    const int want = std::max(rows, std::max(64, 2 * grows));
+    drop_graphs();                       // captured rounds bake in the old block
+    if (gdev) hipFree(gdev);
+    if (ghost) hipHostFree(ghost);
+    gdev = nullptr;
+    ghost = nullptr;
+    grows = 0;
+    if (hipMalloc((void**)&gdev, (size_t)want * kReduceWidth * sizeof(double)) != hipSuccess) {
+        gdev = nullptr;
+        set_error("allocation of the gathered norm block failed");
+        return MG_ERR_OOM;
+    }
+    if (hipHostMalloc((void**)&ghost, (size_t)want * kReduceWidth * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
+        ghost = nullptr;
+        set_error("allocation of the host norm block failed");
+        return MG_ERR_OOM;
+    }
+    grows = want;
+    return MG_OK;
+}
+
+void Engine::drop_graphs() {
+    for (auto& g : graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g.arena.release();
+    }
+    graphs.clear();
+    seen.clear();
+}
+
+void Engine::release() {
+    drop_graphs();
+    if (gdev) hipFree(gdev);
+    if (ghost) hipHostFree(ghost);
+    gdev = nullptr;
+    ghost = nullptr;
+    grows = 0;
+    if (gs) hipStreamDestroy(gs);
+    if (gev) hipEventDestroy(gev);
+    gs = nullptr;
+    gev = nullptr;
+    staging.release();
+}
+
+// Coefficients, right-hand side, compatibility and norm of f for new jobs,
+// batched over all of them.
 int Engine::setup_new(std::vector<Job*>& fresh, hipStream_t st) {
     if (fresh.empty()) return MG_OK;
-    for (Job* j : fresh) {
+    int rc = ensure_gather((int)fresh.size());
+    if (rc) return rc;
+    std::vector<CoeffDesc> cd;
+    std::vector<ReduceDesc> rd;
+    std::vector<CoarseDesc> co_lds, co_glb;
+    std::vector<EltDesc> f32;
+    int cblocks = 0, f32blocks = 0, maxlev = 0;
+    for (size_t q = 0; q < fresh.size(); ++q) {
+        Job* j = fresh[q];
         mg_hierarchy* H = j->H;
         std::memset(&j->st, 0, sizeof j->st);
         j->st.nlevels = H->nlev;
+        j->gslot = -1;
+        for (int l = 0; l < H->nlev; ++l) {       // the buffers as laid out (the values do not depend on it)
+            Level& L = H->lev[l];
+            L.d.phi = L.phi_home_d[0];
+            L.phi2_d = L.phi_home_d[1];
+            L.s.phi = L.phi_home_s[0];
+            L.phi2_s = L.phi_home_s[1];
+        }
         const mg_problem& p = j->pr;
         const double* rho_src = p.rho;
-        if (((uintptr_t)p.rho & 15) != 0) {
+        if (((uintptr_t)p.rho & 15) != 0) {       // the fused sweeps read rho as 16-byte pairs
             BHIP(launch_copy(H->rho_own, p.rho, H->lev[0].N, st));
             rho_src = H->rho_own;
         }
         H->rho = RhoArgs{rho_src, p.beta0_cc, p.beta0_edge, H->px, H->py, H->pz};
-        int rc = build_coefficients(H, p.rho, p.beta0_cc, p.beta0_edge, p.S, p.u, p.v, p.w, st);
-        if (rc) return rc;
-        BHIP(hipMemcpyAsync(H->host + kSlotRhs * kReduceWidth, H->scal + kSlotRhs * kReduceWidth,
-                            kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
+        H->rho32_on = false;
+        Level& L0 = H->lev[0];
+        int g[3];
+        const int nb = coeff_grid(Shape{L0.nx, L0.ny, L0.nz}, g);
+        cd.push_back(CoeffDesc{L0.nx, L0.ny, L0.nz, H->px, H->py, H->pz, L0.h, p.rho, p.beta0_cc, p.beta0_edge, p.S,
+                               p.u, p.v, p.w, nullptr, L0.d.bx, L0.d.by, L0.d.bz, L0.d.f, H->partials, g[0], g[1],
+                               g[2], cblocks});
+        cblocks += nb;
+        rd.push_back(ReduceDesc{H->partials, nb, H->scal + kSlotRhs * kReduceWidth, gdev + q * kReduceWidth});
+        maxlev = std::max(maxlev, H->nlev);
+        Level& Lc = H->lev[H->nlev - 1];
+        const CoarseDesc c{Lc.nx, Lc.ny, Lc.nz, Lc.h, Lc.d.bx, Lc.d.by, Lc.d.bz, H->minv, H->singular ? 1 : 0};
+        (coarse_setup_in_lds(Lc.N) ? co_lds : co_glb).push_back(c);
+        if (H->p.precision == MG_MIXED) {
+            // FP32 coefficient mirrors of the stored levels (the finest FP32
+            // level recomputes its coefficients from an FP32 copy of rho)
+            for (int l = 1; l < H->nlev; ++l) {
+                Level& L = H->lev[l];
+                const double* src[3] = {L.d.bx, L.d.by, L.d.bz};
+                float* dst[3] = {L.s.bx, L.s.by, L.s.bz};
+                for (int a = 0; a < 3; ++a) {
+                    f32.push_back(EltDesc{kEltToF32, f32blocks, L.N, src[a], dst[a], 0.0});
+                    f32blocks += elt_blocks(L.N);
+                }
+            }
+        }
     }
+    const CoeffDesc* dcd = nullptr;
+    if ((rc = push_table(staging, cd, st, &dcd))) return rc;
+    BHIP(launch_coeff_rhs_multi(dcd, (int)cd.size(), cblocks, st));
+    const ReduceDesc* drd = nullptr;
+    if ((rc = push_table(staging, rd, st, &drd))) return rc;
+    BHIP(launch_reduce_multi(drd, (int)rd.size(), st));
+    for (int l = 0; l + 1 < maxlev; ++l) {      // coarse coefficients, one launch per depth
+        std::vector<AvgDesc> av;
+        int ab = 0;
+        for (Job* j : fresh) {
+            mg_hierarchy* H = j->H;
+            if (l + 1 >= H->nlev) continue;
+            Level& F = H->lev[l];
+            Level& C = H->lev[l + 1];
+            av.push_back(AvgDesc{F.nx, F.ny, F.nz, F.d.bx, F.d.by, F.d.bz, C.d.bx, C.d.by, C.d.bz, ab});
+            ab += cell_blocks(C.N);
+        }
+        const AvgDesc* dav = nullptr;
+        if ((rc = push_table(staging, av, st, &dav))) return rc;
+        BHIP(launch_avg_coeff_multi(dav, (int)av.size(), ab, st));
+    }
+    for (int lds = 0; lds < 2; ++lds) {
+        std::vector<CoarseDesc>& v = lds ? co_lds : co_glb;
+        if (v.empty()) continue;
+        const CoarseDesc* dco = nullptr;
+        if ((rc = push_table(staging, v, st, &dco))) return rc;
+        BHIP(launch_coarse_setup_multi(dco, (int)v.size(), lds == 1, st));
+    }
+    if (!f32.empty()) {
+        const EltDesc* de = nullptr;
+        if ((rc = push_table(staging, f32, st, &de))) return rc;
+        BHIP(launch_elt_multi(de, (int)f32.size(), f32blocks, st));
+    }
+    BHIP(hipMemcpyAsync(ghost, gdev, fresh.size() * kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
     BHIP(hipStreamSynchronize(st));
     staging.off = 0;
+    for (Job* j : fresh) j->H->coeffs_valid = true;
+
+    // compatibility and mean removal
     std::vector<Job*> norm;
-    for (Job* j : fresh) {
+    std::vector<RowDesc> nd;
+    std::vector<ReduceDesc> nr;
+    std::vector<EltDesc> el;
+    int nblocks = 0, eblocks = 0;
+    for (size_t q = 0; q < fresh.size(); ++q) {
+        Job* j = fresh[q];
         mg_hierarchy* H = j->H;
-        const double* q = H->host + kSlotRhs * kReduceWidth;
-        const double sf = q[0], saf = q[1], bad = q[2], nonfin = q[3];
+        const double* row = ghost + q * kReduceWidth;
+        const double sf = row[0], saf = row[1], bad = row[2], nonfin = row[3];
         j->st.sum_f = sf;
         j->st.sum_abs_f = saf;
         if (nonfin > 0.0 || !std::isfinite(sf) || !std::isfinite(saf)) {
-            fail_job(*j, MG_ERR_NONFINITE, "non-finite input");
+            fail_job(*j, MG_ERR_NONFINITE);
             continue;
         }
         if (bad > 0.0) {
-            fail_job(*j, MG_ERR_INVALID_ARG, "rho and beta0 must be positive");
+            fail_job(*j, MG_ERR_INVALID_ARG);
             continue;
         }
         if (std::fabs(sf) > 1e-8 * saf) {
-            fail_job(*j, MG_ERR_INCOMPATIBLE_RHS, "incompatible right-hand side");
+            fail_job(*j, MG_ERR_INCOMPATIBLE_RHS);
             continue;
         }
         Level& L0 = H->lev[0];
         if (saf == 0.0) {
-            BHIP(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
+            el.push_back(EltDesc{kEltFill, eblocks, L0.N, nullptr, L0.d.phi, 0.0});
+            eblocks += elt_blocks(L0.N);
             j->st.hist_len = 1;
             j->st.resid_hist[0] = 0.0;
             j->status = MG_OK;
@@ -651,21 +898,31 @@ int Engine::setup_new(std::vector<Job*>& fresh, hipStream_t st) {
         }
         const double mean = sf / (double)L0.N;
         j->st.mean_removed = mean;
-        int np = 0;
-        BHIP(launch_shift_norm(Shape{L0.nx, L0.ny, L0.nz}, L0.d.f, mean, H->partials, &np, st));
-        BHIP(launch_reduce(H->partials, np, H->scal + kSlotNorm * kReduceWidth, st));
-        BHIP(hipMemcpyAsync(H->host + kSlotNorm * kReduceWidth, H->scal + kSlotNorm * kReduceWidth,
-                            kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
+        const int rb = row_blocks(L0.N);
+        nd.push_back(RowDesc{L0.N, L0.d.f, mean, H->partials, rb, nblocks});
+        nblocks += rb;
+        nr.push_back(ReduceDesc{H->partials, rb, H->scal + kSlotNorm * kReduceWidth, gdev + norm.size() * kReduceWidth});
         norm.push_back(j);
     }
-    if (norm.empty()) return MG_OK;
-    BHIP(hipStreamSynchronize(st));
-    for (Job* j : norm) {
+    if (!nd.empty()) {
+        const RowDesc* dnd = nullptr;
+        if ((rc = push_table(staging, nd, st, &dnd))) return rc;
+        BHIP(launch_shift_norm_multi(dnd, (int)nd.size(), nblocks, st));
+        const ReduceDesc* dnr = nullptr;
+        if ((rc = push_table(staging, nr, st, &dnr))) return rc;
+        BHIP(launch_reduce_multi(dnr, (int)nr.size(), st));
+        BHIP(hipMemcpyAsync(ghost, gdev, norm.size() * kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
+        BHIP(hipStreamSynchronize(st));
+        staging.off = 0;
+    }
+    for (size_t q = 0; q < norm.size(); ++q) {
+        Job* j = norm[q];
         mg_hierarchy* H = j->H;
         Level& L0 = H->lev[0];
-        j->fnorm = std::sqrt(H->host[kSlotNorm * kReduceWidth]);
+        j->fnorm = std::sqrt(ghost[q * kReduceWidth]);
         j->st.norm_f = j->fnorm;
-        BHIP(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
+        el.push_back(EltDesc{kEltFill, eblocks, L0.N, nullptr, L0.d.phi, 0.0});
+        eblocks += elt_blocks(L0.N);
         if (j->fnorm == 0.0) {
             j->status = MG_OK;
             j->stage = Job::kFinish;
@@ -676,63 +933,74 @@ int Engine::setup_new(std::vector<Job*>& fresh, hipStream_t st) {
         j->st.resid_hist[0] = 1.0;
         j->st.hist_len = 1;
         if (H->p.precision == MG_MIXED) {
-            // FP32 rho for the finest FP32 sweeps; FP32 residual = s0 f while phi = 0
-            BHIP(launch_coeff_to_f32(H->rho.rho, H->rho32, L0.N, st));
-            H->rho32_on = true;
+            // FP32 rho for the finest FP32 sweeps; FP32 residual = s0 f while
+            // phi = 0; both device scales = s0
             const double s0 = residual_scale(j->fnorm, L0.N);
-            BHIP(launch_scale_to_f32(L0.d.f, L0.s.f, L0.N, s0, st));
-            H->host[kSlotScale * kReduceWidth] = s0;
-            H->host[kSlotScale * kReduceWidth + 1] = s0;
-            BHIP(hipMemcpyAsync(H->scal + kSlotScale * kReduceWidth, H->host + kSlotScale * kReduceWidth,
-                                2 * sizeof(double), hipMemcpyHostToDevice, st));
+            el.push_back(EltDesc{kEltToF32, eblocks, L0.N, H->rho.rho, H->rho32, 0.0});
+            eblocks += elt_blocks(L0.N);
+            el.push_back(EltDesc{kEltScaleToF32, eblocks, L0.N, L0.d.f, L0.s.f, s0});
+            eblocks += elt_blocks(L0.N);
+            el.push_back(EltDesc{kEltFill, eblocks, 2, nullptr, H->scal + kSlotScale * kReduceWidth, s0});
+            eblocks += elt_blocks(2);
+            H->rho32_on = true;
         }
         j->status = MG_ERR_NOT_CONVERGED;
         j->stage = (H->p.rtol >= 1.0) ? Job::kFinish : Job::kSolve;
         if (H->p.rtol >= 1.0) j->status = MG_OK;
     }
+    if (!el.empty()) {
+        const EltDesc* de = nullptr;
+        if ((rc = push_table(staging, el, st, &de))) return rc;
+        BHIP(launch_elt_multi(de, (int)el.size(), eblocks, st));
+    }
     return MG_OK;
 }
 
-// One round: stop tests for solving jobs, one V-cycle for the rest, then
-// the velocity correction of every job that finished.
-int Engine::round(std::vector<Job*>& jobs, hipStream_t st) {
-    std::vector<Job*> solving;
-    for (Job* j : jobs)
-        if (j->stage == Job::kSolve) solving.push_back(j);
-    // stop tests: FP64 jobs measure the residual of their last cycle with a
-    // speculative first pre-sweep; mixed jobs' last refinement left it on the
-    // host already
-    std::vector<mg_hierarchy*> tested;
-    bool mixed_tested = false;
-    for (Job* j : solving)
-        if (j->cycles > 0) {
-            if (j->H->p.precision == MG_MIXED) mixed_tested = true;
-            else tested.push_back(j->H);
-        }
-    if (!tested.empty()) {
-        int rc = multi_norm_sweep(tested, staging, st);
+// The launches of one iteration: FP64 problems one V-cycle (pre_done[i]
+// first pre-sweeps already taken from the last speculative sweep) and the
+// next speculative sweep with its residual norm, rows 0.. of the gathered
+// block; mixed problems one FP32 V-cycle from zero and the FP64 refinement,
+// rows after those.
+static int enqueue_iteration(std::vector<mg_hierarchy*>& h64, const std::vector<int>& pre_done,
+                             std::vector<mg_hierarchy*>& hm, double* gather, Staging& S, hipStream_t st) {
+    if (!h64.empty()) {
+        int rc = multi_vcycle(h64, pre_done, S, st);
+        if (rc) return rc;
+        rc = multi_norm_sweep(h64, gather, S, st);
         if (rc) return rc;
     }
-    if (!tested.empty() || mixed_tested) {
-        BHIP(hipStreamSynchronize(st));
-        staging.off = 0;
+    if (!hm.empty()) {
+        int rc = multi_vcycle_f32(hm, S, st);
+        if (rc) return rc;
+        rc = multi_refine(hm, gather + h64.size() * kReduceWidth, S, st);
+        if (rc) return rc;
     }
-    std::vector<mg_hierarchy*> run, run_mixed;
+    return MG_OK;
+}
+
+// One round: stop tests for solving jobs (their last iteration's norm rows
+// are on the host), one iteration for the rest, then the velocity
+// correction of every job that finished.
+int Engine::round(std::vector<Job*>& jobs, hipStream_t st) {
+    int rc = ensure_gather((int)jobs.size() + 2);
+    if (rc) return rc;
+    std::vector<mg_hierarchy*> run64, runm;
+    std::vector<Job*> jrun64, jrunm;
     std::vector<int> pre_done;
-    for (Job* j : solving) {
+    for (Job* j : jobs) {
+        if (j->stage != Job::kSolve) continue;
         mg_hierarchy* H = j->H;
         const bool mixed = H->p.precision == MG_MIXED;
         int pd = 0;
         if (j->cycles > 0) {
-            const double* r = H->host + kSlotRes * kReduceWidth;
+            const double* r = j->row;
             j->rel = std::sqrt(r[0]) / j->fnorm;
             if (j->cycles < MG_HIST_MAX) {
                 j->st.resid_hist[j->cycles] = j->rel;
                 j->st.hist_len = j->cycles + 1;
             }
             if (r[3] > 0.0 || !std::isfinite(j->rel)) {
-                j->status = MG_ERR_NONFINITE;
-                fail_job(*j, MG_ERR_NONFINITE, "non-finite residual");
+                fail_job(*j, MG_ERR_NONFINITE);
                 continue;
             }
             if (j->rel <= H->p.rtol) {
@@ -754,56 +1022,194 @@ int Engine::round(std::vector<Job*>& jobs, hipStream_t st) {
             continue;
         }
         if (mixed) {
-            run_mixed.push_back(H);
+            runm.push_back(H);
+            jrunm.push_back(j);
         } else {
-            run.push_back(H);
+            run64.push_back(H);
+            jrun64.push_back(j);
             pre_done.push_back(pd);
         }
     }
-    if (!run.empty()) {
-        int rc = multi_vcycle(run, pre_done, staging, st);
+    for (size_t i = 0; i < jrun64.size(); ++i) jrun64[i]->gslot = (int)i;
+    for (size_t i = 0; i < jrunm.size(); ++i) jrunm[i]->gslot = (int)(jrun64.size() + i);
+    const size_t nrun = jrun64.size() + jrunm.size();
+    if (nrun > 0) {
+        rc = iterate(run64, pre_done, runm, st);
         if (rc) return rc;
+        for (Job* j : jrun64) ++j->cycles;
+        for (Job* j : jrunm) ++j->cycles;
     }
-    if (!run_mixed.empty()) {
-        int rc = multi_vcycle_f32(run_mixed, staging, st);
-        if (rc) return rc;
-        rc = multi_refine(run_mixed, staging, st);
-        if (rc) return rc;
-    }
-    for (Job* j : solving)
-        if (j->stage == Job::kSolve) ++j->cycles;
-    // finish: mean removal of phi and the velocity correction
+    // finish: mean removal of phi and the velocity correction, batched; the
+    // sums land in the gathered rows after the iteration's
     std::vector<Job*> fin;
     for (Job* j : jobs)
         if (j->stage == Job::kFinish) fin.push_back(j);
-    for (Job* j : fin) {
-        mg_hierarchy* H = j->H;
-        Level& L0 = H->lev[0];
-        int np = 0;
-        BHIP(launch_sum(Shape{L0.nx, L0.ny, L0.nz}, L0.d.phi, H->partials, &np, st));
-        BHIP(launch_reduce(H->partials, np, H->scal + kSlotPhi * kReduceWidth, st));
-        BHIP(launch_correct(Shape{L0.nx, L0.ny, L0.nz}, H->px, H->py, H->pz, L0.h, j->pr.beta0_cc, j->pr.beta0_edge,
-                            L0.d.bx, L0.d.by, L0.d.bz, L0.d.phi, H->scal + kSlotPhi * kReduceWidth, j->pr.u, j->pr.v,
-                            j->pr.w, j->pr.phi, st));
-        BHIP(hipMemcpyAsync(H->host + kSlotPhi * kReduceWidth, H->scal + kSlotPhi * kReduceWidth,
-                            kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
-    }
     if (!fin.empty()) {
-        BHIP(hipStreamSynchronize(st));
-        staging.off = 0;
-        for (Job* j : fin) {
-            mg_hierarchy* H = j->H;
-            j->st.phi_mean = H->host[kSlotPhi * kReduceWidth] / (double)H->lev[0].N;
-            j->st.cycles = j->cycles;
-            j->st.rel_resid = j->cycles > 0 ? j->rel : j->st.resid_hist[0];
-            if (j->st.hist_len == 1 && j->st.resid_hist[0] == 0.0) j->st.rel_resid = 0.0;
-            j->st.bytes_model = model_bytes(H->p, j->cycles, H->p.precision == MG_MIXED);
-            j->st.status = j->status;
-            j->stage = Job::kDone;
-            H->rho = RhoArgs{};
-            H->rho32_on = false;
+        std::vector<RowDesc> sd;
+        std::vector<ReduceDesc> rd;
+        std::vector<CorrectDesc> cd;
+        int sb = 0, cb = 0;
+        for (size_t q = 0; q < fin.size(); ++q) {
+            mg_hierarchy* H = fin[q]->H;
+            const mg_problem& p = fin[q]->pr;
+            Level& L0 = H->lev[0];
+            const int rb = row_blocks(L0.N);
+            sd.push_back(RowDesc{L0.N, L0.d.phi, 0.0, H->partials, rb, sb});
+            sb += rb;
+            rd.push_back(ReduceDesc{H->partials, rb, H->scal + kSlotPhi * kReduceWidth,
+                                    gdev + (nrun + q) * kReduceWidth});
+            cd.push_back(CorrectDesc{L0.nx, L0.ny, L0.nz, H->px, H->py, H->pz, L0.h, p.beta0_cc, p.beta0_edge, L0.d.bx,
+                                     L0.d.by, L0.d.bz, L0.d.phi, H->scal + kSlotPhi * kReduceWidth, p.u, p.v, p.w,
+                                     p.phi, cb});
+            cb += cell_blocks(L0.N);
+        }
+        const RowDesc* dsd = nullptr;
+        if ((rc = push_table(staging, sd, st, &dsd))) return rc;
+        BHIP(launch_sum_multi(dsd, (int)sd.size(), sb, st));
+        const ReduceDesc* drd = nullptr;
+        if ((rc = push_table(staging, rd, st, &drd))) return rc;
+        BHIP(launch_reduce_multi(drd, (int)rd.size(), st));
+        const CorrectDesc* dcd = nullptr;
+        if ((rc = push_table(staging, cd, st, &dcd))) return rc;
+        BHIP(launch_correct_multi(dcd, (int)cd.size(), cb, st));
+    }
+    const size_t rows = nrun + fin.size();
+    if (rows > 0)
+        BHIP(hipMemcpyAsync(ghost, gdev, rows * kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
+    BHIP(hipStreamSynchronize(st));
+    staging.off = 0;
+    for (Job* j : jrun64) std::memcpy(j->row, ghost + (size_t)j->gslot * kReduceWidth, sizeof j->row);
+    for (Job* j : jrunm) std::memcpy(j->row, ghost + (size_t)j->gslot * kReduceWidth, sizeof j->row);
+    for (size_t q = 0; q < fin.size(); ++q) {
+        Job* j = fin[q];
+        mg_hierarchy* H = j->H;
+        j->st.phi_mean = ghost[(nrun + q) * kReduceWidth] / (double)H->lev[0].N;
+        j->st.cycles = j->cycles;
+        j->st.rel_resid = j->cycles > 0 ? j->rel : j->st.resid_hist[0];
+        if (j->st.hist_len == 1 && j->st.resid_hist[0] == 0.0) j->st.rel_resid = 0.0;
+        j->st.bytes_model = model_bytes(H->p, j->cycles, H->p.precision == MG_MIXED);
+        j->st.status = j->status;
+        j->stage = Job::kDone;
+        H->rho = RhoArgs{};
+        H->rho32_on = false;
+    }
+    return MG_OK;
+}
+
+// One iteration for the running sets: replay the captured graph of this
+// exact work, capture it (graph_mode), or launch it eagerly on `st`.
+int Engine::iterate(std::vector<mg_hierarchy*>& h64, const std::vector<int>& pre_done,
+                    std::vector<mg_hierarchy*>& hm, hipStream_t st) {
+    std::vector<uintptr_t> key;
+    RoundGraph* g = nullptr;
+    bool capture = false;
+    if (graph_mode > 0) {
+        key = round_key(h64, pre_done, hm, gdev);
+        for (auto& c : graphs)
+            if (c.exec && c.key == key) g = &c;
+        if (!g) {
+            if (graph_mode == 1) {
+                capture = true;
+            } else {
+                for (auto& k : seen)
+                    if (k == key) capture = true;
+                if (!capture) {
+                    if (seen.size() >= kMaxSeenKeys) seen.erase(seen.begin());
+                    seen.push_back(key);
+                }
+            }
         }
     }
+    if (!g && !capture) {
+        ++eager;
+        return enqueue_iteration(h64, pre_done, hm, gdev, staging, st);
+    }
+    if (!gs) {
+        BHIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+        BHIP(hipEventCreateWithFlags(&gev, hipEventDisableTiming));
+    }
+    // the graph runs on the engine's own stream, after the caller's earlier work
+    BHIP(hipEventRecord(gev, st));
+    BHIP(hipStreamWaitEvent(gs, gev, 0));
+    if (g) {
+        size_t at = 0;
+        for (auto* H : h64) set_phi_state(H, g->post, at);
+        for (auto* H : hm) set_phi_state(H, g->post, at);
+        ++replays;
+    } else {
+        std::vector<void*> before;
+        for (auto* H : h64) phi_state(H, before);
+        for (auto* H : hm) phi_state(H, before);
+        size_t cap = kArenaMin;
+        RoundGraph fresh;
+        for (int attempt = 0;; ++attempt) {
+            int rc = fresh.arena.init(cap);
+            if (rc) {
+                fresh.arena.release();
+                set_error("allocation of a round's descriptor arena failed");
+                return rc;
+            }
+            staging.rec = &fresh.arena;
+            hipError_t e = hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) {
+                staging.rec = nullptr;
+                fresh.arena.release();
+                return hip_fail(e, "hipStreamBeginCapture", __LINE__);
+            }
+            rc = enqueue_iteration(h64, pre_done, hm, gdev, staging, gs);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(gs, &graph);
+            staging.rec = nullptr;
+            const bool overflow = fresh.arena.overflow;
+            const size_t used = fresh.arena.off;
+            if (rc || e != hipSuccess || overflow) {
+                if (graph) hipGraphDestroy(graph);
+                size_t at = 0;                    // back to the state before the capture
+                for (auto* H : h64) set_phi_state(H, before, at);
+                for (auto* H : hm) set_phi_state(H, before, at);
+                fresh.arena.release();
+                if (rc) return rc;
+                if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
+                if (attempt >= 3) {
+                    set_error("descriptor arena kept overflowing");
+                    return MG_ERR_OOM;
+                }
+                cap = std::max(2 * cap, used + kArenaMin);
+                continue;
+            }
+            e = hipGraphInstantiate(&fresh.exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                fresh.exec = nullptr;
+                size_t at = 0;
+                for (auto* H : h64) set_phi_state(H, before, at);
+                for (auto* H : hm) set_phi_state(H, before, at);
+                fresh.arena.release();
+                return hip_fail(e, "hipGraphInstantiate", __LINE__);
+            }
+            break;
+        }
+        fresh.key = key;
+        for (auto* H : h64) phi_state(H, fresh.post);
+        for (auto* H : hm) phi_state(H, fresh.post);
+        // the tables, once (the pinned bytes never change afterwards)
+        BHIP(hipMemcpyAsync(fresh.arena.dev, fresh.arena.host, fresh.arena.off, hipMemcpyHostToDevice, gs));
+        if (graphs.size() >= kMaxRoundGraphs) {        // least recently used out (its work is complete)
+            size_t lru = 0;
+            for (size_t i = 1; i < graphs.size(); ++i)
+                if (graphs[i].used < graphs[lru].used) lru = i;
+            if (graphs[lru].exec) hipGraphExecDestroy(graphs[lru].exec);
+            graphs[lru].arena.release();
+            graphs.erase(graphs.begin() + lru);
+        }
+        graphs.push_back(std::move(fresh));
+        g = &graphs.back();
+        ++captures;
+    }
+    g->used = ++clock;
+    BHIP(hipGraphLaunch(g->exec, gs));
+    BHIP(hipEventRecord(gev, gs));
+    BHIP(hipStreamWaitEvent(st, gev, 0));
     return MG_OK;
 }
 

@@ -65,8 +65,10 @@ struct Pool {
     int acquire(const mg_params& p, int dev, mg_hierarchy** out) {
         auto& v = idle[key_of(p, dev)];
         if (!v.empty()) {
-            *out = v.back();
-            v.pop_back();
+            // oldest first: a repeated batch gets the same hierarchies in the
+            // same order (and replays its captured rounds)
+            *out = v.front();
+            v.erase(v.begin());
             idle_bytes -= (*out)->ws_bytes;
             busy_bytes += (*out)->ws_bytes;
             (*out)->p = p;
@@ -144,30 +146,43 @@ struct Server {
         std::vector<Job*> active;
         for (;;) {
             std::vector<Job*> fresh;
+            std::deque<Job*> cand;
             {
+                // under the lock only the queue: take the requests that the
+                // in-flight cap allows (the pool is the worker's alone)
                 std::unique_lock<std::mutex> lk(mu);
                 if (active.empty() && queue.empty()) cv.wait(lk, [&] { return stop || !queue.empty(); });
                 if (stop && active.empty() && queue.empty()) return;
-                // admission at the V-cycle boundary: in-flight cap and HBM budget
-                while (!queue.empty() && active.size() + fresh.size() < (size_t)max_inflight) {
-                    Job* j = queue.front();
-                    const bool reuse = pool.has_idle(j->pr.p, device);
-                    const size_t need = reuse ? 0 : j->bytes;
-                    if (pool.busy_bytes + pool.idle_bytes + need > budget) {
-                        const ShapeKey k = key_of(j->pr.p, device);
-                        size_t target = budget > pool.busy_bytes + need ? budget - pool.busy_bytes - need : 0;
-                        pool.trim(target, &k);
-                        if (pool.busy_bytes + pool.idle_bytes + need > budget) break;   // wait for completions
-                    }
+                while (!queue.empty() && active.size() + cand.size() < (size_t)max_inflight) {
+                    cand.push_back(queue.front());
                     queue.pop_front();
-                    j->t_admit = now_s();
-                    // reserve the hierarchy now, so the next request in this
-                    // pass sees the pool as it will be
-                    j->status = pool.acquire(j->pr.p, device, &j->H);
-                    fresh.push_back(j);
-                    inflight_n += 1;
-                    peak = std::max(peak, (double)inflight_n);
                 }
+            }
+            // admission at the V-cycle boundary against the HBM budget, in
+            // arrival order; hierarchies are allocated (and idle ones of other
+            // shapes released) without holding the lock
+            while (!cand.empty()) {
+                Job* j = cand.front();
+                const bool reuse = pool.has_idle(j->pr.p, device);
+                const size_t need = reuse ? 0 : j->bytes;
+                if (pool.busy_bytes + pool.idle_bytes + need > budget) {
+                    const ShapeKey k = key_of(j->pr.p, device);
+                    size_t target = budget > pool.busy_bytes + need ? budget - pool.busy_bytes - need : 0;
+                    pool.trim(target, &k);
+                    if (pool.busy_bytes + pool.idle_bytes + need > budget) break;   // wait for completions
+                }
+                cand.pop_front();
+                j->t_admit = now_s();
+                // reserve the hierarchy now, so the next request in this pass
+                // sees the pool as it will be
+                j->status = pool.acquire(j->pr.p, device, &j->H);
+                fresh.push_back(j);
+            }
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (auto it = cand.rbegin(); it != cand.rend(); ++it) queue.push_front(*it);   // not admitted yet
+                inflight_n += fresh.size();
+                peak = std::max(peak, (double)inflight_n);
             }
             std::vector<Job*> setup_list;
             for (Job* j : fresh) {
@@ -243,6 +258,7 @@ int project_batch(int32_t count, const mg_problem* probs, mg_stats* stats, void*
         if (!g_batch_pool) g_batch_pool = new Pool();
         if (!g_batch_engine) {
             g_batch_engine = new Engine();
+            g_batch_engine->graph_mode = 1;      // a batch's rounds recur: capture at first sight
             if (g_batch_engine->staging.init(kStagingBytes) != MG_OK) {
                 delete g_batch_engine;
                 g_batch_engine = nullptr;
@@ -322,6 +338,7 @@ int serve_create(size_t hbm_budget_bytes, int32_t max_inflight, void** server) {
     if (!S) return MG_ERR_OOM;
     S->budget = hbm_budget_bytes;
     S->max_inflight = max_inflight;
+    S->engine.graph_mode = 2;                    // capture an active set once it recurs
     hipGetDevice(&S->device);
     hipError_t e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -384,7 +401,9 @@ int serve_poll(void* server, uint64_t ticket, mg_stats* out) {
     Job* j = it->second.get();
     if (j->t_done == 0.0) return MG_PENDING;
     if (out) *out = j->st;
-    return j->status;
+    const int status = j->status;
+    if (j->waiters == 0) S->jobs.erase(it);   // final status returned: the ticket is released
+    return status;
 }
 
 int serve_wait(void* server, uint64_t ticket, mg_stats* out) {
@@ -397,9 +416,13 @@ int serve_wait(void* server, uint64_t ticket, mg_stats* out) {
         return MG_ERR_INVALID_ARG;
     }
     Job* j = it->second.get();
+    j->waiters += 1;
     S->done_cv.wait(lk, [&] { return j->t_done != 0.0; });
+    j->waiters -= 1;
     if (out) *out = j->st;
-    return j->status;
+    const int status = j->status;
+    if (j->waiters == 0) S->jobs.erase(ticket);   // final status returned: the ticket is released
+    return status;
 }
 
 int serve_counters(void* server, double out[6]) {

@@ -93,17 +93,27 @@ __device__ inline bool finite_d(double x) { return isfinite(x); }
 // the number of partial rows stays small, with no per-cell index division.
 // ---------------------------------------------------------------------------
 constexpr int kPtX = 64, kPtY = 4;
+// Workgroup (bx, by, bz) of a (gx, gy, gz) grid over problem a.
 template <bool kRhs>
-__global__ __launch_bounds__(kBlock) void k_coeff_rhs(
-    int nx, int ny, int nz, int px, int py, int pz, double h, const double* __restrict__ rho,
-    const double* __restrict__ b0c, const double* __restrict__ b0e, const double* __restrict__ S,
-    const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
-    double* __restrict__ bx, double* __restrict__ by, double* __restrict__ bz,
-    double* __restrict__ f, double* __restrict__ partials, const double* __restrict__ w0) {
+__device__ void coeff_rhs_body(const CoeffDesc& a, int bxi, int byi, int bzi) {
+    const int nx = a.nx, ny = a.ny, nz = a.nz, px = a.px, py = a.py, pz = a.pz;
+    const double h = a.h;
+    const double* __restrict__ rho = a.rho;
+    const double* __restrict__ b0c = a.b0c;
+    const double* __restrict__ b0e = a.b0e;
+    const double* __restrict__ S = a.S;
+    const double* __restrict__ u = a.u;
+    const double* __restrict__ v = a.v;
+    const double* __restrict__ w = a.w;
+    const double* __restrict__ w0 = a.w0;
+    double* __restrict__ bx = a.bx;
+    double* __restrict__ by = a.by;
+    double* __restrict__ bz = a.bz;
+    double* __restrict__ f = a.f;
     double sf = 0.0, saf = 0.0, bad = 0.0, nonfin = 0.0;
-    for (int k = blockIdx.z; k < nz; k += gridDim.z)
-    for (int j = blockIdx.y * kPtY + threadIdx.y; j < ny; j += gridDim.y * kPtY)
-    for (int i = blockIdx.x * kPtX + threadIdx.x; i < nx; i += gridDim.x * kPtX) {
+    for (int k = bzi; k < nz; k += a.gz)
+    for (int j = byi * kPtY + threadIdx.y; j < ny; j += a.gy * kPtY)
+    for (int i = bxi * kPtX + threadIdx.x; i < nx; i += a.gx * kPtX) {
         const size_t c = cidx(i, j, k, nx, ny);
         double rc = rho[c];
         double bk = b0c[k];
@@ -157,8 +167,13 @@ __global__ __launch_bounds__(kBlock) void k_coeff_rhs(
             saf += fabs(fc);
         }
     }
-    const int row = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_reduce_row(sf, saf, bad, nonfin, partials + (size_t)row * kReduceWidth);
+    const int row = (bzi * a.gy + byi) * a.gx + bxi;
+    block_reduce_row(sf, saf, bad, nonfin, a.partials + (size_t)row * kReduceWidth);
+}
+
+template <bool kRhs>
+__global__ __launch_bounds__(kBlock) void k_coeff_rhs(CoeffDesc a) {
+    coeff_rhs_body<kRhs>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partials, int nparts,
@@ -174,23 +189,33 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
     block_reduce_row(a0, a1, a2, a3, out);
 }
 
-__global__ __launch_bounds__(kBlock) void k_shift_norm(size_t N, double* __restrict__ f, double shift,
-                                                       double* __restrict__ partials) {
+// Workgroup b of nb: f -= shift over its strided cells, partial row {sum f^2}.
+__device__ void shift_norm_body(size_t N, double* __restrict__ f, double shift, double* __restrict__ partials,
+                                int b, int nb) {
     double s = 0.0;
-    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock) {
+    for (size_t c = (size_t)b * kBlock + threadIdx.x; c < N; c += (size_t)nb * kBlock) {
         double x = f[c] - shift;
         f[c] = x;
         s += x * x;
     }
-    block_reduce_row(s, 0.0, 0.0, 0.0, partials + (size_t)blockIdx.x * kReduceWidth);
+    block_reduce_row(s, 0.0, 0.0, 0.0, partials + (size_t)b * kReduceWidth);
+}
+
+__device__ void sum_body(size_t N, const double* __restrict__ a, double* __restrict__ partials, int b, int nb) {
+    double s = 0.0;
+    for (size_t c = (size_t)b * kBlock + threadIdx.x; c < N; c += (size_t)nb * kBlock)
+        s += a[c];
+    block_reduce_row(s, 0.0, 0.0, 0.0, partials + (size_t)b * kReduceWidth);
+}
+
+__global__ __launch_bounds__(kBlock) void k_shift_norm(size_t N, double* __restrict__ f, double shift,
+                                                       double* __restrict__ partials) {
+    shift_norm_body(N, f, shift, partials, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum(size_t N, const double* __restrict__ a,
                                                 double* __restrict__ partials) {
-    double s = 0.0;
-    for (size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (size_t)gridDim.x * kBlock)
-        s += a[c];
-    block_reduce_row(s, 0.0, 0.0, 0.0, partials + (size_t)blockIdx.x * kReduceWidth);
+    sum_body(N, a, partials, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -198,14 +223,9 @@ __global__ __launch_bounds__(kBlock) void k_sum(size_t N, const double* __restri
 // fine faces it covers (orders as in the reference definition).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_avg_coeff(int nx, int ny, int nz, const T* __restrict__ bx, const T* __restrict__ by,
-                            const T* __restrict__ bz, T* __restrict__ cbx, T* __restrict__ cby,
-                            T* __restrict__ cbz) {
-    int cx = nx / 2, cy = ny / 2, cz = nz / 2;
-    int I = blockIdx.x * blockDim.x + threadIdx.x;
-    int J = blockIdx.y * blockDim.y + threadIdx.y;
-    int K = blockIdx.z * blockDim.z + threadIdx.z;
-    if (I >= cx || J >= cy || K >= cz) return;
+__device__ inline void avg_coeff_cell(int nx, int ny, int I, int J, int K, int cx, int cy, const T* __restrict__ bx,
+                                      const T* __restrict__ by, const T* __restrict__ bz, T* __restrict__ cbx,
+                                      T* __restrict__ cby, T* __restrict__ cbz) {
     int i = 2 * I, j = 2 * J, k = 2 * K;
     size_t C = cidx(I, J, K, cx, cy);
     const T q = T(0.25);
@@ -215,6 +235,18 @@ __global__ void k_avg_coeff(int nx, int ny, int nz, const T* __restrict__ bx, co
                   by[cidx(i, j, k + 1, nx, ny)] + by[cidx(i + 1, j, k + 1, nx, ny)]);
     cbz[C] = q * (bz[cidx(i, j, k, nx, ny)] + bz[cidx(i + 1, j, k, nx, ny)] +
                   bz[cidx(i, j + 1, k, nx, ny)] + bz[cidx(i + 1, j + 1, k, nx, ny)]);
+}
+
+template <typename T>
+__global__ void k_avg_coeff(int nx, int ny, int nz, const T* __restrict__ bx, const T* __restrict__ by,
+                            const T* __restrict__ bz, T* __restrict__ cbx, T* __restrict__ cby,
+                            T* __restrict__ cbz) {
+    int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    int J = blockIdx.y * blockDim.y + threadIdx.y;
+    int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= cx || J >= cy || K >= cz) return;
+    avg_coeff_cell<T>(nx, ny, I, J, K, cx, cy, bx, by, bz, cbx, cby, cbz);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,17 +419,14 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(int nx, int ny, int nz, T
 constexpr int kSetupThreads = 1024;
 constexpr int kSetupLdsN = 128;      // matrices up to this order are inverted in LDS
 
+// The workgroup's build and inversion of one problem's coarsest matrix; Ms
+// (order-kSetupLdsN LDS matrix, used when kLds), fac, prow (kCoarseMax
+// each) and shift are LDS scratch of the calling kernel.
 template <bool kLds>
-__global__ __launch_bounds__(kSetupThreads) void k_coarse_setup(int nx, int ny, int nz, double h,
-                                                                const double* __restrict__ bx,
-                                                                const double* __restrict__ by,
-                                                                const double* __restrict__ bz,
-                                                                double* __restrict__ Mg, Bnd<double> bnd,
-                                                                int has_bnd, int singular) {
-    __shared__ double Ms[kLds ? kSetupLdsN * kSetupLdsN : 1];
-    __shared__ double fac[kCoarseMax];      // column p before the elimination step
-    __shared__ double prow[kCoarseMax];     // row p before the elimination step
-    __shared__ double shift;
+__device__ void coarse_setup_body(int nx, int ny, int nz, double h, const double* __restrict__ bx,
+                                  const double* __restrict__ by, const double* __restrict__ bz,
+                                  double* __restrict__ Mg, const Bnd<double>& bnd, int has_bnd, int singular,
+                                  double* Ms, double* fac, double* prow, double& shift) {
     const int n = nx * ny * nz;
     const int tid = threadIdx.x, nt = blockDim.x;
     double* M = kLds ? Ms : Mg;
@@ -434,6 +463,20 @@ __global__ __launch_bounds__(kSetupThreads) void k_coarse_setup(int nx, int ny, 
     gj_invert(M, n, fac, prow);
     if (kLds)
         for (int e = tid; e < n * n; e += nt) Mg[e] = Ms[e];
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(kSetupThreads) void k_coarse_setup(int nx, int ny, int nz, double h,
+                                                                const double* __restrict__ bx,
+                                                                const double* __restrict__ by,
+                                                                const double* __restrict__ bz,
+                                                                double* __restrict__ Mg, Bnd<double> bnd,
+                                                                int has_bnd, int singular) {
+    __shared__ double Ms[kLds ? kSetupLdsN * kSetupLdsN : 1];
+    __shared__ double fac[kCoarseMax];      // column p before the elimination step
+    __shared__ double prow[kCoarseMax];     // row p before the elimination step
+    __shared__ double shift;
+    coarse_setup_body<kLds>(nx, ny, nz, h, bx, by, bz, Mg, bnd, has_bnd, singular, Ms, fac, prow, shift);
 }
 
 template <typename T>
@@ -477,16 +520,12 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
 // Velocity correction: U <- U - (b/beta0)_f (phi_c - phi_nb)/h on every
 // non-wall face (low faces of each cell), periodic duplicate faces refreshed.
 // ---------------------------------------------------------------------------
-__global__ void k_correct(int nx, int ny, int nz, int px, int py, int pz, double h,
-                          const double* __restrict__ b0c, const double* __restrict__ b0e,
-                          const double* __restrict__ bx, const double* __restrict__ by,
-                          const double* __restrict__ bz, const double* __restrict__ phi,
-                          const double* __restrict__ phi_sum, double* __restrict__ u,
-                          double* __restrict__ v, double* __restrict__ w, double* __restrict__ phi_out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int k = blockIdx.z * blockDim.z + threadIdx.z;
-    if (i >= nx || j >= ny || k >= nz) return;
+__device__ inline void correct_cell(int i, int j, int k, int nx, int ny, int nz, int px, int py, int pz, double h,
+                                    const double* __restrict__ b0c, const double* __restrict__ b0e,
+                                    const double* __restrict__ bx, const double* __restrict__ by,
+                                    const double* __restrict__ bz, const double* __restrict__ phi,
+                                    const double* __restrict__ phi_sum, double* __restrict__ u,
+                                    double* __restrict__ v, double* __restrict__ w, double* __restrict__ phi_out) {
     const size_t N = (size_t)nx * ny * nz;
     const double m = phi_sum[0] / (double)N;
     size_t c = cidx(i, j, k, nx, ny);
@@ -517,6 +556,19 @@ __global__ void k_correct(int nx, int ny, int nz, int px, int py, int pz, double
         w[e] = wn;
         if (pz && k == 0) w[e + (size_t)nz * plane] = wn;
     }
+}
+
+__global__ void k_correct(int nx, int ny, int nz, int px, int py, int pz, double h,
+                          const double* __restrict__ b0c, const double* __restrict__ b0e,
+                          const double* __restrict__ bx, const double* __restrict__ by,
+                          const double* __restrict__ bz, const double* __restrict__ phi,
+                          const double* __restrict__ phi_sum, double* __restrict__ u,
+                          double* __restrict__ v, double* __restrict__ w, double* __restrict__ phi_out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y * blockDim.y + threadIdx.y;
+    int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= nx || j >= ny || k >= nz) return;
+    correct_cell(i, j, k, nx, ny, nz, px, py, pz, h, b0c, b0e, bx, by, bz, phi, phi_sum, u, v, w, phi_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -843,13 +895,22 @@ static dim3 point_grid(const Shape& s) {
     return dim3(gx, gy, gz);
 }
 
+int coeff_grid(const Shape& s, int g[3]) {
+    const dim3 d = point_grid(s);
+    g[0] = (int)d.x;
+    g[1] = (int)d.y;
+    g[2] = (int)d.z;
+    return g[0] * g[1] * g[2];
+}
+
 hipError_t launch_coeff_rhs(const Shape& s, int px, int py, int pz, double h, const double* rho,
                             const double* b0c, const double* b0e, const double* S, const double* u,
                             const double* v, const double* w, double* bx, double* by, double* bz,
                             double* f, double* partials, int* nparts, hipStream_t st, const double* w0) {
     const dim3 g = point_grid(s);
-    hipLaunchKernelGGL(k_coeff_rhs<true>, g, dim3(kPtX, kPtY), 0, st, s.nx, s.ny, s.nz, px, py, pz, h,
-                       rho, b0c, b0e, S, u, v, w, bx, by, bz, f, partials, w0);
+    const CoeffDesc a{s.nx, s.ny, s.nz, px, py, pz, h, rho, b0c, b0e, S, u, v, w, w0, bx, by, bz, f, partials,
+                      (int)g.x, (int)g.y, (int)g.z, 0};
+    hipLaunchKernelGGL(k_coeff_rhs<true>, g, dim3(kPtX, kPtY), 0, st, a);
     *nparts = (int)(g.x * g.y * g.z);
     return hipGetLastError();
 }
@@ -858,9 +919,9 @@ hipError_t launch_coeff(const Shape& s, int px, int py, int pz, const double* rh
                         const double* b0e, double* bx, double* by, double* bz, double* partials,
                         int* nparts, hipStream_t st) {
     const dim3 g = point_grid(s);
-    hipLaunchKernelGGL(k_coeff_rhs<false>, g, dim3(kPtX, kPtY), 0, st, s.nx, s.ny, s.nz, px, py, pz, 1.0,
-                       rho, b0c, b0e, nullptr, nullptr, nullptr, nullptr, bx, by, bz, nullptr, partials,
-                       (const double*)nullptr);
+    const CoeffDesc a{s.nx, s.ny, s.nz, px, py, pz, 1.0, rho, b0c, b0e, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      bx, by, bz, nullptr, partials, (int)g.x, (int)g.y, (int)g.z, 0};
+    hipLaunchKernelGGL(k_coeff_rhs<false>, g, dim3(kPtX, kPtY), 0, st, a);
     *nparts = (int)(g.x * g.y * g.z);
     return hipGetLastError();
 }
@@ -1148,7 +1209,8 @@ MG_INST(float)
 namespace mg {
 namespace {
 
-__device__ inline int find_problem(const CellDesc* __restrict__ d, int nprob, int b) {
+template <typename D>
+__device__ inline int find_problem(const D* __restrict__ d, int nprob, int b) {
     int lo = 0, hi = nprob;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -1274,9 +1336,127 @@ __global__ __launch_bounds__(kBlock) void k_reduce_multi(const ReduceDesc* __res
         a3 += p[3];
     }
     block_reduce_row(a0, a1, a2, a3, r.out);
+    if (threadIdx.x == 0 && r.copy)
+        for (int q = 0; q < kReduceWidth; ++q) r.copy[q] = r.out[q];
+}
+
+// ---- batched set-up and finishing kernels ----------------------------------
+__global__ __launch_bounds__(kBlock) void k_coeff_rhs_multi(const CoeffDesc* __restrict__ d, int nprob) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const CoeffDesc a = d[p];
+    const int b = blockIdx.x - a.block0;
+    const int bxi = b % a.gx, byi = (b / a.gx) % a.gy, bzi = b / (a.gx * a.gy);
+    if (a.S) coeff_rhs_body<true>(a, bxi, byi, bzi);
+    else coeff_rhs_body<false>(a, bxi, byi, bzi);
+}
+
+__global__ __launch_bounds__(kBlock) void k_shift_norm_multi(const RowDesc* __restrict__ d, int nprob) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const RowDesc r = d[p];
+    shift_norm_body(r.N, r.a, r.shift, r.partials, blockIdx.x - r.block0, r.nb);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_multi(const RowDesc* __restrict__ d, int nprob) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const RowDesc r = d[p];
+    sum_body(r.N, r.a, r.partials, blockIdx.x - r.block0, r.nb);
+}
+
+// threads cover the coarse cells of each problem's level
+__global__ __launch_bounds__(256) void k_avg_coeff_multi(const AvgDesc* __restrict__ d, int nprob) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const AvgDesc a = d[p];
+    const int cx = a.nx / 2, cy = a.ny / 2, cz = a.nz / 2;
+    const long long t = (long long)(blockIdx.x - a.block0) * 256 + threadIdx.x;
+    if (t >= (long long)cx * cy * cz) return;
+    const int I = (int)(t % cx), J = (int)((t / cx) % cy), K = (int)(t / ((long long)cx * cy));
+    avg_coeff_cell<double>(a.nx, a.ny, I, J, K, cx, cy, a.bx, a.by, a.bz, a.cbx, a.cby, a.cbz);
+}
+
+// one workgroup per problem
+template <bool kLds>
+__global__ __launch_bounds__(kSetupThreads) void k_coarse_setup_multi(const CoarseDesc* __restrict__ d) {
+    __shared__ double Ms[kLds ? kSetupLdsN * kSetupLdsN : 1];
+    __shared__ double fac[kCoarseMax];
+    __shared__ double prow[kCoarseMax];
+    __shared__ double shift;
+    const CoarseDesc c = d[blockIdx.x];
+    const Bnd<double> none{};
+    coarse_setup_body<kLds>(c.nx, c.ny, c.nz, c.h, c.bx, c.by, c.bz, c.minv, none, 0, c.singular, Ms, fac, prow,
+                            shift);
+}
+
+__global__ __launch_bounds__(256) void k_elt_multi(const EltDesc* __restrict__ d, int nprob) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const EltDesc c = d[p];
+    const size_t e = (size_t)(blockIdx.x - c.block0) * 256 + threadIdx.x;
+    if (e >= c.n) return;
+    switch (c.op) {
+        case kEltFill: ((double*)c.dst)[e] = c.s; break;
+        case kEltToF32: ((float*)c.dst)[e] = (float)c.src[e]; break;
+        default: ((float*)c.dst)[e] = (float)(c.src[e] * c.s); break;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_correct_multi(const CorrectDesc* __restrict__ d, int nprob) {
+    const int p = find_problem(d, nprob, blockIdx.x);
+    const CorrectDesc c = d[p];
+    const long long t = (long long)(blockIdx.x - c.block0) * 256 + threadIdx.x;
+    if (t >= (long long)c.nx * c.ny * c.nz) return;
+    const int i = (int)(t % c.nx), j = (int)((t / c.nx) % c.ny), k = (int)(t / ((long long)c.nx * c.ny));
+    correct_cell(i, j, k, c.nx, c.ny, c.nz, c.px, c.py, c.pz, c.h, c.b0c, c.b0e, c.bx, c.by, c.bz, c.phi, c.phi_sum,
+                 c.u, c.v, c.w, c.phi_out);
 }
 
 }  // namespace
+
+int row_blocks(size_t n) { return partial_blocks(n); }
+int elt_blocks(size_t n) { return (int)((n + 255) / 256); }
+int cell_blocks(size_t n) { return (int)((n + 255) / 256); }
+bool coarse_setup_in_lds(size_t n) { return n <= (size_t)kSetupLdsN; }
+
+hipError_t launch_coeff_rhs_multi(const CoeffDesc* d, int nprob, int blocks, hipStream_t st) {
+    if (nprob <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coeff_rhs_multi, dim3(blocks), dim3(kPtX, kPtY), 0, st, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_norm_multi(const RowDesc* d, int nprob, int blocks, hipStream_t st) {
+    if (nprob <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shift_norm_multi, dim3(blocks), dim3(kBlock), 0, st, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_multi(const RowDesc* d, int nprob, int blocks, hipStream_t st) {
+    if (nprob <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_multi, dim3(blocks), dim3(kBlock), 0, st, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_avg_coeff_multi(const AvgDesc* d, int nprob, int blocks, hipStream_t st) {
+    if (nprob <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_avg_coeff_multi, dim3(blocks), dim3(256), 0, st, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_setup_multi(const CoarseDesc* d, int nprob, bool lds, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    if (lds) hipLaunchKernelGGL(k_coarse_setup_multi<true>, dim3(nprob), dim3(kSetupThreads), 0, st, d);
+    else hipLaunchKernelGGL(k_coarse_setup_multi<false>, dim3(nprob), dim3(kSetupThreads), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_elt_multi(const EltDesc* d, int nprob, int blocks, hipStream_t st) {
+    if (nprob <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_elt_multi, dim3(blocks), dim3(256), 0, st, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct_multi(const CorrectDesc* d, int nprob, int blocks, hipStream_t st) {
+    if (nprob <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_correct_multi, dim3(blocks), dim3(256), 0, st, d, nprob);
+    return hipGetLastError();
+}
 
 hipError_t launch_rbgs_multi(const CellDesc* d, int nprob, int blocks, int colour, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;

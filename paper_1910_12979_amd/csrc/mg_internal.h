@@ -67,6 +67,8 @@ struct Level {
     LevelArrays<float> s;    // FP32 mirrors (mixed precision only)
     double* phi2_d = nullptr;  // second phi buffer (out-of-place sweeps swap with d.phi)
     float* phi2_s = nullptr;
+    double* phi_home_d[2] = {};  // the two phi buffers as laid out (d.phi, phi2_d at set-up)
+    float* phi_home_s[2] = {};
     double* bnd_d[6] = {};   // outflow boundary-face coefficients (null: not an outflow side)
     float* bnd_s[6] = {};    // FP32 mirrors (mixed precision only)
     double* dg_d = nullptr;  // per-cell boundary diagonal (outflow sides), FP64
@@ -297,12 +299,112 @@ struct ReduceDesc {
     const double* partials;
     int nparts;
     double* out;             // 4 doubles
+    double* copy;            // nullable: a second copy of the row (a gathered block)
+};
+// Level-0 coefficients (+ right-hand side) of one problem: the arguments of
+// launch_coeff_rhs, its point-loop grid gx x gy x gz (coeff_grid) and, in a
+// batched launch, its first block.
+struct CoeffDesc {
+    int nx, ny, nz, px, py, pz;
+    double h;
+    const double* rho;
+    const double* b0c;
+    const double* b0e;
+    const double* S;         // null: coefficients only
+    const double* u;
+    const double* v;
+    const double* w;
+    const double* w0;        // nullable
+    double* bx;
+    double* by;
+    double* bz;
+    double* f;
+    double* partials;
+    int gx, gy, gz;
+    int block0;
+};
+// A strided loop over N cells with one partial row per block (nb blocks, as
+// the single-problem launch): a -= shift with rows {sum a^2} (shift-norm) or
+// rows {sum a} (sum).
+struct RowDesc {
+    size_t N;
+    double* a;
+    double shift;
+    double* partials;
+    int nb;
+    int block0;
+};
+// Coarse coefficients of one fine level (nx, ny, nz) into the next.
+struct AvgDesc {
+    int nx, ny, nz;
+    const double* bx;
+    const double* by;
+    const double* bz;
+    double* cbx;
+    double* cby;
+    double* cbz;
+    int block0;
+};
+// Coarsest-level matrix build and inversion of one problem (no outflow sides).
+struct CoarseDesc {
+    int nx, ny, nz;
+    double h;
+    const double* bx;
+    const double* by;
+    const double* bz;
+    double* minv;
+    int singular;
+};
+// Elementwise operations over n values: kEltFill dst[e] = s (FP64),
+// kEltToF32 dst[e] = (float)src[e], kEltScaleToF32 dst[e] = (float)(src[e] * s).
+enum { kEltFill = 0, kEltToF32 = 1, kEltScaleToF32 = 2 };
+struct EltDesc {
+    int op;
+    int block0;
+    size_t n;
+    const double* src;
+    void* dst;
+    double s;
+};
+// Velocity correction of one problem (the arguments of launch_correct).
+struct CorrectDesc {
+    int nx, ny, nz, px, py, pz;
+    double h;
+    const double* b0c;
+    const double* b0e;
+    const double* bx;
+    const double* by;
+    const double* bz;
+    const double* phi;
+    const double* phi_sum;
+    double* u;
+    double* v;
+    double* w;
+    double* phi_out;
+    int block0;
 };
 hipError_t launch_rbgs_multi(const CellDesc* d, int nprob, int blocks, int colour, hipStream_t st);
 hipError_t launch_resid_restrict_multi(const CellDesc* d, int nprob, int blocks, hipStream_t st);
 hipError_t launch_prolong_multi(const CellDesc* d, int nprob, int blocks, hipStream_t st);
 hipError_t launch_coarse_solve_multi(const CellDesc* d, int nprob, hipStream_t st);
 hipError_t launch_reduce_multi(const ReduceDesc* d, int nprob, hipStream_t st);
+// Batched set-up and finishing kernels: problem p owns blocks [d[p].block0,
+// d[p+1].block0) of a launch of `blocks` workgroups (one per problem for the
+// coarsest set-up), and every problem's values are the ones its
+// single-problem launch gives (same per-block work and partial rows).
+int coeff_grid(const Shape& s, int g[3]);          // point-loop grid; returns its blocks
+int row_blocks(size_t n);                          // blocks of a shift-norm / sum over n cells
+int elt_blocks(size_t n);                          // blocks of an elementwise op over n values
+int cell_blocks(size_t n);                         // blocks of a one-thread-per-cell loop (256 threads)
+hipError_t launch_coeff_rhs_multi(const CoeffDesc* d, int nprob, int blocks, hipStream_t st);
+hipError_t launch_shift_norm_multi(const RowDesc* d, int nprob, int blocks, hipStream_t st);
+hipError_t launch_sum_multi(const RowDesc* d, int nprob, int blocks, hipStream_t st);
+hipError_t launch_avg_coeff_multi(const AvgDesc* d, int nprob, int blocks, hipStream_t st);
+// lds: every problem's coarsest level has at most 128 cells (inverted in LDS)
+hipError_t launch_coarse_setup_multi(const CoarseDesc* d, int nprob, bool lds, hipStream_t st);
+bool coarse_setup_in_lds(size_t n);
+hipError_t launch_elt_multi(const EltDesc* d, int nprob, int blocks, hipStream_t st);
+hipError_t launch_correct_multi(const CorrectDesc* d, int nprob, int blocks, hipStream_t st);
 // Mixed precision: the scale update of launch_next_scale for many problems.
 struct ScaleDesc {
     const double* res;       // reduced residual row (sum r^2 first)

@@ -145,6 +145,10 @@ size_t layout(mg_hierarchy* H, const mg_params* p, char* base) {
             H->lev[l].s = s;
             H->lev[l].phi2_d = phi2_d;
             H->lev[l].phi2_s = phi2_s;
+            H->lev[l].phi_home_d[0] = d.phi;
+            H->lev[l].phi_home_d[1] = phi2_d;
+            H->lev[l].phi_home_s[0] = s.phi;
+            H->lev[l].phi_home_s[1] = phi2_s;
             H->lev[l].has_bnd = false;
             H->lev[l].dg_d = dgd;
             H->lev[l].dg_s = dgs;
@@ -397,11 +401,18 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
     HIPCHK(launch_coarse_setup(shape_of(Lc), Lc.h, Lc.d.bx, Lc.d.by, Lc.d.bz, H->minv, st,
                                Lc.has_bnd ? &cb : nullptr, H->singular ? 1 : 0));
     if (H->p.precision == MG_MIXED) {
+        // FP32 coefficient mirrors; a fused finest level with a plane-parallel
+        // beta0 recomputes its FP32 coefficients from an FP32 copy of rho, so
+        // its stored ones are not mirrored
+        const bool fused0 = H->rho.rho != nullptr && H->p.pre_sweeps >= 1 && H->nlev > 1 &&
+                            sweep_fusable<double>(L0.nx, L0.ny, L0.nz);
         for (int l = 0; l < H->nlev; ++l) {
             Level& L = H->lev[l];
-            HIPCHK(launch_coeff_to_f32(L.d.bx, L.s.bx, L.N, st));
-            HIPCHK(launch_coeff_to_f32(L.d.by, L.s.by, L.N, st));
-            HIPCHK(launch_coeff_to_f32(L.d.bz, L.s.bz, L.N, st));
+            if (!(l == 0 && fused0)) {
+                HIPCHK(launch_coeff_to_f32(L.d.bx, L.s.bx, L.N, st));
+                HIPCHK(launch_coeff_to_f32(L.d.by, L.s.by, L.N, st));
+                HIPCHK(launch_coeff_to_f32(L.d.bz, L.s.bz, L.N, st));
+            }
             for (int q = 0; q < 6; ++q)
                 if (L.bnd_d[q]) HIPCHK(launch_coeff_to_f32(L.bnd_d[q], L.bnd_s[q], bnd_count(q, L.nx, L.ny, L.nz), st));
             if (L.has_bnd) HIPCHK(launch_bnd_diag3<float>(shape_of(L), L.bnd32(), L.dg_s, st));
