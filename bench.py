@@ -19,8 +19,13 @@ Also reported on the same JSON line:
     refinement) and its phi difference from the FP64 GPU solve;
   * batch: 64 independent boxes with edges from {32,48,64,96,128} solved by
     project_batch, against the same problems solved one by one;
+  * n512: the 512^3 box (H = 0.15, 5% density noise) in mixed precision and
+    in FP64, with every solve's phi error against the FP64 oracle's exact
+    discrete solution (definition mode, computed once on the host);
   * serve: Poisson request streams of {32,64,128,256}^3 boxes through the
-    continuous-batching server, solves/s with p50/p99 latency per rate;
+    continuous-batching server at 50 to 2000 req/s (2000 requests per rate
+    after 200 warm-up), solves/s with p50/p99 latency per rate, in FP64 and
+    at two rates in mixed precision;
   * full_rhs: the box with its base state given as p0 and Gamma1 (beta0
     computed on the device each step, dp0/dt term in the right-hand side);
   * cpu_baseline: the FP64 CPU oracle timed on the host cores on whole
@@ -36,6 +41,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -129,12 +136,15 @@ def smoother_leg(args, torch, H, R):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_reps):
-        H.level_step(0, "smooth", 1)                         # one launch = one red+black sweep
-    e1.record(stream)
-    e1.synchronize()
-    launch_ms = e0.elapsed_time(e1) / args.kernel_reps
+    batches = []
+    for _ in range(5):                                       # median of 5 batches of back-to-back launches
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            H.level_step(0, "smooth", 1)                     # one launch = one red+black sweep
+        e1.record(stream)
+        e1.synchronize()
+        batches.append(e0.elapsed_time(e1) / args.kernel_reps)
+    launch_ms = sorted(batches)[2]
     launch_bytes = SWEEP_BYTES_PER_CELL * N
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
 
@@ -170,12 +180,18 @@ def smoother_leg(args, torch, H, R):
     if (SWEEP_TRAFFIC and SWEEP_TRAFFIC["sha1"] == sha and tile is not None
             and list(SWEEP_TRAFFIC["tile"]) == list(tile[:3]) and SWEEP_TRAFFIC["n"] == args.n):
         traffic = SWEEP_TRAFFIC["read"] + SWEEP_TRAFFIC["write"]
+    # the HBM bytes the counters saw, over the same launch time: what the
+    # memory system actually moved (the sweep recomputes its coefficients
+    # from rho, so it moves fewer bytes than the algorithmic figure)
+    counter_gbs = traffic / (launch_ms * 1e-3) / 1e9 if traffic else None
     tx, ty, tz = tile[:3] if tile else (0, 0, 0)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "achieved_counter_GBs": counter_gbs,
+            "frac_counter": counter_gbs / HBM_PEAK_GBS if counter_gbs else None,
             "kernel": f"mg::k_sweep<double, {tx}, {ty}, true, 1, 0, false> (finest level, coefficients from rho, "
                       f"one red+black sweep per launch, {tx}x{ty}-cell tiles, {tz}-plane z-chunks)",
-            "launch_ms": launch_ms, "bytes_per_launch": launch_bytes,
+            "launch_ms": launch_ms, "launch_ms_batches": batches, "bytes_per_launch": launch_bytes,
             "bytes_per_cell": SWEEP_BYTES_PER_CELL,
             "kernel_bytes_per_cell": SWEEP_KERNEL_BYTES_PER_CELL,
             "achieved_at_kernel_bytes": SWEEP_KERNEL_BYTES_PER_CELL * N / (launch_ms * 1e-3) / 1e9,
@@ -184,7 +200,7 @@ def smoother_leg(args, torch, H, R):
             "sweep_source_sha1": sha}
 
 
-def mixed_leg(args, torch, macproj, R, phi64):
+def mixed_leg(args, torch, macproj, R, phi64, phi_ref=None):
     d = R.d
     Hm = macproj.Hierarchy(macproj.params_of(R.prob, precision="mixed"))
 
@@ -206,11 +222,13 @@ def mixed_leg(args, torch, macproj, R, phi64):
     for st in mst:
         assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
     diff = float(torch.linalg.norm(d.phi - phi64) / torch.linalg.norm(phi64))
+    err = float(torch.linalg.norm(d.phi - phi_ref) / torch.linalg.norm(phi_ref)) if phi_ref is not None else None
     Hm.close()
     return {"value": args.mixed_steps / tm, "unit": "solves/s", "ms_per_step": tm * 1e3 / args.mixed_steps,
             "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
             "refinement_steps": mst[-1]["cycles"], "rel_resid": mst[-1]["rel_resid"],
-            "phi_rel_diff_vs_fp64_gpu": diff}
+            "ms_smooth": mst[-1]["ms_smooth"], "ms_other": mst[-1]["ms_other"],
+            "phi_rel_diff_vs_fp64_gpu": diff, "phi_rel_err_vs_fp64_oracle": err}
 
 
 def batch_leg(args, torch, macproj, inputs, dev):
@@ -289,7 +307,7 @@ def serve_leg(args, torch, macproj, inputs, dev):
     free set of its size, has its velocity restored and is submitted at its
     arrival time.  Latency = (submission delay past the arrival time) +
     the server's submit-to-done time."""
-    pools = {32: 12, 64: 10, 128: 6, 256: 3}
+    pools = {32: 32, 64: 24, 128: 12, 256: 8}
     log("serve: generating buffer sets")
     sets = {}
     for e, m in pools.items():
@@ -297,8 +315,9 @@ def serve_leg(args, torch, macproj, inputs, dev):
                                                              seed=50000 + 100 * e + k), dev) for k in range(m)]
     torch.cuda.synchronize()
     out = []
-    for rate in args.serve_rates:
-        reqs = inputs.serving_requests(args.serve_requests, rate)
+    runs = [(r, "fp64") for r in args.serve_rates] + [(r, "mixed") for r in args.serve_mixed_rates]
+    for rate, prec in runs:
+        reqs = inputs.serving_requests(args.serve_warmup + args.serve_requests, rate)
         S = macproj.Server(hbm_budget_bytes=200 << 30, max_inflight=64)
         busy = {e: [None] * len(v) for e, v in sets.items()}   # ticket holding each set
         done = {}
@@ -321,37 +340,50 @@ def serve_leg(args, torch, macproj, inputs, dev):
             finish(busy[e][k])
             return k
 
-        log(f"serve: {len(reqs)} requests at {rate} req/s")
+        log(f"serve ({prec}): {len(reqs)} requests at {rate} req/s ({args.serve_warmup} warm-up)")
         tickets = []
         t0 = time.perf_counter()
-        for (ta, e, H, tol, _seed) in reqs:
+        t_meas = None
+        for q, (ta, e, H, tol, _seed) in enumerate(reqs):
             now = time.perf_counter() - t0
             if ta > now:
                 time.sleep(ta - now)
+            if q == args.serve_warmup:
+                t_meas = time.perf_counter() - t0
             k = free_set(e)
             r = sets[e][k]
             r.restore()
-            p = macproj.params_of(r.prob, rtol=tol)
+            p = macproj.params_of(r.prob, rtol=tol, precision=prec)
             delay = max(0.0, time.perf_counter() - t0 - ta)
             t = S.submit(p, r.d)
             busy[e][k] = t
-            tickets.append((t, delay, e, tol))
-        for t, _, _, _ in tickets:
+            tickets.append((t, delay, e, tol, q >= args.serve_warmup))
+        for t, _, _, _, _ in tickets:
             finish(t)
         t_end = time.perf_counter() - t0
         c = S.counters()
         S.close()
         lat = []
-        for t, delay, e, tol in tickets:
+        for t, delay, e, tol, measured in tickets:
             st = done[t]
             assert st["status_name"] == "OK" and st["rel_resid"] <= tol, (e, st)
-            lat.append(delay * 1e3 + st["ms_total"])
-        mix = {e: sum(1 for _, _, ee, _ in tickets if ee == e) for e in pools}
-        out.append({"rate": rate, "requests": len(reqs), "solves_per_s": len(reqs) / t_end,
+            if measured:
+                lat.append(delay * 1e3 + st["ms_total"])
+        meas = [x for x in tickets if x[4]]
+        mix = {e: sum(1 for x in meas if x[2] == e) for e in pools}
+        t_meas = t_meas if t_meas is not None else 0.0
+        out.append({"rate": rate, "precision": prec, "requests": len(meas), "warmup": args.serve_warmup,
+                    "solves_per_s": len(meas) / max(t_end - t_meas, 1e-9),
                     "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                     "peak_inflight": c["peak_inflight"], "mix": mix})
+        log(f"serve ({prec}) {rate} req/s: {out[-1]['solves_per_s']:.1f} solves/s, "
+            f"p50 {out[-1]['p50_ms']:.2f} ms, p99 {out[-1]['p99_ms']:.2f} ms")
     del sets
-    return {"budget_bytes": 200 << 30, "max_inflight": 64, "precision": "fp64", "rates": out}
+    return {"budget_bytes": 200 << 30, "max_inflight": 64,
+            "workload": "open-loop Poisson arrivals; sizes 32/64/128/256^3 with weights 0.4/0.3/0.2/0.1, "
+                        "H ~ U(0.08, 0.5), rtol 1e-8 or 1e-10 per request; latency = submission delay past the "
+                        "arrival time + submit-to-done; solves/s over the measured requests",
+            "rates": out}
 
 
 def full_leg(args, torch, macproj, inputs, dev):
@@ -481,6 +513,66 @@ def boxes_leg(args, torch, macproj, R):
     return out
 
 
+def n512_leg(args, torch, macproj, inputs, dev):
+    """The 512^3 box (H = 0.15, 5% density noise): mixed precision (FP32
+    cycles, FP64 refinement) against FP64, every solve's phi compared with the
+    FP64 oracle's exact discrete solution (definition mode)."""
+    from oracle import oracle as orc
+    prob = inputs.MIXED_512()
+    log("512^3: FP64 oracle, definition mode (host)")
+    tc = time.perf_counter()
+    ref = orc.mac_project(prob, mode="definition")
+    t_oracle = time.perf_counter() - tc
+    assert ref["status"] == 0
+    R = Restorable(macproj, prob, dev)
+    d = R.d
+    phi_ref = torch.from_numpy(ref["phi"]).to(dev)
+    nref = float(torch.linalg.norm(phi_ref))
+    del ref
+    out = {"workload": "512^3 box, beta0 = exp(-z/0.15), rho = beta0 (1 + 0.05 N(0,1)), S = 0.1 N(0,1) "
+                       "weighted-mean-removed, periodic x,y, walls z, rtol 1e-10",
+           "oracle_definition_s": t_oracle}
+    for prec in ("mixed", "fp64"):
+        H = macproj.Hierarchy(macproj.params_of(prob, precision=prec))
+
+        def step():
+            R.restore()
+            return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+
+        log(f"512^3 {prec}: {args.n512_steps} solves")
+        step()
+        torch.cuda.synchronize()
+        errs, lat = [], []
+        tt = 0.0
+        for _ in range(args.n512_steps):
+            ts = time.perf_counter()
+            st = step()
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - ts) * 1e3)
+            tt += lat[-1] * 1e-3
+            assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+            errs.append(float(torch.linalg.norm(d.phi - phi_ref)) / nref)
+        H.close()
+        out[prec] = {"value": args.n512_steps / tt, "unit": "solves/s", "ms_per_step": tt * 1e3 / args.n512_steps,
+                     "cycles": st["cycles"], "rel_resid": st["rel_resid"],
+                     "phi_rel_err_vs_fp64_oracle": errs, "ms_smooth": st["ms_smooth"]}
+    out["mixed_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    del R, phi_ref
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_leg(args, prob):
     log("CPU oracle baseline")
     from oracle import oracle as orc
@@ -493,7 +585,8 @@ def cpu_leg(args, prob):
         tc = time.perf_counter() - tc0
         if tc >= 10.0 or solves >= 8:
             break
-    return {"value": solves / tc, "unit": "solves/s", "cores": orc.max_threads(), "kind": "oracle",
+    return {"value": solves / tc, "unit": "solves/s", "cores": orc.max_threads(), "cpu_model": cpu_model(),
+            "kind": "oracle",
             "sample": f"{solves} full {args.n}^3 FP64 projections of the same box (algorithm mode, "
                       f"{ref['cycles']} V-cycles each), {tc:.1f} s wall"}
 
@@ -508,13 +601,20 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--batch-reps", type=int, default=3, help="0 skips the batch leg")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the batch's shapes first")
-    ap.add_argument("--serve-rates", type=float, nargs="*", default=[100.0, 400.0, 2000.0])
-    ap.add_argument("--serve-requests", type=int, default=150)
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[50.0, 100.0, 200.0, 500.0, 1000.0, 1500.0,
+                                                                     2000.0])
+    ap.add_argument("--serve-mixed-rates", type=float, nargs="*", default=[200.0, 1000.0],
+                    help="rates served in mixed precision")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per rate")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="requests before the measured ones")
+    ap.add_argument("--n512-steps", type=int, default=3, help="0 skips the 512^3 leg")
     ap.add_argument("--full-steps", type=int, default=5, help="0 skips the p0/Gamma1 base-state leg")
     ap.add_argument("--star-steps", type=int, default=5, help="0 skips the radial-base-state outflow leg")
     ap.add_argument("--nodal-steps", type=int, default=3, help="0 skips the nodal-projection leg")
     ap.add_argument("--boxes-steps", type=int, default=3, help="0 skips the multi-box finest-level leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-check", type=int, default=1,
+                    help="compare the headline phi with the FP64 oracle's exact solution (host)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -539,14 +639,32 @@ def main():
     value = args.steps / elapsed
     cycles = stats[-1]["cycles"]
     phi64 = R.d.phi.clone()
+    parity = None
+    phi_ref = None
+    if args.oracle_check:
+        # every timed solve projects the same input: the last one's phi
+        # against the FP64 oracle's exact discrete solution (definition mode)
+        from oracle import oracle as orc
+        log(f"{n}^3: FP64 oracle, definition mode (host)")
+        tc = time.perf_counter()
+        ref = orc.mac_project(prob, mode="definition")
+        assert ref["status"] == 0
+        phi_ref = torch.from_numpy(ref["phi"]).to(dev)
+        parity = {"phi_rel_err_vs_fp64_oracle": float(torch.linalg.norm(phi64 - phi_ref) / torch.linalg.norm(phi_ref)),
+                  "u_rel_err_vs_fp64_oracle": float(np.linalg.norm(R.d.u.cpu().numpy() - ref["u"])
+                                                    / np.linalg.norm(ref["u"])),
+                  "oracle_definition_s": time.perf_counter() - tc,
+                  "ms_smooth": stats[-1]["ms_smooth"], "ms_other": stats[-1]["ms_other"]}
+        del ref
     log("smoother kernel timing")
     roofline = smoother_leg(args, torch, H, R)
     H.close()
 
-    mixed = mixed_leg(args, torch, macproj, R, phi64) if args.mixed_steps > 0 else None
-    del phi64
+    mixed = mixed_leg(args, torch, macproj, R, phi64, phi_ref) if args.mixed_steps > 0 else None
+    del phi64, phi_ref
     batch = batch_leg(args, torch, macproj, inputs, dev) if args.batch_reps > 0 else None
-    serve = serve_leg(args, torch, macproj, inputs, dev) if args.serve_rates else None
+    serve = serve_leg(args, torch, macproj, inputs, dev) if (args.serve_rates or args.serve_mixed_rates) else None
+    n512 = n512_leg(args, torch, macproj, inputs, dev) if args.n512_steps > 0 else None
     full = full_leg(args, torch, macproj, inputs, dev) if args.full_steps > 0 else None
     star = star_leg(args, torch, macproj, inputs, dev) if args.star_steps > 0 else None
     nodal = nodal_leg(args, torch, macproj, inputs, dev) if args.nodal_steps > 0 else None
@@ -571,11 +689,13 @@ def main():
                                f"FP64 V(2,2) red-black GS multigrid to 1e-10",
                    "n": n, "rtol": 1e-10, "precision": "fp64", "cycles": cycles},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "parity": parity,
         "roofline": roofline,
         "model_roofline_frac": value * model_bytes / (HBM_PEAK_GBS * 1e9),
         "mixed": mixed,
         "batch": batch,
         "serve": serve,
+        "n512": n512,
         "full_rhs": full,
         "star_outflow": star,
         "nodal": nodal,

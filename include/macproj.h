@@ -109,11 +109,15 @@ typedef struct {
     int32_t cycles;          /* V-cycles (FP64) or refinement steps (mixed) */
     int32_t nlevels;
     int32_t hist_len;        /* entries used in resid_hist */
+    double  rel_resid0;      /* relative residual of the starting phi = 0: 1 (0 when f = 0) */
     double  rel_resid;       /* final ||f - L phi||_2 / ||f||_2 */
     double  mean_removed;    /* mean of the right-hand side before removal */
     double  sum_f, sum_abs_f, norm_f;
     double  phi_mean;        /* mean removed from phi on exit */
     double  ms_total;        /* device time of the call (HIP events) */
+    double  ms_smooth;       /* of which the multigrid iterations (sweeps, transfers, coarsest
+                                solves, residual norms, refinement) */
+    double  ms_other;        /* the rest: coefficients, right-hand side, checks, correction */
     double  bytes_model;     /* algorithmic HBM bytes of the call */
     double  resid_hist[MG_HIST_MAX]; /* relative residual after c cycles, [0] = 1 */
 } mg_stats;
@@ -313,7 +317,10 @@ int mg_level_step(mg_handle h, int32_t level, int32_t step, int32_t arg, void* s
 
 /* Solve `count` independent problems (any shapes, each with its own params)
  * with shared launches; stats has `count` entries (nullable).  Each result is
- * the one mac_project gives for that problem alone.  Blocks until done. */
+ * the one mac_project gives for that problem alone.  Blocks until done.
+ * stats[i].ms_total is the device time of the whole call, ms_smooth the
+ * wall time from problem i's first iteration to its last (the iterations are
+ * shared launches), ms_other the difference. */
 int project_batch(int32_t count, const mg_problem* probs, mg_stats* stats, void* stream);
 
 /* Continuous-batching server on the current device.  hbm_budget_bytes caps
@@ -329,7 +336,10 @@ int serve_submit(void* server, const mg_problem* prob, uint64_t* ticket);
  * MG_PENDING while the ticket is queued or running; else its final status,
  * with *out (nullable) filled. */
 int serve_poll(void* server, uint64_t ticket, mg_stats* out);
-/* Block until the ticket completes; returns its status. */
+/* Block until the ticket completes; returns its status.  For served
+ * problems stats ms_total is the time from serve_submit to completion
+ * (queueing included), ms_smooth the wall time from the request's first
+ * iteration to its last, ms_other the difference. */
 int serve_wait(void* server, uint64_t ticket, mg_stats* out);
 /* Server counters: [0] submitted, [1] completed, [2] queued, [3] in flight,
  * [4] resident bytes, [5] peak in-flight problems. */
@@ -348,8 +358,33 @@ int mg_tune_sweep(int32_t cfg);
  * (`reps` sweeps each, on `stream`) and keep the fastest per level shape in a
  * process-wide table used by every later solve of that shape.  Needs
  * coefficients (mg_set_coefficients or mac_project); overwrites the
- * hierarchy's own level arrays, never caller data.  Blocks until done. */
+ * hierarchy's own level arrays, never caller data.  Blocks until done.
+ * With the environment variable MACPROJ_TUNE_CACHE naming a file, the table
+ * is read from it on first use and the whole table is written back after
+ * every mg_autotune (a temporary file renamed over it). */
 int mg_autotune(mg_handle h, int32_t reps, void* stream);
+
+/* The tuning table and its cache file, host-side only (no device work).
+ * Entries are keyed by GPU architecture name (arch, NULL = the current
+ * device's gcnArchName), level shape n[3], coefficient source (rho = 1:
+ * recomputed from rho on the finest level), precision (fp64 = 1: FP64) and
+ * coarse (1: a coarse level of a single-problem V-cycle); the value is a
+ * configuration index as for mg_tune_sweep.  The file is JSON
+ * {"format": "macproj-sweep-tune-1", "entries": [{"arch", "n", "rho",
+ * "fp64", "coarse", "cfg", "tile"}, ...]}; entries whose tile does not match
+ * their index in this build are skipped.
+ * mg_tune_cache_save/load: path NULL = MACPROJ_TUNE_CACHE; return the number
+ * of entries written / taken, or MG_ERR_INVALID_ARG (unreadable, unwritable
+ * or malformed file: a malformed file changes nothing).  Loading merges into
+ * the table.  mg_tune_cache_clear empties the table (the environment's file
+ * is then not read again).  mg_tune_record adds or replaces one entry
+ * (MG_ERR_INVALID_ARG for an index out of range or a tile that does not fit
+ * the shape); mg_tune_lookup returns the entry's index or -1. */
+int mg_tune_cache_save(const char* path);
+int mg_tune_cache_load(const char* path);
+int mg_tune_cache_clear(void);
+int mg_tune_record(const char* arch, const int32_t n[3], int32_t rho, int32_t fp64, int32_t coarse, int32_t cfg);
+int mg_tune_lookup(const char* arch, const int32_t n[3], int32_t rho, int32_t fp64, int32_t coarse);
 
 /* Replayable cycles: with enable = 1 (the default) an FP64 solve captures
  * one V-cycle plus the following residual-norm sweep as a hipGraph on the

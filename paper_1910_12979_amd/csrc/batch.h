@@ -55,6 +55,8 @@ struct Job {
     double t_submit = 0.0;
     double t_admit = 0.0;
     double t_done = 0.0;
+    double t_iter0 = 0.0;     // steady-clock seconds at its first iteration, and after its last
+    double t_iter1 = 0.0;
     size_t bytes = 0;
     int waiters = 0;          // serve_wait calls blocked on this ticket
 };

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -179,21 +180,22 @@ int launch_fused(std::vector<Item>& grp, bool use_rho, int in_mode, int op, Stag
             continue;
         }
         std::vector<SweepArgs<double>> descs;
-        std::vector<int> prefix(1, 0);
+        std::vector<int2> tmap;
         for (Item* it : kv.second) {
             SweepArgs<double> a = sweep_args(it->H, it->l);
             sweep_geometry(a, cfg);
+            const int nt = sweep_tiles(a.nx, a.ny, a.nz, cfg);
+            for (int t = 0; t < nt; ++t) tmap.push_back(make_int2((int)descs.size(), t));
             descs.push_back(a);
-            prefix.push_back(prefix.back() + sweep_tiles(a.nx, a.ny, a.nz, cfg));
         }
         void* dd = nullptr;
         void* dp = nullptr;
         int rc = S.push(descs.data(), descs.size() * sizeof(SweepArgs<double>), st, &dd);
         if (rc) return rc;
-        rc = S.push(prefix.data(), prefix.size() * sizeof(int), st, &dp);
+        rc = S.push(tmap.data(), tmap.size() * sizeof(int2), st, &dp);
         if (rc) return rc;
-        BHIP(launch_sweep_multi<double>((const SweepArgs<double>*)dd, (const int*)dp, (int)descs.size(), prefix.back(),
-                                        use_rho, in_mode, op, cfg, st));
+        BHIP(launch_sweep_multi<double>((const SweepArgs<double>*)dd, (const int2*)dp, (int)tmap.size(), use_rho,
+                                        in_mode, op, cfg, st));
     }
     return MG_OK;
 }
@@ -491,21 +493,22 @@ int launch_group(std::vector<SweepArgs<T>>& args, const std::vector<int>& cfgs, 
             continue;
         }
         std::vector<SweepArgs<T>> descs;
-        std::vector<int> prefix(1, 0);
+        std::vector<int2> tmap;
         for (size_t i : kv.second) {
             SweepArgs<T> a = args[i];
             sweep_geometry(a, cfg);
+            const int nt = sweep_tiles(a.nx, a.ny, a.nz, cfg);
+            for (int t = 0; t < nt; ++t) tmap.push_back(make_int2((int)descs.size(), t));
             descs.push_back(a);
-            prefix.push_back(prefix.back() + sweep_tiles(a.nx, a.ny, a.nz, cfg));
         }
         void* dd = nullptr;
         void* dp = nullptr;
         int rc = S.push(descs.data(), descs.size() * sizeof(SweepArgs<T>), st, &dd);
         if (rc) return rc;
-        rc = S.push(prefix.data(), prefix.size() * sizeof(int), st, &dp);
+        rc = S.push(tmap.data(), tmap.size() * sizeof(int2), st, &dp);
         if (rc) return rc;
-        BHIP(launch_sweep_multi<T>((const SweepArgs<T>*)dd, (const int*)dp, (int)descs.size(), prefix.back(), use_rho,
-                                   in_mode, op, cfg, st));
+        BHIP(launch_sweep_multi<T>((const SweepArgs<T>*)dd, (const int2*)dp, (int)tmap.size(), use_rho, in_mode, op,
+                                   cfg, st));
     }
     return MG_OK;
 }
@@ -652,6 +655,10 @@ static void fail_job(Job& j, int status) {
 }
 
 namespace {
+
+double steady_seconds() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 constexpr size_t kArenaMin = (size_t)1 << 20;
 constexpr size_t kMaxRoundGraphs = 8;
@@ -1033,6 +1040,11 @@ int Engine::round(std::vector<Job*>& jobs, hipStream_t st) {
     for (size_t i = 0; i < jrun64.size(); ++i) jrun64[i]->gslot = (int)i;
     for (size_t i = 0; i < jrunm.size(); ++i) jrunm[i]->gslot = (int)(jrun64.size() + i);
     const size_t nrun = jrun64.size() + jrunm.size();
+    const double t_round = steady_seconds();
+    for (Job* j : jrun64)
+        if (j->cycles == 0) j->t_iter0 = t_round;
+    for (Job* j : jrunm)
+        if (j->cycles == 0) j->t_iter0 = t_round;
     if (nrun > 0) {
         rc = iterate(run64, pre_done, runm, st);
         if (rc) return rc;
@@ -1078,12 +1090,21 @@ int Engine::round(std::vector<Job*>& jobs, hipStream_t st) {
         BHIP(hipMemcpyAsync(ghost, gdev, rows * kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
     BHIP(hipStreamSynchronize(st));
     staging.off = 0;
-    for (Job* j : jrun64) std::memcpy(j->row, ghost + (size_t)j->gslot * kReduceWidth, sizeof j->row);
-    for (Job* j : jrunm) std::memcpy(j->row, ghost + (size_t)j->gslot * kReduceWidth, sizeof j->row);
+    const double t_end = steady_seconds();
+    for (Job* j : jrun64) {
+        std::memcpy(j->row, ghost + (size_t)j->gslot * kReduceWidth, sizeof j->row);
+        j->t_iter1 = t_end;
+    }
+    for (Job* j : jrunm) {
+        std::memcpy(j->row, ghost + (size_t)j->gslot * kReduceWidth, sizeof j->row);
+        j->t_iter1 = t_end;
+    }
     for (size_t q = 0; q < fin.size(); ++q) {
         Job* j = fin[q];
         mg_hierarchy* H = j->H;
         j->st.phi_mean = ghost[(nrun + q) * kReduceWidth] / (double)H->lev[0].N;
+        j->st.rel_resid0 = j->st.resid_hist[0];
+        j->st.ms_smooth = j->cycles > 0 ? (j->t_iter1 - j->t_iter0) * 1e3 : 0.0;
         j->st.cycles = j->cycles;
         j->st.rel_resid = j->cycles > 0 ? j->rel : j->st.resid_hist[0];
         if (j->st.hist_len == 1 && j->st.resid_hist[0] == 0.0) j->st.rel_resid = 0.0;

@@ -134,6 +134,7 @@ struct Server {
         {
             std::lock_guard<std::mutex> lk(mu);
             j->st.ms_total = (t - j->t_submit) * 1e3;
+            j->st.ms_other = std::max(0.0, j->st.ms_total - j->st.ms_smooth);
             j->t_done = t;
             completed += 1;
             inflight_n -= 1;
@@ -317,6 +318,7 @@ int project_batch(int32_t count, const mg_problem* probs, mg_stats* stats, void*
             Job& j = jobs[i];
             if (rc != MG_OK && j.stage != Job::kDone) j.st.status = j.status = rc;
             j.st.ms_total = ms;
+            j.st.ms_other = std::max(0.0, (double)ms - j.st.ms_smooth);
             if (stats) stats[i] = j.st;
             if (j.H) g_batch_pool->release(j.H);
             if (j.status != MG_OK && worst == MG_OK) worst = j.status;

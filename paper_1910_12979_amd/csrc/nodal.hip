@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -681,7 +682,11 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
     int status = MG_OK, cycles = 0;
     double rel = 0.0;
     S_->resid_hist[0] = fnorm > 0.0 ? 1.0 : 0.0;
+    S_->rel_resid0 = S_->resid_hist[0];
     S_->hist_len = 1;
+    // every cycle ends with a host synchronisation: the loop's wall time is
+    // the device time of the cycles
+    const auto t_s0 = std::chrono::steady_clock::now();
     if (fnorm > 0.0 && H->p.rtol < 1.0) {
         status = MG_ERR_NOT_CONVERGED;
         bool on_graph = false;
@@ -758,6 +763,8 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
         NHIP(hipEventRecord(H->gev, H->gstream));
         NHIP(hipStreamWaitEvent(st, H->gev, 0));
     }
+    S_->ms_smooth = cycles > 0 ? std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_s0).count()
+                               : 0.0;
     S_->cycles = cycles;
     S_->rel_resid = rel;
     if (status != MG_OK && status != MG_ERR_NOT_CONVERGED) return S_->status = status;
@@ -777,6 +784,7 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
     float ms = 0.f;
     hipEventElapsedTime(&ms, H->ev0, H->ev1);
     S_->ms_total = ms;
+    S_->ms_other = std::max(0.0, S_->ms_total - S_->ms_smooth);
     S_->status = status;
     if (status == MG_ERR_NOT_CONVERGED) set_error("maximum number of cycles reached");
     return status;

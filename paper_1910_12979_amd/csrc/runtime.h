@@ -45,6 +45,7 @@ struct mg_hierarchy {
     double* w0 = nullptr;         // per-layer dp0/dt term (mac_project_full)
     mg::RhoArgs rho{};            // finest-level coefficient source of the current solve
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evs0 = nullptr, evs1 = nullptr;   // around the multigrid iterations of a solve
     // Replayable V-cycles (FP64 solve): one cycle plus the next residual
     // norm captured as a hipGraph, keyed by everything baked into it.
     bool graphs_on = true;

@@ -262,6 +262,8 @@ int setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_hierarchy** o
     }
     hipEventCreate(&H->ev0);
     hipEventCreate(&H->ev1);
+    hipEventCreate(&H->evs0);
+    hipEventCreate(&H->evs1);
     *out = H;
     return MG_OK;
 }
@@ -313,6 +315,8 @@ int destroy(mg_hierarchy* H) {
     if (H->host) hipHostFree(H->host);
     hipEventDestroy(H->ev0);
     hipEventDestroy(H->ev1);
+    hipEventDestroy(H->evs0);
+    hipEventDestroy(H->evs1);
     for (auto& g : H->graph)
         if (g.exec) hipGraphExecDestroy(g.exec);
     if (H->gstream) hipStreamDestroy(H->gstream);
@@ -1176,8 +1180,21 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         if (fnorm == 0.0) {
             HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
         } else {
+            S_->rel_resid0 = 1.0;
+            const auto t_s0 = std::chrono::steady_clock::now();
+            if (H->evs0) HIPCHK(hipEventRecord(H->evs0, st));
             status = solve_level0(H, fnorm, S_, st);
             if (status != MG_OK && status != MG_ERR_NOT_CONVERGED) return S_->status = status;
+            if (H->evs1) {
+                HIPCHK(hipEventRecord(H->evs1, st));
+                HIPCHK(hipEventSynchronize(H->evs1));
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, H->evs0, H->evs1);
+                S_->ms_smooth = ms;
+            } else {       // every iteration ends with a host synchronisation: wall time of the loop
+                S_->ms_smooth =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_s0).count();
+            }
         }
     }
     int np = 0;
@@ -1210,6 +1227,7 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
     } else {
         S_->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
     }
+    S_->ms_other = std::max(0.0, S_->ms_total - S_->ms_smooth);
     S_->bytes_model = model_bytes(H->p, S_->cycles, H->p.precision == MG_MIXED);
     S_->status = status;
     if (status == MG_ERR_NOT_CONVERGED) set_error("maximum number of cycles reached");
@@ -1348,8 +1366,7 @@ int level_step(mg_hierarchy* H, int l, int step, int arg, hipStream_t st) {
 using namespace mg;
 
 namespace {
-int g_forced_cfg_mirror = -1;     // the value last set through mg_tune_sweep
-int g_forced_for_tuner() { return g_forced_cfg_mirror; }
+int g_forced_for_tuner() { return tune_forced(); }
 }  // namespace
 
 extern "C" {
@@ -1606,6 +1623,10 @@ int mg_autotune(mg_handle h, int32_t reps, void* stream) {
     sweep_force_config(saved);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (rc == MG_OK) {
+        const int w = tune_save_env();          // persist the choices when MACPROJ_TUNE_CACHE names a file
+        if (w < 0) return w;
+    }
     return rc;
 }
 
@@ -1615,7 +1636,6 @@ int mg_tune_sweep(int32_t cfg) {
         return MG_ERR_INVALID_ARG;
     }
     sweep_force_config(cfg);
-    g_forced_cfg_mirror = cfg;
     return MG_OK;
 }
 

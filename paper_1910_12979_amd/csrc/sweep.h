@@ -86,13 +86,14 @@ hipError_t launch_resid_restrict_tiled(const SweepArgs<T>& a, bool use_rho, int 
 hipError_t launch_refine(const SweepArgs<double>& a, bool use_rho, int cfg, int* nparts, hipStream_t st);
 
 // Batched form (one launch, many problems): descriptor i (device) is problem
-// i's SweepArgs with tz/ntx/nty filled (sweep_geometry), prefix (device,
-// nprob+1 entries) its first tile; `op` is kOpSweep, kOpResidRestrict, or
-// (FP64 with rho only) kOpSweepNorm (plain input) or kOpRefine (corrected
-// input).  Tile shapes 32x8, 64x8 and 32x4.
+// i's SweepArgs with tz/ntx/nty filled (sweep_geometry); launch tile b is tile
+// tmap[b].y of problem tmap[b].x (device, `tiles` entries, every problem's
+// tiles in order); `op` is kOpSweep, kOpResidRestrict, or (FP64 with rho
+// only) kOpSweepNorm (plain input) or kOpRefine (corrected input).  Tile
+// shapes 32x8, 64x8 and 32x4.
 template <typename T>
-hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
-                              int in_mode, int op, int cfg, hipStream_t st);
+hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int2* tmap, int tiles, bool use_rho, int in_mode, int op,
+                              int cfg, hipStream_t st);
 void sweep_geometry(SweepArgs<double>& a, int cfg);
 void sweep_geometry(SweepArgs<float>& a, int cfg);
 
@@ -144,5 +145,17 @@ void sweep_force_config(int cfg);
 // Incremented whenever a forced or tuned configuration changes (captured
 // launches are only valid for the epoch they were recorded in).
 unsigned sweep_tune_epoch();
+
+// The tuning table (tune.hip): autotuned configurations keyed by the current
+// device's architecture and the level shape / coefficient source /
+// precision / coarse flag, persisted through the file named by
+// MACPROJ_TUNE_CACHE (read on first use, written by tune_save_env).
+int tune_find(int nx, int ny, int nz, bool rho, bool dbl, bool coarse);    // -1: none
+void tune_put(int nx, int ny, int nz, bool rho, bool dbl, bool coarse, int cfg);
+int tune_count();
+unsigned tune_epoch();
+void tune_force(int cfg);          // -1: per-shape choice
+int tune_forced();
+int tune_save_env();               // entries written (0 without MACPROJ_TUNE_CACHE) or an mg_status
 
 }  // namespace mg

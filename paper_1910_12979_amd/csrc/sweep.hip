@@ -567,25 +567,21 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_wave
     sweep_body<double, TX, TY, kRho, kIn, kOp, false, true>(c, t - b * tpb);
 }
 
-// Batched form: problem p owns tiles [prefix[p], prefix[p+1]) of the launch.
+// Batched form: tile b of the launch is tile tmap[b].y of problem tmap[b].x
+// (one load instead of a search over the problems' tile ranges).
 template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
 __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(false) void k_sweep_multi(const SweepArgs<T>* __restrict__ descs,
-                                                                         const int* __restrict__ prefix, int nprob) {
+                                                                         const int2* __restrict__ tmap) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
-    int lo = 0, hi = nprob;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (prefix[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    const SweepArgs<T> a = descs[lo];
-    sweep_body<T, TX, TY, kRho, kIn, kOp, false>(a, b - prefix[lo]);   // batches have no outflow sides
+    const int2 m = tmap[b];
+    const SweepArgs<T> a = descs[m.x];
+    sweep_body<T, TX, TY, kRho, kIn, kOp, false>(a, m.y);   // batches have no outflow sides
 }
 
 template <typename T, int TX, int TY, bool kRho, int kIn, int kOp = kOpSweep>
-hipError_t launch_multi_t(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, hipStream_t st) {
+hipError_t launch_multi_t(const SweepArgs<T>* d, const int2* tmap, int tiles, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_multi<T, TX, TY, kRho, kIn, kOp>), dim3(tiles), dim3((TX / 2 + 2) * (TY + 4)), 0,
-                       st, d, prefix, nprob);
+                       st, d, tmap);
     return hipGetLastError();
 }
 
@@ -623,59 +619,27 @@ hipError_t launch_mode(const SweepArgs<T>& a, bool use_rho, int in_mode, int tzc
     }
 }
 
-int g_forced_cfg = -1;    // set by mg_tune_sweep (-1: per-shape choice)
-
-// Autotuned choices, keyed by level shape and coefficient source.
-struct TuneKey {
-    int nx, ny, nz, rho, dbl, coarse;
-    bool operator<(const TuneKey& o) const {
-        if (coarse != o.coarse) return coarse < o.coarse;
-        if (nx != o.nx) return nx < o.nx;
-        if (ny != o.ny) return ny < o.ny;
-        if (nz != o.nz) return nz < o.nz;
-        if (rho != o.rho) return rho < o.rho;
-        return dbl < o.dbl;
-    }
-};
-std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tuned;
-unsigned g_tune_epoch = 0;
-
 }  // namespace
 
-void sweep_force_config(int cfg) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_forced_cfg = cfg;
-    ++g_tune_epoch;
-}
+void sweep_force_config(int cfg) { tune_force(cfg); }
 
 void sweep_record_tuned(int nx, int ny, int nz, bool rho, bool dbl, int cfg, bool coarse) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[TuneKey{nx, ny, nz, rho ? 1 : 0, dbl ? 1 : 0, coarse ? 1 : 0}] = cfg;
-    ++g_tune_epoch;
+    tune_put(nx, ny, nz, rho, dbl, coarse, cfg);
 }
 
-unsigned sweep_tune_epoch() {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    return g_tune_epoch;
-}
+unsigned sweep_tune_epoch() { return tune_epoch(); }
 
-int sweep_tuned_count() {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    return (int)g_tuned.size();
-}
+int sweep_tuned_count() { return tune_count(); }
 
 bool sweep_cfg_fits(int nx, int ny, int cfg) {
     return cfg >= 0 && cfg < kNumSweepCfg && nx >= kSweepCfgs[cfg].tx && ny >= kSweepCfgs[cfg].ty;
 }
 
 int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl, bool coarse) {
-    if (g_forced_cfg >= 0 && sweep_cfg_fits(nx, ny, g_forced_cfg)) return g_forced_cfg;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find(TuneKey{nx, ny, nz, rho ? 1 : 0, dbl ? 1 : 0, coarse ? 1 : 0});
-        if (it != g_tuned.end()) return it->second;
-    }
+    const int forced = tune_forced();
+    if (forced >= 0 && sweep_cfg_fits(nx, ny, forced)) return forced;
+    const int tuned = tune_find(nx, ny, nz, rho, dbl, coarse);
+    if (tuned >= 0) return tuned;
     // untuned shapes: choices measured on MI355X for cubic levels.  On the
     // largest boxes 64x16-cell tiles (the halo share of the loads and of the
     // redundant red updates is a third lower than with 64x8 tiles): FP64
@@ -807,42 +771,42 @@ hipError_t launch_refine(const SweepArgs<double>& a, bool use_rho, int cfg, int*
 }
 
 template <typename T, int TX, int TY>
-hipError_t launch_multi_mode(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
+hipError_t launch_multi_mode(const SweepArgs<T>* d, const int2* tmap, int tiles, bool use_rho,
                              int in_mode, int op, hipStream_t st) {
     if (use_rho) {
         if constexpr (std::is_same<T, double>::value) {
             if (op == kOpSweepNorm)
-                return launch_multi_t<T, TX, TY, true, kInPlain, kOpSweepNorm>(d, prefix, nprob, tiles, st);
+                return launch_multi_t<T, TX, TY, true, kInPlain, kOpSweepNorm>(d, tmap, tiles, st);
             if (op == kOpRefine)
-                return launch_multi_t<T, TX, TY, true, kInCorrect, kOpRefine>(d, prefix, nprob, tiles, st);
+                return launch_multi_t<T, TX, TY, true, kInCorrect, kOpRefine>(d, tmap, tiles, st);
         } else {
             if (op == kOpSweepNorm || op == kOpRefine) return hipErrorInvalidValue;
         }
         if (op == kOpResidRestrict)
-            return launch_multi_t<T, TX, TY, true, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
+            return launch_multi_t<T, TX, TY, true, kInPlain, kOpResidRestrict>(d, tmap, tiles, st);
         switch (in_mode) {
-            case kInZero: return launch_multi_t<T, TX, TY, true, kInZero>(d, prefix, nprob, tiles, st);
-            case kInPlain: return launch_multi_t<T, TX, TY, true, kInPlain>(d, prefix, nprob, tiles, st);
-            default: return launch_multi_t<T, TX, TY, true, kInProlong>(d, prefix, nprob, tiles, st);
+            case kInZero: return launch_multi_t<T, TX, TY, true, kInZero>(d, tmap, tiles, st);
+            case kInPlain: return launch_multi_t<T, TX, TY, true, kInPlain>(d, tmap, tiles, st);
+            default: return launch_multi_t<T, TX, TY, true, kInProlong>(d, tmap, tiles, st);
         }
     }
     if (op == kOpResidRestrict)
-        return launch_multi_t<T, TX, TY, false, kInPlain, kOpResidRestrict>(d, prefix, nprob, tiles, st);
+        return launch_multi_t<T, TX, TY, false, kInPlain, kOpResidRestrict>(d, tmap, tiles, st);
     switch (in_mode) {
-        case kInZero: return launch_multi_t<T, TX, TY, false, kInZero>(d, prefix, nprob, tiles, st);
-        case kInPlain: return launch_multi_t<T, TX, TY, false, kInPlain>(d, prefix, nprob, tiles, st);
-        default: return launch_multi_t<T, TX, TY, false, kInProlong>(d, prefix, nprob, tiles, st);
+        case kInZero: return launch_multi_t<T, TX, TY, false, kInZero>(d, tmap, tiles, st);
+        case kInPlain: return launch_multi_t<T, TX, TY, false, kInPlain>(d, tmap, tiles, st);
+        default: return launch_multi_t<T, TX, TY, false, kInProlong>(d, tmap, tiles, st);
     }
 }
 
 template <typename T>
-hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int* prefix, int nprob, int tiles, bool use_rho,
-                              int in_mode, int op, int cfg, hipStream_t st) {
+hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int2* tmap, int tiles, bool use_rho, int in_mode, int op,
+                              int cfg, hipStream_t st) {
     if (tiles <= 0) return hipSuccess;
     const SweepCfg& c = kSweepCfgs[cfg];
-    if (c.tx == 32 && c.ty == 8) return launch_multi_mode<T, 32, 8>(d, prefix, nprob, tiles, use_rho, in_mode, op, st);
-    if (c.tx == 64 && c.ty == 8) return launch_multi_mode<T, 64, 8>(d, prefix, nprob, tiles, use_rho, in_mode, op, st);
-    if (c.tx == 32 && c.ty == 4) return launch_multi_mode<T, 32, 4>(d, prefix, nprob, tiles, use_rho, in_mode, op, st);
+    if (c.tx == 32 && c.ty == 8) return launch_multi_mode<T, 32, 8>(d, tmap, tiles, use_rho, in_mode, op, st);
+    if (c.tx == 64 && c.ty == 8) return launch_multi_mode<T, 64, 8>(d, tmap, tiles, use_rho, in_mode, op, st);
+    if (c.tx == 32 && c.ty == 4) return launch_multi_mode<T, 32, 4>(d, tmap, tiles, use_rho, in_mode, op, st);
     return hipErrorInvalidValue;      // other tile shapes are single-problem only
 }
 
@@ -929,9 +893,9 @@ template hipError_t launch_sweep<double>(const SweepArgs<double>&, bool, int, in
 template hipError_t launch_sweep<float>(const SweepArgs<float>&, bool, int, int, hipStream_t);
 template hipError_t launch_resid_restrict_tiled<double>(const SweepArgs<double>&, bool, int, hipStream_t);
 template hipError_t launch_resid_restrict_tiled<float>(const SweepArgs<float>&, bool, int, hipStream_t);
-template hipError_t launch_sweep_multi<double>(const SweepArgs<double>*, const int*, int, int, bool, int, int, int,
+template hipError_t launch_sweep_multi<double>(const SweepArgs<double>*, const int2*, int, bool, int, int, int,
                                                hipStream_t);
-template hipError_t launch_sweep_multi<float>(const SweepArgs<float>*, const int*, int, int, bool, int, int, int,
+template hipError_t launch_sweep_multi<float>(const SweepArgs<float>*, const int2*, int, bool, int, int, int,
                                               hipStream_t);
 
 }  // namespace mg

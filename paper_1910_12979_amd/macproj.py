@@ -42,10 +42,11 @@ class Params(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("nlevels", ctypes.c_int32),
-                ("hist_len", ctypes.c_int32), ("rel_resid", ctypes.c_double),
+                ("hist_len", ctypes.c_int32), ("rel_resid0", ctypes.c_double), ("rel_resid", ctypes.c_double),
                 ("mean_removed", ctypes.c_double), ("sum_f", ctypes.c_double),
                 ("sum_abs_f", ctypes.c_double), ("norm_f", ctypes.c_double),
                 ("phi_mean", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_smooth", ctypes.c_double), ("ms_other", ctypes.c_double),
                 ("bytes_model", ctypes.c_double), ("resid_hist", ctypes.c_double * HIST_MAX)]
 
     def as_dict(self):
@@ -118,6 +119,12 @@ def lib():
         L.nodal_level_step.argtypes = [vp, i32, i32, i32, vp]
         L.nodal_set_graphs.argtypes = [vp, i32]
         L.mac_project_static.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
+        cp, i3 = ctypes.c_char_p, ctypes.POINTER(i32)
+        L.mg_tune_cache_save.argtypes = [cp]
+        L.mg_tune_cache_load.argtypes = [cp]
+        L.mg_tune_cache_clear.argtypes = []
+        L.mg_tune_record.argtypes = [cp, i3, i32, i32, i32, i32]
+        L.mg_tune_lookup.argtypes = [cp, i3, i32, i32, i32]
         L.mg_strerror.argtypes = [ctypes.c_int]
         L.mg_strerror.restype = ctypes.c_char_p
         L.mg_last_error.argtypes = []
@@ -129,6 +136,40 @@ def lib():
 def mg_tune_sweep(cfg: int):
     """Force a fused-sweep tile configuration (-1: per-shape default)."""
     _check(lib().mg_tune_sweep(int(cfg)))
+
+
+def _cstr(x):
+    return None if x is None else str(x).encode()
+
+
+def tune_cache_save(path=None) -> int:
+    """Write the tuning table (None: to MACPROJ_TUNE_CACHE); entries written."""
+    return _check_count(lib().mg_tune_cache_save(_cstr(path)))
+
+
+def tune_cache_load(path=None) -> int:
+    """Merge a tuning cache file into the table; entries taken."""
+    return _check_count(lib().mg_tune_cache_load(_cstr(path)))
+
+
+def tune_cache_clear():
+    _check(lib().mg_tune_cache_clear())
+
+
+def tune_record(n, cfg, rho=True, fp64=True, coarse=False, arch=None):
+    t = (ctypes.c_int32 * 3)(*[int(a) for a in n])
+    _check(lib().mg_tune_record(_cstr(arch), t, int(rho), int(fp64), int(coarse), int(cfg)))
+
+
+def tune_lookup(n, rho=True, fp64=True, coarse=False, arch=None) -> int:
+    t = (ctypes.c_int32 * 3)(*[int(a) for a in n])
+    return lib().mg_tune_lookup(_cstr(arch), t, int(rho), int(fp64), int(coarse))
+
+
+def _check_count(code):
+    if code < 0:
+        raise MGError(code, last_error())
+    return code
 
 
 def last_error() -> str:
