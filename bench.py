@@ -467,7 +467,7 @@ def nodal_leg(args, torch, macproj, inputs, dev):
     torch.cuda.synchronize()
     tn = time.perf_counter() - t0
     assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
-    # one Gauss-Seidel sweep of the finest level (8 parity-class launches)
+    # one four-colour Gauss-Seidel sweep of the finest level (one fused launch)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     H.level_step(0, "smooth", 1)
     e0.record()

@@ -266,6 +266,11 @@ int nodal_destroy(nodal_handle h);
  * Blocks until done; statuses as mac_project. */
 int nodal_project(nodal_handle h, const double* rho, const double* beta0_cc, const double* S, double* uc,
                   double* vc, double* wc, double* phi, mg_stats* stats, void* stream);
+/* Tuning: force the fused nodal sweep's tile configuration (0..7: 64x8,
+ * 32x8, 32x16, 64x16 nodes with 32-plane chunks, 64x8 with 64, 32x8 with 16,
+ * 32x16 with 64, 64x8 with 16) on every level it takes; -1 restores the
+ * per-level default.  Process-wide; results do not depend on it. */
+int nodal_tune_sweep(int32_t cfg);
 /* Coefficients only (for the single steps below). */
 int nodal_set_coefficients(nodal_handle h, const double* rho, const double* beta0_cc, void* stream);
 /* enable = 1 (the default): the V-cycle and the residual norm after it run as

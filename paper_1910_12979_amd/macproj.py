@@ -118,6 +118,7 @@ def lib():
         L.nodal_level_copy.argtypes = [vp, i32, i32, vp, i32, vp]
         L.nodal_level_step.argtypes = [vp, i32, i32, i32, vp]
         L.nodal_set_graphs.argtypes = [vp, i32]
+        L.nodal_tune_sweep.argtypes = [i32]
         L.mac_project_static.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
         cp, i3 = ctypes.c_char_p, ctypes.POINTER(i32)
         L.mg_tune_cache_save.argtypes = [cp]
@@ -635,6 +636,11 @@ class NodalHierarchy:
 
     def level_step(self, level, step, arg=0, stream=None):
         _check(lib().nodal_level_step(self._h, level, STEP[step], arg, _stream(stream)))
+
+
+def nodal_tune_sweep(cfg: int):
+    """Force a fused nodal sweep tile configuration (-1: per-level default)."""
+    _check(lib().nodal_tune_sweep(int(cfg)))
 
 
 def nodal_to_device(prob, device="cuda", phi=True):
