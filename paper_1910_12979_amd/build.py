@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmacproj.so")
-SOURCES = ["kernels.hip", "sweep.hip", "bottom.hip", "runtime.hip", "batch.hip", "frontends.hip", "nodal.hip", "boxes.hip", "noalloc.hip", "tune.hip"]
+SOURCES = ["kernels.hip", "sweep.hip", "bottom.hip", "runtime.hip", "batch.hip", "frontends.hip", "nodal.hip", "boxes.hip", "noalloc.hip", "tune.hip", "scheduler.cpp"]
 ARCH = "gfx950"
 
 # No FMA contraction (per-cell arithmetic identical across kernel variants);

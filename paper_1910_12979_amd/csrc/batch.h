@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "runtime.h"
+#include "scheduler.h"
 
 namespace mg {
 
@@ -36,29 +37,6 @@ struct Staging {
     int init(size_t bytes);
     void release();
     int push(const void* src, size_t bytes, hipStream_t st, void** out);
-};
-
-// One projection in flight.
-struct Job {
-    enum { kNew = 0, kSolve = 1, kFinish = 2, kDone = 3 };
-    mg_problem pr{};
-    mg_hierarchy* H = nullptr;
-    mg_stats st{};
-    int status = MG_OK;
-    int stage = kNew;
-    int cycles = 0;
-    int gslot = -1;           // row of the gathered norm block written by its last iteration
-    double row[4] = {};       // that row, kept until the next round's stop test
-    double fnorm = 0.0;
-    double rel = 1.0;
-    uint64_t ticket = 0;
-    double t_submit = 0.0;
-    double t_admit = 0.0;
-    double t_done = 0.0;
-    double t_iter0 = 0.0;     // steady-clock seconds at its first iteration, and after its last
-    double t_iter1 = 0.0;
-    size_t bytes = 0;
-    int waiters = 0;          // serve_wait calls blocked on this ticket
 };
 
 // Problems the batched path runs (FP64 with the fused finest-level sweep, or
