@@ -410,23 +410,26 @@ int mg_set_bottom(mg_handle h, int32_t enable);
  * method distributes over MPI processes and tiles (Sec. 3), one
  * process per GPU (Sec. 6), here with every box on one device and the
  * inter-box halo exchange done by a kernel: box[0..2] = cells per box in
- * x, y, z, each even, >= 2 and dividing the domain size; the domain is tiled
- * by n/box boxes, each with its own phi (two buffers), f and face
- * coefficients inside a two-cell ghost shell.  Every later mac_project on h
- * smooths, restricts and prolongates the finest level box by box with a
- * halo exchange (ghost cells from the box that owns the cell, the periodic
- * image, or 0 beyond a wall) after every sweep and after each
- * prolongation; boxes of at least 32 x 8 x 4 cells are swept by the fused
- * red-black sweep, smaller ones one colour per launch with an exchange of
- * that colour in between.  Levels 1 and coarser are the single-box levels.
- * The result agrees with the single-box solve to rounding (the same
- * per-cell arithmetic; the residual norm and the restriction may be summed
- * in another order).  box == NULL or {0, 0, 0} returns to a single box.
+ * x, y, z, each even, >= 2 and at most the domain size.  The domain is tiled
+ * by ceil(n/box) boxes per direction, all of box cells except the last one
+ * of a direction that box does not divide, which holds the (even) remainder:
+ * uneven boxes, as a domain chopped to a maximum box size.  Each box has its
+ * own phi (two buffers), f and face coefficients inside a two-cell ghost
+ * shell.  Every later mac_project on h smooths, restricts and prolongates
+ * the finest level box by box with a halo exchange (ghost cells from the
+ * box that owns the cell, the periodic image, or 0 beyond a wall) after
+ * every sweep and after each prolongation; when every box, the smallest
+ * included, has at least 32 x 8 x 4 cells, the boxes are swept by the fused
+ * red-black sweep, otherwise one colour per launch with an exchange of that
+ * colour in between.  Levels 1 and coarser are the single-box levels.  The
+ * result agrees with the single-box solve to rounding (the same per-cell
+ * arithmetic; the residual norm and the restriction may be summed in
+ * another order).  box == NULL or {0, 0, 0} returns to a single box.
  * Needs FP64 precision, periodic or wall sides and two or more levels
  * (MG_ERR_INVALID_ARG otherwise).  The boxes' arrays are allocated here
  * (device memory, freed by mg_destroy or the next mg_set_boxes), 7 x 8
- * bytes per cell of the ghosted boxes; MG_ERR_HIP if that fails.  Not used
- * by the batch or serving front ends. */
+ * bytes per cell of the ghosted boxes, each sized for a full box; MG_ERR_HIP
+ * if that fails.  Not used by the batch or serving front ends. */
 int mg_set_boxes(mg_handle h, const int32_t box[3]);
 
 /* Fused-sweep tile used on level l of h: tile[0..2] = cells per workgroup

@@ -1,10 +1,14 @@
 // Multi-box finest level: layout and launchers (internal, not part of the
 // C ABI).  The finest level of an n0 x n1 x n2 domain is tiled by
-// nb0 x nb1 x nb2 boxes of B0 x B1 x B2 cells (every B_d even, dividing n_d);
-// box b = (kb nb1 + jb) nb0 + ib, x fastest.  Every box array is ghosted:
-// G0 x G1 x G2 cells, G_d = B_d + 2 kBoxGhost, local cell (i, j, k) of the
-// box at ((k + g) G1 + (j + g)) G0 + (i + g), g = kBoxGhost, boxes one after
-// another (stride G0 G1 G2 elements):
+// nb0 x nb1 x nb2 boxes, nb_d = ceil(n_d / B_d), B_d even: box (ib, jb, kb)
+// starts at cell (ib B0, jb B1, kb B2) and holds B_d cells along d, except
+// the last box of a direction that B_d does not divide, which holds the
+// remainder n_d - (nb_d - 1) B_d (even, at least 2); box
+// b = (kb nb1 + jb) nb0 + ib, x fastest.  Every box array is ghosted and
+// sized for a full box: G0 x G1 x G2 cells, G_d = B_d + 2 kBoxGhost, local
+// cell (i, j, k) of the box at ((k + g) G1 + (j + g)) G0 + (i + g),
+// g = kBoxGhost, boxes one after another (stride G0 G1 G2 elements); a
+// smaller box uses the first E_d + 2g cells of each direction (E_d its cells):
 //   phi, phi2  two buffers (the fused sweep is out of place)
 //   f          the right-hand side, ghosts included (the neighbour's value)
 //   cx, cy, cz face coefficients, cell-aligned low faces in the same layout
@@ -26,7 +30,7 @@ constexpr int kBoxGhost = 2;
 
 struct BoxSet {
     int n[3];         // domain cells
-    int B[3];         // box cells
+    int B[3];         // cells of a full box
     int nb[3];        // boxes per direction
     int per[3];       // periodic directions
     int G[3];         // ghosted box dims
@@ -46,6 +50,11 @@ struct BoxSet {
 };
 
 size_t boxset_cells(const BoxSet& B);
+// Cells along d of the box at box coordinate c.
+__host__ __device__ inline int box_ext(const BoxSet& B, int d, int c) {
+    const int r = B.n[d] - c * B.B[d];
+    return r < B.B[d] ? r : B.B[d];
+}
 // phi = 0 (phi2 is written by a sweep before it is read); f of every
 // ghosted box from the global finest-level f, and with coeffs its face
 // arrays from the cell-aligned bx, by, bz (periodic images; walls as above).

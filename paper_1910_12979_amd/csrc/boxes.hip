@@ -1,5 +1,6 @@
-// Multi-box finest level for gfx950: the domain is tiled by a grid of equal
-// boxes, each holding its own phi (two buffers), f, rho and face
+// Multi-box finest level for gfx950: the domain is tiled by a grid of boxes
+// (equal, except that the last box of a direction the box size does not
+// divide holds the remainder), each holding its own phi (two buffers), f, rho and face
 // coefficients with a two-cell ghost shell.  Smoothing, residual +
 // restriction, prolongation and the residual norm of the finest level run
 // box by box (all boxes in one launch); a halo exchange refills every ghost
@@ -65,6 +66,12 @@ __device__ inline void box_coords(const BoxSet& B, int b, int c[3]) {
     c[0] = b % B.nb[0];
     c[1] = (b / B.nb[0]) % B.nb[1];
     c[2] = b / (B.nb[0] * B.nb[1]);
+}
+
+// Box coordinates and cells of box b.
+__device__ inline void box_shape(const BoxSet& B, int b, int c[3], int E[3]) {
+    box_coords(B, b, c);
+    for (int d = 0; d < 3; ++d) E[d] = box_ext(B, d, c[d]);
 }
 
 __device__ inline size_t gidx(int i, int j, int k, int nx, int ny) { return ((size_t)k * ny + j) * nx + i; }
@@ -140,6 +147,7 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_scatter(BoxSet B, const doubl
         }
     }
     B.phi[e] = 0.0;
+    B.phi2[e] = 0.0;     // cells past a smaller box's shell are read by the tile windows, never written
     double fv = 0.0, cv[3] = {1.0, 1.0, 1.0}, rv = 1.0;
     if (out == 0) {
         const size_t gi = gidx(g[0], g[1], g[2], B.n[0], B.n[1]);
@@ -187,46 +195,50 @@ __global__ void k_box_beta0(BoxSet B, const double* __restrict__ b0c, const doub
 // -1: all.
 constexpr int kExChunk = 4 * kBoxBlock;
 __global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, int colour, int chunks) {
-    const int G0 = B.G[0], G1 = B.G[1], G2 = B.G[2];
+    const int G2 = B.G[2];
     const int chunk = (int)(blockIdx.x % (unsigned)chunks);
     const int kp = (int)((blockIdx.x / (unsigned)chunks) % (unsigned)G2);
     const int b = (int)(blockIdx.x / ((unsigned)chunks * G2));
     const int k = kp - kG;
-    const bool ghost_plane = k < 0 || k >= B.B[2];
-    const int ncell = ghost_plane ? G0 * G1 : 2 * kG * G0 + 2 * kG * B.B[1];
-    int c[3];
-    box_coords(B, b, c);
+    int c[3], E[3];
+    box_shape(B, b, c, E);
+    if (k >= E[2] + kG) return;               // past this box's ghost shell
+    const int W0 = E[0] + 2 * kG, W1 = E[1] + 2 * kG;
+    const bool ghost_plane = k < 0 || k >= E[2];
+    const int ncell = ghost_plane ? W0 * W1 : 2 * kG * W0 + 2 * kG * E[1];
     const BoxView v = view(B, b);
     const int e_end = min(ncell, (chunk + 1) * kExChunk);
     for (int e = chunk * kExChunk + threadIdx.x; e < e_end; e += kBoxBlock) {
         int i, j;
         if (ghost_plane) {
-            i = e % G0 - kG;
-            j = e / G0 - kG;
-        } else if (e < 2 * kG * G0) {         // the ghost rows, whole
-            const int r = e / G0;
-            j = r < kG ? r - kG : B.B[1] + r - kG;
-            i = e % G0 - kG;
+            i = e % W0 - kG;
+            j = e / W0 - kG;
+        } else if (e < 2 * kG * W0) {         // the ghost rows, whole
+            const int r = e / W0;
+            j = r < kG ? r - kG : E[1] + r - kG;
+            i = e % W0 - kG;
         } else {                              // the ghost columns of the interior rows
-            const int e2 = e - 2 * kG * G0;
+            const int e2 = e - 2 * kG * W0;
             j = e2 / (2 * kG);
             const int r = e2 % (2 * kG);
-            i = r < kG ? r - kG : B.B[0] + r - kG;
+            i = r < kG ? r - kG : E[0] + r - kG;
         }
         if (colour >= 0 && ((i + j + k) & 1) != colour) continue;
         // the owner is the adjacent box in each direction the ghost leaves
-        // (a ghost at most two cells out, boxes at least two cells wide)
+        // (a ghost at most two cells out, boxes at least two cells wide);
+        // past the high side its local coordinate starts at 0, below the low
+        // side it counts back from the owner's last cell
         const int L[3] = {i, j, k};
         int S[3], o[3];
         bool wall = false;
         for (int d = 0; d < 3; ++d) {
-            const int step = L[d] < 0 ? -1 : (L[d] >= B.B[d] ? 1 : 0);
-            S[d] = L[d] - step * B.B[d];
+            const int step = L[d] < 0 ? -1 : (L[d] >= E[d] ? 1 : 0);
             o[d] = c[d] + step;
             if (o[d] < 0 || o[d] >= B.nb[d]) {
                 if (B.per[d]) o[d] = o[d] < 0 ? B.nb[d] - 1 : 0;
                 else wall = true;
             }
+            S[d] = step > 0 ? L[d] - E[d] : (step < 0 ? L[d] + box_ext(B, d, wall ? 0 : o[d]) : L[d]);
         }
         double val = 0.0;
         if (!wall) {
@@ -243,7 +255,9 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, int colour
 __global__ __launch_bounds__(kBoxBlock) void k_box_rbgs(BoxSet B, double h2, int colour, int gx, int gy) {
     const Patch q = patch_of(blockIdx.x, gx, gy, B.B[2], kGsTX, kGsTY);
     const int ih = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y, k = q.k;
-    if (2 * ih >= B.B[0] || j >= B.B[1]) return;
+    int c3[3], E[3];
+    box_shape(B, q.b, c3, E);
+    if (2 * ih >= E[0] || j >= E[1] || k >= E[2]) return;
     const int i = 2 * ih + ((j + k + colour) & 1);
     const BoxView v = view(B, q.b);
     const int c = v.p(i, j, k);
@@ -273,14 +287,14 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_resid_restrict(BoxSet B, doub
     const Patch q = patch_of(blockIdx.x, gx, gy, B.B[2] / 2, kRrTX, kRrTY);
     const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
     const int i = q.x0 + tx, j = q.y0 + ty, k = 2 * q.k + tz;
-    int o[3];
-    box_coords(B, q.b, o);
+    int o[3], E[3];
+    box_shape(B, q.b, o, E);
     o[0] *= B.B[0];
     o[1] *= B.B[1];
     o[2] *= B.B[2];
     const BoxView v = view(B, q.b);
     double rv = 0.0;
-    if (i < B.B[0] && j < B.B[1]) {
+    if (i < E[0] && j < E[1] && k < E[2]) {
         const int c = v.p(i, j, k);
         rv = v.f[c] - box_apply(v, c, h2);
     }
@@ -289,7 +303,7 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_resid_restrict(BoxSet B, doub
     const int flat = (tz * kRrTY + ty) * kRrTX + tx;
     if (flat >= (kRrTX / 2) * (kRrTY / 2)) return;
     const int cxl = flat % (kRrTX / 2), cyl = flat / (kRrTX / 2);
-    if (q.x0 + 2 * cxl >= B.B[0] || q.y0 + 2 * cyl >= B.B[1]) return;
+    if (q.x0 + 2 * cxl >= E[0] || q.y0 + 2 * cyl >= E[1] || 2 * q.k >= E[2]) return;
     double s = 0.0;
     for (int dk = 0; dk < 2; ++dk)
         for (int dj = 0; dj < 2; ++dj)
@@ -304,9 +318,9 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_resid_restrict(BoxSet B, doub
 __global__ __launch_bounds__(kBoxBlock) void k_box_prolong(BoxSet B, const double* __restrict__ phic, int gx, int gy) {
     const Patch q = patch_of(blockIdx.x, gx, gy, B.B[2], kCellTX, kCellTY);
     const int i = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y, k = q.k;
-    if (i >= B.B[0] || j >= B.B[1]) return;
-    int o[3];
-    box_coords(B, q.b, o);
+    int o[3], E[3];
+    box_shape(B, q.b, o, E);
+    if (i >= E[0] || j >= E[1] || k >= E[2]) return;
     const BoxView v = view(B, q.b);
     const int c = v.p(i, j, k);
     v.phi[c] = v.phi[c] + phic[gidx((o[0] * B.B[0] + i) >> 1, (o[1] * B.B[1] + j) >> 1, (o[2] * B.B[2] + k) >> 1,
@@ -321,7 +335,9 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_resid_norm(BoxSet B, double h
     for (unsigned t = blockIdx.x; t < npatch; t += gridDim.x) {
         const Patch q = patch_of(t, gx, gy, B.B[2], kCellTX, kCellTY);
         const int i = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y;
-        if (i >= B.B[0] || j >= B.B[1]) continue;
+        int c3[3], E[3];
+        box_shape(B, q.b, c3, E);
+        if (i >= E[0] || j >= E[1] || q.k >= E[2]) continue;
         const BoxView v = view(B, q.b);
         const int c = v.p(i, j, q.k);
         const double r = v.f[c] - box_apply(v, c, h2);
@@ -356,9 +372,9 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_resid_norm(BoxSet B, double h
 __global__ __launch_bounds__(kBoxBlock) void k_box_gather(BoxSet B, double* __restrict__ phi, int gx, int gy) {
     const Patch q = patch_of(blockIdx.x, gx, gy, B.B[2], kCellTX, kCellTY);
     const int i = q.x0 + (int)threadIdx.x, j = q.y0 + (int)threadIdx.y, k = q.k;
-    if (i >= B.B[0] || j >= B.B[1]) return;
-    int o[3];
-    box_coords(B, q.b, o);
+    int o[3], E[3];
+    box_shape(B, q.b, o, E);
+    if (i >= E[0] || j >= E[1] || k >= E[2]) return;
     const BoxView v = view(B, q.b);
     phi[gidx(o[0] * B.B[0] + i, o[1] * B.B[1] + j, o[2] * B.B[2] + k, B.n[0], B.n[1])] = v.phi[v.p(i, j, k)];
 }
@@ -379,7 +395,7 @@ hipError_t exchange(const BoxSet& B, int colour, hipStream_t st) {
 
 }  // namespace
 
-size_t boxset_cells(const BoxSet& B) { return (size_t)B.B[0] * B.B[1] * B.B[2] * B.nbox; }
+size_t boxset_cells(const BoxSet& B) { return (size_t)B.n[0] * B.n[1] * B.n[2]; }
 
 hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx, const double* by, const double* bz,
                               const double* rho, const double* b0c, const double* b0e, bool coeffs, hipStream_t st) {
@@ -425,6 +441,10 @@ BoxGeom box_geom(const BoxSet& B) {
         g.per[d] = B.per[d];
     }
     g.b0stride = B.G[2];
+    for (int d = 0; d < 3; ++d) {
+        g.box[d] = B.B[d];
+        g.n[d] = B.n[d];
+    }
     return g;
 }
 

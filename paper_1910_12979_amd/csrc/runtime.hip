@@ -1665,23 +1665,25 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
         return MG_ERR_INVALID_ARG;
     }
     BoxSet B{};
+    int emin[3];                               // the smallest box's cells per direction
     for (int d = 0; d < 3; ++d) {
         const int n = h->p.n[d];
-        if (box[d] < 2 || box[d] % 2 != 0 || n % box[d] != 0) {
-            set_error("box sizes must be even, at least 2, and divide the domain size in each direction");
+        if (box[d] < 2 || box[d] % 2 != 0 || box[d] > n) {
+            set_error("box sizes must be even, at least 2, and at most the domain size in each direction");
             return MG_ERR_INVALID_ARG;
         }
         B.n[d] = n;
         B.B[d] = box[d];
-        B.nb[d] = n / box[d];
+        B.nb[d] = (n + box[d] - 1) / box[d];  // the last box holds the (even) remainder
         B.G[d] = box[d] + 2 * kBoxGhost;
+        emin[d] = n - (B.nb[d] - 1) * box[d];
     }
     B.per[0] = h->px;
     B.per[1] = h->py;
     B.per[2] = h->pz;
     B.nbox = B.nb[0] * B.nb[1] * B.nb[2];
     B.stride = (size_t)B.G[0] * B.G[1] * B.G[2];
-    B.fused = sweep_boxes_fit(B.B[0], B.B[1], B.B[2]) ? 1 : 0;
+    B.fused = sweep_boxes_fit(emin[0], emin[1], emin[2]) ? 1 : 0;   // every box takes the fused sweep
     if (B.stride >= ((size_t)1 << 31)) {
         set_error("box too large: its ghosted array must stay below 2^31 cells");
         return MG_ERR_INVALID_ARG;

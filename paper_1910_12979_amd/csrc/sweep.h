@@ -115,6 +115,8 @@ struct BoxGeom {
     int nb[3];                 // boxes per direction
     int per[3];                // periodic directions
     int b0stride;              // beta0 entries per box
+    int box[3];                // cells of a full box; the last box of a direction holds n - (nb - 1) box
+    int n[3];                  // domain cells
 };
 bool sweep_boxes_fit(int bx, int by, int bz);
 int sweep_boxes_tiles(int bx, int by, int bz);      // tiles per box

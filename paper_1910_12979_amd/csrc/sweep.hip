@@ -542,11 +542,18 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_wave
     c.phi_out = a.phi_out + off;
     c.f = a.f + off;
     const int bc[3] = {b % g.nb[0], (b / g.nb[0]) % g.nb[1], b / (g.nb[0] * g.nb[1])};
-    const int E[3] = {a.ex, a.ey, a.ez}, O[3] = {a.ox, a.oy, a.oz};
+    // this box's cells (the launch's tiles cover a full box; a smaller last
+    // box leaves the tiles past its cells without writes)
+    const int E[3] = {min(g.box[0], g.n[0] - bc[0] * g.box[0]), min(g.box[1], g.n[1] - bc[1] * g.box[1]),
+                      min(g.box[2], g.n[2] - bc[2] * g.box[2])};
+    const int O[3] = {a.ox, a.oy, a.oz};
+    c.ex = E[0];
+    c.ey = E[1];
+    c.ez = E[2];
     if (kIn == kInProlong || kOp == kOpResidRestrict) {
         for (int d = 0; d < 3; ++d) {
-            c.go[d] = bc[d] * E[d];
-            c.gn[d] = g.nb[d] * E[d];
+            c.go[d] = bc[d] * g.box[d];
+            c.gn[d] = g.n[d];
             c.gp[d] = g.per[d];
         }
     }

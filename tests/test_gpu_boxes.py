@@ -3,7 +3,10 @@ halo exchange between them) against the FP64 CPU oracle and against the
 single-box GPU solve.
 
 Boxes of 32 x 8 x 4 cells and more run the fused sweep on each box interior
-(two-cell ghost shells), smaller ones one launch per colour.
+(two-cell ghost shells), smaller ones one launch per colour.  Uneven boxes:
+a box size that does not divide the domain leaves a smaller last box in that
+direction (its tiles partly empty on the fused path, its neighbours across a
+periodic side of another size).
 
 Bar at rtol 1e-10: phi and U within max(1e-9, 3 x the oracle's own
 algorithm-mode deviation) of the oracle's exact discrete solution, with the
@@ -96,6 +99,11 @@ CASES = [
     ((64, 32, 32), (True, True, True), (32, 16, 16), 9),       # fused, fully periodic
     ((96, 48, 40), (False, False, False), (32, 8, 4), 10),     # fused, walls, the smallest fused box
     ((128, 64, 32), (True, False, False), (64, 32, 16), 11),   # fused with 64-wide tiles
+    # uneven boxes: the last box of a direction holds the remainder
+    ((40, 24, 56), (True, True, False), (16, 16, 24), 12),     # 16+16+8, 16+8, 24+24+8: per colour
+    ((96, 48, 40), (False, False, False), (64, 32, 16), 13),   # fused: 64+32, 32+16, 16+16+8
+    ((96, 64, 64), (True, True, True), (64, 48, 40), 14),      # fused, periodic across unequal boxes
+    ((32, 32, 32), (True, False, True), (30, 32, 18), 15),     # 30+2 and 18+14: two-cell boxes
 ]
 
 
@@ -111,6 +119,8 @@ def test_boxes_match_oracle_and_single_box(mp, n, per, box, seed):
     ((32, 32, 32), (True, True, False), (16, 16, 16), 51),
     ((64, 64, 64), (False, True, False), (32, 16, 64), 52),    # fused sweeps inside the boxes
     ((40, 24, 56), (True, True, False), (20, 12, 28), 53),     # ragged boxes
+    ((96, 64, 64), (True, True, True), (64, 48, 40), 54),      # uneven, fused
+    ((40, 24, 56), (False, True, False), (16, 16, 24), 55),    # uneven, per colour
 ])
 def test_boxes_strict_at_rtol_1e12(mp, n, per, box, seed):
     """Solved to rtol 1e-12, the multi-box phi and U are within 1e-9 of the
@@ -169,7 +179,7 @@ def test_boxes_errors(mp):
     prob = I.make_problem((32, 32, 32), H=0.2, seed=22)
     H = mp.Hierarchy(mp.params_of(prob))
     try:
-        for bad in ((3, 16, 16), (12, 16, 16), (0, 16, 16), (64, 16, 16), (16, -2, 16)):
+        for bad in ((3, 16, 16), (34, 16, 16), (0, 16, 16), (64, 16, 16), (16, -2, 16), (16, 16, 15)):
             with pytest.raises(mp.MGError):
                 H.set_boxes(bad)
     finally:
@@ -194,12 +204,14 @@ def test_boxes_errors(mp):
     assert st["status_name"] == "INCOMPATIBLE_RHS"
 
 
-def test_boxes_256_full_size(mp):
-    """The 256^3 steep-stratification box split into 64 boxes of 64^3: the
-    single-box solve's cycles and result, and the discrete system satisfied to
-    rtol (the oracle's operator in FP64)."""
+@pytest.mark.parametrize("box", [(64, 64, 64), (96, 96, 96)])
+def test_boxes_256_full_size(mp, box):
+    """The 256^3 steep-stratification box split into 64 boxes of 64^3, or
+    into 27 uneven ones (96 + 96 + 64 per direction): the single-box solve's
+    cycles and result, and the discrete system satisfied to rtol (the
+    oracle's operator in FP64)."""
     prob = I.STEEP_256()
-    st, out = run_gpu(mp, prob, box=(64, 64, 64))
+    st, out = run_gpu(mp, prob, box=box)
     assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10
     check_single(mp, prob, st, out)
     c = O.face_coeffs(prob.n, prob.periodic, prob.rho, prob.beta0_cc, prob.beta0_edge)
