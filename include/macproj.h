@@ -124,7 +124,16 @@ typedef struct {
 
 typedef struct mg_hierarchy* mg_handle;
 
-/* One problem for project_batch / serve_submit.  Pointers as for mac_project. */
+typedef enum { MG_KIND_MAC = 0, MG_KIND_NODAL = 1 } mg_problem_kind;
+
+/* One problem for project_batch / serve_submit.
+ * kind MG_KIND_MAC: pointers as for mac_project; box = cells per box of a
+ * multi-box finest level as for mg_set_boxes (FP64, periodic or wall sides),
+ * {0, 0, 0} for a single box.
+ * kind MG_KIND_NODAL: the nodal projection (nodal_project): u, v, w are the
+ * cell-centred velocity components, corrected in place, phi (nullable) the
+ * node values; beta0_edge is not read (may be NULL); box must be {0, 0, 0}.
+ * A zero-filled tail (kind 0, box {0, 0, 0}) is the single-box MAC problem. */
 typedef struct {
     mg_params p;
     const double* rho;
@@ -135,6 +144,8 @@ typedef struct {
     double* v;
     double* w;
     double* phi;             /* nullable */
+    int32_t kind;            /* mg_problem_kind */
+    int32_t box[3];
 } mg_problem;
 
 /* Fill *p with the defaults (V(2,2), rtol 1e-10, 100 cycles, FP64,
@@ -322,7 +333,11 @@ int mg_level_step(mg_handle h, int32_t level, int32_t step, int32_t arg, void* s
 
 /* Solve `count` independent problems (any shapes, each with its own params)
  * with shared launches; stats has `count` entries (nullable).  Each result is
- * the one mac_project gives for that problem alone.  Blocks until done.
+ * the one mac_project (nodal_project for MG_KIND_NODAL) gives for that
+ * problem alone.  Single-box MAC problems whose finest level takes the fused
+ * sweep run together, iteration by iteration; the others (nodal problems,
+ * multi-box problems, small shapes) are solved one at a time on pooled
+ * hierarchies, between those iterations.  Blocks until done.
  * stats[i].ms_total is the device time of the whole call, ms_smooth the
  * wall time from problem i's first iteration to its last (the iterations are
  * shared launches), ms_other the difference. */
@@ -332,8 +347,10 @@ int project_batch(int32_t count, const mg_problem* probs, mg_stats* stats, void*
  * the device memory of resident hierarchies plus in-flight work;
  * max_inflight caps the problems on the device at once. */
 int serve_create(size_t hbm_budget_bytes, int32_t max_inflight, void** server);
-/* Queue a problem; never blocks.  The problem's buffers must stay alive until
- * its ticket completes. */
+/* Queue a problem (any kind, as for project_batch: nodal and multi-box
+ * problems are solved one at a time on pooled hierarchies, between the
+ * shared iterations); never blocks.  The problem's buffers must stay alive
+ * until its ticket completes. */
 int serve_submit(void* server, const mg_problem* prob, uint64_t* ticket);
 /* A ticket is released once a poll or wait has returned its final status
  * (when no other wait is still blocked on it); later calls with it return
@@ -429,7 +446,8 @@ int mg_set_bottom(mg_handle h, int32_t enable);
  * (MG_ERR_INVALID_ARG otherwise).  The boxes' arrays are allocated here
  * (device memory, freed by mg_destroy or the next mg_set_boxes), 7 x 8
  * bytes per cell of the ghosted boxes, each sized for a full box; MG_ERR_HIP
- * if that fails.  Not used by the batch or serving front ends. */
+ * if that fails.  Batches and the server take the box size from
+ * mg_problem.box. */
 int mg_set_boxes(mg_handle h, const int32_t box[3]);
 
 /* Fused-sweep tile used on level l of h: tile[0..2] = cells per workgroup

@@ -1,8 +1,9 @@
 // Batch and serving front ends of the C ABI.
 //
 // project_batch: every problem gets its own hierarchy (reused across calls
-// from a process-wide cache keyed by shape); all batchable problems are
-// solved together by the batched engine, V-cycle by V-cycle.
+// from a process-wide cache keyed by kind and shape); all batchable problems
+// are solved together by the batched engine, V-cycle by V-cycle, the others
+// (nodal, multi-box, small shapes) one at a time.
 //
 // Serving: a Scheduler (scheduler.h: queue, admission against the HBM budget
 // and the in-flight cap at V-cycle boundaries, pool of resident hierarchies,
@@ -25,8 +26,44 @@
 namespace mg {
 namespace {
 
+// A resident state: the hierarchy of a MAC problem (with its boxes when the
+// problem asks for them) or of a nodal one.
+struct Slot {
+    int kind = MG_KIND_MAC;
+    mg_hierarchy* H = nullptr;
+    nodal_handle N = nullptr;
+};
+
+bool has_box(const mg_problem& pr) { return pr.box[0] != 0 || pr.box[1] != 0 || pr.box[2] != 0; }
+
+// Checks a problem can pass before it is queued (the box size itself is
+// checked when its hierarchy is built).
+int check_problem(const mg_problem& pr) {
+    int rc = validate_params(&pr.p);
+    if (rc) return rc;
+    if (pr.kind != MG_KIND_MAC && pr.kind != MG_KIND_NODAL) {
+        set_error("unknown problem kind");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (!pr.rho || !pr.beta0_cc || !pr.S || !pr.u || !pr.v || !pr.w ||
+        (pr.kind == MG_KIND_MAC && !pr.beta0_edge)) {
+        set_error("null field pointer in a problem");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (pr.kind == MG_KIND_NODAL && (has_box(pr) || pr.p.precision != MG_FP64)) {
+        set_error("a nodal problem runs in FP64 on a single box");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (has_box(pr) && (pr.box[0] <= 0 || pr.box[1] <= 0 || pr.box[2] <= 0)) {
+        set_error("box sizes must all be positive, or all zero for a single box");
+        return MG_ERR_INVALID_ARG;
+    }
+    return MG_OK;
+}
+
 // The library's executor: resident states are hierarchies on one device, the
-// work runs on one stream through the batched engine.
+// work runs on one stream; single-box MAC problems whose finest level takes
+// the fused sweep go through the batched engine, the rest are solved alone.
 struct HipExecutor final : Executor {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -38,23 +75,53 @@ struct HipExecutor final : Executor {
         engine.release();
         if (owns_stream && stream) hipStreamDestroy(stream);
     }
-
     void bind() override { hipSetDevice(device); }
-    size_t bytes_for(const mg_params& p) override { return workspace_bytes(&p); }
-    int create(const mg_params& p, void** slot, size_t* bytes) override {
-        mg_hierarchy* H = nullptr;
-        const int rc = setup(&p, nullptr, 0, &H);
-        if (rc != MG_OK) return rc;
-        *slot = H;
-        *bytes = H->ws_bytes;
+    size_t bytes_for(const mg_problem& pr) override {
+        if (pr.kind == MG_KIND_NODAL) return nodal_bytes(&pr.p);
+        return workspace_bytes(&pr.p) + (has_box(pr) ? box_bytes(pr.p, pr.box) : 0);
+    }
+    int create(const mg_problem& pr, void** slot, size_t* bytes) override {
+        auto* s = new (std::nothrow) Slot();
+        if (!s) return MG_ERR_OOM;
+        s->kind = pr.kind;
+        int rc;
+        if (pr.kind == MG_KIND_NODAL) {
+            rc = nodal_setup(&pr.p, &s->N);
+        } else {
+            rc = setup(&pr.p, nullptr, 0, &s->H);
+            if (rc == MG_OK && has_box(pr)) {
+                rc = mg_set_boxes(s->H, pr.box);
+                if (rc != MG_OK) mg::destroy(s->H);
+            }
+        }
+        if (rc != MG_OK) {
+            delete s;
+            return rc;
+        }
+        *slot = s;
+        *bytes = bytes_for(pr);
         return MG_OK;
     }
-    void destroy(void* slot) override { mg::destroy(static_cast<mg_hierarchy*>(slot)); }
-    void rebind(void* slot, const mg_params& p) override { static_cast<mg_hierarchy*>(slot)->p = p; }
-    static mg_hierarchy* attach(Job* j) { return j->H = static_cast<mg_hierarchy*>(j->slot); }
-    bool batchable(Job* j) override { return mg::batchable(attach(j)); }
+    void destroy(void* slot) override {
+        auto* s = static_cast<Slot*>(slot);
+        if (s->N) nodal_destroy(s->N);
+        if (s->H) mg::destroy(s->H);
+        delete s;
+    }
+    void rebind(void* slot, const mg_problem& pr) override {
+        auto* s = static_cast<Slot*>(slot);
+        if (s->N) nodal_rebind(s->N, &pr.p);
+        else s->H->p = pr.p;
+    }
+    static mg_hierarchy* attach(Job* j) { return j->H = static_cast<Slot*>(j->slot)->H; }
+    bool batchable(Job* j) override {
+        mg_hierarchy* H = attach(j);
+        return H && !H->boxes_on && mg::batchable(H);
+    }
     int solo(Job* j) override {
         const mg_problem& p = j->pr;
+        const Slot* s = static_cast<Slot*>(j->slot);
+        if (s->N) return nodal_project(s->N, p.rho, p.beta0_cc, p.S, p.u, p.v, p.w, p.phi, &j->st, stream);
         return project(attach(j), p.rho, p.beta0_cc, p.beta0_edge, p.S, p.u, p.v, p.w, p.phi, &j->st, stream);
     }
     int setup_new(std::vector<Job*>& fresh) override {
@@ -120,13 +187,8 @@ int project_batch(int32_t count, const mg_problem* probs, mg_stats* stats, void*
             Job& j = jobs[i];
             j.pr = probs[i];
             std::memset(&j.st, 0, sizeof j.st);
-            int rc = validate_params(&j.pr.p);
-            if (rc == MG_OK && (!j.pr.rho || !j.pr.beta0_cc || !j.pr.beta0_edge || !j.pr.S || !j.pr.u || !j.pr.v ||
-                                !j.pr.w)) {
-                set_error("null field pointer in a batch problem");
-                rc = MG_ERR_INVALID_ARG;
-            }
-            if (rc == MG_OK) rc = g_batch_pool->acquire(j.pr.p, dev, &j.slot);
+            int rc = check_problem(j.pr);
+            if (rc == MG_OK) rc = g_batch_pool->acquire(j.pr, dev, &j.slot);
             if (rc != MG_OK) {
                 j.st.status = j.status = rc;
                 j.stage = Job::kDone;
@@ -204,12 +266,8 @@ int serve_submit(void* server, const mg_problem* prob, uint64_t* ticket) {
         set_error("bad serve_submit arguments");
         return MG_ERR_INVALID_ARG;
     }
-    int rc = validate_params(&prob->p);
+    int rc = check_problem(*prob);
     if (rc) return rc;
-    if (!prob->rho || !prob->beta0_cc || !prob->beta0_edge || !prob->S || !prob->u || !prob->v || !prob->w) {
-        set_error("null field pointer");
-        return MG_ERR_INVALID_ARG;
-    }
     rc = S->submit(*prob, ticket);
     if (rc == MG_ERR_BUDGET) set_error("request needs more device memory than the server budget");
     return rc;

@@ -890,6 +890,34 @@ int nod_count_levels(const mg_params* p) {
     return nodes <= kCoarseMax ? n : 0;
 }
 
+// Partial-sum rows of the finest level's residual norm.
+size_t nod_partial_rows(const NodLevel& L0) { return std::max<size_t>(2048, (size_t)nod_resid_tiles(L0)); }
+
+// Level shapes of a hierarchy of nl levels for p (into lev), and the device
+// bytes it needs: per level sigma on cells and phi, f, r, phi2 on nodes; the
+// coarsest level's dense inverse, the partial rows and the scalar block.
+size_t nod_layout(const mg_params* p, int nl, NodLevel* lev) {
+    size_t bytes = 0;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    for (int l = 0; l < nl; ++l) {
+        NodLevel& L = lev[l];
+        L.nx = p->n[0] >> l;
+        L.ny = p->n[1] >> l;
+        L.nz = p->n[2] >> l;
+        L.px = p->bc[0] == MG_BC_PERIODIC;
+        L.py = p->bc[1] == MG_BC_PERIODIC;
+        L.pz = p->bc[2] == MG_BC_PERIODIC;
+        L.Nx = L.nx + (L.px ? 0 : 1);
+        L.Ny = L.ny + (L.py ? 0 : 1);
+        L.Nz = L.nz + (L.pz ? 0 : 1);
+        L.h = p->dx * (double)(1 << l);
+        bytes += al(L.cells() * 8) + 4 * al(L.nodes() * 8);
+    }
+    const size_t nc = lev[nl - 1].nodes();
+    bytes += al(nc * nc * 8) + al(nod_partial_rows(lev[0]) * kReduceWidth * 8) + al(64 * 8);
+    return bytes;
+}
+
 #define NHIP(expr)                                                        \
     do {                                                                  \
         hipError_t e_ = (expr);                                           \
@@ -1195,6 +1223,22 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
 
 }  // namespace
 
+namespace mg {
+
+size_t nodal_bytes(const mg_params* p) {
+    if (!p || validate_params(p) != MG_OK) return 0;
+    for (int d = 0; d < 3; ++d)
+        if (p->bc[d] != MG_BC_PERIODIC && p->bc[d] != MG_BC_WALL) return 0;
+    const int nl = nod_count_levels(p);
+    if (nl == 0) return 0;
+    NodLevel lev[kMaxLevels];
+    return nod_layout(p, nl, lev);
+}
+
+void nodal_rebind(nodal_handle h, const mg_params* p) { h->p = *p; }
+
+}  // namespace mg
+
 extern "C" {
 
 int nodal_tune_sweep(int32_t cfg) {
@@ -1239,31 +1283,16 @@ int nodal_setup(const mg_params* p, nodal_handle* out) {
     if (!H) return MG_ERR_OOM;
     H->p = *p;
     H->nlev = nl;
-    size_t bytes = 0;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    for (int l = 0; l < nl; ++l) {
-        NodLevel& L = H->lev[l];
-        L.nx = p->n[0] >> l;
-        L.ny = p->n[1] >> l;
-        L.nz = p->n[2] >> l;
-        L.px = p->bc[0] == MG_BC_PERIODIC;
-        L.py = p->bc[1] == MG_BC_PERIODIC;
-        L.pz = p->bc[2] == MG_BC_PERIODIC;
-        L.Nx = L.nx + (L.px ? 0 : 1);
-        L.Ny = L.ny + (L.py ? 0 : 1);
-        L.Nz = L.nz + (L.pz ? 0 : 1);
-        L.h = p->dx * (double)(1 << l);
-        bytes += al(L.cells() * 8) + 4 * al(L.nodes() * 8);
-    }
-    const size_t nc = H->lev[nl - 1].nodes();
-    const size_t prow = std::max<size_t>(2048, (size_t)nod_resid_tiles(H->lev[0]));   // partial-sum rows
-    bytes += al(nc * nc * 8) + al(prow * kReduceWidth * 8) + al(64 * 8);
+    const size_t bytes = nod_layout(p, nl, H->lev);
     if (hipMalloc(&H->ws, bytes) != hipSuccess) {
         (void)hipGetLastError();
         delete H;
         set_error("hipMalloc of the nodal hierarchy failed");
         return MG_ERR_OOM;
     }
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t nc = H->lev[nl - 1].nodes();
+    const size_t prow = nod_partial_rows(H->lev[0]);
     char* b = (char*)H->ws;
     auto take = [&](size_t n) {
         char* q = b;

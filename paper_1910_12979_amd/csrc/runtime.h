@@ -100,4 +100,14 @@ void bottom_args(mg_hierarchy* H, int l, BottomArgs<T>& a);
 int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, const double* b0e,
                        const double* S, const double* u, const double* v, const double* w, hipStream_t st,
                        const double* w0 = nullptr, const Radial* rad = nullptr);
+// Multi-box finest level of box-cell boxes for params p (MG_ERR_INVALID_ARG
+// for a box size mg_set_boxes refuses), and the device bytes of its arrays
+// (0 for such a box size).
+int box_layout(const mg_params& p, const int32_t box[3], BoxSet* out, size_t* e, size_t* eb);
+size_t box_bytes(const mg_params& p, const int32_t box[3]);
+// Nodal projection: device bytes of a hierarchy for p (0 if not solvable),
+// and new solver controls (rtol, cycles, sweeps) for an existing one of the
+// same shape.
+size_t nodal_bytes(const mg_params* p);
+void nodal_rebind(nodal_handle h, const mg_params* p);
 }  // namespace mg

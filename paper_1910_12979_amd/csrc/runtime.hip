@@ -1369,6 +1369,48 @@ namespace {
 int g_forced_for_tuner() { return tune_forced(); }
 }  // namespace
 
+namespace mg {
+
+// Layout of a multi-box finest level of box-cell boxes for params p: the box
+// grid, ghosted sizes and whether every box takes the fused sweep, and the
+// padded element counts of one box array (e) and of one beta0 table (eb).
+int box_layout(const mg_params& p, const int32_t box[3], BoxSet* out, size_t* e, size_t* eb) {
+    BoxSet B{};
+    int emin[3];                               // the smallest box's cells per direction
+    for (int d = 0; d < 3; ++d) {
+        const int n = p.n[d];
+        if (box[d] < 2 || box[d] % 2 != 0 || box[d] > n) {
+            set_error("box sizes must be even, at least 2, and at most the domain size in each direction");
+            return MG_ERR_INVALID_ARG;
+        }
+        B.n[d] = n;
+        B.B[d] = box[d];
+        B.nb[d] = (n + box[d] - 1) / box[d];  // the last box holds the (even) remainder
+        B.G[d] = box[d] + 2 * kBoxGhost;
+        emin[d] = n - (B.nb[d] - 1) * box[d];
+    }
+    B.nbox = B.nb[0] * B.nb[1] * B.nb[2];
+    B.stride = (size_t)B.G[0] * B.G[1] * B.G[2];
+    B.fused = sweep_boxes_fit(emin[0], emin[1], emin[2]) ? 1 : 0;   // every box takes the fused sweep
+    if (B.stride >= ((size_t)1 << 31)) {
+        set_error("box too large: its ghosted array must stay below 2^31 cells");
+        return MG_ERR_INVALID_ARG;
+    }
+    *e = (B.stride * B.nbox + 31) / 32 * 32;     // 256-byte aligned sub-arrays
+    *eb = ((size_t)B.G[2] * B.nbox + 31) / 32 * 32;
+    *out = B;
+    return MG_OK;
+}
+
+size_t box_bytes(const mg_params& p, const int32_t box[3]) {
+    BoxSet B;
+    size_t e = 0, eb = 0;
+    if (box_layout(p, box, &B, &e, &eb) != MG_OK) return 0;
+    return (7 * e + 2 * eb) * sizeof(double);
+}
+
+}  // namespace mg
+
 extern "C" {
 
 void mg_default_params(mg_params* p, int32_t nx, int32_t ny, int32_t nz, double dx) {
@@ -1665,31 +1707,12 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
         return MG_ERR_INVALID_ARG;
     }
     BoxSet B{};
-    int emin[3];                               // the smallest box's cells per direction
-    for (int d = 0; d < 3; ++d) {
-        const int n = h->p.n[d];
-        if (box[d] < 2 || box[d] % 2 != 0 || box[d] > n) {
-            set_error("box sizes must be even, at least 2, and at most the domain size in each direction");
-            return MG_ERR_INVALID_ARG;
-        }
-        B.n[d] = n;
-        B.B[d] = box[d];
-        B.nb[d] = (n + box[d] - 1) / box[d];  // the last box holds the (even) remainder
-        B.G[d] = box[d] + 2 * kBoxGhost;
-        emin[d] = n - (B.nb[d] - 1) * box[d];
-    }
+    size_t e = 0, eb = 0;
+    const int rc = box_layout(h->p, box, &B, &e, &eb);
+    if (rc) return rc;
     B.per[0] = h->px;
     B.per[1] = h->py;
     B.per[2] = h->pz;
-    B.nbox = B.nb[0] * B.nb[1] * B.nb[2];
-    B.stride = (size_t)B.G[0] * B.G[1] * B.G[2];
-    B.fused = sweep_boxes_fit(emin[0], emin[1], emin[2]) ? 1 : 0;   // every box takes the fused sweep
-    if (B.stride >= ((size_t)1 << 31)) {
-        set_error("box too large: its ghosted array must stay below 2^31 cells");
-        return MG_ERR_INVALID_ARG;
-    }
-    const size_t e = (B.stride * B.nbox + 31) / 32 * 32;     // 256-byte aligned sub-arrays
-    const size_t eb = ((size_t)B.G[2] * B.nbox + 31) / 32 * 32;
     if (h->box_mem) HIPCHK(hipFree(h->box_mem));
     h->box_mem = nullptr;
     h->boxes_on = false;

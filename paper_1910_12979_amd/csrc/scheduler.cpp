@@ -5,8 +5,10 @@
 
 namespace mg {
 
-ShapeKey key_of(const mg_params& p, int device) {
-    return ShapeKey(device, p.n[0], p.n[1], p.n[2], p.bc[0], p.bc[1], p.bc[2], p.precision, p.dx);
+ShapeKey key_of(const mg_problem& pr, int device) {
+    const mg_params& p = pr.p;
+    return ShapeKey(device, pr.kind, p.n[0], p.n[1], p.n[2], p.bc[0], p.bc[1], p.bc[2], p.precision, p.dx,
+                    pr.box[0], pr.box[1], pr.box[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -20,13 +22,13 @@ void SlotPool::clear() {
     idle_bytes = 0;
 }
 
-bool SlotPool::has_idle(const mg_params& p, int dev) const {
-    auto it = idle.find(key_of(p, dev));
+bool SlotPool::has_idle(const mg_problem& pr, int dev) const {
+    auto it = idle.find(key_of(pr, dev));
     return it != idle.end() && !it->second.empty();
 }
 
-int SlotPool::acquire(const mg_params& p, int dev, void** out) {
-    const ShapeKey k = key_of(p, dev);
+int SlotPool::acquire(const mg_problem& pr, int dev, void** out) {
+    const ShapeKey k = key_of(pr, dev);
     auto it = idle.find(k);
     if (it != idle.end() && !it->second.empty()) {
         void* s = it->second.front();
@@ -34,13 +36,13 @@ int SlotPool::acquire(const mg_params& p, int dev, void** out) {
         const size_t b = meta.at(s).bytes;
         idle_bytes -= b;
         busy_bytes += b;
-        ex->rebind(s, p);
+        ex->rebind(s, pr);
         *out = s;
         return MG_OK;
     }
     void* s = nullptr;
     size_t b = 0;
-    const int rc = ex->create(p, &s, &b);
+    const int rc = ex->create(pr, &s, &b);
     if (rc != MG_OK) return rc;
     meta[s] = Meta{k, b};
     busy_bytes += b;
@@ -88,7 +90,7 @@ Scheduler::~Scheduler() {
 }
 
 int Scheduler::submit(const mg_problem& pr, uint64_t* ticket, double t_submit) {
-    const size_t need = ex_->bytes_for(pr.p);
+    const size_t need = ex_->bytes_for(pr);
     if (need > budget_) return MG_ERR_BUDGET;
     auto j = std::make_unique<Job>();
     j->pr = pr;
@@ -185,10 +187,10 @@ void Scheduler::run() {
         // without holding the lock
         while (!cand.empty()) {
             Job* j = cand.front();
-            const bool reuse = pool_.has_idle(j->pr.p, device_);
+            const bool reuse = pool_.has_idle(j->pr, device_);
             const size_t need = reuse ? 0 : j->bytes;
             if (pool_.busy_bytes + pool_.idle_bytes + need > budget_) {
-                const ShapeKey k = key_of(j->pr.p, device_);
+                const ShapeKey k = key_of(j->pr, device_);
                 const size_t target = budget_ > pool_.busy_bytes + need ? budget_ - pool_.busy_bytes - need : 0;
                 pool_.trim(target, &k);
                 if (pool_.busy_bytes + pool_.idle_bytes + need > budget_) break;   // wait for completions
@@ -197,7 +199,7 @@ void Scheduler::run() {
             j->t_admit = ex_->now();
             // reserve the state now, so the next request in this pass sees
             // the pool as it will be
-            j->status = pool_.acquire(j->pr.p, device_, &j->slot);
+            j->status = pool_.acquire(j->pr, device_, &j->slot);
             fresh.push_back(j);
         }
         {

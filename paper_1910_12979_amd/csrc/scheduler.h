@@ -62,13 +62,13 @@ struct Executor {
     virtual ~Executor() = default;
     // first call on the worker thread
     virtual void bind() {}
-    // resident bytes a request of these params needs
-    virtual size_t bytes_for(const mg_params& p) = 0;
-    // a new resident state for a shape (status, *slot, *bytes)
-    virtual int create(const mg_params& p, void** slot, size_t* bytes) = 0;
+    // resident bytes a request needs
+    virtual size_t bytes_for(const mg_problem& pr) = 0;
+    // a new resident state for the request's kind and shape (status, *slot, *bytes)
+    virtual int create(const mg_problem& pr, void** slot, size_t* bytes) = 0;
     virtual void destroy(void* slot) = 0;
-    // hand an idle state of the same shape to a request with params p
-    virtual void rebind(void* slot, const mg_params& p) = 0;
+    // hand an idle state of the same key to a request (its solver controls)
+    virtual void rebind(void* slot, const mg_problem& pr) = 0;
     // false: the job is solved on its own, to completion, by solo()
     virtual bool batchable(Job* j) = 0;
     virtual int solo(Job* j) = 0;
@@ -86,10 +86,11 @@ struct Executor {
     virtual bool idle() { return false; }
 };
 
-using ShapeKey = std::tuple<int, int, int, int, int, int, int, int, double>;
-ShapeKey key_of(const mg_params& p, int device);
+// device, kind, shape, boundaries, precision, spacing, box size
+using ShapeKey = std::tuple<int, int, int, int, int, int, int, int, int, double, int, int, int>;
+ShapeKey key_of(const mg_problem& pr, int device);
 
-// Idle resident states kept for reuse, keyed by device and shape.
+// Idle resident states kept for reuse, keyed by device, kind and shape.
 struct SlotPool {
     Executor* ex = nullptr;
     struct Meta {
@@ -104,10 +105,10 @@ struct SlotPool {
     explicit SlotPool(Executor* e) : ex(e) {}
     ~SlotPool() { clear(); }
     void clear();
-    bool has_idle(const mg_params& p, int dev) const;
-    // the oldest idle state of the shape (a repeated batch gets the same
+    bool has_idle(const mg_problem& pr, int dev) const;
+    // the oldest idle state of the key (a repeated batch gets the same
     // states in the same order), else a new one
-    int acquire(const mg_params& p, int dev, void** out);
+    int acquire(const mg_problem& pr, int dev, void** out);
     void release(void* slot);
     // free idle states (other shapes than *keep first, newest of a shape
     // first) until idle_bytes <= target

@@ -56,10 +56,14 @@ class Stats(ctypes.Structure):
         return d
 
 
+MG_KIND_MAC, MG_KIND_NODAL = 0, 1
+
+
 class Problem(ctypes.Structure):
     _fields_ = [("p", Params), ("rho", ctypes.c_void_p), ("beta0_cc", ctypes.c_void_p),
                 ("beta0_edge", ctypes.c_void_p), ("S", ctypes.c_void_p), ("u", ctypes.c_void_p),
-                ("v", ctypes.c_void_p), ("w", ctypes.c_void_p), ("phi", ctypes.c_void_p)]
+                ("v", ctypes.c_void_p), ("w", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("kind", ctypes.c_int32), ("box", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -480,8 +484,9 @@ def params_of(prob, precision="fp64", rtol=None, max_cycles=None) -> Params:
                        outflow=getattr(prob, "outflow", None))
 
 
-def problem_struct(params: Params, d) -> Problem:
-    """mg_problem for device tensors d (a namespace from to_device)."""
+def problem_struct(params: Params, d, box=None) -> Problem:
+    """mg_problem for device tensors d (a namespace from to_device); box:
+    cells per box of a multi-box finest level (None: one box)."""
     import torch
     sh = field_shapes(tuple(params.n))
     f64 = torch.float64
@@ -495,18 +500,52 @@ def problem_struct(params: Params, d) -> Problem:
     pr.v = _ptr(d.v, f64, sh["v"], "v")
     pr.w = _ptr(d.w, f64, sh["w"], "w")
     pr.phi = _ptr(d.phi, f64, sh["phi"], "phi") if d.phi is not None else None
+    pr.kind = MG_KIND_MAC
+    if box is not None:
+        for k in range(3):
+            pr.box[k] = int(box[k])
     return pr
 
 
-def project_batch(params_list, tensors_list, stream=None):
-    """Solve many problems with shared launches; returns (code, [stats dicts])."""
-    n = len(params_list)
-    arr = (Problem * n)()
-    for i, (p, d) in enumerate(zip(params_list, tensors_list)):
-        arr[i] = problem_struct(p, d)
+def nodal_problem_struct(params: Params, d) -> Problem:
+    """mg_problem of kind MG_KIND_NODAL for device tensors d (a namespace
+    from nodal_to_device): u, v, w are the cell-centred velocities, phi the
+    node values."""
+    import torch
+    nx, ny, nz = tuple(params.n)
+    cell = (nz, ny, nx)
+    per = tuple(params.bc[k] == MG_BC_PERIODIC for k in range(3))
+    f64 = torch.float64
+    pr = Problem()
+    pr.p = params
+    pr.rho = _ptr(d.rho, f64, cell, "rho")
+    pr.beta0_cc = _ptr(d.beta0_cc, f64, (nz,), "beta0_cc")
+    pr.beta0_edge = None
+    pr.S = _ptr(d.S, f64, cell, "S")
+    pr.u = _ptr(d.uc, f64, cell, "uc")
+    pr.v = _ptr(d.vc, f64, cell, "vc")
+    pr.w = _ptr(d.wc, f64, cell, "wc")
+    pr.phi = _ptr(d.phi, f64, node_dims((nx, ny, nz), per)[::-1], "phi") if d.phi is not None else None
+    pr.kind = MG_KIND_NODAL
+    return pr
+
+
+def project_batch_problems(problems, stream=None):
+    """project_batch over mg_problem structs (any kinds); returns (code, [stats dicts])."""
+    n = len(problems)
+    arr = (Problem * max(n, 1))()
+    for i, pr in enumerate(problems):
+        arr[i] = pr
     stats = (Stats * max(n, 1))()
     code = lib().project_batch(n, arr, stats, _stream(stream))
     return code, [stats[i].as_dict() for i in range(n)]
+
+
+def project_batch(params_list, tensors_list, stream=None, boxes=None):
+    """Solve many MAC problems with shared launches; returns (code, [stats dicts])."""
+    boxes = boxes or [None] * len(params_list)
+    return project_batch_problems([problem_struct(p, d, b) for p, d, b in zip(params_list, tensors_list, boxes)],
+                                  stream)
 
 
 class Server:
@@ -517,12 +556,19 @@ class Server:
         _check(lib().serve_create(int(hbm_budget_bytes), int(max_inflight), ctypes.byref(self._s)))
         self._keep = {}
 
-    def submit(self, params: Params, d) -> int:
-        """Queue a projection of the tensors in d; they must stay alive (this
-        object keeps a reference) until the ticket completes."""
+    def submit(self, params: Params, d, box=None) -> int:
+        """Queue a MAC projection of the tensors in d (box: multi-box finest
+        level); they must stay alive (this object keeps a reference) until
+        the ticket completes."""
+        return self.submit_problem(problem_struct(params, d, box), d)
+
+    def submit_nodal(self, params: Params, d) -> int:
+        """Queue a nodal projection of the tensors in d (from nodal_to_device)."""
+        return self.submit_problem(nodal_problem_struct(params, d), d)
+
+    def submit_problem(self, pr: Problem, d) -> int:
         import torch
         torch.cuda.current_stream().synchronize()      # inputs ready for the server's stream
-        pr = problem_struct(params, d)
         t = ctypes.c_uint64()
         _check(lib().serve_submit(self._s, ctypes.byref(pr), ctypes.byref(t)))
         self._keep[t.value] = d            # keep the buffers alive until done

@@ -100,8 +100,10 @@ struct FakeExecutor final : Executor {
         return k;
     }
 
-    size_t bytes_for(const mg_params& p) override { return (size_t)(cells(p) * c.state_bpc); }
-    int create(const mg_params& p, void** slot, size_t* bytes) override {
+    size_t bytes_for(const mg_params& p) const { return (size_t)(cells(p) * c.state_bpc); }
+    size_t bytes_for(const mg_problem& pr) override { return bytes_for(pr.p); }
+    int create(const mg_problem& pr, void** slot, size_t* bytes) override {
+        const mg_params& p = pr.p;
         if (p.n[2] == c.oom_nz) return MG_ERR_OOM;
         auto* s = new State{p, next_id++};
         *slot = s;
@@ -117,7 +119,7 @@ struct FakeExecutor final : Executor {
         rep->live -= (double)bytes_for(s->p);
         delete s;
     }
-    void rebind(void* slot, const mg_params& p) override { static_cast<State*>(slot)->p = p; }
+    void rebind(void* slot, const mg_problem& pr) override { static_cast<State*>(slot)->p = pr.p; }
     bool batchable(Job* j) override { return j->pr.p.n[0] >= c.solo_below_nx; }
     int solo(Job* j) override {
         log_admit(j);

@@ -42,14 +42,15 @@ def test_struct_layouts_match_ctypes(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "macproj.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(mg_params), sizeof(mg_stats),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(mg_params), sizeof(mg_stats),"
         " sizeof(mg_problem), offsetof(mg_params, rtol), offsetof(mg_stats, resid_hist),"
-        " offsetof(mg_problem, phi));return 0;}\n")
+        " offsetof(mg_problem, phi), offsetof(mg_problem, kind), offsetof(mg_problem, box));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(M.Params), ctypes.sizeof(M.Stats), ctypes.sizeof(M.Problem),
-            M.Params.rtol.offset, M.Stats.resid_hist.offset, M.Problem.phi.offset]
+            M.Params.rtol.offset, M.Stats.resid_hist.offset, M.Problem.phi.offset, M.Problem.kind.offset,
+            M.Problem.box.offset]
     assert got == want
 
 

@@ -188,3 +188,146 @@ def test_server_budget_and_failures(mp):
     for i in (0, 2):
         out = {k: getattr(devs[i], k).cpu().numpy() for k in ("phi", "u", "v", "w")}
         assert same(out, ref[i][1])
+
+
+# ---------------------------------------------------------------- other problem kinds
+def solo_boxes(mp, prob, box):
+    H = mp.Hierarchy(mp.params_of(prob))
+    H.set_boxes(box)
+    d = mp.to_device(prob)
+    st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+    torch.cuda.synchronize()
+    H.close()
+    return st, {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+
+
+def nodal_params(mp, prob):
+    return mp.make_params(prob.n, prob.dx, prob.periodic, rtol=prob.rtol)
+
+
+def solo_nodal(mp, prob):
+    H = mp.NodalHierarchy(nodal_params(mp, prob))
+    d = mp.nodal_to_device(prob)
+    st = H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi)
+    torch.cuda.synchronize()
+    H.close()
+    return st, nodal_out(d)
+
+
+def nodal_out(d):
+    return {"phi": d.phi.cpu().numpy(), "u": d.uc.cpu().numpy(), "v": d.vc.cpu().numpy(), "w": d.wc.cpu().numpy()}
+
+
+def mac_out(d):
+    return {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+
+
+def check_mac_oracle(prob, out):
+    ref = O.mac_project(prob, mode="definition")
+    alg = O.mac_project(prob)
+    assert ref["status"] == 0 and alg["status"] == 0
+    for k in ("phi", "u", "v", "w"):
+        assert rel(out[k], ref[k]) <= max(1e-9, 3 * rel(alg[k], ref[k])), k
+
+
+def check_nodal_oracle(prob, out):
+    ref = O.nodal_project(prob, mode="definition")
+    alg = O.nodal_project(prob)
+    assert ref["status"] == 0 and alg["status"] == 0
+    for k in ("phi", "u", "v", "w"):
+        assert rel(out[k], ref[k]) <= max(1e-9, 3 * rel(alg[k], ref[k])), k
+
+
+def kinds_mix():
+    """Single-box MAC problems (batched), multi-box ones with even and uneven
+    boxes, and nodal projections."""
+    mac = [I.make_problem(32, H=0.15, seed=301), I.make_problem(64, H=0.1, seed=302)]
+    boxed = [(I.make_problem((40, 24, 56), H=0.15, rho_noise=0.05, seed=303, dx=1 / 40), (16, 16, 24)),
+             (I.make_problem((96, 64, 64), H=0.15, rho_noise=0.05, seed=304, periodic=(True, True, True),
+                             dx=1 / 96), (64, 48, 40)),
+             (I.make_problem(32, H=0.2, rho_noise=0.05, seed=305), (16, 16, 16))]
+    nodal = [I.make_nodal_problem((32, 32, 32), seed=306, periodic=(True, True, False)),
+             I.make_nodal_problem((24, 16, 32), seed=307, periodic=(False, False, False))]
+    return mac, boxed, nodal
+
+
+def test_batch_of_mixed_kinds_matches_solo_and_oracle(mp):
+    """One project_batch call holding single-box, multi-box (uneven boxes
+    included) and nodal problems: every result equals its own entry point's
+    solo result bit for bit, and is within the oracle bar of its kind."""
+    mac, boxed, nodal = kinds_mix()
+    ref_mac = [solo(mp, p) for p in mac]
+    ref_box = [solo_boxes(mp, p, b) for p, b in boxed]
+    ref_nod = [solo_nodal(mp, p) for p in nodal]
+    d_mac = [mp.to_device(p) for p in mac]
+    d_box = [mp.to_device(p) for p, _ in boxed]
+    d_nod = [mp.nodal_to_device(p) for p in nodal]
+    probs = ([mp.problem_struct(mp.params_of(p), d) for p, d in zip(mac, d_mac)]
+             + [mp.problem_struct(mp.params_of(p), d, b) for (p, b), d in zip(boxed, d_box)]
+             + [mp.nodal_problem_struct(nodal_params(mp, p), d) for p, d in zip(nodal, d_nod)])
+    # interleave the kinds
+    order = [0, 2, 5, 1, 3, 6, 4]
+    code, stats = mp.project_batch_problems([probs[i] for i in order])
+    torch.cuda.synchronize()
+    assert code == 0, stats
+    st = [None] * len(order)
+    for pos, i in enumerate(order):
+        st[i] = stats[pos]
+    refs = ref_mac + ref_box + ref_nod
+    outs = [mac_out(d) for d in d_mac] + [mac_out(d) for d in d_box] + [nodal_out(d) for d in d_nod]
+    for i, ((st0, out0), s, out) in enumerate(zip(refs, st, outs)):
+        assert s["status_name"] == "OK", (i, s)
+        assert s["cycles"] == st0["cycles"] and s["rel_resid"] == st0["rel_resid"], i
+        assert same(out, out0), i
+    check_mac_oracle(boxed[1][0], outs[3])
+    check_mac_oracle(boxed[0][0], outs[2])
+    check_nodal_oracle(nodal[0], outs[5])
+    check_nodal_oracle(nodal[1], outs[6])
+
+
+def test_server_of_mixed_kinds_matches_solo_and_oracle(mp):
+    """The same mixture served (arrivals while others run): each result equals
+    the solo one bit for bit; one uneven-box and one nodal result against the
+    oracle; a nodal request with boxes is refused at submission, a mixed-
+    precision request with boxes fails at admission."""
+    mac, boxed, nodal = kinds_mix()
+    ref_mac = [solo(mp, p) for p in mac]
+    ref_box = [solo_boxes(mp, p, b) for p, b in boxed]
+    ref_nod = [solo_nodal(mp, p) for p in nodal]
+    S = mp.Server(hbm_budget_bytes=8 << 30, max_inflight=8)
+    d_mac = [mp.to_device(p) for p in mac]
+    d_box = [mp.to_device(p) for p, _ in boxed]
+    d_nod = [mp.nodal_to_device(p) for p in nodal]
+    t = []
+    t.append(S.submit(mp.params_of(mac[0]), d_mac[0]))
+    t.append(S.submit_nodal(nodal_params(mp, nodal[0]), d_nod[0]))
+    t.append(S.submit(mp.params_of(boxed[1][0]), d_box[1], box=boxed[1][1]))
+    time.sleep(0.002)
+    t.append(S.submit(mp.params_of(mac[1]), d_mac[1]))
+    t.append(S.submit(mp.params_of(boxed[0][0]), d_box[0], box=boxed[0][1]))
+    t.append(S.submit_nodal(nodal_params(mp, nodal[1]), d_nod[1]))
+    t.append(S.submit(mp.params_of(boxed[2][0]), d_box[2], box=boxed[2][1]))
+    bad_n = I.make_nodal_problem((16, 16, 16), seed=308, periodic=(True, True, False))
+    pr = mp.nodal_problem_struct(nodal_params(mp, bad_n), mp.nodal_to_device(bad_n))
+    pr.box[0] = pr.box[1] = pr.box[2] = 8
+    with pytest.raises(mp.MGError):
+        S.submit_problem(pr, None)
+    bad_m = I.make_problem(32, seed=309)
+    d_bad = mp.to_device(bad_m)
+    t_bad = S.submit(mp.params_of(bad_m, precision="mixed"), d_bad, box=(16, 16, 16))
+    res = [S.wait(x) for x in t]
+    r_bad = S.wait(t_bad)
+    c = S.counters()
+    S.close()
+    assert r_bad["status_name"] == "INVALID_ARG"
+    assert c["completed"] == len(t) + 1
+    got = {0: (res[0], mac_out(d_mac[0]), ref_mac[0]), 1: (res[1], nodal_out(d_nod[0]), ref_nod[0]),
+           2: (res[2], mac_out(d_box[1]), ref_box[1]), 3: (res[3], mac_out(d_mac[1]), ref_mac[1]),
+           4: (res[4], mac_out(d_box[0]), ref_box[0]), 5: (res[5], nodal_out(d_nod[1]), ref_nod[1]),
+           6: (res[6], mac_out(d_box[2]), ref_box[2])}
+    for i, (r, out, (st0, out0)) in got.items():
+        assert r["status_name"] == "OK", (i, r)
+        assert r["cycles"] == st0["cycles"], i
+        assert same(out, out0), i
+    check_mac_oracle(boxed[1][0], got[2][1])
+    check_nodal_oracle(nodal[1], got[5][1])
