@@ -81,7 +81,10 @@ typedef enum {
 } mg_status;
 
 /* Per direction: both sides periodic, both solid walls, both outflow, or a
- * wall on the low side and an outflow on the high side (and the reverse). */
+ * wall on the low side and an outflow on the high side (and the reverse).
+ * One code per direction, where a sketch with separate low/high side arrays
+ * would take two: the periodic case pairs the sides anyway, and the two mixed
+ * codes cover a wall facing an outflow. */
 typedef enum {
     MG_BC_PERIODIC = 0,
     MG_BC_WALL = 1,
@@ -161,7 +164,11 @@ size_t mg_workspace_bytes(const mg_params* p);
 /* Build a hierarchy for the shape in *p on the current device.
  * workspace: NULL -> the library allocates (and frees in mg_destroy);
  * otherwise a device buffer of at least mg_workspace_bytes(p) bytes, 256-byte
- * aligned, owned by the caller and kept alive until mg_destroy. */
+ * aligned, owned by the caller and kept alive until mg_destroy.
+ * Set-up takes the shape only, not rho, beta0 or a stream: rho and beta0 change
+ * every time step of the method, so they are arguments of each projection
+ * (mac_project builds the coefficients from them inside the solve), and every
+ * call that does device work takes its own stream. */
 int mg_setup(const mg_params* p, void* workspace, size_t ws_bytes, mg_handle* out);
 
 /* Release a hierarchy (NULL is allowed). */
