@@ -133,9 +133,10 @@ typedef enum { MG_KIND_MAC = 0, MG_KIND_NODAL = 1 } mg_problem_kind;
  * kind MG_KIND_MAC: pointers as for mac_project; box = cells per box of a
  * multi-box finest level as for mg_set_boxes (FP64, periodic or wall sides),
  * {0, 0, 0} for a single box.
- * kind MG_KIND_NODAL: the nodal projection (nodal_project): u, v, w are the
- * cell-centred velocity components, corrected in place, phi (nullable) the
- * node values; beta0_edge is not read (may be NULL); box must be {0, 0, 0}.
+ * kind MG_KIND_NODAL: the nodal projection (nodal_project, FP64 or mixed):
+ * u, v, w are the cell-centred velocity components, corrected in place, phi
+ * (nullable) the node values; beta0_edge is not read (may be NULL); box must
+ * be {0, 0, 0}.
  * A zero-filled tail (kind 0, box {0, 0, 0}) is the single-box MAC problem. */
 typedef struct {
     mg_params p;
@@ -266,7 +267,11 @@ int mg_map_radial(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t nr, dou
  * rho_c with G the cell's mean gradient of phi.  The projection is
  * approximate: L is not D sigma G, so the corrected velocity meets the
  * constraint to truncation error.  Boundaries: periodic (node n is node 0) or
- * solid wall (natural: wall nodes are unknowns); FP64.
+ * solid wall (natural: wall nodes are unknowns).  Precision: FP64, or
+ * MG_MIXED: each iteration one FP32 V-cycle from zero on the FP64 residual
+ * scaled by the power of two nearest 1/rms(r), the FP32 correction added to
+ * the FP64 phi (divided by that power of two, exactly), r = f - L phi and
+ * its norm in FP64, the same stop test; stats.cycles counts iterations.
  * Layout: rho, S, uc, vc, wc (nz, ny, nx) cells; beta0_cc (nz); phi nodes
  * (Nz, Ny, Nx) with N = n (periodic) or n + 1 (walls), C order.  Device
  * pointers, caller-owned. */
@@ -275,7 +280,8 @@ typedef struct nodal_hierarchy* nodal_handle;
 /* Levels for params (0: not solvable: bc other than periodic/wall, or the
  * coarsest level would exceed 512 nodes). */
 int32_t nodal_num_levels_for(const mg_params* p);
-/* Allocate a nodal hierarchy (p->precision must be MG_FP64). */
+/* Allocate a nodal hierarchy (FP64, or MG_MIXED with FP32 copies of every
+ * level's arrays). */
 int nodal_setup(const mg_params* p, nodal_handle* out);
 int nodal_destroy(nodal_handle h);
 /* The whole nodal projection: coefficients and right-hand side,

@@ -50,8 +50,8 @@ int check_problem(const mg_problem& pr) {
         set_error("null field pointer in a problem");
         return MG_ERR_INVALID_ARG;
     }
-    if (pr.kind == MG_KIND_NODAL && (has_box(pr) || pr.p.precision != MG_FP64)) {
-        set_error("a nodal problem runs in FP64 on a single box");
+    if (pr.kind == MG_KIND_NODAL && has_box(pr)) {
+        set_error("a nodal problem runs on a single box");
         return MG_ERR_INVALID_ARG;
     }
     if (has_box(pr) && (pr.box[0] <= 0 || pr.box[1] <= 0 || pr.box[2] <= 0)) {

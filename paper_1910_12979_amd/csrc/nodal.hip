@@ -44,20 +44,23 @@ namespace {
 constexpr int kNodBlock = 256;
 constexpr int kNodSetupThreads = 1024;
 
-// One level of the nodal hierarchy: cells (nx, ny, nz), nodes (Nx, Ny, Nz).
-struct NodLevel {
+// One level of the nodal hierarchy: cells (nx, ny, nz), nodes (Nx, Ny, Nz);
+// arrays in T (FP64, or FP32 for the inner cycle of a mixed-precision solve).
+template <typename T>
+struct NodLevelT {
     int nx, ny, nz;
     int Nx, Ny, Nz;
     int px, py, pz;
     double h;
-    double* sig;        // cells
-    double* phi;        // nodes
-    double* f;
-    double* r;
-    double* phi2;       // nodes: the other buffer of the out-of-place fused sweep
+    T* sig;             // cells
+    T* phi;             // nodes
+    T* f;
+    T* r;
+    T* phi2;            // nodes: the other buffer of the out-of-place fused sweep
     __host__ __device__ size_t nodes() const { return (size_t)Nx * Ny * Nz; }
     __host__ __device__ size_t cells() const { return (size_t)nx * ny * nz; }
 };
+using NodLevel = NodLevelT<double>;
 
 __device__ inline int nod_cell(int I, int s, int n, int per) {
     int c = s ? I : I - 1;
@@ -71,11 +74,13 @@ __device__ inline int nod_node(int I, int o, int N, int per) {
     return (m >= 0 && m < N) ? m : -1;
 }
 
-__device__ inline size_t nidx(const NodLevel& L, int I, int J, int K) {
+template <typename T>
+__device__ inline size_t nidx(const NodLevelT<T>& L, int I, int J, int K) {
     return ((size_t)K * L.Ny + J) * L.Nx + I;
 }
 
-__device__ inline size_t cidx3(const NodLevel& L, int i, int j, int k) {
+template <typename T>
+__device__ inline size_t cidx3(const NodLevelT<T>& L, int i, int j, int k) {
     return ((size_t)k * L.ny + j) * L.nx + i;
 }
 
@@ -109,12 +114,14 @@ __device__ inline NodAxis nod_axis(int X, int N, int n, int per) {
 // The 20 neighbours of node (I, J, K) that the stencil couples (moved in at
 // least two directions), each loaded once: v[dz+1][dy+1][dx+1]; entries
 // whose node does not exist (beyond a wall) are never used and stay 0.
+template <typename T>
 struct NodNbr {
-    double v[3][3][3];
+    T v[3][3][3];
 };
 
-__device__ inline void nod_load_nbrs(const NodLevel& L, const double* __restrict__ phi, int I, const NodAxis& ax,
-                                     const NodAxis& ay, const NodAxis& az, int J, int K, NodNbr& N) {
+template <typename T>
+__device__ inline void nod_load_nbrs(const NodLevelT<T>& L, const T* __restrict__ phi, int I, const NodAxis& ax,
+                                     const NodAxis& ay, const NodAxis& az, int J, int K, NodNbr<T>& N) {
     const long long Nx = L.Nx, NxNy = (long long)L.Nx * L.Ny;
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz)
@@ -127,7 +134,7 @@ __device__ inline void nod_load_nbrs(const NodLevel& L, const double* __restrict
                 const long long xi = dx == 0 ? I : ax.m[dx > 0];
                 const long long yi = dy == 0 ? J : ay.m[dy > 0];
                 const long long zi = dz == 0 ? K : az.m[dz > 0];
-                N.v[dz + 1][dy + 1][dx + 1] = ok ? phi[zi * NxNy + yi * Nx + xi] : 0.0;
+                N.v[dz + 1][dy + 1][dx + 1] = ok ? phi[zi * NxNy + yi * Nx + xi] : T(0);
             }
 }
 
@@ -135,16 +142,17 @@ __device__ inline void nod_load_nbrs(const NodLevel& L, const double* __restrict
 // the existing cells at node (I, J, K), in the oracle's order (cells sz, sy,
 // sx; far corners of the cell on side (sx, sy, sz): x+y, x+z, y+z, x+y+z
 // moved), with per-axis index tables and each neighbour loaded once.
-__device__ inline void nod_stencil_fast(const NodLevel& L, const double* __restrict__ phi, int I, int J, int K,
-                                        double& num, double& den) {
+template <typename T>
+__device__ inline void nod_stencil_fast(const NodLevelT<T>& L, const T* __restrict__ phi, int I, int J, int K,
+                                        T& num, T& den) {
     const NodAxis ax = nod_axis(I, L.Nx, L.nx, L.px);
     const NodAxis ay = nod_axis(J, L.Ny, L.ny, L.py);
     const NodAxis az = nod_axis(K, L.Nz, L.nz, L.pz);
-    NodNbr N;
+    NodNbr<T> N;
     nod_load_nbrs(L, phi, I, ax, ay, az, J, K, N);
     const long long nx = L.nx, nxny = (long long)L.nx * L.ny;
-    num = 0.0;
-    den = 0.0;
+    num = T(0);
+    den = T(0);
 #pragma unroll
     for (int sz = 0; sz < 2; ++sz) {
         if (!az.e[sz]) continue;
@@ -157,14 +165,14 @@ __device__ inline void nod_stencil_fast(const NodLevel& L, const double* __restr
             for (int sx = 0; sx < 2; ++sx) {
                 if (!ax.e[sx]) continue;
                 const int ox = sx ? 2 : 0;
-                const double sig = L.sig[az.c[sz] * nxny + ay.c[sy] * nx + ax.c[sx]];
-                double acc = 0.0;
+                const T sig = L.sig[az.c[sz] * nxny + ay.c[sy] * nx + ax.c[sx]];
+                T acc = T(0);
                 acc += N.v[1][oy][ox];
                 acc += N.v[oz][1][ox];
                 acc += N.v[oz][oy][1];
                 acc += N.v[oz][oy][ox];
                 num += sig * acc;
-                den += 4.0 * sig;
+                den += T(4) * sig;
             }
         }
     }
@@ -262,15 +270,17 @@ __global__ __launch_bounds__(kNodBlock) void k_nod_rhs(NodLevel L, const double*
 
 // One colour of the Gauss-Seidel sweep; thread (I, tj, tk) owns node
 // (I, 2 tj + (col & 1), 2 tk + (col >> 1)).
-__global__ void k_nod_gs(NodLevel L, int col) {
+template <typename T>
+__global__ void k_nod_gs(NodLevelT<T> L, int col) {
     const int I = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     const int J = 2 * (int)(blockIdx.y * blockDim.y + threadIdx.y) + (col & 1);
     const int K = 2 * (int)(blockIdx.z * blockDim.z + threadIdx.z) + (col >> 1);
     if (I >= L.Nx || J >= L.Ny || K >= L.Nz) return;
-    double num, den;
+    T num, den;
     nod_stencil_fast(L, L.phi, I, J, K, num, den);
     const size_t n = nidx(L, I, J, K);
-    L.phi[n] = (num - 12.0 * (L.h * L.h) * L.f[n]) / den;
+    const T c12 = (T)(12.0 * (L.h * L.h));
+    L.phi[n] = (num - c12 * L.f[n]) / den;
 }
 
 // ---------------------------------------------------------------------------
@@ -313,12 +323,12 @@ __device__ inline int nod_m3(int k) {
     return k < 0 ? k + 3 : k;
 }
 
-template <int TX, int TY>
-__global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel L, double* __restrict__ out, int tz,
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevelT<T> L, T* __restrict__ out, int tz,
                                                                       int ntx, int nty, int etop) {
     constexpr int WX = TX + 8, WY = TY + 8, WP = WY / 2;
-    __shared__ double sp[4][WY][WX];        // node planes, by plane & 3
-    __shared__ double ss[3][WY - 1][WX];    // cell layers, by layer mod 3; [jw][wx]: the cell whose low corner is
+    __shared__ T sp[4][WY][WX];             // node planes, by plane & 3
+    __shared__ T ss[3][WY - 1][WX];         // cell layers, by layer mod 3; [jw][wx]: the cell whose low corner is
                                             // node (wx, jw) (the window's last row of cells is never read)
     const int tile = blockIdx.x;
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tc = tile / (ntx * nty);
@@ -341,7 +351,7 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
     const size_t NxNy = (size_t)L.Nx * L.Ny, nxny = (size_t)L.nx * L.ny;
     const size_t ne = (size_t)Jwe * L.Nx + Iw, no = (size_t)Jwo * L.Nx + Iw;
     const size_t ce = (size_t)jwe * L.nx + iw, co = (size_t)jwo * L.nx + iw;
-    const double c12 = 12.0 * (L.h * L.h);
+    const T c12 = (T)(12.0 * (L.h * L.h));
 
     auto plane_ok = [&](int K) { return L.pz || (K >= 0 && K < L.Nz); };
     auto layer_ok = [&](int k) { return L.pz || (k >= 0 && k < L.nz); };
@@ -351,39 +361,39 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
     // a set of them is plain load results the compiler never has to wait for
     // early; the values of nodes and cells beyond a wall are replaced by 0
     // when they are stored into LDS.
-    auto ld_phi = [&](int K, double& a, double& b) {
+    auto ld_phi = [&](int K, T& a, T& b) {
         const size_t o = (size_t)pw(K) * NxNy;
         a = L.phi[o + ne];
         b = L.phi[o + no];
     };
-    auto ld_sig = [&](int k, double& a, double& b) {
+    auto ld_sig = [&](int k, T& a, T& b) {
         const size_t o = (size_t)lw(k) * nxny;
         a = L.sig[o + ce];
         b = L.sig[o + co];
     };
-    auto ld_f = [&](int K, double& a, double& b) {
+    auto ld_f = [&](int K, T& a, T& b) {
         const size_t o = (size_t)pw(K) * NxNy;
         a = L.f[o + ne];
         b = L.f[o + no];
     };
-    auto st_phi = [&](int K, double a, double b) {
+    auto st_phi = [&](int K, T a, T b) {
         const bool ok = plane_ok(K) && xn;
-        sp[K & 3][je][wx] = (ok && yne) ? a : 0.0;
-        sp[K & 3][jo][wx] = (ok && yno) ? b : 0.0;
+        sp[K & 3][je][wx] = (ok && yne) ? a : T(0);
+        sp[K & 3][jo][wx] = (ok && yno) ? b : T(0);
     };
-    auto st_sig = [&](int k, double a, double b) {
+    auto st_sig = [&](int k, T a, T b) {
         const bool ok = layer_ok(k) && xc;
-        ss[nod_m3(k)][je][wx] = (ok && yce) ? a : 0.0;
-        if (jo < WY - 1) ss[nod_m3(k)][jo][wx] = (ok && yco) ? b : 0.0;
+        ss[nod_m3(k)][je][wx] = (ok && yce) ? a : T(0);
+        if (jo < WY - 1) ss[nod_m3(k)][jo][wx] = (ok && yco) ? b : T(0);
     };
     // the update of window node (x, y) of plane slot pc with planes below
     // (pm) and above (pp) and cell layers below (sm) and above (sq): the 20
     // coupled neighbours and 8 cell coefficients are read from LDS first (all
     // loads independent), then combined in the per-colour kernel's order:
     // cells sz, sy, sx; far corners x+y, x+z, y+z, x+y+z
-    auto update = [&](int x, int y, int pm, int pc, int pp, int sm, int sq, double fv) -> double {
-        double v[3][3][3];
-        double sg[2][2][2];
+    auto update = [&](int x, int y, int pm, int pc, int pp, int sm, int sq, T fv) -> T {
+        T v[3][3][3];
+        T sg[2][2][2];
 #pragma unroll
         for (int dz = 0; dz < 3; ++dz) {
             const int pl = dz == 0 ? pm : (dz == 1 ? pc : pp);
@@ -391,7 +401,7 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx)
-                    v[dz][dy][dx] = ((dx != 1) + (dy != 1) + (dz != 1) >= 2) ? sp[pl][y - 1 + dy][x - 1 + dx] : 0.0;
+                    v[dz][dy][dx] = ((dx != 1) + (dy != 1) + (dz != 1) >= 2) ? sp[pl][y - 1 + dy][x - 1 + dx] : T(0);
         }
 #pragma unroll
         for (int sz = 0; sz < 2; ++sz)
@@ -399,7 +409,7 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
             for (int sy = 0; sy < 2; ++sy)
 #pragma unroll
                 for (int sx = 0; sx < 2; ++sx) sg[sz][sy][sx] = ss[sz ? sq : sm][y - 1 + sy][x - 1 + sx];
-        double num = 0.0, den = 0.0;
+        T num = T(0), den = T(0);
 #pragma unroll
         for (int sz = 0; sz < 2; ++sz) {
             const int oz = sz ? 2 : 0;
@@ -409,13 +419,13 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
 #pragma unroll
                 for (int sx = 0; sx < 2; ++sx) {
                     const int ox = sx ? 2 : 0;
-                    const double sig = sg[sz][sy][sx];
-                    double acc = v[1][oy][ox];
+                    const T sig = sg[sz][sy][sx];
+                    T acc = v[1][oy][ox];
                     acc += v[oz][1][ox];
                     acc += v[oz][oy][1];
                     acc += v[oz][oy][ox];
-                    num = __fma_rn(sig, acc, num);
-                    den = __fma_rn(4.0, sig, den);
+                    num = fma(sig, acc, num);
+                    den = fma(T(4), sig, den);
                 }
             }
         }
@@ -434,7 +444,7 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
 
     // prologue: planes ks-1, ks, ks+1, layers ks-1, ks, f of plane ks
     {
-        double a0, b0, a1, b1, a2, b2, a3, b3, a4, b4;
+        T a0, b0, a1, b1, a2, b2, a3, b3, a4, b4;
         ld_phi(ks - 1, a0, b0);
         ld_phi(ks, a1, b1);
         ld_phi(ks + 1, a2, b2);
@@ -446,14 +456,14 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
         st_sig(ks - 1, a3, b3);
         st_sig(ks, a4, b4);
     }
-    double fe0, fo0, fe1 = 0.0, fo1 = 0.0;      // f of the even plane (e/o rows), of the odd plane below
+    T fe0, fo0, fe1 = T(0), fo1 = T(0);         // f of the even plane (e/o rows), of the odd plane below
     ld_f(ks, fe0, fo0);
     __syncthreads();
 
     for (int E = ks; E <= ke; E += 2) {
         // next step's loads in flight: planes E+2, E+3, layers E+1, E+2, f of planes E+2, E+1
         const bool more = E + 2 <= ke;
-        double q0, q1, q2, q3, s0, s1, s2, s3, nfe, nfo, nfe1, nfo1;
+        T q0, q1, q2, q3, s0, s1, s2, s3, nfe, nfo, nfe1, nfo1;
         ld_phi(E + 2, q0, q1);
         ld_phi(E + 3, q2, q3);
         ld_sig(E + 1, s0, s1);
@@ -464,7 +474,7 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
         const int sm = nod_m3(E - 1), sq = nod_m3(E), smm = nod_m3(E - 2);
         const bool even_ok = plane_ok(E);
         // A: colour 0 of plane E (ring 3)
-        double ve = 0.0, vo = 0.0;
+        T ve = T(0), vo = T(0);
         if (st0 && even_ok) {
             ve = update(wx, je, pm, pc, pp, sm, sq, fe0);
             sp[pc][je][wx] = ve;
@@ -484,7 +494,7 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevel 
         __syncthreads();
         if (E > ks) {
             // C: colour 2 of plane E-1 (ring 1)
-            double ve2 = 0.0, vo2 = 0.0;
+            T ve2 = T(0), vo2 = T(0);
             if (st2) {
                 ve2 = update(wx, je, pmm, pm, pc, smm, sm, fe1);
                 sp[pm][je][wx] = ve2;
@@ -525,14 +535,15 @@ constexpr int kRTX = 32, kRTY = 8, kRTZ = 8;
 constexpr int kRWX = kRTX + 2, kRWY = kRTY + 2, kRWZ = kRTZ + 2;      // node window
 constexpr int kRCX = kRTX + 1, kRCY = kRTY + 1, kRCZ = kRTZ + 1;      // cell window
 
-inline int nod_resid_tiles(const NodLevel& L) {
+template <typename T>
+inline int nod_resid_tiles(const NodLevelT<T>& L) {
     return ((L.Nx + kRTX - 1) / kRTX) * ((L.Ny + kRTY - 1) / kRTY) * ((L.Nz + kRTZ - 1) / kRTZ);
 }
 
-template <bool kStore, bool kNorm>
-__global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevel L, double* __restrict__ partials) {
-    __shared__ double sphi[kRWZ][kRWY][kRWX];
-    __shared__ double ssig[kRCZ][kRCY][kRCX];
+template <typename T, bool kStore, bool kNorm>
+__global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevelT<T> L, double* __restrict__ partials) {
+    __shared__ __align__(16) T sphi[kRWZ][kRWY][kRWX];
+    __shared__ T ssig[kRCZ][kRCY][kRCX];
     const int ntx = (L.Nx + kRTX - 1) / kRTX, nty = (L.Ny + kRTY - 1) / kRTY;
     const int b = blockIdx.x;
     const int I0 = (b % ntx) * kRTX, J0 = ((b / ntx) % nty) * kRTY, K0 = (b / (ntx * nty)) * kRTZ;
@@ -556,7 +567,7 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevel L, doub
     // they are all in flight together
     constexpr int kNT = kRTX * kRTY;
     constexpr int kPN = (kRWX * kRWY * kRWZ + kNT - 1) / kNT, kPC = (kRCX * kRCY * kRCZ + kNT - 1) / kNT;
-    double vp[kPN], vs[kPC];
+    T vp[kPN], vs[kPC];
 #pragma unroll
     for (int q = 0; q < kPN; ++q) {
         const int e = min(tid + q * kNT, kRWX * kRWY * kRWZ - 1);
@@ -565,7 +576,7 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevel L, doub
         const int I = at(I0 - 1 + x, L.Nx, L.px, ok), J = at(J0 - 1 + y, L.Ny, L.py, ok);
         const int K = at(K0 - 1 + z, L.Nz, L.pz, ok);
         vp[q] = L.phi[(size_t)K * NxNy + (size_t)J * L.Nx + I];
-        if (!ok) vp[q] = 0.0;
+        if (!ok) vp[q] = T(0);
     }
 #pragma unroll
     for (int q = 0; q < kPC; ++q) {
@@ -575,7 +586,7 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevel L, doub
         const int i = at(I0 - 1 + x, L.nx, L.px, ok), j = at(J0 - 1 + y, L.ny, L.py, ok);
         const int k = at(K0 - 1 + z, L.nz, L.pz, ok);
         vs[q] = L.sig[(size_t)k * nxny + (size_t)j * L.nx + i];
-        if (!ok) vs[q] = 0.0;
+        if (!ok) vs[q] = T(0);
     }
 #pragma unroll
     for (int q = 0; q < kPN; ++q) {
@@ -590,15 +601,15 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevel L, doub
     __syncthreads();
     const int tx = tid % kRTX, ty = tid / kRTX;
     const int I = I0 + tx, J = J0 + ty;
-    const double ih = 12.0 * L.h * L.h;
+    const T ih = (T)(12.0 * L.h * L.h);
     double s2 = 0.0, mx = 0.0, nonfin = 0.0;
     if (I < L.Nx && J < L.Ny) {
         for (int tz = 0; tz < kRTZ; ++tz) {
             const int K = K0 + tz;
             if (K >= L.Nz) break;
             const int x = tx + 1, y = ty + 1, z = tz + 1;        // the node in the windows
-            const double pn = sphi[z][y][x];
-            double sum = 0.0;
+            const T pn = sphi[z][y][x];
+            T sum = T(0);
 #pragma unroll
             for (int sz = 0; sz < 2; ++sz) {
                 const int zo = sz ? z + 1 : z - 1;
@@ -609,30 +620,31 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevel L, doub
                     for (int sx = 0; sx < 2; ++sx) {
                         const int xo = sx ? x + 1 : x - 1;
                         // the cell on side (sx, sy, sz) of the node: cell window index node - 1 + s
-                        const double sig = ssig[z - 1 + sz][y - 1 + sy][x - 1 + sx];
-                        double acc = 0.0;
+                        const T sig = ssig[z - 1 + sz][y - 1 + sy][x - 1 + sx];
+                        T acc = T(0);
                         acc += sphi[z][yo][xo];
                         acc += sphi[zo][y][xo];
                         acc += sphi[zo][yo][x];
                         acc += sphi[zo][yo][xo];
-                        sum += sig * (acc - 4.0 * pn);
+                        sum += sig * (acc - T(4) * pn);
                     }
                 }
             }
             const size_t n = (size_t)K * NxNy + (size_t)J * L.Nx + I;
-            const double r = L.f[n] - sum / ih;
+            const T r = L.f[n] - sum / ih;
             if (kStore) L.r[n] = r;
             if (kNorm) {
-                if (!isfinite(r)) nonfin += 1.0;
-                s2 += r * r;
-                mx = fmax(mx, fabs(r));
+                const double rd = (double)r;
+                if (!isfinite(rd)) nonfin += 1.0;
+                s2 += rd * rd;
+                mx = fmax(mx, fabs(rd));
             }
         }
     }
     if (kNorm) {
         // fixed-order tree over the workgroup, in the (now free) phi window
         static_assert(sizeof(sphi) >= 3 * kRTX * kRTY * sizeof(double), "reduction buffer");
-        double* red = &sphi[0][0][0];
+        double* red = reinterpret_cast<double*>(&sphi[0][0][0]);
         constexpr int nt = kRTX * kRTY;
         __syncthreads();
         red[tid] = s2;
@@ -658,49 +670,51 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevel L, doub
 }
 
 // coarse f = 1/8 sum_d w(d) r_{2C+d} (existing fine nodes), coarse phi = 0.
-__global__ void k_nod_restrict(NodLevel F, NodLevel C) {
+template <typename T>
+__global__ void k_nod_restrict(NodLevelT<T> F, NodLevelT<T> C) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;
     const int K = blockIdx.z * blockDim.z + threadIdx.z;
     if (I >= C.Nx || J >= C.Ny || K >= C.Nz) return;
     const int X[3] = {2 * I, 2 * J, 2 * K};
     const int Nn[3] = {F.Nx, F.Ny, F.Nz}, per[3] = {F.px, F.py, F.pz};
-    double s = 0.0;
+    T s = T(0);
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 const int D[3] = {dx, dy, dz};
                 int m[3];
                 bool ok = true;
-                double w = 1.0;
+                T w = T(1);
                 for (int d = 0; d < 3; ++d) {
                     m[d] = nod_node(X[d], D[d], Nn[d], per[d]);
                     if (m[d] < 0) ok = false;
-                    if (D[d] != 0) w *= 0.5;
+                    if (D[d] != 0) w *= T(0.5);
                 }
                 if (ok) s += w * F.r[nidx(F, m[0], m[1], m[2])];
             }
     const size_t c = nidx(C, I, J, K);
-    C.f[c] = 0.125 * s;
-    C.phi[c] = 0.0;
+    C.f[c] = T(0.125) * s;
+    C.phi[c] = T(0);
 }
 
 // fine phi += trilinear interpolation of the coarse phi.
-__global__ void k_nod_prolong(NodLevel F, NodLevel C) {
+template <typename T>
+__global__ void k_nod_prolong(NodLevelT<T> F, NodLevelT<T> C) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;
     const int K = blockIdx.z * blockDim.z + threadIdx.z;
     if (I >= F.Nx || J >= F.Ny || K >= F.Nz) return;
     const int X[3] = {I, J, K};
     const int Nc[3] = {C.Nx, C.Ny, C.Nz}, per[3] = {C.px, C.py, C.pz};
-    double v = 0.0;
+    T v = T(0);
     for (int bz = 0; bz < 2; ++bz)
         for (int by = 0; by < 2; ++by)
             for (int bx = 0; bx < 2; ++bx) {
                 const int B[3] = {bx, by, bz};
                 int m[3];
                 bool ok = true;
-                double w = 1.0;
+                T w = T(1);
                 for (int d = 0; d < 3; ++d) {
                     if ((X[d] & 1) == 0) {
                         if (B[d]) {
@@ -711,7 +725,7 @@ __global__ void k_nod_prolong(NodLevel F, NodLevel C) {
                     } else {
                         m[d] = B[d] ? (X[d] + 1) >> 1 : (X[d] - 1) >> 1;
                         if (per[d] && m[d] >= Nc[d]) m[d] -= Nc[d];
-                        w *= 0.5;
+                        w *= T(0.5);
                     }
                 }
                 if (ok) v += w * C.phi[nidx(C, m[0], m[1], m[2])];
@@ -815,6 +829,13 @@ __global__ void k_nod_correct(NodLevel L, const double* __restrict__ rho, const 
     w[c] = w[c] - (g2 / h4) / rho[c];
 }
 
+// phi += e / s for the FP32 correction e of a mixed-precision iteration (s a
+// power of two: the division is exact).
+__global__ void k_nod_add_corr(size_t n, const float* __restrict__ e, double inv_s, double* __restrict__ phi) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        phi[i] = phi[i] + (double)e[i] * inv_s;
+}
+
 __global__ void k_nod_shift_out(size_t n, const double* __restrict__ phi, const double* __restrict__ phi_sum,
                                 double* __restrict__ out) {
     const double m = phi_sum[0] / (double)n;
@@ -853,6 +874,10 @@ struct nodal_hierarchy {
     mg_params p{};
     int nlev = 0;
     NodLevel lev[kMaxLevels];
+    // mixed precision: FP32 mirrors of every level (sigma, phi, f, r, phi2),
+    // the inner V-cycle's arrays
+    bool mixed = false;
+    NodLevelT<float> lev32[kMaxLevels];
     void* ws = nullptr;
     double* minv = nullptr;
     double* partials = nullptr;
@@ -894,8 +919,9 @@ int nod_count_levels(const mg_params* p) {
 size_t nod_partial_rows(const NodLevel& L0) { return std::max<size_t>(2048, (size_t)nod_resid_tiles(L0)); }
 
 // Level shapes of a hierarchy of nl levels for p (into lev), and the device
-// bytes it needs: per level sigma on cells and phi, f, r, phi2 on nodes; the
-// coarsest level's dense inverse, the partial rows and the scalar block.
+// bytes it needs: per level sigma on cells and phi, f, r, phi2 on nodes (in
+// mixed precision also FP32 copies of all five); the coarsest level's dense
+// inverse, the partial rows and the scalar block.
 size_t nod_layout(const mg_params* p, int nl, NodLevel* lev) {
     size_t bytes = 0;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -912,6 +938,7 @@ size_t nod_layout(const mg_params* p, int nl, NodLevel* lev) {
         L.Nz = L.nz + (L.pz ? 0 : 1);
         L.h = p->dx * (double)(1 << l);
         bytes += al(L.cells() * 8) + 4 * al(L.nodes() * 8);
+        if (p->precision == MG_MIXED) bytes += al(L.cells() * 4) + 4 * al(L.nodes() * 4);
     }
     const size_t nc = lev[nl - 1].nodes();
     bytes += al(nc * nc * 8) + al(nod_partial_rows(lev[0]) * kReduceWidth * 8) + al(64 * 8);
@@ -935,19 +962,20 @@ int nod_reduce(nodal_hierarchy* H, int nparts, int slot, hipStream_t st) {
 // The fused sweep takes levels whose colouring is consistent across periodic
 // wraps (even node counts there), an even number of node planes to march
 // (the top plane of a walled z is even) and at least one 32 x 8 tile.
-bool nod_sweep_fits(const NodLevel& L) {
+template <typename T>
+bool nod_sweep_fits(const NodLevelT<T>& L) {
     if (L.Nx < 32 || L.Ny < 16) return false;
     if (L.py && L.Ny % 2 != 0) return false;
     if (L.pz ? (L.Nz % 2 != 0) : (L.nz % 2 != 0)) return false;
     return (L.pz ? L.Nz : L.Nz - 1) >= 2;
 }
 
-template <int TX, int TY>
-hipError_t launch_nod_sweep_t(const NodLevel& L, double* out, int tz, hipStream_t st) {
+template <typename T, int TX, int TY>
+hipError_t launch_nod_sweep_t(const NodLevelT<T>& L, T* out, int tz, hipStream_t st) {
     const int etop = L.pz ? L.Nz : L.Nz - 1;
     const int ntx = (L.Nx + TX - 1) / TX, nty = (L.Ny + TY - 1) / TY, nch = (etop + tz - 1) / tz;
-    hipLaunchKernelGGL((k_nod_sweep<TX, TY>), dim3(ntx * nty * nch), dim3((TX + 8) * (TY + 8) / 2), 0, st, L, out,
-                       tz, ntx, nty, etop);
+    hipLaunchKernelGGL((k_nod_sweep<T, TX, TY>), dim3(ntx * nty * nch), dim3((TX + 8) * (TY + 8) / 2), 0, st, L,
+                       out, tz, ntx, nty, etop);
     return hipGetLastError();
 }
 
@@ -960,18 +988,28 @@ constexpr NodSweepCfg kNodSweepCfgs[kNumNodSweepCfg] = {{64, 8, 32}, {32, 8, 32}
                                                        {64, 8, 64}, {32, 8, 16}, {32, 16, 64}, {64, 8, 16}};
 std::atomic<int> g_nod_cfg{-1};                  // forced configuration (-1: the default below)
 
-hipError_t launch_nod_sweep(const NodLevel& L, double* out, int cfg, hipStream_t st) {
+template <typename T>
+hipError_t launch_nod_sweep(const NodLevelT<T>& L, T* out, int cfg, hipStream_t st) {
     const NodSweepCfg& c = kNodSweepCfgs[cfg];
-    if (c.tx == 64 && c.ty == 8) return launch_nod_sweep_t<64, 8>(L, out, c.tz, st);
-    if (c.tx == 32 && c.ty == 8) return launch_nod_sweep_t<32, 8>(L, out, c.tz, st);
-    if (c.tx == 32 && c.ty == 16) return launch_nod_sweep_t<32, 16>(L, out, c.tz, st);
-    return launch_nod_sweep_t<64, 16>(L, out, c.tz, st);
+    if (c.tx == 64 && c.ty == 8) return launch_nod_sweep_t<T, 64, 8>(L, out, c.tz, st);
+    if (c.tx == 32 && c.ty == 8) return launch_nod_sweep_t<T, 32, 8>(L, out, c.tz, st);
+    if (c.tx == 32 && c.ty == 16) return launch_nod_sweep_t<T, 32, 16>(L, out, c.tz, st);
+    return launch_nod_sweep_t<T, 64, 16>(L, out, c.tz, st);
 }
+
+// The levels a V-cycle in T runs on: the FP64 hierarchy, or its FP32 mirrors.
+template <typename T>
+NodLevelT<T>* nod_levels(nodal_hierarchy* H);
+template <>
+NodLevelT<double>* nod_levels<double>(nodal_hierarchy* H) { return H->lev; }
+template <>
+NodLevelT<float>* nod_levels<float>(nodal_hierarchy* H) { return H->lev32; }
 
 // Sweeps on level l: the fused out-of-place sweep where it fits (the level's
 // two phi buffers swap), else one in-place launch per colour.
+template <typename T = double>
 int nod_smooth(nodal_hierarchy* H, int l, int nsweeps, hipStream_t st) {
-    NodLevel& L = H->lev[l];
+    NodLevelT<T>& L = nod_levels<T>(H)[l];
     // default: the fused sweep on levels of 4M nodes or more, 32 x 16 tiles
     // of 32-plane chunks (measured on MI355X: 215 us per 256^3 sweep against
     // 346 us for four colour launches; on a 128^3 level the colour launches
@@ -990,46 +1028,57 @@ int nod_smooth(nodal_hierarchy* H, int l, int nsweeps, hipStream_t st) {
     const dim3 block(64, 2, 2);
     const dim3 grid = grid3(L.Nx, (L.Ny + 1) / 2, (L.Nz + 1) / 2, block);
     for (int s = 0; s < nsweeps; ++s)
-        for (int col = 0; col < 4; ++col) hipLaunchKernelGGL(k_nod_gs, grid, block, 0, st, L, col);
+        for (int col = 0; col < 4; ++col) hipLaunchKernelGGL(k_nod_gs<T>, grid, block, 0, st, L, col);
     NHIP(hipGetLastError());
     return MG_OK;
 }
 
+template <typename T = double>
 int nod_resid_restrict(nodal_hierarchy* H, int l, hipStream_t st) {
-    const NodLevel& F = H->lev[l];
-    const NodLevel& C = H->lev[l + 1];
-    hipLaunchKernelGGL((k_nod_resid_tile<true, false>), dim3(nod_resid_tiles(F)), dim3(kRTX * kRTY), 0, st, F,
+    const NodLevelT<T>& F = nod_levels<T>(H)[l];
+    const NodLevelT<T>& C = nod_levels<T>(H)[l + 1];
+    hipLaunchKernelGGL((k_nod_resid_tile<T, true, false>), dim3(nod_resid_tiles(F)), dim3(kRTX * kRTY), 0, st, F,
                        (double*)nullptr);
     const dim3 block(32, 4, 2);
-    hipLaunchKernelGGL(k_nod_restrict, grid3(C.Nx, C.Ny, C.Nz, block), block, 0, st, F, C);
+    hipLaunchKernelGGL(k_nod_restrict<T>, grid3(C.Nx, C.Ny, C.Nz, block), block, 0, st, F, C);
     NHIP(hipGetLastError());
     return MG_OK;
 }
 
+template <typename T = double>
 int nod_prolong(nodal_hierarchy* H, int l, hipStream_t st) {
-    const NodLevel& F = H->lev[l];
-    const NodLevel& C = H->lev[l + 1];
+    const NodLevelT<T>& F = nod_levels<T>(H)[l];
+    const NodLevelT<T>& C = nod_levels<T>(H)[l + 1];
     const dim3 block(32, 4, 2);
-    hipLaunchKernelGGL(k_nod_prolong, grid3(F.Nx, F.Ny, F.Nz, block), block, 0, st, F, C);
+    hipLaunchKernelGGL(k_nod_prolong<T>, grid3(F.Nx, F.Ny, F.Nz, block), block, 0, st, F, C);
     NHIP(hipGetLastError());
     return MG_OK;
 }
 
+hipError_t nod_coarse_solve(int n, const double* minv, const double* f, double* phi, hipStream_t st) {
+    return launch_coarse_solve(n, minv, f, phi, st, 1);
+}
+hipError_t nod_coarse_solve(int n, const double* minv, const float* f, float* phi, hipStream_t st) {
+    return launch_coarse_solve_f32(n, minv, f, phi, st, 1);
+}
+
+// V-cycle from level l in T (the coarsest solve applies the FP64 inverse).
+template <typename T = double>
 int nod_vcycle(nodal_hierarchy* H, int l, hipStream_t st) {
     if (l == H->nlev - 1) {
-        const NodLevel& L = H->lev[l];
-        NHIP(launch_coarse_solve((int)L.nodes(), H->minv, L.f, L.phi, st, 1));
+        const NodLevelT<T>& L = nod_levels<T>(H)[l];
+        NHIP(nod_coarse_solve((int)L.nodes(), H->minv, L.f, L.phi, st));
         return MG_OK;
     }
-    int rc = nod_smooth(H, l, H->p.pre_sweeps, st);
+    int rc = nod_smooth<T>(H, l, H->p.pre_sweeps, st);
     if (rc) return rc;
-    rc = nod_resid_restrict(H, l, st);
+    rc = nod_resid_restrict<T>(H, l, st);
     if (rc) return rc;
-    rc = nod_vcycle(H, l + 1, st);
+    rc = nod_vcycle<T>(H, l + 1, st);
     if (rc) return rc;
-    rc = nod_prolong(H, l, st);
+    rc = nod_prolong<T>(H, l, st);
     if (rc) return rc;
-    return nod_smooth(H, l, H->p.post_sweeps, st);
+    return nod_smooth<T>(H, l, H->p.post_sweeps, st);
 }
 
 // sigma on every level from rho and beta0, coarsest inverse; partial rows
@@ -1060,6 +1109,61 @@ int nod_coefficients(nodal_hierarchy* H, const double* rho, const double* b0c, c
         return MG_ERR_INVALID_ARG;
     }
     H->coeffs_valid = true;
+    return MG_OK;
+}
+
+// Mixed-precision solve (iterative refinement with the multigrid of Sec. 3
+// as its inner solver): each iteration runs one FP32 V-cycle from zero on the
+// FP64 residual scaled by the power of two nearest 1/rms(r), adds the FP32
+// correction divided by that power of two (exact) to the FP64 phi, and
+// recomputes r = f - L phi and its norm in FP64; the stop test is the FP64
+// solve's.  Returns MG_OK or a launch error; *status is the solve's.
+int nod_solve_mixed(nodal_hierarchy* H, double fnorm, mg_stats* S_, int* status_out, int* cycles_out,
+                    double* rel_out, hipStream_t st) {
+    NodLevel& L0 = H->lev[0];
+    NodLevelT<float>& M0 = H->lev32[0];
+    const size_t NN = L0.nodes();
+    for (int l = 0; l < H->nlev; ++l)
+        NHIP(launch_coeff_to_f32(H->lev[l].sig, H->lev32[l].sig, H->lev[l].cells(), st));
+    double s = residual_scale(fnorm, NN);
+    NHIP(launch_scale_to_f32(L0.f, M0.f, NN, s, st));        // the residual of phi = 0 is f
+    const int nt = nod_resid_tiles(L0);
+    int status = MG_ERR_NOT_CONVERGED, cycles = 0;
+    double rel = 1.0;
+    while (cycles < H->p.max_cycles) {
+        NHIP(launch_fill<float>(M0.phi, NN, 0.0f, st));
+        int rc = nod_vcycle<float>(H, 0, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_nod_add_corr, dim3(nod_partial_blocks(NN)), dim3(kNodBlock), 0, st, NN, M0.phi, 1.0 / s,
+                           L0.phi);
+        hipLaunchKernelGGL((k_nod_resid_tile<double, true, true>), dim3(nt), dim3(kRTX * kRTY), 0, st, L0,
+                           H->partials);
+        NHIP(hipGetLastError());
+        rc = nod_reduce(H, nt, kSlotRes, st);
+        if (rc) return rc;
+        ++cycles;
+        const double* r = H->host + kSlotRes * kReduceWidth;
+        rel = std::sqrt(r[0]) / fnorm;
+        if (cycles < MG_HIST_MAX) {
+            S_->resid_hist[cycles] = rel;
+            S_->hist_len = cycles + 1;
+        }
+        if (r[3] > 0.0 || !std::isfinite(rel)) {
+            set_error("non-finite residual during the solve");
+            status = MG_ERR_NONFINITE;
+            break;
+        }
+        if (rel <= H->p.rtol) {
+            status = MG_OK;
+            break;
+        }
+        if (cycles >= H->p.max_cycles) break;
+        s = residual_scale(std::sqrt(r[0]), NN);
+        NHIP(launch_scale_to_f32(L0.r, M0.f, NN, s, st));
+    }
+    *status_out = status;
+    *cycles_out = cycles;
+    *rel_out = rel;
     return MG_OK;
 }
 
@@ -1106,14 +1210,17 @@ int nod_project(nodal_hierarchy* H, const double* rho, const double* b0c, const 
     // every cycle ends with a host synchronisation: the loop's wall time is
     // the device time of the cycles
     const auto t_s0 = std::chrono::steady_clock::now();
-    if (fnorm > 0.0 && H->p.rtol < 1.0) {
+    if (fnorm > 0.0 && H->p.rtol < 1.0 && H->mixed) {
+        rc = nod_solve_mixed(H, fnorm, S_, &status, &cycles, &rel, st);
+        if (rc) return S_->status = rc;
+    } else if (fnorm > 0.0 && H->p.rtol < 1.0) {
         status = MG_ERR_NOT_CONVERGED;
         bool on_graph = false;
         auto cycle = [&](hipStream_t s) -> int {
             int r2 = nod_vcycle(H, 0, s);
             if (r2) return r2;
-            hipLaunchKernelGGL((k_nod_resid_tile<false, true>), dim3(nod_resid_tiles(L0)), dim3(kRTX * kRTY), 0, s,
-                               L0, H->partials);
+            hipLaunchKernelGGL((k_nod_resid_tile<double, false, true>), dim3(nod_resid_tiles(L0)),
+                               dim3(kRTX * kRTY), 0, s, L0, H->partials);
             NHIP(hipGetLastError());
             NHIP(launch_reduce(H->partials, nod_resid_tiles(L0), H->scal + kSlotRes * kReduceWidth, s));
             NHIP(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
@@ -1270,8 +1377,8 @@ int nodal_setup(const mg_params* p, nodal_handle* out) {
             set_error("the nodal projection takes periodic or wall boundaries");
             return MG_ERR_INVALID_ARG;
         }
-    if (p->precision != MG_FP64) {
-        set_error("the nodal projection runs in FP64");
+    if (p->precision != MG_FP64 && p->precision != MG_MIXED) {
+        set_error("unknown precision");
         return MG_ERR_INVALID_ARG;
     }
     const int nl = nod_count_levels(p);
@@ -1306,6 +1413,23 @@ int nodal_setup(const mg_params* p, nodal_handle* out) {
         L.f = take(L.nodes() * 8);
         L.r = take(L.nodes() * 8);
         L.phi2 = take(L.nodes() * 8);
+    }
+    H->mixed = p->precision == MG_MIXED;
+    if (H->mixed) {
+        auto take32 = [&](size_t n) { return reinterpret_cast<float*>(take(n * 4)); };
+        for (int l = 0; l < nl; ++l) {
+            const NodLevel& L = H->lev[l];
+            NodLevelT<float>& M = H->lev32[l];
+            M.nx = L.nx; M.ny = L.ny; M.nz = L.nz;
+            M.Nx = L.Nx; M.Ny = L.Ny; M.Nz = L.Nz;
+            M.px = L.px; M.py = L.py; M.pz = L.pz;
+            M.h = L.h;
+            M.sig = take32(L.cells());
+            M.phi = take32(L.nodes());
+            M.f = take32(L.nodes());
+            M.r = take32(L.nodes());
+            M.phi2 = take32(L.nodes());
+        }
     }
     H->minv = take(nc * nc * 8);
     H->partials = take(prow * kReduceWidth * 8);

@@ -201,12 +201,12 @@ def solo_boxes(mp, prob, box):
     return st, {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
 
 
-def nodal_params(mp, prob):
-    return mp.make_params(prob.n, prob.dx, prob.periodic, rtol=prob.rtol)
+def nodal_params(mp, prob, precision="fp64"):
+    return mp.make_params(prob.n, prob.dx, prob.periodic, rtol=prob.rtol, precision=precision)
 
 
-def solo_nodal(mp, prob):
-    H = mp.NodalHierarchy(nodal_params(mp, prob))
+def solo_nodal(mp, prob, precision="fp64"):
+    H = mp.NodalHierarchy(nodal_params(mp, prob, precision))
     d = mp.nodal_to_device(prob)
     st = H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi)
     torch.cuda.synchronize()
@@ -331,3 +331,23 @@ def test_server_of_mixed_kinds_matches_solo_and_oracle(mp):
         assert same(out, out0), i
     check_mac_oracle(boxed[1][0], got[2][1])
     check_nodal_oracle(nodal[1], got[5][1])
+
+
+def test_batch_nodal_mixed_precision_matches_solo_and_oracle(mp):
+    """Nodal problems in FP64 and in mixed precision in one batch: each equals
+    its solo solve bit for bit and meets the oracle bar."""
+    probs = [I.make_nodal_problem((32, 32, 32), seed=311, periodic=(True, True, False)),
+             I.make_nodal_problem((24, 16, 32), seed=312, periodic=(False, False, False)),
+             I.make_nodal_problem((32, 32, 32), seed=313, periodic=(True, False, True))]
+    precs = ["mixed", "mixed", "fp64"]
+    refs = [solo_nodal(mp, p, pr) for p, pr in zip(probs, precs)]
+    devs = [mp.nodal_to_device(p) for p in probs]
+    code, stats = mp.project_batch_problems([mp.nodal_problem_struct(nodal_params(mp, p, pr), d)
+                                             for p, pr, d in zip(probs, precs, devs)])
+    torch.cuda.synchronize()
+    assert code == 0, stats
+    for p, (st0, out0), s, d in zip(probs, refs, stats, devs):
+        out = nodal_out(d)
+        assert s["status_name"] == "OK" and s["cycles"] == st0["cycles"]
+        assert same(out, out0)
+        check_nodal_oracle(p, out)

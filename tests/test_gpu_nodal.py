@@ -3,6 +3,9 @@ oracle: phi within 1e-9 (relative L2, zero mean) of the oracle's exact
 discrete solution with the GPU residual <= rtol, the correction exact
 (<= 1e-12) given the GPU's phi, U within max(1e-9, 3 x the oracle's own
 algorithm-mode deviation) of the exact projection, single steps <= 1e-13.
+Mixed precision (FP32 V-cycles inside FP64 iterative refinement) is held to
+the same oracle bar, its residual measured in FP64, and to the FP64 GPU
+solve's phi within 1e-9.
 """
 import numpy as np
 import pytest
@@ -18,8 +21,9 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-def run_gpu(mp, prob, rtol=None, allow=(0,)):
-    params = mp.make_params(prob.n, prob.dx, prob.periodic, rtol=prob.rtol if rtol is None else rtol)
+def run_gpu(mp, prob, rtol=None, allow=(0,), precision="fp64"):
+    params = mp.make_params(prob.n, prob.dx, prob.periodic, rtol=prob.rtol if rtol is None else rtol,
+                            precision=precision)
     H = mp.NodalHierarchy(params)
     d = mp.nodal_to_device(prob)
     st = H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi, allow=allow)
@@ -237,3 +241,57 @@ def test_nodal_graph_replays_equal_eager(mp):
     for c, *a in outs[1][1:]:
         for x, y in zip(a, outs[1][0][1:]):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("n,per,seed,force", [
+    ((16, 16, 16), (True, True, False), 41, -1),
+    ((24, 16, 32), (False, False, False), 42, -1),
+    ((32, 32, 32), (True, False, True), 43, -1),
+    ((64, 64, 64), (True, True, False), 44, -1),
+    ((6, 10, 14), (True, True, False), 45, -1),        # two levels
+    ((4, 4, 4), (False, False, False), 46, -1),        # direct solve only
+    ((128, 96, 96), (True, True, False), 47, 2),       # the fused FP32 sweep on the levels it fits
+    ((96, 112, 128), (False, False, False), 48, 2),
+])
+def test_nodal_mixed_matches_oracle(mp, n, per, seed, force):
+    prob = I.make_nodal_problem(n, seed=seed, periodic=per)
+    if force >= 0:
+        mp.nodal_tune_sweep(force)
+    try:
+        st, out = run_gpu(mp, prob, precision="mixed")
+    finally:
+        mp.nodal_tune_sweep(-1)
+    check(prob, st, out)
+    st64, out64 = run_gpu(mp, prob)
+    assert st["cycles"] <= st64["cycles"] + 2
+    for k in ("phi", "u", "v", "w"):
+        assert rel(out[k], out64[k]) <= 1e-9, k
+
+
+@pytest.mark.parametrize("n,per,seed", [((32, 32, 32), (True, True, False), 51), ((24, 16, 32), (False, False, False), 52)])
+def test_nodal_mixed_strict_at_rtol_1e12(mp, n, per, seed):
+    """Mixed precision solved to rtol 1e-12: phi and U within 1e-9 of the
+    oracle's exact discrete solution outright."""
+    prob = I.make_nodal_problem(n, seed=seed, periodic=per, rtol=1e-12)
+    st, out = run_gpu(mp, prob, precision="mixed")
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-12
+    ref = O.nodal_project(prob, mode="definition")
+    assert ref["status"] == 0
+    for k in ("phi", "u", "v", "w"):
+        assert rel(out[k], ref[k]) <= 1e-9, (k, rel(out[k], ref[k]))
+
+
+def test_nodal_mixed_fused_size(mp):
+    """A 192 x 192 x 128 steep box (4.8 M nodes: the fused FP32 sweep on the
+    finest level by default) in mixed precision: converged in FP64 terms,
+    residual by the oracle's operator, phi within 1e-9 of the FP64 GPU solve."""
+    prob = I.make_nodal_problem((192, 192, 128), H=0.1, seed=7, periodic=(True, True, False))
+    st, out = run_gpu(mp, prob, precision="mixed")
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10
+    st64, out64 = run_gpu(mp, prob)
+    assert rel(out["phi"], out64["phi"]) <= 1e-9
+    sig = O.nodal_sigma(prob.rho, prob.beta0_cc)
+    f = O.nodal_rhs(prob.n, prob.periodic, prob.dx, prob.beta0_cc, prob.uc, prob.vc, prob.wc, prob.S)
+    f -= f.mean()
+    r = f - O.nodal_apply(prob.n, prob.periodic, prob.dx, sig, out["phi"])
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(f)
