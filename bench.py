@@ -448,7 +448,7 @@ def star_leg(args, torch, macproj, inputs, dev):
 
 def nodal_leg(args, torch, macproj, inputs, dev):
     """The nodal (cell-velocity) projection of the same box size: phi on the
-    nodes, cell-centred velocities, FP64."""
+    nodes, cell-centred velocities, FP64 and mixed precision."""
     prob = inputs.make_nodal_problem(args.n, H=0.1, rho_noise=0.01, seed=7)
     d = macproj.nodal_to_device(prob, dev)
     u0, v0, w0 = d.uc.clone(), d.vc.clone(), d.wc.clone()
@@ -476,11 +476,33 @@ def nodal_leg(args, torch, macproj, inputs, dev):
     torch.cuda.synchronize()
     sweep_ms = e0.elapsed_time(e1) / args.kernel_reps
     H.close()
+    phi64 = d.phi.clone()
+    # the same problem in mixed precision (FP32 V-cycles, FP64 refinement)
+    Hm = macproj.NodalHierarchy(macproj.make_params(prob.n, prob.dx, prob.periodic, precision="mixed"))
+    log(f"nodal projection, mixed precision: {args.nodal_steps} steps")
+
+    def step_m():
+        d.uc.copy_(u0); d.vc.copy_(v0); d.wc.copy_(w0)
+        return Hm.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi)
+
+    step_m()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.nodal_steps):
+        stm = step_m()
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    assert stm["status_name"] == "OK" and stm["rel_resid"] <= 1e-10, stm
+    diff = float(torch.linalg.vector_norm(d.phi - phi64) / torch.linalg.vector_norm(phi64))
+    Hm.close()
     nodes = (args.n ** 2) * (args.n + 1)
     return {"value": args.nodal_steps / tn, "unit": "solves/s", "ms_per_step": tn * 1e3 / args.nodal_steps,
             "cycles": st["cycles"], "rel_resid": st["rel_resid"],
             "fine_sweep_ms": sweep_ms,
             "fine_sweep_GBs_at_24B_per_node": 24.0 * nodes / (sweep_ms * 1e-3) / 1e9,
+            "mixed": {"value": args.nodal_steps / tm, "unit": "solves/s", "ms_per_step": tm * 1e3 / args.nodal_steps,
+                      "refinement_steps": stm["cycles"], "rel_resid": stm["rel_resid"],
+                      "phi_rel_diff_vs_fp64_gpu": diff},
             "workload": f"{args.n}^3 cells ({nodes} nodes), beta0 = exp(-z/0.1), periodic x,y, walls z, rtol 1e-10"}
 
 

@@ -455,11 +455,13 @@ int mg_set_bottom(mg_handle h, int32_t enable);
  * result agrees with the single-box solve to rounding (the same per-cell
  * arithmetic; the residual norm and the restriction may be summed in
  * another order).  box == NULL or {0, 0, 0} returns to a single box.
- * Needs FP64 precision, periodic or wall sides and two or more levels
- * (MG_ERR_INVALID_ARG otherwise).  The boxes' arrays are allocated here
+ * Needs periodic or wall sides and two or more levels; in mixed precision
+ * (FP32 box sweeps, FP32 residual + restriction and an FP64 refinement over
+ * the boxes, halos exchanged after each) also every box taking the fused
+ * sweep and at most 2048 box tiles (MG_ERR_INVALID_ARG otherwise).  The boxes' arrays are allocated here
  * (device memory, freed by mg_destroy or the next mg_set_boxes), 7 x 8
- * bytes per cell of the ghosted boxes, each sized for a full box; MG_ERR_HIP
- * if that fails.  Batches and the server take the box size from
+ * bytes per cell of the ghosted boxes (7 x 4 more in mixed precision), each
+ * sized for a full box; MG_ERR_HIP if that fails.  Batches and the server take the box size from
  * mg_problem.box. */
 int mg_set_boxes(mg_handle h, const int32_t box[3]);
 

@@ -47,6 +47,16 @@ struct BoxSet {
     double* b0c;
     double* b0e;
     int rho_on;       // this solve's coefficients come from rho (plane-parallel beta0)
+    // mixed precision (null otherwise): FP32 arrays in the same layout, the
+    // inner V-cycle's finest level: phi (two buffers), f (the scaled FP64
+    // residual), rho and the face coefficients
+    float* phi32;
+    float* phi2_32;
+    float* f32;
+    float* rho32;
+    float* cx32;
+    float* cy32;
+    float* cz32;
 };
 
 size_t boxset_cells(const BoxSet& B);
@@ -83,5 +93,22 @@ hipError_t launch_box_prolong(const BoxSet& B, const double* phic, hipStream_t s
 hipError_t launch_box_resid_norm(const BoxSet& B, double h, double* partials, int* nparts, hipStream_t st);
 // Global phi from the box interiors.
 hipError_t launch_box_gather(const BoxSet& B, double* phi, hipStream_t st);
+
+// ---- mixed precision (fused boxes only) --------------------------------
+// f32 = s f over every ghosted cell, and the FP32 copy of this solve's
+// coefficient source (rho, or the three face arrays).
+hipError_t launch_box_to_f32(const BoxSet& B, double s, hipStream_t st);
+// nsweeps FP32 sweeps of phi32, each followed by an exchange of phi32; the
+// first starts from 0 (zero_first) or from phi32 + P phic (phic: level 1's
+// FP32 phi); swaps phi32 and phi2_32.
+hipError_t launch_box_smooth32(BoxSet& B, double h, int nsweeps, bool zero_first, const float* phic,
+                               hipStream_t st);
+// FP32 residual of phi32 restricted into level 1's FP32 fc, phic = 0.
+hipError_t launch_box_resid_restrict32(const BoxSet& B, double h, float* fc, float* phic, hipStream_t st);
+// FP64 refinement over the interiors: phi = phi + phi32 / scales[0], f32 =
+// scales[1] (f - L phi), partial rows {sum r^2, 0, 0, 0} of that residual
+// (*nparts rows); then exchanges of phi and f32.  Swaps phi and phi2.
+hipError_t launch_box_refine(BoxSet& B, double h, const double* scales, double* partials, int* nparts,
+                             hipStream_t st);
 
 }  // namespace mg

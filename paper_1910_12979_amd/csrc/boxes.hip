@@ -194,7 +194,8 @@ __global__ void k_box_beta0(BoxSet B, const double* __restrict__ b0c, const doub
 // only that colour's ghosts (a ghost has the global parity of its cell);
 // -1: all.
 constexpr int kExChunk = 4 * kBoxBlock;
-__global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, int colour, int chunks) {
+template <typename T>
+__global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, T* __restrict__ arr, int colour, int chunks) {
     const int G2 = B.G[2];
     const int chunk = (int)(blockIdx.x % (unsigned)chunks);
     const int kp = (int)((blockIdx.x / (unsigned)chunks) % (unsigned)G2);
@@ -206,7 +207,9 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, int colour
     const int W0 = E[0] + 2 * kG, W1 = E[1] + 2 * kG;
     const bool ghost_plane = k < 0 || k >= E[2];
     const int ncell = ghost_plane ? W0 * W1 : 2 * kG * W0 + 2 * kG * E[1];
-    const BoxView v = view(B, b);
+    const int gx = B.G[0], gxy = B.G[0] * B.G[1];
+    auto p = [&](int i, int j, int k) { return (k + kG) * gxy + (j + kG) * gx + (i + kG); };
+    T* own = arr + (size_t)b * B.stride;
     const int e_end = min(ncell, (chunk + 1) * kExChunk);
     for (int e = chunk * kExChunk + threadIdx.x; e < e_end; e += kBoxBlock) {
         int i, j;
@@ -240,12 +243,12 @@ __global__ __launch_bounds__(kBoxBlock) void k_box_exchange(BoxSet B, int colour
             }
             S[d] = step > 0 ? L[d] - E[d] : (step < 0 ? L[d] + box_ext(B, d, wall ? 0 : o[d]) : L[d]);
         }
-        double val = 0.0;
+        T val = T(0);
         if (!wall) {
             const int sb = (o[2] * B.nb[1] + o[1]) * B.nb[0] + o[0];
-            val = B.phi[(size_t)sb * B.stride + v.p(S[0], S[1], S[2])];
+            val = arr[(size_t)sb * B.stride + p(S[0], S[1], S[2])];
         }
-        v.phi[v.p(i, j, k)] = val;
+        own[p(i, j, k)] = val;
     }
 }
 
@@ -386,11 +389,20 @@ inline void cell_grid(const BoxSet& B, int& gx, int& gy, unsigned& blocks) {
     blocks = (unsigned)gx * gy * B.B[2] * B.nbox;
 }
 
-hipError_t exchange(const BoxSet& B, int colour, hipStream_t st) {
+template <typename T>
+hipError_t exchange_arr(const BoxSet& B, T* arr, int colour, hipStream_t st) {
     const int chunks = cdiv(B.G[0] * B.G[1], kExChunk);
-    hipLaunchKernelGGL(k_box_exchange, dim3((unsigned)chunks * B.G[2] * B.nbox), dim3(kBoxBlock), 0, st, B, colour,
-                       chunks);
+    hipLaunchKernelGGL(k_box_exchange<T>, dim3((unsigned)chunks * B.G[2] * B.nbox), dim3(kBoxBlock), 0, st, B, arr,
+                       colour, chunks);
     return hipGetLastError();
+}
+
+hipError_t exchange(const BoxSet& B, int colour, hipStream_t st) { return exchange_arr<double>(B, B.phi, colour, st); }
+
+// f32 = s f (s a power of two) and the plain FP32 copies, over whole arrays.
+__global__ void k_box_f32(size_t n, const double* __restrict__ a, float* __restrict__ b, double s) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = (float)(s * a[i]);
 }
 
 }  // namespace
@@ -410,7 +422,8 @@ hipError_t launch_box_scatter(const BoxSet& B, const double* f, const double* bx
 
 hipError_t launch_box_exchange(const BoxSet& B, int colour, hipStream_t st) { return exchange(B, colour, st); }
 
-// Arguments of the fused sweep over every box interior.
+// Arguments of the fused sweep over every box interior (FP64 arrays; the
+// FP32 ones by box_sweep_args32).
 SweepArgs<double> box_sweep_args(const BoxSet& B, double h) {
     SweepArgs<double> a{};
     a.nx = B.G[0];
@@ -428,6 +441,29 @@ SweepArgs<double> box_sweep_args(const BoxSet& B, double h) {
     a.bz = B.cz;
     if (B.rho_on) {
         a.rho = B.rho;
+        a.b0c = B.b0c;
+        a.b0e = B.b0e;
+    }
+    return a;
+}
+
+SweepArgs<float> box_sweep_args32(const BoxSet& B, double h) {
+    SweepArgs<float> a{};
+    a.nx = B.G[0];
+    a.ny = B.G[1];
+    a.nz = B.G[2];
+    a.px = a.py = a.pz = 1;
+    a.ox = a.oy = a.oz = kG;
+    a.ex = B.B[0];
+    a.ey = B.B[1];
+    a.ez = B.B[2];
+    a.h2 = (float)(h * h);
+    a.f = B.f32;
+    a.bx = B.cx32;
+    a.by = B.cy32;
+    a.bz = B.cz32;
+    if (B.rho_on) {
+        a.rho = B.rho32;
         a.b0c = B.b0c;
         a.b0e = B.b0e;
     }
@@ -531,6 +567,66 @@ hipError_t launch_box_gather(const BoxSet& B, double* phi, hipStream_t st) {
     cell_grid(B, gx, gy, blocks);
     hipLaunchKernelGGL(k_box_gather, dim3(blocks), dim3(kCellTX, kCellTY), 0, st, B, phi, gx, gy);
     return hipGetLastError();
+}
+
+// ---- mixed precision ------------------------------------------------------
+hipError_t launch_box_to_f32(const BoxSet& B, double s, hipStream_t st) {
+    const size_t n = B.stride * B.nbox;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + kBoxBlock - 1) / kBoxBlock, 4096);
+    hipLaunchKernelGGL(k_box_f32, dim3(blocks), dim3(kBoxBlock), 0, st, n, B.f, B.f32, s);
+    if (B.rho_on) {
+        hipLaunchKernelGGL(k_box_f32, dim3(blocks), dim3(kBoxBlock), 0, st, n, B.rho, B.rho32, 1.0);
+    } else {
+        hipLaunchKernelGGL(k_box_f32, dim3(blocks), dim3(kBoxBlock), 0, st, n, B.cx, B.cx32, 1.0);
+        hipLaunchKernelGGL(k_box_f32, dim3(blocks), dim3(kBoxBlock), 0, st, n, B.cy, B.cy32, 1.0);
+        hipLaunchKernelGGL(k_box_f32, dim3(blocks), dim3(kBoxBlock), 0, st, n, B.cz, B.cz32, 1.0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_box_smooth32(BoxSet& B, double h, int nsweeps, bool zero_first, const float* phic,
+                               hipStream_t st) {
+    if (!B.fused || !B.phi32) return hipErrorInvalidValue;
+    SweepArgs<float> a = box_sweep_args32(B, h);
+    a.phic = phic;
+    for (int s = 0; s < nsweeps; ++s) {
+        a.phi_in = B.phi32;
+        a.phi_out = B.phi2_32;
+        const int mode = s > 0 ? kBoxSweep : (zero_first ? kBoxSweepZero : (phic ? kBoxSweepProlong : kBoxSweep));
+        hipError_t e = launch_sweep_boxes_mode<float>(a, box_geom(B), B.nbox, B.stride, mode, nullptr, st);
+        if (e != hipSuccess) return e;
+        std::swap(B.phi32, B.phi2_32);
+        e = exchange_arr<float>(B, B.phi32, -1, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_box_resid_restrict32(const BoxSet& B, double h, float* fc, float* phic, hipStream_t st) {
+    if (!B.fused || !B.phi32) return hipErrorInvalidValue;
+    SweepArgs<float> a = box_sweep_args32(B, h);
+    a.phi_in = B.phi32;
+    a.fc = fc;
+    a.phic_out = phic;
+    return launch_sweep_boxes_mode<float>(a, box_geom(B), B.nbox, B.stride, kBoxResidRestrict, nullptr, st);
+}
+
+hipError_t launch_box_refine(BoxSet& B, double h, const double* scales, double* partials, int* nparts,
+                             hipStream_t st) {
+    if (!B.fused || !B.phi32) return hipErrorInvalidValue;
+    SweepArgs<double> a = box_sweep_args(B, h);
+    a.phi_in = B.phi;
+    a.phi_out = B.phi2;
+    a.corr = B.phi32;
+    a.r32 = B.f32;
+    a.scales = scales;
+    a.partials = partials;
+    hipError_t e = launch_sweep_boxes_mode<double>(a, box_geom(B), B.nbox, B.stride, kBoxRefine, nparts, st);
+    if (e != hipSuccess) return e;
+    std::swap(B.phi, B.phi2);
+    e = exchange_arr<double>(B, B.phi, -1, st);
+    if (e != hipSuccess) return e;
+    return exchange_arr<float>(B, B.f32, -1, st);
 }
 
 }  // namespace mg

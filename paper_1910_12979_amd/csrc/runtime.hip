@@ -1007,9 +1007,77 @@ static int solve_level0_boxes(mg_hierarchy* H, double fnorm, mg_stats* stats, hi
     return status;
 }
 
+// Mixed-precision solve on the box-split finest level: the single-box mixed
+// solve's iteration (one FP32 V-cycle from zero on the FP64 residual scaled
+// by a power of two, then one FP64 refinement) with the finest level's FP32
+// sweeps, FP32 residual + restriction and the FP64 refinement run box by box
+// and the halo of phi32, phi and the scaled residual exchanged after each;
+// levels 1 and coarser are the single-box FP32 levels.
+static int solve_level0_boxes_mixed(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStream_t st) {
+    Level& L0 = H->lev[0];
+    Level& L1 = H->lev[1];
+    BoxSet& B = H->box;
+    if (!B.phi32 || !B.fused || H->p.pre_sweeps < 1 || H->p.post_sweeps < 1) {
+        set_error("mixed precision on boxes needs fused boxes and at least one pre- and one post-sweep");
+        return MG_ERR_INVALID_ARG;
+    }
+    B.rho_on = H->rho.rho != nullptr;            // plane-parallel beta0: coefficients from rho
+    HIPCHK(launch_box_scatter(B, L0.d.f, L0.d.bx, L0.d.by, L0.d.bz, H->rho.rho, H->rho.b0c, H->rho.b0e, !B.rho_on,
+                              st));
+    const double s0 = residual_scale(fnorm, L0.N);      // residual = f while phi = 0
+    HIPCHK(launch_box_to_f32(B, s0, st));
+    double* scales = H->scal + kSlotScale * kReduceWidth;
+    H->host[kSlotScale * kReduceWidth] = s0;
+    H->host[kSlotScale * kReduceWidth + 1] = s0;
+    HIPCHK(hipMemcpyAsync(scales, H->host + kSlotScale * kReduceWidth, 2 * sizeof(double), hipMemcpyHostToDevice,
+                          st));
+    int status = H->p.rtol >= 1.0 ? MG_OK : MG_ERR_NOT_CONVERGED;
+    int cycles = 0;
+    double rel = 1.0;
+    if (stats) {
+        stats->resid_hist[0] = 1.0;
+        stats->hist_len = 1;
+    }
+    while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
+        HIPCHK(launch_box_smooth32(B, L0.h, H->p.pre_sweeps, true, nullptr, st));
+        HIPCHK(launch_box_resid_restrict32(B, L0.h, L1.s.f, L1.s.phi, st));
+        int rc = vcycle<float>(H, 1, st);
+        if (rc) return rc;
+        HIPCHK(launch_box_smooth32(B, L0.h, H->p.post_sweeps, false, L1.s.phi, st));   // prolongation first
+        int np = 0;
+        HIPCHK(launch_box_refine(B, L0.h, scales, H->partials, &np, st));
+        rc = reduce_to(H, np, kSlotRes, st);
+        if (rc) return rc;
+        HIPCHK(launch_next_scale(H->scal + kSlotRes * kReduceWidth, scales, L0.N, st));
+        rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
+        if (rc) return rc;
+        ++cycles;
+        const double* r = H->host + kSlotRes * kReduceWidth;
+        rel = std::sqrt(r[0]) / fnorm;
+        if (stats && cycles < MG_HIST_MAX) {
+            stats->resid_hist[cycles] = rel;
+            stats->hist_len = cycles + 1;
+        }
+        if (r[3] > 0.0 || !std::isfinite(rel)) {
+            status = MG_ERR_NONFINITE;
+            set_error("non-finite residual during the solve");
+            break;
+        }
+        if (rel <= H->p.rtol) status = MG_OK;
+    }
+    HIPCHK(launch_box_gather(B, L0.d.phi, st));
+    if (stats) {
+        stats->cycles = cycles;
+        stats->rel_resid = rel;
+    }
+    return status;
+}
+
 // Solve on level 0 after f (mean-removed) and the coefficients are in place.
 static int solve_level0(mg_hierarchy* H, double fnorm, mg_stats* stats, hipStream_t st) {
-    if (H->boxes_on) return solve_level0_boxes(H, fnorm, stats, st);
+    if (H->boxes_on)
+        return H->p.precision == MG_MIXED ? solve_level0_boxes_mixed(H, fnorm, stats, st)
+                                          : solve_level0_boxes(H, fnorm, stats, st);
     Level& L0 = H->lev[0];
     HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
     int status = MG_ERR_NOT_CONVERGED;
@@ -1406,7 +1474,7 @@ size_t box_bytes(const mg_params& p, const int32_t box[3]) {
     BoxSet B;
     size_t e = 0, eb = 0;
     if (box_layout(p, box, &B, &e, &eb) != MG_OK) return 0;
-    return (7 * e + 2 * eb) * sizeof(double);
+    return (7 * e + 2 * eb) * sizeof(double) + (p.precision == MG_MIXED ? 7 * e * sizeof(float) : 0);
 }
 
 }  // namespace mg
@@ -1702,14 +1770,23 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
         h->boxes_on = false;
         return MG_OK;
     }
-    if (h->outflow || h->p.precision != MG_FP64 || h->nlev < 2) {
-        set_error("a multi-box finest level needs periodic or wall sides, FP64 precision and two or more levels");
+    if (h->outflow || h->nlev < 2) {
+        set_error("a multi-box finest level needs periodic or wall sides and two or more levels");
         return MG_ERR_INVALID_ARG;
     }
     BoxSet B{};
     size_t e = 0, eb = 0;
     const int rc = box_layout(h->p, box, &B, &e, &eb);
     if (rc) return rc;
+    const bool mixed = h->p.precision == MG_MIXED;
+    if (mixed && !B.fused) {
+        set_error("mixed precision on boxes needs every box to take the fused sweep (at least 32 x 8 x 4 cells)");
+        return MG_ERR_INVALID_ARG;
+    }
+    if (mixed && (long long)sweep_boxes_tiles(B.B[0], B.B[1], B.B[2]) * B.nbox > kMaxPartialRows) {
+        set_error("mixed precision on boxes: too many box tiles for the residual-norm rows");
+        return MG_ERR_INVALID_ARG;
+    }
     B.per[0] = h->px;
     B.per[1] = h->py;
     B.per[2] = h->pz;
@@ -1717,7 +1794,7 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
     h->box_mem = nullptr;
     h->boxes_on = false;
     void* mem = nullptr;
-    HIPCHK(hipMalloc(&mem, (7 * e + 2 * eb) * sizeof(double)));
+    HIPCHK(hipMalloc(&mem, (7 * e + 2 * eb) * sizeof(double) + (mixed ? 7 * e * sizeof(float) : 0)));
     double* p = static_cast<double*>(mem);
     B.phi = p;
     B.phi2 = p + e;
@@ -1728,6 +1805,16 @@ int mg_set_boxes(mg_handle h, const int32_t box[3]) {
     B.rho = p + 6 * e;
     B.b0c = p + 7 * e;
     B.b0e = B.b0c + eb;
+    if (mixed) {                               // FP32 arrays after the FP64 ones (256-byte aligned)
+        float* q = reinterpret_cast<float*>(B.b0e + eb);
+        B.phi32 = q;
+        B.phi2_32 = q + e;
+        B.f32 = q + 2 * e;
+        B.rho32 = q + 3 * e;
+        B.cx32 = q + 4 * e;
+        B.cy32 = q + 5 * e;
+        B.cz32 = q + 6 * e;
+    }
     h->box_mem = mem;
     h->box = B;
     h->boxes_on = true;

@@ -127,6 +127,17 @@ int sweep_boxes_tiles(int bx, int by, int bz);      // tiles per box
 // single-box residual + restriction does.
 hipError_t launch_sweep_boxes(const SweepArgs<double>& a, const BoxGeom& g, int nbox, size_t bstride, int* nparts,
                               hipStream_t st, bool prolong = false, bool restrict_only = false);
+// The same over every box in T with an explicit operation: a sweep of phi_in
+// as stored, of 0 (kInZero) or of phi_in + P phic; the residual + restriction;
+// and (FP64, partial rows) the sweep with the residual norm of its input or
+// the mixed-precision refinement (phi_out = phi_in + corr / scales[0] on the
+// interiors, r32 = scales[1] (f - L phi_out) there, corr and r32 in the same
+// box layout).  nparts must be given exactly for the two row-writing modes.
+enum { kBoxSweep = 0, kBoxSweepZero = 1, kBoxSweepProlong = 2, kBoxSweepNorm = 3, kBoxResidRestrict = 4,
+       kBoxRefine = 5 };
+template <typename T>
+hipError_t launch_sweep_boxes_mode(const SweepArgs<T>& a, const BoxGeom& g, int nbox, size_t bstride, int mode,
+                                   int* nparts, hipStream_t st);
 
 // Number of tiles (= partial rows) a sweep of this shape launches with cfg.
 int sweep_tiles(int nx, int ny, int nz, int cfg);

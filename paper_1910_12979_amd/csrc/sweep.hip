@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <map>
 #include <mutex>
 
@@ -530,17 +531,18 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) MG_SWEEP_WAVES(kBnd) void 
 // before it.  kRho: coefficients from the boxes' ghosted rho and per-box
 // beta0 (a.b0c, a.b0e: g.b0stride entries per box, indexed by ghosted
 // plane), with the domain's walls placed per box.
-template <int TX, int TY, int kOp, bool kRho, int kIn>
+template <typename T, int TX, int TY, int kOp, bool kRho, int kIn>
 __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_waves_per_eu(
-    SweepWaves<double, TX, TY, false>::value))) void k_sweep_boxes(SweepArgs<double> a, BoxGeom g, int tpb,
-                                                                   size_t bstride) {
+    SweepWaves<T, TX, TY, false>::value))) void k_sweep_boxes(SweepArgs<T> a, BoxGeom g, int tpb, size_t bstride) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int b = t / tpb;
     const size_t off = (size_t)b * bstride;
-    SweepArgs<double> c = a;
+    SweepArgs<T> c = a;
     c.phi_in = a.phi_in + off;
     c.phi_out = a.phi_out + off;
     c.f = a.f + off;
+    if (kIn == kInCorrect) c.corr = a.corr + off;          // the FP32 correction, in the same box layout
+    if (kOp == kOpRefine) c.r32 = a.r32 + off;
     const int bc[3] = {b % g.nb[0], (b / g.nb[0]) % g.nb[1], b / (g.nb[0] * g.nb[1])};
     // this box's cells (the launch's tiles cover a full box; a smaller last
     // box leaves the tiles past its cells without writes)
@@ -570,8 +572,8 @@ __global__ __launch_bounds__((TX / 2 + 2) * (TY + 4)) __attribute__((amdgpu_wave
         c.by = a.by + off;
         c.bz = a.bz + off;
     }
-    if (kOp == kOpSweepNorm) c.partials = a.partials + (size_t)b * tpb * kReduceWidth;
-    sweep_body<double, TX, TY, kRho, kIn, kOp, false, true>(c, t - b * tpb);
+    if (kOp == kOpSweepNorm || kOp == kOpRefine) c.partials = a.partials + (size_t)b * tpb * kReduceWidth;
+    sweep_body<T, TX, TY, kRho, kIn, kOp, false, true>(c, t - b * tpb);
 }
 
 // Batched form: tile b of the launch is tile tmap[b].y of problem tmap[b].x
@@ -840,23 +842,48 @@ bool sweep_boxes_fit(int bx, int by, int bz) {
     return bx >= kSweepTX && by >= 8 && bz >= 4 && bx % 2 == 0 && by % 2 == 0 && bz % 2 == 0;
 }
 
-template <int TX, int TY, int kOp, int kIn>
-void launch_boxes_t(const SweepArgs<double>& a, const BoxGeom& g, int tpb, size_t bstride, unsigned blocks,
+template <typename T, int TX, int TY, int kOp, int kIn>
+void launch_boxes_t(const SweepArgs<T>& a, const BoxGeom& g, int tpb, size_t bstride, unsigned blocks,
                     hipStream_t st) {
     if (a.rho)
-        hipLaunchKernelGGL((k_sweep_boxes<TX, TY, kOp, true, kIn>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0,
-                           st, a, g, tpb, bstride);
+        hipLaunchKernelGGL((k_sweep_boxes<T, TX, TY, kOp, true, kIn>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)),
+                           0, st, a, g, tpb, bstride);
     else
-        hipLaunchKernelGGL((k_sweep_boxes<TX, TY, kOp, false, kIn>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)), 0,
-                           st, a, g, tpb, bstride);
+        hipLaunchKernelGGL((k_sweep_boxes<T, TX, TY, kOp, false, kIn>), dim3(blocks), dim3((TX / 2 + 2) * (TY + 4)),
+                           0, st, a, g, tpb, bstride);
 }
 
-hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, const BoxGeom& g, int nbox, size_t bstride, int* nparts,
-                              hipStream_t st, bool prolong, bool restrict_only) {
-    SweepArgs<double> a = a0;
+template <typename T, int TX, int TY>
+void launch_boxes_mode(const SweepArgs<T>& a, const BoxGeom& g, int tpb, size_t bstride, unsigned blocks, int mode,
+                       hipStream_t st) {
+    switch (mode) {
+        case kBoxSweepZero: launch_boxes_t<T, TX, TY, kOpSweep, kInZero>(a, g, tpb, bstride, blocks, st); break;
+        case kBoxSweepProlong: launch_boxes_t<T, TX, TY, kOpSweep, kInProlong>(a, g, tpb, bstride, blocks, st); break;
+        case kBoxResidRestrict:
+            launch_boxes_t<T, TX, TY, kOpResidRestrict, kInPlain>(a, g, tpb, bstride, blocks, st);
+            break;
+        case kBoxSweepNorm:
+            if constexpr (std::is_same<T, double>::value)
+                launch_boxes_t<T, TX, TY, kOpSweepNorm, kInPlain>(a, g, tpb, bstride, blocks, st);
+            break;
+        case kBoxRefine:
+            if constexpr (std::is_same<T, double>::value)
+                launch_boxes_t<T, TX, TY, kOpRefine, kInCorrect>(a, g, tpb, bstride, blocks, st);
+            break;
+        default: launch_boxes_t<T, TX, TY, kOpSweep, kInPlain>(a, g, tpb, bstride, blocks, st); break;
+    }
+}
+
+template <typename T>
+hipError_t launch_sweep_boxes_mode(const SweepArgs<T>& a0, const BoxGeom& g, int nbox, size_t bstride, int mode,
+                                   int* nparts, hipStream_t st) {
+    SweepArgs<T> a = a0;
     if (!sweep_boxes_fit(a.ex, a.ey, a.ez) || a.ox < 2 || a.oy < 2 || a.oz < 2 || a.nx < a.ex + 2 * a.ox ||
         a.ny < a.ey + 2 * a.oy || a.nz < a.ez + 2 * a.oz)
         return hipErrorInvalidValue;
+    const bool rows = mode == kBoxSweepNorm || mode == kBoxRefine;
+    if (rows != (nparts != nullptr)) return hipErrorInvalidValue;
+    if (!std::is_same<T, double>::value && rows) return hipErrorInvalidValue;   // FP64 only
     // the finest level's own tile (64 x 16) where the box takes it, else 32 x 8
     const bool wide = a.ex % 64 == 0 && a.ey % 16 == 0;
     const int TXc = wide ? 64 : 32, TYc = wide ? 16 : 8;
@@ -866,27 +893,26 @@ hipError_t launch_sweep_boxes(const SweepArgs<double>& a0, const BoxGeom& g, int
     const int ntz = (a.ez + a.tz - 1) / a.tz;
     const int tpb = a.ntx * a.nty * ntz;
     const unsigned blocks = (unsigned)tpb * nbox;
-    if (nparts) {
-        if (blocks > (unsigned)kMaxPartialRows || prolong) return hipErrorInvalidValue;
+    if (rows) {
+        if (blocks > (unsigned)kMaxPartialRows) return hipErrorInvalidValue;
         *nparts = (int)blocks;
-        if (wide) launch_boxes_t<64, 16, kOpSweepNorm, kInPlain>(a, g, tpb, bstride, blocks, st);
-        else launch_boxes_t<32, 8, kOpSweepNorm, kInPlain>(a, g, tpb, bstride, blocks, st);
-        return hipGetLastError();
     }
-    if (restrict_only) {
-        if (prolong || nparts) return hipErrorInvalidValue;
-        if (wide) launch_boxes_t<64, 16, kOpResidRestrict, kInPlain>(a, g, tpb, bstride, blocks, st);
-        else launch_boxes_t<32, 8, kOpResidRestrict, kInPlain>(a, g, tpb, bstride, blocks, st);
-        return hipGetLastError();
-    }
-    if (prolong) {
-        if (wide) launch_boxes_t<64, 16, kOpSweep, kInProlong>(a, g, tpb, bstride, blocks, st);
-        else launch_boxes_t<32, 8, kOpSweep, kInProlong>(a, g, tpb, bstride, blocks, st);
-        return hipGetLastError();
-    }
-    if (wide) launch_boxes_t<64, 16, kOpSweep, kInPlain>(a, g, tpb, bstride, blocks, st);
-    else launch_boxes_t<32, 8, kOpSweep, kInPlain>(a, g, tpb, bstride, blocks, st);
+    if (wide) launch_boxes_mode<T, 64, 16>(a, g, tpb, bstride, blocks, mode, st);
+    else launch_boxes_mode<T, 32, 8>(a, g, tpb, bstride, blocks, mode, st);
     return hipGetLastError();
+}
+template hipError_t launch_sweep_boxes_mode<double>(const SweepArgs<double>&, const BoxGeom&, int, size_t, int, int*,
+                                                    hipStream_t);
+template hipError_t launch_sweep_boxes_mode<float>(const SweepArgs<float>&, const BoxGeom&, int, size_t, int, int*,
+                                                   hipStream_t);
+
+hipError_t launch_sweep_boxes(const SweepArgs<double>& a, const BoxGeom& g, int nbox, size_t bstride, int* nparts,
+                              hipStream_t st, bool prolong, bool restrict_only) {
+    if (nparts && (prolong || restrict_only)) return hipErrorInvalidValue;
+    if (prolong && restrict_only) return hipErrorInvalidValue;
+    const int mode = nparts ? kBoxSweepNorm : (restrict_only ? kBoxResidRestrict : (prolong ? kBoxSweepProlong
+                                                                                            : kBoxSweep));
+    return launch_sweep_boxes_mode(a, g, nbox, bstride, mode, nparts, st);
 }
 
 int sweep_tiles(int nx, int ny, int nz, int cfg) {

@@ -351,3 +351,27 @@ def test_batch_nodal_mixed_precision_matches_solo_and_oracle(mp):
         assert s["status_name"] == "OK" and s["cycles"] == st0["cycles"]
         assert same(out, out0)
         check_nodal_oracle(p, out)
+
+
+def test_batch_boxes_mixed_precision_matches_solo_and_oracle(mp):
+    """A multi-box problem in mixed precision (fused boxes, uneven) inside a
+    batch with a single-box one: each equals its solo solve bit for bit, the
+    boxed one meets the oracle bar."""
+    pb = I.make_problem((96, 48, 40), H=0.15, rho_noise=0.05, seed=321, periodic=(False, False, False), dx=1 / 96)
+    ps = I.make_problem(32, H=0.2, seed=322)
+    H = mp.Hierarchy(mp.params_of(pb, precision="mixed"))
+    H.set_boxes((64, 32, 16))
+    d = mp.to_device(pb)
+    st0 = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+    torch.cuda.synchronize()
+    H.close()
+    out0 = mac_out(d)
+    ref_s = solo(mp, ps, "mixed")
+    db, ds = mp.to_device(pb), mp.to_device(ps)
+    code, stats = mp.project_batch_problems([mp.problem_struct(mp.params_of(pb, precision="mixed"), db, (64, 32, 16)),
+                                             mp.problem_struct(mp.params_of(ps, precision="mixed"), ds)])
+    torch.cuda.synchronize()
+    assert code == 0, stats
+    assert stats[0]["cycles"] == st0["cycles"] and same(mac_out(db), out0)
+    assert stats[1]["cycles"] == ref_s[0]["cycles"] and same(mac_out(ds), ref_s[1])
+    check_mac_oracle(pb, mac_out(db))

@@ -33,10 +33,10 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_gpu(mp, prob, box=None, allow=(0,), H=None):
+def run_gpu(mp, prob, box=None, allow=(0,), H=None, precision="fp64"):
     own = H is None
     if own:
-        H = mp.Hierarchy(mp.params_of(prob))
+        H = mp.Hierarchy(mp.params_of(prob, precision=precision))
         if box is not None:
             H.set_boxes(box)
     d = mp.to_device(prob)
@@ -243,3 +243,63 @@ def test_boxes_cycle_cap(mp):
     assert st["cycles"] == st1["cycles"] == 2
     for k in out:
         assert rel(out[k], out1[k]) <= 1e-12, k
+
+
+
+MIXED_CASES = [
+    ((64, 64, 64), (False, True, False), (32, 16, 64), 61),    # fused, 32x8 tiles
+    ((128, 64, 32), (True, False, False), (64, 32, 16), 62),   # fused, 64-wide tiles
+    ((96, 48, 40), (False, False, False), (64, 32, 16), 63),   # uneven: 64+32, 32+16, 16+16+8
+    ((96, 64, 64), (True, True, True), (64, 48, 40), 64),      # uneven, periodic across unequal boxes
+]
+
+
+@pytest.mark.parametrize("n,per,box,seed", MIXED_CASES)
+def test_boxes_mixed_precision_matches_oracle(mp, n, per, box, seed):
+    """Mixed precision on boxes (FP32 box sweeps and FP64 refinement over the
+    boxes): the oracle bar of the single-box solve, and within 1e-9 of the
+    single-box mixed solve."""
+    prob = I.make_problem(n, H=0.15, rho_noise=0.05, seed=seed, periodic=per, dx=1.0 / n[0])
+    st, out = run_gpu(mp, prob, box=box, precision="mixed")
+    check_oracle(prob, st, out)
+    H1 = mp.Hierarchy(mp.params_of(prob, precision="mixed"))
+    st1, out1 = run_gpu(mp, prob, H=H1)
+    H1.close()
+    assert abs(st["cycles"] - st1["cycles"]) <= 1
+    for k in ("phi", "u", "v", "w"):
+        assert rel(out[k], out1[k]) <= 1e-9, k
+
+
+def test_boxes_mixed_precision_strict_and_radial(mp):
+    """Solved to rtol 1e-12 in mixed precision on uneven boxes: within 1e-9 of
+    the exact solution outright; and a radial base state inside walls (the
+    FP32 stored-coefficient box sweep) at the oracle bar."""
+    prob = I.make_problem((96, 64, 64), H=0.15, rho_noise=0.05, seed=65, periodic=(True, True, True), dx=1 / 96,
+                          rtol=1e-12)
+    st, out = run_gpu(mp, prob, box=(64, 48, 40), precision="mixed")
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-12
+    ref = O.mac_project(prob, mode="definition")
+    assert ref["status"] == 0
+    for k in ("phi", "u", "v", "w"):
+        assert rel(out[k], ref[k]) <= 1e-9, (k, rel(out[k], ref[k]))
+    rad = _radial_walls((64, 32, 48), 66)
+    st, out = run_gpu(mp, rad, box=(32, 16, 24), precision="mixed")
+    check_oracle(rad, st, out)
+
+
+def test_boxes_mixed_256_full_size(mp):
+    """The 256^3 steep box in 64 boxes of 64^3, mixed precision: converged in
+    FP64 terms by the oracle's operator, and within 1e-9 of the single-box
+    mixed solve."""
+    prob = I.STEEP_256()
+    st, out = run_gpu(mp, prob, box=(64, 64, 64), precision="mixed")
+    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10
+    H1 = mp.Hierarchy(mp.params_of(prob, precision="mixed"))
+    st1, out1 = run_gpu(mp, prob, H=H1)
+    H1.close()
+    assert rel(out["phi"], out1["phi"]) <= 1e-9
+    c = O.face_coeffs(prob.n, prob.periodic, prob.rho, prob.beta0_cc, prob.beta0_edge)
+    f = O.rhs(prob.n, prob.periodic, prob.dx, prob.beta0_cc, prob.beta0_edge, prob.u, prob.v, prob.w, prob.S)
+    f -= f.mean()
+    r = O.residual(prob.n, prob.periodic, prob.dx, c, out["phi"], f)
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(f)
