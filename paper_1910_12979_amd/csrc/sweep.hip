@@ -131,8 +131,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const bool r1c0 = row_r1 && lp >= 1;            // even cell inside the ring-1 window
     const bool r1c1 = row_r1 && lp < WP - 1;        // odd cell
     const bool writes = ly >= 2 && ly < WY - 2 && lp >= 1 && lp <= WP - 2 && gx0 < ox + ex && gy < oy + ey;
-    const size_t plane = (size_t)nx * ny;
+    // 32-bit element offsets (a fused level holds fewer than 2^32 cells):
+    // the per-plane index arithmetic stays in single scalar instructions
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
     const size_t col = (size_t)gyw * nx + gxw;
+    // the plane part is uniform over the workgroup (scalar); the column part per lane
+    auto base = [&](auto* p, int tw) { return p + (size_t)((unsigned)tw * plane); };
     const T h2 = a.h2;
     const T ih2 = T(1) / a.h2;
     const T half = T(0.5);
@@ -177,7 +181,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             return;
         }
         int tw = wrap3(t, nz);
-        ld2(a.phi_in + (size_t)tw * plane + col, v0, v1);
+        ld2(base(a.phi_in, tw) + col, v0, v1);
         if (kIn == kInProlong) {
             const int Z = kBox ? gwrap(a.go[2] + tw - oz, a.gn[2], a.gp[2]) : tw;
             T c = a.phic[(size_t)(Z >> 1) * (kBox ? cplane : (plane >> 2)) + ccol];
@@ -186,20 +190,20 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         }
         if (kIn == kInCorrect) {
             float e0, e1;
-            ld2(a.corr + (size_t)tw * plane + col, e0, e1);
+            ld2(base(a.corr, tw) + col, e0, e1);
             v0 = v0 + cscale * (T)e0;
             v1 = v1 + cscale * (T)e1;
         }
     };
     auto load_f = [&](int t, T& v0, T& v1) {
         int tw = wrap3(t, nz);
-        ld2(a.f + (size_t)tw * plane + col, v0, v1);
+        ld2(base(a.f, tw) + col, v0, v1);
     };
     // rho (finest level) or the stored low z-face coefficient of plane t
     auto load_q = [&](int t, T& v0, T& v1) {
         int tw = wrap3(t, nz);
-        if (kRho) ld2(a.rho + (size_t)tw * plane + col, v0, v1);
-        else ld2(a.bz + (size_t)tw * plane + col, v0, v1);
+        if (kRho) ld2(base(a.rho, tw) + col, v0, v1);
+        else ld2(base(a.bz, tw) + col, v0, v1);
     };
     // low z-face coefficient of plane t from the queue values of planes t-1, t
     auto zface = [&](int t, T q_below, T q_here) -> T {
@@ -236,15 +240,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         load_q(min(s + 4, z1 + 1), X.q0, X.q1);
         if (!kRho) {
             int tw = wrap3(min(s + 3, z1), nz);
-            ld2(a.bx + (size_t)tw * plane + col, X.x0, X.x1);
-            ld2(a.by + (size_t)tw * plane + col, X.y0, X.y1);
+            ld2(base(a.bx, tw) + col, X.x0, X.x1);
+            ld2(base(a.by, tw) + col, X.y0, X.y1);
         }
         load_f(min(s + 2, z1), X.f0, X.f1);
         if constexpr (kBnd) {
             const int tw = wrap3(min(s + 2, z1), nz);
             X.g0 = T(0);
             X.g1 = T(0);
-            if (bl || zbnd(tw)) ld2(a.dg + (size_t)tw * plane + col, X.g0, X.g1);
+            if (bl || zbnd(tw)) ld2(base(a.dg, tw) + col, X.g0, X.g1);
         }
     };
     Fly A, B;
@@ -294,10 +298,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     } else {
         int tw = wrap3(z0 - 1, nz);
         T t0, t1;
-        ld2(a.bx + (size_t)tw * plane + col, t0, t1);
+        ld2(base(a.bx, tw) + col, t0, t1);
         sbx[(z0 - 1 + 3) % 3][ly][lx0] = t0;
         sbx[(z0 - 1 + 3) % 3][ly][lx0 + 1] = t1;
-        ld2(a.by + (size_t)tw * plane + col, t0, t1);
+        ld2(base(a.by, tw) + col, t0, t1);
         sby[(z0 - 1 + 3) % 3][ly][lx0] = t0;
         sby[(z0 - 1 + 3) % 3][ly][lx0 + 1] = t1;
     }
@@ -335,7 +339,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const size_t ccols = kBox ? (size_t)(a.gn[0] >> 1) * (a.gn[1] >> 1) : (size_t)(nx >> 1) * (ny >> 1);
     const size_t cc = kBox ? (size_t)((a.go[1] + gyw - oy) >> 1) * (a.gn[0] >> 1) + ((a.go[0] + gxw - ox) >> 1)
                            : (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
-    auto step = [&](int t, Fly& X) {
+    // m3 = t mod 3 (t >= -1), carried by the caller instead of divided out
+    auto step = [&](int t, int m3, Fly& X) {
         // 0. slide the z window, taking in the set issued two steps ago:
         //    phi[t+1], rho[t+2] (or bz[t+2]), f[t], bx/by[t+1]; then re-issue
         Fm0 = Fc0; Fm1 = Fc1;
@@ -359,7 +364,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             cy0 = X.y0; cy1 = X.y1;
         }
         issue(t, X);                             // consumed by step t+2
-        const int s_t = (t + 3) % 3, s_p = (t + 4) % 3, s_m = (t + 2) % 3;
+        const int s_t = m3, s_p = m3 == 2 ? 0 : m3 + 1, s_m = m3 == 0 ? 2 : m3 - 1;
         const int cur = t & 1, nxt = (t + 1) & 1;
         const int rsel = (gy + t) & 1;           // red cell of the pair at plane t (black at t-1)
         // 1. x/y coefficients of plane t+1 (read by the next step)
@@ -416,9 +421,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             const double d0 = (double)r0, d1 = (double)r1;
             nrm2 += d0 * d0;
             nrm2 += d1 * d1;
-            const size_t o = (size_t)t * plane + col;
-            st2(a.phi_out + o, Pc0, Pc1);
-            st2(a.r32 + o, (float)(rscale * d0), (float)(rscale * d1));
+            st2(base(a.phi_out, t) + col, Pc0, Pc1);
+            st2(base(a.r32, t) + col, (float)(rscale * d0), (float)(rscale * d1));
         }
         // 3. (kRR) restriction of plane t-1, whose residuals the previous step wrote
         const int tb = t - 1;
@@ -455,7 +459,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + bzh;
             if constexpr (kBnd) den = den + (rsel ? Gm1 : Gm0);
             const T blk = qdiv(num - h2 * (rsel ? Fm1 : Fm0), den);
-            T* dst = a.phi_out + (size_t)tb * plane + col;
+            T* dst = base(a.phi_out, tb) + col;
             if (rsel) st2(dst, Rm, blk);
             else st2(dst, blk, Rm);
         }
@@ -473,11 +477,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         __syncthreads();
     };
     int t = z0 - 1;
+    int m3 = (t + 3) % 3;
     for (; t + 1 <= z1; t += 2) {
-        step(t, A);
-        step(t + 1, B);
+        step(t, m3, A);
+        m3 = m3 == 2 ? 0 : m3 + 1;
+        step(t + 1, m3, B);
+        m3 = m3 == 2 ? 0 : m3 + 1;
     }
-    if (t <= z1) step(t, A);
+    if (t <= z1) step(t, m3, A);
     if (kNorm || kIR) {
         // fixed-order block reduction into this tile's partial row (in the
         // red-value buffer, free after the last step's barrier)
@@ -676,7 +683,8 @@ int sweep_config_for(int nx, int ny, int nz, bool rho, bool dbl, bool coarse) {
 
 template <typename T>
 bool sweep_fusable(int nx, int ny, int nz) {
-    return nx >= kSweepTX && ny >= kSweepTY && nz >= 4 && nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0;
+    return nx >= kSweepTX && ny >= kSweepTY && nz >= 4 && nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 &&
+           (unsigned long long)nx * ny * nz < (1ull << 32);      // 32-bit element offsets
 }
 
 template <typename T>
