@@ -231,6 +231,77 @@ def mixed_leg(args, torch, macproj, R, phi64, phi_ref=None):
             "phi_rel_diff_vs_fp64_gpu": diff, "phi_rel_err_vs_fp64_oracle": err}
 
 
+# finest-level tile configurations the batched sweep takes (32x8, 64x8 tiles)
+BATCH_TILE_CFGS = (0, 1, 2, 6, 7, 8)
+
+
+def batch_autotune(args, torch, macproj, rs, specs):
+    """Tile choice for the batch as a whole: every problem of a shape sweeps
+    its finest level with the same configuration, which the process-wide
+    tuning table holds, so a problem solved alone afterwards takes the same
+    tiles and the batched results stay bit-identical to one-by-one solves.
+    Timed on whole project_batch calls (inputs restored before each): first
+    one configuration for every shape, then each shape's own, largest
+    shapes first, kept when it is faster by more than 1%.  FP64 entries on
+    the FP64 batch, then the FP32 entries on the mixed-precision batch."""
+    edges = sorted({e for e, _, _ in specs}, reverse=True)
+    macproj.tune_cache_clear()
+    choice = {}
+
+    cfg_tile = {0: [32, 8, 32], 1: [32, 8, 64], 2: [64, 8, 32], 6: [32, 8, 16], 7: [32, 8, 8], 8: [64, 8, 64]}
+
+    def fits(e, c):
+        return cfg_tile[c][0] <= e and cfg_tile[c][1] <= e
+
+    def record(fp64):
+        for e in edges:
+            macproj.tune_record((e, e, e), choice[(e, fp64)], rho=True, fp64=fp64, coarse=False)
+
+    def timed(prec):
+        params = [macproj.params_of(r.prob, precision=prec) for r in rs]
+        best = None
+        for _ in range(3):
+            for r in rs:
+                r.restore()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code, _ = macproj.project_batch(params, [r.d for r in rs])
+            torch.cuda.synchronize()
+            assert code == 0, code
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    for fp64, prec in ((True, "fp64"), (False, "mixed")):
+        log(f"batch autotune ({prec}): {len(BATCH_TILE_CFGS)} uniform choices, then per shape")
+        results = {}
+        for c in BATCH_TILE_CFGS:
+            for e in edges:
+                choice[(e, fp64)] = c if fits(e, c) else 0
+            record(fp64)
+            results[c] = timed(prec)
+        cur = min(results, key=results.get)
+        for e in edges:
+            choice[(e, fp64)] = cur if fits(e, cur) else 0
+        record(fp64)
+        t_cur = results[cur]
+        for e in edges:
+            for c in BATCH_TILE_CFGS:
+                if c == choice[(e, fp64)] or not fits(e, c):
+                    continue
+                old = choice[(e, fp64)]
+                choice[(e, fp64)] = c
+                record(fp64)
+                t = timed(prec)
+                if t < 0.99 * t_cur:
+                    t_cur = t
+                else:
+                    choice[(e, fp64)] = old
+                    record(fp64)
+    return [{"edge": e, "fp64_level0_tile": cfg_tile[choice[(e, True)]],
+             "fp32_level0_tile": cfg_tile[choice[(e, False)]]} for e in sorted(edges)]
+
+
 def batch_leg(args, torch, macproj, inputs, dev):
     """64 independent uneven boxes: one project_batch call against one
     mac_project call per problem (hierarchies kept, as the batch keeps them),
@@ -239,15 +310,7 @@ def batch_leg(args, torch, macproj, inputs, dev):
     log("batch: generating 64 problems")
     rs = [Restorable(macproj, inputs.make_problem(e, H=H, rho_noise=0.01, seed=s), dev) for e, H, s in specs]
     cells = sum(r.prob.ncells for r in rs)
-    tuned = []
-    if args.autotune:
-        for e in sorted({e for e, _, _ in specs}):
-            r = next(r for r in rs if r.prob.n[0] == e)
-            Ht = macproj.Hierarchy(macproj.params_of(r.prob))
-            Ht.set_coefficients(r.d.rho, r.d.beta0_cc, r.d.beta0_edge)
-            Ht.mg_autotune(reps=5)
-            tuned.append({"edge": e, "level0_tile": Ht.sweep_config(0)})
-            Ht.close()
+    tuned = batch_autotune(args, torch, macproj, rs, specs) if args.autotune else []
     out = {"problems": 64, "cells": cells, "autotuned": tuned}
     for prec in ("mixed", "fp64"):
         params = [macproj.params_of(r.prob, precision=prec) for r in rs]
@@ -622,7 +685,7 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=5)
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--batch-reps", type=int, default=3, help="0 skips the batch leg")
-    ap.add_argument("--autotune", type=int, default=1, help="autotune the batch's shapes first")
+    ap.add_argument("--autotune", type=int, default=1, help="tune the batch's tile choices on the batch first")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[50.0, 100.0, 200.0, 500.0, 1000.0, 1500.0,
                                                                      2000.0])
     ap.add_argument("--serve-mixed-rates", type=float, nargs="*", default=[200.0, 1000.0],
