@@ -231,8 +231,8 @@ def mixed_leg(args, torch, macproj, R, phi64, phi_ref=None):
             "phi_rel_diff_vs_fp64_gpu": diff, "phi_rel_err_vs_fp64_oracle": err}
 
 
-# finest-level tile configurations the batched sweep takes (32x8, 64x8 tiles)
-BATCH_TILE_CFGS = (0, 1, 2, 6, 7, 8)
+# finest-level tile configurations the batched sweep takes (32x8, 64x8, 64x16 tiles)
+BATCH_TILE_CFGS = (0, 1, 2, 6, 7, 8, 9, 11)
 
 
 def batch_autotune(args, torch, macproj, rs, specs):
@@ -248,7 +248,8 @@ def batch_autotune(args, torch, macproj, rs, specs):
     macproj.tune_cache_clear()
     choice = {}
 
-    cfg_tile = {0: [32, 8, 32], 1: [32, 8, 64], 2: [64, 8, 32], 6: [32, 8, 16], 7: [32, 8, 8], 8: [64, 8, 64]}
+    cfg_tile = {0: [32, 8, 32], 1: [32, 8, 64], 2: [64, 8, 32], 6: [32, 8, 16], 7: [32, 8, 8], 8: [64, 8, 64],
+                9: [64, 16, 32], 11: [64, 16, 64]}
 
     def fits(e, c):
         return cfg_tile[c][0] <= e and cfg_tile[c][1] <= e

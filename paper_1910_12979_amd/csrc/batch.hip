@@ -151,7 +151,8 @@ SweepArgs<double> sweep_args(mg_hierarchy* H, int l) {
 
 bool multi_tile_shape(int cfg) {
     const SweepCfg& c = kSweepCfgs[cfg];
-    return (c.tx == 32 && c.ty == 8) || (c.tx == 64 && c.ty == 8) || (c.tx == 32 && c.ty == 4);
+    return (c.tx == 32 && c.ty == 8) || (c.tx == 64 && c.ty == 8) || (c.tx == 32 && c.ty == 4) ||
+           (c.tx == 64 && c.ty == 16);
 }
 
 // One batched launch of the fused sweep kernel (op) over `grp`, grouped by

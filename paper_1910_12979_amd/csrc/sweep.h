@@ -90,7 +90,7 @@ hipError_t launch_refine(const SweepArgs<double>& a, bool use_rho, int cfg, int*
 // tmap[b].y of problem tmap[b].x (device, `tiles` entries, every problem's
 // tiles in order); `op` is kOpSweep, kOpResidRestrict, or (FP64 with rho
 // only) kOpSweepNorm (plain input) or kOpRefine (corrected input).  Tile
-// shapes 32x8, 64x8 and 32x4.
+// shapes 32x8, 64x8, 32x4 and 64x16.
 template <typename T>
 hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int2* tmap, int tiles, bool use_rho, int in_mode, int op,
                               int cfg, hipStream_t st);

@@ -824,6 +824,7 @@ hipError_t launch_sweep_multi(const SweepArgs<T>* d, const int2* tmap, int tiles
     if (c.tx == 32 && c.ty == 8) return launch_multi_mode<T, 32, 8>(d, tmap, tiles, use_rho, in_mode, op, st);
     if (c.tx == 64 && c.ty == 8) return launch_multi_mode<T, 64, 8>(d, tmap, tiles, use_rho, in_mode, op, st);
     if (c.tx == 32 && c.ty == 4) return launch_multi_mode<T, 32, 4>(d, tmap, tiles, use_rho, in_mode, op, st);
+    if (c.tx == 64 && c.ty == 16) return launch_multi_mode<T, 64, 16>(d, tmap, tiles, use_rho, in_mode, op, st);
     return hipErrorInvalidValue;      // other tile shapes are single-problem only
 }
 

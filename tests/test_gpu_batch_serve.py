@@ -375,3 +375,29 @@ def test_batch_boxes_mixed_precision_matches_solo_and_oracle(mp):
     assert stats[0]["cycles"] == st0["cycles"] and same(mac_out(db), out0)
     assert stats[1]["cycles"] == ref_s[0]["cycles"] and same(mac_out(ds), ref_s[1])
     check_mac_oracle(pb, mac_out(db))
+
+
+def test_batch_with_64x16_tiles_matches_solo(mp):
+    """A shape whose finest level is tuned to 64x16-cell tiles (the batched
+    sweep's widest form) in FP64 and in mixed precision: batched results equal
+    the solo ones bit for bit."""
+    n = (128, 64, 64)
+    try:
+        mp.tune_record(n, 9, rho=True, fp64=True, coarse=False)
+        mp.tune_record(n, 11, rho=True, fp64=False, coarse=False)
+        probs = [I.make_problem(n, H=0.15, seed=331, dx=1 / 128), I.make_problem(n, H=0.2, seed=332, dx=1 / 128),
+                 I.make_problem(64, H=0.1, seed=333)]
+        precs = ["fp64", "mixed", "fp64"]
+        refs = [solo(mp, p, pr) for p, pr in zip(probs, precs)]
+        devs = [mp.to_device(p) for p in probs]
+        code, stats = mp.project_batch([mp.params_of(p, precision=pr) for p, pr in zip(probs, precs)], devs)
+        torch.cuda.synchronize()
+        assert code == 0, stats
+        for (st0, out0), s, d in zip(refs, stats, devs):
+            assert s["status_name"] == "OK" and s["cycles"] == st0["cycles"] and s["rel_resid"] == st0["rel_resid"]
+            assert same(mac_out(d), out0)
+        H = mp.Hierarchy(mp.params_of(probs[0]))
+        assert H.sweep_config(0)[:2] == (64, 16)
+        H.close()
+    finally:
+        mp.tune_cache_clear()
