@@ -698,40 +698,63 @@ __global__ void k_nod_restrict(NodLevelT<T> F, NodLevelT<T> C) {
     C.phi[c] = T(0);
 }
 
-// fine phi += trilinear interpolation of the coarse phi.
+// fine phi += trilinear interpolation of the coarse phi.  One thread per
+// coarse node (I, J, K) updates the up to 8 fine nodes (2I + dx, 2J + dy,
+// 2K + dz), dx, dy, dz in {0, 1}, from the 8 coarse values around it,
+// loaded once; per fine node the parents are summed in the order (z, y, x)
+// with the weight 1 or 1/2 per direction.
 template <typename T>
 __global__ void k_nod_prolong(NodLevelT<T> F, NodLevelT<T> C) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;
     const int K = blockIdx.z * blockDim.z + threadIdx.z;
-    if (I >= F.Nx || J >= F.Ny || K >= F.Nz) return;
-    const int X[3] = {I, J, K};
-    const int Nc[3] = {C.Nx, C.Ny, C.Nz}, per[3] = {C.px, C.py, C.pz};
-    T v = T(0);
-    for (int bz = 0; bz < 2; ++bz)
-        for (int by = 0; by < 2; ++by)
-            for (int bx = 0; bx < 2; ++bx) {
-                const int B[3] = {bx, by, bz};
-                int m[3];
-                bool ok = true;
-                T w = T(1);
-                for (int d = 0; d < 3; ++d) {
-                    if ((X[d] & 1) == 0) {
-                        if (B[d]) {
-                            ok = false;
-                            break;
+    if (I >= C.Nx || J >= C.Ny || K >= C.Nz) return;
+    // coarse node + 1 in each direction (the periodic image; beyond a wall
+    // the node itself, whose value is never used: no fine node lies there)
+    const int I1 = I + 1 < C.Nx ? I + 1 : (C.px ? 0 : I);
+    const int J1 = J + 1 < C.Ny ? J + 1 : (C.py ? 0 : J);
+    const int K1 = K + 1 < C.Nz ? K + 1 : (C.pz ? 0 : K);
+    T c[2][2][2];
+    c[0][0][0] = C.phi[nidx(C, I, J, K)];
+    c[0][0][1] = C.phi[nidx(C, I1, J, K)];
+    c[0][1][0] = C.phi[nidx(C, I, J1, K)];
+    c[0][1][1] = C.phi[nidx(C, I1, J1, K)];
+    c[1][0][0] = C.phi[nidx(C, I, J, K1)];
+    c[1][0][1] = C.phi[nidx(C, I1, J, K1)];
+    c[1][1][0] = C.phi[nidx(C, I, J1, K1)];
+    c[1][1][1] = C.phi[nidx(C, I1, J1, K1)];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int X = 2 * I + dx, Y = 2 * J + dy, Z = 2 * K + dz;
+                if (X >= F.Nx || Y >= F.Ny || Z >= F.Nz) continue;
+                const int D[3] = {dx, dy, dz};
+                T v = T(0);
+#pragma unroll
+                for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+                    for (int by = 0; by < 2; ++by)
+#pragma unroll
+                        for (int bx = 0; bx < 2; ++bx) {
+                            const int B[3] = {bx, by, bz};
+                            bool ok = true;
+                            T w = T(1);
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                if (D[d] == 0) {
+                                    if (B[d]) ok = false;    // an even fine index has one parent
+                                } else {
+                                    w *= T(0.5);
+                                }
+                            }
+                            if (ok) v += w * c[bz][by][bx];
                         }
-                        m[d] = X[d] >> 1;
-                    } else {
-                        m[d] = B[d] ? (X[d] + 1) >> 1 : (X[d] - 1) >> 1;
-                        if (per[d] && m[d] >= Nc[d]) m[d] -= Nc[d];
-                        w *= T(0.5);
-                    }
-                }
-                if (ok) v += w * C.phi[nidx(C, m[0], m[1], m[2])];
+                const size_t n = nidx(F, X, Y, Z);
+                F.phi[n] = F.phi[n] + v;
             }
-    const size_t n = nidx(F, I, J, K);
-    F.phi[n] = F.phi[n] + v;
 }
 
 __global__ void k_nod_avg_sigma(NodLevel F, NodLevel C) {
@@ -1050,7 +1073,7 @@ int nod_prolong(nodal_hierarchy* H, int l, hipStream_t st) {
     const NodLevelT<T>& F = nod_levels<T>(H)[l];
     const NodLevelT<T>& C = nod_levels<T>(H)[l + 1];
     const dim3 block(32, 4, 2);
-    hipLaunchKernelGGL(k_nod_prolong<T>, grid3(F.Nx, F.Ny, F.Nz, block), block, 0, st, F, C);
+    hipLaunchKernelGGL(k_nod_prolong<T>, grid3(C.Nx, C.Ny, C.Nz, block), block, 0, st, F, C);
     NHIP(hipGetLastError());
     return MG_OK;
 }
