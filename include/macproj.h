@@ -301,6 +301,12 @@ int nodal_set_coefficients(nodal_handle h, const double* rho, const double* beta
  * one captured hipGraph replayed every cycle (all buffers are fixed);
  * results are identical either way. */
 int nodal_set_graphs(nodal_handle h, int32_t enable);
+/* enable = 1 (the default): the coarse levels whose phi, f and r fit in
+ * 136 KB of LDS (with every coarser level's) run as one workgroup per V-cycle
+ * (colours, residual, restriction, coarsest solve, prolongation with
+ * barriers in between) instead of one launch per step; the per-node
+ * arithmetic is the same, so results are identical either way. */
+int nodal_set_bottom(nodal_handle h, int32_t enable);
 typedef enum { MG_NOD_PHI = 0, MG_NOD_F = 1, MG_NOD_SIGMA = 2 } mg_nodal_array;
 /* dims = {Nx, Ny, Nz, nx, ny, nz} of level l; *dx its spacing. */
 int nodal_level_info(nodal_handle h, int32_t level, int32_t dims[6], double* dx);

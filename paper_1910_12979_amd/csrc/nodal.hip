@@ -866,6 +866,224 @@ __global__ void k_nod_shift_out(size_t n, const double* __restrict__ phi, const 
         out[e] = phi[e] - m;
 }
 
+// ---------------------------------------------------------------------------
+// Bottom of the nodal V-cycle in one workgroup: from the first level whose
+// phi, f and r (with every coarser level's) fit in LDS down to the coarsest
+// solve and back, with barriers between dependent steps instead of one
+// launch of a few microseconds per colour, residual, restriction and
+// prolongation.  Per node the arithmetic is that of the per-level kernels
+// (the same stencil routine for the colours, the same sums in the same
+// order for the residual, restriction, prolongation and coarsest solve), so
+// a bottom launch gives the same bits as the launches it replaces.  sigma
+// stays in global memory.
+// ---------------------------------------------------------------------------
+constexpr int kNodBottomThreads = 1024;
+constexpr size_t kNodBottomLds = 136 * 1024;     // phi, f, r of every bottom level
+constexpr int kNodBottomMax = 8;
+
+template <typename T>
+struct NodBottomArgs {
+    int nlev;
+    NodLevelT<T> lev[kNodBottomMax];    // sig global; phi, f of lev[0] global (in and out)
+    int off[kNodBottomMax];             // element offsets of each level's phi, f, r in LDS
+    const double* minv;
+    int pre, post;
+};
+
+// (L phi) at node (I, J, K) as the residual kernel forms it: cells sz, sy,
+// sx, each sigma times (far corners - 4 phi_n), nodes beyond a wall 0 and
+// cells beyond it skipped (their sigma is 0 there).
+template <typename T>
+__device__ inline T nb_apply(const NodLevelT<T>& L, const T* P, int I, int J, int K) {
+    const NodAxis ax = nod_axis(I, L.Nx, L.nx, L.px);
+    const NodAxis ay = nod_axis(J, L.Ny, L.ny, L.py);
+    const NodAxis az = nod_axis(K, L.Nz, L.nz, L.pz);
+    NodNbr<T> N;
+    nod_load_nbrs(L, P, I, ax, ay, az, J, K, N);
+    const T pn = P[((size_t)K * L.Ny + J) * L.Nx + I];
+    const long long nx = L.nx, nxny = (long long)L.nx * L.ny;
+    T sum = T(0);
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz) {
+        const int oz = sz ? 2 : 0;
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            const int oy = sy ? 2 : 0;
+#pragma unroll
+            for (int sx = 0; sx < 2; ++sx) {
+                const int ox = sx ? 2 : 0;
+                T sig = T(0);
+                if (az.e[sz] && ay.e[sy] && ax.e[sx]) sig = L.sig[az.c[sz] * nxny + ay.c[sy] * nx + ax.c[sx]];
+                T acc = T(0);
+                acc += N.v[1][oy][ox];
+                acc += N.v[oz][1][ox];
+                acc += N.v[oz][oy][1];
+                acc += N.v[oz][oy][ox];
+                sum += sig * (acc - T(4) * pn);
+            }
+        }
+    }
+    return sum;
+}
+
+template <typename T>
+__device__ void nb_colour(const NodLevelT<T>& L, T* P, const T* F, int col) {
+    const int hy = (L.Ny + 1 - (col & 1)) >> 1, hz = (L.Nz + 1 - (col >> 1)) >> 1;
+    const int items = L.Nx * hy * hz;
+    const T c12 = (T)(12.0 * (L.h * L.h));
+    for (int e = threadIdx.x; e < items; e += blockDim.x) {
+        const int I = e % L.Nx, r = e / L.Nx;
+        const int J = 2 * (r % hy) + (col & 1), K = 2 * (r / hy) + (col >> 1);
+        T num, den;
+        nod_stencil_fast(L, P, I, J, K, num, den);
+        const size_t n = ((size_t)K * L.Ny + J) * L.Nx + I;
+        P[n] = (num - c12 * F[n]) / den;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void nb_resid(const NodLevelT<T>& L, const T* P, const T* F, T* R) {
+    const int items = L.Nx * L.Ny * L.Nz;
+    const T ih = (T)(12.0 * L.h * L.h);
+    for (int e = threadIdx.x; e < items; e += blockDim.x) {
+        const int I = e % L.Nx, J = (e / L.Nx) % L.Ny, K = e / (L.Nx * L.Ny);
+        R[e] = F[e] - nb_apply(L, P, I, J, K) / ih;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void nb_restrict(const NodLevelT<T>& Fl, const T* R, const NodLevelT<T>& Cl, T* cP, T* cF) {
+    const int items = Cl.Nx * Cl.Ny * Cl.Nz;
+    const int Nn[3] = {Fl.Nx, Fl.Ny, Fl.Nz}, per[3] = {Fl.px, Fl.py, Fl.pz};
+    for (int e = threadIdx.x; e < items; e += blockDim.x) {
+        const int I = e % Cl.Nx, J = (e / Cl.Nx) % Cl.Ny, K = e / (Cl.Nx * Cl.Ny);
+        const int X[3] = {2 * I, 2 * J, 2 * K};
+        T s = T(0);
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int D[3] = {dx, dy, dz};
+                    int m[3];
+                    bool ok = true;
+                    T w = T(1);
+                    for (int d = 0; d < 3; ++d) {
+                        m[d] = nod_node(X[d], D[d], Nn[d], per[d]);
+                        if (m[d] < 0) ok = false;
+                        if (D[d] != 0) w *= T(0.5);
+                    }
+                    if (ok) s += w * R[((size_t)m[2] * Fl.Ny + m[1]) * Fl.Nx + m[0]];
+                }
+        cF[e] = T(0.125) * s;
+        cP[e] = T(0);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void nb_prolong(const NodLevelT<T>& Fl, T* P, const NodLevelT<T>& Cl, const T* cP) {
+    const int items = Fl.Nx * Fl.Ny * Fl.Nz;
+    const int Nc[3] = {Cl.Nx, Cl.Ny, Cl.Nz}, per[3] = {Cl.px, Cl.py, Cl.pz};
+    for (int e = threadIdx.x; e < items; e += blockDim.x) {
+        const int X[3] = {e % Fl.Nx, (e / Fl.Nx) % Fl.Ny, e / (Fl.Nx * Fl.Ny)};
+        T v = T(0);
+        for (int bz = 0; bz < 2; ++bz)
+            for (int by = 0; by < 2; ++by)
+                for (int bx = 0; bx < 2; ++bx) {
+                    const int B[3] = {bx, by, bz};
+                    int m[3];
+                    bool ok = true;
+                    T w = T(1);
+                    for (int d = 0; d < 3; ++d) {
+                        if ((X[d] & 1) == 0) {
+                            if (B[d]) {
+                                ok = false;
+                                break;
+                            }
+                            m[d] = X[d] >> 1;
+                        } else {
+                            m[d] = B[d] ? (X[d] + 1) >> 1 : (X[d] - 1) >> 1;
+                            if (per[d] && m[d] >= Nc[d]) m[d] -= Nc[d];
+                            w *= T(0.5);
+                        }
+                    }
+                    if (ok) v += w * cP[((size_t)m[2] * Cl.Ny + m[1]) * Cl.Nx + m[0]];
+                }
+        P[e] = P[e] + v;
+    }
+    __syncthreads();
+}
+
+// Coarsest level as the coarse-solve kernel does it: remove mean(f), x =
+// Minv (-f'), remove mean(x), serial sums and row dot products in its order.
+template <typename T>
+__device__ void nb_coarse(int n, const double* __restrict__ minv, const T* F, T* P, double* rhs, double* x,
+                          double* mean) {
+    for (int c = threadIdx.x; c < n; c += blockDim.x) rhs[c] = (double)F[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int c = 0; c < n; ++c) s += rhs[c];
+        *mean = s / n;
+    }
+    __syncthreads();
+    const double m = *mean;
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) rhs[c] = -(rhs[c] - m);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const double* row = minv + (size_t)r * n;
+        double s = 0.0;
+        for (int c = 0; c < n; ++c) s += row[c] * rhs[c];
+        x[r] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int c = 0; c < n; ++c) s += x[c];
+        *mean = s / n;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) P[c] = (T)(x[c] - *mean);
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNodBottomThreads) void k_nod_bottom(NodBottomArgs<T> A) {
+    __shared__ double lds_raw[kNodBottomLds / sizeof(double)];
+    __shared__ double rhs[kCoarseMax], x[kCoarseMax];
+    __shared__ double mean;
+    T* lds = reinterpret_cast<T*>(lds_raw);
+    const int nb = A.nlev;
+    auto nodes = [&](int b) { return (int)A.lev[b].nodes(); };
+    auto Pof = [&](int b) { return lds + A.off[b]; };
+    auto Fof = [&](int b) { return lds + A.off[b] + nodes(b); };
+    auto Rof = [&](int b) { return lds + A.off[b] + 2 * nodes(b); };
+    {   // first bottom level: f from the restriction above, phi = 0
+        const int n0 = nodes(0);
+        for (int e = threadIdx.x; e < n0; e += blockDim.x) {
+            Fof(0)[e] = A.lev[0].f[e];
+            Pof(0)[e] = T(0);
+        }
+        __syncthreads();
+    }
+    for (int b = 0; b + 1 < nb; ++b) {
+        for (int s = 0; s < A.pre; ++s)
+            for (int col = 0; col < 4; ++col) nb_colour(A.lev[b], Pof(b), Fof(b), col);
+        nb_resid(A.lev[b], Pof(b), Fof(b), Rof(b));
+        nb_restrict(A.lev[b], Rof(b), A.lev[b + 1], Pof(b + 1), Fof(b + 1));
+    }
+    nb_coarse(nodes(nb - 1), A.minv, Fof(nb - 1), Pof(nb - 1), rhs, x, &mean);
+    for (int b = nb - 2; b >= 0; --b) {
+        nb_prolong(A.lev[b], Pof(b), A.lev[b + 1], Pof(b + 1));
+        for (int s = 0; s < A.post; ++s)
+            for (int col = 0; col < 4; ++col) nb_colour(A.lev[b], Pof(b), Fof(b), col);
+    }
+    const int n0 = nodes(0);
+    for (int e = threadIdx.x; e < n0; e += blockDim.x) A.lev[0].phi[e] = Pof(0)[e];
+}
+
 // Grid of a point loop over an X x Y x Z box: at most 2048 workgroups (the
 // partial rows), the planes shared out among them.
 inline dim3 point_grid(int X, int Y, int Z) {
@@ -914,6 +1132,7 @@ struct nodal_hierarchy {
     // fused sweeps swap them; with an even number of sweeps a cycle they
     // come back, so one capture serves every cycle of every solve).
     bool graphs_on = true;
+    bool bottom_on = true;      // the coarse levels that fit in LDS run in one workgroup (k_nod_bottom)
     hipStream_t gstream = nullptr;
     hipEvent_t gev = nullptr;
     hipGraphExec_t cycle_exec = nullptr;
@@ -1085,9 +1304,40 @@ hipError_t nod_coarse_solve(int n, const double* minv, const float* f, float* ph
     return launch_coarse_solve_f32(n, minv, f, phi, st, 1);
 }
 
+// First level (>= 1) from which every level's phi, f and r fit in the
+// bottom kernel's LDS, or -1 (no level above the coarsest qualifies).
+template <typename T>
+int nod_bottom_start(const nodal_hierarchy* H) {
+    const NodLevelT<T>* lev = nod_levels<T>(const_cast<nodal_hierarchy*>(H));
+    size_t bytes = 0;
+    int start = -1;
+    for (int l = H->nlev - 1; l >= 1; --l) {
+        bytes += 3 * lev[l].nodes() * sizeof(T);
+        if (bytes > kNodBottomLds || H->nlev - l > kNodBottomMax) break;
+        start = l;
+    }
+    return start < H->nlev - 1 ? start : -1;
+}
+
 // V-cycle from level l in T (the coarsest solve applies the FP64 inverse).
 template <typename T = double>
 int nod_vcycle(nodal_hierarchy* H, int l, hipStream_t st) {
+    if (H->bottom_on && l > 0 && l == nod_bottom_start<T>(H)) {
+        NodBottomArgs<T> a{};
+        a.nlev = H->nlev - l;
+        size_t off = 0;
+        for (int b = 0; b < a.nlev; ++b) {
+            a.lev[b] = nod_levels<T>(H)[l + b];
+            a.off[b] = (int)off;
+            off += 3 * a.lev[b].nodes();
+        }
+        a.minv = H->minv;
+        a.pre = H->p.pre_sweeps;
+        a.post = H->p.post_sweeps;
+        hipLaunchKernelGGL(k_nod_bottom<T>, dim3(1), dim3(kNodBottomThreads), 0, st, a);
+        NHIP(hipGetLastError());
+        return MG_OK;
+    }
     if (l == H->nlev - 1) {
         const NodLevelT<T>& L = nod_levels<T>(H)[l];
         NHIP(nod_coarse_solve((int)L.nodes(), H->minv, L.f, L.phi, st));
@@ -1511,6 +1761,19 @@ int nodal_set_graphs(nodal_handle h, int32_t enable) {
         return MG_ERR_INVALID_ARG;
     }
     h->graphs_on = enable != 0;
+    return MG_OK;
+}
+
+int nodal_set_bottom(nodal_handle h, int32_t enable) {
+    if (!h) {
+        set_error("null handle");
+        return MG_ERR_INVALID_ARG;
+    }
+    h->bottom_on = enable != 0;
+    if (h->cycle_exec) {                 // a captured cycle baked in the other choice
+        hipGraphExecDestroy(h->cycle_exec);
+        h->cycle_exec = nullptr;
+    }
     return MG_OK;
 }
 

@@ -122,6 +122,7 @@ def lib():
         L.nodal_level_copy.argtypes = [vp, i32, i32, vp, i32, vp]
         L.nodal_level_step.argtypes = [vp, i32, i32, i32, vp]
         L.nodal_set_graphs.argtypes = [vp, i32]
+        L.nodal_set_bottom.argtypes = [vp, i32]
         L.nodal_tune_sweep.argtypes = [i32]
         L.mac_project_static.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, S, vp]
         cp, i3 = ctypes.c_char_p, ctypes.POINTER(i32)
@@ -663,6 +664,9 @@ class NodalHierarchy:
 
     def set_graphs(self, enable: bool):
         _check(lib().nodal_set_graphs(self._h, 1 if enable else 0))
+
+    def set_bottom(self, enable: bool):
+        _check(lib().nodal_set_bottom(self._h, 1 if enable else 0))
 
     def set_coefficients(self, rho, beta0_cc, stream=None):
         import torch

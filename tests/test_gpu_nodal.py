@@ -295,3 +295,29 @@ def test_nodal_mixed_fused_size(mp):
     f -= f.mean()
     r = f - O.nodal_apply(prob.n, prob.periodic, prob.dx, sig, out["phi"])
     assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("n,per,prec", [
+    ((64, 64, 64), (True, True, False), "fp64"),
+    ((64, 64, 64), (True, True, False), "mixed"),
+    ((48, 32, 64), (False, False, False), "fp64"),
+    ((32, 32, 32), (True, True, True), "mixed"),
+])
+def test_nodal_bottom_solver_bit_equal(mp, n, per, prec):
+    """The one-workgroup bottom of the V-cycle gives the same bits as the
+    per-level launches it replaces (FP64 and mixed, walls and periodic)."""
+    prob = I.make_nodal_problem(n, seed=61, periodic=per)
+    outs = []
+    for bottom in (True, False):
+        params = mp.make_params(prob.n, prob.dx, prob.periodic, rtol=prob.rtol, precision=prec)
+        H = mp.NodalHierarchy(params)
+        H.set_bottom(bottom)
+        d = mp.nodal_to_device(prob)
+        st = H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi)
+        torch.cuda.synchronize()
+        outs.append((st, {"phi": d.phi.cpu().numpy(), "u": d.uc.cpu().numpy()}))
+        H.close()
+    (s1, o1), (s0, o0) = outs
+    assert s1["status_name"] == "OK" and s1["cycles"] == s0["cycles"] and s1["rel_resid"] == s0["rel_resid"]
+    for k in o1:
+        assert np.array_equal(o1[k], o0[k]), k
