@@ -6,9 +6,11 @@ walls in z, beta0 = exp(-z/0.1), rho = beta0 (1 + 0.01 N(0,1)), S = 0.1 N(0,1)
 with its beta0-weighted mean removed, U ~ N(0,1)), FP64, V(2,2) red-black GS
 cycles to a 1e-10 relative residual.  One step = one whole projection
 (coefficients, right-hand side, V-cycles, velocity correction) of the same
-input; the input velocity is restored from a device copy before each step (a
-device-to-device copy inside the timed region).  Inputs are resident in HBM
-before timing.
+input.  The projection corrects its velocity in place, so every timed step
+gets its own device copy of the input velocity, made before the timed region
+(up to STAGE_CAP_BYTES of copies; beyond that the velocity is restored from
+one device copy before each step, inside the timed region, and the line says
+so).  Inputs are resident in HBM before timing.
 
 Also reported on the same JSON line:
   * roofline: the finest-level fused sweep (the dominant kernel), its launch
@@ -98,31 +100,58 @@ class Restorable:
         self.d.v.copy_(self.v0)
         self.d.w.copy_(self.w0)
 
+    def stage(self, k):
+        """k device copies of the input velocity, one per timed step, or None
+        when they would take more than STAGE_CAP_BYTES."""
+        per = sum(t.numel() * t.element_size() for t in (self.u0, self.v0, self.w0))
+        if k * per > STAGE_CAP_BYTES:
+            return None
+        return [(self.u0.clone(), self.v0.clone(), self.w0.clone()) for _ in range(k)]
 
-def fp64_leg(args, torch, macproj, R):
-    d = R.d
-    H = macproj.Hierarchy(macproj.params_of(R.prob))
 
-    def step():
-        R.restore()
-        return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+# device copies of the input velocity staged for the timed steps (bytes)
+STAGE_CAP_BYTES = 48 << 30
 
-    log(f"{args.n}^3 FP64 warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
+
+def timed_steps(torch, R, solve, k):
+    """k timed projections of R's input by solve(u, v, w): each on its own
+    staged copy of the input velocity when they fit, else on R's velocity
+    restored before each step.  Returns (seconds, per-step latencies in ms,
+    per-step stats, the last step's corrected u, whether copies were staged)."""
+    sets = R.stage(k)
     torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
     lat, stats = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(k):
         ts = time.perf_counter()
-        stats.append(step())          # returns after the solve's final status is on the host
+        if sets is None:
+            R.restore()
+            u, v, w = R.d.u, R.d.v, R.d.w
+        else:
+            u, v, w = sets[i]
+        stats.append(solve(u, v, w))  # returns after the solve's final status is on the host
         lat.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for st in stats:
         assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
-    return H, elapsed, lat, stats
+    return elapsed, lat, stats, u, sets is not None
+
+
+def fp64_leg(args, torch, macproj, R):
+    d = R.d
+    H = macproj.Hierarchy(macproj.params_of(R.prob))
+
+    def solve(u, v, w):
+        return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, u, v, w, d.phi)
+
+    log(f"{args.n}^3 FP64 warmup {args.warmup}")
+    for _ in range(args.warmup):
+        R.restore()
+        solve(d.u, d.v, d.w)
+    log(f"timing {args.steps} steps")
+    elapsed, lat, stats, u_last, staged = timed_steps(torch, R, solve, args.steps)
+    return H, elapsed, lat, stats, u_last, staged
 
 
 def smoother_leg(args, torch, H, R):
@@ -132,7 +161,8 @@ def smoother_leg(args, torch, H, R):
     N = args.n ** 3
     tile = H.sweep_config(0)
     H.set_coefficients(d.rho, d.beta0_cc, d.beta0_edge)    # finest level reads rho, as in the solve
-    H.level_step(0, "smooth", 1)
+    for _ in range(max(50, 2 * args.kernel_reps)):           # steady clocks before timing (an idle GPU
+        H.level_step(0, "smooth", 1)                         # starts slow, e.g. after host-only work)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -204,23 +234,13 @@ def mixed_leg(args, torch, macproj, R, phi64, phi_ref=None):
     d = R.d
     Hm = macproj.Hierarchy(macproj.params_of(R.prob, precision="mixed"))
 
-    def step():
-        R.restore()
-        return Hm.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+    def solve(u, v, w):
+        return Hm.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, u, v, w, d.phi)
 
     log(f"mixed precision {args.mixed_steps} steps")
-    step()
-    torch.cuda.synchronize()
-    lat, mst = [], []
-    tm0 = time.perf_counter()
-    for _ in range(args.mixed_steps):
-        ts = time.perf_counter()
-        mst.append(step())
-        lat.append((time.perf_counter() - ts) * 1e3)
-    torch.cuda.synchronize()
-    tm = time.perf_counter() - tm0
-    for st in mst:
-        assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+    R.restore()
+    solve(d.u, d.v, d.w)
+    tm, lat, mst, _, staged = timed_steps(torch, R, solve, args.mixed_steps)
     diff = float(torch.linalg.norm(d.phi - phi64) / torch.linalg.norm(phi64))
     err = float(torch.linalg.norm(d.phi - phi_ref) / torch.linalg.norm(phi_ref)) if phi_ref is not None else None
     Hm.close()
@@ -228,6 +248,7 @@ def mixed_leg(args, torch, macproj, R, phi64, phi_ref=None):
             "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
             "refinement_steps": mst[-1]["cycles"], "rel_resid": mst[-1]["rel_resid"],
             "ms_smooth": mst[-1]["ms_smooth"], "ms_other": mst[-1]["ms_other"],
+            "input_copies_staged": staged,
             "phi_rel_diff_vs_fp64_gpu": diff, "phi_rel_err_vs_fp64_oracle": err}
 
 
@@ -721,7 +742,7 @@ def main():
     prob = inputs.STEEP_256(n=n)
     R = Restorable(macproj, prob, dev)
 
-    H, elapsed, lat, stats = fp64_leg(args, torch, macproj, R)
+    H, elapsed, lat, stats, u_last, staged = fp64_leg(args, torch, macproj, R)
     value = args.steps / elapsed
     cycles = stats[-1]["cycles"]
     phi64 = R.d.phi.clone()
@@ -737,7 +758,7 @@ def main():
         assert ref["status"] == 0
         phi_ref = torch.from_numpy(ref["phi"]).to(dev)
         parity = {"phi_rel_err_vs_fp64_oracle": float(torch.linalg.norm(phi64 - phi_ref) / torch.linalg.norm(phi_ref)),
-                  "u_rel_err_vs_fp64_oracle": float(np.linalg.norm(R.d.u.cpu().numpy() - ref["u"])
+                  "u_rel_err_vs_fp64_oracle": float(np.linalg.norm(u_last.cpu().numpy() - ref["u"])
                                                     / np.linalg.norm(ref["u"])),
                   "oracle_definition_s": time.perf_counter() - tc,
                   "ms_smooth": stats[-1]["ms_smooth"], "ms_other": stats[-1]["ms_other"]}
@@ -773,7 +794,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}^3 steep-stratification box (H=0.1, periodic x,y, walls z), "
                                f"FP64 V(2,2) red-black GS multigrid to 1e-10",
-                   "n": n, "rtol": 1e-10, "precision": "fp64", "cycles": cycles},
+                   "n": n, "rtol": 1e-10, "precision": "fp64", "cycles": cycles,
+                   "input_copies_staged": staged},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "parity": parity,
         "roofline": roofline,

@@ -32,10 +32,9 @@ __device__ void b_colour(const BottomLevel<T>& lv, T* P, const T* F, int colour)
     const int items = hx * ny * nz;
     const T h2 = lv.h2;
     for (int e = threadIdx.x; e < items; e += blockDim.x) {
-        const int ih = e % hx;
-        const int r = e / hx;
-        const int j = r % ny;
-        const int k = r / ny;
+        int ih, r, j, k;
+        small_divmod(e, hx, r, ih);
+        small_divmod(r, ny, k, j);
         const int i = 2 * ih + ((j + k + colour) & 1);
         if (i >= nx) continue;
         const int im = i > 0 ? i - 1 : nx - 1, ip = i < nx - 1 ? i + 1 : 0;
@@ -89,9 +88,9 @@ __device__ void b_resid_restrict(const BottomLevel<T>& lv, const T* P, const T* 
     const int cx = lv.nx >> 1, cy = lv.ny >> 1, cz = lv.nz >> 1;
     const int items = cx * cy * cz;
     for (int e = threadIdx.x; e < items; e += blockDim.x) {
-        const int I = e % cx;
-        const int J = (e / cx) % cy;
-        const int K = e / (cx * cy);
+        int I, J, K, r;
+        small_divmod(e, cx, r, I);
+        small_divmod(r, cy, K, J);
         T s = T(0);
         for (int dk = 0; dk < 2; ++dk)
             for (int dj = 0; dj < 2; ++dj)
@@ -112,9 +111,9 @@ __device__ void b_prolong(const BottomLevel<T>& lv, T* P, const T* cP) {
     const int nx = lv.nx, ny = lv.ny, nz = lv.nz;
     const int items = nx * ny * nz;
     for (int e = threadIdx.x; e < items; e += blockDim.x) {
-        const int i = e % nx;
-        const int j = (e / nx) % ny;
-        const int k = e / (nx * ny);
+        int i, j, k, r;
+        small_divmod(e, nx, r, i);
+        small_divmod(r, ny, k, j);
         P[e] = P[e] + cP[bidx(i >> 1, j >> 1, k >> 1, nx >> 1, ny >> 1)];
     }
     __syncthreads();

@@ -29,6 +29,33 @@ struct LevelArrays {
     T* bz = nullptr;
 };
 
+// q = a / d, r = a % d for 0 <= a < 2^20 and 1 <= d < 2^11 with d the same
+// across the workgroup (a level size), as the one-workgroup bottom solvers
+// decode their item indices: those run issue-bound on one CU, and an integer
+// division by a run-time value takes about twenty instructions.  A power of
+// two is a shift and a mask; otherwise the FP32 quotient a * rcp(d) (a exact
+// in FP32, relative error below 2^-22, so within 1/4 of a / d) truncated and
+// corrected once by the exact integer remainder.
+__device__ __forceinline__ void small_divmod(int a, int d, int& q, int& r) {
+    if ((d & (d - 1)) == 0) {
+        const int s = __ffs(d) - 1;
+        q = a >> s;
+        r = a & (d - 1);
+        return;
+    }
+    int t = (int)((float)a * __builtin_amdgcn_rcpf((float)d));
+    int m = a - t * d;
+    if (m < 0) {
+        t -= 1;
+        m += d;
+    } else if (m >= d) {
+        t += 1;
+        m -= d;
+    }
+    q = t;
+    r = m;
+}
+
 // Outflow sides of a level (phi = 0 on their boundary faces): for each side
 // (x low, x high, y low, y high, z low, z high) the coefficient of the
 // boundary face of every cell on that side, or null for a periodic or wall

@@ -932,8 +932,10 @@ __device__ void nb_colour(const NodLevelT<T>& L, T* P, const T* F, int col) {
     const int items = L.Nx * hy * hz;
     const T c12 = (T)(12.0 * (L.h * L.h));
     for (int e = threadIdx.x; e < items; e += blockDim.x) {
-        const int I = e % L.Nx, r = e / L.Nx;
-        const int J = 2 * (r % hy) + (col & 1), K = 2 * (r / hy) + (col >> 1);
+        int I, r, jh, kh;
+        small_divmod(e, L.Nx, r, I);
+        small_divmod(r, hy, kh, jh);
+        const int J = 2 * jh + (col & 1), K = 2 * kh + (col >> 1);
         T num, den;
         nod_stencil_fast(L, P, I, J, K, num, den);
         const size_t n = ((size_t)K * L.Ny + J) * L.Nx + I;
@@ -947,7 +949,9 @@ __device__ void nb_resid(const NodLevelT<T>& L, const T* P, const T* F, T* R) {
     const int items = L.Nx * L.Ny * L.Nz;
     const T ih = (T)(12.0 * L.h * L.h);
     for (int e = threadIdx.x; e < items; e += blockDim.x) {
-        const int I = e % L.Nx, J = (e / L.Nx) % L.Ny, K = e / (L.Nx * L.Ny);
+        int I, J, K, r;
+        small_divmod(e, L.Nx, r, I);
+        small_divmod(r, L.Ny, K, J);
         R[e] = F[e] - nb_apply(L, P, I, J, K) / ih;
     }
     __syncthreads();
@@ -958,7 +962,9 @@ __device__ void nb_restrict(const NodLevelT<T>& Fl, const T* R, const NodLevelT<
     const int items = Cl.Nx * Cl.Ny * Cl.Nz;
     const int Nn[3] = {Fl.Nx, Fl.Ny, Fl.Nz}, per[3] = {Fl.px, Fl.py, Fl.pz};
     for (int e = threadIdx.x; e < items; e += blockDim.x) {
-        const int I = e % Cl.Nx, J = (e / Cl.Nx) % Cl.Ny, K = e / (Cl.Nx * Cl.Ny);
+        int I, J, K, r;
+        small_divmod(e, Cl.Nx, r, I);
+        small_divmod(r, Cl.Ny, K, J);
         const int X[3] = {2 * I, 2 * J, 2 * K};
         T s = T(0);
         for (int dz = -1; dz <= 1; ++dz)
@@ -986,7 +992,9 @@ __device__ void nb_prolong(const NodLevelT<T>& Fl, T* P, const NodLevelT<T>& Cl,
     const int items = Fl.Nx * Fl.Ny * Fl.Nz;
     const int Nc[3] = {Cl.Nx, Cl.Ny, Cl.Nz}, per[3] = {Cl.px, Cl.py, Cl.pz};
     for (int e = threadIdx.x; e < items; e += blockDim.x) {
-        const int X[3] = {e % Fl.Nx, (e / Fl.Nx) % Fl.Ny, e / (Fl.Nx * Fl.Ny)};
+        int X[3], r;
+        small_divmod(e, Fl.Nx, r, X[0]);
+        small_divmod(r, Fl.Ny, X[2], X[1]);
         T v = T(0);
         for (int bz = 0; bz < 2; ++bz)
             for (int by = 0; by < 2; ++by)
