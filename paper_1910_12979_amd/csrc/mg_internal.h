@@ -278,6 +278,14 @@ hipError_t launch_correct(const Shape& s, int px, int py, int pz, double h, cons
                           const double* b0e, const double* bx, const double* by,
                           const double* bz, const double* phi, const double* phi_sum,
                           double* u, double* v, double* w, double* phi_out, hipStream_t st);
+// The same correction with the face coefficients recomputed from rho and a
+// plane-parallel beta0 (the values the coefficient kernel stores).
+hipError_t launch_correct_rho(const Shape& s, int px, int py, int pz, double h, const double* rho,
+                              const double* b0c, const double* b0e, const double* phi, const double* phi_sum,
+                              double* u, double* v, double* w, double* phi_out, hipStream_t st);
+// First coarse level's coefficients from level 0's recomputed from rho.
+hipError_t launch_avg_coeff_rho(const Shape& fine, int px, int py, int pz, const double* rho, const double* b0c,
+                                const double* b0e, double* cbx, double* cby, double* cbz, hipStream_t st);
 // Fills and copies (graph-safe replacements for memset / memcpy).
 template <typename T>
 hipError_t launch_fill(T* a, size_t n, T value, hipStream_t st);

@@ -377,6 +377,9 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
                        hipStream_t st, const double* w0, const Radial* rad) {
     Level& L0 = H->lev[0];
     int np = 0;
+    // level 0 from rho with a plane-parallel beta0 (no outflow side): the
+    // first coarse averaging recomputes its coefficients from rho
+    const bool plane_rho = !H->outflow && !(rad && rad->prof);
     if (H->outflow || (rad && rad->prof)) {
         GenArgs g = gen_args(H, rho, b0c, b0e, rad);
         g.S = S;
@@ -397,7 +400,11 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
     for (int l = 0; l + 1 < H->nlev; ++l) {
         Level& F = H->lev[l];
         Level& C = H->lev[l + 1];
-        HIPCHK(launch_avg_coeff<double>(shape_of(F), F.d.bx, F.d.by, F.d.bz, C.d.bx, C.d.by, C.d.bz, st));
+        if (l == 0 && plane_rho)
+            HIPCHK(launch_avg_coeff_rho(shape_of(F), H->px, H->py, H->pz, rho, b0c, b0e, C.d.bx, C.d.by, C.d.bz,
+                                        st));
+        else
+            HIPCHK(launch_avg_coeff<double>(shape_of(F), F.d.bx, F.d.by, F.d.bz, C.d.bx, C.d.by, C.d.bz, st));
         if (F.has_bnd) HIPCHK(launch_avg_bnd<double>(shape_of(F), F.bnd64(), C.bnd_d, st));
     }
     Level& Lc = H->lev[H->nlev - 1];
@@ -1276,8 +1283,8 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         HIPCHK(launch_correct_gen(g, L0.d.phi, H->singular ? H->scal + kSlotPhi * kReduceWidth : nullptr, u, v, w,
                                   phi_out, st));
     } else {
-        HIPCHK(launch_correct(shape_of(L0), H->px, H->py, H->pz, L0.h, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
-                              L0.d.phi, H->scal + kSlotPhi * kReduceWidth, u, v, w, phi_out, st));
+        HIPCHK(launch_correct_rho(shape_of(L0), H->px, H->py, H->pz, L0.h, rho, b0c, b0e, L0.d.phi,
+                                  H->scal + kSlotPhi * kReduceWidth, u, v, w, phi_out, st));
     }
     if (H->ev1) HIPCHK(hipEventRecord(H->ev1, st));
     if (H->singular) {

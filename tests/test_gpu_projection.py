@@ -155,6 +155,59 @@ def _put(H, l, name, a):
     H.level_copy(l, name, torch.from_numpy(np.ascontiguousarray(a)).cuda(), to_hierarchy=True)
 
 
+@pytest.mark.parametrize("shape,per", [
+    ((32, 16, 24), (True, True, False)),
+    ((24, 32, 16), (False, True, True)),
+])
+def test_rho_recomputed_coefficients_equal_stored(mp, shape, per):
+    """The velocity correction and the first coarse averaging recompute the
+    level-0 face coefficients from rho: both must use exactly the values the
+    coefficient kernel stores.  Level 1 equals the stored level 0 averaged
+    over the 2 x 2 fine faces of each coarse face (in the kernel's order), and
+    the corrected U equals U - (b / beta0) grad(phi) formed from the stored
+    coefficients and the returned phi, bit for bit."""
+    prob = I.make_problem(shape, H=0.1, rho_noise=0.2, seed=21, periodic=per)
+    H = mp.Hierarchy(mp.params_of(prob))
+    d = mp.to_device(prob)
+    st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+    torch.cuda.synchronize()
+    assert st["status_name"] == "OK"
+    bx, by, bz = (_get(H, 0, n) for n in ("bx", "by", "bz"))
+    cbx, cby, cbz = (_get(H, 1, n) for n in ("bx", "by", "bz"))
+    H.close()
+    q = 0.25
+    assert np.array_equal(cbx, q * (bx[0::2, 0::2, 0::2] + bx[0::2, 1::2, 0::2] + bx[1::2, 0::2, 0::2]
+                                    + bx[1::2, 1::2, 0::2]))
+    assert np.array_equal(cby, q * (by[0::2, 0::2, 0::2] + by[0::2, 0::2, 1::2] + by[1::2, 0::2, 0::2]
+                                    + by[1::2, 0::2, 1::2]))
+    assert np.array_equal(cbz, q * (bz[0::2, 0::2, 0::2] + bz[0::2, 0::2, 1::2] + bz[0::2, 1::2, 0::2]
+                                    + bz[0::2, 1::2, 1::2]))
+    P = d.phi.cpu().numpy()                       # phi minus its mean, as the correction uses it
+    h = prob.dx
+    nx, ny, nz = prob.n
+    b0c = prob.beta0_cc[:, None, None]
+    b0e = prob.beta0_edge[:nz, None, None]
+    u, v, w = prob.u.copy(), prob.v.copy(), prob.w.copy()
+    lo = 0 if per[0] else 1
+    g = (P - np.roll(P, 1, axis=2)) / h
+    u[:, :, lo:nx] = u[:, :, lo:nx] - (bx / b0c)[:, :, lo:] * g[:, :, lo:]
+    if per[0]:
+        u[:, :, nx] = u[:, :, 0]
+    lo = 0 if per[1] else 1
+    g = (P - np.roll(P, 1, axis=1)) / h
+    v[:, lo:ny, :] = v[:, lo:ny, :] - (by / b0c)[:, lo:, :] * g[:, lo:, :]
+    if per[1]:
+        v[:, ny, :] = v[:, 0, :]
+    lo = 0 if per[2] else 1
+    g = (P - np.roll(P, 1, axis=0)) / h
+    w[lo:nz] = w[lo:nz] - (bz / b0e)[lo:] * g[lo:]
+    if per[2]:
+        w[nz] = w[0]
+    assert np.array_equal(d.u.cpu().numpy(), u)
+    assert np.array_equal(d.v.cpu().numpy(), v)
+    assert np.array_equal(d.w.cpu().numpy(), w)
+
+
 def test_step_coefficients_all_levels(mp):
     prob = I.make_problem((32, 16, 24), H=0.1, rho_noise=0.2, seed=4, dx=1 / 32)
     H, OH = _step_setup(mp, prob)
