@@ -87,34 +87,6 @@ __device__ void block_reduce_row(double v0, double v1, double v2, double v3, dou
 
 __device__ inline bool finite_d(double x) { return isfinite(x); }
 
-// Low-face coefficients of level-0 cell (i, j, k) with a plane-parallel
-// beta0: beta0 at the face over the mean of the two cells' rho, 0 on a wall
-// face.  The coefficient kernel stores exactly these values; the velocity
-// correction and the first coarse averaging recompute them from rho (one
-// array read instead of three) with the same expressions, so the same bits.
-struct RhoFaces {
-    const double* __restrict__ rho;
-    const double* __restrict__ b0c;
-    const double* __restrict__ b0e;
-    int nx, ny, nz, px, py, pz;
-    // rc = rho of cell (i, j, k) at linear index c
-    __device__ double x(int i, size_t c, int k, double rc) const {
-        const double bk = b0c[k];
-        if (i > 0) return qdiv(bk, 0.5 * (rho[c - 1] + rc));
-        return px ? qdiv(bk, 0.5 * (rho[c + (nx - 1)] + rc)) : 0.0;
-    }
-    __device__ double y(int j, size_t c, int k, double rc) const {
-        const double bk = b0c[k];
-        if (j > 0) return qdiv(bk, 0.5 * (rho[c - nx] + rc));
-        return py ? qdiv(bk, 0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc)) : 0.0;
-    }
-    __device__ double z(int k, size_t c, double rc) const {
-        const size_t plane = (size_t)nx * ny;
-        if (k > 0) return qdiv(b0e[k], 0.5 * (rho[c - plane] + rc));
-        return pz ? qdiv(b0e[0], 0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc)) : 0.0;
-    }
-};
-
 // ---------------------------------------------------------------------------
 // Level-0 face coefficients (+ optional right-hand side).  64 x 4 threads per
 // workgroup over (x, y); the workgroups stride over x, y and the planes so
@@ -138,7 +110,6 @@ __device__ void coeff_rhs_body(const CoeffDesc& a, int bxi, int byi, int bzi) {
     double* __restrict__ by = a.by;
     double* __restrict__ bz = a.bz;
     double* __restrict__ f = a.f;
-    const RhoFaces faces{rho, b0c, b0e, nx, ny, nz, px, py, pz};
     double sf = 0.0, saf = 0.0, bad = 0.0, nonfin = 0.0;
     for (int k = bzi; k < nz; k += a.gz)
     for (int j = byi * kPtY + threadIdx.y; j < ny; j += a.gy * kPtY)
@@ -149,11 +120,19 @@ __device__ void coeff_rhs_body(const CoeffDesc& a, int bxi, int byi, int bzi) {
         double bek = b0e[k];
         if (!finite_d(rc) || !finite_d(bk) || !finite_d(bek)) nonfin += 1.0;
         if (!(rc > 0.0) || !(bk > 0.0) || !(bek > 0.0)) bad = 1.0;
-        // low faces x, y, z (periodic z: face 0 uses beta0_edge[0])
-        const double cx = faces.x(i, c, k, rc);
-        const double cy = faces.y(j, c, k, rc);
-        const double cz = faces.z(k, c, rc);
-        const size_t plane = (size_t)nx * ny;
+        // x-low face i
+        double cx;
+        if (i > 0) cx = qdiv(bk, 0.5 * (rho[c - 1] + rc));
+        else cx = px ? qdiv(bk, 0.5 * (rho[c + (nx - 1)] + rc)) : 0.0;
+        // y-low face j
+        double cy;
+        if (j > 0) cy = qdiv(bk, 0.5 * (rho[c - nx] + rc));
+        else cy = py ? qdiv(bk, 0.5 * (rho[c + (size_t)(ny - 1) * nx] + rc)) : 0.0;
+        // z-low face k (periodic: face 0 uses beta0_edge[0])
+        double cz;
+        size_t plane = (size_t)nx * ny;
+        if (k > 0) cz = qdiv(bek, 0.5 * (rho[c - plane] + rc));
+        else cz = pz ? qdiv(b0e[0], 0.5 * (rho[c + (size_t)(nz - 1) * plane] + rc)) : 0.0;
         bx[c] = cx;
         by[c] = cy;
         bz[c] = cz;
@@ -197,8 +176,13 @@ __global__ __launch_bounds__(kBlock) void k_coeff_rhs(CoeffDesc a) {
     coeff_rhs_body<kRhs>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+__device__ void next_scale(const double* res, double* scales, double n);
+
+// Sum of the partial rows into out; with scales, also the next power-of-two
+// scale of the FP32 residual from out[0] (next_scale), in the same launch.
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partials, int nparts,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out, double* __restrict__ scales,
+                                                   double n) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int r = threadIdx.x; r < nparts; r += kBlock) {
         const double* p = partials + (size_t)r * kReduceWidth;
@@ -208,6 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
         a3 += p[3];
     }
     block_reduce_row(a0, a1, a2, a3, out);
+    if (scales && threadIdx.x == 0 && threadIdx.y == 0) next_scale(out, scales, n);   // out written by this thread
 }
 
 // Workgroup b of nb: f -= shift over its strided cells, partial row {sum f^2}.
@@ -258,46 +243,25 @@ __device__ inline void avg_coeff_cell(int nx, int ny, int I, int J, int K, int c
                   bz[cidx(i, j + 1, k, nx, ny)] + bz[cidx(i + 1, j + 1, k, nx, ny)]);
 }
 
-// The first coarse level's coefficients averaged from the level-0 ones
-// recomputed from rho (the stored level-0 arrays hold the same values).
-__global__ void k_avg_coeff_rho(RhoFaces fa, double* __restrict__ cbx, double* __restrict__ cby,
-                                double* __restrict__ cbz) {
-    const int nx = fa.nx, ny = fa.ny;
-    const int cx = nx / 2, cy = ny / 2, cz = fa.nz / 2;
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int J = blockIdx.y * blockDim.y + threadIdx.y;
-    const int K = blockIdx.z * blockDim.z + threadIdx.z;
-    if (I >= cx || J >= cy || K >= cz) return;
-    const int i = 2 * I, j = 2 * J, k = 2 * K;
-    auto X = [&](int ii, int jj, int kk) {
-        const size_t c = cidx(ii, jj, kk, nx, ny);
-        return fa.x(ii, c, kk, fa.rho[c]);
-    };
-    auto Y = [&](int ii, int jj, int kk) {
-        const size_t c = cidx(ii, jj, kk, nx, ny);
-        return fa.y(jj, c, kk, fa.rho[c]);
-    };
-    auto Z = [&](int ii, int jj, int kk) {
-        const size_t c = cidx(ii, jj, kk, nx, ny);
-        return fa.z(kk, c, fa.rho[c]);
-    };
-    const size_t C = cidx(I, J, K, cx, cy);
-    const double q = 0.25;
-    cbx[C] = q * (X(i, j, k) + X(i, j + 1, k) + X(i, j, k + 1) + X(i, j + 1, k + 1));
-    cby[C] = q * (Y(i, j, k) + Y(i + 1, j, k) + Y(i, j, k + 1) + Y(i + 1, j, k + 1));
-    cbz[C] = q * (Z(i, j, k) + Z(i + 1, j, k) + Z(i, j + 1, k) + Z(i + 1, j + 1, k));
-}
-
+// With mx non-null, also the FP32 mirrors of the coarse coefficients (the
+// conversion the separate mirror pass makes).
 template <typename T>
 __global__ void k_avg_coeff(int nx, int ny, int nz, const T* __restrict__ bx, const T* __restrict__ by,
                             const T* __restrict__ bz, T* __restrict__ cbx, T* __restrict__ cby,
-                            T* __restrict__ cbz) {
+                            T* __restrict__ cbz, float* __restrict__ mx, float* __restrict__ my,
+                            float* __restrict__ mz) {
     int cx = nx / 2, cy = ny / 2, cz = nz / 2;
     int I = blockIdx.x * blockDim.x + threadIdx.x;
     int J = blockIdx.y * blockDim.y + threadIdx.y;
     int K = blockIdx.z * blockDim.z + threadIdx.z;
     if (I >= cx || J >= cy || K >= cz) return;
     avg_coeff_cell<T>(nx, ny, I, J, K, cx, cy, bx, by, bz, cbx, cby, cbz);
+    if (mx) {
+        const size_t C = cidx(I, J, K, cx, cy);
+        mx[C] = (float)cbx[C];
+        my[C] = (float)cby[C];
+        mz[C] = (float)cbz[C];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -389,6 +353,35 @@ struct RhoCoeff {
         b[5] = low(2, czp, i, j, kp);
     }
 };
+
+// The first coarse level's coefficients averaged (as k_avg_coeff does) from
+// level 0's recomputed from rho: one array read instead of the three stored
+// ones, which hold the same values.  With mx non-null, also the FP32 mirrors.
+__global__ void k_avg_coeff_rho(RhoCoeff co, double* __restrict__ cbx, double* __restrict__ cby,
+                                double* __restrict__ cbz, float* __restrict__ mx, float* __restrict__ my,
+                                float* __restrict__ mz) {
+    const int nx = co.nx, ny = co.ny;
+    const int cx = nx / 2, cy = ny / 2, cz = co.nz / 2;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= cx || J >= cy || K >= cz) return;
+    const int i = 2 * I, j = 2 * J, k = 2 * K;
+    auto b = [&](int d, int ii, int jj, int kk) { return co.low(d, cidx(ii, jj, kk, nx, ny), ii, jj, kk); };
+    const size_t C = cidx(I, J, K, cx, cy);
+    const double q = 0.25;
+    const double vx = q * (b(0, i, j, k) + b(0, i, j + 1, k) + b(0, i, j, k + 1) + b(0, i, j + 1, k + 1));
+    const double vy = q * (b(1, i, j, k) + b(1, i + 1, j, k) + b(1, i, j, k + 1) + b(1, i + 1, j, k + 1));
+    const double vz = q * (b(2, i, j, k) + b(2, i + 1, j, k) + b(2, i, j + 1, k) + b(2, i + 1, j + 1, k));
+    cbx[C] = vx;
+    cby[C] = vy;
+    cbz[C] = vz;
+    if (mx) {
+        mx[C] = (float)vx;
+        my[C] = (float)vy;
+        mz[C] = (float)vz;
+    }
+}
 
 // (L phi)_c = (sum_f b_f (phi_nb - phi_c)) / h^2, faces in the fixed order.
 template <typename T, typename C>
@@ -571,30 +564,12 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
 // Velocity correction: U <- U - (b/beta0)_f (phi_c - phi_nb)/h on every
 // non-wall face (low faces of each cell), periodic duplicate faces refreshed.
 // ---------------------------------------------------------------------------
-// Face coefficients of the velocity correction: the stored arrays, or the
-// same values recomputed from rho (RhoFaces).
-struct StoredCoef {
-    const double* __restrict__ bx;
-    const double* __restrict__ by;
-    const double* __restrict__ bz;
-    __device__ double x(int, int, int, size_t c) const { return bx[c]; }
-    __device__ double y(int, int, int, size_t c) const { return by[c]; }
-    __device__ double z(int, int, int, size_t c) const { return bz[c]; }
-};
-
-struct RhoCoef {
-    RhoFaces f;
-    __device__ double x(int i, int, int k, size_t c) const { return f.x(i, c, k, f.rho[c]); }
-    __device__ double y(int, int j, int k, size_t c) const { return f.y(j, c, k, f.rho[c]); }
-    __device__ double z(int, int, int k, size_t c) const { return f.z(k, c, f.rho[c]); }
-};
-
-template <class Co>
-__device__ inline void correct_core(int i, int j, int k, int nx, int ny, int nz, int px, int py, int pz, double h,
-                                    const double* __restrict__ b0c, const double* __restrict__ b0e, const Co& co,
-                                    const double* __restrict__ phi, const double* __restrict__ phi_sum,
-                                    double* __restrict__ u, double* __restrict__ v, double* __restrict__ w,
-                                    double* __restrict__ phi_out) {
+__device__ inline void correct_cell(int i, int j, int k, int nx, int ny, int nz, int px, int py, int pz, double h,
+                                    const double* __restrict__ b0c, const double* __restrict__ b0e,
+                                    const double* __restrict__ bx, const double* __restrict__ by,
+                                    const double* __restrict__ bz, const double* __restrict__ phi,
+                                    const double* __restrict__ phi_sum, double* __restrict__ u,
+                                    double* __restrict__ v, double* __restrict__ w, double* __restrict__ phi_out) {
     const size_t N = (size_t)nx * ny * nz;
     const double m = phi_sum[0] / (double)N;
     size_t c = cidx(i, j, k, nx, ny);
@@ -605,7 +580,7 @@ __device__ inline void correct_core(int i, int j, int k, int nx, int ny, int nz,
         int im = i > 0 ? i - 1 : nx - 1;
         double g = (pc - (phi[cidx(im, j, k, nx, ny)] - m)) / h;
         size_t e = ((size_t)k * ny + j) * (nx + 1) + i;
-        double un = u[e] - (co.x(i, j, k, c) / b0c[k]) * g;
+        double un = u[e] - (bx[c] / b0c[k]) * g;
         u[e] = un;
         if (px && i == 0) u[e + nx] = un;
     }
@@ -613,7 +588,7 @@ __device__ inline void correct_core(int i, int j, int k, int nx, int ny, int nz,
         int jm = j > 0 ? j - 1 : ny - 1;
         double g = (pc - (phi[cidx(i, jm, k, nx, ny)] - m)) / h;
         size_t e = ((size_t)k * (ny + 1) + j) * nx + i;
-        double vn = v[e] - (co.y(i, j, k, c) / b0c[k]) * g;
+        double vn = v[e] - (by[c] / b0c[k]) * g;
         v[e] = vn;
         if (py && j == 0) v[e + (size_t)ny * nx] = vn;
     }
@@ -621,33 +596,10 @@ __device__ inline void correct_core(int i, int j, int k, int nx, int ny, int nz,
         int km = k > 0 ? k - 1 : nz - 1;
         double g = (pc - (phi[cidx(i, j, km, nx, ny)] - m)) / h;
         size_t e = (size_t)k * plane + (size_t)j * nx + i;
-        double wn = w[e] - (co.z(i, j, k, c) / b0e[k]) * g;
+        double wn = w[e] - (bz[c] / b0e[k]) * g;
         w[e] = wn;
         if (pz && k == 0) w[e + (size_t)nz * plane] = wn;
     }
-}
-
-__device__ inline void correct_cell(int i, int j, int k, int nx, int ny, int nz, int px, int py, int pz, double h,
-                                    const double* __restrict__ b0c, const double* __restrict__ b0e,
-                                    const double* __restrict__ bx, const double* __restrict__ by,
-                                    const double* __restrict__ bz, const double* __restrict__ phi,
-                                    const double* __restrict__ phi_sum, double* __restrict__ u,
-                                    double* __restrict__ v, double* __restrict__ w, double* __restrict__ phi_out) {
-    correct_core(i, j, k, nx, ny, nz, px, py, pz, h, b0c, b0e, StoredCoef{bx, by, bz}, phi, phi_sum, u, v, w,
-                 phi_out);
-}
-
-// The correction with the level-0 coefficients recomputed from rho.
-__global__ void k_correct_rho(int nx, int ny, int nz, int px, int py, int pz, double h, RhoFaces faces,
-                              const double* __restrict__ phi, const double* __restrict__ phi_sum,
-                              double* __restrict__ u, double* __restrict__ v, double* __restrict__ w,
-                              double* __restrict__ phi_out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int k = blockIdx.z * blockDim.z + threadIdx.z;
-    if (i >= nx || j >= ny || k >= nz) return;
-    correct_core(i, j, k, nx, ny, nz, px, py, pz, h, faces.b0c, faces.b0e, RhoCoef{faces}, phi, phi_sum, u, v, w,
-                 phi_out);
 }
 
 __global__ void k_correct(int nx, int ny, int nz, int px, int py, int pz, double h,
@@ -939,7 +891,7 @@ __global__ void k_dp0_term(int nz, const double* __restrict__ p0c, const double*
     if (k < nz) w0[k] = dp0dt[k] / (g1c[k] * p0c[k]);
 }
 
-__device__ inline void next_scale(const double* res, double* scales, double n) {
+__device__ void next_scale(const double* res, double* scales, double n) {
     const double rms = sqrt(res[0] / n);
     double s = 1.0;
     if (rms > 0.0 && isfinite(rms)) s = ldexp(1.0, -ilogb(rms));
@@ -1019,7 +971,13 @@ hipError_t launch_coeff(const Shape& s, int px, int py, int pz, const double* rh
 }
 
 hipError_t launch_reduce(const double* partials, int nparts, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nparts, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nparts, out, (double*)nullptr, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_scale(const double* partials, int nparts, double* out, double* scales, size_t n,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nparts, out, scales, (double)n);
     return hipGetLastError();
 }
 
@@ -1039,19 +997,21 @@ hipError_t launch_sum(const Shape& s, const double* a, double* partials, int* np
 }
 
 hipError_t launch_avg_coeff_rho(const Shape& fine, int px, int py, int pz, const double* rho, const double* b0c,
-                                const double* b0e, double* cbx, double* cby, double* cbz, hipStream_t st) {
+                                const double* b0e, double* cbx, double* cby, double* cbz, float* const* m32,
+                                hipStream_t st) {
     Launch3 L = cell_launch(fine.nx / 2, fine.ny / 2, fine.nz / 2);
-    const RhoFaces fa{rho, b0c, b0e, fine.nx, fine.ny, fine.nz, px, py, pz};
-    hipLaunchKernelGGL(k_avg_coeff_rho, L.grid, L.block, 0, st, fa, cbx, cby, cbz);
+    RhoCoeff co{rho, b0c, b0e, fine.nx, fine.ny, fine.nz, px, py, pz, Bnd<double>{}, 0};
+    hipLaunchKernelGGL(k_avg_coeff_rho, L.grid, L.block, 0, st, co, cbx, cby, cbz, m32 ? m32[0] : nullptr,
+                       m32 ? m32[1] : nullptr, m32 ? m32[2] : nullptr);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_avg_coeff(const Shape& fine, const T* bx, const T* by, const T* bz, T* cbx, T* cby,
-                            T* cbz, hipStream_t st) {
+                            T* cbz, hipStream_t st, float* const* m32) {
     Launch3 L = cell_launch(fine.nx / 2, fine.ny / 2, fine.nz / 2);
     hipLaunchKernelGGL(k_avg_coeff<T>, L.grid, L.block, 0, st, fine.nx, fine.ny, fine.nz, bx, by, bz, cbx,
-                       cby, cbz);
+                       cby, cbz, m32 ? m32[0] : nullptr, m32 ? m32[1] : nullptr, m32 ? m32[2] : nullptr);
     return hipGetLastError();
 }
 
@@ -1214,16 +1174,6 @@ hipError_t launch_avg_bnd(const Shape& fine, const Bnd<T>& fb, T* const cb[6], h
     return hipGetLastError();
 }
 
-hipError_t launch_correct_rho(const Shape& s, int px, int py, int pz, double h, const double* rho,
-                              const double* b0c, const double* b0e, const double* phi, const double* phi_sum,
-                              double* u, double* v, double* w, double* phi_out, hipStream_t st) {
-    Launch3 L = cell_launch(s.nx, s.ny, s.nz);
-    const RhoFaces fa{rho, b0c, b0e, s.nx, s.ny, s.nz, px, py, pz};
-    hipLaunchKernelGGL(k_correct_rho, L.grid, L.block, 0, st, s.nx, s.ny, s.nz, px, py, pz, h, fa, phi, phi_sum, u,
-                       v, w, phi_out);
-    return hipGetLastError();
-}
-
 hipError_t launch_correct(const Shape& s, int px, int py, int pz, double h, const double* b0c,
                           const double* b0e, const double* bx, const double* by, const double* bz,
                           const double* phi, const double* phi_sum, double* u, double* v, double* w,
@@ -1292,7 +1242,7 @@ hipError_t launch_coeff_to_f32(const double* a, float* b, size_t n, hipStream_t 
 // explicit instantiations
 #define MG_INST(T)                                                                                      \
     template hipError_t launch_avg_coeff<T>(const Shape&, const T*, const T*, const T*, T*, T*, T*,      \
-                                            hipStream_t);                                                \
+                                            hipStream_t, float* const*);                                 \
     template hipError_t launch_rbgs<T>(const Shape&, double, T*, const T*, const T*, const T*, const T*, \
                                        int, hipStream_t, const Bnd<T>*);                                 \
     template hipError_t launch_resid_restrict<T>(const Shape&, double, const T*, const T*, const T*,     \

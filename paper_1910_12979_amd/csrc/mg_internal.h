@@ -227,13 +227,18 @@ hipError_t launch_coeff(const Shape& s, int px, int py, int pz, const double* rh
                         double* bz, double* partials, int* nparts, hipStream_t st);
 // Fixed-order reduction of nparts rows of kReduceWidth doubles into out[0..3].
 hipError_t launch_reduce(const double* partials, int nparts, double* out, hipStream_t st);
+// The same, then the next residual scale from out[0] as launch_next_scale
+// computes it (one launch instead of two).
+hipError_t launch_reduce_scale(const double* partials, int nparts, double* out, double* scales, size_t n,
+                               hipStream_t st);
 // f -= shift; partial row = {sum f^2 (after), 0, 0, 0}.
 hipError_t launch_shift_norm(const Shape& s, double* f, double shift, double* partials,
                              int* nparts, hipStream_t st);
-// Coarse coefficients = mean of the 4 coincident fine faces.
+// Coarse coefficients = mean of the 4 coincident fine faces; with m32
+// (three FP32 arrays), also their FP32 mirrors.
 template <typename T>
 hipError_t launch_avg_coeff(const Shape& fine, const T* bx, const T* by, const T* bz,
-                            T* cbx, T* cby, T* cbz, hipStream_t st);
+                            T* cbx, T* cby, T* cbz, hipStream_t st, float* const* m32 = nullptr);
 // One red-black GS sweep (red then black), in place.
 template <typename T>
 hipError_t launch_rbgs(const Shape& s, double h, T* phi, const T* f, const T* bx,
@@ -278,14 +283,10 @@ hipError_t launch_correct(const Shape& s, int px, int py, int pz, double h, cons
                           const double* b0e, const double* bx, const double* by,
                           const double* bz, const double* phi, const double* phi_sum,
                           double* u, double* v, double* w, double* phi_out, hipStream_t st);
-// The same correction with the face coefficients recomputed from rho and a
-// plane-parallel beta0 (the values the coefficient kernel stores).
-hipError_t launch_correct_rho(const Shape& s, int px, int py, int pz, double h, const double* rho,
-                              const double* b0c, const double* b0e, const double* phi, const double* phi_sum,
-                              double* u, double* v, double* w, double* phi_out, hipStream_t st);
 // First coarse level's coefficients from level 0's recomputed from rho.
 hipError_t launch_avg_coeff_rho(const Shape& fine, int px, int py, int pz, const double* rho, const double* b0c,
-                                const double* b0e, double* cbx, double* cby, double* cbz, hipStream_t st);
+                                const double* b0e, double* cbx, double* cby, double* cbz, float* const* m32,
+                                hipStream_t st);
 // Fills and copies (graph-safe replacements for memset / memcpy).
 template <typename T>
 hipError_t launch_fill(T* a, size_t n, T value, hipStream_t st);

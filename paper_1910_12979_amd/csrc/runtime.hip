@@ -397,29 +397,35 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
     }
     int rc = reduce_to(H, np, kSlotRhs, st);
     if (rc) return rc;
+    // mixed precision: the averaging also writes the FP32 mirrors of every
+    // coarse level's coefficients
+    const bool mixed = H->p.precision == MG_MIXED;
     for (int l = 0; l + 1 < H->nlev; ++l) {
         Level& F = H->lev[l];
         Level& C = H->lev[l + 1];
+        float* const m32[3] = {C.s.bx, C.s.by, C.s.bz};
         if (l == 0 && plane_rho)
             HIPCHK(launch_avg_coeff_rho(shape_of(F), H->px, H->py, H->pz, rho, b0c, b0e, C.d.bx, C.d.by, C.d.bz,
-                                        st));
+                                        mixed ? m32 : nullptr, st));
         else
-            HIPCHK(launch_avg_coeff<double>(shape_of(F), F.d.bx, F.d.by, F.d.bz, C.d.bx, C.d.by, C.d.bz, st));
+            HIPCHK(launch_avg_coeff<double>(shape_of(F), F.d.bx, F.d.by, F.d.bz, C.d.bx, C.d.by, C.d.bz, st,
+                                            mixed ? m32 : nullptr));
         if (F.has_bnd) HIPCHK(launch_avg_bnd<double>(shape_of(F), F.bnd64(), C.bnd_d, st));
     }
     Level& Lc = H->lev[H->nlev - 1];
     const Bnd<double> cb = Lc.bnd64();
     HIPCHK(launch_coarse_setup(shape_of(Lc), Lc.h, Lc.d.bx, Lc.d.by, Lc.d.bz, H->minv, st,
                                Lc.has_bnd ? &cb : nullptr, H->singular ? 1 : 0));
-    if (H->p.precision == MG_MIXED) {
-        // FP32 coefficient mirrors; a fused finest level with a plane-parallel
-        // beta0 recomputes its FP32 coefficients from an FP32 copy of rho, so
-        // its stored ones are not mirrored
+    if (mixed) {
+        // FP32 coefficient mirrors of level 0 (the coarse ones came with the
+        // averaging); a fused finest level with a plane-parallel beta0
+        // recomputes its FP32 coefficients from an FP32 copy of rho, so its
+        // stored ones are not mirrored
         const bool fused0 = H->rho.rho != nullptr && H->p.pre_sweeps >= 1 && H->nlev > 1 &&
                             sweep_fusable<double>(L0.nx, L0.ny, L0.nz);
         for (int l = 0; l < H->nlev; ++l) {
             Level& L = H->lev[l];
-            if (!(l == 0 && fused0)) {
+            if (l == 0 && !fused0) {
                 HIPCHK(launch_coeff_to_f32(L.d.bx, L.s.bx, L.N, st));
                 HIPCHK(launch_coeff_to_f32(L.d.by, L.s.by, L.N, st));
                 HIPCHK(launch_coeff_to_f32(L.d.bz, L.s.bz, L.N, st));
@@ -914,9 +920,7 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
         int np = 0;
         HIPCHK(launch_refine(a, rho0, cfg, &np, s));
         std::swap(L0.d.phi, L0.phi2_d);
-        rc = reduce_to(H, np, kSlotRes, s);
-        if (rc) return rc;
-        HIPCHK(launch_next_scale(H->scal + kSlotRes * kReduceWidth, scales, L0.N, s));
+        HIPCHK(launch_reduce_scale(H->partials, np, H->scal + kSlotRes * kReduceWidth, scales, L0.N, s));
         HIPCHK(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
                               kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, s));
         return (int)MG_OK;
@@ -1053,9 +1057,7 @@ static int solve_level0_boxes_mixed(mg_hierarchy* H, double fnorm, mg_stats* sta
         HIPCHK(launch_box_smooth32(B, L0.h, H->p.post_sweeps, false, L1.s.phi, st));   // prolongation first
         int np = 0;
         HIPCHK(launch_box_refine(B, L0.h, scales, H->partials, &np, st));
-        rc = reduce_to(H, np, kSlotRes, st);
-        if (rc) return rc;
-        HIPCHK(launch_next_scale(H->scal + kSlotRes * kReduceWidth, scales, L0.N, st));
+        HIPCHK(launch_reduce_scale(H->partials, np, H->scal + kSlotRes * kReduceWidth, scales, L0.N, st));
         rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
         if (rc) return rc;
         ++cycles;
@@ -1283,8 +1285,8 @@ static int project_impl(mg_hierarchy* H, const double* rho, const double* b0c, c
         HIPCHK(launch_correct_gen(g, L0.d.phi, H->singular ? H->scal + kSlotPhi * kReduceWidth : nullptr, u, v, w,
                                   phi_out, st));
     } else {
-        HIPCHK(launch_correct_rho(shape_of(L0), H->px, H->py, H->pz, L0.h, rho, b0c, b0e, L0.d.phi,
-                                  H->scal + kSlotPhi * kReduceWidth, u, v, w, phi_out, st));
+        HIPCHK(launch_correct(shape_of(L0), H->px, H->py, H->pz, L0.h, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
+                              L0.d.phi, H->scal + kSlotPhi * kReduceWidth, u, v, w, phi_out, st));
     }
     if (H->ev1) HIPCHK(hipEventRecord(H->ev1, st));
     if (H->singular) {

@@ -160,12 +160,12 @@ def _put(H, l, name, a):
     ((24, 32, 16), (False, True, True)),
 ])
 def test_rho_recomputed_coefficients_equal_stored(mp, shape, per):
-    """The velocity correction and the first coarse averaging recompute the
-    level-0 face coefficients from rho: both must use exactly the values the
-    coefficient kernel stores.  Level 1 equals the stored level 0 averaged
-    over the 2 x 2 fine faces of each coarse face (in the kernel's order), and
-    the corrected U equals U - (b / beta0) grad(phi) formed from the stored
-    coefficients and the returned phi, bit for bit."""
+    """The first coarse averaging recomputes the level-0 face coefficients
+    from rho: it must use exactly the values the coefficient kernel stores.
+    Level 1 equals the stored level 0 averaged over the 2 x 2 fine faces of
+    each coarse face (in the kernel's order), and the corrected U equals
+    U - (b / beta0) grad(phi) formed from the stored coefficients and the
+    returned phi, bit for bit."""
     prob = I.make_problem(shape, H=0.1, rho_noise=0.2, seed=21, periodic=per)
     H = mp.Hierarchy(mp.params_of(prob))
     d = mp.to_device(prob)
