@@ -110,12 +110,14 @@ __device__ void coeff_rhs_body(const CoeffDesc& a, int bxi, int byi, int bzi) {
     double* __restrict__ by = a.by;
     double* __restrict__ bz = a.bz;
     double* __restrict__ f = a.f;
+    float* __restrict__ rho32 = a.rho32;
     double sf = 0.0, saf = 0.0, bad = 0.0, nonfin = 0.0;
     for (int k = bzi; k < nz; k += a.gz)
     for (int j = byi * kPtY + threadIdx.y; j < ny; j += a.gy * kPtY)
     for (int i = bxi * kPtX + threadIdx.x; i < nx; i += a.gx * kPtX) {
         const size_t c = cidx(i, j, k, nx, ny);
         double rc = rho[c];
+        if (rho32) rho32[c] = (float)rc;
         double bk = b0c[k];
         double bek = b0e[k];
         if (!finite_d(rc) || !finite_d(bk) || !finite_d(bek)) nonfin += 1.0;
@@ -950,10 +952,11 @@ int coeff_grid(const Shape& s, int g[3]) {
 hipError_t launch_coeff_rhs(const Shape& s, int px, int py, int pz, double h, const double* rho,
                             const double* b0c, const double* b0e, const double* S, const double* u,
                             const double* v, const double* w, double* bx, double* by, double* bz,
-                            double* f, double* partials, int* nparts, hipStream_t st, const double* w0) {
+                            double* f, double* partials, int* nparts, hipStream_t st, const double* w0,
+                            float* rho32) {
     const dim3 g = point_grid(s);
     const CoeffDesc a{s.nx, s.ny, s.nz, px, py, pz, h, rho, b0c, b0e, S, u, v, w, w0, bx, by, bz, f, partials,
-                      (int)g.x, (int)g.y, (int)g.z, 0};
+                      (int)g.x, (int)g.y, (int)g.z, 0, rho32};
     hipLaunchKernelGGL(k_coeff_rhs<true>, g, dim3(kPtX, kPtY), 0, st, a);
     *nparts = (int)(g.x * g.y * g.z);
     return hipGetLastError();

@@ -214,7 +214,8 @@ hipError_t launch_coeff_rhs(const Shape& s, int px, int py, int pz, double h,
                             const double* rho, const double* b0c, const double* b0e,
                             const double* S, const double* u, const double* v, const double* w,
                             double* bx, double* by, double* bz, double* f,
-                            double* partials, int* nparts, hipStream_t st, const double* w0 = nullptr);
+                            double* partials, int* nparts, hipStream_t st, const double* w0 = nullptr,
+                            float* rho32 = nullptr);
 // beta0 at layer centres and z faces from p0 (faces, centres) and the layer
 // Gamma1 (one workgroup); w0[k] = dp0dt[k] / (Gamma1[k] p0[k]).
 hipError_t launch_beta0_from_p0(int nz, double rho0, const double* p0e, const double* p0c, const double* g1c,
@@ -358,6 +359,7 @@ struct CoeffDesc {
     double* partials;
     int gx, gy, gz;
     int block0;
+    float* rho32;            // nullable: FP32 copy of rho, written on the way
 };
 // A strided loop over N cells with one partial row per block (nb blocks, as
 // the single-problem launch): a -= shift with rows {sum a^2} (shift-norm) or

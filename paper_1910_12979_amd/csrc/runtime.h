@@ -39,6 +39,7 @@ struct mg_hierarchy {
     double* r64 = nullptr;        // FP64 residual (mixed precision)
     float* rho32 = nullptr;       // FP32 copy of rho (mixed precision, fused finest level)
     bool rho32_on = false;        // rho32 holds the current solve's rho
+    bool rho32_fresh = false;     // rho32 written by this call's coefficient kernel
     double* rho_own = nullptr;    // copies made by mg_set_coefficients
     double* b0c_own = nullptr;
     double* b0e_own = nullptr;

@@ -380,6 +380,8 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
     // level 0 from rho with a plane-parallel beta0 (no outflow side): the
     // first coarse averaging recomputes its coefficients from rho
     const bool plane_rho = !H->outflow && !(rad && rad->prof);
+    const bool mixed = H->p.precision == MG_MIXED;
+    H->rho32_fresh = false;
     if (H->outflow || (rad && rad->prof)) {
         GenArgs g = gen_args(H, rho, b0c, b0e, rad);
         g.S = S;
@@ -389,8 +391,12 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
         g.w0 = w0;
         HIPCHK(launch_coeff_rhs_gen(g, &np, st));
     } else if (S) {
+        // mixed precision: the FP32 copy of rho the FP32 finest-level sweeps
+        // read is written on the way
+        float* r32 = mixed ? H->rho32 : nullptr;
         HIPCHK(launch_coeff_rhs(shape_of(L0), H->px, H->py, H->pz, L0.h, rho, b0c, b0e, S, u, v, w, L0.d.bx,
-                                L0.d.by, L0.d.bz, L0.d.f, H->partials, &np, st, w0));
+                                L0.d.by, L0.d.bz, L0.d.f, H->partials, &np, st, w0, r32));
+        H->rho32_fresh = r32 != nullptr;
     } else {
         HIPCHK(launch_coeff(shape_of(L0), H->px, H->py, H->pz, rho, b0c, b0e, L0.d.bx, L0.d.by, L0.d.bz,
                             H->partials, &np, st));
@@ -399,7 +405,6 @@ int build_coefficients(mg_hierarchy* H, const double* rho, const double* b0c, co
     if (rc) return rc;
     // mixed precision: the averaging also writes the FP32 mirrors of every
     // coarse level's coefficients
-    const bool mixed = H->p.precision == MG_MIXED;
     for (int l = 0; l + 1 < H->nlev; ++l) {
         Level& F = H->lev[l];
         Level& C = H->lev[l + 1];
@@ -879,7 +884,8 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
                                     const std::function<void(int, double)>& record, hipStream_t st) {
     Level& L0 = H->lev[0];
     const bool rho0 = H->rho.rho != nullptr;      // else stored finest-level coefficients (radial beta0)
-    if (rho0) HIPCHK(launch_coeff_to_f32(H->rho.rho, H->rho32, L0.N, st));
+    if (rho0 && !H->rho32_fresh) HIPCHK(launch_coeff_to_f32(H->rho.rho, H->rho32, L0.N, st));
+    H->rho32_fresh = false;
     H->rho32_on = rho0;
     HIPCHK(launch_fill<double>(L0.d.phi, L0.N, 0.0, st));
     const double s0 = residual_scale(fnorm, L0.N);           // residual = f while phi = 0
@@ -1315,7 +1321,7 @@ int project(mg_hierarchy* H, const double* rho, const double* b0c, const double*
             double* u, double* v, double* w, double* phi_out, mg_stats* stats, hipStream_t st, const double* w0,
             const Radial* rad) {
     int rc = project_impl(H, rho, b0c, b0e, S, u, v, w, phi_out, stats, st, w0, rad);
-    if (H) H->rho32_on = false;
+    if (H) H->rho32_on = H->rho32_fresh = false;
     // the caller's rho may not outlive the call: later mg_vcycle / step calls
     // use the stored finest-level coefficients (bit-identical values)
     if (H) H->rho = RhoArgs{};
