@@ -10,7 +10,9 @@ input.  The projection corrects its velocity in place, so every timed step
 gets its own device copy of the input velocity, made before the timed region
 (up to STAGE_CAP_BYTES of copies; beyond that the velocity is restored from
 one device copy before each step, inside the timed region, and the line says
-so).  Inputs are resident in HBM before timing.
+so); the other legs below time their solves and batches the same way, except
+the server, whose requests restore their inputs as they are submitted.
+Inputs are resident in HBM before timing.
 
 Also reported on the same JSON line:
   * roofline: the finest-level fused sweep (the dominant kernel), its launch
@@ -43,6 +45,7 @@ import json
 import os
 import sys
 import time
+import types
 
 import numpy as np
 
@@ -63,8 +66,8 @@ SWEEP_KERNEL_BYTES_PER_CELL = 32.0
 # for the sweep source it was taken on (SHA-1 of the files below) and tile.
 SWEEP_SOURCES = ("paper_1910_12979_amd/csrc/sweep.hip", "paper_1910_12979_amd/csrc/sweep.h",
                  "paper_1910_12979_amd/csrc/devmath.h")
-SWEEP_TRAFFIC = {"sha1": "34b2e0186dee335ab053a60ee55838e46b45888d", "tile": [64, 16, 64], "n": 256,
-                 "read": 435224951, "write": 133695480}
+SWEEP_TRAFFIC = {"sha1": "fc96e67fd80568eb986cf4addc8852347269bc2a", "tile": [64, 16, 64], "n": 256,
+                 "read": 435216147, "write": 133695480}
 
 
 def percentile(xs, q):
@@ -111,6 +114,34 @@ class Restorable:
 
 # device copies of the input velocity staged for the timed steps (bytes)
 STAGE_CAP_BYTES = 48 << 30
+
+
+def stage_problems(rs, k):
+    """k sets of the problems' device inputs (namespaces like Restorable.d),
+    each with its own copies of the input velocities, made before a timed
+    region; None when they would take more than STAGE_CAP_BYTES."""
+    per = sum(t.numel() * t.element_size() for r in rs for t in (r.u0, r.v0, r.w0))
+    if k * per > STAGE_CAP_BYTES:
+        return None
+    sets = []
+    for _ in range(k):
+        ds = []
+        for r in rs:
+            d = types.SimpleNamespace(**vars(r.d))
+            d.u, d.v, d.w = r.u0.clone(), r.v0.clone(), r.w0.clone()
+            ds.append(d)
+        sets.append(ds)
+    return sets
+
+
+class CellVelocities(Restorable):
+    """The cell-centred velocity of a nodal problem, restorable and stageable
+    like a face velocity (u, v, w stand for uc, vc, wc)."""
+
+    def __init__(self, d):
+        self.prob = None
+        self.d = types.SimpleNamespace(u=d.uc, v=d.vc, w=d.wc)
+        self.u0, self.v0, self.w0 = d.uc.clone(), d.vc.clone(), d.wc.clone()
 
 
 def timed_steps(torch, R, solve, k):
@@ -337,42 +368,48 @@ def batch_leg(args, torch, macproj, inputs, dev):
     for prec in ("mixed", "fp64"):
         params = [macproj.params_of(r.prob, precision=prec) for r in rs]
 
-        def run_batch():
-            for r in rs:
-                r.restore()
-            code, st = macproj.project_batch(params, [r.d for r in rs])
+        def run_batch(ds=None):
+            if ds is None:                      # restored in place (untimed, or past the staging cap)
+                for r in rs:
+                    r.restore()
+                ds = [r.d for r in rs]
+            code, st = macproj.project_batch(params, ds)
             assert code == 0 and all(s["status_name"] == "OK" and s["rel_resid"] <= 1e-10 for s in st), code
             return st
 
         log(f"batch ({prec}): {args.batch_reps} x project_batch(64)")
         run_batch()
+        sets = stage_problems(rs, args.batch_reps)   # each timed call projects its own input copies
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.batch_reps):
-            st = run_batch()
+        for i in range(args.batch_reps):
+            st = run_batch(sets[i] if sets else None)
         torch.cuda.synchronize()
         tb = (time.perf_counter() - t0) / args.batch_reps
+        staged = sets is not None
+        del sets
         phis = [r.d.phi.clone() for r in rs]
 
         log(f"batch ({prec}): the same 64 problems one by one")
         hs = [macproj.Hierarchy(p) for p in params]
 
-        def run_solo():
-            for r in rs:
-                r.restore()
-            res = []
-            for h, r in zip(hs, rs):
-                d = r.d
-                res.append(h.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi))
-            return res
+        def run_solo(ds=None):
+            if ds is None:
+                for r in rs:
+                    r.restore()
+                ds = [r.d for r in rs]
+            return [h.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+                    for h, d in zip(hs, ds)]
 
         run_solo()
+        sets = stage_problems(rs, args.batch_reps)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.batch_reps):
-            so = run_solo()
+        for i in range(args.batch_reps):
+            so = run_solo(sets[i] if sets else None)
         torch.cuda.synchronize()
         ts = (time.perf_counter() - t0) / args.batch_reps
+        del sets
         identical = all(torch.equal(p, r.d.phi) for p, r in zip(phis, rs))
         for h in hs:
             h.close()
@@ -381,7 +418,7 @@ def batch_leg(args, torch, macproj, inputs, dev):
                      "one_by_one": {"value": 64 / ts, "ms_per_batch": ts * 1e3},
                      "speedup_vs_one_by_one": ts / tb,
                      "cycles_total": sum(s["cycles"] for s in st), "cycles_one_by_one": sum(s["cycles"] for s in so),
-                     "phi_identical_to_one_by_one": identical}
+                     "phi_identical_to_one_by_one": identical, "input_copies_staged": staged}
     del rs
     return out
 
@@ -481,23 +518,18 @@ def full_leg(args, torch, macproj, inputs, dev):
     d = R.d
     H = macproj.Hierarchy(macproj.params_of(prob))
 
-    def step():
-        R.restore()
+    def solve(u, v, w):
         b0c, b0e = macproj.mg_beta0_from_p0(prob.rho0_base, d.p0_edge, d.p0_cc, d.gamma1_cc)
-        return H.mac_project_full(d.rho, b0c, b0e, d.S, d.p0_cc, d.gamma1_cc, d.dp0dt_cc, d.u, d.v, d.w, d.phi)
+        return H.mac_project_full(d.rho, b0c, b0e, d.S, d.p0_cc, d.gamma1_cc, d.dp0dt_cc, u, v, w, d.phi)
 
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.full_steps):
-        st = step()
-    torch.cuda.synchronize()
-    tf = time.perf_counter() - t0
-    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+    R.restore()
+    solve(d.u, d.v, d.w)
+    tf, _, stats, _, staged = timed_steps(torch, R, solve, args.full_steps)
     H.close()
     return {"value": args.full_steps / tf, "unit": "solves/s", "ms_per_step": tf * 1e3 / args.full_steps,
-            "cycles": st["cycles"], "workload": f"{args.n}^3, p0 = exp(-z/0.25), Gamma1 1.67 -> 1.3, "
-                                                "beta0 computed on the device each step, dp0/dt term in f"}
+            "cycles": stats[-1]["cycles"], "input_copies_staged": staged,
+            "workload": f"{args.n}^3, p0 = exp(-z/0.25), Gamma1 1.67 -> 1.3, "
+                        "beta0 computed on the device each step, dp0/dt term in f"}
 
 
 def star_leg(args, torch, macproj, inputs, dev):
@@ -513,21 +545,16 @@ def star_leg(args, torch, macproj, inputs, dev):
         log(f"star box ({prec}): {args.star_steps} steps")
         H = macproj.Hierarchy(macproj.params_of(prob, precision=prec))
 
-        def step():
-            R.restore()
-            return H.mac_project_radial(d.rho, d.beta0_r, prob.dr_base, prob.centre, d.S, d.u, d.v, d.w, d.phi)
+        def solve(u, v, w):
+            return H.mac_project_radial(d.rho, d.beta0_r, prob.dr_base, prob.centre, d.S, u, v, w, d.phi)
 
-        step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.star_steps):
-            st = step()
-        torch.cuda.synchronize()
-        ts = time.perf_counter() - t0
-        assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+        R.restore()
+        solve(d.u, d.v, d.w)
+        ts, _, stats, _, staged = timed_steps(torch, R, solve, args.star_steps)
         H.close()
         out[prec] = {"value": args.star_steps / ts, "unit": "solves/s", "ms_per_step": ts * 1e3 / args.star_steps,
-                     "cycles": st["cycles"], "rel_resid": st["rel_resid"]}
+                     "cycles": stats[-1]["cycles"], "rel_resid": stats[-1]["rel_resid"],
+                     "input_copies_staged": staged}
     return out
 
 
@@ -536,22 +563,17 @@ def nodal_leg(args, torch, macproj, inputs, dev):
     nodes, cell-centred velocities, FP64 and mixed precision."""
     prob = inputs.make_nodal_problem(args.n, H=0.1, rho_noise=0.01, seed=7)
     d = macproj.nodal_to_device(prob, dev)
-    u0, v0, w0 = d.uc.clone(), d.vc.clone(), d.wc.clone()
+    R = CellVelocities(d)
     H = macproj.NodalHierarchy(macproj.make_params(prob.n, prob.dx, prob.periodic))
     log(f"nodal projection: {args.nodal_steps} steps")
 
-    def step():
-        d.uc.copy_(u0); d.vc.copy_(v0); d.wc.copy_(w0)
-        return H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi)
+    def solve(u, v, w):
+        return H.project(d.rho, d.beta0_cc, d.S, u, v, w, d.phi)
 
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.nodal_steps):
-        st = step()
-    torch.cuda.synchronize()
-    tn = time.perf_counter() - t0
-    assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+    R.restore()
+    solve(d.uc, d.vc, d.wc)
+    tn, _, stats, _, staged = timed_steps(torch, R, solve, args.nodal_steps)
+    st = stats[-1]
     # one four-colour Gauss-Seidel sweep of the finest level (one fused launch)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     H.level_step(0, "smooth", 1)
@@ -566,23 +588,18 @@ def nodal_leg(args, torch, macproj, inputs, dev):
     Hm = macproj.NodalHierarchy(macproj.make_params(prob.n, prob.dx, prob.periodic, precision="mixed"))
     log(f"nodal projection, mixed precision: {args.nodal_steps} steps")
 
-    def step_m():
-        d.uc.copy_(u0); d.vc.copy_(v0); d.wc.copy_(w0)
-        return Hm.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi)
+    def solve_m(u, v, w):
+        return Hm.project(d.rho, d.beta0_cc, d.S, u, v, w, d.phi)
 
-    step_m()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.nodal_steps):
-        stm = step_m()
-    torch.cuda.synchronize()
-    tm = time.perf_counter() - t0
-    assert stm["status_name"] == "OK" and stm["rel_resid"] <= 1e-10, stm
+    R.restore()
+    solve_m(d.uc, d.vc, d.wc)
+    tm, _, stats_m, _, _ = timed_steps(torch, R, solve_m, args.nodal_steps)
+    stm = stats_m[-1]
     diff = float(torch.linalg.vector_norm(d.phi - phi64) / torch.linalg.vector_norm(phi64))
     Hm.close()
     nodes = (args.n ** 2) * (args.n + 1)
     return {"value": args.nodal_steps / tn, "unit": "solves/s", "ms_per_step": tn * 1e3 / args.nodal_steps,
-            "cycles": st["cycles"], "rel_resid": st["rel_resid"],
+            "cycles": st["cycles"], "rel_resid": st["rel_resid"], "input_copies_staged": staged,
             "fine_sweep_ms": sweep_ms,
             "fine_sweep_GBs_at_24B_per_node": 24.0 * nodes / (sweep_ms * 1e-3) / 1e9,
             "mixed": {"value": args.nodal_steps / tm, "unit": "solves/s", "ms_per_step": tm * 1e3 / args.nodal_steps,
@@ -602,21 +619,16 @@ def boxes_leg(args, torch, macproj, R):
         H = macproj.Hierarchy(macproj.params_of(R.prob))
         H.set_boxes((b, b, b))
 
-        def step():
-            R.restore()
-            return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+        def solve(u, v, w):
+            return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, u, v, w, d.phi)
 
-        step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.boxes_steps):
-            st = step()
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
+        R.restore()
+        solve(d.u, d.v, d.w)
+        tb, _, stats, _, staged = timed_steps(torch, R, solve, args.boxes_steps)
         H.close()
         out[f"{b}^3 x {(args.n // b) ** 3}"] = {"value": args.boxes_steps / tb, "unit": "solves/s",
-                                               "ms_per_step": tb * 1e3 / args.boxes_steps, "cycles": st["cycles"]}
+                                               "ms_per_step": tb * 1e3 / args.boxes_steps,
+                                               "cycles": stats[-1]["cycles"], "input_copies_staged": staged}
     return out
 
 
@@ -642,24 +654,32 @@ def n512_leg(args, torch, macproj, inputs, dev):
     for prec in ("mixed", "fp64"):
         H = macproj.Hierarchy(macproj.params_of(prob, precision=prec))
 
-        def step():
-            R.restore()
-            return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+        def solve(u, v, w):
+            return H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, u, v, w, d.phi)
 
         log(f"512^3 {prec}: {args.n512_steps} solves")
-        step()
+        R.restore()
+        solve(d.u, d.v, d.w)
+        sets = R.stage(args.n512_steps)            # one input copy per timed solve, made untimed
         torch.cuda.synchronize()
         errs, lat = [], []
         tt = 0.0
-        for _ in range(args.n512_steps):
+        for i in range(args.n512_steps):
+            if sets is None:
+                R.restore()
+                torch.cuda.synchronize()
+                u, v, w = d.u, d.v, d.w
+            else:
+                u, v, w = sets[i]
             ts = time.perf_counter()
-            st = step()
+            st = solve(u, v, w)
             torch.cuda.synchronize()
             lat.append((time.perf_counter() - ts) * 1e3)
             tt += lat[-1] * 1e-3
             assert st["status_name"] == "OK" and st["rel_resid"] <= 1e-10, st
             errs.append(float(torch.linalg.norm(d.phi - phi_ref)) / nref)
         H.close()
+        del sets
         out[prec] = {"value": args.n512_steps / tt, "unit": "solves/s", "ms_per_step": tt * 1e3 / args.n512_steps,
                      "cycles": st["cycles"], "rel_resid": st["rel_resid"],
                      "phi_rel_err_vs_fp64_oracle": errs, "ms_smooth": st["ms_smooth"]}
