@@ -876,10 +876,11 @@ double residual_scale(double norm2_sqrt, size_t n) {
 // V-cycle from zero on the scaled FP64 residual, then one FP64 refinement
 // kernel adds the correction to phi, recomputes r = f - L phi with exact FP64
 // coefficients from rho, writes its per-tile norm rows and the next FP32
-// residual; a one-thread kernel then advances the two device-side scales
-// (the residual's, and the power of two nearest 1/rms(r) for the next).  The
-// FP32 finest-level sweeps recompute their coefficients from an FP32 copy of
-// rho.  Iterations after the first replay a captured graph.
+// residual; the reduction of those rows then also advances the two
+// device-side scales (the residual's, and the power of two nearest
+// 1/rms(r) for the next).  The FP32 finest-level sweeps recompute their
+// coefficients from an FP32 copy of rho (written by the coefficient kernel
+// when it could).  Iterations after the first replay a captured graph.
 static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_out, double* rel_out,
                                     const std::function<void(int, double)>& record, hipStream_t st) {
     Level& L0 = H->lev[0];
