@@ -540,8 +540,23 @@ inline int nod_resid_tiles(const NodLevelT<T>& L) {
     return ((L.Nx + kRTX - 1) / kRTX) * ((L.Ny + kRTY - 1) / kRTY) * ((L.Nz + kRTZ - 1) / kRTZ);
 }
 
-template <typename T, bool kStore, bool kNorm>
-__global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevelT<T> L, double* __restrict__ partials) {
+// The refinement step of a mixed-precision solve in the same pass (kRefine):
+// the window's phi is phi + corr / s (corr the FP32 V-cycle's correction,
+// s = scales[0] the scale its residual carried, a power of two), written out
+// of place for the tile's own nodes (neighbouring tiles read the old phi of
+// their halos), and the residual of the updated phi is written in FP32 times
+// scales[1] (the scale of the previous residual: lagged by one step, as the
+// reduction advances the scales afterwards).
+struct NodRefine {
+    const float* corr;
+    const double* scales;
+    double* phi_out;
+    float* r32;
+};
+
+template <typename T, bool kStore, bool kNorm, bool kRefine = false>
+__global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevelT<T> L, double* __restrict__ partials,
+                                                                NodRefine ra = NodRefine{}) {
     __shared__ __align__(16) T sphi[kRWZ][kRWY][kRWX];
     __shared__ T ssig[kRCZ][kRCY][kRCX];
     const int ntx = (L.Nx + kRTX - 1) / kRTX, nty = (L.Ny + kRTY - 1) / kRTY;
@@ -568,6 +583,8 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevelT<T> L, 
     constexpr int kNT = kRTX * kRTY;
     constexpr int kPN = (kRWX * kRWY * kRWZ + kNT - 1) / kNT, kPC = (kRCX * kRCY * kRCZ + kNT - 1) / kNT;
     T vp[kPN], vs[kPC];
+    const double inv_s = kRefine ? 1.0 / ra.scales[0] : 0.0;     // exact: a power of two
+    const double r_s = kRefine ? ra.scales[1] : 0.0;
 #pragma unroll
     for (int q = 0; q < kPN; ++q) {
         const int e = min(tid + q * kNT, kRWX * kRWY * kRWZ - 1);
@@ -575,7 +592,9 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevelT<T> L, 
         bool ok = true;
         const int I = at(I0 - 1 + x, L.Nx, L.px, ok), J = at(J0 - 1 + y, L.Ny, L.py, ok);
         const int K = at(K0 - 1 + z, L.Nz, L.pz, ok);
-        vp[q] = L.phi[(size_t)K * NxNy + (size_t)J * L.Nx + I];
+        const size_t n = (size_t)K * NxNy + (size_t)J * L.Nx + I;
+        vp[q] = L.phi[n];
+        if (kRefine) vp[q] = vp[q] + (double)ra.corr[n] * inv_s;   // the correction add's expression
         if (!ok) vp[q] = T(0);
     }
 #pragma unroll
@@ -633,6 +652,10 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevelT<T> L, 
             const size_t n = (size_t)K * NxNy + (size_t)J * L.Nx + I;
             const T r = L.f[n] - sum / ih;
             if (kStore) L.r[n] = r;
+            if (kRefine) {
+                ra.phi_out[n] = pn;
+                ra.r32[n] = (float)(r * r_s);
+            }
             if (kNorm) {
                 const double rd = (double)r;
                 if (!isfinite(rd)) nonfin += 1.0;
@@ -850,13 +873,6 @@ __global__ void k_nod_correct(NodLevel L, const double* __restrict__ rho, const 
     u[c] = u[c] - (g0 / h4) / rho[c];
     v[c] = v[c] - (g1 / h4) / rho[c];
     w[c] = w[c] - (g2 / h4) / rho[c];
-}
-
-// phi += e / s for the FP32 correction e of a mixed-precision iteration (s a
-// power of two: the division is exact).
-__global__ void k_nod_add_corr(size_t n, const float* __restrict__ e, double inv_s, double* __restrict__ phi) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        phi[i] = phi[i] + (double)e[i] * inv_s;
 }
 
 __global__ void k_nod_shift_out(size_t n, const double* __restrict__ phi, const double* __restrict__ phi_sum,
@@ -1406,8 +1422,12 @@ int nod_solve_mixed(nodal_hierarchy* H, double fnorm, mg_stats* S_, int* status_
     const size_t NN = L0.nodes();
     for (int l = 0; l < H->nlev; ++l)
         NHIP(launch_coeff_to_f32(H->lev[l].sig, H->lev32[l].sig, H->lev[l].cells(), st));
-    double s = residual_scale(fnorm, NN);
-    NHIP(launch_scale_to_f32(L0.f, M0.f, NN, s, st));        // the residual of phi = 0 is f
+    const double s0 = residual_scale(fnorm, NN);
+    NHIP(launch_scale_to_f32(L0.f, M0.f, NN, s0, st));       // the residual of phi = 0 is f
+    double* scales = H->scal + kSlotScale * kReduceWidth;      // {scale of the FP32 residual, scale for the next}
+    H->host[kSlotScale * kReduceWidth] = s0;
+    H->host[kSlotScale * kReduceWidth + 1] = s0;
+    NHIP(hipMemcpyAsync(scales, H->host + kSlotScale * kReduceWidth, 2 * sizeof(double), hipMemcpyHostToDevice, st));
     const int nt = nod_resid_tiles(L0);
     int status = MG_ERR_NOT_CONVERGED, cycles = 0;
     double rel = 1.0;
@@ -1415,13 +1435,18 @@ int nod_solve_mixed(nodal_hierarchy* H, double fnorm, mg_stats* S_, int* status_
         NHIP(launch_fill<float>(M0.phi, NN, 0.0f, st));
         int rc = nod_vcycle<float>(H, 0, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_nod_add_corr, dim3(nod_partial_blocks(NN)), dim3(kNodBlock), 0, st, NN, M0.phi, 1.0 / s,
-                           L0.phi);
-        hipLaunchKernelGGL((k_nod_resid_tile<double, true, true>), dim3(nt), dim3(kRTX * kRTY), 0, st, L0,
-                           H->partials);
+        // phi += corr / s, r = f - L phi with its norm rows, FP32 r for the
+        // next cycle, in one pass (phi out of place); the reduction then
+        // advances the scales
+        const NodRefine ra{M0.phi, scales, L0.phi2, M0.f};
+        hipLaunchKernelGGL((k_nod_resid_tile<double, false, true, true>), dim3(nt), dim3(kRTX * kRTY), 0, st, L0,
+                           H->partials, ra);
         NHIP(hipGetLastError());
-        rc = nod_reduce(H, nt, kSlotRes, st);
-        if (rc) return rc;
+        std::swap(L0.phi, L0.phi2);
+        NHIP(launch_reduce_scale(H->partials, nt, H->scal + kSlotRes * kReduceWidth, scales, NN, st));
+        NHIP(hipMemcpyAsync(H->host + kSlotRes * kReduceWidth, H->scal + kSlotRes * kReduceWidth,
+                            kReduceWidth * sizeof(double), hipMemcpyDeviceToHost, st));
+        NHIP(hipStreamSynchronize(st));
         ++cycles;
         const double* r = H->host + kSlotRes * kReduceWidth;
         rel = std::sqrt(r[0]) / fnorm;
@@ -1439,8 +1464,6 @@ int nod_solve_mixed(nodal_hierarchy* H, double fnorm, mg_stats* S_, int* status_
             break;
         }
         if (cycles >= H->p.max_cycles) break;
-        s = residual_scale(std::sqrt(r[0]), NN);
-        NHIP(launch_scale_to_f32(L0.r, M0.f, NN, s, st));
     }
     *status_out = status;
     *cycles_out = cycles;
