@@ -602,10 +602,17 @@ int bottom_start(const mg_hierarchy* H) {
             break;
         }
     }
-    if (L < 0 || H->nlev - L > kMaxBottomLevels) return -1;
-    size_t bytes = 0;
-    for (int l = L; l < H->nlev; ++l) bytes += 2 * H->lev[l].N * sizeof(T);
-    return bytes <= kBottomLdsBytes ? L : -1;
+    if (L < 0) return -1;
+    // the first level from there down whose phi and f, with every coarser
+    // level's, fit in the workgroup's LDS (a 24^3 level in FP64 does not:
+    // it keeps one launch per step, and the bottom takes 12^3 and below)
+    for (int b = L; b + 1 < H->nlev; ++b) {
+        if (H->nlev - b > kMaxBottomLevels) continue;
+        size_t bytes = 0;
+        for (int l = b; l < H->nlev; ++l) bytes += 2 * H->lev[l].N * sizeof(T);
+        if (bytes <= kBottomLdsBytes) return b;
+    }
+    return -1;
 }
 
 template <typename T>

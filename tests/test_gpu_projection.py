@@ -398,12 +398,16 @@ def test_graph_replays_match_eager_mixed(mp):
     ((64, 64, 64), (True, True, True), "mixed"),
     ((128, 64, 32), (True, True, False), "mixed"),
     ((64, 32, 32), (True, False, True), "mixed"),
+    ((48, 48, 48), (True, True, False), "fp64"),
+    ((96, 48, 48), (False, True, False), "fp64"),
 ])
 def test_bottom_solver_matches_per_level_launches(mp, shape, per, prec):
     """The one-workgroup bottom of the V-cycle gives the per-level launches'
-    solve bit for bit (same cycles, residual history, phi and U).  The last
-    case's first bottom level (32 x 16 x 16 in FP32) has 4096 cells per
-    colour: past the two per thread whose indices the bottom decodes once."""
+    solve bit for bit (same cycles, residual history, phi and U).  The
+    (64, 32, 32) mixed case has a 32 x 16 x 16 first bottom level in FP32
+    (4096 cells per colour); in the two FP64 cases with 48-cell sides the
+    first level the fused sweep cannot take (24-cell sides) does not fit in
+    the bottom's LDS, which then starts one level lower."""
     prob = I.make_problem(shape, H=0.2, rho_noise=0.05, seed=43, periodic=per)
     res = []
     for on in (False, True):
