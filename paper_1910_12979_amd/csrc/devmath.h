@@ -31,4 +31,11 @@ __device__ __forceinline__ float qdiv(float x, float y) {
     return x * r;
 }
 
+// Divisions of the fused sweep: qdiv in FP64; in FP32 (the sweeps of the
+// inner cycle of a mixed-precision solve, a preconditioner whose error the
+// FP64 refinement removes) the hardware reciprocal times x, within 2 ulp,
+// two instructions fewer per division in a kernel bound by instruction issue.
+__device__ __forceinline__ double pdiv(double x, double y) { return qdiv(x, y); }
+__device__ __forceinline__ float pdiv(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+
 }  // namespace mg

@@ -208,7 +208,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     // low z-face coefficient of plane t from the queue values of planes t-1, t
     auto zface = [&](int t, T q_below, T q_here) -> T {
         if (!kRho) return q_here;
-        const T b = qdiv((T)sb0e[t - zb], half * (q_below + q_here));
+        const T b = pdiv((T)sb0e[t - zb], half * (q_below + q_here));
         const bool wall = kBox ? (t == a.wlo[2] || t == a.whi[2]) : (wrap3(t, nz) == 0 && !a.pz);
         return wall ? T(0) : b;                              // solid wall: no flux
     };
@@ -276,8 +276,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const int lx = lx0 + c;
-            const T cx = qdiv(b0, half * (rl[c] + rc[c]));
-            const T cy = qdiv(b0, half * (srho[b][ly > 0 ? ly - 1 : 0][lx] + rc[c]));
+            const T cx = pdiv(b0, half * (rl[c] + rc[c]));
+            const T cy = pdiv(b0, half * (srho[b][ly > 0 ? ly - 1 : 0][lx] + rc[c]));
             const bool xwall = kBox ? (gxw + c == a.wlo[0] || gxw + c == a.whi[0]) : ((gxw + c == 0) && !a.px);
             const bool ywall = kBox ? (gyw == a.wlo[1] || gyw == a.whi[1]) : (gyw == 0 && !a.py);
             sbx[s][ly][lx] = xwall ? T(0) : cx;
@@ -399,7 +399,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + bzh;
             if constexpr (kBnd) den = den + (rsel ? Gc1 : Gc0);
             const T pin = Rcur;
-            Rcur = qdiv(num - h2 * (rsel ? Fc1 : Fc0), den);
+            Rcur = pdiv(num - h2 * (rsel ? Fc1 : Fc0), den);
             // the update solves den phi_new = num - h^2 f, so f - L phi_in =
             // den (phi_in - phi_new) / h^2 (exact up to rounding)
             if (kNorm) rred = den * (pin - Rcur) * ih2;
@@ -458,7 +458,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             den = den + bzl;
             den = den + bzh;
             if constexpr (kBnd) den = den + (rsel ? Gm1 : Gm0);
-            const T blk = qdiv(num - h2 * (rsel ? Fm1 : Fm0), den);
+            const T blk = pdiv(num - h2 * (rsel ? Fm1 : Fm0), den);
             T* dst = base(a.phi_out, tb) + col;
             if (rsel) st2(dst, Rm, blk);
             else st2(dst, blk, Rm);
