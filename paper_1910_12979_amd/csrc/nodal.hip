@@ -35,6 +35,7 @@
 #include <string>
 
 #include "dense.h"
+#include "devmath.h"
 #include "mg_internal.h"
 #include "runtime.h"
 
@@ -280,7 +281,7 @@ __global__ void k_nod_gs(NodLevelT<T> L, int col) {
     nod_stencil_fast(L, L.phi, I, J, K, num, den);
     const size_t n = nidx(L, I, J, K);
     const T c12 = (T)(12.0 * (L.h * L.h));
-    L.phi[n] = (num - c12 * L.f[n]) / den;
+    L.phi[n] = pdiv(num - c12 * L.f[n], den);
 }
 
 // ---------------------------------------------------------------------------
@@ -429,7 +430,7 @@ __global__ __launch_bounds__((TX + 8) * (TY + 8) / 2) void k_nod_sweep(NodLevelT
                 }
             }
         }
-        return (num - c12 * fv) / den;
+        return pdiv(num - c12 * fv, den);
     };
 
     // rings (window rows / columns) of the four colour stages
@@ -650,7 +651,7 @@ __global__ __launch_bounds__(kRTX * kRTY) void k_nod_resid_tile(NodLevelT<T> L, 
                 }
             }
             const size_t n = (size_t)K * NxNy + (size_t)J * L.Nx + I;
-            const T r = L.f[n] - sum / ih;
+            const T r = L.f[n] - pdiv(sum, ih);
             if (kStore) L.r[n] = r;
             if (kRefine) {
                 ra.phi_out[n] = pn;
@@ -955,7 +956,7 @@ __device__ void nb_colour(const NodLevelT<T>& L, T* P, const T* F, int col) {
         T num, den;
         nod_stencil_fast(L, P, I, J, K, num, den);
         const size_t n = ((size_t)K * L.Ny + J) * L.Nx + I;
-        P[n] = (num - c12 * F[n]) / den;
+        P[n] = pdiv(num - c12 * F[n], den);
     }
     __syncthreads();
 }
@@ -968,7 +969,7 @@ __device__ void nb_resid(const NodLevelT<T>& L, const T* P, const T* F, T* R) {
         int I, J, K, r;
         small_divmod(e, L.Nx, r, I);
         small_divmod(r, L.Ny, K, J);
-        R[e] = F[e] - nb_apply(L, P, I, J, K) / ih;
+        R[e] = F[e] - pdiv(nb_apply(L, P, I, J, K), ih);
     }
     __syncthreads();
 }
