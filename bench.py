@@ -270,7 +270,7 @@ def mixed_leg(args, torch, macproj, R, phi64):
     """The same box in mixed precision; returns the leg's figures and the
     last solve's phi (its error against the oracle is added by the caller)."""
     d = R.d
-    Hm = macproj.Hierarchy(macproj.params_of(R.prob, precision="mixed"))
+    Hm = macproj.Hierarchy(macproj.params_of(R.prob, precision="mixed", inner_cycles=args.inner_cycles))
 
     def solve(u, v, w):
         return Hm.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, u, v, w, d.phi)
@@ -732,6 +732,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--mixed-steps", type=int, default=5)
+    ap.add_argument("--inner-cycles", type=int, default=0,
+                    help="FP32 V-cycles per refinement step of the single-box mixed solves (0: one)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--batch-reps", type=int, default=3, help="0 skips the batch leg")
     ap.add_argument("--autotune", type=int, default=1, help="tune the batch's tile choices on the batch first")

@@ -514,10 +514,10 @@ int launch_group(std::vector<SweepArgs<T>>& args, const std::vector<int>& cfgs, 
     return MG_OK;
 }
 
-// FP32 V-cycle from zero on every problem (all of whose levels above the
-// bottom are fused-sweep levels), the batched form of vcycle<float> with a
-// zero start.
-int multi_vcycle_f32(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st) {
+// FP32 V-cycle on every problem (all of whose levels above the bottom are
+// fused-sweep levels), the batched form of vcycle<float>: from zero, or
+// (zero_start false) from the current finest-level correction.
+int multi_vcycle_f32(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st, bool zero_start) {
     std::vector<int> stop(hs.size());
     int lmax = 0;
     for (size_t i = 0; i < hs.size(); ++i) {
@@ -548,7 +548,7 @@ int multi_vcycle_f32(std::vector<mg_hierarchy*>& hs, Staging& S, hipStream_t st)
         return MG_OK;        // (batched mixed problems have post-sweeps: the prolongation is folded in)
     };
     for (int l = 0; l < lmax; ++l) {
-        int rc = sweeps(l, false, kInZero);
+        int rc = sweeps(l, false, l == 0 && !zero_start ? (int)kInPlain : (int)kInZero);
         if (rc) return rc;
         std::vector<SweepArgs<float>> args;
         std::vector<int> cfgs;
@@ -967,8 +967,8 @@ int Engine::setup_new(std::vector<Job*>& fresh, hipStream_t st) {
 // The launches of one iteration: FP64 problems one V-cycle (pre_done[i]
 // first pre-sweeps already taken from the last speculative sweep) and the
 // next speculative sweep with its residual norm, rows 0.. of the gathered
-// block; mixed problems one FP32 V-cycle from zero and the FP64 refinement,
-// rows after those.
+// block; mixed problems their FP32 V-cycles (the first from zero) and the
+// FP64 refinement, rows after those.
 static int enqueue_iteration(std::vector<mg_hierarchy*>& h64, const std::vector<int>& pre_done,
                              std::vector<mg_hierarchy*>& hm, double* gather, Staging& S, hipStream_t st) {
     if (!h64.empty()) {
@@ -978,8 +978,17 @@ static int enqueue_iteration(std::vector<mg_hierarchy*>& h64, const std::vector<
         if (rc) return rc;
     }
     if (!hm.empty()) {
-        int rc = multi_vcycle_f32(hm, S, st);
+        // each problem's inner_cycles FP32 V-cycles: the first from zero
+        int rc = multi_vcycle_f32(hm, S, st, true);
         if (rc) return rc;
+        for (int c = 1;; ++c) {
+            std::vector<mg_hierarchy*> more;
+            for (mg_hierarchy* H : hm)
+                if (inner_cycles_of(H->p) > c) more.push_back(H);
+            if (more.empty()) break;
+            rc = multi_vcycle_f32(more, S, st, false);
+            if (rc) return rc;
+        }
         rc = multi_refine(hm, gather + h64.size() * kReduceWidth, S, st);
         if (rc) return rc;
     }

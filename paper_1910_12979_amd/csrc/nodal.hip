@@ -1432,10 +1432,13 @@ int nod_solve_mixed(nodal_hierarchy* H, double fnorm, mg_stats* S_, int* status_
     const int nt = nod_resid_tiles(L0);
     int status = MG_ERR_NOT_CONVERGED, cycles = 0;
     double rel = 1.0;
+    const int inner = inner_cycles_of(H->p);
     while (cycles < H->p.max_cycles) {
         NHIP(launch_fill<float>(M0.phi, NN, 0.0f, st));
-        int rc = nod_vcycle<float>(H, 0, st);
-        if (rc) return rc;
+        for (int c = 0; c < inner; ++c) {                 // the FP32 correction: V-cycles from zero
+            int rc = nod_vcycle<float>(H, 0, st);
+            if (rc) return rc;
+        }
         // phi += corr / s, r = f - L phi with its norm rows, FP32 r for the
         // next cycle, in one pass (phi out of place); the reduction then
         // advances the scales

@@ -78,7 +78,8 @@ int validate_params(const mg_params* p) {
             return MG_ERR_INVALID_ARG;
         }
     if (p->pre_sweeps < 0 || p->post_sweeps < 0 || p->max_cycles < 0 || p->max_cycles > 100000 ||
-        !(p->rtol >= 0.0) || (p->precision != MG_FP64 && p->precision != MG_MIXED)) {
+        !(p->rtol >= 0.0) || (p->precision != MG_FP64 && p->precision != MG_MIXED) || p->inner_cycles < 0 ||
+        p->inner_cycles > 8) {
         set_error("invalid solver controls");
         return MG_ERR_INVALID_ARG;
     }
@@ -879,8 +880,9 @@ double residual_scale(double norm2_sqrt, size_t n) {
 }
 
 // Mixed-precision solve on a fusable finest level (Sec. 3 multigrid used as
-// the inner solver of iterative refinement): each iteration runs one FP32
-// V-cycle from zero on the scaled FP64 residual, then one FP64 refinement
+// the inner solver of iterative refinement): each iteration runs
+// inner_cycles FP32 V-cycles (the first from zero) on the scaled FP64
+// residual, then one FP64 refinement
 // kernel adds the correction to phi, recomputes r = f - L phi with exact FP64
 // coefficients from rho, writes its per-tile norm rows and the next FP32
 // residual; the reduction of those rows then also advances the two
@@ -904,9 +906,13 @@ static int solve_level0_mixed_fused(mg_hierarchy* H, double fnorm, int* cycles_o
     HIPCHK(hipMemcpyAsync(scales, H->host + kSlotScale * kReduceWidth, 2 * sizeof(double), hipMemcpyHostToDevice,
                           st));
     const int cfg = sweep_config_for(L0.nx, L0.ny, L0.nz, rho0);
-    auto iteration = [H, &L0, cfg, scales, rho0](hipStream_t s) {
-        int rc = vcycle<float>(H, 0, s, 0, true);
-        if (rc) return rc;
+    const int inner = inner_cycles_of(H->p);
+    auto iteration = [H, &L0, cfg, scales, rho0, inner](hipStream_t s) {
+        // the FP32 correction: V-cycles on the scaled residual, from zero
+        for (int c = 0; c < inner; ++c) {
+            int rc = vcycle<float>(H, 0, s, 0, c == 0);
+            if (rc) return rc;
+        }
         SweepArgs<double> a{};
         a.nx = L0.nx;
         a.ny = L0.ny;
@@ -1063,16 +1069,19 @@ static int solve_level0_boxes_mixed(mg_hierarchy* H, double fnorm, mg_stats* sta
         stats->resid_hist[0] = 1.0;
         stats->hist_len = 1;
     }
+    const int inner = inner_cycles_of(H->p);
     while (status == MG_ERR_NOT_CONVERGED && cycles < H->p.max_cycles) {
-        HIPCHK(launch_box_smooth32(B, L0.h, H->p.pre_sweeps, true, nullptr, st));
-        HIPCHK(launch_box_resid_restrict32(B, L0.h, L1.s.f, L1.s.phi, st));
-        int rc = vcycle<float>(H, 1, st);
-        if (rc) return rc;
-        HIPCHK(launch_box_smooth32(B, L0.h, H->p.post_sweeps, false, L1.s.phi, st));   // prolongation first
+        for (int c = 0; c < inner; ++c) {          // the FP32 correction: V-cycles, the first from zero
+            HIPCHK(launch_box_smooth32(B, L0.h, H->p.pre_sweeps, c == 0, nullptr, st));
+            HIPCHK(launch_box_resid_restrict32(B, L0.h, L1.s.f, L1.s.phi, st));
+            int rc = vcycle<float>(H, 1, st);
+            if (rc) return rc;
+            HIPCHK(launch_box_smooth32(B, L0.h, H->p.post_sweeps, false, L1.s.phi, st));   // prolongation first
+        }
         int np = 0;
         HIPCHK(launch_box_refine(B, L0.h, scales, H->partials, &np, st));
         HIPCHK(launch_reduce_scale(H->partials, np, H->scal + kSlotRes * kReduceWidth, scales, L0.N, st));
-        rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
+        int rc = read_scalars(H, kSlotRes * kReduceWidth, kReduceWidth, st);
         if (rc) return rc;
         ++cycles;
         const double* r = H->host + kSlotRes * kReduceWidth;
@@ -1519,6 +1528,7 @@ void mg_default_params(mg_params* p, int32_t nx, int32_t ny, int32_t nz, double 
     p->rtol = 1e-10;
     p->max_cycles = 100;
     p->precision = MG_FP64;
+    p->inner_cycles = 0;          // the default: two FP32 V-cycles per refinement step
 }
 
 int32_t mg_num_levels_for(const mg_params* p) {

@@ -37,7 +37,8 @@ class MGError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double), ("bc", ctypes.c_int32 * 3),
                 ("pre_sweeps", ctypes.c_int32), ("post_sweeps", ctypes.c_int32),
-                ("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("inner_cycles", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -219,9 +220,11 @@ def bc_code(periodic_d, out_lo, out_hi):
 
 
 def make_params(n, dx, periodic=(True, True, False), pre_sweeps=2, post_sweeps=2, rtol=1e-10,
-                max_cycles=100, precision="fp64", outflow=None) -> Params:
+                max_cycles=100, precision="fp64", outflow=None, inner_cycles=0) -> Params:
     """``outflow``: None or six booleans (x low, x high, ..., z high) marking
-    sides of non-periodic directions as outflow sides (phi = 0)."""
+    sides of non-periodic directions as outflow sides (phi = 0).
+    ``inner_cycles``: FP32 V-cycles per refinement step in mixed precision
+    (0: one)."""
     p = Params()
     nx, ny, nz = n
     lib().mg_default_params(ctypes.byref(p), nx, ny, nz, float(dx))
@@ -231,6 +234,7 @@ def make_params(n, dx, periodic=(True, True, False), pre_sweeps=2, post_sweeps=2
     p.pre_sweeps, p.post_sweeps = pre_sweeps, post_sweeps
     p.rtol, p.max_cycles = float(rtol), int(max_cycles)
     p.precision = MG_MIXED if precision in ("mixed", MG_MIXED) else MG_FP64
+    p.inner_cycles = int(inner_cycles)
     return p
 
 
@@ -478,11 +482,11 @@ def to_device(prob, device="cuda", phi=True):
     return SimpleNamespace(**t)
 
 
-def params_of(prob, precision="fp64", rtol=None, max_cycles=None) -> Params:
+def params_of(prob, precision="fp64", rtol=None, max_cycles=None, inner_cycles=0) -> Params:
     return make_params(prob.n, prob.dx, prob.periodic, prob.pre_sweeps, prob.post_sweeps,
                        prob.rtol if rtol is None else rtol,
                        prob.max_cycles if max_cycles is None else max_cycles, precision,
-                       outflow=getattr(prob, "outflow", None))
+                       outflow=getattr(prob, "outflow", None), inner_cycles=inner_cycles)
 
 
 def problem_struct(params: Params, d, box=None) -> Problem:

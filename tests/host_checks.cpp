@@ -37,6 +37,7 @@ static void fuzz_params(std::mt19937& rng) {
             p.precision = prec(rng);
             p.max_cycles = cyc(rng);
             p.rtol = specials[pick(rng)];
+            p.inner_cycles = sw(rng) * 3;
         }
         const int levels = mg_num_levels_for(&p);
         const size_t bytes = mg_workspace_bytes(&p);
@@ -91,6 +92,11 @@ static void null_paths() {
     mg_params bad = p;
     bad.dx = -1.0;
     CHECK(mac_project_static(&bad, &d, &d, &d, &d, &d, &d, &d, &d, &st, nullptr) == MG_ERR_INVALID_ARG);
+    for (int inner : {-1, 9}) {           // FP32 V-cycles per refinement step: 0..8
+        bad = p;
+        bad.inner_cycles = inner;
+        CHECK(mac_project_static(&bad, &d, &d, &d, &d, &d, &d, &d, &d, &st, nullptr) == MG_ERR_INVALID_ARG);
+    }
     mg_default_params(&bad, 37, 37, 37, 1.0);
     CHECK(mac_project_static(&bad, &d, &d, &d, &d, &d, &d, &d, &d, &st, nullptr) == MG_ERR_BAD_SIZE);
     for (int code = -20; code <= 5; ++code) CHECK(mg_strerror(code) != nullptr && std::strlen(mg_strerror(code)) > 0);

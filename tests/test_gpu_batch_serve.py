@@ -19,8 +19,8 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def solo(mp, prob, precision="fp64"):
-    H = mp.Hierarchy(mp.params_of(prob, precision=precision))
+def solo(mp, prob, precision="fp64", inner_cycles=0):
+    H = mp.Hierarchy(mp.params_of(prob, precision=precision, inner_cycles=inner_cycles))
     d = mp.to_device(prob)
     st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi,
                        allow=(0, -1, -3, -4, -5))
@@ -79,6 +79,28 @@ def test_batch_mixed_precision_matches_single_problem_bitwise(mp):
         assert st["status_name"] == "OK" and st["rel_resid"] <= p.rtol
         assert st["cycles"] == st0["cycles"] and st["rel_resid"] == st0["rel_resid"], (p.n, prec)
         assert same(out, out0), (p.n, prec)
+
+
+def test_batch_mixed_inner_cycles_match_single_problem_bitwise(mp):
+    """Mixed-precision problems with 1, 2 (the default) and 3 FP32 V-cycles
+    per refinement step in one batch: the batch runs each problem's extra
+    V-cycles on the subset that has them, and every problem equals its
+    single-problem solve bit for bit."""
+    probs = [(I.make_problem(64, H=0.1, seed=31), 1), (I.make_problem(64, H=0.1, seed=31), 0),
+             (I.make_problem(48, H=0.2, seed=32), 3), (I.make_problem(32, seed=33), 1),
+             (I.make_problem((128, 64, 32), seed=34, dx=1 / 128), 2)]
+    ref = [solo(mp, p, "mixed", inner_cycles=k) for p, k in probs]
+    devs = [mp.to_device(p) for p, _ in probs]
+    code, stats = mp.project_batch([mp.params_of(p, precision="mixed", inner_cycles=k) for p, k in probs], devs)
+    torch.cuda.synchronize()
+    assert code == 0
+    for (p, k), (st0, out0), st, d in zip(probs, ref, stats, devs):
+        out = {name: getattr(d, name).cpu().numpy() for name in ("phi", "u", "v", "w")}
+        assert st["status_name"] == "OK" and st["rel_resid"] <= p.rtol
+        assert st["cycles"] == st0["cycles"] and st["rel_resid"] == st0["rel_resid"], (p.n, k)
+        assert same(out, out0), (p.n, k)
+    # more V-cycles per step, fewer refinement steps
+    assert stats[0]["cycles"] >= stats[1]["cycles"]
 
 
 def test_batch_isolates_failing_problems(mp):

@@ -33,10 +33,10 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_gpu(mp, prob, box=None, allow=(0,), H=None, precision="fp64"):
+def run_gpu(mp, prob, box=None, allow=(0,), H=None, precision="fp64", inner_cycles=0):
     own = H is None
     if own:
-        H = mp.Hierarchy(mp.params_of(prob, precision=precision))
+        H = mp.Hierarchy(mp.params_of(prob, precision=precision, inner_cycles=inner_cycles))
         if box is not None:
             H.set_boxes(box)
     d = mp.to_device(prob)
@@ -52,7 +52,10 @@ def run_gpu(mp, prob, box=None, allow=(0,), H=None, precision="fp64"):
     return st, out
 
 
-def check_oracle(prob, st, out):
+def check_oracle(prob, st, out, vcycles_per_step=1):
+    """The oracle bar; vcycles_per_step: V-cycles behind one of the solve's
+    cycles (a mixed-precision refinement step runs inner_cycles of them, 2 by
+    default), so that the V-cycle counts compare."""
     ref = O.mac_project(prob, mode="definition")
     alg = O.mac_project(prob)
     assert ref["status"] == 0 and alg["status"] == 0
@@ -75,7 +78,8 @@ def check_oracle(prob, st, out):
         assert rel(out[name], ref[name]) <= max(1e-9, 3 * rel(alg[name], ref[name])), name
     r = f - O.apply_gen(prob.n, sides, prob.dx, coeffs, out["phi"])
     assert np.linalg.norm(r) <= 1.05 * prob.rtol * np.linalg.norm(f)
-    assert abs(st["cycles"] - alg["cycles"]) <= 1
+    k = vcycles_per_step
+    assert abs(st["cycles"] * k - alg["cycles"]) <= max(1, k), (st["cycles"], k, alg["cycles"])
 
 
 def check_single(mp, prob, st, out):
@@ -261,7 +265,7 @@ def test_boxes_mixed_precision_matches_oracle(mp, n, per, box, seed):
     single-box mixed solve."""
     prob = I.make_problem(n, H=0.15, rho_noise=0.05, seed=seed, periodic=per, dx=1.0 / n[0])
     st, out = run_gpu(mp, prob, box=box, precision="mixed")
-    check_oracle(prob, st, out)
+    check_oracle(prob, st, out, vcycles_per_step=2)
     H1 = mp.Hierarchy(mp.params_of(prob, precision="mixed"))
     st1, out1 = run_gpu(mp, prob, H=H1)
     H1.close()
@@ -284,7 +288,20 @@ def test_boxes_mixed_precision_strict_and_radial(mp):
         assert rel(out[k], ref[k]) <= 1e-9, (k, rel(out[k], ref[k]))
     rad = _radial_walls((64, 32, 48), 66)
     st, out = run_gpu(mp, rad, box=(32, 16, 24), precision="mixed")
-    check_oracle(rad, st, out)
+    check_oracle(rad, st, out, vcycles_per_step=2)
+
+
+def test_boxes_mixed_inner_cycles(mp):
+    """Mixed precision on boxes with one FP32 V-cycle per refinement step
+    and with three (the default is two): each at the oracle bar, and more
+    V-cycles per step need no more refinement steps."""
+    prob = I.make_problem((64, 48, 48), H=0.2, rho_noise=0.05, seed=67, dx=1 / 64)
+    res = {}
+    for k in (1, 3):
+        st, out = run_gpu(mp, prob, box=(32, 24, 24), precision="mixed", inner_cycles=k)
+        check_oracle(prob, st, out, vcycles_per_step=k)
+        res[k] = st["cycles"]
+    assert res[3] <= res[1]
 
 
 def test_boxes_mixed_256_full_size(mp):

@@ -29,8 +29,8 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_gpu(mp, prob, precision="fp64", rtol=None, max_cycles=None, allow=(0,)):
-    params = mp.params_of(prob, precision=precision, rtol=rtol, max_cycles=max_cycles)
+def run_gpu(mp, prob, precision="fp64", rtol=None, max_cycles=None, allow=(0,), inner_cycles=0):
+    params = mp.params_of(prob, precision=precision, rtol=rtol, max_cycles=max_cycles, inner_cycles=inner_cycles)
     H = mp.Hierarchy(params)
     d = mp.to_device(prob)
     st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi, allow=allow)
@@ -508,6 +508,18 @@ def test_mixed_precision_shapes(mp, shape, per):
     check_against_definition(prob, st, out)
     st64, _ = run_gpu(mp, prob)
     assert st["cycles"] <= st64["cycles"] + 2, (st["cycles"], st64["cycles"])
+
+
+@pytest.mark.parametrize("inner", [1, 3])
+def test_mixed_precision_inner_cycles(mp, inner):
+    """Mixed precision with 1 and 3 FP32 V-cycles per refinement step (the
+    default is 2) against the exact discrete solution; more V-cycles per
+    step need no more refinement steps."""
+    prob = I.make_problem((64, 32, 48), H=0.2, rho_noise=0.05, seed=37)
+    st, out = run_gpu(mp, prob, precision="mixed", inner_cycles=inner)
+    check_against_definition(prob, st, out)
+    st2, _ = run_gpu(mp, prob, precision="mixed")
+    assert (st["cycles"] >= st2["cycles"]) if inner == 1 else (st["cycles"] <= st2["cycles"])
 
 
 def test_mixed_precision_512_full_size(mp):
