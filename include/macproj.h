@@ -104,7 +104,7 @@ typedef struct {
     int32_t max_cycles;      /* V-cycles (or refinement steps) cap (default 100) */
     int32_t precision;       /* mg_precision */
     int32_t inner_cycles;    /* MG_MIXED: FP32 V-cycles per FP64 refinement step, 1..8 (the first
-                                from zero); 0: the default, 2 */
+                                from zero); 0: the default, 2 (nodal solves: 1) */
 } mg_params;
 
 #define MG_HIST_MAX 128

@@ -56,8 +56,8 @@ __device__ __forceinline__ void small_divmod(int a, int d, int& q, int& r) {
     r = m;
 }
 
-// FP32 V-cycles per refinement step of a mixed-precision solve (0 in the
-// parameters: the default, two).
+// FP32 V-cycles per refinement step of a mixed-precision MAC solve (0 in
+// the parameters: the default, two; the nodal solve's default is one).
 inline int inner_cycles_of(const mg_params& p) { return p.inner_cycles > 0 ? p.inner_cycles : 2; }
 
 // Outflow sides of a level (phi = 0 on their boundary faces): for each side

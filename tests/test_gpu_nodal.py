@@ -21,9 +21,9 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-def run_gpu(mp, prob, rtol=None, allow=(0,), precision="fp64"):
+def run_gpu(mp, prob, rtol=None, allow=(0,), precision="fp64", inner_cycles=0):
     params = mp.make_params(prob.n, prob.dx, prob.periodic, rtol=prob.rtol if rtol is None else rtol,
-                            precision=precision)
+                            precision=precision, inner_cycles=inner_cycles)
     H = mp.NodalHierarchy(params)
     d = mp.nodal_to_device(prob)
     st = H.project(d.rho, d.beta0_cc, d.S, d.uc, d.vc, d.wc, d.phi, allow=allow)
@@ -266,6 +266,16 @@ def test_nodal_mixed_matches_oracle(mp, n, per, seed, force):
     assert st["cycles"] <= st64["cycles"] + 2
     for k in ("phi", "u", "v", "w"):
         assert rel(out[k], out64[k]) <= 1e-9, k
+
+
+def test_nodal_mixed_two_inner_cycles(mp):
+    """Two FP32 V-cycles per refinement step (the nodal default is one):
+    the oracle bar, and no more refinement steps than with one."""
+    prob = I.make_nodal_problem((48, 32, 40), seed=49, periodic=(True, True, False))
+    st, out = run_gpu(mp, prob, precision="mixed", inner_cycles=2)
+    check(prob, st, out)
+    st1, _ = run_gpu(mp, prob, precision="mixed")
+    assert st["cycles"] <= st1["cycles"]
 
 
 @pytest.mark.parametrize("n,per,seed", [((32, 32, 32), (True, True, False), 51), ((24, 16, 32), (False, False, False), 52)])
