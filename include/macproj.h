@@ -270,10 +270,11 @@ int mg_map_radial(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t nr, dou
  * approximate: L is not D sigma G, so the corrected velocity meets the
  * constraint to truncation error.  Boundaries: periodic (node n is node 0) or
  * solid wall (natural: wall nodes are unknowns).  Precision: FP64, or
- * MG_MIXED: each iteration one FP32 V-cycle from zero on the FP64 residual
- * scaled by the power of two nearest 1/rms(r), the FP32 correction added to
- * the FP64 phi (divided by that power of two, exactly), r = f - L phi and
- * its norm in FP64, the same stop test; stats.cycles counts iterations.
+ * MG_MIXED: each iteration p.inner_cycles FP32 V-cycles (default one here;
+ * the first from zero) on the FP64 residual scaled by a power of two near
+ * 1/rms(r), the FP32 correction added to the FP64 phi (divided by that
+ * power of two, exactly), r = f - L phi and its norm in FP64, the same stop
+ * test; stats.cycles counts iterations.
  * Layout: rho, S, uc, vc, wc (nz, ny, nx) cells; beta0_cc (nz); phi nodes
  * (Nz, Ny, Nx) with N = n (periodic) or n + 1 (walls), C order.  Device
  * pointers, caller-owned. */

@@ -710,6 +710,7 @@ std::vector<uintptr_t> round_key(const std::vector<mg_hierarchy*>& h64, const st
         k.push_back((uintptr_t)H->nlev);
         k.push_back((uintptr_t)H->p.pre_sweeps);
         k.push_back((uintptr_t)H->p.post_sweeps);
+        k.push_back((uintptr_t)inner_cycles_of(H->p));
         k.push_back((uintptr_t)H->bottom_on);
         k.push_back((uintptr_t)H->rho.rho);
         k.push_back((uintptr_t)H->rho.b0c);

@@ -766,6 +766,7 @@ static std::vector<uintptr_t> graph_key(const mg_hierarchy* H, int kind) {
     k.push_back((uintptr_t)H->rho.b0e);
     k.push_back((uintptr_t)H->p.pre_sweeps);
     k.push_back((uintptr_t)H->p.post_sweeps);
+    k.push_back((uintptr_t)inner_cycles_of(H->p));
     k.push_back((uintptr_t)sweep_tune_epoch());
     k.push_back((uintptr_t)H->bottom_on);
     for (int l = 0; l < H->nlev; ++l) {

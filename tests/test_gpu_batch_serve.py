@@ -103,6 +103,25 @@ def test_batch_mixed_inner_cycles_match_single_problem_bitwise(mp):
     assert stats[0]["cycles"] >= stats[1]["cycles"]
 
 
+def test_batch_reuses_pooled_states_with_other_inner_cycles(mp):
+    """Back-to-back batches of the same shapes reuse the pooled states and
+    their captured rounds; a batch that asks for another number of FP32
+    V-cycles per refinement step must run that number, not replay the
+    previous batch's rounds."""
+    probs = [I.make_problem(64, H=0.1, seed=41), I.make_problem(64, H=0.2, seed=42)]
+    for k in (1, 3, 1):
+        ref = [solo(mp, p, "mixed", inner_cycles=k) for p in probs]
+        devs = [mp.to_device(p) for p in probs]
+        code, stats = mp.project_batch([mp.params_of(p, precision="mixed", inner_cycles=k) for p in probs], devs)
+        torch.cuda.synchronize()
+        assert code == 0
+        for p, (st0, out0), st, d in zip(probs, ref, stats, devs):
+            out = {name: getattr(d, name).cpu().numpy() for name in ("phi", "u", "v", "w")}
+            assert st["status_name"] == "OK"
+            assert st["cycles"] == st0["cycles"] and st["rel_resid"] == st0["rel_resid"], k
+            assert same(out, out0), k
+
+
 def test_batch_isolates_failing_problems(mp):
     good = I.make_problem(32, seed=11)
     bad_rhs = I.make_problem(32, seed=12); bad_rhs.w[0, 3, 3] = 1.0

@@ -522,6 +522,33 @@ def test_mixed_precision_inner_cycles(mp, inner):
     assert (st["cycles"] >= st2["cycles"]) if inner == 1 else (st["cycles"] <= st2["cycles"])
 
 
+def test_mixed_inner_cycles_changed_on_a_live_hierarchy(mp):
+    """mg_set_params changing the FP32 V-cycles per refinement step between
+    solves: the captured iteration graph is not reused, and each solve
+    equals a fresh hierarchy's with the same count bit for bit."""
+    prob = I.make_problem(64, H=0.15, rho_noise=0.05, seed=38)
+
+    def solve(H):
+        d = mp.to_device(prob)
+        st = H.mac_project(d.rho, d.beta0_cc, d.beta0_edge, d.S, d.u, d.v, d.w, d.phi)
+        torch.cuda.synchronize()
+        return st, {k: getattr(d, k).cpu().numpy() for k in ("phi", "u", "v", "w")}
+
+    live = mp.Hierarchy(mp.params_of(prob, precision="mixed"))
+    try:
+        for k in (0, 1, 3, 0):
+            live.set_params(mp.params_of(prob, precision="mixed", inner_cycles=k))
+            for _ in range(2):                    # the second solve replays the captured iteration
+                st, out = solve(live)
+                fresh = mp.Hierarchy(mp.params_of(prob, precision="mixed", inner_cycles=k))
+                st0, out0 = solve(fresh)
+                fresh.close()
+                assert st["cycles"] == st0["cycles"] and st["rel_resid"] == st0["rel_resid"], k
+                assert same_out(out, out0), k
+    finally:
+        live.close()
+
+
 def test_mixed_precision_512_full_size(mp):
     """The 512^3 mixed-precision box (FP32 cycles, FP64 refinement): phi
     within 1e-9 of the FP64 oracle's exact discrete solution (definition
