@@ -286,24 +286,24 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     };
     // LDS before the first step (t = z0-1): phi_in of z0-1, coefficients of
     // z0-1, rho of z0
-    sphi[(z0 - 1) & 1][ly][lx0] = Pp0;
-    sphi[(z0 - 1) & 1][ly][lx0 + 1] = Pp1;
+    sphi[0][ly][lx0] = Pp0;
+    sphi[0][ly][lx0 + 1] = Pp1;
     if (kRho) {
-        srho[(z0 - 1) & 1][ly][lx0] = Rp0;
-        srho[(z0 - 1) & 1][ly][lx0 + 1] = Rp1;
+        srho[0][ly][lx0] = Rp0;
+        srho[0][ly][lx0 + 1] = Rp1;
         __syncthreads();                               // beta0 and rho of z0-1 staged
-        rho_coeffs(z0 - 1, (z0 - 1 + 3) % 3, (z0 - 1) & 1, Rp0, Rp1);
-        srho[z0 & 1][ly][lx0] = Rq0;
-        srho[z0 & 1][ly][lx0 + 1] = Rq1;
+        rho_coeffs(z0 - 1, 0, 0, Rp0, Rp1);
+        srho[1][ly][lx0] = Rq0;
+        srho[1][ly][lx0 + 1] = Rq1;
     } else {
         int tw = wrap3(z0 - 1, nz);
         T t0, t1;
         ld2(base(a.bx, tw) + col, t0, t1);
-        sbx[(z0 - 1 + 3) % 3][ly][lx0] = t0;
-        sbx[(z0 - 1 + 3) % 3][ly][lx0 + 1] = t1;
+        sbx[0][ly][lx0] = t0;
+        sbx[0][ly][lx0 + 1] = t1;
         ld2(base(a.by, tw) + col, t0, t1);
-        sby[(z0 - 1 + 3) % 3][ly][lx0] = t0;
-        sby[(z0 - 1 + 3) % 3][ly][lx0 + 1] = t1;
+        sby[0][ly][lx0] = t0;
+        sby[0][ly][lx0 + 1] = t1;
     }
     T bm0 = T(0), bm1 = T(0), bc0 = T(0), bc1 = T(0);
     T bp0 = zface(z0 - 1, Rc0, Rp0), bp1 = zface(z0 - 1, Rc1, Rp1);   // low face of plane z0-1
@@ -339,8 +339,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const size_t ccols = kBox ? (size_t)(a.gn[0] >> 1) * (a.gn[1] >> 1) : (size_t)(nx >> 1) * (ny >> 1);
     const size_t cc = kBox ? (size_t)((a.go[1] + gyw - oy) >> 1) * (a.gn[0] >> 1) + ((a.go[0] + gxw - ox) >> 1)
                            : (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
-    // m3 = t mod 3 (t >= -1), carried by the caller instead of divided out
-    auto step = [&](int t, int m3, Fly& X) {
+    // Step j = t - (z0 - 1) of the march.  The LDS planes are chosen by j
+    // mod 2 and j mod 3 (any fixed relabelling of the buffers serves), which
+    // the caller passes as a compile-time constant J = j mod 6: every LDS
+    // address is then a constant offset, and the z windows rotate through
+    // registers without copies over the six steps of the unrolled loop.
+    auto step = [&](int t, auto J, Fly& X) {
+        constexpr int m3 = decltype(J)::value % 3;
         // 0. slide the z window, taking in the set issued two steps ago:
         //    phi[t+1], rho[t+2] (or bz[t+2]), f[t], bx/by[t+1]; then re-issue
         Fm0 = Fc0; Fm1 = Fc1;
@@ -364,8 +369,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             cy0 = X.y0; cy1 = X.y1;
         }
         issue(t, X);                             // consumed by step t+2
-        const int s_t = m3, s_p = m3 == 2 ? 0 : m3 + 1, s_m = m3 == 0 ? 2 : m3 - 1;
-        const int cur = t & 1, nxt = (t + 1) & 1;
+        constexpr int s_t = m3, s_p = (m3 + 1) % 3, s_m = (m3 + 2) % 3;
+        constexpr int cur = decltype(J)::value & 1, nxt = cur ^ 1;
         const int rsel = (gy + t) & 1;           // red cell of the pair at plane t (black at t-1)
         // 1. x/y coefficients of plane t+1 (read by the next step)
         if (t + 1 <= z1) {
@@ -427,7 +432,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         // 3. (kRR) restriction of plane t-1, whose residuals the previous step wrote
         const int tb = t - 1;
         if (kRR && tb >= z0 && tb < z1 && writes && rrow) {
-            const int pb = tb & 1;
+            constexpr int pb = nxt;             // plane t-1
             if (((tb - z0) & 1) == 0) racc = T(0);
             racc = racc + sR[pb][ly][lx0];
             racc = racc + sR[pb][ly][lx0 + 1];
@@ -441,7 +446,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         }
         // 4. black update at plane t-1 on the tile; write the pair of plane t-1
         if (kGS && tb >= z0 && writes) {
-            const int sb = tb & 1;
+            constexpr int sb = nxt;             // plane t-1
             const int lxb = lx0 + rsel;
             const T bxl = sbx[s_m][ly][lxb], bxh = sbx[s_m][ly][lxb + 1];
             const T byl = sby[s_m][ly][lxb], byh = sby[s_m][ly + 1][lxb];
@@ -476,15 +481,21 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         }
         __syncthreads();
     };
+    using std::integral_constant;
     int t = z0 - 1;
-    int m3 = (t + 3) % 3;
-    for (; t + 1 <= z1; t += 2) {
-        step(t, m3, A);
-        m3 = m3 == 2 ? 0 : m3 + 1;
-        step(t + 1, m3, B);
-        m3 = m3 == 2 ? 0 : m3 + 1;
+    for (; t + 5 <= z1; t += 6) {
+        step(t, integral_constant<int, 0>{}, A);
+        step(t + 1, integral_constant<int, 1>{}, B);
+        step(t + 2, integral_constant<int, 2>{}, A);
+        step(t + 3, integral_constant<int, 3>{}, B);
+        step(t + 4, integral_constant<int, 4>{}, A);
+        step(t + 5, integral_constant<int, 5>{}, B);
     }
-    if (t <= z1) step(t, m3, A);
+    if (t <= z1) step(t, integral_constant<int, 0>{}, A);
+    if (t + 1 <= z1) step(t + 1, integral_constant<int, 1>{}, B);
+    if (t + 2 <= z1) step(t + 2, integral_constant<int, 2>{}, A);
+    if (t + 3 <= z1) step(t + 3, integral_constant<int, 3>{}, B);
+    if (t + 4 <= z1) step(t + 4, integral_constant<int, 4>{}, A);
     if (kNorm || kIR) {
         // fixed-order block reduction into this tile's partial row (in the
         // red-value buffer, free after the last step's barrier)
