@@ -340,12 +340,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     const size_t cc = kBox ? (size_t)((a.go[1] + gyw - oy) >> 1) * (a.gn[0] >> 1) + ((a.go[0] + gxw - ox) >> 1)
                            : (size_t)(gyw >> 1) * (nx >> 1) + (gxw >> 1);
     // Step j = t - (z0 - 1) of the march.  The LDS planes are chosen by j
-    // mod 2 and j mod 3 (any fixed relabelling of the buffers serves), which
-    // the caller passes as a compile-time constant J = j mod 6: every LDS
-    // address is then a constant offset, and the z windows rotate through
-    // registers without copies over the six steps of the unrolled loop.
+    // mod 2 and j mod 3 (any fixed relabelling of the buffers serves) from
+    // J = j mod 6, which the six-step unrolled loop passes as a compile-time
+    // constant: every LDS address is then a constant offset, and the z
+    // windows rotate through registers without copies.  The variants that
+    // would spill unrolled pass J at run time: the outflow ones (kBnd) and
+    // the FP64 64x8 ones, which are held to 128 registers.
     auto step = [&](int t, auto J, Fly& X) {
-        constexpr int m3 = decltype(J)::value % 3;
+        const int jj = static_cast<int>(J);
+        const int m3 = jj % 3;
         // 0. slide the z window, taking in the set issued two steps ago:
         //    phi[t+1], rho[t+2] (or bz[t+2]), f[t], bx/by[t+1]; then re-issue
         Fm0 = Fc0; Fm1 = Fc1;
@@ -369,8 +372,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
             cy0 = X.y0; cy1 = X.y1;
         }
         issue(t, X);                             // consumed by step t+2
-        constexpr int s_t = m3, s_p = (m3 + 1) % 3, s_m = (m3 + 2) % 3;
-        constexpr int cur = decltype(J)::value & 1, nxt = cur ^ 1;
+        const int s_t = m3, s_p = m3 == 2 ? 0 : m3 + 1, s_m = m3 == 0 ? 2 : m3 - 1;
+        const int cur = jj & 1, nxt = cur ^ 1;
         const int rsel = (gy + t) & 1;           // red cell of the pair at plane t (black at t-1)
         // 1. x/y coefficients of plane t+1 (read by the next step)
         if (t + 1 <= z1) {
@@ -432,7 +435,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         // 3. (kRR) restriction of plane t-1, whose residuals the previous step wrote
         const int tb = t - 1;
         if (kRR && tb >= z0 && tb < z1 && writes && rrow) {
-            constexpr int pb = nxt;             // plane t-1
+            const int pb = nxt;                 // plane t-1
             if (((tb - z0) & 1) == 0) racc = T(0);
             racc = racc + sR[pb][ly][lx0];
             racc = racc + sR[pb][ly][lx0 + 1];
@@ -446,7 +449,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
         }
         // 4. black update at plane t-1 on the tile; write the pair of plane t-1
         if (kGS && tb >= z0 && writes) {
-            constexpr int sb = nxt;             // plane t-1
+            const int sb = nxt;                 // plane t-1
             const int lxb = lx0 + rsel;
             const T bxl = sbx[s_m][ly][lxb], bxh = sbx[s_m][ly][lxb + 1];
             const T byl = sby[s_m][ly][lxb], byh = sby[s_m][ly + 1][lxb];
@@ -483,19 +486,30 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     };
     using std::integral_constant;
     int t = z0 - 1;
-    for (; t + 5 <= z1; t += 6) {
-        step(t, integral_constant<int, 0>{}, A);
-        step(t + 1, integral_constant<int, 1>{}, B);
-        step(t + 2, integral_constant<int, 2>{}, A);
-        step(t + 3, integral_constant<int, 3>{}, B);
-        step(t + 4, integral_constant<int, 4>{}, A);
-        step(t + 5, integral_constant<int, 5>{}, B);
+    constexpr bool kRunPhase = kBnd || (sizeof(T) == 8 && TX == 64 && TY == 8);
+    if constexpr (kRunPhase) {
+        int j = 0;
+        for (; t + 1 <= z1; t += 2) {
+            step(t, j, A);
+            step(t + 1, j + 1, B);
+            j = j == 4 ? 0 : j + 2;
+        }
+        if (t <= z1) step(t, j, A);
+    } else {
+        for (; t + 5 <= z1; t += 6) {
+            step(t, integral_constant<int, 0>{}, A);
+            step(t + 1, integral_constant<int, 1>{}, B);
+            step(t + 2, integral_constant<int, 2>{}, A);
+            step(t + 3, integral_constant<int, 3>{}, B);
+            step(t + 4, integral_constant<int, 4>{}, A);
+            step(t + 5, integral_constant<int, 5>{}, B);
+        }
+        if (t <= z1) step(t, integral_constant<int, 0>{}, A);
+        if (t + 1 <= z1) step(t + 1, integral_constant<int, 1>{}, B);
+        if (t + 2 <= z1) step(t + 2, integral_constant<int, 2>{}, A);
+        if (t + 3 <= z1) step(t + 3, integral_constant<int, 3>{}, B);
+        if (t + 4 <= z1) step(t + 4, integral_constant<int, 4>{}, A);
     }
-    if (t <= z1) step(t, integral_constant<int, 0>{}, A);
-    if (t + 1 <= z1) step(t + 1, integral_constant<int, 1>{}, B);
-    if (t + 2 <= z1) step(t + 2, integral_constant<int, 2>{}, A);
-    if (t + 3 <= z1) step(t + 3, integral_constant<int, 3>{}, B);
-    if (t + 4 <= z1) step(t + 4, integral_constant<int, 4>{}, A);
     if (kNorm || kIR) {
         // fixed-order block reduction into this tile's partial row (in the
         // red-value buffer, free after the last step's barrier)
