@@ -345,7 +345,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     // constant: every LDS address is then a constant offset, and the z
     // windows rotate through registers without copies.  The variants that
     // would spill unrolled pass J at run time: the outflow ones (kBnd) and
-    // the FP64 64x8 ones, which are held to 128 registers.
+    // the FP64 64x8 ones, which are held to 128 registers; so does the FP32
+    // zero-start sweep, whose 64x16 tiles fit two workgroups per CU only
+    // within 80 registers (unrolled it takes 84).
     auto step = [&](int t, auto J, Fly& X) {
         const int jj = static_cast<int>(J);
         const int m3 = jj % 3;
@@ -486,7 +488,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, const int tile
     };
     using std::integral_constant;
     int t = z0 - 1;
-    constexpr bool kRunPhase = kBnd || (sizeof(T) == 8 && TX == 64 && TY == 8);
+    constexpr bool kRunPhase = kBnd || (sizeof(T) == 8 && TX == 64 && TY == 8) || (sizeof(T) == 4 && kIn == kInZero);
     if constexpr (kRunPhase) {
         int j = 0;
         for (; t + 1 <= z1; t += 2) {
